@@ -1,0 +1,167 @@
+"""Pins for the solve and the loss/emission reductions (sections 2.4-2.7)."""
+
+import numpy as np
+import pytest
+
+from oracle import electron as el
+from oracle.dda import solve_point, system
+from oracle.interaction import dense_matrix
+from oracle.solve import bicgstab, lu_solve
+from workloads import sphere_mask, capped_rod_mask, random_mask
+
+HBARC = 197.3269804
+ALPHA = 7.2973525693e-3
+
+
+def _one_dipole():
+    return np.ones((1, 1, 1), dtype=np.uint8)
+
+
+@pytest.mark.parametrize("pol", ["ldr", "rr", "cm"])
+def test_single_dipole_vacuum_matches_textbook_small_particle_formula(pol):
+    """One dipole in vacuum: the classic small-particle loss probability
+    (e.g. Garcia de Abajo, Rev. Mod. Phys. 82, 209 (2010)), per unit loss
+    energy, written in its own notation:
+      Gamma = 4 alpha_fs E^2 / (pi (hbar c)^3 beta^4 gamma^2)
+              [K1(omega b/v gamma)^2 + K0(omega b/v gamma)^2 / gamma^2] Im(alpha)."""
+    d, E, beta, b = 2.0, 3.0, 0.55, 5.0
+    eps = -8.0 + 0.8j
+    res = solve_point(_one_dipole(), d, [eps], 1.0, beta, (b, 0.0, 0.0), E, pol=pol)
+    _, alpha, _, _ = system(_one_dipole(), d, [eps], 1.0, E, pol)
+    gam = 1.0 / np.sqrt(1 - beta * beta)
+    x = (E / HBARC) * b / (beta * gam)
+    K0, K1 = el.besselk01(np.array([x]))
+    ref = 4 * ALPHA * E ** 2 / (np.pi * HBARC ** 3 * beta ** 4 * gam ** 2) * \
+        (K1[0] ** 2 + K0[0] ** 2 / gam ** 2).real * np.imag(alpha[0])
+    assert res.p_eels == pytest.approx(ref, rel=1e-12)
+    assert res.p_ext == pytest.approx(ref, rel=1e-12)
+
+
+@pytest.mark.parametrize("m_h,beta", [(1.45, 0.55), (2.0, 0.55), (1.5 + 0.05j, 0.6),
+                                      (2.0 + 0.01j, 0.7)])
+def test_single_dipole_closed_form_any_host(m_h, beta):
+    """One dipole, p = alpha e_hat.  From eqs. (25), (34), (37):
+    P_EELS = Pi Im[alpha (K1^2 + K0^2/gamma_h^2) / (m_h^2 gamma_h^2)],
+    Pi = 4 alpha_fs k0^2/(pi hbar c beta^4), K at k_t b (hand derivation; the
+    (x-x0)^2 + (y-y0)^2 = b^2 collapse of the transverse part is what it tests)."""
+    d, E = 1.5, 2.2
+    eps = -6.0 + 0.5j
+    r0 = (3.0, 4.0, -7.0)
+    res = solve_point(_one_dipole(), d, [eps], m_h, beta, r0, E, pol="ldr")
+    _, alpha, _, _ = system(_one_dipole(), d, [eps], m_h, E, "ldr")
+    g = el.gamma_h(beta, m_h)
+    kt = el.transverse_wavenumber(E, beta, m_h)
+    K0, K1 = el.besselk01(np.array([kt * 5.0]))
+    Pi = 4 * ALPHA * (E / HBARC) ** 2 / (np.pi * HBARC * beta ** 4)
+    ref = Pi * np.imag(alpha[0] * (K1[0] ** 2 + K0[0] ** 2 / g ** 2) / (m_h * g) ** 2)
+    assert res.p_eels == pytest.approx(ref, rel=1e-12)
+
+
+def _small_case(m_h=1.45, beta=0.55, eps=-10.0 + 1.0j, n=6, d=2.0, E=2.5, pol="ldr"):
+    mask = sphere_mask(n, d, n * d / 2)
+    r0 = (n * d / 2 + 2.0, 0.3, 0.0)
+    return mask, d, eps, m_h, beta, r0, E, pol
+
+
+def test_energy_budget_discrete_identity():
+    """Real host, beta_h < 1: P_EELS = P_ext (section 2.4) and
+    P_ext = P_abs + P_CL (the budget of Fig. 1 / eq. 41 with W_0 = 0)."""
+    mask, d, eps, m_h, beta, r0, E, pol = _small_case()
+    r = solve_point(mask, d, [eps] * int(mask.sum()), m_h, beta, r0, E, pol=pol)
+    assert r.p_eels == pytest.approx(r.p_ext, rel=1e-11)
+    assert r.p_abs + r.p_cl == pytest.approx(r.p_ext, rel=1e-11)
+    assert r.p_eels > 0 and r.p_cl > 0 and r.p_abs > 0
+
+
+def test_lossless_particle_and_host():
+    """Non-absorbing particle and host, beta_h < 1: nothing is absorbed and
+    every lost quantum is emitted, P_abs = 0 and P_EELS = P_CL (section S6)."""
+    mask, d, eps, m_h, beta, r0, E, pol = _small_case(eps=3.0 + 0j)
+    r = solve_point(mask, d, [eps] * int(mask.sum()), m_h, beta, r0, E, pol=pol)
+    assert abs(r.p_abs) <= 1e-10 * r.p_cl
+    assert r.p_eels == pytest.approx(r.p_cl, rel=1e-10)
+
+
+def test_cherenkov_eels_differs_from_extinction():
+    """beta_h > 1: W_enh != W_ext (section 2.4, Fig. 8), so P_EELS != P_ext,
+    while P_CL stays positive (section 2.6)."""
+    mask, d, eps, m_h, beta, r0, E, pol = _small_case(m_h=2.0, beta=0.7, d=5.0, E=3.0)
+    r = solve_point(mask, d, [eps] * int(mask.sum()), m_h, beta, r0, E, pol=pol)
+    assert abs(r.p_eels - r.p_ext) > 1e-3 * abs(r.p_ext)
+    assert r.p_cl > 0
+    # the discrete budget still closes for the extinction form
+    assert r.p_abs + r.p_cl == pytest.approx(r.p_ext, rel=1e-10)
+
+
+def test_scale_invariance_host_to_vacuum_eq45():
+    """Eq. (45): host m_h at hbar omega equals vacuum with v -> m_h v,
+    m_p -> m_p/m_h and hbar omega -> m_h hbar omega, same geometry."""
+    mask, d, eps, m_h, beta, r0, E, pol = _small_case()
+    n = int(mask.sum())
+    host = solve_point(mask, d, [eps] * n, m_h, beta, r0, E, pol=pol)
+    vac = solve_point(mask, d, [eps / m_h ** 2] * n, 1.0, beta * m_h, r0, E * m_h, pol=pol)
+    for f in ["p_eels", "p_ext", "p_abs", "p_cl"]:
+        assert getattr(vac, f) == pytest.approx(getattr(host, f), rel=1e-11)
+
+
+def test_scale_invariance_geometric_eq46():
+    """Eq. (46): keep omega, scale v -> m_h v, m_p -> m_p/m_h and every length
+    by m_h; the vacuum probabilities are m_h times the host ones."""
+    mask, d, eps, m_h, beta, r0, E, pol = _small_case()
+    n = int(mask.sum())
+    host = solve_point(mask, d, [eps] * n, m_h, beta, r0, E, pol=pol)
+    vac = solve_point(mask, d * m_h, [eps / m_h ** 2] * n, 1.0, beta * m_h,
+                      tuple(m_h * v for v in r0), E, pol=pol)
+    assert vac.p_eels == pytest.approx(m_h * host.p_eels, rel=1e-11)
+    assert vac.p_cl == pytest.approx(m_h * host.p_cl, rel=1e-11)
+
+
+@pytest.mark.parametrize("xi,eta,m_h,beta", [(2.0, 1.0, 1.45, 0.55), (0.5, 1.25, 2.0, 0.6),
+                                             (1.5, 1.1, 1.8 + 0.05j, 0.7)])
+def test_general_scale_invariance_eq43_44(xi, eta, m_h, beta):
+    """Eqs. (43)-(44): m_h -> m_h/eta, m_p -> m_p/eta, v -> eta v, lengths
+    -> lengths/xi, omega -> xi eta omega give P -> P/xi; the Cherenkov and
+    absorbing cases included (only P_EELS and P_ext are defined there)."""
+    mask, d, eps, _, _, r0, E, pol = _small_case(m_h=m_h, beta=beta, d=3.0)
+    n = int(mask.sum())
+    a = solve_point(mask, d, [eps] * n, m_h, beta, r0, E, pol=pol)
+    b = solve_point(mask, d / xi, [eps / eta ** 2] * n, m_h / eta, beta * eta,
+                    tuple(v / xi for v in r0), E * xi * eta, pol=pol)
+    assert b.p_eels == pytest.approx(a.p_eels / xi, rel=1e-10)
+    assert b.p_ext == pytest.approx(a.p_ext / xi, rel=1e-10)
+
+
+def test_z0_shift_changes_nothing():
+    """Section S5: moving the beam centre along the trajectory only changes a
+    constant phase of the fields; every probability is unchanged."""
+    mask, d, eps, m_h, beta, r0, E, pol = _small_case(m_h=2.0 + 0.01j, beta=0.7)
+    n = int(mask.sum())
+    a = solve_point(mask, d, [eps] * n, m_h, beta, r0, E, pol=pol)
+    b = solve_point(mask, d, [eps] * n, m_h, beta, (r0[0], r0[1], r0[2] + 37.3), E, pol=pol)
+    for f in ["p_eels", "p_ext", "p_abs", "p_cl"]:
+        assert getattr(b, f) == pytest.approx(getattr(a, f), rel=1e-11)
+
+
+def test_bicgstab_matches_lu():
+    mask = capped_rod_mask(12, 4, 4, 1.0, radius=2.0, length=12.0)
+    d, E, m_h, beta = 1.0, 2.0, 1.45, 0.55
+    n = int(mask.sum())
+    centres, alpha, k, _ = system(mask, d, [-6.0 + 0.6j] * n, m_h, E)
+    e = el.incident_field(centres, E, beta, m_h, (8.0, 0.0, 0.0))
+    p_lu = lu_solve(centres, alpha, k, e)
+    p_it, it, res = bicgstab(centres, alpha, k, e, tol=1e-13)
+    assert res <= 1e-13
+    assert np.max(np.abs(p_it - p_lu)) <= 1e-10 * np.max(np.abs(p_lu))
+
+
+def test_reciprocity_of_solutions():
+    """A = A^T implies e1 . A^-1 e2 = e2 . A^-1 e1 (bilinear)."""
+    mask = random_mask(5, 4, 3, 0.7, seed=11)
+    centres, alpha, k, _ = system(mask, 1.7, [2.0 + 0.3j] * int(mask.sum()), 1.3 + 0.02j, 2.7)
+    rng = np.random.default_rng(4)
+    e1 = rng.standard_normal((len(alpha), 3)) + 1j * rng.standard_normal((len(alpha), 3))
+    e2 = rng.standard_normal((len(alpha), 3)) + 1j * rng.standard_normal((len(alpha), 3))
+    A = dense_matrix(centres, alpha, k)
+    x1 = np.linalg.solve(A, e1.ravel())
+    x2 = np.linalg.solve(A, e2.ravel())
+    assert np.sum(e2.ravel() * x1) == pytest.approx(np.sum(e1.ravel() * x2), rel=1e-12)
