@@ -1,0 +1,202 @@
+/*
+ * libdda -- discrete-dipole-approximation solve for fast-electron EELS and
+ * cathodoluminescence of a particle in an arbitrary (possibly absorbing,
+ * possibly Cherenkov) host medium, on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Kichigin & Yurkin, "Simulating electron energy-loss spectroscopy
+ * and cathodoluminescence for particles in arbitrary host medium using the
+ * discrete dipole approximation" (arXiv 2208.01348).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Units: lengths in nm, loss energies in eV, electron speed as beta = v/c,
+ * probabilities per unit loss energy in 1/eV (section 2.5, eq. 37).
+ *
+ * Lattice: nx x ny x nz cubic cells of size d, centred on the origin; cell
+ * (i, j, l) has its centre at d*(i - nx/2 + 1/2, j - ny/2 + 1/2, l - nz/2 + 1/2).
+ * The mask is uint8 [nz][ny][nx] (x fastest); a non-zero entry marks an
+ * occupied cell, i.e. a dipole.  Occupied cells are numbered 0..n_occ-1 in
+ * increasing linear index l*ny*nx + j*nx + i; every per-dipole array follows
+ * that order.
+ *
+ * Electron: point charge moving along +z with speed beta*c through the point
+ * r0 = (x0, y0, z0) (eqs. 20-21).  A trajectory is given as 3 doubles (nm).
+ *
+ * Host: refractive index m_h = mh_re + i mh_im with 0 <= arg m_h < pi/2
+ * (section 2.1); k = m_h * E / (hbar c) is the host wavenumber.
+ *
+ * Device vectors ("field" layout): complex128 (two doubles, re then im),
+ * [nrhs][3][n_occ] -- right-hand side, then Cartesian component, then dipole.
+ * Right-hand sides of a batch are numbered rhs = e * n_traj + t for energy e
+ * and trajectory t.  Device pointers are borrowed, never freed by the
+ * library, and used in stream order on the stream given to dda_setup: the
+ * caller keeps them alive until that stream has passed the call.  Host
+ * arrays are read before the call returns.
+ *
+ * Unknowns: dda_solve returns p_hat with A p_hat = e_hat (below), the dipole
+ * moments in the normalisation p_hat = p_SI / (4 pi eps0 m_h^2 C), C the
+ * amplitude of eq. (25).  e_hat is the dimensionless shape of eq. (25).
+ *
+ * Errors: every call returns a dda_status.  Nothing throws across the ABI.
+ * On an error the outputs are left untouched, except DDA_ENOCONV and
+ * DDA_EBREAKDOWN, which leave the best iterate in p and fill `info`.
+ * dda_last_error() then describes the failure (thread-local, valid until the
+ * next call on the same thread).
+ *
+ * Threads: a context must not be used by two threads at once.
+ */
+#ifndef DDA_H
+#define DDA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dda_ctx dda_ctx;
+
+typedef enum {
+    DDA_OK = 0,
+    DDA_EINVAL = -1,      /* bad argument (sizes, NaN, non-passive host, ...)  */
+    DDA_ENOMEM = -2,      /* device allocation failed                          */
+    DDA_EDEVICE = -3,     /* HIP runtime error                                  */
+    DDA_ENOCONV = -4,     /* iteration limit reached before the tolerance       */
+    DDA_EBREAKDOWN = -5,  /* Krylov breakdown that a restart could not cure     */
+    DDA_ESINGULAR = -6    /* beta_h = 1 (eq. 24) or a trajectory through a dipole */
+} dda_status;
+
+enum { DDA_POL_LDR = 0, DDA_POL_CM = 1, DDA_POL_RR = 2 };
+enum { DDA_SOLVER_BICGSTAB = 0 };
+enum { DDA_PREC_FP64 = 0, DDA_PREC_MIXED = 1 };
+
+typedef struct {
+    int polarizability;   /* DDA_POL_*; lattice dispersion relation by default      */
+    int solver;           /* DDA_SOLVER_*                                             */
+    int precision;        /* DDA_PREC_FP64: complex128 throughout.
+                             DDA_PREC_MIXED: complex64 FFT matvecs inside an FP64
+                             iterative-refinement loop                               */
+    double tol;           /* stopping threshold on ||e - A p|| / ||e|| (unscaled)    */
+    int maxit;            /* iteration limit (matvec pairs for BiCGStab)              */
+    int check_every;      /* host polls convergence every this many iterations       */
+} dda_options;
+
+typedef struct {
+    int iters;            /* Krylov iterations taken (inner ones for MIXED)           */
+    int matvecs;          /* FFT matvecs applied to this right-hand side              */
+    double rel_residual;  /* final true ||e - A p|| / ||e|| in FP64                   */
+    int status;           /* dda_status of this right-hand side                        */
+} dda_solve_info;
+
+typedef struct {
+    double p_eels;  /* particle-induced loss probability, eqs. (32), (34), (37)   */
+    double p_ext;   /* extinction probability, eqs. (17), (48)                    */
+    double p_abs;   /* absorption probability, eq. (18) / discrete DDA absorption */
+    double p_cl;    /* cathodoluminescence probability, eq. (42)                  */
+} dda_result;
+
+/* Default options: LDR, BiCGStab, FP64, tol 1e-10, maxit 100000, check 16. */
+void dda_default_options(dda_options* opt);
+
+/* Relativistic v/c of an electron of the given kinetic energy (keV). */
+double dda_beta_from_keV(double kinetic_keV);
+
+/*
+ * Builds a context for one lattice and host medium.  Copies the mask, builds
+ * the index maps on the host and uploads them.  `hip_stream` is a hipStream_t
+ * (NULL = the default stream) on which every later call is ordered.
+ * Errors: DDA_EINVAL for sizes < 1, d <= 0, a lattice side above 256, a
+ * non-passive or non-finite m_h, bad options; DDA_ENOMEM / DDA_EDEVICE.
+ * An empty mask is allowed (n_occ = 0: every later call is a no-op).
+ */
+int dda_setup(const uint8_t* mask, int nx, int ny, int nz, double d_nm,
+              double mh_re, double mh_im, const dda_options* opt,
+              void* hip_stream, dda_ctx** out);
+
+/* Number of occupied cells (dipoles). */
+int dda_n_occ(const dda_ctx* ctx, int64_t* n_occ);
+
+/* FFT grid of the block-Toeplitz embedding: the smallest 2^a 3^b sizes
+ * (b <= 1) that are >= 2n - 1 per axis. */
+int dda_grid_dims(const dda_ctx* ctx, int* mx, int* my, int* mz);
+
+/*
+ * Incident field shape of the electron (eq. 25) at every dipole, for
+ * n_energy energies x n_traj trajectories:
+ *   e_hat = exp(i omega (z - z0)/v) ((x-x0)/b K1(k_t b), (y-y0)/b K1(k_t b),
+ *                                    -(i/gamma_h) K0(k_t b)),
+ *   k_t = omega/(gamma_h v), gamma_h on the first-quadrant branch of eq. (24).
+ * energy_eV [n_energy] host; r0_nm [n_traj][3] host; einc_dev complex128
+ * [n_energy*n_traj][3][n_occ], caller-owned.  FP64 throughout.
+ * Errors: DDA_ESINGULAR if |beta_h^2 - 1| < 1e-12 or a trajectory passes
+ * within 1e-9 d of a dipole centre (eq. 25 is singular at b = 0);
+ * DDA_EINVAL for beta outside (0, 1) or non-positive energies.
+ */
+int dda_einc_electron(dda_ctx* ctx, int n_energy, const double* energy_eV, double beta,
+                      const double* r0_nm, int n_traj, void* einc_dev);
+
+/*
+ * Solves A p_hat = e_hat for every right-hand side of a batch:
+ *   (A p)_i = p_i / alpha_i - sum_{j != i} G(r_i - r_j) p_j,
+ *   G(R) = (k^2 I + grad grad) exp(ikR)/R (eq. 5 times 4 pi k^2),
+ * with the matvec done as a zero-padded 3D FFT convolution (block-Toeplitz
+ * embedding) and alpha_i from m_i^2 = eps_i / m_h^2 (eq. 2) by the chosen
+ * polarizability.  eps_dipole [n_energy][n_occ][2] host: absolute particle
+ * permittivity per dipole per energy.  einc_dev as written by
+ * dda_einc_electron; p_dev complex128 [n_energy*n_traj][3][n_occ] out;
+ * info [n_energy*n_traj] host out (may be NULL).
+ * Returns DDA_OK when every right-hand side met the tolerance, else the
+ * first failing status (per-RHS statuses are in info).
+ */
+int dda_solve(dda_ctx* ctx, int n_energy, const double* energy_eV, const double* eps_dipole,
+              const void* einc_dev, int n_traj, void* p_dev, dda_solve_info* info);
+
+/*
+ * Loss and emission probabilities for every right-hand side (FP64 sums):
+ *   P_EELS = -Pi Im[ sum_i g_i . p_i / (m_h gamma_h)^2 ],  g the auxiliary
+ *            field of the conjugate source, eq. (34), built on the fly;
+ *   P_ext  =  Pi Im[ m_h^2 sum_i conj(e_i) . p_i ] / (|m_h|^4 |gamma_h|^2);
+ *   P_abs  =  real m_h: Pi/(m_h^2|gamma_h|^2) sum_i [-Im(1/alpha_i) - 2k^3/3]|p_i|^2;
+ *             complex m_h: eq. (18) with P = (eps - eps_h) E per cell;
+ *   P_CL   =  Pi Re(m_h^2)/(|m_h|^4|gamma_h|^2) [Im(p^H G_off p) + 2 Re(k)^3 ||p||^2/3]
+ *             (eq. 42; nominal in an absorbing host),
+ *   Pi = 4 alpha_fs k0^2 / (pi hbar c beta^4).
+ * Uses one extra FP64 FFT matvec per right-hand side (for G_off p).
+ * Arguments as for dda_solve; out [n_energy*n_traj] host.
+ */
+int dda_eels_cl(dda_ctx* ctx, int n_energy, const double* energy_eV, double beta,
+                const double* eps_dipole, const double* r0_nm, int n_traj,
+                const void* einc_dev, const void* p_dev, dda_result* out);
+
+/*
+ * One FFT matvec y = A x (or y = sum_{j!=i} G x_j when interaction_only) for
+ * nrhs vectors of one energy, in the given precision.  x_dev and y_dev are
+ * complex128 [nrhs][3][n_occ]; for DDA_PREC_MIXED they are complex64 and the
+ * matvec runs in FP32.  Exposed for testing and benchmarking the kernel chain.
+ */
+int dda_matvec(dda_ctx* ctx, double energy_eV, const double* eps_dipole, int precision,
+               int interaction_only, const void* x_dev, void* y_dev, int nrhs);
+
+/* Average device time (ms) and launch count of each matvec kernel since the
+ * last reset, measured with HIP events on the context's stream when timing
+ * is enabled.  names: "unpack_xfft", "yfft", "zconv", "iyfft", "ixfft_pack". */
+int dda_set_timing(dda_ctx* ctx, int enabled);
+int dda_kernel_time(dda_ctx* ctx, const char* name, double* avg_ms, int64_t* launches);
+
+int dda_destroy(dda_ctx* ctx);
+
+/* Test hook: the device K0/K1 routine of dda_einc_electron at n complex
+ * points.  z: [n][2] host (re, im); k0k1: [n][4] host out (K0 re, im, K1 re,
+ * im).  Arguments are expected in Re z >= 0 (eq. 25 only needs
+ * -pi/2 <= arg z <= 0).  Synchronous; uses the default stream. */
+int dda_debug_besselk01(const double* z, int64_t n, double* k0k1);
+
+/* Thread-local description of the last failure on this thread. */
+const char* dda_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DDA_H */

@@ -40,6 +40,10 @@ def load():
         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int]
     lib.oracle_dense_matvec.restype = None
     lib.oracle_num_threads.restype = ctypes.c_int
+    lib.oracle_dense_matvec_rows.argtypes = [
+        ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
+        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int]
+    lib.oracle_dense_matvec_rows.restype = None
     _lib = lib
     return lib
 
@@ -63,4 +67,23 @@ def matvec(centres: np.ndarray, alpha: np.ndarray, k: complex, x: np.ndarray,
     lib.oracle_dense_matvec(n, c.ctypes.data, ai.ctypes.data, float(np.real(k)),
                             float(np.imag(k)), xx.ctypes.data, y.ctypes.data,
                             1 if interaction_only else 0)
+    return y
+
+
+def matvec_rows(centres: np.ndarray, alpha: np.ndarray, k: complex, x: np.ndarray,
+                rows: np.ndarray, interaction_only: bool = False) -> np.ndarray:
+    """Rows `rows` of A x (or of G_off x); returns [len(rows)][3] complex128."""
+    lib = load()
+    c = np.ascontiguousarray(centres, dtype=np.float64)
+    n = c.shape[0]
+    xx = np.ascontiguousarray(x, dtype=np.complex128).reshape(n, 3)
+    rr = np.ascontiguousarray(rows, dtype=np.int64)
+    if interaction_only:
+        ai = np.zeros(n, dtype=np.complex128)
+    else:
+        ai = np.ascontiguousarray(1.0 / np.asarray(alpha, dtype=np.complex128))
+    y = np.empty((rr.size, 3), dtype=np.complex128)
+    lib.oracle_dense_matvec_rows(n, c.ctypes.data, ai.ctypes.data, float(np.real(k)),
+                                 float(np.imag(k)), xx.ctypes.data, rr.ctypes.data, rr.size,
+                                 y.ctypes.data, 1 if interaction_only else 0)
     return y

@@ -78,3 +78,51 @@ int oracle_num_threads(void)
 #endif
     return t;
 }
+
+/*
+ * Selected rows of the same product: y[r] = (A x)_{rows[r]} (mode 0) or the
+ * interaction part only (mode 1), for r < nrows.  y is [nrows][3] complex.
+ * Lets large lattices be checked on sampled outputs in O(nrows * n) work.
+ */
+void oracle_dense_matvec_rows(int64_t n, const double *centres, const double *alpha_inv,
+                              double k_re, double k_im, const double *x, const int64_t *rows,
+                              int64_t nrows, double *y, int mode)
+{
+    const double complex k = k_re + I * k_im;
+    const double complex *xc = (const double complex *)x;
+    const double complex *ai = (const double complex *)alpha_inv;
+    double complex *yc = (double complex *)y;
+
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t q = 0; q < nrows; ++q) {
+        const int64_t i = rows[q];
+        const double xi = centres[3 * i], yi = centres[3 * i + 1], zi = centres[3 * i + 2];
+        double complex s0 = 0, s1 = 0, s2 = 0;
+        for (int64_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            const double Rx = xi - centres[3 * j];
+            const double Ry = yi - centres[3 * j + 1];
+            const double Rz = zi - centres[3 * j + 2];
+            const double r = sqrt(Rx * Rx + Ry * Ry + Rz * Rz);
+            const double complex kr = k * r;
+            const double complex e = cexp(I * kr) / (r * r * r);
+            const double complex a = e * (kr * kr + I * kr - 1.0);
+            const double complex b = e * (3.0 - 3.0 * I * kr - kr * kr);
+            const double hx = Rx / r, hy = Ry / r, hz = Rz / r;
+            const double complex x0 = xc[3 * j], x1 = xc[3 * j + 1], x2 = xc[3 * j + 2];
+            const double complex proj = b * (hx * x0 + hy * x1 + hz * x2);
+            s0 += a * x0 + proj * hx;
+            s1 += a * x1 + proj * hy;
+            s2 += a * x2 + proj * hz;
+        }
+        if (mode == 0) {
+            yc[3 * q] = xc[3 * i] * ai[i] - s0;
+            yc[3 * q + 1] = xc[3 * i + 1] * ai[i] - s1;
+            yc[3 * q + 2] = xc[3 * i + 2] * ai[i] - s2;
+        } else {
+            yc[3 * q] = s0;
+            yc[3 * q + 1] = s1;
+            yc[3 * q + 2] = s2;
+        }
+    }
+}

@@ -1,0 +1,208 @@
+"""ctypes binding of libdda (include/dda.h): same names, argument marshalling
+only.  Every computation runs in the library's HIP kernels; there is no CPU
+fallback, and loading fails loudly when the library has not been built."""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdda.so")
+
+DDA_OK, DDA_EINVAL, DDA_ENOMEM, DDA_EDEVICE, DDA_ENOCONV, DDA_EBREAKDOWN, DDA_ESINGULAR = \
+    0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "DDA_OK", -1: "DDA_EINVAL", -2: "DDA_ENOMEM", -3: "DDA_EDEVICE",
+                -4: "DDA_ENOCONV", -5: "DDA_EBREAKDOWN", -6: "DDA_ESINGULAR"}
+DDA_POL_LDR, DDA_POL_CM, DDA_POL_RR = 0, 1, 2
+DDA_SOLVER_BICGSTAB = 0
+DDA_PREC_FP64, DDA_PREC_MIXED = 0, 1
+
+# every symbol include/dda.h declares
+EXPORTED = ["dda_default_options", "dda_beta_from_keV", "dda_setup", "dda_n_occ",
+            "dda_grid_dims", "dda_einc_electron", "dda_solve", "dda_eels_cl", "dda_matvec",
+            "dda_set_timing", "dda_kernel_time", "dda_destroy", "dda_last_error",
+            "dda_debug_besselk01"]
+
+
+class DDAError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("polarizability", ctypes.c_int), ("solver", ctypes.c_int),
+                ("precision", ctypes.c_int), ("tol", ctypes.c_double),
+                ("maxit", ctypes.c_int), ("check_every", ctypes.c_int)]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("matvecs", ctypes.c_int),
+                ("rel_residual", ctypes.c_double), ("status", ctypes.c_int)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("p_eels", ctypes.c_double), ("p_ext", ctypes.c_double),
+                ("p_abs", ctypes.c_double), ("p_cl", ctypes.c_double)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_i = ctypes.c_int
+_d = ctypes.c_double
+_i64 = ctypes.c_int64
+
+
+def load() -> ctypes.CDLL:
+    """Loads libdda.so; raises RuntimeError when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "(hipcc for gfx950); there is no fallback path")
+    lib = ctypes.CDLL(LIB_PATH)
+    sig = {
+        "dda_default_options": (None, [_vp]),
+        "dda_beta_from_keV": (_d, [_d]),
+        "dda_setup": (_i, [_vp, _i, _i, _i, _d, _d, _d, _vp, _vp, _vp]),
+        "dda_n_occ": (_i, [_vp, _vp]),
+        "dda_grid_dims": (_i, [_vp, _vp, _vp, _vp]),
+        "dda_einc_electron": (_i, [_vp, _i, _vp, _d, _vp, _i, _vp]),
+        "dda_solve": (_i, [_vp, _i, _vp, _vp, _vp, _i, _vp, _vp]),
+        "dda_eels_cl": (_i, [_vp, _i, _vp, _d, _vp, _vp, _i, _vp, _vp, _vp]),
+        "dda_matvec": (_i, [_vp, _d, _vp, _i, _i, _vp, _vp, _i]),
+        "dda_set_timing": (_i, [_vp, _i]),
+        "dda_kernel_time": (_i, [_vp, ctypes.c_char_p, _vp, _vp]),
+        "dda_destroy": (_i, [_vp]),
+        "dda_last_error": (ctypes.c_char_p, []),
+        "dda_debug_besselk01": (_i, [_vp, _i64, _vp]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(st: int) -> int:
+    if st != DDA_OK:
+        raise DDAError(st, load().dda_last_error().decode())
+    return st
+
+
+def _ptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _eps_pairs(eps) -> np.ndarray:
+    e = np.ascontiguousarray(np.asarray(eps, dtype=np.complex128))
+    return e.view(np.float64)
+
+
+def dda_default_options() -> Options:
+    o = Options()
+    load().dda_default_options(ctypes.byref(o))
+    return o
+
+
+def dda_beta_from_keV(kinetic_keV: float) -> float:
+    return float(load().dda_beta_from_keV(float(kinetic_keV)))
+
+
+def dda_setup(mask: np.ndarray, nx: int, ny: int, nz: int, d_nm: float, mh_re: float,
+              mh_im: float, opt: Options, hip_stream: int = 0) -> ctypes.c_void_p:
+    m = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8))
+    if m.size != nx * ny * nz:
+        raise ValueError("mask size does not match nx*ny*nz")
+    ctx = ctypes.c_void_p()
+    _check(load().dda_setup(_ptr(m), nx, ny, nz, float(d_nm), float(mh_re), float(mh_im),
+                            ctypes.byref(opt), ctypes.c_void_p(hip_stream or None),
+                            ctypes.byref(ctx)))
+    return ctx
+
+
+def dda_n_occ(ctx) -> int:
+    n = ctypes.c_int64()
+    _check(load().dda_n_occ(ctx, ctypes.byref(n)))
+    return int(n.value)
+
+
+def dda_grid_dims(ctx):
+    a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(load().dda_grid_dims(ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+def dda_einc_electron(ctx, energy_eV, beta: float, r0_nm, einc_dev: int) -> None:
+    E = _f64(energy_eV).ravel()
+    R = _f64(r0_nm).reshape(-1, 3)
+    _check(load().dda_einc_electron(ctx, E.size, _ptr(E), float(beta), _ptr(R), R.shape[0],
+                                    ctypes.c_void_p(einc_dev)))
+
+
+def dda_solve(ctx, energy_eV, eps_dipole, einc_dev: int, n_traj: int, p_dev: int,
+              raise_on_error: bool = True):
+    """eps_dipole: complex [n_energy][n_occ].  Returns (status, info array)."""
+    E = _f64(energy_eV).ravel()
+    eps = _eps_pairs(eps_dipole)
+    info = (SolveInfo * max(1, E.size * n_traj))()
+    st = load().dda_solve(ctx, E.size, _ptr(E), _ptr(eps), ctypes.c_void_p(einc_dev), n_traj,
+                          ctypes.c_void_p(p_dev), info)
+    if raise_on_error and st not in (DDA_OK,):
+        _check(st)
+    return st, [(i.iters, i.matvecs, i.rel_residual, i.status) for i in info[:E.size * n_traj]]
+
+
+def dda_eels_cl(ctx, energy_eV, beta: float, eps_dipole, r0_nm, einc_dev: int,
+                p_dev: int) -> np.ndarray:
+    """Returns float64 [n_energy * n_traj][4]: P_EELS, P_ext, P_abs, P_CL (1/eV)."""
+    E = _f64(energy_eV).ravel()
+    R = _f64(r0_nm).reshape(-1, 3)
+    eps = _eps_pairs(eps_dipole)
+    out = np.zeros((E.size * R.shape[0], 4), dtype=np.float64)
+    _check(load().dda_eels_cl(ctx, E.size, _ptr(E), float(beta), _ptr(eps), _ptr(R), R.shape[0],
+                              ctypes.c_void_p(einc_dev), ctypes.c_void_p(p_dev), _ptr(out)))
+    return out
+
+
+def dda_matvec(ctx, energy_eV: float, eps_dipole, precision: int, interaction_only: bool,
+               x_dev: int, y_dev: int, nrhs: int) -> None:
+    eps = _eps_pairs(eps_dipole) if eps_dipole is not None else None
+    _check(load().dda_matvec(ctx, float(energy_eV), None if eps is None else _ptr(eps),
+                             int(precision), int(bool(interaction_only)), ctypes.c_void_p(x_dev),
+                             ctypes.c_void_p(y_dev), int(nrhs)))
+
+
+def dda_set_timing(ctx, enabled: bool) -> None:
+    _check(load().dda_set_timing(ctx, int(bool(enabled))))
+
+
+def dda_kernel_time(ctx, name: str):
+    ms = ctypes.c_double()
+    n = ctypes.c_int64()
+    _check(load().dda_kernel_time(ctx, name.encode(), ctypes.byref(ms), ctypes.byref(n)))
+    return float(ms.value), int(n.value)
+
+
+def dda_destroy(ctx) -> None:
+    _check(load().dda_destroy(ctx))
+
+
+def dda_last_error() -> str:
+    return load().dda_last_error().decode()
+
+
+def dda_debug_besselk01(z) -> np.ndarray:
+    zz = np.ascontiguousarray(np.asarray(z, dtype=np.complex128).ravel())
+    out = np.zeros((zz.size, 4), dtype=np.float64)
+    _check(load().dda_debug_besselk01(_ptr(zz.view(np.float64)), zz.size, _ptr(out)))
+    return out[:, 0] + 1j * out[:, 1], out[:, 2] + 1j * out[:, 3]

@@ -1,0 +1,1042 @@
+// C ABI of the gfx950 DDA library (declared in include/dda.h) and the host
+// orchestration of its kernels.
+#include "dda.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <list>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "krylov.h"
+
+using dda::Error;
+using dda::z128;
+using dda::z64;
+using cplx = std::complex<double>;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+constexpr double kHbarC = 197.3269804;        // eV nm
+constexpr double kAlphaFs = 7.2973525693e-3;  // fine-structure constant
+constexpr double kMeC2 = 510.99895;           // keV
+constexpr double kPi = 3.14159265358979323846;
+constexpr int kMaxSide = 256;
+constexpr int kMaxRestarts = 20;
+constexpr double kInnerTol = 1e-4;   // relative tolerance of the FP32 inner solves
+constexpr int kMaxOuter = 60;
+
+// ------------------------------------------------------------------ memory
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    void ensure(size_t n) {
+        if (n <= bytes && p) return;
+        release();
+        if (n == 0) n = 256;
+        DDA_HIP_CHECK(hipMalloc(&p, n));
+        bytes = n;
+    }
+    template <typename T>
+    T* as() const { return static_cast<T*>(p); }
+};
+
+struct PinnedBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    ~PinnedBuf() {
+        if (p) (void)hipHostFree(p);
+    }
+    void ensure(size_t n) {
+        if (n <= bytes && p) return;
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        DDA_HIP_CHECK(hipHostMalloc(&p, std::max<size_t>(n, 256), hipHostMallocDefault));
+        bytes = std::max<size_t>(n, 256);
+    }
+    template <typename T>
+    T* as() const { return static_cast<T*>(p); }
+};
+
+// D(k) for one host wavenumber: FP64 always, FP32 copy on demand.
+struct DEntry {
+    DevBuf d128, d64;
+    bool has64 = false;
+    uint64_t last_use = 0;
+};
+
+struct Timer {
+    std::vector<hipEvent_t> pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    double total_ms[5] = {0, 0, 0, 0, 0};
+    int64_t count[5] = {0, 0, 0, 0, 0};
+    ~Timer() {
+        for (auto& e : pool) (void)hipEventDestroy(e);
+        for (auto& p : pending) {
+            (void)hipEventDestroy(p.second.first);
+            (void)hipEventDestroy(p.second.second);
+        }
+    }
+    hipEvent_t get() {
+        if (!pool.empty()) {
+            hipEvent_t e = pool.back();
+            pool.pop_back();
+            return e;
+        }
+        hipEvent_t e;
+        DDA_HIP_CHECK(hipEventCreate(&e));
+        return e;
+    }
+};
+
+const char* const kKernelNames[5] = {"unpack_xfft", "yfft", "zconv", "iyfft", "ixfft_pack"};
+
+int choose_fft_len(int n) {
+    static const int sizes[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512};
+    for (int s : sizes)
+        if (s >= 2 * n - 1) return s;
+    return -1;
+}
+
+cplx gamma_h_of(double beta, cplx mh) {
+    // gamma_h = i / sqrt(beta_h^2 - 1), principal root; beta_h^2 - 1 lies in
+    // the closed upper half plane for a passive host (eq. 24), and a zero
+    // imaginary part is taken as +0.
+    cplx bh = beta * mh;
+    cplx w = bh * bh - 1.0;
+    if (std::abs(w) < 1e-12)
+        throw Error(DDA_ESINGULAR, "beta_h = 1: the electron field is singular (eq. 24)");
+    if (w.imag() == 0.0) w = cplx(w.real(), 0.0);
+    cplx sq = (w.imag() == 0.0 && w.real() < 0.0) ? cplx(0.0, std::sqrt(-w.real())) : std::sqrt(w);
+    return cplx(0.0, 1.0) / sq;
+}
+
+}  // namespace
+
+struct dda_ctx {
+    dda::Geo g{};
+    double d = 1.0;
+    cplx mh;
+    dda_options opt{};
+    hipStream_t stream = nullptr;
+    std::vector<int> occ_lin;  // host copy
+    DevBuf map, occ;
+    DevBuf tw128[3], tw64[3];
+    std::map<std::pair<double, double>, std::unique_ptr<DEntry>> dcache;
+    uint64_t use_clock = 0;
+    uint64_t pin_clock = 0;   // entries used at or after this tick are in use
+    size_t dcache_limit = size_t(64) << 30;
+    // work space
+    DevBuf G, vec128, vec64, st, partial, counters, act, slot_sys, dptr, ainv128, ainv64, misc;
+    PinnedBuf host_st, host_act, host_misc;
+    int max_blocks = 1024;
+    bool timing = false;
+    Timer timer;
+
+    int64_t nv() const { return 3 * g.n_occ; }
+};
+
+namespace {
+
+template <typename T>
+const dda::cx<T>* tw_of(const dda_ctx* c, int axis);
+template <>
+const z128* tw_of<double>(const dda_ctx* c, int axis) { return c->tw128[axis].as<z128>(); }
+template <>
+const z64* tw_of<float>(const dda_ctx* c, int axis) { return c->tw64[axis].as<z64>(); }
+
+void check_finite(double v, const char* what) {
+    if (!std::isfinite(v)) throw Error(DDA_EINVAL, std::string(what) + " is not finite");
+}
+
+// Copies a pageable host array to the device in the order of the context's
+// stream and waits for it (the host array may go out of scope afterwards).
+void upload(dda_ctx* c, void* dst, const void* src, size_t bytes) {
+    if (bytes == 0) return;
+    DDA_HIP_CHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream));
+    DDA_HIP_CHECK(hipStreamSynchronize(c->stream));
+}
+
+struct Tic {
+    dda_ctx* c;
+    int k;
+    hipEvent_t a = nullptr, b = nullptr;
+    Tic(dda_ctx* c_, int k_) : c(c_), k(k_) {
+        if (c->timing) {
+            a = c->timer.get();
+            b = c->timer.get();
+            DDA_HIP_CHECK(hipEventRecord(a, c->stream));
+        }
+    }
+    ~Tic() {
+        if (c->timing) {
+            (void)hipEventRecord(b, c->stream);
+            c->timer.pending.push_back({k, {a, b}});
+        }
+    }
+};
+
+void flush_timer(dda_ctx* c) {
+    if (c->timer.pending.empty()) return;
+    DDA_HIP_CHECK(hipStreamSynchronize(c->stream));
+    for (auto& p : c->timer.pending) {
+        float ms = 0.f;
+        DDA_HIP_CHECK(hipEventElapsedTime(&ms, p.second.first, p.second.second));
+        c->timer.total_ms[p.first] += ms;
+        c->timer.count[p.first] += 1;
+        c->timer.pool.push_back(p.second.first);
+        c->timer.pool.push_back(p.second.second);
+    }
+    c->timer.pending.clear();
+}
+
+// y = A x (or G_off x) for the slots listed in act (device) / n_act.
+template <typename T>
+void matvec(dda_ctx* c, const dda::cx<T>* x, dda::cx<T>* y, const int* act, int n_act,
+            const dda::cx<T>* const* dptr, const int* slot_sys, const dda::cx<T>* ainv,
+            bool interaction_only) {
+    if (n_act == 0 || c->g.n_occ == 0) return;
+    const dda::Geo& g = c->g;
+    auto* G = c->G.as<dda::cx<T>>();
+    hipStream_t s = c->stream;
+    const int64_t plane = int64_t(g.my) * g.mx;
+    {
+        Tic t(c, 0);
+        dda::launch_unpack_xfft<T>(x, c->map.as<int>(), G, tw_of<T>(c, 0), g, act, n_act, s);
+    }
+    {
+        Tic t(c, 1);
+        dda::launch_fft_mid<T>(G, tw_of<T>(c, 1), g.my, false, int64_t(n_act) * 3 * g.nz, g.mx,
+                               g.ny, g.my, plane, s);
+    }
+    {
+        Tic t(c, 2);
+        dda::launch_zconv<T>(G, dptr, tw_of<T>(c, 2), g, act, slot_sys, n_act, s);
+    }
+    {
+        Tic t(c, 3);
+        dda::launch_fft_mid<T>(G, tw_of<T>(c, 1), g.my, true, int64_t(n_act) * 3 * g.nz, g.mx,
+                               g.my, g.ny, plane, s);
+    }
+    {
+        Tic t(c, 4);
+        dda::launch_ixfft_pack<T>(G, x, ainv, y, c->map.as<int>(), tw_of<T>(c, 0), g, act,
+                                  slot_sys, n_act, interaction_only, s);
+    }
+}
+
+// ------------------------------------------------------------ D cache
+DEntry* get_D(dda_ctx* c, double energy, bool need64) {
+    const cplx k = c->mh * (energy / kHbarC);
+    auto key = std::make_pair(k.real(), k.imag());
+    auto it = c->dcache.find(key);
+    DEntry* e;
+    if (it == c->dcache.end()) {
+        const size_t b128 = size_t(dda::dgrid_elems(c->g)) * sizeof(z128);
+        // evict least recently used entries beyond the limit
+        size_t used = 0;
+        for (auto& kv : c->dcache) used += kv.second->d128.bytes + kv.second->d64.bytes;
+        while (used + b128 * 2 > c->dcache_limit) {
+            auto victim = c->dcache.end();
+            for (auto i2 = c->dcache.begin(); i2 != c->dcache.end(); ++i2)
+                if (i2->second->last_use < c->pin_clock &&
+                    (victim == c->dcache.end() || i2->second->last_use < victim->second->last_use))
+                    victim = i2;
+            if (victim == c->dcache.end()) break;  // everything cached is in use
+            used -= victim->second->d128.bytes + victim->second->d64.bytes;
+            c->dcache.erase(victim);
+        }
+        auto ne = std::make_unique<DEntry>();
+        ne->d128.ensure(b128);
+        dda::launch_build_D(ne->d128.as<z128>(), c->g, c->d, k.real(), k.imag(),
+                            c->tw128[0].as<z128>(), c->tw128[1].as<z128>(),
+                            c->tw128[2].as<z128>(), c->stream);
+        e = ne.get();
+        c->dcache[key] = std::move(ne);
+    } else {
+        e = it->second.get();
+    }
+    if (need64 && !e->has64) {
+        const int64_t n = dda::dgrid_elems(c->g);
+        e->d64.ensure(size_t(n) * sizeof(z64));
+        dda::launch_convert_z128_to_z64(e->d128.as<z128>(), e->d64.as<z64>(), n, c->stream);
+        e->has64 = true;
+    }
+    e->last_use = ++c->use_clock;
+    return e;
+}
+
+// ---------------------------------------------------------- polarizability
+cplx polarizability(int kind, cplx eps, cplx mh, double d, cplx k) {
+    const cplx m2 = eps / (mh * mh);
+    const double d3 = d * d * d;
+    const cplx acm = (3.0 * d3 / (4.0 * kPi)) * (m2 - 1.0) / (m2 + 2.0);
+    const cplx I(0.0, 1.0);
+    if (kind == DDA_POL_CM) return acm;
+    if (kind == DDA_POL_RR) return acm / (1.0 - (2.0 / 3.0) * I * k * k * k * acm);
+    // lattice dispersion relation (Draine & Goodman 1993), S = 0 for the
+    // electron moving along the lattice z axis with a transverse field
+    const double b1 = -1.8915316, b2 = 0.1648469;
+    const cplx kd = k * d;
+    const cplx corr = (b1 + m2 * b2) * kd * kd - (2.0 / 3.0) * I * kd * kd * kd;
+    return acm / (1.0 + (acm / d3) * corr);
+}
+
+void read_eps(const double* eps, int64_t idx, cplx& out) {
+    out = cplx(eps[2 * idx], eps[2 * idx + 1]);
+    if (!std::isfinite(out.real()) || !std::isfinite(out.imag()))
+        throw Error(DDA_EINVAL, "permittivity is not finite");
+}
+
+// Builds 1/alpha for systems [e0, e0+ns) into ctx->ainv128 (and ainv64).
+void upload_ainv(dda_ctx* c, const double* energy, const double* eps, int e0, int ns, bool need64) {
+    const int64_t n = c->g.n_occ;
+    std::vector<z128> h(size_t(ns) * n);
+    for (int s = 0; s < ns; ++s) {
+        const cplx k = c->mh * (energy[e0 + s] / kHbarC);
+        for (int64_t i = 0; i < n; ++i) {
+            cplx ep;
+            read_eps(eps, int64_t(e0 + s) * n + i, ep);
+            const cplx a = polarizability(c->opt.polarizability, ep, c->mh, c->d, k);
+            if (a == cplx(0.0, 0.0) || !std::isfinite(std::abs(a)))
+                throw Error(DDA_EINVAL, "permittivity gives a zero or infinite polarizability");
+            const cplx ai = 1.0 / a;
+            h[size_t(s) * n + i] = z128{ai.real(), ai.imag()};
+        }
+    }
+    c->ainv128.ensure(h.size() * sizeof(z128));
+    DDA_HIP_CHECK(hipMemcpyAsync(c->ainv128.p, h.data(), h.size() * sizeof(z128),
+                                 hipMemcpyHostToDevice, c->stream));
+    if (need64) {
+        c->ainv64.ensure(h.size() * sizeof(z64));
+        dda::launch_convert_z128_to_z64(c->ainv128.as<z128>(), c->ainv64.as<z64>(),
+                                        int64_t(h.size()), c->stream);
+    }
+    DDA_HIP_CHECK(hipStreamSynchronize(c->stream));  // h goes out of scope
+}
+
+// Per-chunk device tables: slot -> system, system -> D pointer.
+template <typename T>
+const dda::cx<T>* const* upload_dptrs(dda_ctx* c, const std::vector<DEntry*>& ents);
+template <>
+const z128* const* upload_dptrs<double>(dda_ctx* c, const std::vector<DEntry*>& ents) {
+    std::vector<const z128*> h;
+    for (auto* e : ents) h.push_back(e->d128.as<z128>());
+    c->dptr.ensure(2 * h.size() * sizeof(void*));
+    upload(c, c->dptr.p, h.data(), h.size() * sizeof(void*));
+    return c->dptr.as<const z128* const>();
+}
+template <>
+const z64* const* upload_dptrs<float>(dda_ctx* c, const std::vector<DEntry*>& ents) {
+    std::vector<const z64*> h;
+    for (auto* e : ents) h.push_back(e->d64.as<z64>());
+    c->dptr.ensure(2 * h.size() * sizeof(void*));
+    auto* base = reinterpret_cast<char*>(c->dptr.p) + h.size() * sizeof(void*);
+    upload(c, base, h.data(), h.size() * sizeof(void*));
+    return reinterpret_cast<const z64* const*>(base);
+}
+
+dda::RedScratch red_of(dda_ctx* c) {
+    return dda::RedScratch{c->partial.as<double>(), c->counters.as<unsigned>(), c->max_blocks};
+}
+
+void ensure_slots(dda_ctx* c, int nslots) {
+    c->st.ensure(size_t(nslots) * sizeof(dda::BicgSlot));
+    c->partial.ensure(size_t(nslots) * c->max_blocks * 8 * sizeof(double));
+    if (c->counters.bytes < size_t(nslots) * sizeof(unsigned)) {
+        c->counters.ensure(size_t(nslots) * sizeof(unsigned));
+        DDA_HIP_CHECK(hipMemsetAsync(c->counters.p, 0, c->counters.bytes, c->stream));
+    }
+    c->act.ensure(size_t(nslots) * sizeof(int));
+    c->slot_sys.ensure(size_t(nslots) * sizeof(int));
+    c->host_st.ensure(size_t(nslots) * sizeof(dda::BicgSlot));
+    c->host_act.ensure(size_t(nslots) * sizeof(int));
+}
+
+void upload_act(dda_ctx* c, const std::vector<int>& act) {
+    if (act.empty()) return;
+    std::memcpy(c->host_act.p, act.data(), act.size() * sizeof(int));
+    DDA_HIP_CHECK(hipMemcpyAsync(c->act.p, c->host_act.p, act.size() * sizeof(int),
+                                 hipMemcpyHostToDevice, c->stream));
+}
+
+std::vector<dda::BicgSlot> read_states(dda_ctx* c, int nslots) {
+    DDA_HIP_CHECK(hipMemcpyAsync(c->host_st.p, c->st.p, size_t(nslots) * sizeof(dda::BicgSlot),
+                                 hipMemcpyDeviceToHost, c->stream));
+    DDA_HIP_CHECK(hipStreamSynchronize(c->stream));
+    auto* p = c->host_st.as<dda::BicgSlot>();
+    return std::vector<dda::BicgSlot>(p, p + nslots);
+}
+
+// Work vectors of one precision inside a chunk.
+template <typename T>
+struct Vecs {
+    dda::cx<T>*r, *rhat, *p, *v, *s, *t;
+};
+
+// BiCGStab over the slots of a chunk, from x0 = 0.  b and x are
+// slot-indexed.  The host only looks at the device scalars every
+// `check_every` iterations: converged or broken-down slots leave the active
+// list; with true_check a slot reporting convergence is verified with a true
+// residual b - A x and restarted from it when it drifted above tol.
+template <typename T>
+void run_bicgstab(dda_ctx* c, int nslots, const dda::cx<T>* b, dda::cx<T>* x, Vecs<T> w,
+                  double tol, int maxit, bool true_check, const dda::cx<T>* const* dptr,
+                  const dda::cx<T>* ainv, std::vector<int>& iters, std::vector<int>& matvecs,
+                  std::vector<int>& status, std::vector<double>& relres) {
+    const int64_t nv = c->nv();
+    hipStream_t s = c->stream;
+    auto* st = c->st.as<dda::BicgSlot>();
+    const int* slot_sys = c->slot_sys.as<int>();
+    auto red = red_of(c);
+    std::vector<int> act(nslots);
+    for (int i = 0; i < nslots; ++i) act[i] = i;
+    upload_act(c, act);
+    const int* dact = c->act.as<int>();
+    dda::bicg_norm_b<T>(b, st, dact, nslots, nv, tol * tol, red, s);
+    DDA_HIP_CHECK(hipMemsetAsync(x, 0, size_t(nslots) * nv * sizeof(dda::cx<T>), s));
+    DDA_HIP_CHECK(hipMemcpyAsync(w.r, b, size_t(nslots) * nv * sizeof(dda::cx<T>),
+                                 hipMemcpyDeviceToDevice, s));
+    dda::bicg_reset<T>(w.r, w.rhat, w.p, w.v, st, dact, nslots, nv, red, s);
+    std::vector<int> restarts(nslots, 0);
+    status.assign(nslots, DDA_OK);
+    iters.assign(nslots, 0);
+    matvecs.assign(nslots, 0);
+    relres.assign(nslots, 0.0);
+    const int check = std::max(1, c->opt.check_every);
+    while (true) {
+        auto S = read_states(c, nslots);
+        std::vector<int> verify, next;
+        for (int i : act) {
+            iters[i] = S[i].iters;  // device counter, cumulative over restarts
+            if (S[i].status == dda::SLOT_CONVERGED || S[i].status == dda::SLOT_BREAKDOWN) {
+                verify.push_back(i);
+            } else if (iters[i] >= maxit) {
+                status[i] = DDA_ENOCONV;
+                relres[i] = S[i].bnorm2 > 0 ? std::sqrt(S[i].rnorm2 / S[i].bnorm2) : 0.0;
+            } else {
+                next.push_back(i);
+            }
+        }
+        if (!verify.empty() && !true_check) {
+            for (int i : verify) {
+                relres[i] = S[i].bnorm2 > 0 ? std::sqrt(S[i].rnorm2 / S[i].bnorm2) : 0.0;
+                status[i] = S[i].status == dda::SLOT_BREAKDOWN ? DDA_EBREAKDOWN : DDA_OK;
+            }
+        } else if (!verify.empty()) {
+            // true residual: y = A x into w.t, r = b - y (rnorm2)
+            upload_act(c, verify);
+            matvec<T>(c, x, w.t, dact, int(verify.size()), dptr, slot_sys, ainv, false);
+            dda::residual<T>(b, w.t, w.r, st, dact, int(verify.size()), nv, red, s);
+            auto S2 = read_states(c, nslots);
+            std::vector<int> again;
+            for (int i : verify) {
+                matvecs[i] += 1;
+                const double rr = S2[i].bnorm2 > 0 ? std::sqrt(S2[i].rnorm2 / S2[i].bnorm2) : 0.0;
+                relres[i] = rr;
+                if (rr <= tol) {
+                    status[i] = DDA_OK;
+                } else if (restarts[i] >= kMaxRestarts || iters[i] >= maxit) {
+                    status[i] = S[i].status == dda::SLOT_BREAKDOWN ? DDA_EBREAKDOWN : DDA_ENOCONV;
+                } else {
+                    restarts[i] += 1;
+                    again.push_back(i);
+                }
+            }
+            if (!again.empty()) {
+                upload_act(c, again);
+                dda::bicg_reset<T>(w.r, w.rhat, w.p, w.v, st, dact, int(again.size()), nv, red, s);
+                next.insert(next.end(), again.begin(), again.end());
+            }
+        }
+        std::sort(next.begin(), next.end());
+        act = next;
+        const int n_act = int(act.size());
+        if (n_act == 0) break;
+        upload_act(c, act);
+        for (int k = 0; k < check; ++k) {
+            dda::bicg_update_p<T>(w.r, w.p, w.v, st, dact, n_act, nv, s);
+            matvec<T>(c, w.p, w.v, dact, n_act, dptr, slot_sys, ainv, false);
+            dda::bicg_alpha<T>(w.rhat, w.v, st, dact, n_act, nv, red, s);
+            dda::bicg_update_s<T>(w.r, w.v, w.s, st, dact, n_act, nv, red, s);
+            matvec<T>(c, w.s, w.t, dact, n_act, dptr, slot_sys, ainv, false);
+            dda::bicg_omega<T>(w.t, w.s, st, dact, n_act, nv, red, s);
+            dda::bicg_update_xr<T>(x, w.r, w.rhat, w.p, w.s, w.t, st, dact, n_act, nv, red, s);
+            for (int i : act) matvecs[i] += 2;
+        }
+    }
+}
+
+// Writes rnorm2 = rn[i]^2 into the device scalars of every slot.
+void set_rnorm2(dda_ctx* c, int nslots, const std::vector<double>& rn) {
+    auto S = read_states(c, nslots);
+    for (int i = 0; i < nslots; ++i) S[i].rnorm2 = rn[i] * rn[i];
+    std::memcpy(c->host_st.p, S.data(), S.size() * sizeof(dda::BicgSlot));
+    DDA_HIP_CHECK(hipMemcpyAsync(c->st.p, c->host_st.p, S.size() * sizeof(dda::BicgSlot),
+                                 hipMemcpyHostToDevice, c->stream));
+    DDA_HIP_CHECK(hipStreamSynchronize(c->stream));
+}
+
+// Mixed precision: x = 0, r = b; repeat { d = FP32-BiCGStab(A, r/||r||) to
+// kInnerTol; x += ||r|| d; r = b - A x in FP64 } until ||r|| <= tol ||b||.
+void run_mixed(dda_ctx* c, int nslots, const z128* b, z128* x, const z128* const* dptr64,
+               const z64* const* dptr32, std::vector<int>& iters, std::vector<int>& mvs,
+               std::vector<int>& status, std::vector<double>& relres) {
+    const int64_t nv = c->nv();
+    const size_t q = size_t(nslots) * nv;
+    c->vec128.ensure(2 * q * sizeof(z128));
+    c->vec64.ensure(8 * q * sizeof(z64));
+    auto* V = c->vec128.as<z128>();
+    auto* U = c->vec64.as<z64>();
+    z128* r64 = V;
+    z128* y64 = V + q;
+    z64* r32 = U;
+    z64* d32 = U + q;
+    Vecs<float> w{U + 2 * q, U + 3 * q, U + 4 * q, U + 5 * q, U + 6 * q, U + 7 * q};
+    auto* st = c->st.as<dda::BicgSlot>();
+    auto red = red_of(c);
+    const double tol = c->opt.tol;
+    iters.assign(nslots, 0);
+    mvs.assign(nslots, 0);
+    status.assign(nslots, DDA_ENOCONV);
+    relres.assign(nslots, 1.0);
+    std::vector<int> all(nslots);
+    for (int i = 0; i < nslots; ++i) all[i] = i;
+    upload_act(c, all);
+    dda::bicg_norm_b<double>(b, st, c->act.as<int>(), nslots, nv, tol * tol, red, c->stream);
+    std::vector<double> bn(nslots), rn(nslots);
+    {
+        auto S = read_states(c, nslots);
+        for (int i = 0; i < nslots; ++i) bn[i] = rn[i] = std::sqrt(S[i].bnorm2);
+    }
+    DDA_HIP_CHECK(hipMemsetAsync(x, 0, q * sizeof(z128), c->stream));
+    DDA_HIP_CHECK(hipMemcpyAsync(r64, b, q * sizeof(z128), hipMemcpyDeviceToDevice, c->stream));
+    std::vector<int> stalls(nslots, 0);
+    for (int outer = 0; outer < kMaxOuter; ++outer) {
+        std::vector<int> need;
+        std::vector<char> isneed(nslots, 0);
+        for (int i = 0; i < nslots; ++i) {
+            relres[i] = bn[i] > 0 ? rn[i] / bn[i] : 0.0;
+            if (relres[i] <= tol) status[i] = DDA_OK;
+            else if (iters[i] < c->opt.maxit && stalls[i] < 3) { need.push_back(i); isneed[i] = 1; }
+        }
+        if (need.empty()) break;
+        // inner right-hand side r/||r|| on the slots that need work, 0 elsewhere
+        // (a zero right-hand side converges at once, with no iteration)
+        set_rnorm2(c, nslots, rn);
+        upload_act(c, need);
+        dda::scale_down(r64, r32, st, c->act.as<int>(), int(need.size()), nv, c->stream);
+        for (int i = 0; i < nslots; ++i)
+            if (!isneed[i])
+                DDA_HIP_CHECK(hipMemsetAsync(r32 + size_t(i) * nv, 0, nv * sizeof(z64), c->stream));
+        std::vector<int> it_in, mv_in, st_in;
+        std::vector<double> rr_in;
+        run_bicgstab<float>(c, nslots, r32, d32, w, kInnerTol, c->opt.maxit, false, dptr32,
+                            c->ainv64.as<z64>(), it_in, mv_in, st_in, rr_in);
+        set_rnorm2(c, nslots, rn);
+        upload_act(c, need);
+        dda::accumulate_up(x, d32, st, c->act.as<int>(), int(need.size()), nv, c->stream);
+        matvec<double>(c, x, y64, c->act.as<int>(), int(need.size()), dptr64,
+                       c->slot_sys.as<int>(), c->ainv128.as<z128>(), false);
+        dda::residual<double>(b, y64, r64, st, c->act.as<int>(), int(need.size()), nv, red,
+                              c->stream);
+        auto S = read_states(c, nslots);
+        for (int i : need) {
+            iters[i] += it_in[i];
+            mvs[i] += mv_in[i] + 1;
+            const double nr = std::sqrt(S[i].rnorm2);
+            stalls[i] = (nr < 0.9 * rn[i]) ? 0 : stalls[i] + 1;
+            rn[i] = nr;
+        }
+    }
+    for (int i = 0; i < nslots; ++i) {
+        relres[i] = bn[i] > 0 ? rn[i] / bn[i] : 0.0;
+        status[i] = relres[i] <= tol ? DDA_OK : DDA_ENOCONV;
+    }
+}
+
+// Sizes of the per-slot work space, in bytes.
+size_t slot_bytes(const dda_ctx* c, bool mixed) {
+    const size_t ge = size_t(dda::grid_elems(c->g));
+    const size_t nv = size_t(c->nv());
+    if (!mixed) return ge * sizeof(z128) + 6 * nv * sizeof(z128);
+    return ge * sizeof(z128) + 2 * nv * sizeof(z128) + 8 * nv * sizeof(z64);
+}
+
+void host_trajectory_check(const dda_ctx* c, const double* r0, int n_traj) {
+    const dda::Geo& g = c->g;
+    // occupied (x, y) columns
+    std::vector<char> col(size_t(g.nx) * g.ny, 0);
+    for (int lin : c->occ_lin) col[lin % (g.nx * g.ny)] = 1;
+    for (int t = 0; t < n_traj; ++t) {
+        for (int q = 0; q < 3; ++q) check_finite(r0[3 * t + q], "trajectory coordinate");
+        for (int iy = 0; iy < g.ny; ++iy)
+            for (int ix = 0; ix < g.nx; ++ix) {
+                if (!col[size_t(iy) * g.nx + ix]) continue;
+                const double px = c->d * (ix - 0.5 * g.nx + 0.5);
+                const double py = c->d * (iy - 0.5 * g.ny + 0.5);
+                if (std::hypot(px - r0[3 * t], py - r0[3 * t + 1]) < 1e-9 * c->d)
+                    throw Error(DDA_ESINGULAR,
+                                "trajectory passes through a dipole centre (b = 0 in eq. 25)");
+            }
+    }
+}
+
+void check_energies(int n_energy, const double* energy) {
+    if (n_energy < 0) throw Error(DDA_EINVAL, "n_energy < 0");
+    for (int e = 0; e < n_energy; ++e) {
+        check_finite(energy[e], "energy");
+        if (energy[e] <= 0) throw Error(DDA_EINVAL, "energies must be positive");
+    }
+}
+
+void check_beta(dda_ctx* c, double beta) {
+    check_finite(beta, "beta");
+    if (!(beta > 0.0 && beta < 1.0)) throw Error(DDA_EINVAL, "beta must lie in (0, 1)");
+    (void)gamma_h_of(beta, c->mh);
+}
+
+// Number of systems per chunk that fit the work-space budget.
+int systems_per_chunk(dda_ctx* c, int n_energy, int n_traj, bool mixed) {
+    size_t free_b = 0, total_b = 0;
+    DDA_HIP_CHECK(hipMemGetInfo(&free_b, &total_b));
+    const size_t dsz = size_t(dda::dgrid_elems(c->g)) * (sizeof(z128) + (mixed ? sizeof(z64) : 0));
+    const size_t per_sys = size_t(n_traj) * slot_bytes(c, mixed) + dsz +
+                           size_t(c->g.n_occ) * (sizeof(z128) + sizeof(z64));
+    const size_t budget = std::min<size_t>(free_b / 10 * 7, size_t(96) << 30);
+    int ns = int(std::max<size_t>(1, budget / std::max<size_t>(per_sys, 1)));
+    ns = std::min(ns, n_energy);
+    ns = std::min(ns, std::max(1, 65535 / std::max(1, n_traj)));
+    return std::max(ns, 1);
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+
+#define DDA_API_BEGIN try {
+#define DDA_API_END                                    \
+    }                                                  \
+    catch (const dda::Error& e) {                      \
+        g_last_error = e.what();                       \
+        return e.status;                               \
+    }                                                  \
+    catch (const std::bad_alloc&) {                    \
+        g_last_error = "host allocation failed";       \
+        return DDA_ENOMEM;                             \
+    }                                                  \
+    catch (const std::exception& e) {                  \
+        g_last_error = e.what();                       \
+        return DDA_EDEVICE;                            \
+    }
+
+extern "C" {
+
+void dda_default_options(dda_options* opt) {
+    if (!opt) return;
+    opt->polarizability = DDA_POL_LDR;
+    opt->solver = DDA_SOLVER_BICGSTAB;
+    opt->precision = DDA_PREC_FP64;
+    opt->tol = 1e-10;
+    opt->maxit = 100000;
+    opt->check_every = 16;
+}
+
+double dda_beta_from_keV(double kinetic_keV) {
+    const double gam = 1.0 + kinetic_keV / kMeC2;
+    return std::sqrt(1.0 - 1.0 / (gam * gam));
+}
+
+const char* dda_last_error(void) { return g_last_error.c_str(); }
+
+int dda_setup(const uint8_t* mask, int nx, int ny, int nz, double d_nm, double mh_re,
+              double mh_im, const dda_options* opt, void* hip_stream, dda_ctx** out) {
+    DDA_API_BEGIN
+    g_last_error.clear();
+    if (!out) throw Error(DDA_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!mask) throw Error(DDA_EINVAL, "mask is NULL");
+    if (nx < 1 || ny < 1 || nz < 1 || nx > kMaxSide || ny > kMaxSide || nz > kMaxSide)
+        throw Error(DDA_EINVAL, "lattice sides must lie in [1, 256]");
+    check_finite(d_nm, "d");
+    check_finite(mh_re, "Re m_h");
+    check_finite(mh_im, "Im m_h");
+    if (d_nm <= 0) throw Error(DDA_EINVAL, "d must be positive");
+    if (!(mh_re > 0.0) || mh_im < 0.0)
+        throw Error(DDA_EINVAL, "host must be passive: Re m_h > 0, Im m_h >= 0");
+    auto c = std::make_unique<dda_ctx>();
+    if (opt) c->opt = *opt; else dda_default_options(&c->opt);
+    if (c->opt.polarizability < 0 || c->opt.polarizability > 2)
+        throw Error(DDA_EINVAL, "unknown polarizability");
+    if (c->opt.solver != DDA_SOLVER_BICGSTAB) throw Error(DDA_EINVAL, "unknown solver");
+    if (c->opt.precision != DDA_PREC_FP64 && c->opt.precision != DDA_PREC_MIXED)
+        throw Error(DDA_EINVAL, "unknown precision");
+    if (!(c->opt.tol > 0.0) || !(c->opt.tol < 1.0)) throw Error(DDA_EINVAL, "tol must lie in (0, 1)");
+    if (c->opt.maxit < 1) throw Error(DDA_EINVAL, "maxit must be >= 1");
+    c->d = d_nm;
+    c->mh = cplx(mh_re, mh_im);
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    dda::Geo& g = c->g;
+    g.nx = nx; g.ny = ny; g.nz = nz;
+    g.mx = choose_fft_len(nx);
+    g.my = choose_fft_len(ny);
+    g.mz = choose_fft_len(nz);
+    const int64_t N = int64_t(nx) * ny * nz;
+    std::vector<int> hmap(size_t(N), -1);
+    for (int64_t i = 0; i < N; ++i) {
+        if (mask[i]) {
+            hmap[size_t(i)] = int(c->occ_lin.size());
+            c->occ_lin.push_back(int(i));
+        }
+    }
+    g.n_occ = int64_t(c->occ_lin.size());
+    c->map.ensure(size_t(N) * sizeof(int));
+    DDA_HIP_CHECK(hipMemcpy(c->map.p, hmap.data(), size_t(N) * sizeof(int), hipMemcpyHostToDevice));
+    c->occ.ensure(std::max<size_t>(1, c->occ_lin.size()) * sizeof(int));
+    if (!c->occ_lin.empty())
+        DDA_HIP_CHECK(hipMemcpy(c->occ.p, c->occ_lin.data(), c->occ_lin.size() * sizeof(int),
+                                hipMemcpyHostToDevice));
+    const int Ls[3] = {g.mx, g.my, g.mz};
+    for (int a = 0; a < 3; ++a) {
+        const int L = Ls[a];
+        std::vector<z128> t128(L);
+        std::vector<z64> t64(L);
+        for (int t = 0; t < L; ++t) {
+            const long double ang = -2.0L * 3.141592653589793238462643383279502884L * t / L;
+            t128[t] = z128{double(cosl(ang)), double(sinl(ang))};
+            t64[t] = z64{float(cosl(ang)), float(sinl(ang))};
+        }
+        c->tw128[a].ensure(L * sizeof(z128));
+        c->tw64[a].ensure(L * sizeof(z64));
+        DDA_HIP_CHECK(hipMemcpy(c->tw128[a].p, t128.data(), L * sizeof(z128), hipMemcpyHostToDevice));
+        DDA_HIP_CHECK(hipMemcpy(c->tw64[a].p, t64.data(), L * sizeof(z64), hipMemcpyHostToDevice));
+    }
+    *out = c.release();
+    return DDA_OK;
+    DDA_API_END
+}
+
+int dda_n_occ(const dda_ctx* ctx, int64_t* n_occ) {
+    if (!ctx || !n_occ) { g_last_error = "NULL argument"; return DDA_EINVAL; }
+    *n_occ = ctx->g.n_occ;
+    return DDA_OK;
+}
+
+int dda_grid_dims(const dda_ctx* ctx, int* mx, int* my, int* mz) {
+    if (!ctx || !mx || !my || !mz) { g_last_error = "NULL argument"; return DDA_EINVAL; }
+    *mx = ctx->g.mx; *my = ctx->g.my; *mz = ctx->g.mz;
+    return DDA_OK;
+}
+
+int dda_einc_electron(dda_ctx* c, int n_energy, const double* energy_eV, double beta,
+                      const double* r0_nm, int n_traj, void* einc_dev) {
+    DDA_API_BEGIN
+    if (!c) throw Error(DDA_EINVAL, "ctx is NULL");
+    if (n_energy < 0 || n_traj < 0) throw Error(DDA_EINVAL, "negative batch size");
+    if (n_energy == 0 || n_traj == 0 || c->g.n_occ == 0) return DDA_OK;
+    if (!energy_eV || !r0_nm || !einc_dev) throw Error(DDA_EINVAL, "NULL argument");
+    check_energies(n_energy, energy_eV);
+    check_beta(c, beta);
+    host_trajectory_check(c, r0_nm, n_traj);
+    const cplx gam = gamma_h_of(beta, c->mh);
+    std::vector<dda::EincSys> sys(n_energy);
+    for (int e = 0; e < n_energy; ++e) {
+        const double k0 = energy_eV[e] / kHbarC;
+        const cplx kt = k0 / (beta * gam);
+        const cplx ig = cplx(0.0, -1.0) / gam;
+        sys[e] = dda::EincSys{k0, kt.real(), kt.imag(), ig.real(), ig.imag()};
+    }
+    const size_t sb = sys.size() * sizeof(dda::EincSys), rb = size_t(n_traj) * 3 * sizeof(double);
+    c->misc.ensure(sb + rb + 64);
+    char* base = c->misc.as<char>();
+    DDA_HIP_CHECK(hipMemcpyAsync(base, sys.data(), sb, hipMemcpyHostToDevice, c->stream));
+    DDA_HIP_CHECK(hipMemcpyAsync(base + sb, r0_nm, rb, hipMemcpyHostToDevice, c->stream));
+    dda::launch_einc(static_cast<z128*>(einc_dev), c->occ.as<int>(), c->g, c->d, beta,
+                     reinterpret_cast<dda::EincSys*>(base), reinterpret_cast<double*>(base + sb),
+                     n_energy, n_traj, c->stream);
+    DDA_HIP_CHECK(hipStreamSynchronize(c->stream));  // host vectors go out of scope
+    return DDA_OK;
+    DDA_API_END
+}
+
+int dda_solve(dda_ctx* c, int n_energy, const double* energy_eV, const double* eps_dipole,
+              const void* einc_dev, int n_traj, void* p_dev, dda_solve_info* info) {
+    DDA_API_BEGIN
+    if (!c) throw Error(DDA_EINVAL, "ctx is NULL");
+    if (n_energy < 0 || n_traj < 0) throw Error(DDA_EINVAL, "negative batch size");
+    const int64_t nrhs = int64_t(n_energy) * n_traj;
+    if (nrhs == 0) return DDA_OK;
+    if (c->g.n_occ == 0) {
+        if (info)
+            for (int64_t i = 0; i < nrhs; ++i) info[i] = dda_solve_info{0, 0, 0.0, DDA_OK};
+        return DDA_OK;
+    }
+    if (!energy_eV || !eps_dipole || !einc_dev || !p_dev) throw Error(DDA_EINVAL, "NULL argument");
+    check_energies(n_energy, energy_eV);
+    const bool mixed = c->opt.precision == DDA_PREC_MIXED;
+    const int64_t nv = c->nv();
+    const int spc = systems_per_chunk(c, n_energy, n_traj, mixed);
+    int overall = DDA_OK;
+    for (int e0 = 0; e0 < n_energy; e0 += spc) {
+        const int ns = std::min(spc, n_energy - e0);
+        const int nslots = ns * n_traj;
+        ensure_slots(c, nslots);
+        // slot -> chunk-local system
+        {
+            std::vector<int> ss(nslots);
+            for (int i = 0; i < nslots; ++i) ss[i] = i / n_traj;
+            upload(c, c->slot_sys.p, ss.data(), ss.size() * sizeof(int));
+        }
+        std::vector<DEntry*> ents;
+        c->pin_clock = c->use_clock + 1;
+        for (int s = 0; s < ns; ++s) ents.push_back(get_D(c, energy_eV[e0 + s], mixed));
+        upload_ainv(c, energy_eV, eps_dipole, e0, ns, mixed);
+        c->G.ensure(size_t(nslots) * dda::grid_elems(c->g) * sizeof(z128));
+        const auto* b = static_cast<const z128*>(einc_dev) + int64_t(e0) * n_traj * nv;
+        auto* x = static_cast<z128*>(p_dev) + int64_t(e0) * n_traj * nv;
+        std::vector<int> iters, mvs, status;
+        std::vector<double> relres;
+        if (!mixed) {
+            c->vec128.ensure(size_t(6) * nslots * nv * sizeof(z128));
+            auto* V = c->vec128.as<z128>();
+            const size_t q = size_t(nslots) * nv;
+            Vecs<double> w{V, V + q, V + 2 * q, V + 3 * q, V + 4 * q, V + 5 * q};
+            auto dptr = upload_dptrs<double>(c, ents);
+            run_bicgstab<double>(c, nslots, b, x, w, c->opt.tol, c->opt.maxit, true, dptr,
+                                 c->ainv128.as<z128>(), iters, mvs, status, relres);
+        } else {
+            auto dptr64 = upload_dptrs<double>(c, ents);
+            auto dptr32 = upload_dptrs<float>(c, ents);
+            run_mixed(c, nslots, b, x, dptr64, dptr32, iters, mvs, status, relres);
+        }
+        for (int i = 0; i < nslots; ++i) {
+            if (info) info[int64_t(e0) * n_traj + i] = dda_solve_info{iters[i], mvs[i], relres[i], status[i]};
+            if (status[i] != DDA_OK && overall == DDA_OK) overall = status[i];
+        }
+    }
+    DDA_HIP_CHECK(hipStreamSynchronize(c->stream));
+    if (overall != DDA_OK) {
+        g_last_error = overall == DDA_ENOCONV ? "iteration limit reached before the tolerance"
+                                              : "Krylov breakdown";
+    }
+    return overall;
+    DDA_API_END
+}
+
+int dda_eels_cl(dda_ctx* c, int n_energy, const double* energy_eV, double beta,
+                const double* eps_dipole, const double* r0_nm, int n_traj, const void* einc_dev,
+                const void* p_dev, dda_result* out) {
+    DDA_API_BEGIN
+    if (!c) throw Error(DDA_EINVAL, "ctx is NULL");
+    if (n_energy < 0 || n_traj < 0) throw Error(DDA_EINVAL, "negative batch size");
+    const int64_t nrhs = int64_t(n_energy) * n_traj;
+    if (nrhs == 0) return DDA_OK;
+    if (!out) throw Error(DDA_EINVAL, "out is NULL");
+    if (c->g.n_occ == 0) {
+        for (int64_t i = 0; i < nrhs; ++i) out[i] = dda_result{0, 0, 0, 0};
+        return DDA_OK;
+    }
+    if (!energy_eV || !eps_dipole || !r0_nm || !einc_dev || !p_dev)
+        throw Error(DDA_EINVAL, "NULL argument");
+    check_energies(n_energy, energy_eV);
+    check_beta(c, beta);
+    const cplx gam = gamma_h_of(beta, c->mh);
+    const cplx mh = c->mh;
+    const bool real_host = mh.imag() == 0.0;
+    const int64_t n = c->g.n_occ, nv = c->nv();
+    const int spc = systems_per_chunk(c, n_energy, n_traj, false);
+    for (int e0 = 0; e0 < n_energy; e0 += spc) {
+        const int ns = std::min(spc, n_energy - e0);
+        const int nslots = ns * n_traj;
+        ensure_slots(c, nslots);
+        {
+            std::vector<int> ss(nslots);
+            for (int i = 0; i < nslots; ++i) ss[i] = i / n_traj;
+            upload(c, c->slot_sys.p, ss.data(), ss.size() * sizeof(int));
+        }
+        std::vector<DEntry*> ents;
+        c->pin_clock = c->use_clock + 1;
+        for (int s = 0; s < ns; ++s) ents.push_back(get_D(c, energy_eV[e0 + s], false));
+        upload_ainv(c, energy_eV, eps_dipole, e0, ns, false);
+        // absorption weights and omega/v per system
+        std::vector<double> wts(size_t(ns) * n), kv(ns);
+        for (int s = 0; s < ns; ++s) {
+            const double E = energy_eV[e0 + s];
+            const double k0 = E / kHbarC;
+            kv[s] = k0 / beta;
+            const cplx k = mh * k0;
+            for (int64_t i = 0; i < n; ++i) {
+                cplx ep;
+                read_eps(eps_dipole, int64_t(e0 + s) * n + i, ep);
+                if (real_host) {
+                    const cplx a = polarizability(c->opt.polarizability, ep, mh, c->d, k);
+                    const double kr = k.real();
+                    wts[size_t(s) * n + i] = -(1.0 / a).imag() - (2.0 / 3.0) * kr * kr * kr;
+                } else {
+                    const cplx m2 = ep / (mh * mh);
+                    const double d3 = c->d * c->d * c->d;
+                    wts[size_t(s) * n + i] =
+                        4.0 * kPi * (mh * mh * m2).imag() / (std::norm(m2 - 1.0) * d3);
+                }
+            }
+        }
+        c->G.ensure(size_t(nslots) * dda::grid_elems(c->g) * sizeof(z128));
+        c->vec128.ensure(size_t(nslots) * nv * sizeof(z128));
+        const size_t wb = wts.size() * sizeof(double), kb = kv.size() * sizeof(double);
+        const size_t rb = size_t(n_traj) * 3 * sizeof(double), ob = size_t(nslots) * 8 * sizeof(double);
+        c->misc.ensure(wb + kb + rb + ob + 256);
+        char* base = c->misc.as<char>();
+        double* dw = reinterpret_cast<double*>(base);
+        double* dkv = reinterpret_cast<double*>(base + wb);
+        double* dr0 = reinterpret_cast<double*>(base + wb + kb);
+        double* dout = reinterpret_cast<double*>(base + wb + kb + rb);
+        DDA_HIP_CHECK(hipMemcpyAsync(dw, wts.data(), wb, hipMemcpyHostToDevice, c->stream));
+        DDA_HIP_CHECK(hipMemcpyAsync(dkv, kv.data(), kb, hipMemcpyHostToDevice, c->stream));
+        DDA_HIP_CHECK(hipMemcpyAsync(dr0, r0_nm, rb, hipMemcpyHostToDevice, c->stream));
+        const auto* P = static_cast<const z128*>(p_dev) + int64_t(e0) * n_traj * nv;
+        auto dptr = upload_dptrs<double>(c, ents);
+        auto* Y = c->vec128.as<z128>();
+        matvec<double>(c, P, Y, nullptr, nslots, dptr, c->slot_sys.as<int>(), c->ainv128.as<z128>(),
+                       true);
+        dda::loss_sums(static_cast<const z128*>(einc_dev), static_cast<const z128*>(p_dev), Y, dw,
+                       c->occ.as<int>(), c->g, c->d, dkv, dr0, n_traj, int64_t(e0) * n_traj,
+                       nslots, dout, red_of(c), c->stream);
+        std::vector<double> sums(size_t(nslots) * 8);
+        DDA_HIP_CHECK(hipMemcpyAsync(sums.data(), dout, ob, hipMemcpyDeviceToHost, c->stream));
+        DDA_HIP_CHECK(hipStreamSynchronize(c->stream));
+        for (int i = 0; i < nslots; ++i) {
+            const int s = i / n_traj;
+            const double E = energy_eV[e0 + s];
+            const double k0 = E / kHbarC;
+            const double Pi = 4.0 * kAlphaFs * k0 * k0 / (kPi * kHbarC * std::pow(beta, 4));
+            const double* q = &sums[size_t(i) * 8];
+            const cplx Sa(q[0], q[1]), Se(q[2], q[3]), Spy(q[5], q[6]);
+            const double Sw = q[4], Spp = q[7];
+            const double g2 = std::norm(gam), mh4 = std::norm(mh * mh);
+            dda_result r;
+            r.p_eels = -Pi * (Sa / ((mh * gam) * (mh * gam))).imag();
+            r.p_ext = Pi * (mh * mh * Se).imag() / (mh4 * g2);
+            if (real_host) r.p_abs = Pi / (mh.real() * mh.real() * g2) * Sw;
+            else r.p_abs = Pi / (mh4 * g2) * Sw;
+            const double kr = (mh * k0).real();
+            r.p_cl = Pi * (mh * mh).real() / (mh4 * g2) * (Spy.imag() + (2.0 / 3.0) * kr * kr * kr * Spp);
+            out[int64_t(e0) * n_traj + i] = r;
+        }
+    }
+    return DDA_OK;
+    DDA_API_END
+}
+
+int dda_matvec(dda_ctx* c, double energy_eV, const double* eps_dipole, int precision,
+               int interaction_only, const void* x_dev, void* y_dev, int nrhs) {
+    DDA_API_BEGIN
+    if (!c) throw Error(DDA_EINVAL, "ctx is NULL");
+    if (nrhs < 0) throw Error(DDA_EINVAL, "nrhs < 0");
+    if (nrhs == 0 || c->g.n_occ == 0) return DDA_OK;
+    if (!x_dev || !y_dev || (!interaction_only && !eps_dipole)) throw Error(DDA_EINVAL, "NULL argument");
+    if (nrhs > 65535) throw Error(DDA_EINVAL, "nrhs > 65535");
+    check_energies(1, &energy_eV);
+    const bool fp32 = precision == DDA_PREC_MIXED;
+    if (precision != DDA_PREC_FP64 && precision != DDA_PREC_MIXED) throw Error(DDA_EINVAL, "bad precision");
+    ensure_slots(c, nrhs);
+    std::vector<int> ss(nrhs, 0);
+    upload(c, c->slot_sys.p, ss.data(), ss.size() * sizeof(int));
+    c->pin_clock = c->use_clock + 1;
+    std::vector<DEntry*> ents{get_D(c, energy_eV, fp32)};
+    if (!interaction_only) {
+        upload_ainv(c, &energy_eV, eps_dipole, 0, 1, fp32);
+    } else {
+        c->ainv128.ensure(size_t(c->g.n_occ) * sizeof(z128));
+        c->ainv64.ensure(size_t(c->g.n_occ) * sizeof(z64));
+    }
+    c->G.ensure(size_t(nrhs) * dda::grid_elems(c->g) * sizeof(z128));
+    if (!fp32) {
+        auto dptr = upload_dptrs<double>(c, ents);
+        matvec<double>(c, static_cast<const z128*>(x_dev), static_cast<z128*>(y_dev), nullptr, nrhs,
+                       dptr, c->slot_sys.as<int>(), c->ainv128.as<z128>(), interaction_only != 0);
+    } else {
+        auto dptr = upload_dptrs<float>(c, ents);
+        matvec<float>(c, static_cast<const z64*>(x_dev), static_cast<z64*>(y_dev), nullptr, nrhs,
+                      dptr, c->slot_sys.as<int>(), c->ainv64.as<z64>(), interaction_only != 0);
+    }
+    return DDA_OK;
+    DDA_API_END
+}
+
+int dda_set_timing(dda_ctx* c, int enabled) {
+    DDA_API_BEGIN
+    if (!c) throw Error(DDA_EINVAL, "ctx is NULL");
+    flush_timer(c);
+    c->timing = enabled != 0;
+    for (int k = 0; k < 5; ++k) { c->timer.total_ms[k] = 0; c->timer.count[k] = 0; }
+    return DDA_OK;
+    DDA_API_END
+}
+
+int dda_kernel_time(dda_ctx* c, const char* name, double* avg_ms, int64_t* launches) {
+    DDA_API_BEGIN
+    if (!c || !name || !avg_ms || !launches) throw Error(DDA_EINVAL, "NULL argument");
+    flush_timer(c);
+    for (int k = 0; k < 5; ++k) {
+        if (std::strcmp(name, kKernelNames[k]) == 0) {
+            *launches = c->timer.count[k];
+            *avg_ms = c->timer.count[k] ? c->timer.total_ms[k] / double(c->timer.count[k]) : 0.0;
+            return DDA_OK;
+        }
+    }
+    throw Error(DDA_EINVAL, "unknown kernel name");
+    DDA_API_END
+}
+
+int dda_destroy(dda_ctx* c) {
+    DDA_API_BEGIN
+    if (!c) return DDA_OK;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    else (void)hipDeviceSynchronize();
+    delete c;
+    return DDA_OK;
+    DDA_API_END
+}
+
+int dda_debug_besselk01(const double* z, int64_t n, double* k0k1) {
+    DDA_API_BEGIN
+    if (n < 0 || (n > 0 && (!z || !k0k1))) throw Error(DDA_EINVAL, "bad arguments");
+    if (n == 0) return DDA_OK;
+    DevBuf dz, d0, d1;
+    dz.ensure(size_t(n) * sizeof(z128));
+    d0.ensure(size_t(n) * sizeof(z128));
+    d1.ensure(size_t(n) * sizeof(z128));
+    DDA_HIP_CHECK(hipMemcpy(dz.p, z, size_t(n) * sizeof(z128), hipMemcpyHostToDevice));
+    dda::launch_besselk01(dz.as<z128>(), d0.as<z128>(), d1.as<z128>(), n, nullptr);
+    std::vector<z128> h0(n), h1(n);
+    DDA_HIP_CHECK(hipMemcpy(h0.data(), d0.p, size_t(n) * sizeof(z128), hipMemcpyDeviceToHost));
+    DDA_HIP_CHECK(hipMemcpy(h1.data(), d1.p, size_t(n) * sizeof(z128), hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < n; ++i) {
+        k0k1[4 * i] = h0[i].x;
+        k0k1[4 * i + 1] = h0[i].y;
+        k0k1[4 * i + 2] = h1[i].x;
+        k0k1[4 * i + 3] = h1[i].y;
+    }
+    return DDA_OK;
+    DDA_API_END
+}
+
+}  // extern "C"

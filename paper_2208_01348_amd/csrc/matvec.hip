@@ -1,0 +1,458 @@
+// FFT matvec chain of the DDA operator on gfx950, and the interaction
+// spectrum D it multiplies by.
+//
+// The DDA operator (A x)_i = x_i/alpha_i - sum_{j != i} G(r_i - r_j) x_j has a
+// block-Toeplitz interaction part on the cubic lattice.  Embedding it in a
+// circulant of size mx x my x mz (each >= 2n - 1) turns it into a 3D cyclic
+// convolution: zero-pad x, forward FFT, multiply by the 3x3 symmetric
+// spectrum D at every frequency, inverse FFT, keep the lattice part.
+//
+// The 3D transforms are done axis by axis so that every pass streams HBM
+// once, and each pass skips what the zero padding makes trivial:
+//   K1 unpack + x-FFT : rows (z<nz, y<ny) gathered from the compact vector
+//   K2 y-FFT          : columns of the nz planes, ny non-zero inputs
+//   K3 z-conv         : z-FFT of nz inputs, D multiply, z-iFFT keeping nz
+//   K4 y-iFFT         : keep ny outputs
+//   K5 x-iFFT + pack  : keep nx outputs, scatter to occupied cells, add x/alpha
+// Lines are staged in LDS in tiles whose global rows are contiguous
+// (coalesced), and transformed there by the compile-time planned Stockham
+// kernels of fft_core.h.
+#include <algorithm>
+
+#include "fft_core.h"
+#include "kernels.h"
+
+namespace dda {
+
+constexpr int NTHR = 256;
+
+constexpr int pow2floor(int v) {
+    int p = 1;
+    while (p * 2 <= v) p *= 2;
+    return p;
+}
+constexpr int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// rows per block for row kernels (about 2048 elements per block)
+template <typename T, int L>
+constexpr int rows_nl() { return L >= 2048 ? 1 : 2048 / L; }
+// columns per block for strided-axis kernels
+template <typename T, int L>
+constexpr int mid_tx() { return clampi(pow2floor(2048 / L), 1, sizeof(T) == 8 ? 16 : 32); }
+template <typename T, int L>
+constexpr int zconv_tx() {
+    return clampi(pow2floor((sizeof(T) == 8 ? 1024 : 2048) / L), 1, sizeof(T) == 8 ? 16 : 32);
+}
+
+#define DDA_FOR_EACH_L(X) \
+    X(1) X(2) X(3) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
+
+bool fft_length_supported(int L) {
+    switch (L) {
+#define DDA_CASE(N) case N:
+        DDA_FOR_EACH_L(DDA_CASE)
+#undef DDA_CASE
+        return true;
+        default:
+            return false;
+    }
+}
+
+// ---------------------------------------------------------------- K1 ------
+template <typename T, int L>
+__global__ __launch_bounds__(NTHR) void k_unpack_xfft(const cx<T>* __restrict__ xin,
+                                                      const int* __restrict__ map,
+                                                      cx<T>* __restrict__ G,
+                                                      const cx<T>* __restrict__ tw, Geo g,
+                                                      const int* __restrict__ act) {
+    constexpr int NL = rows_nl<T, L>();
+    __shared__ cx<T> lds[NL * L];
+    const int tid = threadIdx.x;
+    const int c = blockIdx.y;
+    const int pos = blockIdx.z;
+    const int64_t slot = act ? act[pos] : pos;
+    const int nrows = g.nz * g.ny;
+    const int row0 = blockIdx.x * NL;
+    const cx<T>* src = xin + (slot * 3 + c) * g.n_occ;
+    for (int e = tid; e < NL * L; e += NTHR) {
+        const int rr = e / L, x = e % L;
+        const int row = row0 + rr;
+        cx<T> v{T(0), T(0)};
+        if (row < nrows && x < g.nx) {
+            const int idx = map[int64_t(row) * g.nx + x];
+            if (idx >= 0) v = src[idx];
+        }
+        lds[e] = v;
+    }
+    __syncthreads();
+    fft_tile<T, L, false, NL, L, 1, NTHR>(lds, tw, tid);
+    cx<T>* dst = G + (int64_t(pos) * 3 + c) * g.nz * g.my * int64_t(g.mx);
+    for (int e = tid; e < NL * L; e += NTHR) {
+        const int rr = e / L, x = e % L;
+        const int row = row0 + rr;
+        if (row < nrows) {
+            const int z = row / g.ny, y = row - z * g.ny;
+            dst[(int64_t(z) * g.my + y) * g.mx + x] = lds[e];
+        }
+    }
+}
+
+// ------------------------------------------------------------ K2 / K4 -----
+// FFT along the middle axis of data[outer][L][inner]: the first n_in rows are
+// read (the rest are zero), the first n_out rows are written.
+template <typename T, int L, bool INV>
+__global__ __launch_bounds__(NTHR) void k_fft_mid(cx<T>* __restrict__ data,
+                                                  const cx<T>* __restrict__ tw, int64_t inner,
+                                                  int n_in, int n_out, int64_t outer_stride,
+                                                  int64_t tiles_per_outer) {
+    constexpr int TX = mid_tx<T, L>();
+    __shared__ cx<T> lds[L * TX];
+    const int tid = threadIdx.x;
+    const int64_t o = blockIdx.x / tiles_per_outer;
+    const int64_t col0 = (blockIdx.x - o * tiles_per_outer) * TX;
+    cx<T>* base = data + o * outer_stride + col0;
+    for (int e = tid; e < L * TX; e += NTHR) {
+        const int row = e / TX, col = e % TX;
+        cx<T> v{T(0), T(0)};
+        if (row < n_in && col0 + col < inner) v = base[int64_t(row) * inner + col];
+        lds[e] = v;
+    }
+    __syncthreads();
+    fft_tile<T, L, INV, TX, 1, TX, NTHR>(lds, tw, tid);
+    for (int e = tid; e < n_out * TX; e += NTHR) {
+        const int row = e / TX, col = e % TX;
+        if (col0 + col < inner) base[int64_t(row) * inner + col] = lds[e];
+    }
+}
+
+// ---------------------------------------------------------------- K3 ------
+// Per (kx tile, ky, slot): z-FFT of the three components (nz non-zero
+// inputs), w = D u with D the symmetric 3x3 spectrum, z-iFFT, keep nz rows.
+template <typename T, int L>
+__global__ __launch_bounds__(NTHR) void k_zconv(cx<T>* __restrict__ G,
+                                                const cx<T>* const* __restrict__ Dptr,
+                                                const cx<T>* __restrict__ tw, Geo g,
+                                                const int* __restrict__ act,
+                                                const int* __restrict__ slot_sys) {
+    constexpr int TX = zconv_tx<T, L>();
+    constexpr int W = 3 * TX;  // lines per tile: (component, column)
+    __shared__ cx<T> lds[L * W];
+    const int tid = threadIdx.x;
+    const int col0 = blockIdx.x * TX;
+    const int ky = blockIdx.y;
+    const int pos = blockIdx.z;
+    const int slot = act ? act[pos] : pos;
+    const int sys = slot_sys[slot];
+    const int64_t plane = int64_t(g.my) * g.mx;
+    cx<T>* gbase = G + int64_t(pos) * 3 * g.nz * plane + int64_t(ky) * g.mx + col0;
+    for (int e = tid; e < L * W; e += NTHR) {
+        const int z = e / W, rem = e % W, c = rem / TX, col = rem % TX;
+        cx<T> v{T(0), T(0)};
+        if (z < g.nz && col0 + col < g.mx) v = gbase[(int64_t(c) * g.nz + z) * plane + col];
+        lds[e] = v;
+    }
+    __syncthreads();
+    fft_tile<T, L, false, W, 1, W, NTHR>(lds, tw, tid);
+    const cx<T>* dbase = Dptr[sys] + int64_t(ky) * g.mx + col0;
+    const int64_t dcomp = int64_t(g.mz) * plane;
+    for (int e = tid; e < L * TX; e += NTHR) {
+        const int kz = e / TX, col = e % TX;
+        if (col0 + col < g.mx) {
+            const cx<T>* dp = dbase + int64_t(kz) * plane + col;
+            const cx<T> dxx = dp[0], dxy = dp[dcomp], dxz = dp[2 * dcomp];
+            const cx<T> dyy = dp[3 * dcomp], dyz = dp[4 * dcomp], dzz = dp[5 * dcomp];
+            cx<T>* u = lds + kz * W + col;
+            const cx<T> ux = u[0], uy = u[TX], uz = u[2 * TX];
+            u[0] = dxx * ux + dxy * uy + dxz * uz;
+            u[TX] = dxy * ux + dyy * uy + dyz * uz;
+            u[2 * TX] = dxz * ux + dyz * uy + dzz * uz;
+        }
+    }
+    __syncthreads();
+    fft_tile<T, L, true, W, 1, W, NTHR>(lds, tw, tid);
+    for (int e = tid; e < g.nz * W; e += NTHR) {
+        const int z = e / W, rem = e % W, c = rem / TX, col = rem % TX;
+        if (col0 + col < g.mx) gbase[(int64_t(c) * g.nz + z) * plane + col] = lds[e];
+    }
+}
+
+// ---------------------------------------------------------------- K5 ------
+template <typename T, int L, bool INTERACTION_ONLY>
+__global__ __launch_bounds__(NTHR) void k_ixfft_pack(const cx<T>* __restrict__ G,
+                                                     const cx<T>* __restrict__ xin,
+                                                     const cx<T>* __restrict__ ainv,
+                                                     cx<T>* __restrict__ yout,
+                                                     const int* __restrict__ map,
+                                                     const cx<T>* __restrict__ tw, Geo g,
+                                                     const int* __restrict__ act,
+                                                     const int* __restrict__ slot_sys) {
+    constexpr int NL = rows_nl<T, L>();
+    __shared__ cx<T> lds[NL * L];
+    const int tid = threadIdx.x;
+    const int c = blockIdx.y;
+    const int pos = blockIdx.z;
+    const int64_t slot = act ? act[pos] : pos;
+    const int64_t sys = slot_sys[slot];
+    const int nrows = g.nz * g.ny;
+    const int row0 = blockIdx.x * NL;
+    const cx<T>* gsrc = G + (int64_t(pos) * 3 + c) * g.nz * g.my * int64_t(g.mx);
+    for (int e = tid; e < NL * L; e += NTHR) {
+        const int rr = e / L, x = e % L;
+        const int row = row0 + rr;
+        cx<T> v{T(0), T(0)};
+        if (row < nrows) {
+            const int z = row / g.ny, y = row - z * g.ny;
+            v = gsrc[(int64_t(z) * g.my + y) * g.mx + x];
+        }
+        lds[e] = v;
+    }
+    __syncthreads();
+    fft_tile<T, L, true, NL, L, 1, NTHR>(lds, tw, tid);
+    const int64_t voff = (slot * 3 + c) * g.n_occ;
+    for (int e = tid; e < NL * L; e += NTHR) {
+        const int rr = e / L, x = e % L;
+        const int row = row0 + rr;
+        if (row < nrows && x < g.nx) {
+            const int idx = map[int64_t(row) * g.nx + x];
+            if (idx >= 0) {
+                const cx<T> conv = lds[e];
+                if (INTERACTION_ONLY) {
+                    yout[voff + idx] = conv;
+                } else {
+                    yout[voff + idx] = xin[voff + idx] * ainv[sys * g.n_occ + idx] - conv;
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------ launchers ---
+static inline unsigned nblk(int64_t n, int64_t per) { return unsigned((n + per - 1) / per); }
+
+template <typename T>
+void launch_unpack_xfft(const cx<T>* xin, const int* map, cx<T>* G, const cx<T>* tw_x,
+                        const Geo& g, const int* act, int n_act, hipStream_t s) {
+    if (n_act == 0) return;
+    const int64_t nrows = int64_t(g.nz) * g.ny;
+    switch (g.mx) {
+#define DDA_CASE(N)                                                                    \
+    case N: {                                                                          \
+        dim3 grid(nblk(nrows, rows_nl<T, N>()), 3, n_act);                             \
+        k_unpack_xfft<T, N><<<grid, NTHR, 0, s>>>(xin, map, G, tw_x, g, act);           \
+        break;                                                                         \
+    }
+        DDA_FOR_EACH_L(DDA_CASE)
+#undef DDA_CASE
+        default:
+            throw Error(-1, "unsupported FFT length along x");
+    }
+    DDA_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_fft_mid(cx<T>* data, const cx<T>* tw, int L, bool inverse, int64_t n_outer,
+                    int64_t inner, int n_in, int n_out, int64_t outer_stride, hipStream_t s) {
+    switch (L) {
+#define DDA_CASE(N)                                                                        \
+    case N: {                                                                              \
+        const int64_t tiles = (inner + mid_tx<T, N>() - 1) / mid_tx<T, N>();               \
+        dim3 grid(unsigned(tiles * n_outer));                                              \
+        if (inverse)                                                                       \
+            k_fft_mid<T, N, true><<<grid, NTHR, 0, s>>>(data, tw, inner, n_in, n_out,      \
+                                                        outer_stride, tiles);              \
+        else                                                                               \
+            k_fft_mid<T, N, false><<<grid, NTHR, 0, s>>>(data, tw, inner, n_in, n_out,     \
+                                                         outer_stride, tiles);             \
+        break;                                                                             \
+    }
+        DDA_FOR_EACH_L(DDA_CASE)
+#undef DDA_CASE
+        default:
+            throw Error(-1, "unsupported FFT length");
+    }
+    DDA_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_zconv(cx<T>* G, const cx<T>* const* Dptr, const cx<T>* tw_z, const Geo& g,
+                  const int* act, const int* slot_sys, int n_act, hipStream_t s) {
+    if (n_act == 0) return;
+    switch (g.mz) {
+#define DDA_CASE(N)                                                                    \
+    case N: {                                                                          \
+        dim3 grid(nblk(g.mx, zconv_tx<T, N>()), g.my, n_act);                           \
+        k_zconv<T, N><<<grid, NTHR, 0, s>>>(G, Dptr, tw_z, g, act, slot_sys);           \
+        break;                                                                         \
+    }
+        DDA_FOR_EACH_L(DDA_CASE)
+#undef DDA_CASE
+        default:
+            throw Error(-1, "unsupported FFT length along z");
+    }
+    DDA_LAUNCH_CHECK();
+}
+
+template <typename T>
+void launch_ixfft_pack(const cx<T>* G, const cx<T>* xin, const cx<T>* ainv, cx<T>* yout,
+                       const int* map, const cx<T>* tw_x, const Geo& g, const int* act,
+                       const int* slot_sys, int n_act, bool interaction_only, hipStream_t s) {
+    if (n_act == 0) return;
+    const int64_t nrows = int64_t(g.nz) * g.ny;
+    switch (g.mx) {
+#define DDA_CASE(N)                                                                        \
+    case N: {                                                                              \
+        dim3 grid(nblk(nrows, rows_nl<T, N>()), 3, n_act);                                 \
+        if (interaction_only)                                                              \
+            k_ixfft_pack<T, N, true><<<grid, NTHR, 0, s>>>(G, xin, ainv, yout, map, tw_x,   \
+                                                           g, act, slot_sys);              \
+        else                                                                               \
+            k_ixfft_pack<T, N, false><<<grid, NTHR, 0, s>>>(G, xin, ainv, yout, map, tw_x,  \
+                                                            g, act, slot_sys);             \
+        break;                                                                             \
+    }
+        DDA_FOR_EACH_L(DDA_CASE)
+#undef DDA_CASE
+        default:
+            throw Error(-1, "unsupported FFT length along x");
+    }
+    DDA_LAUNCH_CHECK();
+}
+
+template void launch_unpack_xfft<double>(const z128*, const int*, z128*, const z128*, const Geo&,
+                                         const int*, int, hipStream_t);
+template void launch_unpack_xfft<float>(const z64*, const int*, z64*, const z64*, const Geo&,
+                                        const int*, int, hipStream_t);
+template void launch_fft_mid<double>(z128*, const z128*, int, bool, int64_t, int64_t, int, int,
+                                     int64_t, hipStream_t);
+template void launch_fft_mid<float>(z64*, const z64*, int, bool, int64_t, int64_t, int, int,
+                                    int64_t, hipStream_t);
+template void launch_zconv<double>(z128*, const z128* const*, const z128*, const Geo&, const int*,
+                                   const int*, int, hipStream_t);
+template void launch_zconv<float>(z64*, const z64* const*, const z64*, const Geo&, const int*,
+                                  const int*, int, hipStream_t);
+template void launch_ixfft_pack<double>(const z128*, const z128*, const z128*, z128*,
+                                        const int*, const z128*, const Geo&, const int*,
+                                        const int*, int, bool, hipStream_t);
+template void launch_ixfft_pack<float>(const z64*, const z64*, const z64*, z64*, const int*,
+                                       const z64*, const Geo&, const int*, const int*, int, bool,
+                                       hipStream_t);
+
+// ------------------------------------------------------------ D build -----
+// G_tilde(R) = exp(ikR)/R^3 [(k^2R^2 + ikR - 1) I + (3 - 3ikR - k^2R^2) Rh Rh]
+// at every point of the embedding grid: grid index m along an axis of n cells
+// and size M stands for the offset m (m <= n-1) or m - M (m >= M - n + 1);
+// the remaining indices, and the zero offset, hold 0.  Pre-scaled by
+// 1/(mx my mz) so that the inverse FFTs of the matvec need no scaling.
+__device__ __forceinline__ bool embed_offset(int m, int n, int M, int& off) {
+    if (m <= n - 1) { off = m; return true; }
+    if (m >= M - (n - 1)) { off = m - M; return true; }
+    return false;
+}
+
+__global__ __launch_bounds__(NTHR) void k_gtens(z128* __restrict__ D, Geo g, double d,
+                                                double k_re, double k_im, double scale) {
+    const int64_t plane = int64_t(g.my) * g.mx;
+    const int64_t total = plane * g.mz;
+    for (int64_t t = blockIdx.x * int64_t(NTHR) + threadIdx.x; t < total;
+         t += int64_t(gridDim.x) * NTHR) {
+        const int mz = int(t / plane);
+        const int64_t rem = t - mz * plane;
+        const int my = int(rem / g.mx), mx = int(rem - int64_t(my) * g.mx);
+        int ox, oy, oz;
+        z128 v[6];
+        for (int q = 0; q < 6; ++q) v[q] = z128{0.0, 0.0};
+        if (embed_offset(mx, g.nx, g.mx, ox) && embed_offset(my, g.ny, g.my, oy) &&
+            embed_offset(mz, g.nz, g.mz, oz) && (ox | oy | oz) != 0) {
+            const double rx = d * ox, ry = d * oy, rz = d * oz;
+            const double r2 = rx * rx + ry * ry + rz * rz;
+            const double r = sqrt(r2);
+            const double hx = rx / r, hy = ry / r, hz = rz / r;
+            // kr = k r (complex), e = exp(i k r) / r^3
+            const z128 kr{k_re * r, k_im * r};
+            double sn, cs;
+            sincos(kr.x, &sn, &cs);
+            const double mag = exp(-kr.y) / (r2 * r);
+            const z128 e{mag * cs, mag * sn};
+            const z128 kr2 = kr * kr;
+            const z128 a = e * z128{kr2.x - 1.0 - kr.y, kr2.y + kr.x};          // k2r2 + ikr - 1
+            const z128 b = e * z128{3.0 - kr2.x + 3.0 * kr.y, -3.0 * kr.x - kr2.y};  // 3 - 3ikr - k2r2
+            const double h[3] = {hx, hy, hz};
+            int q = 0;
+            for (int i = 0; i < 3; ++i)
+                for (int j = i; j < 3; ++j) {
+                    z128 val = (h[i] * h[j]) * b;
+                    if (i == j) val = val + a;
+                    v[q++] = scale * val;
+                }
+        }
+        for (int q = 0; q < 6; ++q) D[q * total + t] = v[q];
+    }
+}
+
+template <int L>
+__global__ __launch_bounds__(NTHR) void k_fft_rows(z128* __restrict__ data,
+                                                   const z128* __restrict__ tw, int64_t nrows) {
+    constexpr int NL = rows_nl<double, L>();
+    __shared__ z128 lds[NL * L];
+    const int tid = threadIdx.x;
+    const int64_t row0 = int64_t(blockIdx.x) * NL;
+    for (int e = tid; e < NL * L; e += NTHR) {
+        const int rr = e / L;
+        lds[e] = (row0 + rr < nrows) ? data[row0 * L + e] : z128{0.0, 0.0};
+    }
+    __syncthreads();
+    fft_tile<double, L, false, NL, L, 1, NTHR>(lds, tw, tid);
+    for (int e = tid; e < NL * L; e += NTHR) {
+        const int rr = e / L;
+        if (row0 + rr < nrows) data[row0 * L + e] = lds[e];
+    }
+}
+
+void launch_build_D(z128* D, const Geo& g, double d, double k_re, double k_im,
+                    const z128* tw_x, const z128* tw_y, const z128* tw_z, hipStream_t s) {
+    const int64_t plane = int64_t(g.my) * g.mx;
+    const int64_t total = plane * g.mz;
+    const double scale = 1.0 / double(total);
+    k_gtens<<<nblk(total, NTHR), NTHR, 0, s>>>(D, g, d, k_re, k_im, scale);
+    DDA_LAUNCH_CHECK();
+    const int64_t nrows = 6 * int64_t(g.mz) * g.my;
+    switch (g.mx) {
+#define DDA_CASE(N)                                                                \
+    case N:                                                                        \
+        k_fft_rows<N><<<nblk(nrows, rows_nl<double, N>()), NTHR, 0, s>>>(D, tw_x, nrows); \
+        break;
+        DDA_FOR_EACH_L(DDA_CASE)
+#undef DDA_CASE
+        default:
+            throw Error(-1, "unsupported FFT length along x");
+    }
+    DDA_LAUNCH_CHECK();
+    launch_fft_mid<double>(D, tw_y, g.my, false, 6 * int64_t(g.mz), g.mx, g.my, g.my, plane, s);
+    launch_fft_mid<double>(D, tw_z, g.mz, false, 6, plane, g.mz, g.mz, total, s);
+}
+
+__global__ void k_z128_to_z64(const z128* __restrict__ in, z64* __restrict__ out, int64_t n) {
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x)
+        out[i] = cvt<float>(in[i]);
+}
+__global__ void k_z64_to_z128(const z64* __restrict__ in, z128* __restrict__ out, int64_t n) {
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x)
+        out[i] = cvt<double>(in[i]);
+}
+
+void launch_convert_z128_to_z64(const z128* in, z64* out, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    const unsigned b = unsigned(std::min<int64_t>(nblk(n, NTHR), 65536));
+    k_z128_to_z64<<<b, NTHR, 0, s>>>(in, out, n);
+    DDA_LAUNCH_CHECK();
+}
+void launch_convert_z64_to_z128(const z64* in, z128* out, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    const unsigned b = unsigned(std::min<int64_t>(nblk(n, NTHR), 65536));
+    k_z64_to_z128<<<b, NTHR, 0, s>>>(in, out, n);
+    DDA_LAUNCH_CHECK();
+}
+
+}  // namespace dda

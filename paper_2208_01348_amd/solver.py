@@ -1,0 +1,114 @@
+"""Torch-facing convenience wrapper over the C ABI.
+
+Torch provides device memory and the stream; every step of the path (the
+electron field, the FFT matvecs, the Krylov iterations and the loss sums)
+runs in libdda's HIP kernels.  This module only allocates tensors and passes
+their pointers.
+"""
+
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+_POL = {"ldr": L.DDA_POL_LDR, "cm": L.DDA_POL_CM, "rr": L.DDA_POL_RR}
+_PREC = {"fp64": L.DDA_PREC_FP64, "mixed": L.DDA_PREC_MIXED}
+
+
+@dataclass
+class SolveInfo:
+    iters: int
+    matvecs: int
+    rel_residual: float
+    status: int
+
+
+class DDASolver:
+    """One lattice and host medium on one GPU (the current torch device)."""
+
+    def __init__(self, mask: np.ndarray, d_nm: float, m_h: complex, polarizability: str = "ldr",
+                 precision: str = "fp64", tol: float = 1e-10, maxit: int = 100000,
+                 check_every: int = 16, stream: Optional[torch.cuda.Stream] = None):
+        m = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8))
+        if m.ndim != 3:
+            raise ValueError("mask must be [nz][ny][nx]")
+        self.nz, self.ny, self.nx = m.shape
+        self.d = float(d_nm)
+        self.m_h = complex(m_h)
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        opt = L.dda_default_options()
+        opt.polarizability = _POL[polarizability]
+        opt.precision = _PREC[precision]
+        opt.tol = float(tol)
+        opt.maxit = int(maxit)
+        opt.check_every = int(check_every)
+        self.ctx = L.dda_setup(m, self.nx, self.ny, self.nz, self.d, self.m_h.real,
+                               self.m_h.imag, opt, self.stream.cuda_stream)
+        self.n_occ = L.dda_n_occ(self.ctx)
+        self.grid = L.dda_grid_dims(self.ctx)
+
+    def close(self) -> None:
+        if self.ctx is not None:
+            L.dda_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _field(self, nrhs: int, dtype=torch.complex128) -> torch.Tensor:
+        return torch.empty((nrhs, 3, self.n_occ), dtype=dtype, device=self.device)
+
+    def einc(self, energies: Sequence[float], beta: float, r0: np.ndarray,
+             out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        E = np.atleast_1d(np.asarray(energies, dtype=np.float64))
+        R = np.asarray(r0, dtype=np.float64).reshape(-1, 3)
+        e = out if out is not None else self._field(E.size * R.shape[0])
+        L.dda_einc_electron(self.ctx, E, beta, R, e.data_ptr())
+        return e
+
+    def solve(self, energies: Sequence[float], eps: np.ndarray, einc: torch.Tensor,
+              n_traj: int, out: Optional[torch.Tensor] = None, raise_on_error: bool = True):
+        """eps: complex [n_energy][n_occ] (absolute permittivity per dipole)."""
+        E = np.atleast_1d(np.asarray(energies, dtype=np.float64))
+        p = out if out is not None else self._field(E.size * n_traj)
+        eps = np.asarray(eps, dtype=np.complex128).reshape(E.size, self.n_occ)
+        st, info = L.dda_solve(self.ctx, E, eps, einc.data_ptr(), n_traj, p.data_ptr(),
+                               raise_on_error=raise_on_error)
+        return p, [SolveInfo(*i) for i in info], st
+
+    def losses(self, energies: Sequence[float], beta: float, eps: np.ndarray, r0: np.ndarray,
+               einc: torch.Tensor, p: torch.Tensor) -> np.ndarray:
+        E = np.atleast_1d(np.asarray(energies, dtype=np.float64))
+        eps = np.asarray(eps, dtype=np.complex128).reshape(E.size, self.n_occ)
+        return L.dda_eels_cl(self.ctx, E, beta, eps, r0, einc.data_ptr(), p.data_ptr())
+
+    def matvec(self, energy: float, eps: Optional[np.ndarray], x: torch.Tensor,
+               precision: str = "fp64", interaction_only: bool = False,
+               out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        y = out if out is not None else torch.empty_like(x)
+        L.dda_matvec(self.ctx, energy, eps, _PREC[precision], interaction_only, x.data_ptr(),
+                     y.data_ptr(), x.shape[0])
+        return y
+
+    def spectrum(self, energies: Sequence[float], beta: float, eps: np.ndarray, r0: np.ndarray):
+        """Electron field -> solve -> losses for every (energy, trajectory).
+        Returns (probabilities [n_energy * n_traj][4], solve infos)."""
+        R = np.asarray(r0, dtype=np.float64).reshape(-1, 3)
+        e = self.einc(energies, beta, R)
+        p, info, _ = self.solve(energies, eps, e, R.shape[0])
+        return self.losses(energies, beta, eps, R, e, p), info
+
+    def set_timing(self, enabled: bool) -> None:
+        L.dda_set_timing(self.ctx, enabled)
+
+    def kernel_time(self, name: str):
+        return L.dda_kernel_time(self.ctx, name)
