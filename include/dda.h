@@ -178,11 +178,19 @@ int dda_eels_cl(dda_ctx* ctx, int n_energy, const double* energy_eV, double beta
 int dda_matvec(dda_ctx* ctx, double energy_eV, const double* eps_dipole, int precision,
                int interaction_only, const void* x_dev, void* y_dev, int nrhs);
 
-/* Average device time (ms) and launch count of each matvec kernel since the
- * last reset, measured with HIP events on the context's stream when timing
- * is enabled.  names: "unpack_xfft", "yfft", "zconv", "iyfft", "ixfft_pack". */
+/* Per-kernel timing of the matvec chain, measured with HIP events recorded on
+ * the context's stream around every launch while timing is enabled
+ * (dda_set_timing resets the counters).  For kernel `name` ("unpack_xfft",
+ * "yfft", "zconv", "iyfft", "ixfft_pack"): average device time per launch
+ * (ms), number of launches, and average right-hand sides per launch. */
 int dda_set_timing(dda_ctx* ctx, int enabled);
-int dda_kernel_time(dda_ctx* ctx, const char* name, double* avg_ms, int64_t* launches);
+int dda_kernel_time(dda_ctx* ctx, const char* name, double* avg_ms, int64_t* launches,
+                    double* avg_rhs);
+
+/* Frees the cached interaction spectra D(k) (they are rebuilt on demand).
+ * The context keeps one D per host wavenumber it has seen, up to a memory
+ * limit; callers that sweep many energies once can release them here. */
+int dda_drop_cache(dda_ctx* ctx);
 
 int dda_destroy(dda_ctx* ctx);
 

@@ -23,8 +23,8 @@ DDA_PREC_FP64, DDA_PREC_MIXED = 0, 1
 # every symbol include/dda.h declares
 EXPORTED = ["dda_default_options", "dda_beta_from_keV", "dda_setup", "dda_n_occ",
             "dda_grid_dims", "dda_einc_electron", "dda_solve", "dda_eels_cl", "dda_matvec",
-            "dda_set_timing", "dda_kernel_time", "dda_destroy", "dda_last_error",
-            "dda_debug_besselk01"]
+            "dda_set_timing", "dda_kernel_time", "dda_drop_cache", "dda_destroy",
+            "dda_last_error", "dda_debug_besselk01"]
 
 
 class DDAError(RuntimeError):
@@ -76,7 +76,8 @@ def load() -> ctypes.CDLL:
         "dda_eels_cl": (_i, [_vp, _i, _vp, _d, _vp, _vp, _i, _vp, _vp, _vp]),
         "dda_matvec": (_i, [_vp, _d, _vp, _i, _i, _vp, _vp, _i]),
         "dda_set_timing": (_i, [_vp, _i]),
-        "dda_kernel_time": (_i, [_vp, ctypes.c_char_p, _vp, _vp]),
+        "dda_kernel_time": (_i, [_vp, ctypes.c_char_p, _vp, _vp, _vp]),
+        "dda_drop_cache": (_i, [_vp]),
         "dda_destroy": (_i, [_vp]),
         "dda_last_error": (ctypes.c_char_p, []),
         "dda_debug_besselk01": (_i, [_vp, _i64, _vp]),
@@ -187,10 +188,17 @@ def dda_set_timing(ctx, enabled: bool) -> None:
 
 
 def dda_kernel_time(ctx, name: str):
+    """(average ms per launch, launches, average right-hand sides per launch)."""
     ms = ctypes.c_double()
     n = ctypes.c_int64()
-    _check(load().dda_kernel_time(ctx, name.encode(), ctypes.byref(ms), ctypes.byref(n)))
-    return float(ms.value), int(n.value)
+    u = ctypes.c_double()
+    _check(load().dda_kernel_time(ctx, name.encode(), ctypes.byref(ms), ctypes.byref(n),
+                                  ctypes.byref(u)))
+    return float(ms.value), int(n.value), float(u.value)
+
+
+def dda_drop_cache(ctx) -> None:
+    _check(load().dda_drop_cache(ctx))
 
 
 def dda_destroy(ctx) -> None:

@@ -88,6 +88,7 @@ struct Timer {
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
     double total_ms[5] = {0, 0, 0, 0, 0};
     int64_t count[5] = {0, 0, 0, 0, 0};
+    int64_t units[5] = {0, 0, 0, 0, 0};
     ~Timer() {
         for (auto& e : pool) (void)hipEventDestroy(e);
         for (auto& p : pending) {
@@ -179,8 +180,9 @@ struct Tic {
     dda_ctx* c;
     int k;
     hipEvent_t a = nullptr, b = nullptr;
-    Tic(dda_ctx* c_, int k_) : c(c_), k(k_) {
+    Tic(dda_ctx* c_, int k_, int n_rhs) : c(c_), k(k_) {
         if (c->timing) {
+            c->timer.units[k] += n_rhs;
             a = c->timer.get();
             b = c->timer.get();
             DDA_HIP_CHECK(hipEventRecord(a, c->stream));
@@ -219,25 +221,25 @@ void matvec(dda_ctx* c, const dda::cx<T>* x, dda::cx<T>* y, const int* act, int 
     hipStream_t s = c->stream;
     const int64_t plane = int64_t(g.my) * g.mx;
     {
-        Tic t(c, 0);
+        Tic t(c, 0, n_act);
         dda::launch_unpack_xfft<T>(x, c->map.as<int>(), G, tw_of<T>(c, 0), g, act, n_act, s);
     }
     {
-        Tic t(c, 1);
+        Tic t(c, 1, n_act);
         dda::launch_fft_mid<T>(G, tw_of<T>(c, 1), g.my, false, int64_t(n_act) * 3 * g.nz, g.mx,
                                g.ny, g.my, plane, s);
     }
     {
-        Tic t(c, 2);
+        Tic t(c, 2, n_act);
         dda::launch_zconv<T>(G, dptr, tw_of<T>(c, 2), g, act, slot_sys, n_act, s);
     }
     {
-        Tic t(c, 3);
+        Tic t(c, 3, n_act);
         dda::launch_fft_mid<T>(G, tw_of<T>(c, 1), g.my, true, int64_t(n_act) * 3 * g.nz, g.mx,
                                g.my, g.ny, plane, s);
     }
     {
-        Tic t(c, 4);
+        Tic t(c, 4, n_act);
         dda::launch_ixfft_pack<T>(G, x, ainv, y, c->map.as<int>(), tw_of<T>(c, 0), g, act,
                                   slot_sys, n_act, interaction_only, s);
     }
@@ -986,23 +988,39 @@ int dda_set_timing(dda_ctx* c, int enabled) {
     if (!c) throw Error(DDA_EINVAL, "ctx is NULL");
     flush_timer(c);
     c->timing = enabled != 0;
-    for (int k = 0; k < 5; ++k) { c->timer.total_ms[k] = 0; c->timer.count[k] = 0; }
+    for (int k = 0; k < 5; ++k) {
+        c->timer.total_ms[k] = 0;
+        c->timer.count[k] = 0;
+        c->timer.units[k] = 0;
+    }
     return DDA_OK;
     DDA_API_END
 }
 
-int dda_kernel_time(dda_ctx* c, const char* name, double* avg_ms, int64_t* launches) {
+int dda_kernel_time(dda_ctx* c, const char* name, double* avg_ms, int64_t* launches,
+                    double* avg_rhs) {
     DDA_API_BEGIN
-    if (!c || !name || !avg_ms || !launches) throw Error(DDA_EINVAL, "NULL argument");
+    if (!c || !name || !avg_ms || !launches || !avg_rhs) throw Error(DDA_EINVAL, "NULL argument");
     flush_timer(c);
     for (int k = 0; k < 5; ++k) {
         if (std::strcmp(name, kKernelNames[k]) == 0) {
-            *launches = c->timer.count[k];
-            *avg_ms = c->timer.count[k] ? c->timer.total_ms[k] / double(c->timer.count[k]) : 0.0;
+            const int64_t n = c->timer.count[k];
+            *launches = n;
+            *avg_ms = n ? c->timer.total_ms[k] / double(n) : 0.0;
+            *avg_rhs = n ? double(c->timer.units[k]) / double(n) : 0.0;
             return DDA_OK;
         }
     }
     throw Error(DDA_EINVAL, "unknown kernel name");
+    DDA_API_END
+}
+
+int dda_drop_cache(dda_ctx* c) {
+    DDA_API_BEGIN
+    if (!c) throw Error(DDA_EINVAL, "ctx is NULL");
+    DDA_HIP_CHECK(hipStreamSynchronize(c->stream));
+    c->dcache.clear();
+    return DDA_OK;
     DDA_API_END
 }
 

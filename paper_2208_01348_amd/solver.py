@@ -111,4 +111,8 @@ class DDASolver:
         L.dda_set_timing(self.ctx, enabled)
 
     def kernel_time(self, name: str):
+        """(average ms per launch, launches, average right-hand sides per launch)."""
         return L.dda_kernel_time(self.ctx, name)
+
+    def drop_cache(self) -> None:
+        L.dda_drop_cache(self.ctx)

@@ -82,7 +82,8 @@ def test_einc_parity(name, m_h, beta):
     mask = W.random_mask(11, 9, 7, 0.6, seed=5)
     d = 2.5
     energies = np.array([1.0, 2.2, 3.9])
-    r0 = np.array([[16.0, 1.25, -3.0], [0.0, 0.0, 0.0], [-20.0, 14.0, 50.0]])
+    # the 11 x 9 lattice has a dipole column at (0, 0): keep trajectories off it
+    r0 = np.array([[16.0, 1.25, -3.0], [0.3, -0.2, 0.0], [-20.0, 14.0, 50.0]])
     say("einc", name)
     s = DDASolver(mask, d, m_h)
     e = s.einc(energies, beta, r0)
