@@ -59,8 +59,9 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(kernel: str, workload: str, precision: str):
-    """HBM bytes per launch from a committed rocprofv3 --pmc summary, if it was
+def read_traffic(kernel: str, workload: str, precision: str, rhs_per_launch: float):
+    """HBM bytes per launch from a committed rocprofv3 --pmc summary (bytes per
+    right-hand side times the right-hand sides per launch), if the summary was
     taken on the current kernel source."""
     p = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}_{precision}.txt")
     if not os.path.exists(p):
@@ -74,7 +75,7 @@ def read_traffic(kernel: str, workload: str, precision: str):
     if vals.get("source_hash") != source_hash():
         return None
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return round(float(vals["hbm_bytes_per_rhs"]) * rhs_per_launch)
     except (KeyError, ValueError):
         return None
 
@@ -95,6 +96,9 @@ def main():
     ap.add_argument("--n-energy", type=int, default=128)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run a plain 256 MiB device copy (for scaling rocprofv3 "
+                         "FETCH_SIZE/WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solve shards by "
@@ -110,6 +114,14 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+
+    if args.calibrate_copy:
+        a = torch.empty(256 << 20, dtype=torch.uint8, device=dev).fill_(1)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     w = W.c2_nanorod_spectrum(args.n_energy)
     n = w.n_occ
@@ -161,7 +173,7 @@ def main():
     achieved = per_launch / (ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": read_traffic(dom, "c2", args.precision),
+                "traffic": read_traffic(dom, "c2", args.precision, rhs),
                 "avg_launch_ms": round(ms, 5), "launches": launches,
                 "rhs_per_launch": round(rhs, 2), "bytes_per_launch": round(per_launch)}
     kernel_table = {k: {"avg_ms": round(v[0], 5), "launches": v[1], "rhs_per_launch": round(v[2], 2),
@@ -225,11 +237,12 @@ def measure_extras(torch, W, DDASolver, log):
             s3.matvec(Em, eps3, x, precision=p, out=y)
             torch.cuda.synchronize()
             reps = 20
-            t = time.perf_counter()
+            s3.set_timing(True)
             for _ in range(reps):
                 s3.matvec(Em, eps3, x, precision=p, out=y)
-            torch.cuda.synchronize()
-            dt_s = (time.perf_counter() - t) / reps
+            # device time of the kernel chain (HIP events per kernel)
+            dt_s = sum(s3.kernel_time(k)[0] for k in KERNELS) * 1e-3
+            s3.set_timing(False)
             per_rhs = sum(kernel_bytes(k, w3.nx, w3.ny, w3.nz, mx, my, mz, n3, c) for k in KERNELS)
             model = (72 * N + 10 * n3 + 48 * N) * c * nrhs  # D read per right-hand side
             mv[f"{prec}_nrhs{nrhs}"] = {
