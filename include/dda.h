@@ -68,15 +68,21 @@ typedef enum {
 } dda_status;
 
 enum { DDA_POL_LDR = 0, DDA_POL_CM = 1, DDA_POL_RR = 2 };
-enum { DDA_SOLVER_BICGSTAB = 0 };
+enum { DDA_SOLVER_BICGSTAB = 0, DDA_SOLVER_COCG = 1 };
 enum { DDA_PREC_FP64 = 0, DDA_PREC_MIXED = 1 };
 
 typedef struct {
     int polarizability;   /* DDA_POL_*; lattice dispersion relation by default      */
-    int solver;           /* DDA_SOLVER_*                                             */
+    int solver;           /* DDA_SOLVER_BICGSTAB (two matvecs per iteration) or
+                             DDA_SOLVER_COCG: conjugate-orthogonal CG for the
+                             complex-symmetric DDA matrix (reciprocity, section
+                             2.4), one matvec per iteration                        */
     int precision;        /* DDA_PREC_FP64: complex128 throughout.
-                             DDA_PREC_MIXED: complex64 FFT matvecs inside an FP64
-                             iterative-refinement loop                               */
+                             DDA_PREC_MIXED: complex64 FFT matvecs and Krylov vectors
+                             with FP64 refinement: BiCGStab restarts from the FP64
+                             residual; COCG keeps iterating and periodically
+                             replaces its residual by the FP64 one while the
+                             solution accumulates in FP64 (reliable updates)       */
     double tol;           /* stopping threshold on ||e - A p|| / ||e|| (unscaled)    */
     int maxit;            /* iteration limit (matvec pairs for BiCGStab)              */
     int check_every;      /* host polls convergence every this many iterations       */

@@ -12,6 +12,7 @@
 #include <map>
 #include <memory>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "kernels.h"
@@ -146,7 +147,8 @@ struct dda_ctx {
     uint64_t pin_clock = 0;   // entries used at or after this tick are in use
     size_t dcache_limit = size_t(64) << 30;
     // work space
-    DevBuf G, vec128, vec64, st, partial, counters, act, slot_sys, dptr, ainv128, ainv64, misc;
+    DevBuf G, vec128, vec64, st, partial, act, slot_sys, dptr, ainv128, ainv64, misc;
+    DevBuf dfull;  // scratch of the full-grid transform during a D build
     PinnedBuf host_st, host_act, host_misc;
     int max_blocks = 1024;
     bool timing = false;
@@ -210,19 +212,28 @@ void flush_timer(dda_ctx* c) {
     c->timer.pending.clear();
 }
 
-// y = A x (or G_off x) for the slots listed in act (device) / n_act.
+dda::RedScratch red_of(dda_ctx* c) {
+    return dda::RedScratch{c->partial.as<double>(), c->max_blocks};
+}
+
+// One FFT matvec for the slots listed in act (device) / n_act:
+// mode PACK_AX (y = A x), PACK_GX (y = G_off x) or PACK_AX_COCG (y = A x with
+// the COCG scalars fused; then fuse_r gives the direction update
+// x <- fuse_r + beta x done in place by the first kernel).
 template <typename T>
-void matvec(dda_ctx* c, const dda::cx<T>* x, dda::cx<T>* y, const int* act, int n_act,
-            const dda::cx<T>* const* dptr, const int* slot_sys, const dda::cx<T>* ainv,
-            bool interaction_only) {
+void matvec(dda_ctx* c, dda::cx<T>* x, dda::cx<T>* y, const int* act, int n_act,
+            const dda::cx<T>* const* dptr, const int* slot_sys, const dda::cx<T>* ainv, int mode,
+            const dda::cx<T>* fuse_r = nullptr) {
     if (n_act == 0 || c->g.n_occ == 0) return;
     const dda::Geo& g = c->g;
     auto* G = c->G.as<dda::cx<T>>();
     hipStream_t s = c->stream;
+    auto* st = c->st.as<dda::BicgSlot>();
     const int64_t plane = int64_t(g.my) * g.mx;
     {
         Tic t(c, 0, n_act);
-        dda::launch_unpack_xfft<T>(x, c->map.as<int>(), G, tw_of<T>(c, 0), g, act, n_act, s);
+        dda::launch_unpack_xfft<T>(x, c->map.as<int>(), G, tw_of<T>(c, 0), g, act, n_act, fuse_r,
+                                   st, s);
     }
     {
         Tic t(c, 1, n_act);
@@ -241,8 +252,10 @@ void matvec(dda_ctx* c, const dda::cx<T>* x, dda::cx<T>* y, const int* act, int 
     {
         Tic t(c, 4, n_act);
         dda::launch_ixfft_pack<T>(G, x, ainv, y, c->map.as<int>(), tw_of<T>(c, 0), g, act,
-                                  slot_sys, n_act, interaction_only, s);
+                                  slot_sys, n_act, mode, st, red_of(c), s);
     }
+    if (mode == dda::PACK_AX_COCG)
+        dda::cocg_alpha_finalize(st, act, n_act, red_of(c), dda::pack_blocks_per_slot(g), s);
 }
 
 // ------------------------------------------------------------ D cache
@@ -252,7 +265,7 @@ DEntry* get_D(dda_ctx* c, double energy, bool need64) {
     auto it = c->dcache.find(key);
     DEntry* e;
     if (it == c->dcache.end()) {
-        const size_t b128 = size_t(dda::dgrid_elems(c->g)) * sizeof(z128);
+        const size_t b128 = size_t(dda::dred_elems(c->g)) * sizeof(z128);
         // evict least recently used entries beyond the limit
         size_t used = 0;
         for (auto& kv : c->dcache) used += kv.second->d128.bytes + kv.second->d64.bytes;
@@ -268,7 +281,8 @@ DEntry* get_D(dda_ctx* c, double energy, bool need64) {
         }
         auto ne = std::make_unique<DEntry>();
         ne->d128.ensure(b128);
-        dda::launch_build_D(ne->d128.as<z128>(), c->g, c->d, k.real(), k.imag(),
+        c->dfull.ensure(size_t(dda::dgrid_elems(c->g)) * sizeof(z128));
+        dda::launch_build_D(ne->d128.as<z128>(), c->dfull.as<z128>(), c->g, c->d, k.real(), k.imag(),
                             c->tw128[0].as<z128>(), c->tw128[1].as<z128>(),
                             c->tw128[2].as<z128>(), c->stream);
         e = ne.get();
@@ -277,7 +291,7 @@ DEntry* get_D(dda_ctx* c, double energy, bool need64) {
         e = it->second.get();
     }
     if (need64 && !e->has64) {
-        const int64_t n = dda::dgrid_elems(c->g);
+        const int64_t n = dda::dred_elems(c->g);
         e->d64.ensure(size_t(n) * sizeof(z64));
         dda::launch_convert_z128_to_z64(e->d128.as<z128>(), e->d64.as<z64>(), n, c->stream);
         e->has64 = true;
@@ -356,17 +370,10 @@ const z64* const* upload_dptrs<float>(dda_ctx* c, const std::vector<DEntry*>& en
     return reinterpret_cast<const z64* const*>(base);
 }
 
-dda::RedScratch red_of(dda_ctx* c) {
-    return dda::RedScratch{c->partial.as<double>(), c->counters.as<unsigned>(), c->max_blocks};
-}
 
 void ensure_slots(dda_ctx* c, int nslots) {
     c->st.ensure(size_t(nslots) * sizeof(dda::BicgSlot));
     c->partial.ensure(size_t(nslots) * c->max_blocks * 8 * sizeof(double));
-    if (c->counters.bytes < size_t(nslots) * sizeof(unsigned)) {
-        c->counters.ensure(size_t(nslots) * sizeof(unsigned));
-        DDA_HIP_CHECK(hipMemsetAsync(c->counters.p, 0, c->counters.bytes, c->stream));
-    }
     c->act.ensure(size_t(nslots) * sizeof(int));
     c->slot_sys.ensure(size_t(nslots) * sizeof(int));
     c->host_st.ensure(size_t(nslots) * sizeof(dda::BicgSlot));
@@ -413,7 +420,7 @@ void run_bicgstab(dda_ctx* c, int nslots, const dda::cx<T>* b, dda::cx<T>* x, Ve
     for (int i = 0; i < nslots; ++i) act[i] = i;
     upload_act(c, act);
     const int* dact = c->act.as<int>();
-    dda::bicg_norm_b<T>(b, st, dact, nslots, nv, tol * tol, red, s);
+    dda::bicg_norm_b<T>(b, st, dact, nslots, nv, tol * tol, 0.0, red, s);
     DDA_HIP_CHECK(hipMemsetAsync(x, 0, size_t(nslots) * nv * sizeof(dda::cx<T>), s));
     DDA_HIP_CHECK(hipMemcpyAsync(w.r, b, size_t(nslots) * nv * sizeof(dda::cx<T>),
                                  hipMemcpyDeviceToDevice, s));
@@ -446,7 +453,7 @@ void run_bicgstab(dda_ctx* c, int nslots, const dda::cx<T>* b, dda::cx<T>* x, Ve
         } else if (!verify.empty()) {
             // true residual: y = A x into w.t, r = b - y (rnorm2)
             upload_act(c, verify);
-            matvec<T>(c, x, w.t, dact, int(verify.size()), dptr, slot_sys, ainv, false);
+            matvec<T>(c, x, w.t, dact, int(verify.size()), dptr, slot_sys, ainv, dda::PACK_AX);
             dda::residual<T>(b, w.t, w.r, st, dact, int(verify.size()), nv, red, s);
             auto S2 = read_states(c, nslots);
             std::vector<int> again;
@@ -476,10 +483,10 @@ void run_bicgstab(dda_ctx* c, int nslots, const dda::cx<T>* b, dda::cx<T>* x, Ve
         upload_act(c, act);
         for (int k = 0; k < check; ++k) {
             dda::bicg_update_p<T>(w.r, w.p, w.v, st, dact, n_act, nv, s);
-            matvec<T>(c, w.p, w.v, dact, n_act, dptr, slot_sys, ainv, false);
+            matvec<T>(c, w.p, w.v, dact, n_act, dptr, slot_sys, ainv, dda::PACK_AX);
             dda::bicg_alpha<T>(w.rhat, w.v, st, dact, n_act, nv, red, s);
             dda::bicg_update_s<T>(w.r, w.v, w.s, st, dact, n_act, nv, red, s);
-            matvec<T>(c, w.s, w.t, dact, n_act, dptr, slot_sys, ainv, false);
+            matvec<T>(c, w.s, w.t, dact, n_act, dptr, slot_sys, ainv, dda::PACK_AX);
             dda::bicg_omega<T>(w.t, w.s, st, dact, n_act, nv, red, s);
             dda::bicg_update_xr<T>(x, w.r, w.rhat, w.p, w.s, w.t, st, dact, n_act, nv, red, s);
             for (int i : act) matvecs[i] += 2;
@@ -523,7 +530,7 @@ void run_mixed(dda_ctx* c, int nslots, const z128* b, z128* x, const z128* const
     std::vector<int> all(nslots);
     for (int i = 0; i < nslots; ++i) all[i] = i;
     upload_act(c, all);
-    dda::bicg_norm_b<double>(b, st, c->act.as<int>(), nslots, nv, tol * tol, red, c->stream);
+    dda::bicg_norm_b<double>(b, st, c->act.as<int>(), nslots, nv, tol * tol, 0.0, red, c->stream);
     std::vector<double> bn(nslots), rn(nslots);
     {
         auto S = read_states(c, nslots);
@@ -557,7 +564,7 @@ void run_mixed(dda_ctx* c, int nslots, const z128* b, z128* x, const z128* const
         upload_act(c, need);
         dda::accumulate_up(x, d32, st, c->act.as<int>(), int(need.size()), nv, c->stream);
         matvec<double>(c, x, y64, c->act.as<int>(), int(need.size()), dptr64,
-                       c->slot_sys.as<int>(), c->ainv128.as<z128>(), false);
+                       c->slot_sys.as<int>(), c->ainv128.as<z128>(), dda::PACK_AX);
         dda::residual<double>(b, y64, r64, st, c->act.as<int>(), int(need.size()), nv, red,
                               c->stream);
         auto S = read_states(c, nslots);
@@ -575,12 +582,120 @@ void run_mixed(dda_ctx* c, int nslots, const z128* b, z128* x, const z128* const
     }
 }
 
+// COCG (conjugate-orthogonal CG: CG with the bilinear product x^T y, for
+// the complex-symmetric DDA matrix) over the slots of a chunk, from x0 = 0.
+// b and x are FP64 and slot-indexed; r, p, q are in T.  One matvec per
+// iteration; the direction update and p^T q are fused into the matvec.
+// For T = float the steps accumulate in x_lo (FP32) and a reliable update
+// (x += x_lo, r = b - A x in FP64, rho from the new r) is made whenever the
+// recursive residual fell by kUpdateDrop since the last one, and whenever it
+// reports convergence; for T = double only the convergence is verified that
+// way.  The recursion then continues (p and beta are kept); a breakdown
+// restarts it from the true residual (p = r).
+constexpr double kUpdateDrop = 0.1;
+
+template <typename T>
+void run_cocg(dda_ctx* c, int nslots, const z128* b, z128* x, dda::cx<T>* r, dda::cx<T>* p,
+              dda::cx<T>* q, z64* x_lo, z128* y64, const dda::cx<T>* const* dptr,
+              const dda::cx<T>* ainv, const z128* const* dptr64, const z128* ainv64, double tol,
+              int maxit, std::vector<int>& iters, std::vector<int>& matvecs,
+              std::vector<int>& status, std::vector<double>& relres) {
+    constexpr bool mixed = std::is_same<T, float>::value;
+    const int64_t nv = c->nv();
+    hipStream_t s = c->stream;
+    auto* st = c->st.as<dda::BicgSlot>();
+    const int* slot_sys = c->slot_sys.as<int>();
+    const int* dact = c->act.as<int>();
+    auto red = red_of(c);
+    const size_t q128 = size_t(nslots) * nv;
+    std::vector<int> act(nslots);
+    for (int i = 0; i < nslots; ++i) act[i] = i;
+    upload_act(c, act);
+    dda::bicg_norm_b<double>(b, st, dact, nslots, nv, tol * tol,
+                             mixed ? kUpdateDrop * kUpdateDrop : 0.0, red, s);
+    DDA_HIP_CHECK(hipMemsetAsync(x, 0, q128 * sizeof(z128), s));
+    if (mixed) DDA_HIP_CHECK(hipMemsetAsync(x_lo, 0, q128 * sizeof(z64), s));
+    DDA_HIP_CHECK(hipMemsetAsync(y64, 0, q128 * sizeof(z128), s));
+    dda::true_residual<T>(b, y64, r, st, dact, nslots, nv, red, s);  // r = b
+    dda::cocg_reset<T>(r, p, st, dact, nslots, nv, red, s);
+    std::vector<int> restarts(nslots, 0);
+    status.assign(nslots, DDA_OK);
+    iters.assign(nslots, 0);
+    matvecs.assign(nslots, 0);
+    relres.assign(nslots, 0.0);
+    const int check = std::max(1, c->opt.check_every);
+    while (true) {
+        auto S = read_states(c, nslots);
+        std::vector<int> upd, rst, next;
+        std::vector<char> final_(nslots, 0);
+        for (int i : act) {
+            iters[i] = S[i].iters;
+            if (S[i].status == dda::SLOT_BREAKDOWN) {
+                rst.push_back(i);
+            } else if (S[i].status == dda::SLOT_CONVERGED || S[i].want_update) {
+                upd.push_back(i);
+            } else if (iters[i] >= maxit) {
+                upd.push_back(i);
+                final_[i] = 1;
+            } else {
+                next.push_back(i);
+            }
+        }
+        std::vector<int> ur = upd;
+        ur.insert(ur.end(), rst.begin(), rst.end());
+        if (!ur.empty()) {
+            upload_act(c, ur);
+            const int nu = int(ur.size());
+            if (mixed) dda::accumulate_lo(x, x_lo, dact, nu, nv, s);
+            matvec<double>(c, x, y64, dact, nu, dptr64, slot_sys, ainv64, dda::PACK_AX);
+            dda::true_residual<T>(b, y64, r, st, dact, nu, nv, red, s);
+            if (!rst.empty()) {
+                upload_act(c, rst);
+                dda::cocg_reset<T>(r, p, st, dact, int(rst.size()), nv, red, s);
+            }
+            auto S2 = read_states(c, nslots);
+            for (int i : ur) {
+                matvecs[i] += 1;
+                const double rr = S2[i].bnorm2 > 0 ? std::sqrt(S2[i].rnorm2 / S2[i].bnorm2) : 0.0;
+                relres[i] = rr;
+                const bool was_breakdown = S[i].status == dda::SLOT_BREAKDOWN;
+                if (rr <= tol) {
+                    status[i] = DDA_OK;
+                } else if (final_[i] || iters[i] >= maxit) {
+                    status[i] = DDA_ENOCONV;
+                } else if (was_breakdown && restarts[i] >= kMaxRestarts) {
+                    status[i] = DDA_EBREAKDOWN;
+                } else {
+                    if (was_breakdown) restarts[i] += 1;
+                    next.push_back(i);
+                }
+            }
+        }
+        std::sort(next.begin(), next.end());
+        act = next;
+        const int n_act = int(act.size());
+        if (n_act == 0) break;
+        upload_act(c, act);
+        for (int k = 0; k < check; ++k) {
+            matvec<T>(c, p, q, dact, n_act, dptr, slot_sys, ainv, dda::PACK_AX_COCG, r);
+            if (mixed)
+                dda::cocg_update_xr<T>(reinterpret_cast<dda::cx<T>*>(x_lo), r, p, q, st, dact,
+                                       n_act, nv, red, s);
+            else
+                dda::cocg_update_xr<T>(reinterpret_cast<dda::cx<T>*>(x), r, p, q, st, dact, n_act,
+                                       nv, red, s);
+            for (int i : act) matvecs[i] += 1;
+        }
+    }
+}
+
 // Sizes of the per-slot work space, in bytes.
 size_t slot_bytes(const dda_ctx* c, bool mixed) {
     const size_t ge = size_t(dda::grid_elems(c->g));
     const size_t nv = size_t(c->nv());
-    if (!mixed) return ge * sizeof(z128) + 6 * nv * sizeof(z128);
-    return ge * sizeof(z128) + 2 * nv * sizeof(z128) + 8 * nv * sizeof(z64);
+    const size_t red = size_t(c->max_blocks) * 8 * sizeof(double) + sizeof(dda::BicgSlot);
+    if (!mixed) return ge * sizeof(z128) + 6 * nv * sizeof(z128) + red;
+    return ge * sizeof(z128) + 2 * nv * sizeof(z128) + 8 * nv * sizeof(z64) + red;
 }
 
 void host_trajectory_check(const dda_ctx* c, const double* r0, int n_traj) {
@@ -620,7 +735,7 @@ void check_beta(dda_ctx* c, double beta) {
 int systems_per_chunk(dda_ctx* c, int n_energy, int n_traj, bool mixed) {
     size_t free_b = 0, total_b = 0;
     DDA_HIP_CHECK(hipMemGetInfo(&free_b, &total_b));
-    const size_t dsz = size_t(dda::dgrid_elems(c->g)) * (sizeof(z128) + (mixed ? sizeof(z64) : 0));
+    const size_t dsz = size_t(dda::dred_elems(c->g)) * (sizeof(z128) + (mixed ? sizeof(z64) : 0));
     const size_t per_sys = size_t(n_traj) * slot_bytes(c, mixed) + dsz +
                            size_t(c->g.n_occ) * (sizeof(z128) + sizeof(z64));
     const size_t budget = std::min<size_t>(free_b / 10 * 7, size_t(96) << 30);
@@ -688,7 +803,8 @@ int dda_setup(const uint8_t* mask, int nx, int ny, int nz, double d_nm, double m
     if (opt) c->opt = *opt; else dda_default_options(&c->opt);
     if (c->opt.polarizability < 0 || c->opt.polarizability > 2)
         throw Error(DDA_EINVAL, "unknown polarizability");
-    if (c->opt.solver != DDA_SOLVER_BICGSTAB) throw Error(DDA_EINVAL, "unknown solver");
+    if (c->opt.solver != DDA_SOLVER_BICGSTAB && c->opt.solver != DDA_SOLVER_COCG)
+        throw Error(DDA_EINVAL, "unknown solver");
     if (c->opt.precision != DDA_PREC_FP64 && c->opt.precision != DDA_PREC_MIXED)
         throw Error(DDA_EINVAL, "unknown precision");
     if (!(c->opt.tol > 0.0) || !(c->opt.tol < 1.0)) throw Error(DDA_EINVAL, "tol must lie in (0, 1)");
@@ -710,6 +826,7 @@ int dda_setup(const uint8_t* mask, int nx, int ny, int nz, double d_nm, double m
         }
     }
     g.n_occ = int64_t(c->occ_lin.size());
+    c->max_blocks = std::max(1024, dda::pack_blocks_per_slot(g));
     c->map.ensure(size_t(N) * sizeof(int));
     DDA_HIP_CHECK(hipMemcpy(c->map.p, hmap.data(), size_t(N) * sizeof(int), hipMemcpyHostToDevice));
     c->occ.ensure(std::max<size_t>(1, c->occ_lin.size()) * sizeof(int));
@@ -816,10 +933,28 @@ int dda_solve(dda_ctx* c, int n_energy, const double* energy_eV, const double* e
         auto* x = static_cast<z128*>(p_dev) + int64_t(e0) * n_traj * nv;
         std::vector<int> iters, mvs, status;
         std::vector<double> relres;
-        if (!mixed) {
-            c->vec128.ensure(size_t(6) * nslots * nv * sizeof(z128));
+        const size_t q = size_t(nslots) * nv;
+        if (c->opt.solver == DDA_SOLVER_COCG) {
+            auto dptr64 = upload_dptrs<double>(c, ents);
+            if (!mixed) {
+                c->vec128.ensure(4 * q * sizeof(z128));
+                auto* V = c->vec128.as<z128>();
+                run_cocg<double>(c, nslots, b, x, V, V + q, V + 2 * q, nullptr, V + 3 * q, dptr64,
+                                 c->ainv128.as<z128>(), dptr64, c->ainv128.as<z128>(), c->opt.tol,
+                                 c->opt.maxit, iters, mvs, status, relres);
+            } else {
+                c->vec128.ensure(q * sizeof(z128));
+                c->vec64.ensure(4 * q * sizeof(z64));
+                auto* U = c->vec64.as<z64>();
+                auto dptr32 = upload_dptrs<float>(c, ents);
+                run_cocg<float>(c, nslots, b, x, U, U + q, U + 2 * q, U + 3 * q,
+                                c->vec128.as<z128>(), dptr32, c->ainv64.as<z64>(), dptr64,
+                                c->ainv128.as<z128>(), c->opt.tol, c->opt.maxit, iters, mvs,
+                                status, relres);
+            }
+        } else if (!mixed) {
+            c->vec128.ensure(size_t(6) * q * sizeof(z128));
             auto* V = c->vec128.as<z128>();
-            const size_t q = size_t(nslots) * nv;
             Vecs<double> w{V, V + q, V + 2 * q, V + 3 * q, V + 4 * q, V + 5 * q};
             auto dptr = upload_dptrs<double>(c, ents);
             run_bicgstab<double>(c, nslots, b, x, w, c->opt.tol, c->opt.maxit, true, dptr,
@@ -916,8 +1051,8 @@ int dda_eels_cl(dda_ctx* c, int n_energy, const double* energy_eV, double beta,
         const auto* P = static_cast<const z128*>(p_dev) + int64_t(e0) * n_traj * nv;
         auto dptr = upload_dptrs<double>(c, ents);
         auto* Y = c->vec128.as<z128>();
-        matvec<double>(c, P, Y, nullptr, nslots, dptr, c->slot_sys.as<int>(), c->ainv128.as<z128>(),
-                       true);
+        matvec<double>(c, const_cast<z128*>(P), Y, nullptr, nslots, dptr, c->slot_sys.as<int>(),
+                       c->ainv128.as<z128>(), dda::PACK_GX);
         dda::loss_sums(static_cast<const z128*>(einc_dev), static_cast<const z128*>(p_dev), Y, dw,
                        c->occ.as<int>(), c->g, c->d, dkv, dr0, n_traj, int64_t(e0) * n_traj,
                        nslots, dout, red_of(c), c->stream);
@@ -972,12 +1107,14 @@ int dda_matvec(dda_ctx* c, double energy_eV, const double* eps_dipole, int preci
     c->G.ensure(size_t(nrhs) * dda::grid_elems(c->g) * sizeof(z128));
     if (!fp32) {
         auto dptr = upload_dptrs<double>(c, ents);
-        matvec<double>(c, static_cast<const z128*>(x_dev), static_cast<z128*>(y_dev), nullptr, nrhs,
-                       dptr, c->slot_sys.as<int>(), c->ainv128.as<z128>(), interaction_only != 0);
+        matvec<double>(c, const_cast<z128*>(static_cast<const z128*>(x_dev)),
+                       static_cast<z128*>(y_dev), nullptr, nrhs, dptr, c->slot_sys.as<int>(),
+                       c->ainv128.as<z128>(), interaction_only ? dda::PACK_GX : dda::PACK_AX);
     } else {
         auto dptr = upload_dptrs<float>(c, ents);
-        matvec<float>(c, static_cast<const z64*>(x_dev), static_cast<z64*>(y_dev), nullptr, nrhs,
-                      dptr, c->slot_sys.as<int>(), c->ainv64.as<z64>(), interaction_only != 0);
+        matvec<float>(c, const_cast<z64*>(static_cast<const z64*>(x_dev)),
+                      static_cast<z64*>(y_dev), nullptr, nrhs, dptr, c->slot_sys.as<int>(),
+                      c->ainv64.as<z64>(), interaction_only ? dda::PACK_GX : dda::PACK_AX);
     }
     return DDA_OK;
     DDA_API_END

@@ -2,6 +2,7 @@
 #pragma once
 
 #include "common.h"
+#include "slots.h"
 
 namespace dda {
 
@@ -13,9 +14,17 @@ struct Geo {
 };
 
 // Grid buffer per slot: [3][nz][my][mx] complex, rows y >= ny unused before the
-// y-pass.  D per system: [6][mz][my][mx] complex, components xx xy xz yy yz zz.
+// y-pass.
 inline int64_t grid_elems(const Geo& g) { return int64_t(3) * g.nz * g.my * g.mx; }
+// D per system, components xx xy xz yy yz zz.  Every component of the
+// interaction is even or odd along each axis (xy odd in x and y, xz in x and
+// z, yz in y and z, the diagonal ones even), and so is its transform over the
+// circulant embedding: D(M - k) = +-D(k) per axis.  Only the corner
+// k in [0, M/2] per axis is stored: [6][mz/2+1][my/2+1][mx/2+1].
 inline int64_t dgrid_elems(const Geo& g) { return int64_t(6) * g.mz * g.my * g.mx; }
+inline int64_t dred_elems(const Geo& g) {
+    return int64_t(6) * (g.mz / 2 + 1) * (g.my / 2 + 1) * (g.mx / 2 + 1);
+}
 
 bool fft_length_supported(int L);
 
@@ -24,23 +33,35 @@ bool fft_length_supported(int L);
 // list: act[pos] = slot (act == NULL: pos = slot).  slot_sys[slot] is the
 // system (energy) of a slot; D and 1/alpha are per system: Dptr[sys] points to
 // [6][mz][my][mx], ainv + sys * n_occ to the dipoles' 1/alpha.
+// With fuse_r != NULL the kernel first updates the input in place,
+// x <- fuse_r + beta x with beta = st[slot].beta (the COCG direction update),
+// and transforms the updated vector.
 template <typename T>
-void launch_unpack_xfft(const cx<T>* xin, const int* map, cx<T>* G, const cx<T>* tw_x,
-                        const Geo& g, const int* act, int n_act, hipStream_t s);
+void launch_unpack_xfft(cx<T>* xin, const int* map, cx<T>* G, const cx<T>* tw_x, const Geo& g,
+                        const int* act, int n_act, const cx<T>* fuse_r, const BicgSlot* st,
+                        hipStream_t s);
 template <typename T>
 void launch_fft_mid(cx<T>* data, const cx<T>* tw, int L, bool inverse, int64_t n_outer,
                     int64_t inner, int n_in, int n_out, int64_t outer_stride, hipStream_t s);
 template <typename T>
 void launch_zconv(cx<T>* G, const cx<T>* const* Dptr, const cx<T>* tw_z, const Geo& g,
                   const int* act, const int* slot_sys, int n_act, hipStream_t s);
+// mode PACK_AX: y = x/alpha - G_off x; PACK_GX: y = G_off x; PACK_AX_COCG:
+// y = A x and, fused, the partial rows of mu = x^T y per slot in `red`
+// (pack_blocks_per_slot rows, which must not exceed max_blocks); the caller
+// then runs cocg_alpha_finalize.
+enum PackMode { PACK_AX = 0, PACK_GX = 1, PACK_AX_COCG = 2 };
+int pack_blocks_per_slot(const Geo& g);
 template <typename T>
 void launch_ixfft_pack(const cx<T>* G, const cx<T>* xin, const cx<T>* ainv, cx<T>* yout,
                        const int* map, const cx<T>* tw_x, const Geo& g, const int* act,
-                       const int* slot_sys, int n_act, bool interaction_only, hipStream_t s);
+                       const int* slot_sys, int n_act, int mode, BicgSlot* st, RedScratch red,
+                       hipStream_t s);
 
 // Interaction spectrum: D = FFT3(G_tilde on the embedding grid) / (mx my mz),
-// FP64, for one host wavenumber k.
-void launch_build_D(z128* D, const Geo& g, double d, double k_re, double k_im,
+// FP64, for one host wavenumber k.  `full` is scratch of dgrid_elems; the
+// reduced corner is written to `Dred` (dred_elems).
+void launch_build_D(z128* Dred, z128* full, const Geo& g, double d, double k_re, double k_im,
                     const z128* tw_x, const z128* tw_y, const z128* tw_z, hipStream_t s);
 void launch_convert_z128_to_z64(const z128* in, z64* out, int64_t n, hipStream_t s);
 void launch_convert_z64_to_z128(const z64* in, z128* out, int64_t n, hipStream_t s);

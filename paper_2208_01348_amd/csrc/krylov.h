@@ -2,41 +2,16 @@
 #pragma once
 
 #include "kernels.h"
+#include "slots.h"
 
 namespace dda {
 
-enum SlotStatus : int {
-    SLOT_ACTIVE = 0,
-    SLOT_CONVERGED = 1,
-    SLOT_HALF = 2,       // ||s|| met the tolerance inside an iteration
-    SLOT_BREAKDOWN = 3,  // rho, <rhat, v> or omega vanished
-};
-
-// Per right-hand-side scalars, resident on the device.
-struct BicgSlot {
-    z128 rho, rho_old, alpha, omega;
-    z128 rv, ts;          // <rhat, v>, <t, s>
-    double tt;            // <t, t>
-    double bnorm2;        // ||b||^2
-    double rnorm2;        // ||r||^2 (recursive, or true after a residual pass)
-    double tol2;          // tol^2
-    int status;
-    int iters;
-};
-
-// Reduction scratch: per slot, up to `max_blocks` partial rows of up to 8
-// doubles, and one arrival counter per slot (zero between kernels).
-struct RedScratch {
-    double* partial;      // [max_slots][max_blocks][8]
-    unsigned* counters;   // [max_slots]
-    int max_blocks;
-};
-
 // Vectors are [slot][nv] (nv = 3 n_occ); `act` lists the slots to process
 // (n_act of them).  Each launcher is one kernel.
+// bnorm2 = ||b||^2; also sets tol2, upd2 and zeroes the iteration counter
 template <typename T>
 void bicg_norm_b(const cx<T>* b, BicgSlot* st, const int* act, int n_act, int64_t nv,
-                 double tol2, RedScratch red, hipStream_t s);
+                 double tol2, double upd2, RedScratch red, hipStream_t s);
 template <typename T>
 void bicg_reset(const cx<T>* r, cx<T>* rhat, cx<T>* p, cx<T>* v, BicgSlot* st, const int* act,
                 int n_act, int64_t nv, RedScratch red, hipStream_t s);
@@ -60,6 +35,32 @@ void bicg_update_xr(cx<T>* x, cx<T>* r, const cx<T>* rhat, const cx<T>* p, const
 template <typename T>
 void residual(const cx<T>* b, const cx<T>* y, cx<T>* r, BicgSlot* st, const int* act, int n_act,
               int64_t nv, RedScratch red, hipStream_t s);
+
+// COCG (conjugate-orthogonal CG for complex-symmetric A, bilinear products
+// x^T y): p = r, rho = r^T r, beta = 0.
+template <typename T>
+void cocg_reset(const cx<T>* r, cx<T>* p, BicgSlot* st, const int* act, int n_act, int64_t nv,
+                RedScratch red, hipStream_t s);
+// mu = p^T q, alpha = rho / mu (used when the matvec does not fuse it)
+template <typename T>
+void cocg_alpha(const cx<T>* p, const cx<T>* q, BicgSlot* st, const int* act, int n_act,
+                int64_t nv, RedScratch red, hipStream_t s);
+// alpha = rho / mu from the partial rows the fused pack kernel wrote (nblk
+// rows per slot)
+void cocg_alpha_finalize(BicgSlot* st, const int* act, int n_act, RedScratch red, int nblk,
+                         hipStream_t s);
+// x += alpha p; r -= alpha q; rho' = r^T r; beta = rho'/rho; convergence,
+// reliable-update and breakdown flags
+template <typename T>
+void cocg_update_xr(cx<T>* x, cx<T>* r, const cx<T>* p, const cx<T>* q, BicgSlot* st,
+                    const int* act, int n_act, int64_t nv, RedScratch red, hipStream_t s);
+// FP64 residual pass: r = b - y (FP64), r_lo = r rounded to T, rho = r_lo^T
+// r_lo, rnorm2 = ||r||^2, rmax2 = rnorm2; status from the FP64 norm.
+template <typename T>
+void true_residual(const z128* b, const z128* y, cx<T>* r_lo, BicgSlot* st, const int* act,
+                   int n_act, int64_t nv, RedScratch red, hipStream_t s);
+// x64 += x_lo; x_lo = 0
+void accumulate_lo(z128* x, z64* x_lo, const int* act, int n_act, int64_t nv, hipStream_t s);
 
 // Mixed precision helpers: r32 = r64 / sqrt(rnorm2); x64 += sqrt(rnorm2) * d32.
 void scale_down(const z128* r, z64* r32, const BicgSlot* st, const int* act, int n_act,

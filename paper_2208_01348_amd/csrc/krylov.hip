@@ -1,12 +1,14 @@
-// BiCGStab (van der Vorst 1992) over many right-hand sides at once, with all
-// scalars resident on the device, and the FP64 loss reductions.
+// Krylov solvers over many right-hand sides at once (BiCGStab, van der Vorst
+// 1992; COCG, the conjugate-orthogonal CG for complex-symmetric matrices,
+// van der Vorst & Melissen 1990), with every scalar resident on the device,
+// and the FP64 loss reductions.
 //
 // One grid covers every active slot: blockIdx.y picks the slot from the
-// active list, blockIdx.x a contiguous piece of its vector.  Dot products are
-// reduced deterministically: each block writes its partial sums to a fixed
-// row, and the last block of a slot to arrive (counted with an atomic) sums the
-// rows in index order and updates that slot's scalars.  The host never
-// synchronises inside an iteration.
+// active list, blockIdx.x a contiguous piece of its vector.  Each dot product
+// is a work kernel that writes one partial row per block and a finalize
+// kernel (one block per slot) that sums the rows in index order and updates
+// the slot's scalars: deterministic, without atomics or fences.  The host
+// never synchronises inside an iteration.
 #include "krylov.h"
 
 namespace dda {
@@ -14,7 +16,7 @@ namespace dda {
 namespace {
 
 constexpr int NT = 256;
-constexpr int EPB = 2048;  // vector elements per block
+constexpr int EPB = 1024;  // vector elements per block
 
 inline int blocks_for(int64_t nv, int max_blocks) {
     int64_t b = (nv + EPB - 1) / EPB;
@@ -23,79 +25,19 @@ inline int blocks_for(int64_t nv, int max_blocks) {
     return int(b);
 }
 
-template <int K>
-__device__ __forceinline__ void wave_sum(double (&v)[K]) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) v[k] += __shfl_down(v[k], off, 64);
-    }
-}
-
-// Block-reduces K values, stores them as this block's partial row, and
-// returns true in the (single) last block of the slot, where `tot` then
-// holds the slot totals summed in fixed order (valid in thread 0).
-template <int K>
-__device__ bool reduce_last(double (&v)[K], double (&tot)[K], RedScratch red, int slot,
-                            int nblk) {
-    __shared__ double sm[NT / 64][K];
-    __shared__ bool is_last;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    wave_sum<K>(v);
-    if (lane == 0)
-        for (int k = 0; k < K; ++k) sm[w][k] = v[k];
-    __syncthreads();
-    double* rows = red.partial + (int64_t(slot) * red.max_blocks) * 8;
-    if (tid == 0) {
-        for (int k = 0; k < K; ++k) {
-            double s = 0.0;
-            for (int q = 0; q < NT / 64; ++q) s += sm[q][k];
-            rows[blockIdx.x * 8 + k] = s;
-        }
-        __threadfence();
-        const unsigned prev = atomicAdd(&red.counters[slot], 1u);
-        is_last = (prev == unsigned(nblk - 1));
-    }
-    __syncthreads();
-    if (!is_last) return false;
-    __threadfence();
-    double acc[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) acc[k] = 0.0;
-    for (int b = tid; b < nblk; b += NT) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) acc[k] += __builtin_nontemporal_load(&rows[b * 8 + k]);
-    }
-    wave_sum<K>(acc);
-    __syncthreads();
-    if (lane == 0)
-        for (int k = 0; k < K; ++k) sm[w][k] = acc[k];
-    __syncthreads();
-    if (tid == 0) {
-        for (int k = 0; k < K; ++k) {
-            double s = 0.0;
-            for (int q = 0; q < NT / 64; ++q) s += sm[q][k];
-            tot[k] = s;
-        }
-        red.counters[slot] = 0u;
-    }
-    return true;
-}
-
-__device__ __forceinline__ z128 zdiv(z128 a, z128 b) {
-    const double s = 1.0 / (b.x * b.x + b.y * b.y);
-    return z128{(a.x * b.x + a.y * b.y) * s, (a.y * b.x - a.x * b.y) * s};
-}
-
-template <typename T>
-__device__ __forceinline__ z128 up(cx<T> a) { return z128{double(a.x), double(a.y)}; }
-
 // conj(a) * b accumulated in double
 template <typename T>
 __device__ __forceinline__ void acc_cdot(double& re, double& im, cx<T> a, cx<T> b) {
     const double ax = a.x, ay = a.y, bx = b.x, by = b.y;
     re += ax * bx + ay * by;
     im += ax * by - ay * bx;
+}
+// a * b (bilinear) accumulated in double
+template <typename T>
+__device__ __forceinline__ void acc_bdot(double& re, double& im, cx<T> a, cx<T> b) {
+    const double ax = a.x, ay = a.y, bx = b.x, by = b.y;
+    re += ax * bx - ay * by;
+    im += ax * by + ay * bx;
 }
 
 #define SLOT_PROLOGUE                                                   \
@@ -104,28 +46,46 @@ __device__ __forceinline__ void acc_cdot(double& re, double& im, cx<T> a, cx<T> 
     const int64_t i0 = int64_t(blockIdx.x) * NT + threadIdx.x;          \
     const int64_t stride = int64_t(gridDim.x) * NT;
 
-// ---------------------------------------------------------------- kernels
+// Finalize kernels: one block per listed slot.
+#define FIN_PROLOGUE(K)                                                 \
+    const int slot = act[blockIdx.x];                                   \
+    double tot[K];                                                      \
+    sum_rows<K, NT>(red, slot, nblk, tot);                              \
+    if (threadIdx.x != 0) return;                                       \
+    BicgSlot& S = st[slot];
 
+__device__ __forceinline__ bool all_finite(const double* t, int k) {
+    for (int i = 0; i < k; ++i)
+        if (!isfinite(t[i])) return false;
+    return true;
+}
+
+// ------------------------------------------------------------- ||b||^2 ----
 template <typename T>
-__global__ __launch_bounds__(NT) void k_norm_b(const cx<T>* __restrict__ b, BicgSlot* st,
+__global__ __launch_bounds__(NT) void k_norm_b(const cx<T>* __restrict__ b,
                                                const int* __restrict__ act, int64_t nv,
-                                               double tol2, RedScratch red) {
+                                               RedScratch red) {
     SLOT_PROLOGUE
     double v[1] = {0.0};
     for (int64_t i = i0; i < nv; i += stride) v[0] += double(norm2(b[base + i]));
-    double tot[1];
-    if (reduce_last<1>(v, tot, red, slot, gridDim.x) && threadIdx.x == 0) {
-        st[slot].bnorm2 = tot[0];
-        st[slot].tol2 = tol2;
-        st[slot].iters = 0;
-    }
+    block_partial<1, NT>(v, red, slot, blockIdx.x);
+}
+__global__ __launch_bounds__(NT) void k_fin_norm_b(BicgSlot* st, const int* act, RedScratch red,
+                                                   int nblk, double tol2, double upd2) {
+    FIN_PROLOGUE(1)
+    S.bnorm2 = tot[0];
+    S.tol2 = tol2;
+    S.upd2 = upd2;
+    S.iters = 0;
+    S.want_update = 0;
 }
 
+// ------------------------------------------------------------ BiCGStab ----
 template <typename T>
 __global__ __launch_bounds__(NT) void k_reset(const cx<T>* __restrict__ r, cx<T>* __restrict__ rhat,
                                               cx<T>* __restrict__ p, cx<T>* __restrict__ v,
-                                              BicgSlot* st, const int* __restrict__ act,
-                                              int64_t nv, RedScratch red) {
+                                              const int* __restrict__ act, int64_t nv,
+                                              RedScratch red) {
     SLOT_PROLOGUE
     double s[1] = {0.0};
     const cx<T> zero{T(0), T(0)};
@@ -136,16 +96,17 @@ __global__ __launch_bounds__(NT) void k_reset(const cx<T>* __restrict__ r, cx<T>
         v[base + i] = zero;
         s[0] += double(norm2(ri));
     }
-    double tot[1];
-    if (reduce_last<1>(s, tot, red, slot, gridDim.x) && threadIdx.x == 0) {
-        BicgSlot& S = st[slot];
-        S.rho = z128{tot[0], 0.0};
-        S.rho_old = z128{1.0, 0.0};
-        S.alpha = z128{1.0, 0.0};
-        S.omega = z128{1.0, 0.0};
-        S.rnorm2 = tot[0];
-        S.status = (tot[0] <= S.tol2 * S.bnorm2) ? SLOT_CONVERGED : SLOT_ACTIVE;
-    }
+    block_partial<1, NT>(s, red, slot, blockIdx.x);
+}
+__global__ __launch_bounds__(NT) void k_fin_reset(BicgSlot* st, const int* act, RedScratch red,
+                                                  int nblk) {
+    FIN_PROLOGUE(1)
+    S.rho = z128{tot[0], 0.0};
+    S.rho_old = z128{1.0, 0.0};
+    S.alpha = z128{1.0, 0.0};
+    S.omega = z128{1.0, 0.0};
+    S.rnorm2 = tot[0];
+    S.status = (tot[0] <= S.tol2 * S.bnorm2) ? SLOT_CONVERGED : SLOT_ACTIVE;
 }
 
 template <typename T>
@@ -166,29 +127,28 @@ __global__ __launch_bounds__(NT) void k_update_p(const cx<T>* __restrict__ r, cx
 
 template <typename T>
 __global__ __launch_bounds__(NT) void k_alpha(const cx<T>* __restrict__ rhat,
-                                              const cx<T>* __restrict__ v, BicgSlot* st,
+                                              const cx<T>* __restrict__ v, const BicgSlot* st,
                                               const int* __restrict__ act, int64_t nv,
                                               RedScratch red) {
     SLOT_PROLOGUE
     if (st[slot].status != SLOT_ACTIVE) return;
     double s[2] = {0.0, 0.0};
     for (int64_t i = i0; i < nv; i += stride) acc_cdot(s[0], s[1], rhat[base + i], v[base + i]);
-    double tot[2];
-    if (reduce_last<2>(s, tot, red, slot, gridDim.x) && threadIdx.x == 0) {
-        BicgSlot& S = st[slot];
-        S.rv = z128{tot[0], tot[1]};
-        if (tot[0] == 0.0 && tot[1] == 0.0) {
-            S.status = SLOT_BREAKDOWN;
-        } else {
-            S.alpha = zdiv(S.rho, S.rv);
-        }
-    }
+    block_partial<2, NT>(s, red, slot, blockIdx.x);
+}
+__global__ __launch_bounds__(NT) void k_fin_alpha(BicgSlot* st, const int* act, RedScratch red,
+                                                  int nblk) {
+    if (st[act[blockIdx.x]].status != SLOT_ACTIVE) return;  // uniform per block
+    FIN_PROLOGUE(2)
+    S.rv = z128{tot[0], tot[1]};
+    if ((tot[0] == 0.0 && tot[1] == 0.0) || !all_finite(tot, 2)) S.status = SLOT_BREAKDOWN;
+    else S.alpha = zdiv(S.rho, S.rv);
 }
 
 template <typename T>
 __global__ __launch_bounds__(NT) void k_update_s(const cx<T>* __restrict__ r,
                                                  const cx<T>* __restrict__ v, cx<T>* __restrict__ sv,
-                                                 BicgSlot* st, const int* __restrict__ act,
+                                                 const BicgSlot* st, const int* __restrict__ act,
                                                  int64_t nv, RedScratch red) {
     SLOT_PROLOGUE
     if (st[slot].status != SLOT_ACTIVE) return;
@@ -200,38 +160,43 @@ __global__ __launch_bounds__(NT) void k_update_s(const cx<T>* __restrict__ r,
         sv[base + i] = si;
         s[0] += double(norm2(si));
     }
-    double tot[1];
-    if (reduce_last<1>(s, tot, red, slot, gridDim.x) && threadIdx.x == 0) {
-        BicgSlot& S = st[slot];
-        if (tot[0] <= S.tol2 * S.bnorm2) S.status = SLOT_HALF;
-    }
+    block_partial<1, NT>(s, red, slot, blockIdx.x);
+}
+__global__ __launch_bounds__(NT) void k_fin_s(BicgSlot* st, const int* act, RedScratch red,
+                                              int nblk) {
+    if (st[act[blockIdx.x]].status != SLOT_ACTIVE) return;
+    FIN_PROLOGUE(1)
+    if (tot[0] <= S.tol2 * S.bnorm2) S.status = SLOT_HALF;
 }
 
 template <typename T>
 __global__ __launch_bounds__(NT) void k_omega(const cx<T>* __restrict__ t,
-                                              const cx<T>* __restrict__ sv, BicgSlot* st,
+                                              const cx<T>* __restrict__ sv, const BicgSlot* st,
                                               const int* __restrict__ act, int64_t nv,
                                               RedScratch red) {
     SLOT_PROLOGUE
-    const int status = st[slot].status;
-    if (status == SLOT_HALF) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) st[slot].omega = z128{0.0, 0.0};
-        return;
-    }
-    if (status != SLOT_ACTIVE) return;
+    if (st[slot].status != SLOT_ACTIVE) return;
     double s[3] = {0.0, 0.0, 0.0};
     for (int64_t i = i0; i < nv; i += stride) {
         const cx<T> ti = t[base + i];
         acc_cdot(s[0], s[1], ti, sv[base + i]);
         s[2] += double(norm2(ti));
     }
-    double tot[3];
-    if (reduce_last<3>(s, tot, red, slot, gridDim.x) && threadIdx.x == 0) {
-        BicgSlot& S = st[slot];
-        S.ts = z128{tot[0], tot[1]};
-        S.tt = tot[2];
-        S.omega = tot[2] > 0.0 ? z128{tot[0] / tot[2], tot[1] / tot[2]} : z128{0.0, 0.0};
+    block_partial<3, NT>(s, red, slot, blockIdx.x);
+}
+__global__ __launch_bounds__(NT) void k_fin_omega(BicgSlot* st, const int* act, RedScratch red,
+                                                  int nblk) {
+    const int sl = act[blockIdx.x];
+    const int status = st[sl].status;
+    if (status == SLOT_HALF) {
+        if (threadIdx.x == 0) st[sl].omega = z128{0.0, 0.0};
+        return;
     }
+    if (status != SLOT_ACTIVE) return;
+    FIN_PROLOGUE(3)
+    S.ts = z128{tot[0], tot[1]};
+    S.tt = tot[2];
+    S.omega = tot[2] > 0.0 ? z128{tot[0] / tot[2], tot[1] / tot[2]} : z128{0.0, 0.0};
 }
 
 template <typename T>
@@ -239,7 +204,7 @@ __global__ __launch_bounds__(NT) void k_update_xr(cx<T>* __restrict__ x, cx<T>* 
                                                   const cx<T>* __restrict__ rhat,
                                                   const cx<T>* __restrict__ p,
                                                   const cx<T>* __restrict__ sv,
-                                                  const cx<T>* __restrict__ t, BicgSlot* st,
+                                                  const cx<T>* __restrict__ t, const BicgSlot* st,
                                                   const int* __restrict__ act, int64_t nv,
                                                   RedScratch red) {
     SLOT_PROLOGUE
@@ -256,28 +221,31 @@ __global__ __launch_bounds__(NT) void k_update_xr(cx<T>* __restrict__ x, cx<T>* 
         acc_cdot(s[0], s[1], rhat[base + i], ri);
         s[2] += double(norm2(ri));
     }
-    double tot[3];
-    if (reduce_last<3>(s, tot, red, slot, gridDim.x) && threadIdx.x == 0) {
-        BicgSlot& S = st[slot];
-        S.iters += 1;
-        S.rho_old = S.rho;
-        S.rho = z128{tot[0], tot[1]};
-        S.rnorm2 = tot[2];
-        if (!isfinite(tot[0]) || !isfinite(tot[1]) || !isfinite(tot[2])) {
-            S.status = SLOT_BREAKDOWN;
-        } else if (status == SLOT_HALF || tot[2] <= S.tol2 * S.bnorm2) {
-            S.status = SLOT_CONVERGED;
-        } else if ((tot[0] == 0.0 && tot[1] == 0.0) || (S.omega.x == 0.0 && S.omega.y == 0.0)) {
-            S.status = SLOT_BREAKDOWN;
-        }
+    block_partial<3, NT>(s, red, slot, blockIdx.x);
+}
+__global__ __launch_bounds__(NT) void k_fin_xr(BicgSlot* st, const int* act, RedScratch red,
+                                               int nblk) {
+    const int status = st[act[blockIdx.x]].status;
+    if (status != SLOT_ACTIVE && status != SLOT_HALF) return;
+    FIN_PROLOGUE(3)
+    S.iters += 1;
+    S.rho_old = S.rho;
+    S.rho = z128{tot[0], tot[1]};
+    S.rnorm2 = tot[2];
+    if (!all_finite(tot, 3)) {
+        S.status = SLOT_BREAKDOWN;
+    } else if (status == SLOT_HALF || tot[2] <= S.tol2 * S.bnorm2) {
+        S.status = SLOT_CONVERGED;
+    } else if ((tot[0] == 0.0 && tot[1] == 0.0) || (S.omega.x == 0.0 && S.omega.y == 0.0)) {
+        S.status = SLOT_BREAKDOWN;
     }
 }
 
 template <typename T>
 __global__ __launch_bounds__(NT) void k_residual(const cx<T>* __restrict__ b,
                                                  const cx<T>* __restrict__ y, cx<T>* __restrict__ r,
-                                                 BicgSlot* st, const int* __restrict__ act,
-                                                 int64_t nv, RedScratch red) {
+                                                 const int* __restrict__ act, int64_t nv,
+                                                 RedScratch red) {
     SLOT_PROLOGUE
     double s[1] = {0.0};
     for (int64_t i = i0; i < nv; i += stride) {
@@ -285,8 +253,12 @@ __global__ __launch_bounds__(NT) void k_residual(const cx<T>* __restrict__ b,
         r[base + i] = ri;
         s[0] += double(norm2(ri));
     }
-    double tot[1];
-    if (reduce_last<1>(s, tot, red, slot, gridDim.x) && threadIdx.x == 0) st[slot].rnorm2 = tot[0];
+    block_partial<1, NT>(s, red, slot, blockIdx.x);
+}
+__global__ __launch_bounds__(NT) void k_fin_residual(BicgSlot* st, const int* act, RedScratch red,
+                                                     int nblk) {
+    FIN_PROLOGUE(1)
+    S.rnorm2 = tot[0];
 }
 
 __global__ __launch_bounds__(NT) void k_scale_down(const z128* __restrict__ r, z64* __restrict__ r32,
@@ -304,10 +276,137 @@ __global__ __launch_bounds__(NT) void k_accumulate_up(z128* __restrict__ x,
                                                       const int* __restrict__ act, int64_t nv) {
     SLOT_PROLOGUE
     const double sc = sqrt(st[slot].rnorm2);
-    for (int64_t i = i0; i < nv; i += stride) x[base + i] = x[base + i] + sc * cvt<double>(d32[base + i]);
+    for (int64_t i = i0; i < nv; i += stride)
+        x[base + i] = x[base + i] + sc * cvt<double>(d32[base + i]);
 }
 
-// Loss sums (see krylov.h).  Slot s is right-hand side rhs0 + s.
+// ---------------------------------------------------------------- COCG ----
+template <typename T>
+__global__ __launch_bounds__(NT) void k_cocg_reset(const cx<T>* __restrict__ r,
+                                                   cx<T>* __restrict__ p,
+                                                   const int* __restrict__ act, int64_t nv,
+                                                   RedScratch red) {
+    SLOT_PROLOGUE
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = i0; i < nv; i += stride) {
+        const cx<T> ri = r[base + i];
+        p[base + i] = ri;
+        acc_bdot(s[0], s[1], ri, ri);
+        s[2] += double(norm2(ri));
+    }
+    block_partial<3, NT>(s, red, slot, blockIdx.x);
+}
+__global__ __launch_bounds__(NT) void k_fin_cocg_reset(BicgSlot* st, const int* act,
+                                                       RedScratch red, int nblk) {
+    FIN_PROLOGUE(3)
+    S.rho = z128{tot[0], tot[1]};
+    S.beta = z128{0.0, 0.0};
+    S.rnorm2 = tot[2];
+    S.rmax2 = tot[2];
+    S.want_update = 0;
+    S.status = (tot[2] <= S.tol2 * S.bnorm2) ? SLOT_CONVERGED : SLOT_ACTIVE;
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_cocg_alpha(const cx<T>* __restrict__ p,
+                                                   const cx<T>* __restrict__ q,
+                                                   const int* __restrict__ act, int64_t nv,
+                                                   RedScratch red) {
+    SLOT_PROLOGUE
+    double s[2] = {0.0, 0.0};
+    for (int64_t i = i0; i < nv; i += stride) acc_bdot(s[0], s[1], p[base + i], q[base + i]);
+    block_partial<2, NT>(s, red, slot, blockIdx.x);
+}
+__global__ __launch_bounds__(NT) void k_fin_cocg_alpha(BicgSlot* st, const int* act,
+                                                       RedScratch red, int nblk) {
+    FIN_PROLOGUE(2)
+    if (S.status != SLOT_ACTIVE) return;
+    S.rv = z128{tot[0], tot[1]};
+    if ((tot[0] == 0.0 && tot[1] == 0.0) || !all_finite(tot, 2)) S.status = SLOT_BREAKDOWN;
+    else S.alpha = zdiv(S.rho, S.rv);
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_cocg_xr(cx<T>* __restrict__ x, cx<T>* __restrict__ r,
+                                                const cx<T>* __restrict__ p,
+                                                const cx<T>* __restrict__ q, const BicgSlot* st,
+                                                const int* __restrict__ act, int64_t nv,
+                                                RedScratch red) {
+    SLOT_PROLOGUE
+    if (st[slot].status != SLOT_ACTIVE) return;
+    const z128 al = st[slot].alpha;
+    const cx<T> a{T(al.x), T(al.y)};
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = i0; i < nv; i += stride) {
+        x[base + i] = x[base + i] + a * p[base + i];
+        const cx<T> ri = r[base + i] - a * q[base + i];
+        r[base + i] = ri;
+        acc_bdot(s[0], s[1], ri, ri);
+        s[2] += double(norm2(ri));
+    }
+    block_partial<3, NT>(s, red, slot, blockIdx.x);
+}
+__global__ __launch_bounds__(NT) void k_fin_cocg_xr(BicgSlot* st, const int* act, RedScratch red,
+                                                    int nblk) {
+    if (st[act[blockIdx.x]].status != SLOT_ACTIVE) return;
+    FIN_PROLOGUE(3)
+    S.iters += 1;
+    S.rnorm2 = tot[2];
+    if (!all_finite(tot, 3)) {
+        S.status = SLOT_BREAKDOWN;
+        return;
+    }
+    const z128 rho_new{tot[0], tot[1]};
+    const bool conv = tot[2] <= S.tol2 * S.bnorm2;
+    const bool rho0 = S.rho.x == 0.0 && S.rho.y == 0.0;
+    const bool rhon0 = rho_new.x == 0.0 && rho_new.y == 0.0;
+    S.beta = rho0 ? z128{0.0, 0.0} : zdiv(rho_new, S.rho);
+    S.rho = rho_new;
+    if (tot[2] > S.rmax2) S.rmax2 = tot[2];
+    if (S.upd2 > 0.0 && tot[2] < S.upd2 * S.rmax2) S.want_update = 1;
+    if (conv) S.status = SLOT_CONVERGED;
+    else if (rho0 || rhon0) S.status = SLOT_BREAKDOWN;
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_true_residual(const z128* __restrict__ b,
+                                                      const z128* __restrict__ y,
+                                                      cx<T>* __restrict__ r_lo,
+                                                      const int* __restrict__ act, int64_t nv,
+                                                      RedScratch red) {
+    SLOT_PROLOGUE
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = i0; i < nv; i += stride) {
+        const z128 ri = b[base + i] - y[base + i];
+        const cx<T> rl = cvt<T>(ri);
+        r_lo[base + i] = rl;
+        acc_bdot(s[0], s[1], rl, rl);
+        s[2] += ri.x * ri.x + ri.y * ri.y;
+    }
+    block_partial<3, NT>(s, red, slot, blockIdx.x);
+}
+__global__ __launch_bounds__(NT) void k_fin_true_residual(BicgSlot* st, const int* act,
+                                                          RedScratch red, int nblk) {
+    FIN_PROLOGUE(3)
+    S.rho = z128{tot[0], tot[1]};
+    S.rnorm2 = tot[2];
+    S.rmax2 = tot[2];
+    S.want_update = 0;
+    S.status = (tot[2] <= S.tol2 * S.bnorm2) ? SLOT_CONVERGED : SLOT_ACTIVE;
+}
+
+__global__ __launch_bounds__(NT) void k_accumulate_lo(z128* __restrict__ x, z64* __restrict__ x_lo,
+                                                      const int* __restrict__ act, int64_t nv) {
+    SLOT_PROLOGUE
+    for (int64_t i = i0; i < nv; i += stride) {
+        x[base + i] = x[base + i] + cvt<double>(x_lo[base + i]);
+        x_lo[base + i] = z64{0.f, 0.f};
+    }
+}
+
+// --------------------------------------------------------- loss sums ------
+// Slot s is right-hand side rhs0 + s; einc and p are indexed by the global
+// right-hand side, y, w and kv by the chunk (system = slot / n_traj).
 __global__ __launch_bounds__(NT) void k_loss_sums(const z128* __restrict__ einc,
                                                   const z128* __restrict__ p,
                                                   const z128* __restrict__ y,
@@ -315,11 +414,10 @@ __global__ __launch_bounds__(NT) void k_loss_sums(const z128* __restrict__ einc,
                                                   const int* __restrict__ occ_lin, Geo g, double d,
                                                   const double* __restrict__ kv,
                                                   const double* __restrict__ r0, int n_traj,
-                                                  int64_t rhs0, double* __restrict__ out,
-                                                  RedScratch red) {
+                                                  int64_t rhs0, RedScratch red) {
     const int slot = blockIdx.y;
     const int64_t rhs = rhs0 + slot;
-    const int sys = slot / n_traj;  // chunk-local system (chunks hold whole energies)
+    const int sys = slot / n_traj;
     const int t = slot - sys * n_traj;
     const double z0 = r0[3 * t + 2];
     const double kvs = kv[sys];
@@ -339,11 +437,9 @@ __global__ __launch_bounds__(NT) void k_loss_sums(const z128* __restrict__ einc,
         double p2 = 0.0;
         for (int c = 0; c < 3; ++c) {
             const z128 e = E[c * n + i], pc = P[c * n + i], yc = Y[c * n + i];
-            z128 gq = ph * e;
+            z128 gq = ph * e;  // auxiliary field of eq. (34)
             if (c < 2) gq = -gq;
-            const z128 gp = gq * pc;  // bilinear, eq. (32)
-            s[0] += gp.x;
-            s[1] += gp.y;
+            acc_bdot(s[0], s[1], gq, pc);  // bilinear, eq. (32)
             acc_cdot(s[2], s[3], e, pc);
             acc_cdot(s[5], s[6], pc, yc);
             p2 += norm2(pc);
@@ -351,8 +447,14 @@ __global__ __launch_bounds__(NT) void k_loss_sums(const z128* __restrict__ einc,
         s[4] += W[i] * p2;
         s[7] += p2;
     }
+    block_partial<8, NT>(s, red, slot, blockIdx.x);
+}
+__global__ __launch_bounds__(NT) void k_fin_loss(double* __restrict__ out, RedScratch red,
+                                                 int nblk) {
+    const int slot = blockIdx.x;
     double tot[8];
-    if (reduce_last<8>(s, tot, red, slot, gridDim.x) && threadIdx.x == 0)
+    sum_rows<8, NT>(red, slot, nblk, tot);
+    if (threadIdx.x == 0)
         for (int k = 0; k < 8; ++k) out[slot * 8 + k] = tot[k];
 }
 
@@ -361,20 +463,28 @@ __global__ __launch_bounds__(NT) void k_loss_sums(const z128* __restrict__ einc,
 // ---------------------------------------------------------------- launchers
 
 #define GRID(nv) dim3(blocks_for(nv, red.max_blocks), n_act)
+#define FIN(kernel, ...)                                                          \
+    do {                                                                          \
+        kernel<<<n_act, NT, 0, s>>>(st, act, red, blocks_for(nv, red.max_blocks), \
+                                    ##__VA_ARGS__);                               \
+        DDA_LAUNCH_CHECK();                                                       \
+    } while (0)
 
 template <typename T>
 void bicg_norm_b(const cx<T>* b, BicgSlot* st, const int* act, int n_act, int64_t nv, double tol2,
-                 RedScratch red, hipStream_t s) {
+                 double upd2, RedScratch red, hipStream_t s) {
     if (n_act == 0) return;
-    k_norm_b<T><<<GRID(nv), NT, 0, s>>>(b, st, act, nv, tol2, red);
+    k_norm_b<T><<<GRID(nv), NT, 0, s>>>(b, act, nv, red);
     DDA_LAUNCH_CHECK();
+    FIN(k_fin_norm_b, tol2, upd2);
 }
 template <typename T>
 void bicg_reset(const cx<T>* r, cx<T>* rhat, cx<T>* p, cx<T>* v, BicgSlot* st, const int* act,
                 int n_act, int64_t nv, RedScratch red, hipStream_t s) {
     if (n_act == 0) return;
-    k_reset<T><<<GRID(nv), NT, 0, s>>>(r, rhat, p, v, st, act, nv, red);
+    k_reset<T><<<GRID(nv), NT, 0, s>>>(r, rhat, p, v, act, nv, red);
     DDA_LAUNCH_CHECK();
+    FIN(k_fin_reset);
 }
 template <typename T>
 void bicg_update_p(const cx<T>* r, cx<T>* p, const cx<T>* v, BicgSlot* st, const int* act,
@@ -390,6 +500,7 @@ void bicg_alpha(const cx<T>* rhat, const cx<T>* v, BicgSlot* st, const int* act,
     if (n_act == 0) return;
     k_alpha<T><<<GRID(nv), NT, 0, s>>>(rhat, v, st, act, nv, red);
     DDA_LAUNCH_CHECK();
+    FIN(k_fin_alpha);
 }
 template <typename T>
 void bicg_update_s(const cx<T>* r, const cx<T>* v, cx<T>* sv, BicgSlot* st, const int* act,
@@ -397,6 +508,7 @@ void bicg_update_s(const cx<T>* r, const cx<T>* v, cx<T>* sv, BicgSlot* st, cons
     if (n_act == 0) return;
     k_update_s<T><<<GRID(nv), NT, 0, s>>>(r, v, sv, st, act, nv, red);
     DDA_LAUNCH_CHECK();
+    FIN(k_fin_s);
 }
 template <typename T>
 void bicg_omega(const cx<T>* t, const cx<T>* sv, BicgSlot* st, const int* act, int n_act,
@@ -404,6 +516,7 @@ void bicg_omega(const cx<T>* t, const cx<T>* sv, BicgSlot* st, const int* act, i
     if (n_act == 0) return;
     k_omega<T><<<GRID(nv), NT, 0, s>>>(t, sv, st, act, nv, red);
     DDA_LAUNCH_CHECK();
+    FIN(k_fin_omega);
 }
 template <typename T>
 void bicg_update_xr(cx<T>* x, cx<T>* r, const cx<T>* rhat, const cx<T>* p, const cx<T>* sv,
@@ -412,15 +525,60 @@ void bicg_update_xr(cx<T>* x, cx<T>* r, const cx<T>* rhat, const cx<T>* p, const
     if (n_act == 0) return;
     k_update_xr<T><<<GRID(nv), NT, 0, s>>>(x, r, rhat, p, sv, t, st, act, nv, red);
     DDA_LAUNCH_CHECK();
+    FIN(k_fin_xr);
 }
 template <typename T>
 void residual(const cx<T>* b, const cx<T>* y, cx<T>* r, BicgSlot* st, const int* act, int n_act,
               int64_t nv, RedScratch red, hipStream_t s) {
     if (n_act == 0) return;
-    k_residual<T><<<GRID(nv), NT, 0, s>>>(b, y, r, st, act, nv, red);
+    k_residual<T><<<GRID(nv), NT, 0, s>>>(b, y, r, act, nv, red);
+    DDA_LAUNCH_CHECK();
+    FIN(k_fin_residual);
+}
+template <typename T>
+void cocg_reset(const cx<T>* r, cx<T>* p, BicgSlot* st, const int* act, int n_act, int64_t nv,
+                RedScratch red, hipStream_t s) {
+    if (n_act == 0) return;
+    k_cocg_reset<T><<<GRID(nv), NT, 0, s>>>(r, p, act, nv, red);
+    DDA_LAUNCH_CHECK();
+    FIN(k_fin_cocg_reset);
+}
+template <typename T>
+void cocg_alpha(const cx<T>* p, const cx<T>* q, BicgSlot* st, const int* act, int n_act,
+                int64_t nv, RedScratch red, hipStream_t s) {
+    if (n_act == 0) return;
+    k_cocg_alpha<T><<<GRID(nv), NT, 0, s>>>(p, q, act, nv, red);
+    DDA_LAUNCH_CHECK();
+    FIN(k_fin_cocg_alpha);
+}
+void cocg_alpha_finalize(BicgSlot* st, const int* act, int n_act, RedScratch red, int nblk,
+                         hipStream_t s) {
+    if (n_act == 0) return;
+    k_fin_cocg_alpha<<<n_act, NT, 0, s>>>(st, act, red, nblk);
     DDA_LAUNCH_CHECK();
 }
-
+template <typename T>
+void cocg_update_xr(cx<T>* x, cx<T>* r, const cx<T>* p, const cx<T>* q, BicgSlot* st,
+                    const int* act, int n_act, int64_t nv, RedScratch red, hipStream_t s) {
+    if (n_act == 0) return;
+    k_cocg_xr<T><<<GRID(nv), NT, 0, s>>>(x, r, p, q, st, act, nv, red);
+    DDA_LAUNCH_CHECK();
+    FIN(k_fin_cocg_xr);
+}
+template <typename T>
+void true_residual(const z128* b, const z128* y, cx<T>* r_lo, BicgSlot* st, const int* act,
+                   int n_act, int64_t nv, RedScratch red, hipStream_t s) {
+    if (n_act == 0) return;
+    k_true_residual<T><<<GRID(nv), NT, 0, s>>>(b, y, r_lo, act, nv, red);
+    DDA_LAUNCH_CHECK();
+    FIN(k_fin_true_residual);
+}
+void accumulate_lo(z128* x, z64* x_lo, const int* act, int n_act, int64_t nv, hipStream_t s) {
+    if (n_act == 0) return;
+    dim3 grid(blocks_for(nv, 1 << 20), n_act);
+    k_accumulate_lo<<<grid, NT, 0, s>>>(x, x_lo, act, nv);
+    DDA_LAUNCH_CHECK();
+}
 void scale_down(const z128* r, z64* r32, const BicgSlot* st, const int* act, int n_act, int64_t nv,
                 hipStream_t s) {
     if (n_act == 0) return;
@@ -440,14 +598,17 @@ void loss_sums(const z128* einc, const z128* p, const z128* y, const double* w, 
                const Geo& g, double d, const double* kv, const double* r0, int n_traj, int64_t rhs0,
                int nslots, double* out, RedScratch red, hipStream_t s) {
     if (nslots == 0) return;
-    dim3 grid(blocks_for(g.n_occ, red.max_blocks), nslots);
-    k_loss_sums<<<grid, NT, 0, s>>>(einc, p, y, w, occ_lin, g, d, kv, r0, n_traj, rhs0, out, red);
+    const int nb = blocks_for(g.n_occ, red.max_blocks);
+    k_loss_sums<<<dim3(nb, nslots), NT, 0, s>>>(einc, p, y, w, occ_lin, g, d, kv, r0, n_traj, rhs0,
+                                                red);
+    DDA_LAUNCH_CHECK();
+    k_fin_loss<<<nslots, NT, 0, s>>>(out, red, nb);
     DDA_LAUNCH_CHECK();
 }
 
 #define DDA_INST(T)                                                                              \
     template void bicg_norm_b<T>(const cx<T>*, BicgSlot*, const int*, int, int64_t, double,      \
-                                 RedScratch, hipStream_t);                                       \
+                                 double, RedScratch, hipStream_t);                               \
     template void bicg_reset<T>(const cx<T>*, cx<T>*, cx<T>*, cx<T>*, BicgSlot*, const int*, int, \
                                 int64_t, RedScratch, hipStream_t);                               \
     template void bicg_update_p<T>(const cx<T>*, cx<T>*, const cx<T>*, BicgSlot*, const int*,    \
@@ -462,7 +623,15 @@ void loss_sums(const z128* einc, const z128* p, const z128* y, const double* w, 
                                     const cx<T>*, BicgSlot*, const int*, int, int64_t,           \
                                     RedScratch, hipStream_t);                                    \
     template void residual<T>(const cx<T>*, const cx<T>*, cx<T>*, BicgSlot*, const int*, int,    \
-                              int64_t, RedScratch, hipStream_t);
+                              int64_t, RedScratch, hipStream_t);                                 \
+    template void cocg_reset<T>(const cx<T>*, cx<T>*, BicgSlot*, const int*, int, int64_t,       \
+                                RedScratch, hipStream_t);                                        \
+    template void cocg_alpha<T>(const cx<T>*, const cx<T>*, BicgSlot*, const int*, int, int64_t, \
+                                RedScratch, hipStream_t);                                        \
+    template void cocg_update_xr<T>(cx<T>*, cx<T>*, const cx<T>*, const cx<T>*, BicgSlot*,       \
+                                    const int*, int, int64_t, RedScratch, hipStream_t);          \
+    template void true_residual<T>(const z128*, const z128*, cx<T>*, BicgSlot*, const int*, int, \
+                                   int64_t, RedScratch, hipStream_t);
 DDA_INST(double)
 DDA_INST(float)
 

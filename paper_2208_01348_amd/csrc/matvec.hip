@@ -59,12 +59,14 @@ bool fft_length_supported(int L) {
 }
 
 // ---------------------------------------------------------------- K1 ------
-template <typename T, int L>
-__global__ __launch_bounds__(NTHR) void k_unpack_xfft(const cx<T>* __restrict__ xin,
+template <typename T, int L, bool FUSE_P>
+__global__ __launch_bounds__(NTHR) void k_unpack_xfft(cx<T>* __restrict__ xin,
                                                       const int* __restrict__ map,
                                                       cx<T>* __restrict__ G,
                                                       const cx<T>* __restrict__ tw, Geo g,
-                                                      const int* __restrict__ act) {
+                                                      const int* __restrict__ act,
+                                                      const cx<T>* __restrict__ fuse_r,
+                                                      const BicgSlot* __restrict__ st) {
     constexpr int NL = rows_nl<T, L>();
     __shared__ cx<T> lds[NL * L];
     const int tid = threadIdx.x;
@@ -73,14 +75,23 @@ __global__ __launch_bounds__(NTHR) void k_unpack_xfft(const cx<T>* __restrict__ 
     const int64_t slot = act ? act[pos] : pos;
     const int nrows = g.nz * g.ny;
     const int row0 = blockIdx.x * NL;
-    const cx<T>* src = xin + (slot * 3 + c) * g.n_occ;
+    cx<T>* src = xin + (slot * 3 + c) * g.n_occ;
+    const cx<T>* rsrc = FUSE_P ? fuse_r + (slot * 3 + c) * g.n_occ : nullptr;
+    cx<T> beta{T(0), T(0)};
+    if (FUSE_P) beta = cvt<T>(st[slot].beta);
     for (int e = tid; e < NL * L; e += NTHR) {
         const int rr = e / L, x = e % L;
         const int row = row0 + rr;
         cx<T> v{T(0), T(0)};
         if (row < nrows && x < g.nx) {
             const int idx = map[int64_t(row) * g.nx + x];
-            if (idx >= 0) v = src[idx];
+            if (idx >= 0) {
+                v = src[idx];
+                if (FUSE_P) {  // each occupied element is visited by exactly one thread
+                    v = rsrc[idx] + beta * v;
+                    src[idx] = v;
+                }
+            }
         }
         lds[e] = v;
     }
@@ -153,14 +164,24 @@ __global__ __launch_bounds__(NTHR) void k_zconv(cx<T>* __restrict__ G,
     }
     __syncthreads();
     fft_tile<T, L, false, W, 1, W, NTHR>(lds, tw, tid);
-    const cx<T>* dbase = Dptr[sys] + int64_t(ky) * g.mx + col0;
-    const int64_t dcomp = int64_t(g.mz) * plane;
+    // D from its stored corner: index M - k reads k, odd components flip sign
+    const int mxh = g.mx / 2 + 1, myh = g.my / 2 + 1, mzh = g.mz / 2 + 1;
+    const bool fy = ky > g.my / 2;
+    const int kyr = fy ? g.my - ky : ky;
+    const int64_t dcomp = int64_t(mzh) * myh * mxh;
+    const cx<T>* dbase = Dptr[sys] + int64_t(kyr) * mxh;
     for (int e = tid; e < L * TX; e += NTHR) {
         const int kz = e / TX, col = e % TX;
-        if (col0 + col < g.mx) {
-            const cx<T>* dp = dbase + int64_t(kz) * plane + col;
-            const cx<T> dxx = dp[0], dxy = dp[dcomp], dxz = dp[2 * dcomp];
-            const cx<T> dyy = dp[3 * dcomp], dyz = dp[4 * dcomp], dzz = dp[5 * dcomp];
+        const int kx = col0 + col;
+        if (kx < g.mx) {
+            const bool fx = kx > g.mx / 2, fz = kz > g.mz / 2;
+            const int kxr = fx ? g.mx - kx : kx, kzr = fz ? g.mz - kz : kz;
+            const cx<T>* dp = dbase + int64_t(kzr) * myh * mxh + kxr;
+            const cx<T> dxx = dp[0], dyy = dp[3 * dcomp], dzz = dp[5 * dcomp];
+            cx<T> dxy = dp[dcomp], dxz = dp[2 * dcomp], dyz = dp[4 * dcomp];
+            if (fx != fy) dxy = -dxy;
+            if (fx != fz) dxz = -dxz;
+            if (fy != fz) dyz = -dyz;
             cx<T>* u = lds + kz * W + col;
             const cx<T> ux = u[0], uy = u[TX], uz = u[2 * TX];
             u[0] = dxx * ux + dxy * uy + dxz * uz;
@@ -177,7 +198,7 @@ __global__ __launch_bounds__(NTHR) void k_zconv(cx<T>* __restrict__ G,
 }
 
 // ---------------------------------------------------------------- K5 ------
-template <typename T, int L, bool INTERACTION_ONLY>
+template <typename T, int L, int MODE>
 __global__ __launch_bounds__(NTHR) void k_ixfft_pack(const cx<T>* __restrict__ G,
                                                      const cx<T>* __restrict__ xin,
                                                      const cx<T>* __restrict__ ainv,
@@ -185,7 +206,8 @@ __global__ __launch_bounds__(NTHR) void k_ixfft_pack(const cx<T>* __restrict__ G
                                                      const int* __restrict__ map,
                                                      const cx<T>* __restrict__ tw, Geo g,
                                                      const int* __restrict__ act,
-                                                     const int* __restrict__ slot_sys) {
+                                                     const int* __restrict__ slot_sys,
+                                                     BicgSlot* st, RedScratch red) {
     constexpr int NL = rows_nl<T, L>();
     __shared__ cx<T> lds[NL * L];
     const int tid = threadIdx.x;
@@ -209,6 +231,7 @@ __global__ __launch_bounds__(NTHR) void k_ixfft_pack(const cx<T>* __restrict__ G
     __syncthreads();
     fft_tile<T, L, true, NL, L, 1, NTHR>(lds, tw, tid);
     const int64_t voff = (slot * 3 + c) * g.n_occ;
+    double mu[2] = {0.0, 0.0};
     for (int e = tid; e < NL * L; e += NTHR) {
         const int rr = e / L, x = e % L;
         const int row = row0 + rr;
@@ -216,29 +239,49 @@ __global__ __launch_bounds__(NTHR) void k_ixfft_pack(const cx<T>* __restrict__ G
             const int idx = map[int64_t(row) * g.nx + x];
             if (idx >= 0) {
                 const cx<T> conv = lds[e];
-                if (INTERACTION_ONLY) {
+                if (MODE == PACK_GX) {
                     yout[voff + idx] = conv;
                 } else {
-                    yout[voff + idx] = xin[voff + idx] * ainv[sys * g.n_occ + idx] - conv;
+                    const cx<T> xi = xin[voff + idx];
+                    const cx<T> yi = xi * ainv[sys * g.n_occ + idx] - conv;
+                    yout[voff + idx] = yi;
+                    if (MODE == PACK_AX_COCG) {  // bilinear x^T y
+                        mu[0] += double(xi.x) * yi.x - double(xi.y) * yi.y;
+                        mu[1] += double(xi.x) * yi.y + double(xi.y) * yi.x;
+                    }
                 }
             }
         }
     }
+    if constexpr (MODE == PACK_AX_COCG)  // partial rows; alpha is finalized by the caller
+        block_partial<2, NTHR>(mu, red, int(slot), blockIdx.y * gridDim.x + blockIdx.x);
 }
 
 // ------------------------------------------------------------ launchers ---
 static inline unsigned nblk(int64_t n, int64_t per) { return unsigned((n + per - 1) / per); }
 
+int pack_blocks_per_slot(const Geo& g) {
+    const int64_t nrows = int64_t(g.nz) * g.ny;
+    const int nl = g.mx >= 2048 ? 1 : 2048 / g.mx;  // rows_nl<T, L>() for either T
+    return int(3 * ((nrows + nl - 1) / nl));
+}
+
 template <typename T>
-void launch_unpack_xfft(const cx<T>* xin, const int* map, cx<T>* G, const cx<T>* tw_x,
-                        const Geo& g, const int* act, int n_act, hipStream_t s) {
+void launch_unpack_xfft(cx<T>* xin, const int* map, cx<T>* G, const cx<T>* tw_x, const Geo& g,
+                        const int* act, int n_act, const cx<T>* fuse_r, const BicgSlot* st,
+                        hipStream_t s) {
     if (n_act == 0) return;
     const int64_t nrows = int64_t(g.nz) * g.ny;
     switch (g.mx) {
 #define DDA_CASE(N)                                                                    \
     case N: {                                                                          \
         dim3 grid(nblk(nrows, rows_nl<T, N>()), 3, n_act);                             \
-        k_unpack_xfft<T, N><<<grid, NTHR, 0, s>>>(xin, map, G, tw_x, g, act);           \
+        if (fuse_r)                                                                    \
+            k_unpack_xfft<T, N, true><<<grid, NTHR, 0, s>>>(xin, map, G, tw_x, g, act,  \
+                                                            fuse_r, st);               \
+        else                                                                           \
+            k_unpack_xfft<T, N, false><<<grid, NTHR, 0, s>>>(xin, map, G, tw_x, g, act, \
+                                                             nullptr, nullptr);        \
         break;                                                                         \
     }
         DDA_FOR_EACH_L(DDA_CASE)
@@ -295,19 +338,25 @@ void launch_zconv(cx<T>* G, const cx<T>* const* Dptr, const cx<T>* tw_z, const G
 template <typename T>
 void launch_ixfft_pack(const cx<T>* G, const cx<T>* xin, const cx<T>* ainv, cx<T>* yout,
                        const int* map, const cx<T>* tw_x, const Geo& g, const int* act,
-                       const int* slot_sys, int n_act, bool interaction_only, hipStream_t s) {
+                       const int* slot_sys, int n_act, int mode, BicgSlot* st, RedScratch red,
+                       hipStream_t s) {
     if (n_act == 0) return;
+    if (mode == PACK_AX_COCG && pack_blocks_per_slot(g) > red.max_blocks)
+        throw Error(-3, "reduction scratch too small for the fused pack kernel");
     const int64_t nrows = int64_t(g.nz) * g.ny;
     switch (g.mx) {
 #define DDA_CASE(N)                                                                        \
     case N: {                                                                              \
         dim3 grid(nblk(nrows, rows_nl<T, N>()), 3, n_act);                                 \
-        if (interaction_only)                                                              \
-            k_ixfft_pack<T, N, true><<<grid, NTHR, 0, s>>>(G, xin, ainv, yout, map, tw_x,   \
-                                                           g, act, slot_sys);              \
+        if (mode == PACK_GX)                                                               \
+            k_ixfft_pack<T, N, PACK_GX><<<grid, NTHR, 0, s>>>(G, xin, ainv, yout, map, tw_x,\
+                                                              g, act, slot_sys, st, red);  \
+        else if (mode == PACK_AX)                                                          \
+            k_ixfft_pack<T, N, PACK_AX><<<grid, NTHR, 0, s>>>(G, xin, ainv, yout, map, tw_x,\
+                                                              g, act, slot_sys, st, red);  \
         else                                                                               \
-            k_ixfft_pack<T, N, false><<<grid, NTHR, 0, s>>>(G, xin, ainv, yout, map, tw_x,  \
-                                                            g, act, slot_sys);             \
+            k_ixfft_pack<T, N, PACK_AX_COCG><<<grid, NTHR, 0, s>>>(G, xin, ainv, yout, map, \
+                                                       tw_x, g, act, slot_sys, st, red);   \
         break;                                                                             \
     }
         DDA_FOR_EACH_L(DDA_CASE)
@@ -318,10 +367,11 @@ void launch_ixfft_pack(const cx<T>* G, const cx<T>* xin, const cx<T>* ainv, cx<T
     DDA_LAUNCH_CHECK();
 }
 
-template void launch_unpack_xfft<double>(const z128*, const int*, z128*, const z128*, const Geo&,
-                                         const int*, int, hipStream_t);
-template void launch_unpack_xfft<float>(const z64*, const int*, z64*, const z64*, const Geo&,
-                                        const int*, int, hipStream_t);
+template void launch_unpack_xfft<double>(z128*, const int*, z128*, const z128*, const Geo&,
+                                         const int*, int, const z128*, const BicgSlot*,
+                                         hipStream_t);
+template void launch_unpack_xfft<float>(z64*, const int*, z64*, const z64*, const Geo&, const int*,
+                                        int, const z64*, const BicgSlot*, hipStream_t);
 template void launch_fft_mid<double>(z128*, const z128*, int, bool, int64_t, int64_t, int, int,
                                      int64_t, hipStream_t);
 template void launch_fft_mid<float>(z64*, const z64*, int, bool, int64_t, int64_t, int, int,
@@ -332,10 +382,10 @@ template void launch_zconv<float>(z64*, const z64* const*, const z64*, const Geo
                                   const int*, int, hipStream_t);
 template void launch_ixfft_pack<double>(const z128*, const z128*, const z128*, z128*,
                                         const int*, const z128*, const Geo&, const int*,
-                                        const int*, int, bool, hipStream_t);
+                                        const int*, int, int, BicgSlot*, RedScratch, hipStream_t);
 template void launch_ixfft_pack<float>(const z64*, const z64*, const z64*, z64*, const int*,
-                                       const z64*, const Geo&, const int*, const int*, int, bool,
-                                       hipStream_t);
+                                       const z64*, const Geo&, const int*, const int*, int, int,
+                                       BicgSlot*, RedScratch, hipStream_t);
 
 // ------------------------------------------------------------ D build -----
 // G_tilde(R) = exp(ikR)/R^3 [(k^2R^2 + ikR - 1) I + (3 - 3ikR - k^2R^2) Rh Rh]
@@ -408,7 +458,22 @@ __global__ __launch_bounds__(NTHR) void k_fft_rows(z128* __restrict__ data,
     }
 }
 
-void launch_build_D(z128* D, const Geo& g, double d, double k_re, double k_im,
+__global__ __launch_bounds__(NTHR) void k_extract_corner(const z128* __restrict__ full,
+                                                         z128* __restrict__ red, Geo g) {
+    const int mxh = g.mx / 2 + 1, myh = g.my / 2 + 1, mzh = g.mz / 2 + 1;
+    const int64_t total = int64_t(6) * mzh * myh * mxh;
+    for (int64_t t = blockIdx.x * int64_t(NTHR) + threadIdx.x; t < total;
+         t += int64_t(gridDim.x) * NTHR) {
+        int64_t r = t;
+        const int kx = int(r % mxh); r /= mxh;
+        const int ky = int(r % myh); r /= myh;
+        const int kz = int(r % mzh);
+        const int q = int(r / mzh);
+        red[t] = full[((int64_t(q) * g.mz + kz) * g.my + ky) * g.mx + kx];
+    }
+}
+
+void launch_build_D(z128* Dred, z128* D, const Geo& g, double d, double k_re, double k_im,
                     const z128* tw_x, const z128* tw_y, const z128* tw_z, hipStream_t s) {
     const int64_t plane = int64_t(g.my) * g.mx;
     const int64_t total = plane * g.mz;
@@ -429,6 +494,9 @@ void launch_build_D(z128* D, const Geo& g, double d, double k_re, double k_im,
     DDA_LAUNCH_CHECK();
     launch_fft_mid<double>(D, tw_y, g.my, false, 6 * int64_t(g.mz), g.mx, g.my, g.my, plane, s);
     launch_fft_mid<double>(D, tw_z, g.mz, false, 6, plane, g.mz, g.mz, total, s);
+    const int64_t nred = dred_elems(g);
+    k_extract_corner<<<unsigned(std::min<int64_t>(nblk(nred, NTHR), 65536)), NTHR, 0, s>>>(D, Dred, g);
+    DDA_LAUNCH_CHECK();
 }
 
 __global__ void k_z128_to_z64(const z128* __restrict__ in, z64* __restrict__ out, int64_t n) {

@@ -1,0 +1,104 @@
+// Per right-hand-side solver state resident on the device, and the
+// deterministic block reduction shared by the Krylov and the fused FFT
+// kernels.
+#pragma once
+
+#include "common.h"
+
+namespace dda {
+
+enum SlotStatus : int {
+    SLOT_ACTIVE = 0,
+    SLOT_CONVERGED = 1,  // the recursive residual met the tolerance
+    SLOT_HALF = 2,       // BiCGStab: ||s|| met the tolerance inside an iteration
+    SLOT_BREAKDOWN = 3,  // a Krylov scalar vanished or went non-finite
+};
+
+struct BicgSlot {
+    z128 rho, rho_old, alpha, omega;  // BiCGStab; COCG uses rho and alpha
+    z128 rv, ts;                      // BiCGStab <rhat, v>, <t, s>; COCG: rv = p^T q
+    z128 beta;                        // COCG: p <- r + beta p
+    double tt;                        // <t, t>
+    double bnorm2;                    // ||b||^2
+    double rnorm2;                    // ||r||^2 (recursive, or true after a residual pass)
+    double rmax2;                     // largest ||r||^2 since the last FP64 residual
+    double tol2;                      // tol^2
+    double upd2;                      // reliable update when rnorm2 < upd2 * rmax2 (0: never)
+    int status;
+    int iters;
+    int want_update;                  // set by the device, cleared by the FP64 residual pass
+    int pad_;
+};
+
+// Reduction scratch: per slot, up to `max_blocks` partial rows of up to 8
+// doubles.  A reduction is two kernels: the work kernel writes one row per
+// block (block_partial), then a finalize kernel with one block per slot sums
+// the rows in index order (sum_rows) and updates the slot's scalars.  No
+// atomics and no fences; the result does not depend on block scheduling.
+struct RedScratch {
+    double* partial;  // [max_slots][max_blocks][8]
+    int max_blocks;
+};
+
+__device__ __forceinline__ z128 zdiv(z128 a, z128 b) {
+    const double s = 1.0 / (b.x * b.x + b.y * b.y);
+    return z128{(a.x * b.x + a.y * b.y) * s, (a.y * b.x - a.x * b.y) * s};
+}
+
+template <int K>
+__device__ __forceinline__ void wave_sum(double (&v)[K]) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] += __shfl_down(v[k], off, 64);
+    }
+}
+
+// Block-reduces K values (blockDim.x == NT) and stores them as partial row
+// `blk` of `slot`.  Must be called by every thread of the block.
+template <int K, int NT>
+__device__ __forceinline__ void block_partial(double (&v)[K], RedScratch red, int slot, int blk) {
+    __shared__ double sm[NT / 64][K];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    wave_sum<K>(v);
+    if (lane == 0)
+        for (int k = 0; k < K; ++k) sm[w][k] = v[k];
+    __syncthreads();
+    if (tid == 0) {
+        double* row = red.partial + (int64_t(slot) * red.max_blocks + blk) * 8;
+        for (int k = 0; k < K; ++k) {
+            double s = 0.0;
+            for (int q = 0; q < NT / 64; ++q) s += sm[q][k];
+            row[k] = s;
+        }
+    }
+}
+
+// Sums rows 0..nblk-1 of `slot` in a fixed order; the totals are valid in
+// thread 0.  Must be called by every thread of the block.
+template <int K, int NT>
+__device__ __forceinline__ void sum_rows(RedScratch red, int slot, int nblk, double (&tot)[K]) {
+    __shared__ double sm[NT / 64][K];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const double* rows = red.partial + int64_t(slot) * red.max_blocks * 8;
+    double acc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = 0.0;
+    for (int b = tid; b < nblk; b += NT) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) acc[k] += rows[int64_t(b) * 8 + k];
+    }
+    wave_sum<K>(acc);
+    if (lane == 0)
+        for (int k = 0; k < K; ++k) sm[w][k] = acc[k];
+    __syncthreads();
+    if (tid == 0) {
+        for (int k = 0; k < K; ++k) {
+            double s = 0.0;
+            for (int q = 0; q < NT / 64; ++q) s += sm[q][k];
+            tot[k] = s;
+        }
+    }
+}
+
+}  // namespace dda

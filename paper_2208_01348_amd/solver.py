@@ -18,6 +18,7 @@ from . import _lib as L
 
 _POL = {"ldr": L.DDA_POL_LDR, "cm": L.DDA_POL_CM, "rr": L.DDA_POL_RR}
 _PREC = {"fp64": L.DDA_PREC_FP64, "mixed": L.DDA_PREC_MIXED}
+_SOLVER = {"bicgstab": L.DDA_SOLVER_BICGSTAB, "cocg": L.DDA_SOLVER_COCG}
 
 
 @dataclass
@@ -33,6 +34,7 @@ class DDASolver:
 
     def __init__(self, mask: np.ndarray, d_nm: float, m_h: complex, polarizability: str = "ldr",
                  precision: str = "fp64", tol: float = 1e-10, maxit: int = 100000,
+                 solver: str = "bicgstab",
                  check_every: int = 16, stream: Optional[torch.cuda.Stream] = None):
         m = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8))
         if m.ndim != 3:
@@ -45,6 +47,7 @@ class DDASolver:
         opt = L.dda_default_options()
         opt.polarizability = _POL[polarizability]
         opt.precision = _PREC[precision]
+        opt.solver = _SOLVER[solver]
         opt.tol = float(tol)
         opt.maxit = int(maxit)
         opt.check_every = int(check_every)

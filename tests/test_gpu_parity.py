@@ -167,16 +167,18 @@ def _small_particle():
 
 @pytest.mark.parametrize("name,m_h,beta", SOLVE_CASES)
 @pytest.mark.parametrize("precision,bar", [("fp64", 1e-9), ("mixed", 1e-5)])
-def test_losses_match_oracle(name, m_h, beta, precision, bar):
+@pytest.mark.parametrize("solver", ["bicgstab", "cocg"])
+def test_losses_match_oracle(name, m_h, beta, precision, bar, solver):
     mask, d, r0 = _small_particle()
     n = int(mask.sum())
     energies = np.array([1.8, 2.6])
     eps_tab = W.drude_eps(energies)
     eps = np.repeat(eps_tab[:, None], n, axis=1)
-    say("losses", name, precision, "n_occ", n)
+    say("losses", name, precision, solver, "n_occ", n)
     s = DDASolver(mask, d, m_h, precision=precision, tol=1e-12 if precision == "fp64" else 1e-10,
-                  maxit=20000)
+                  maxit=20000, solver=solver)
     P, info = s.spectrum(energies, beta, eps, r0)
+    say("  iterations", [i.iters for i in info], "matvecs", [i.matvecs for i in info])
     for i, inf in enumerate(info):
         assert inf.status == 0 and inf.rel_residual <= (1e-12 if precision == "fp64" else 1e-10)
     k = 0
@@ -194,29 +196,35 @@ def test_losses_match_oracle(name, m_h, beta, precision, bar):
     s.close()
 
 
-def test_c1_full_size_matches_oracle_golden():
+@pytest.mark.parametrize("solver,precision", [("bicgstab", "fp64"), ("cocg", "fp64"),
+                                              ("cocg", "mixed")])
+def test_c1_full_size_matches_oracle_golden(solver, precision):
     with open(os.path.join(HERE, "golden", "oracle_c1.json")) as f:
         gold = json.load(f)
     w = W.c1_single_solve()
-    say("c1 full size", w.n_occ)
-    s = DDASolver(w.mask, w.d, w.m_h, tol=1e-12, maxit=50000)
+    say("c1 full size", w.n_occ, solver, precision)
+    s = DDASolver(w.mask, w.d, w.m_h, tol=1e-12 if precision == "fp64" else 1e-10, maxit=50000,
+                  solver=solver, precision=precision)
     P, info = s.spectrum(w.energies, w.beta, w.eps_dipoles(0)[None, :], w.r0)
     say("iters", info[0].iters, "residual", info[0].rel_residual)
     for j, nm in enumerate(["p_eels", "p_ext", "p_abs", "p_cl"]):
         err = abs(P[0][j] - gold[nm]) / abs(gold[nm])
         say(f"  {nm}: gpu={P[0][j]:.15e} oracle={gold[nm]:.15e} rel={err:.2e}")
-        assert err <= 1e-9
+        assert err <= (1e-9 if precision == "fp64" else 1e-5)
     s.close()
 
 
-def test_batch_equals_single():
+@pytest.mark.parametrize("solver,precision", [("bicgstab", "fp64"), ("cocg", "fp64"),
+                                              ("cocg", "mixed")])
+def test_batch_equals_single(solver, precision):
     """Energies x trajectories as one batch give the same result as one solve
-    per right-hand side."""
+    per right-hand side (each right-hand side runs the same arithmetic in the
+    same order whatever else shares the launch)."""
     mask, d, r0 = _small_particle()
     n = int(mask.sum())
     energies = np.array([1.5, 2.0, 2.5])
     eps = np.repeat(W.drude_eps(energies)[:, None], n, axis=1)
-    s = DDASolver(mask, d, 1.45, tol=1e-11, maxit=20000)
+    s = DDASolver(mask, d, 1.45, tol=1e-11, maxit=20000, solver=solver, precision=precision)
     Pb, _ = s.spectrum(energies, 0.55, eps, r0)
     k = 0
     for ie, E in enumerate(energies):
