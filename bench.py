@@ -28,7 +28,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-KERNELS = ["unpack_xfft", "yfft", "zconv", "iyfft", "ixfft_pack"]
+KERNELS = ["unpack_xfft", "yfft", "zconv", "iyfft", "ixfft_pack", "yzconv"]
+# the costliest kernel of the matvec chain: the fused yz kernel on lattices
+# whose padded yz plane fits in LDS, the z pass otherwise (profiles/)
+CONV_KERNELS = ["yzconv", "zconv"]
 
 
 def kernel_bytes(name: str, nx, ny, nz, mx, my, mz, n_occ, c: int) -> float:
@@ -49,6 +52,9 @@ def kernel_bytes(name: str, nx, ny, nz, mx, my, mz, n_occ, c: int) -> float:
         return (full_y + row_x) * c
     if name == "ixfft_pack":
         return row_x * c + 4 * N + (3 + 1 + 3) * n_occ * c
+    if name == "yzconv":
+        # T[kx][3][nz][ny] in and out, D as kx slabs of its [0, L/2]^2 corner
+        return (2 * row_x + 6 * (mx // 2 + 1) * (my // 2 + 1) * (mz // 2 + 1)) * c
     raise KeyError(name)
 
 
@@ -96,6 +102,8 @@ def main():
     ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
     ap.add_argument("--solver", choices=["cocg", "bicgstab"], default="cocg")
     ap.add_argument("--n-energy", type=int, default=128)
+    ap.add_argument("--check-every", type=int, default=16,
+                    help="Krylov iterations between host convergence checks")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -130,7 +138,7 @@ def main():
     E = w.energies
     eps = np.repeat(w.eps_table()[:, None], n, axis=1)
     solver = DDASolver(w.mask, w.d, w.m_h, precision=args.precision, tol=w.tol, maxit=50000,
-                       solver=args.solver)
+                       solver=args.solver, check_every=args.check_every)
     mx, my, mz = solver.grid
     log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
     log(f"workload {w.name}: n_occ={n} grid={solver.grid} energies={E.size} "
@@ -146,7 +154,8 @@ def main():
         torch.cuda.synchronize()
         log(f"warmup {i}: {time.perf_counter() - t:.3f} s")
 
-    solver.set_timing(True)
+    # HIP events around the dominant kernel only (fewer host calls per launch)
+    solver.set_timing(True, kernels=CONV_KERNELS)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(args.steps):
@@ -163,17 +172,12 @@ def main():
         f"min/median/max {min(iters)}/{int(np.median(iters))}/{max(iters)}")
     statuses = sorted(set(x.status for x in info))
 
-    # per-kernel roofline (HIP events on the library's stream)
+    # roofline of the dominant kernel (HIP events on the library's stream);
+    # in the mixed path the launches mix FP32 (iterations) and FP64 (reliable
+    # updates); the algorithmic bytes use the FP32 size, which dominates
     c = 8 if args.precision == "mixed" else 16
-    ktimes = {}
-    for k in KERNELS:
-        ms, launches, rhs = solver.kernel_time(k)
-        ktimes[k] = (ms, launches, rhs)
-    # the FP32 kernels dominate the mixed path; report the costliest kernel
-    dom = max(KERNELS, key=lambda k: ktimes[k][0] * ktimes[k][1])
-    ms, launches, rhs = ktimes[dom]
-    # launches mix FP32 (inner) and FP64 (refinement) matvecs in the mixed
-    # path; the algorithmic bytes use the inner precision, which dominates
+    dom = max(CONV_KERNELS, key=lambda k: solver.kernel_time(k)[1])
+    ms, launches, rhs = solver.kernel_time(dom)
     per_launch = kernel_bytes(dom, w.nx, w.ny, w.nz, mx, my, mz, n, c) * rhs
     achieved = per_launch / (ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
@@ -181,10 +185,6 @@ def main():
                 "traffic": read_traffic(dom, "c2", args.precision, rhs),
                 "avg_launch_ms": round(ms, 5), "launches": launches,
                 "rhs_per_launch": round(rhs, 2), "bytes_per_launch": round(per_launch)}
-    kernel_table = {k: {"avg_ms": round(v[0], 5), "launches": v[1], "rhs_per_launch": round(v[2], 2),
-                        "GBps": round(kernel_bytes(k, w.nx, w.ny, w.nz, mx, my, mz, n, c) * v[2]
-                                      / max(v[0], 1e-12) / 1e6, 1)}
-                    for k, v in ktimes.items()}
     solver.set_timing(False)
 
     extras = {}
@@ -208,6 +208,7 @@ def main():
         "vs_baseline": None,
         "dtype": "c64 matvec + f64 refinement" if args.precision == "mixed" else "c128",
         "data": "synthetic (Drude nanorod, seeded; no optical data or measured spectra)",
+        "check_every": args.check_every,
         "config": {"workload": "c2 nanorod spectrum: capped rod 20x20x80 nm on 96x24x24 dipoles "
                                f"(n_occ={n}), host 1.45, beta 0.55, {E.size} energies over 1-3 eV, "
                                f"tol {w.tol}, LDR",
@@ -217,7 +218,6 @@ def main():
                   "iterations_max": max(iters), "matvecs_total": int(sum(mvs)),
                   "max_rel_residual": max(x.rel_residual for x in info), "statuses": statuses},
         "roofline": roofline,
-        "kernels": kernel_table,
         "cpu_baseline": cpu,
     }
     out.update(extras)
@@ -247,9 +247,10 @@ def measure_extras(torch, W, DDASolver, log):
             for _ in range(reps):
                 s3.matvec(Em, eps3, x, precision=p, out=y)
             # device time of the kernel chain (HIP events per kernel)
-            dt_s = sum(s3.kernel_time(k)[0] for k in KERNELS) * 1e-3
+            kt = {k: s3.kernel_time(k)[0] for k in KERNELS if s3.kernel_time(k)[1] > 0}
+            dt_s = sum(kt.values()) * 1e-3
             s3.set_timing(False)
-            per_rhs = sum(kernel_bytes(k, w3.nx, w3.ny, w3.nz, mx, my, mz, n3, c) for k in KERNELS)
+            per_rhs = sum(kernel_bytes(k, w3.nx, w3.ny, w3.nz, mx, my, mz, n3, c) for k in kt)
             d_red = 6 * (mz // 2 + 1) * (my // 2 + 1) * (mx // 2 + 1)
             model = ((72 * N + 10 * n3) * nrhs + d_red) * c  # one D shared by the batch
             mv[f"{prec}_nrhs{nrhs}"] = {
@@ -257,7 +258,9 @@ def measure_extras(torch, W, DDASolver, log):
                 "model_bytes_per_matvec": int(model),
                 "GBps_model": round(model / dt_s / 1e9, 1),
                 "GBps_kernels": round(per_rhs * nrhs / dt_s / 1e9, 1),
-                "frac_of_hbm_peak": round(model / dt_s / 1e9 / HBM_PEAK_GBS, 4)}
+                "frac_of_hbm_peak": round(model / dt_s / 1e9 / HBM_PEAK_GBS, 4),
+                "kernels_GBps": {k: round(kernel_bytes(k, w3.nx, w3.ny, w3.nz, mx, my, mz, n3, c)
+                                          * nrhs / (kt[k] * 1e-3) / 1e9, 1) for k in kt}}
             log(f"matvec 64^3 {prec} nrhs={nrhs}: {dt_s * 1e3:.3f} ms, "
                 f"{model / dt_s / 1e9:.0f} GB/s (model)")
     s3.close()

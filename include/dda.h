@@ -186,9 +186,14 @@ int dda_matvec(dda_ctx* ctx, double energy_eV, const double* eps_dipole, int pre
 
 /* Per-kernel timing of the matvec chain, measured with HIP events recorded on
  * the context's stream around every launch while timing is enabled
- * (dda_set_timing resets the counters).  For kernel `name` ("unpack_xfft",
- * "yfft", "zconv", "iyfft", "ixfft_pack"): average device time per launch
- * (ms), number of launches, and average right-hand sides per launch. */
+ * (dda_set_timing resets the counters).  enabled: 0 off, 1 all kernels,
+ * otherwise a bit mask of the kernels to time, bit k for the k-th name of
+ * "unpack_xfft", "yfft", "zconv", "iyfft", "ixfft_pack", "yzconv" (fewer
+ * events, less host work per launch).  Lattices whose padded yz plane fits in
+ * LDS run a three-pass chain timed as "unpack_xfft", "yzconv", "ixfft_pack";
+ * the others the five-pass chain of the first five names.
+ * dda_kernel_time gives, for one kernel: average device time per launch (ms),
+ * number of launches, and average right-hand sides per launch. */
 int dda_set_timing(dda_ctx* ctx, int enabled);
 int dda_kernel_time(dda_ctx* ctx, const char* name, double* avg_ms, int64_t* launches,
                     double* avg_rhs);

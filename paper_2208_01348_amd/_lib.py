@@ -183,8 +183,19 @@ def dda_matvec(ctx, energy_eV: float, eps_dipole, precision: int, interaction_on
                              ctypes.c_void_p(y_dev), int(nrhs)))
 
 
-def dda_set_timing(ctx, enabled: bool) -> None:
-    _check(load().dda_set_timing(ctx, int(bool(enabled))))
+KERNEL_NAMES = ["unpack_xfft", "yfft", "zconv", "iyfft", "ixfft_pack", "yzconv"]
+
+
+def dda_set_timing(ctx, enabled, kernels=None) -> None:
+    """enabled: False/True; kernels: optional list of names to time."""
+    if not enabled:
+        v = 0
+    elif kernels is None:
+        v = 1
+    else:
+        v = sum(1 << KERNEL_NAMES.index(k) for k in kernels)
+        v = v if v != 1 else (1 << 5) | 1  # bit 0 alone must not read as "all"
+    _check(load().dda_set_timing(ctx, int(v)))
 
 
 def dda_kernel_time(ctx, name: str):

@@ -87,9 +87,9 @@ struct DEntry {
 struct Timer {
     std::vector<hipEvent_t> pool;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
-    double total_ms[5] = {0, 0, 0, 0, 0};
-    int64_t count[5] = {0, 0, 0, 0, 0};
-    int64_t units[5] = {0, 0, 0, 0, 0};
+    double total_ms[6] = {0, 0, 0, 0, 0, 0};
+    int64_t count[6] = {0, 0, 0, 0, 0, 0};
+    int64_t units[6] = {0, 0, 0, 0, 0, 0};
     ~Timer() {
         for (auto& e : pool) (void)hipEventDestroy(e);
         for (auto& p : pending) {
@@ -109,7 +109,8 @@ struct Timer {
     }
 };
 
-const char* const kKernelNames[5] = {"unpack_xfft", "yfft", "zconv", "iyfft", "ixfft_pack"};
+const char* const kKernelNames[6] = {"unpack_xfft", "yfft", "zconv", "iyfft", "ixfft_pack",
+                                     "yzconv"};
 
 int choose_fft_len(int n) {
     static const int sizes[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512};
@@ -152,7 +153,9 @@ struct dda_ctx {
     PinnedBuf host_st, host_act, host_misc;
     int max_blocks = 1024;
     bool timing = false;
+    unsigned timing_mask = 0x3f;  // which matvec kernels are timed
     Timer timer;
+    hipEvent_t sync_ev = nullptr;  // for low-latency host waits
 
     int64_t nv() const { return 3 * g.n_occ; }
 };
@@ -170,20 +173,34 @@ void check_finite(double v, const char* what) {
     if (!std::isfinite(v)) throw Error(DDA_EINVAL, std::string(what) + " is not finite");
 }
 
+// Waits until the context's stream has drained, spinning on an event: the
+// solver loop waits for a few scalars every few iterations, and a sleeping
+// wait costs about a millisecond of wake-up latency each time.
+void wait_stream(dda_ctx* c) {
+    if (!c->sync_ev)
+        DDA_HIP_CHECK(hipEventCreateWithFlags(&c->sync_ev, hipEventDisableTiming));
+    DDA_HIP_CHECK(hipEventRecord(c->sync_ev, c->stream));
+    hipError_t e;
+    while ((e = hipEventQuery(c->sync_ev)) == hipErrorNotReady) {
+    }
+    DDA_HIP_CHECK(e);
+}
+
 // Copies a pageable host array to the device in the order of the context's
 // stream and waits for it (the host array may go out of scope afterwards).
 void upload(dda_ctx* c, void* dst, const void* src, size_t bytes) {
     if (bytes == 0) return;
     DDA_HIP_CHECK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->stream));
-    DDA_HIP_CHECK(hipStreamSynchronize(c->stream));
+    wait_stream(c);
 }
 
 struct Tic {
     dda_ctx* c;
     int k;
     hipEvent_t a = nullptr, b = nullptr;
-    Tic(dda_ctx* c_, int k_, int n_rhs) : c(c_), k(k_) {
-        if (c->timing) {
+    bool on;
+    Tic(dda_ctx* c_, int k_, int n_rhs) : c(c_), k(k_), on(c_->timing && ((c_->timing_mask >> k_) & 1u)) {
+        if (on) {
             c->timer.units[k] += n_rhs;
             a = c->timer.get();
             b = c->timer.get();
@@ -191,7 +208,7 @@ struct Tic {
         }
     }
     ~Tic() {
-        if (c->timing) {
+        if (on) {
             (void)hipEventRecord(b, c->stream);
             c->timer.pending.push_back({k, {a, b}});
         }
@@ -220,6 +237,11 @@ dda::RedScratch red_of(dda_ctx* c) {
 // mode PACK_AX (y = A x), PACK_GX (y = G_off x) or PACK_AX_COCG (y = A x with
 // the COCG scalars fused; then fuse_r gives the direction update
 // x <- fuse_r + beta x done in place by the first kernel).
+int pack_blocks(const dda_ctx* c, int csize) {
+    return dda::yz_fused_ok(c->g, csize) ? dda::yz_pack_blocks_per_slot(c->g)
+                                         : dda::pack_blocks_per_slot(c->g);
+}
+
 template <typename T>
 void matvec(dda_ctx* c, dda::cx<T>* x, dda::cx<T>* y, const int* act, int n_act,
             const dda::cx<T>* const* dptr, const int* slot_sys, const dda::cx<T>* ainv, int mode,
@@ -229,43 +251,85 @@ void matvec(dda_ctx* c, dda::cx<T>* x, dda::cx<T>* y, const int* act, int n_act,
     auto* G = c->G.as<dda::cx<T>>();
     hipStream_t s = c->stream;
     auto* st = c->st.as<dda::BicgSlot>();
-    const int64_t plane = int64_t(g.my) * g.mx;
-    {
-        Tic t(c, 0, n_act);
-        dda::launch_unpack_xfft<T>(x, c->map.as<int>(), G, tw_of<T>(c, 0), g, act, n_act, fuse_r,
-                                   st, s);
-    }
-    {
-        Tic t(c, 1, n_act);
-        dda::launch_fft_mid<T>(G, tw_of<T>(c, 1), g.my, false, int64_t(n_act) * 3 * g.nz, g.mx,
-                               g.ny, g.my, plane, s);
-    }
-    {
-        Tic t(c, 2, n_act);
-        dda::launch_zconv<T>(G, dptr, tw_of<T>(c, 2), g, act, slot_sys, n_act, s);
-    }
-    {
-        Tic t(c, 3, n_act);
-        dda::launch_fft_mid<T>(G, tw_of<T>(c, 1), g.my, true, int64_t(n_act) * 3 * g.nz, g.mx,
-                               g.my, g.ny, plane, s);
-    }
-    {
-        Tic t(c, 4, n_act);
-        dda::launch_ixfft_pack<T>(G, x, ainv, y, c->map.as<int>(), tw_of<T>(c, 0), g, act,
-                                  slot_sys, n_act, mode, st, red_of(c), s);
+    constexpr int csize = int(sizeof(dda::cx<T>));
+    if (dda::yz_fused_ok(g, csize)) {
+        {
+            Tic t(c, 0, n_act);
+            dda::launch_xfft_t<T>(x, c->map.as<int>(), G, tw_of<T>(c, 0), g, act, n_act, fuse_r,
+                                  st, s);
+        }
+        {
+            Tic t(c, 5, n_act);
+            dda::launch_yzconv<T>(G, dptr, tw_of<T>(c, 1), tw_of<T>(c, 2), g, act, slot_sys, n_act,
+                                  s);
+        }
+        {
+            Tic t(c, 4, n_act);
+            dda::launch_ixfft_t<T>(G, x, ainv, y, c->map.as<int>(), tw_of<T>(c, 0), g, act,
+                                   slot_sys, n_act, mode, red_of(c), s);
+        }
+    } else {
+        const int64_t plane = int64_t(g.my) * g.mx;
+        {
+            Tic t(c, 0, n_act);
+            dda::launch_unpack_xfft<T>(x, c->map.as<int>(), G, tw_of<T>(c, 0), g, act, n_act,
+                                       fuse_r, st, s);
+        }
+        {
+            Tic t(c, 1, n_act);
+            dda::launch_fft_mid<T>(G, tw_of<T>(c, 1), g.my, false, int64_t(n_act) * 3 * g.nz,
+                                   g.mx, g.ny, g.my, plane, s);
+        }
+        {
+            Tic t(c, 2, n_act);
+            dda::launch_zconv<T>(G, dptr, tw_of<T>(c, 2), g, act, slot_sys, n_act, s);
+        }
+        {
+            Tic t(c, 3, n_act);
+            dda::launch_fft_mid<T>(G, tw_of<T>(c, 1), g.my, true, int64_t(n_act) * 3 * g.nz,
+                                   g.mx, g.my, g.ny, plane, s);
+        }
+        {
+            Tic t(c, 4, n_act);
+            dda::launch_ixfft_pack<T>(G, x, ainv, y, c->map.as<int>(), tw_of<T>(c, 0), g, act,
+                                      slot_sys, n_act, mode, st, red_of(c), s);
+        }
     }
     if (mode == dda::PACK_AX_COCG)
-        dda::cocg_alpha_finalize(st, act, n_act, red_of(c), dda::pack_blocks_per_slot(g), s);
+        dda::cocg_alpha_finalize(st, act, n_act, red_of(c), pack_blocks(c, csize), s);
 }
 
 // ------------------------------------------------------------ D cache
+// Stored D layout of a precision's matvec path: kx slabs for the three-pass
+// chain, the [0, M/2]^3 corner otherwise.
+bool uses_yz(const dda_ctx* c, int csize) { return dda::yz_fused_ok(c->g, csize); }
+size_t d_elems(const dda_ctx* c, int csize) {
+    return size_t(uses_yz(c, csize) ? dda::dyz_elems(c->g) : dda::dred_elems(c->g));
+}
+
+void build_full_D(dda_ctx* c, cplx k) {
+    c->dfull.ensure(size_t(dda::dgrid_elems(c->g)) * sizeof(z128));
+    dda::launch_build_D(c->dfull.as<z128>(), c->g, c->d, k.real(), k.imag(),
+                        c->tw128[0].as<z128>(), c->tw128[1].as<z128>(), c->tw128[2].as<z128>(),
+                        c->stream);
+}
+
+template <typename T>
+void extract_D(dda_ctx* c, dda::cx<T>* out) {
+    if (uses_yz(c, int(sizeof(dda::cx<T>))))
+        dda::launch_extract_yz<T>(c->dfull.as<z128>(), out, c->g, c->stream);
+    else
+        dda::launch_extract_corner<T>(c->dfull.as<z128>(), out, c->g, c->stream);
+}
+
 DEntry* get_D(dda_ctx* c, double energy, bool need64) {
     const cplx k = c->mh * (energy / kHbarC);
     auto key = std::make_pair(k.real(), k.imag());
     auto it = c->dcache.find(key);
     DEntry* e;
+    bool full_ready = false;
     if (it == c->dcache.end()) {
-        const size_t b128 = size_t(dda::dred_elems(c->g)) * sizeof(z128);
+        const size_t b128 = d_elems(c, 16) * sizeof(z128);
         // evict least recently used entries beyond the limit
         size_t used = 0;
         for (auto& kv : c->dcache) used += kv.second->d128.bytes + kv.second->d64.bytes;
@@ -281,19 +345,18 @@ DEntry* get_D(dda_ctx* c, double energy, bool need64) {
         }
         auto ne = std::make_unique<DEntry>();
         ne->d128.ensure(b128);
-        c->dfull.ensure(size_t(dda::dgrid_elems(c->g)) * sizeof(z128));
-        dda::launch_build_D(ne->d128.as<z128>(), c->dfull.as<z128>(), c->g, c->d, k.real(), k.imag(),
-                            c->tw128[0].as<z128>(), c->tw128[1].as<z128>(),
-                            c->tw128[2].as<z128>(), c->stream);
+        build_full_D(c, k);
+        full_ready = true;
+        extract_D<double>(c, ne->d128.as<z128>());
         e = ne.get();
         c->dcache[key] = std::move(ne);
     } else {
         e = it->second.get();
     }
     if (need64 && !e->has64) {
-        const int64_t n = dda::dred_elems(c->g);
-        e->d64.ensure(size_t(n) * sizeof(z64));
-        dda::launch_convert_z128_to_z64(e->d128.as<z128>(), e->d64.as<z64>(), n, c->stream);
+        e->d64.ensure(d_elems(c, 8) * sizeof(z64));
+        if (!full_ready) build_full_D(c, k);
+        extract_D<float>(c, e->d64.as<z64>());
         e->has64 = true;
     }
     e->last_use = ++c->use_clock;
@@ -390,7 +453,7 @@ void upload_act(dda_ctx* c, const std::vector<int>& act) {
 std::vector<dda::BicgSlot> read_states(dda_ctx* c, int nslots) {
     DDA_HIP_CHECK(hipMemcpyAsync(c->host_st.p, c->st.p, size_t(nslots) * sizeof(dda::BicgSlot),
                                  hipMemcpyDeviceToHost, c->stream));
-    DDA_HIP_CHECK(hipStreamSynchronize(c->stream));
+    wait_stream(c);
     auto* p = c->host_st.as<dda::BicgSlot>();
     return std::vector<dda::BicgSlot>(p, p + nslots);
 }
@@ -735,7 +798,7 @@ void check_beta(dda_ctx* c, double beta) {
 int systems_per_chunk(dda_ctx* c, int n_energy, int n_traj, bool mixed) {
     size_t free_b = 0, total_b = 0;
     DDA_HIP_CHECK(hipMemGetInfo(&free_b, &total_b));
-    const size_t dsz = size_t(dda::dred_elems(c->g)) * (sizeof(z128) + (mixed ? sizeof(z64) : 0));
+    const size_t dsz = d_elems(c, 16) * sizeof(z128) + (mixed ? d_elems(c, 8) * sizeof(z64) : 0);
     const size_t per_sys = size_t(n_traj) * slot_bytes(c, mixed) + dsz +
                            size_t(c->g.n_occ) * (sizeof(z128) + sizeof(z64));
     const size_t budget = std::min<size_t>(free_b / 10 * 7, size_t(96) << 30);
@@ -826,7 +889,8 @@ int dda_setup(const uint8_t* mask, int nx, int ny, int nz, double d_nm, double m
         }
     }
     g.n_occ = int64_t(c->occ_lin.size());
-    c->max_blocks = std::max(1024, dda::pack_blocks_per_slot(g));
+    c->max_blocks = std::max(1024, std::max(dda::pack_blocks_per_slot(g),
+                                            dda::yz_pack_blocks_per_slot(g)));
     c->map.ensure(size_t(N) * sizeof(int));
     DDA_HIP_CHECK(hipMemcpy(c->map.p, hmap.data(), size_t(N) * sizeof(int), hipMemcpyHostToDevice));
     c->occ.ensure(std::max<size_t>(1, c->occ_lin.size()) * sizeof(int));
@@ -1125,7 +1189,8 @@ int dda_set_timing(dda_ctx* c, int enabled) {
     if (!c) throw Error(DDA_EINVAL, "ctx is NULL");
     flush_timer(c);
     c->timing = enabled != 0;
-    for (int k = 0; k < 5; ++k) {
+    c->timing_mask = (enabled == 1) ? 0x3fu : unsigned(enabled) & 0x3fu;
+    for (int k = 0; k < 6; ++k) {
         c->timer.total_ms[k] = 0;
         c->timer.count[k] = 0;
         c->timer.units[k] = 0;
@@ -1139,7 +1204,7 @@ int dda_kernel_time(dda_ctx* c, const char* name, double* avg_ms, int64_t* launc
     DDA_API_BEGIN
     if (!c || !name || !avg_ms || !launches || !avg_rhs) throw Error(DDA_EINVAL, "NULL argument");
     flush_timer(c);
-    for (int k = 0; k < 5; ++k) {
+    for (int k = 0; k < 6; ++k) {
         if (std::strcmp(name, kKernelNames[k]) == 0) {
             const int64_t n = c->timer.count[k];
             *launches = n;
@@ -1166,6 +1231,7 @@ int dda_destroy(dda_ctx* c) {
     if (!c) return DDA_OK;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
+    if (c->sync_ev) (void)hipEventDestroy(c->sync_ev);
     delete c;
     return DDA_OK;
     DDA_API_END

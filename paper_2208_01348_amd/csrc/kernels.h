@@ -59,10 +59,34 @@ void launch_ixfft_pack(const cx<T>* G, const cx<T>* xin, const cx<T>* ainv, cx<T
                        hipStream_t s);
 
 // Interaction spectrum: D = FFT3(G_tilde on the embedding grid) / (mx my mz),
-// FP64, for one host wavenumber k.  `full` is scratch of dgrid_elems; the
-// reduced corner is written to `Dred` (dred_elems).
-void launch_build_D(z128* Dred, z128* full, const Geo& g, double d, double k_re, double k_im,
+// FP64 over the full grid (dgrid_elems), for one host wavenumber k.  The
+// matvec reads one of two stored layouts, extracted from it:
+//   corner [6][mz/2+1][my/2+1][mx/2+1]           (five-pass chain, dred_elems)
+//   kx slabs [mx/2+1][6][L/2+1][L/2+1], L = my = mz (three-pass chain, dyz_elems)
+void launch_build_D(z128* full, const Geo& g, double d, double k_re, double k_im,
                     const z128* tw_x, const z128* tw_y, const z128* tw_z, hipStream_t s);
+template <typename T>
+void launch_extract_corner(const z128* full, cx<T>* out, const Geo& g, hipStream_t s);
+template <typename T>
+void launch_extract_yz(const z128* full, cx<T>* out, const Geo& g, hipStream_t s);
+int64_t dyz_elems(const Geo& g);
+
+// Three-pass chain (matvec_yz.hip), used when the padded yz plane of the three
+// components fits in LDS (my == mz, see yz_fused_ok).  The work buffer holds
+// T[pos][kx][3][nz][ny] (at most grid_elems).
+bool yz_fused_ok(const Geo& g, int csize);
+int yz_pack_blocks_per_slot(const Geo& g);
+template <typename T>
+void launch_xfft_t(cx<T>* xin, const int* map, cx<T>* Tb, const cx<T>* tw_x, const Geo& g,
+                   const int* act, int n_act, const cx<T>* fuse_r, const BicgSlot* st,
+                   hipStream_t s);
+template <typename T>
+void launch_yzconv(cx<T>* Tb, const cx<T>* const* Dptr, const cx<T>* tw_y, const cx<T>* tw_z,
+                   const Geo& g, const int* act, const int* slot_sys, int n_act, hipStream_t s);
+template <typename T>
+void launch_ixfft_t(const cx<T>* Tb, const cx<T>* xin, const cx<T>* ainv, cx<T>* yout,
+                    const int* map, const cx<T>* tw_x, const Geo& g, const int* act,
+                    const int* slot_sys, int n_act, int mode, RedScratch red, hipStream_t s);
 void launch_convert_z128_to_z64(const z128* in, z64* out, int64_t n, hipStream_t s);
 void launch_convert_z64_to_z128(const z64* in, z128* out, int64_t n, hipStream_t s);
 

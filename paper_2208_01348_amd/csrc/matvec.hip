@@ -39,9 +39,11 @@ constexpr int rows_nl() { return L >= 2048 ? 1 : 2048 / L; }
 // columns per block for strided-axis kernels
 template <typename T, int L>
 constexpr int mid_tx() { return clampi(pow2floor(2048 / L), 1, sizeof(T) == 8 ? 16 : 32); }
+// columns per z-conv block: two mirror sets x 3 components x TX lines of
+// length L within about 64 KB of LDS
 template <typename T, int L>
 constexpr int zconv_tx() {
-    return clampi(pow2floor((sizeof(T) == 8 ? 1024 : 2048) / L), 1, sizeof(T) == 8 ? 16 : 32);
+    return clampi(pow2floor(32768 / (6 * L * int(2 * sizeof(T)))), 1, sizeof(T) == 8 ? 4 : 8);
 }
 
 #define DDA_FOR_EACH_L(X) \
@@ -137,8 +139,12 @@ __global__ __launch_bounds__(NTHR) void k_fft_mid(cx<T>* __restrict__ data,
 }
 
 // ---------------------------------------------------------------- K3 ------
-// Per (kx tile, ky, slot): z-FFT of the three components (nz non-zero
+// Per (kx tile, ky pair, slot): z-FFT of the three components (nz non-zero
 // inputs), w = D u with D the symmetric 3x3 spectrum, z-iFFT, keep nz rows.
+// A block takes the pencils of ky and of its mirror my - ky, and every D
+// value it loads from the stored corner serves the four frequencies
+// (+-kx fixed by the column, ky or my - ky, kz or mz - kz) that share it,
+// with the sign flips of the odd components: four times fewer D loads.
 template <typename T, int L>
 __global__ __launch_bounds__(NTHR) void k_zconv(cx<T>* __restrict__ G,
                                                 const cx<T>* const* __restrict__ Dptr,
@@ -146,54 +152,67 @@ __global__ __launch_bounds__(NTHR) void k_zconv(cx<T>* __restrict__ G,
                                                 const int* __restrict__ act,
                                                 const int* __restrict__ slot_sys) {
     constexpr int TX = zconv_tx<T, L>();
-    constexpr int W = 3 * TX;  // lines per tile: (component, column)
+    constexpr int W = 6 * TX;  // lines per tile: (mirror set, component, column)
     __shared__ cx<T> lds[L * W];
     const int tid = threadIdx.x;
     const int col0 = blockIdx.x * TX;
-    const int ky = blockIdx.y;
+    const int ky0 = blockIdx.y;                 // 0 <= ky0 <= my/2
+    const int ky1 = (g.my - ky0) % g.my;        // its mirror
+    const bool pair = ky1 != ky0;
     const int pos = blockIdx.z;
     const int slot = act ? act[pos] : pos;
     const int sys = slot_sys[slot];
     const int64_t plane = int64_t(g.my) * g.mx;
-    cx<T>* gbase = G + int64_t(pos) * 3 * g.nz * plane + int64_t(ky) * g.mx + col0;
+    cx<T>* gb = G + int64_t(pos) * 3 * g.nz * plane + col0;
+    cx<T>* gset[2] = {gb + int64_t(ky0) * g.mx, gb + int64_t(ky1) * g.mx};
     for (int e = tid; e < L * W; e += NTHR) {
-        const int z = e / W, rem = e % W, c = rem / TX, col = rem % TX;
+        const int z = e / W, rem = e % W, set = rem / (3 * TX), c = (rem / TX) % 3, col = rem % TX;
         cx<T> v{T(0), T(0)};
-        if (z < g.nz && col0 + col < g.mx) v = gbase[(int64_t(c) * g.nz + z) * plane + col];
+        if (z < g.nz && col0 + col < g.mx && (set == 0 || pair))
+            v = gset[set][(int64_t(c) * g.nz + z) * plane + col];
         lds[e] = v;
     }
     __syncthreads();
     fft_tile<T, L, false, W, 1, W, NTHR>(lds, tw, tid);
-    // D from its stored corner: index M - k reads k, odd components flip sign
+    // D from its stored corner [0, M/2]^3: index M - k reads k, odd
+    // components flip sign (xy: x and y, xz: x and z, yz: y and z)
     const int mxh = g.mx / 2 + 1, myh = g.my / 2 + 1, mzh = g.mz / 2 + 1;
-    const bool fy = ky > g.my / 2;
-    const int kyr = fy ? g.my - ky : ky;
     const int64_t dcomp = int64_t(mzh) * myh * mxh;
-    const cx<T>* dbase = Dptr[sys] + int64_t(kyr) * mxh;
-    for (int e = tid; e < L * TX; e += NTHR) {
-        const int kz = e / TX, col = e % TX;
+    const cx<T>* dbase = Dptr[sys] + int64_t(ky0) * mxh;
+    for (int e = tid; e < mzh * TX; e += NTHR) {
+        const int kzp = e / TX, col = e % TX;
         const int kx = col0 + col;
-        if (kx < g.mx) {
-            const bool fx = kx > g.mx / 2, fz = kz > g.mz / 2;
-            const int kxr = fx ? g.mx - kx : kx, kzr = fz ? g.mz - kz : kz;
-            const cx<T>* dp = dbase + int64_t(kzr) * myh * mxh + kxr;
-            const cx<T> dxx = dp[0], dyy = dp[3 * dcomp], dzz = dp[5 * dcomp];
-            cx<T> dxy = dp[dcomp], dxz = dp[2 * dcomp], dyz = dp[4 * dcomp];
-            if (fx != fy) dxy = -dxy;
-            if (fx != fz) dxz = -dxz;
-            if (fy != fz) dyz = -dyz;
-            cx<T>* u = lds + kz * W + col;
-            const cx<T> ux = u[0], uy = u[TX], uz = u[2 * TX];
-            u[0] = dxx * ux + dxy * uy + dxz * uz;
-            u[TX] = dxy * ux + dyy * uy + dyz * uz;
-            u[2 * TX] = dxz * ux + dyz * uy + dzz * uz;
+        if (kx >= g.mx) continue;
+        const bool fx = kx > g.mx / 2;
+        const int kxr = fx ? g.mx - kx : kx;
+        const cx<T>* dp = dbase + int64_t(kzp) * myh * mxh + kxr;
+        const cx<T> dxx = dp[0], dxy0 = dp[dcomp], dxz0 = dp[2 * dcomp];
+        const cx<T> dyy = dp[3 * dcomp], dyz0 = dp[4 * dcomp], dzz = dp[5 * dcomp];
+        const int kz1 = (g.mz - kzp) % g.mz;
+        const int nz_ = (kz1 != kzp) ? 2 : 1;
+        const int nset = pair ? 2 : 1;
+        for (int zi = 0; zi < nz_; ++zi) {
+            const int kz = zi ? kz1 : kzp;
+            const bool fz = zi != 0;
+            for (int set = 0; set < nset; ++set) {
+                const bool fy = set != 0;
+                const cx<T> dxy = (fx != fy) ? -dxy0 : dxy0;
+                const cx<T> dxz = (fx != fz) ? -dxz0 : dxz0;
+                const cx<T> dyz = (fy != fz) ? -dyz0 : dyz0;
+                cx<T>* u = lds + kz * W + set * 3 * TX + col;
+                const cx<T> ux = u[0], uy = u[TX], uz = u[2 * TX];
+                u[0] = dxx * ux + dxy * uy + dxz * uz;
+                u[TX] = dxy * ux + dyy * uy + dyz * uz;
+                u[2 * TX] = dxz * ux + dyz * uy + dzz * uz;
+            }
         }
     }
     __syncthreads();
     fft_tile<T, L, true, W, 1, W, NTHR>(lds, tw, tid);
     for (int e = tid; e < g.nz * W; e += NTHR) {
-        const int z = e / W, rem = e % W, c = rem / TX, col = rem % TX;
-        if (col0 + col < g.mx) gbase[(int64_t(c) * g.nz + z) * plane + col] = lds[e];
+        const int z = e / W, rem = e % W, set = rem / (3 * TX), c = (rem / TX) % 3, col = rem % TX;
+        if (col0 + col < g.mx && (set == 0 || pair))
+            gset[set][(int64_t(c) * g.nz + z) * plane + col] = lds[e];
     }
 }
 
@@ -323,7 +342,7 @@ void launch_zconv(cx<T>* G, const cx<T>* const* Dptr, const cx<T>* tw_z, const G
     switch (g.mz) {
 #define DDA_CASE(N)                                                                    \
     case N: {                                                                          \
-        dim3 grid(nblk(g.mx, zconv_tx<T, N>()), g.my, n_act);                           \
+        dim3 grid(nblk(g.mx, zconv_tx<T, N>()), g.my / 2 + 1, n_act);                   \
         k_zconv<T, N><<<grid, NTHR, 0, s>>>(G, Dptr, tw_z, g, act, slot_sys);           \
         break;                                                                         \
     }
@@ -458,8 +477,9 @@ __global__ __launch_bounds__(NTHR) void k_fft_rows(z128* __restrict__ data,
     }
 }
 
+template <typename T>
 __global__ __launch_bounds__(NTHR) void k_extract_corner(const z128* __restrict__ full,
-                                                         z128* __restrict__ red, Geo g) {
+                                                         cx<T>* __restrict__ red, Geo g) {
     const int mxh = g.mx / 2 + 1, myh = g.my / 2 + 1, mzh = g.mz / 2 + 1;
     const int64_t total = int64_t(6) * mzh * myh * mxh;
     for (int64_t t = blockIdx.x * int64_t(NTHR) + threadIdx.x; t < total;
@@ -469,11 +489,21 @@ __global__ __launch_bounds__(NTHR) void k_extract_corner(const z128* __restrict_
         const int ky = int(r % myh); r /= myh;
         const int kz = int(r % mzh);
         const int q = int(r / mzh);
-        red[t] = full[((int64_t(q) * g.mz + kz) * g.my + ky) * g.mx + kx];
+        red[t] = cvt<T>(full[((int64_t(q) * g.mz + kz) * g.my + ky) * g.mx + kx]);
     }
 }
 
-void launch_build_D(z128* Dred, z128* D, const Geo& g, double d, double k_re, double k_im,
+template <typename T>
+void launch_extract_corner(const z128* full, cx<T>* out, const Geo& g, hipStream_t s) {
+    const int64_t nred = dred_elems(g);
+    k_extract_corner<T><<<unsigned(std::min<int64_t>(nblk(nred, NTHR), 65536)), NTHR, 0, s>>>(
+        full, out, g);
+    DDA_LAUNCH_CHECK();
+}
+template void launch_extract_corner<double>(const z128*, z128*, const Geo&, hipStream_t);
+template void launch_extract_corner<float>(const z128*, z64*, const Geo&, hipStream_t);
+
+void launch_build_D(z128* D, const Geo& g, double d, double k_re, double k_im,
                     const z128* tw_x, const z128* tw_y, const z128* tw_z, hipStream_t s) {
     const int64_t plane = int64_t(g.my) * g.mx;
     const int64_t total = plane * g.mz;
@@ -494,9 +524,6 @@ void launch_build_D(z128* Dred, z128* D, const Geo& g, double d, double k_re, do
     DDA_LAUNCH_CHECK();
     launch_fft_mid<double>(D, tw_y, g.my, false, 6 * int64_t(g.mz), g.mx, g.my, g.my, plane, s);
     launch_fft_mid<double>(D, tw_z, g.mz, false, 6, plane, g.mz, g.mz, total, s);
-    const int64_t nred = dred_elems(g);
-    k_extract_corner<<<unsigned(std::min<int64_t>(nblk(nred, NTHR), 65536)), NTHR, 0, s>>>(D, Dred, g);
-    DDA_LAUNCH_CHECK();
 }
 
 __global__ void k_z128_to_z64(const z128* __restrict__ in, z64* __restrict__ out, int64_t n) {

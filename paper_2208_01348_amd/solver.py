@@ -110,8 +110,8 @@ class DDASolver:
         p, info, _ = self.solve(energies, eps, e, R.shape[0])
         return self.losses(energies, beta, eps, R, e, p), info
 
-    def set_timing(self, enabled: bool) -> None:
-        L.dda_set_timing(self.ctx, enabled)
+    def set_timing(self, enabled: bool, kernels=None) -> None:
+        L.dda_set_timing(self.ctx, enabled, kernels)
 
     def kernel_time(self, name: str):
         """(average ms per launch, launches, average right-hand sides per launch)."""

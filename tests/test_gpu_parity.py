@@ -108,6 +108,10 @@ MATVEC_LATTICES = [
     ("rod_24x6x6", W.capped_rod_mask(24, 6, 6, 1.0, 3.0, 24.0), 1.0),
     ("sphere_16", W.sphere_mask(16, 1.0, 8.0), 1.0),
     ("random_9x4x13", W.random_mask(9, 4, 13, 0.5, seed=3), 2.0),
+    # y, z grids of 64: FP32 takes the three-pass (yz plane in LDS) chain,
+    # FP64 the five-pass one
+    ("random_5x17x17", W.random_mask(5, 17, 17, 0.6, seed=9), 1.3),
+    ("sphere_32", W.sphere_mask(32, 1.0, 16.0), 1.0),
 ]
 
 
@@ -193,6 +197,29 @@ def test_losses_match_oracle(name, m_h, beta, precision, bar, solver):
                 say(f"  E={E} t={t} {nm}: gpu={g:.15e} oracle={v:.15e} rel={err:.2e}")
                 assert err <= bar, (name, precision, E, t, nm, err)
             k += 1
+    s.close()
+
+
+@pytest.mark.parametrize("solver,precision,bar", [("cocg", "mixed", 1e-5), ("cocg", "fp64", 1e-9)])
+def test_losses_when_precisions_use_different_chains(solver, precision, bar):
+    """A 5 x 17 x 17 lattice (FFT grid 12 x 64 x 64): the FP32 matvecs of the
+    mixed path run the three-pass chain, its FP64 reliable updates and the
+    FP64 path the five-pass one; both D layouts come from one build."""
+    mask = W.random_mask(5, 17, 17, 0.6, seed=9)
+    d = 1.3
+    n = int(mask.sum())
+    energies = np.array([2.1])
+    eps = np.repeat(W.drude_eps(energies)[:, None], n, axis=1)
+    r0 = np.array([[9.0, 0.65, 0.0]])
+    say("mixed chains", precision, "n_occ", n)
+    s = DDASolver(mask, d, 1.45, precision=precision, solver=solver,
+                  tol=1e-12 if precision == "fp64" else 1e-10, maxit=20000)
+    P, info = s.spectrum(energies, 0.55, eps, r0)
+    assert info[0].status == 0
+    ref = solve_point(mask, d, eps[0], 1.45, 0.55, r0[0], energies[0], method="lu")
+    vals = [ref.p_eels, ref.p_ext, ref.p_abs, ref.p_cl]
+    for g, v in zip(P[0], vals):
+        assert abs(g - v) <= bar * abs(v), (g, v)
     s.close()
 
 
