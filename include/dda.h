@@ -85,7 +85,17 @@ typedef struct {
                              solution accumulates in FP64 (reliable updates)       */
     double tol;           /* stopping threshold on ||e - A p|| / ||e|| (unscaled)    */
     int maxit;            /* iteration limit (matvec pairs for BiCGStab)              */
-    int check_every;      /* host polls convergence every this many iterations       */
+    int check_every;      /* BiCGStab: the host polls convergence every this many
+                             iterations.  COCG: iterations per interval; each
+                             interval starts with the FP64 residual check of the
+                             right-hand sides that asked for one, and the host
+                             reads the solver states two intervals behind without
+                             stalling the stream                                    */
+    int use_graphs;       /* COCG on a non-default stream: send each interval as a
+                             captured HIP graph (replayed while the set of active
+                             right-hand sides keeps its size); 0 launches kernels
+                             one by one, and so does a context whose kernel timing
+                             is on (dda_set_timing).  Results are identical.       */
 } dda_options;
 
 typedef struct {

@@ -36,7 +36,8 @@ class DDAError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("polarizability", ctypes.c_int), ("solver", ctypes.c_int),
                 ("precision", ctypes.c_int), ("tol", ctypes.c_double),
-                ("maxit", ctypes.c_int), ("check_every", ctypes.c_int)]
+                ("maxit", ctypes.c_int), ("check_every", ctypes.c_int),
+                ("use_graphs", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):

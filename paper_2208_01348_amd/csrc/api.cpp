@@ -150,7 +150,16 @@ struct dda_ctx {
     // work space
     DevBuf G, vec128, vec64, st, partial, act, slot_sys, dptr, ainv128, ainv64, misc;
     DevBuf dfull;  // scratch of the full-grid transform during a D build
+    DevBuf eps_dev, matsys;  // permittivities and wavenumbers of a chunk
     PinnedBuf host_st, host_act, host_misc;
+    int slot_cap = 0;                   // slots per region of host_st / host_act
+    int act_seq = 0;                    // next host_act region
+    hipEvent_t act_ev[4] = {};          // per host_act region: its last upload
+    hipEvent_t ring_ev[4] = {};         // per host_st region: its last state snapshot
+    // Captured COCG interval (not used while kernels are timed: events
+    // recorded by graph nodes carry no timestamps)
+    hipGraphExec_t graph_exec = nullptr;
+    int graph_key = -1;  // active-list length it was captured for
     int max_blocks = 1024;
     bool timing = false;
     unsigned timing_mask = 0x3f;  // which matvec kernels are timed
@@ -184,6 +193,15 @@ void wait_stream(dda_ctx* c) {
     while ((e = hipEventQuery(c->sync_ev)) == hipErrorNotReady) {
     }
     DDA_HIP_CHECK(e);
+}
+
+// Spins until an event has completed (an event never recorded counts as
+// complete).
+void wait_event(hipEvent_t e) {
+    hipError_t r;
+    while ((r = hipEventQuery(e)) == hipErrorNotReady) {
+    }
+    DDA_HIP_CHECK(r);
 }
 
 // Copies a pageable host array to the device in the order of the context's
@@ -229,6 +247,50 @@ void flush_timer(dda_ctx* c) {
     c->timer.pending.clear();
 }
 
+void drop_graph(dda_ctx* c) {
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    c->graph_exec = nullptr;
+    c->graph_key = -1;
+}
+
+// Launches body() on the context's stream through a captured graph: replayed
+// while `key` is unchanged, captured again otherwise (the executable is
+// updated in place when the topology allows it, else instantiated anew).
+template <typename F>
+void launch_captured(dda_ctx* c, int key, F&& body) {
+    hipStream_t s = c->stream;
+    if (!c->graph_exec || c->graph_key != key) {
+        hipGraph_t gr = nullptr;
+        DDA_HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        try {
+            body();
+        } catch (...) {
+            hipGraph_t tmp = nullptr;
+            (void)hipStreamEndCapture(s, &tmp);
+            if (tmp) (void)hipGraphDestroy(tmp);
+            throw;
+        }
+        DDA_HIP_CHECK(hipStreamEndCapture(s, &gr));
+        bool updated = false;
+        if (c->graph_exec) {
+            hipGraphNode_t bad = nullptr;
+            hipGraphExecUpdateResult res;
+            updated = hipGraphExecUpdate(c->graph_exec, gr, &bad, &res) == hipSuccess &&
+                      res == hipGraphExecUpdateSuccess;
+            if (!updated) {
+                (void)hipGetLastError();
+                drop_graph(c);
+            }
+        }
+        hipError_t e = hipSuccess;
+        if (!updated) e = hipGraphInstantiate(&c->graph_exec, gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        DDA_HIP_CHECK(e);
+        c->graph_key = key;
+    }
+    DDA_HIP_CHECK(hipGraphLaunch(c->graph_exec, s));
+}
+
 dda::RedScratch red_of(dda_ctx* c) {
     return dda::RedScratch{c->partial.as<double>(), c->max_blocks};
 }
@@ -245,8 +307,11 @@ int pack_blocks(const dda_ctx* c, int csize) {
 template <typename T>
 void matvec(dda_ctx* c, dda::cx<T>* x, dda::cx<T>* y, const int* act, int n_act,
             const dda::cx<T>* const* dptr, const int* slot_sys, const dda::cx<T>* ainv, int mode,
-            const dda::cx<T>* fuse_r = nullptr) {
+            const dda::cx<T>* fuse_r = nullptr,
+            dda::SlotFilter f = dda::SlotFilter{nullptr, dda::FILTER_ALL}) {
     if (n_act == 0 || c->g.n_occ == 0) return;
+    if ((fuse_r || f.mode != dda::FILTER_ALL) && !f.st)
+        throw Error(DDA_EDEVICE, "slot filter without slot states");
     const dda::Geo& g = c->g;
     auto* G = c->G.as<dda::cx<T>>();
     hipStream_t s = c->stream;
@@ -256,24 +321,24 @@ void matvec(dda_ctx* c, dda::cx<T>* x, dda::cx<T>* y, const int* act, int n_act,
         {
             Tic t(c, 0, n_act);
             dda::launch_xfft_t<T>(x, c->map.as<int>(), G, tw_of<T>(c, 0), g, act, n_act, fuse_r,
-                                  st, s);
+                                  f, s);
         }
         {
             Tic t(c, 5, n_act);
             dda::launch_yzconv<T>(G, dptr, tw_of<T>(c, 1), tw_of<T>(c, 2), g, act, slot_sys, n_act,
-                                  s);
+                                  f, s);
         }
         {
             Tic t(c, 4, n_act);
             dda::launch_ixfft_t<T>(G, x, ainv, y, c->map.as<int>(), tw_of<T>(c, 0), g, act,
-                                   slot_sys, n_act, mode, red_of(c), s);
+                                   slot_sys, n_act, mode, f, red_of(c), s);
         }
     } else {
         const int64_t plane = int64_t(g.my) * g.mx;
         {
             Tic t(c, 0, n_act);
             dda::launch_unpack_xfft<T>(x, c->map.as<int>(), G, tw_of<T>(c, 0), g, act, n_act,
-                                       fuse_r, st, s);
+                                       fuse_r, f, s);
         }
         {
             Tic t(c, 1, n_act);
@@ -282,7 +347,7 @@ void matvec(dda_ctx* c, dda::cx<T>* x, dda::cx<T>* y, const int* act, int n_act,
         }
         {
             Tic t(c, 2, n_act);
-            dda::launch_zconv<T>(G, dptr, tw_of<T>(c, 2), g, act, slot_sys, n_act, s);
+            dda::launch_zconv<T>(G, dptr, tw_of<T>(c, 2), g, act, slot_sys, n_act, f, s);
         }
         {
             Tic t(c, 3, n_act);
@@ -292,7 +357,7 @@ void matvec(dda_ctx* c, dda::cx<T>* x, dda::cx<T>* y, const int* act, int n_act,
         {
             Tic t(c, 4, n_act);
             dda::launch_ixfft_pack<T>(G, x, ainv, y, c->map.as<int>(), tw_of<T>(c, 0), g, act,
-                                      slot_sys, n_act, mode, st, red_of(c), s);
+                                      slot_sys, n_act, mode, f, red_of(c), s);
         }
     }
     if (mode == dda::PACK_AX_COCG)
@@ -363,53 +428,45 @@ DEntry* get_D(dda_ctx* c, double energy, bool need64) {
     return e;
 }
 
-// ---------------------------------------------------------- polarizability
-cplx polarizability(int kind, cplx eps, cplx mh, double d, cplx k) {
-    const cplx m2 = eps / (mh * mh);
-    const double d3 = d * d * d;
-    const cplx acm = (3.0 * d3 / (4.0 * kPi)) * (m2 - 1.0) / (m2 + 2.0);
-    const cplx I(0.0, 1.0);
-    if (kind == DDA_POL_CM) return acm;
-    if (kind == DDA_POL_RR) return acm / (1.0 - (2.0 / 3.0) * I * k * k * k * acm);
-    // lattice dispersion relation (Draine & Goodman 1993), S = 0 for the
-    // electron moving along the lattice z axis with a transverse field
-    const double b1 = -1.8915316, b2 = 0.1648469;
-    const cplx kd = k * d;
-    const cplx corr = (b1 + m2 * b2) * kd * kd - (2.0 / 3.0) * I * kd * kd * kd;
-    return acm / (1.0 + (acm / d3) * corr);
-}
-
-void read_eps(const double* eps, int64_t idx, cplx& out) {
-    out = cplx(eps[2 * idx], eps[2 * idx + 1]);
-    if (!std::isfinite(out.real()) || !std::isfinite(out.imag()))
-        throw Error(DDA_EINVAL, "permittivity is not finite");
-}
-
-// Builds 1/alpha for systems [e0, e0+ns) into ctx->ainv128 (and ainv64).
-void upload_ainv(dda_ctx* c, const double* energy, const double* eps, int e0, int ns, bool need64) {
+// ------------------------------------------------------------ material terms
+// Copies the permittivities of systems [e0, e0 + ns) to the device and
+// evaluates there, per dipole, 1/alpha (FP64 if need128, FP32 if need64) and,
+// if w_dev is given, the absorption weight [ns][n_occ].  A non-finite
+// permittivity or a vanishing or infinite polarizability is an EINVAL error
+// before any solve runs.
+void compute_material(dda_ctx* c, const double* energy, const double* eps, int e0, int ns,
+                      bool need128, bool need64, double* w_dev) {
     const int64_t n = c->g.n_occ;
-    std::vector<z128> h(size_t(ns) * n);
-    for (int s = 0; s < ns; ++s) {
-        const cplx k = c->mh * (energy[e0 + s] / kHbarC);
-        for (int64_t i = 0; i < n; ++i) {
-            cplx ep;
-            read_eps(eps, int64_t(e0 + s) * n + i, ep);
-            const cplx a = polarizability(c->opt.polarizability, ep, c->mh, c->d, k);
-            if (a == cplx(0.0, 0.0) || !std::isfinite(std::abs(a)))
-                throw Error(DDA_EINVAL, "permittivity gives a zero or infinite polarizability");
-            const cplx ai = 1.0 / a;
-            h[size_t(s) * n + i] = z128{ai.real(), ai.imag()};
-        }
+    const size_t cnt = size_t(ns) * size_t(n);
+    if (cnt == 0) return;
+    c->eps_dev.ensure(cnt * sizeof(z128));
+    std::vector<dda::MatSys> hs(ns);
+    for (int i = 0; i < ns; ++i) {
+        const cplx k = c->mh * (energy[e0 + i] / kHbarC);
+        hs[i] = dda::MatSys{k.real(), k.imag()};
     }
-    c->ainv128.ensure(h.size() * sizeof(z128));
-    DDA_HIP_CHECK(hipMemcpyAsync(c->ainv128.p, h.data(), h.size() * sizeof(z128),
+    const size_t sb = hs.size() * sizeof(dda::MatSys);
+    const size_t sb_al = (sb + 255) / 256 * 256;
+    c->matsys.ensure(sb_al + 256);
+    int* err = reinterpret_cast<int*>(c->matsys.as<char>() + sb_al);
+    DDA_HIP_CHECK(hipMemcpyAsync(c->eps_dev.p, eps + 2 * int64_t(e0) * n, cnt * sizeof(z128),
                                  hipMemcpyHostToDevice, c->stream));
-    if (need64) {
-        c->ainv64.ensure(h.size() * sizeof(z64));
-        dda::launch_convert_z128_to_z64(c->ainv128.as<z128>(), c->ainv64.as<z64>(),
-                                        int64_t(h.size()), c->stream);
-    }
-    DDA_HIP_CHECK(hipStreamSynchronize(c->stream));  // h goes out of scope
+    DDA_HIP_CHECK(hipMemcpyAsync(c->matsys.p, hs.data(), sb, hipMemcpyHostToDevice, c->stream));
+    DDA_HIP_CHECK(hipMemsetAsync(err, 0, sizeof(int), c->stream));
+    if (need128) c->ainv128.ensure(cnt * sizeof(z128));
+    if (need64) c->ainv64.ensure(cnt * sizeof(z64));
+    dda::MatParams mp{c->opt.polarizability, c->mh.imag() == 0.0 ? 1 : 0, c->mh.real(),
+                      c->mh.imag(), c->d};
+    dda::launch_material(c->eps_dev.as<z128>(), c->matsys.as<dda::MatSys>(), n, ns, mp,
+                         need128 ? c->ainv128.as<z128>() : nullptr,
+                         need64 ? c->ainv64.as<z64>() : nullptr, w_dev, err, c->stream);
+    c->host_misc.ensure(256);
+    DDA_HIP_CHECK(hipMemcpyAsync(c->host_misc.p, err, sizeof(int), hipMemcpyDeviceToHost,
+                                 c->stream));
+    wait_stream(c);  // also keeps hs alive until its copy has run
+    const int herr = *c->host_misc.as<int>();
+    if (herr == 1) throw Error(DDA_EINVAL, "permittivity is not finite");
+    if (herr != 0) throw Error(DDA_EINVAL, "permittivity gives a zero or infinite polarizability");
 }
 
 // Per-chunk device tables: slot -> system, system -> D pointer.
@@ -434,20 +491,38 @@ const z64* const* upload_dptrs<float>(dda_ctx* c, const std::vector<DEntry*>& en
 }
 
 
+// Pinned staging: host_act and host_st hold kRing regions of slot_cap
+// entries each, so that an upload or a state snapshot can be in flight while
+// the host fills the next region.
+constexpr int kRing = 4;
+
 void ensure_slots(dda_ctx* c, int nslots) {
     c->st.ensure(size_t(nslots) * sizeof(dda::BicgSlot));
     c->partial.ensure(size_t(nslots) * c->max_blocks * 8 * sizeof(double));
     c->act.ensure(size_t(nslots) * sizeof(int));
     c->slot_sys.ensure(size_t(nslots) * sizeof(int));
-    c->host_st.ensure(size_t(nslots) * sizeof(dda::BicgSlot));
-    c->host_act.ensure(size_t(nslots) * sizeof(int));
+    if (nslots > c->slot_cap) {
+        // earlier uploads and snapshots read the old pinned buffers
+        for (auto e : c->act_ev) if (e) wait_event(e);
+        for (auto e : c->ring_ev) if (e) wait_event(e);
+        c->slot_cap = nslots;
+    }
+    c->host_st.ensure(size_t(kRing) * c->slot_cap * sizeof(dda::BicgSlot));
+    c->host_act.ensure(size_t(kRing) * c->slot_cap * sizeof(int));
 }
 
+// Stream-ordered upload of an active list into c->act.  The staging region
+// is reused only after its previous copy has run.
 void upload_act(dda_ctx* c, const std::vector<int>& act) {
     if (act.empty()) return;
-    std::memcpy(c->host_act.p, act.data(), act.size() * sizeof(int));
-    DDA_HIP_CHECK(hipMemcpyAsync(c->act.p, c->host_act.p, act.size() * sizeof(int),
-                                 hipMemcpyHostToDevice, c->stream));
+    const int r = c->act_seq++ % kRing;
+    if (!c->act_ev[r]) DDA_HIP_CHECK(hipEventCreateWithFlags(&c->act_ev[r], hipEventDisableTiming));
+    wait_event(c->act_ev[r]);
+    int* h = c->host_act.as<int>() + size_t(r) * c->slot_cap;
+    std::memcpy(h, act.data(), act.size() * sizeof(int));
+    DDA_HIP_CHECK(hipMemcpyAsync(c->act.p, h, act.size() * sizeof(int), hipMemcpyHostToDevice,
+                                 c->stream));
+    DDA_HIP_CHECK(hipEventRecord(c->act_ev[r], c->stream));
 }
 
 std::vector<dda::BicgSlot> read_states(dda_ctx* c, int nslots) {
@@ -483,7 +558,7 @@ void run_bicgstab(dda_ctx* c, int nslots, const dda::cx<T>* b, dda::cx<T>* x, Ve
     for (int i = 0; i < nslots; ++i) act[i] = i;
     upload_act(c, act);
     const int* dact = c->act.as<int>();
-    dda::bicg_norm_b<T>(b, st, dact, nslots, nv, tol * tol, 0.0, red, s);
+    dda::bicg_norm_b<T>(b, st, dact, nslots, nv, tol * tol, 0.0, maxit, red, s);
     DDA_HIP_CHECK(hipMemsetAsync(x, 0, size_t(nslots) * nv * sizeof(dda::cx<T>), s));
     DDA_HIP_CHECK(hipMemcpyAsync(w.r, b, size_t(nslots) * nv * sizeof(dda::cx<T>),
                                  hipMemcpyDeviceToDevice, s));
@@ -593,7 +668,8 @@ void run_mixed(dda_ctx* c, int nslots, const z128* b, z128* x, const z128* const
     std::vector<int> all(nslots);
     for (int i = 0; i < nslots; ++i) all[i] = i;
     upload_act(c, all);
-    dda::bicg_norm_b<double>(b, st, c->act.as<int>(), nslots, nv, tol * tol, 0.0, red, c->stream);
+    dda::bicg_norm_b<double>(b, st, c->act.as<int>(), nslots, nv, tol * tol, 0.0, c->opt.maxit,
+                             red, c->stream);
     std::vector<double> bn(nslots), rn(nslots);
     {
         auto S = read_states(c, nslots);
@@ -653,9 +729,20 @@ void run_mixed(dda_ctx* c, int nslots, const z128* b, z128* x, const z128* const
 // (x += x_lo, r = b - A x in FP64, rho from the new r) is made whenever the
 // recursive residual fell by kUpdateDrop since the last one, and whenever it
 // reports convergence; for T = double only the convergence is verified that
-// way.  The recursion then continues (p and beta are kept); a breakdown
-// restarts it from the true residual (p = r).
+// way.
+//
+// The device drives the iteration.  Work goes out in intervals: a check
+// phase (the FP64 residual of every slot that asked for one decides
+// convergence, the iteration limit, a restart after a breakdown or a reliable
+// update) followed by check_every iterations of the slots still iterating;
+// every kernel skips the slots its filter rejects.  The host never waits
+// inside an interval: after each one the slot states are copied to pinned
+// memory, and before sending interval k the host reads the copy made after
+// interval k - kLag (already complete while interval k - 1 runs) and drops the
+// finished slots from the active list.  On a non-default stream an interval
+// is a captured graph, replayed while the active list keeps its length.
 constexpr double kUpdateDrop = 0.1;
+constexpr int kLag = 2;
 
 template <typename T>
 void run_cocg(dda_ctx* c, int nslots, const z128* b, z128* x, dda::cx<T>* r, dda::cx<T>* p,
@@ -675,79 +762,78 @@ void run_cocg(dda_ctx* c, int nslots, const z128* b, z128* x, dda::cx<T>* r, dda
     for (int i = 0; i < nslots; ++i) act[i] = i;
     upload_act(c, act);
     dda::bicg_norm_b<double>(b, st, dact, nslots, nv, tol * tol,
-                             mixed ? kUpdateDrop * kUpdateDrop : 0.0, red, s);
+                             mixed ? kUpdateDrop * kUpdateDrop : 0.0, maxit, red, s);
     DDA_HIP_CHECK(hipMemsetAsync(x, 0, q128 * sizeof(z128), s));
     if (mixed) DDA_HIP_CHECK(hipMemsetAsync(x_lo, 0, q128 * sizeof(z64), s));
     DDA_HIP_CHECK(hipMemsetAsync(y64, 0, q128 * sizeof(z128), s));
-    dda::true_residual<T>(b, y64, r, st, dact, nslots, nv, red, s);  // r = b
-    dda::cocg_reset<T>(r, p, st, dact, nslots, nv, red, s);
-    std::vector<int> restarts(nslots, 0);
+    dda::cocg_start<T>(b, y64, r, st, dact, nslots, nv, red, s);  // r = b
+
+    const int check = std::max(1, c->opt.check_every);
+    const dda::SlotFilter fchk{st, dda::FILTER_CHECK}, fact{st, dda::FILTER_ACTIVE};
+    dda::cx<T>* xs = mixed ? reinterpret_cast<dda::cx<T>*>(x_lo) : reinterpret_cast<dda::cx<T>*>(x);
+    auto interval = [&](int n_act) {
+        if (mixed) dda::accumulate_lo(x, x_lo, dact, n_act, nv, fchk, s);
+        matvec<double>(c, x, y64, dact, n_act, dptr64, slot_sys, ainv64, dda::PACK_AX, nullptr,
+                       fchk);
+        dda::cocg_check<T>(b, y64, r, st, dact, n_act, nv, kMaxRestarts, red, s);
+        for (int k = 0; k < check; ++k) {
+            matvec<T>(c, p, q, dact, n_act, dptr, slot_sys, ainv, dda::PACK_AX_COCG, r, fact);
+            dda::cocg_update_xr<T>(xs, r, p, q, st, dact, n_act, nv, red, s);
+        }
+    };
+    const bool graphs = c->opt.use_graphs != 0 && s != nullptr && !c->timing;
+    for (auto& e : c->ring_ev)
+        if (!e) DDA_HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    auto* ring = c->host_st.as<dda::BicgSlot>();
+    drop_graph(c);
+    try {
+        for (int64_t k = 0;; ++k) {
+            if (k >= kLag) {
+                const int rk = int((k - kLag) % kRing);
+                wait_event(c->ring_ev[rk]);
+                const dda::BicgSlot* S = ring + size_t(rk) * c->slot_cap;
+                std::vector<int> next;
+                next.reserve(act.size());
+                for (int i : act)
+                    if (!dda::slot_terminal(S[i].status)) next.push_back(i);
+                if (next.empty()) break;
+                if (next.size() != act.size()) {
+                    act.swap(next);
+                    upload_act(c, act);
+                }
+            }
+            const int n_act = int(act.size());
+            if (graphs) {
+                launch_captured(c, n_act, [&] { interval(n_act); });
+            } else {
+                interval(n_act);
+            }
+            const int wk = int(k % kRing);
+            DDA_HIP_CHECK(hipMemcpyAsync(ring + size_t(wk) * c->slot_cap, st,
+                                         size_t(nslots) * sizeof(dda::BicgSlot),
+                                         hipMemcpyDeviceToHost, s));
+            DDA_HIP_CHECK(hipEventRecord(c->ring_ev[wk], s));
+        }
+    } catch (...) {
+        (void)hipStreamSynchronize(s);
+        drop_graph(c);
+        throw;
+    }
+    drop_graph(c);  // the graph holds this chunk's buffer addresses
+    auto S = read_states(c, nslots);
     status.assign(nslots, DDA_OK);
     iters.assign(nslots, 0);
     matvecs.assign(nslots, 0);
     relres.assign(nslots, 0.0);
-    const int check = std::max(1, c->opt.check_every);
-    while (true) {
-        auto S = read_states(c, nslots);
-        std::vector<int> upd, rst, next;
-        std::vector<char> final_(nslots, 0);
-        for (int i : act) {
-            iters[i] = S[i].iters;
-            if (S[i].status == dda::SLOT_BREAKDOWN) {
-                rst.push_back(i);
-            } else if (S[i].status == dda::SLOT_CONVERGED || S[i].want_update) {
-                upd.push_back(i);
-            } else if (iters[i] >= maxit) {
-                upd.push_back(i);
-                final_[i] = 1;
-            } else {
-                next.push_back(i);
-            }
-        }
-        std::vector<int> ur = upd;
-        ur.insert(ur.end(), rst.begin(), rst.end());
-        if (!ur.empty()) {
-            upload_act(c, ur);
-            const int nu = int(ur.size());
-            if (mixed) dda::accumulate_lo(x, x_lo, dact, nu, nv, s);
-            matvec<double>(c, x, y64, dact, nu, dptr64, slot_sys, ainv64, dda::PACK_AX);
-            dda::true_residual<T>(b, y64, r, st, dact, nu, nv, red, s);
-            if (!rst.empty()) {
-                upload_act(c, rst);
-                dda::cocg_reset<T>(r, p, st, dact, int(rst.size()), nv, red, s);
-            }
-            auto S2 = read_states(c, nslots);
-            for (int i : ur) {
-                matvecs[i] += 1;
-                const double rr = S2[i].bnorm2 > 0 ? std::sqrt(S2[i].rnorm2 / S2[i].bnorm2) : 0.0;
-                relres[i] = rr;
-                const bool was_breakdown = S[i].status == dda::SLOT_BREAKDOWN;
-                if (rr <= tol) {
-                    status[i] = DDA_OK;
-                } else if (final_[i] || iters[i] >= maxit) {
-                    status[i] = DDA_ENOCONV;
-                } else if (was_breakdown && restarts[i] >= kMaxRestarts) {
-                    status[i] = DDA_EBREAKDOWN;
-                } else {
-                    if (was_breakdown) restarts[i] += 1;
-                    next.push_back(i);
-                }
-            }
-        }
-        std::sort(next.begin(), next.end());
-        act = next;
-        const int n_act = int(act.size());
-        if (n_act == 0) break;
-        upload_act(c, act);
-        for (int k = 0; k < check; ++k) {
-            matvec<T>(c, p, q, dact, n_act, dptr, slot_sys, ainv, dda::PACK_AX_COCG, r);
-            if (mixed)
-                dda::cocg_update_xr<T>(reinterpret_cast<dda::cx<T>*>(x_lo), r, p, q, st, dact,
-                                       n_act, nv, red, s);
-            else
-                dda::cocg_update_xr<T>(reinterpret_cast<dda::cx<T>*>(x), r, p, q, st, dact, n_act,
-                                       nv, red, s);
-            for (int i : act) matvecs[i] += 1;
+    for (int i = 0; i < nslots; ++i) {
+        iters[i] = S[i].iters;
+        matvecs[i] = S[i].matvecs;
+        relres[i] = S[i].bnorm2 > 0 ? std::sqrt(S[i].rnorm2 / S[i].bnorm2) : 0.0;
+        switch (S[i].status) {
+            case dda::SLOT_DONE: status[i] = DDA_OK; break;
+            case dda::SLOT_FAIL_NOCONV: status[i] = DDA_ENOCONV; break;
+            case dda::SLOT_FAIL_BREAKDOWN: status[i] = DDA_EBREAKDOWN; break;
+            default: throw Error(DDA_EDEVICE, "COCG slot left in a non-terminal state");
         }
     }
 }
@@ -838,6 +924,7 @@ void dda_default_options(dda_options* opt) {
     opt->tol = 1e-10;
     opt->maxit = 100000;
     opt->check_every = 16;
+    opt->use_graphs = 1;
 }
 
 double dda_beta_from_keV(double kinetic_keV) {
@@ -991,7 +1078,7 @@ int dda_solve(dda_ctx* c, int n_energy, const double* energy_eV, const double* e
         std::vector<DEntry*> ents;
         c->pin_clock = c->use_clock + 1;
         for (int s = 0; s < ns; ++s) ents.push_back(get_D(c, energy_eV[e0 + s], mixed));
-        upload_ainv(c, energy_eV, eps_dipole, e0, ns, mixed);
+        compute_material(c, energy_eV, eps_dipole, e0, ns, true, mixed, nullptr);
         c->G.ensure(size_t(nslots) * dda::grid_elems(c->g) * sizeof(z128));
         const auto* b = static_cast<const z128*>(einc_dev) + int64_t(e0) * n_traj * nv;
         auto* x = static_cast<z128*>(p_dev) + int64_t(e0) * n_traj * nv;
@@ -1076,32 +1163,12 @@ int dda_eels_cl(dda_ctx* c, int n_energy, const double* energy_eV, double beta,
         std::vector<DEntry*> ents;
         c->pin_clock = c->use_clock + 1;
         for (int s = 0; s < ns; ++s) ents.push_back(get_D(c, energy_eV[e0 + s], false));
-        upload_ainv(c, energy_eV, eps_dipole, e0, ns, false);
-        // absorption weights and omega/v per system
-        std::vector<double> wts(size_t(ns) * n), kv(ns);
-        for (int s = 0; s < ns; ++s) {
-            const double E = energy_eV[e0 + s];
-            const double k0 = E / kHbarC;
-            kv[s] = k0 / beta;
-            const cplx k = mh * k0;
-            for (int64_t i = 0; i < n; ++i) {
-                cplx ep;
-                read_eps(eps_dipole, int64_t(e0 + s) * n + i, ep);
-                if (real_host) {
-                    const cplx a = polarizability(c->opt.polarizability, ep, mh, c->d, k);
-                    const double kr = k.real();
-                    wts[size_t(s) * n + i] = -(1.0 / a).imag() - (2.0 / 3.0) * kr * kr * kr;
-                } else {
-                    const cplx m2 = ep / (mh * mh);
-                    const double d3 = c->d * c->d * c->d;
-                    wts[size_t(s) * n + i] =
-                        4.0 * kPi * (mh * mh * m2).imag() / (std::norm(m2 - 1.0) * d3);
-                }
-            }
-        }
+        // absorption weights (device) and omega/v per system
+        std::vector<double> kv(ns);
+        for (int s = 0; s < ns; ++s) kv[s] = energy_eV[e0 + s] / kHbarC / beta;
         c->G.ensure(size_t(nslots) * dda::grid_elems(c->g) * sizeof(z128));
         c->vec128.ensure(size_t(nslots) * nv * sizeof(z128));
-        const size_t wb = wts.size() * sizeof(double), kb = kv.size() * sizeof(double);
+        const size_t wb = size_t(ns) * n * sizeof(double), kb = kv.size() * sizeof(double);
         const size_t rb = size_t(n_traj) * 3 * sizeof(double), ob = size_t(nslots) * 8 * sizeof(double);
         c->misc.ensure(wb + kb + rb + ob + 256);
         char* base = c->misc.as<char>();
@@ -1109,7 +1176,7 @@ int dda_eels_cl(dda_ctx* c, int n_energy, const double* energy_eV, double beta,
         double* dkv = reinterpret_cast<double*>(base + wb);
         double* dr0 = reinterpret_cast<double*>(base + wb + kb);
         double* dout = reinterpret_cast<double*>(base + wb + kb + rb);
-        DDA_HIP_CHECK(hipMemcpyAsync(dw, wts.data(), wb, hipMemcpyHostToDevice, c->stream));
+        compute_material(c, energy_eV, eps_dipole, e0, ns, false, false, dw);
         DDA_HIP_CHECK(hipMemcpyAsync(dkv, kv.data(), kb, hipMemcpyHostToDevice, c->stream));
         DDA_HIP_CHECK(hipMemcpyAsync(dr0, r0_nm, rb, hipMemcpyHostToDevice, c->stream));
         const auto* P = static_cast<const z128*>(p_dev) + int64_t(e0) * n_traj * nv;
@@ -1122,7 +1189,7 @@ int dda_eels_cl(dda_ctx* c, int n_energy, const double* energy_eV, double beta,
                        nslots, dout, red_of(c), c->stream);
         std::vector<double> sums(size_t(nslots) * 8);
         DDA_HIP_CHECK(hipMemcpyAsync(sums.data(), dout, ob, hipMemcpyDeviceToHost, c->stream));
-        DDA_HIP_CHECK(hipStreamSynchronize(c->stream));
+        wait_stream(c);
         for (int i = 0; i < nslots; ++i) {
             const int s = i / n_traj;
             const double E = energy_eV[e0 + s];
@@ -1163,7 +1230,7 @@ int dda_matvec(dda_ctx* c, double energy_eV, const double* eps_dipole, int preci
     c->pin_clock = c->use_clock + 1;
     std::vector<DEntry*> ents{get_D(c, energy_eV, fp32)};
     if (!interaction_only) {
-        upload_ainv(c, &energy_eV, eps_dipole, 0, 1, fp32);
+        compute_material(c, &energy_eV, eps_dipole, 0, 1, true, fp32, nullptr);
     } else {
         c->ainv128.ensure(size_t(c->g.n_occ) * sizeof(z128));
         c->ainv64.ensure(size_t(c->g.n_occ) * sizeof(z64));
@@ -1232,6 +1299,9 @@ int dda_destroy(dda_ctx* c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
     if (c->sync_ev) (void)hipEventDestroy(c->sync_ev);
+    for (auto e : c->act_ev) if (e) (void)hipEventDestroy(e);
+    for (auto e : c->ring_ev) if (e) (void)hipEventDestroy(e);
+    drop_graph(c);
     delete c;
     return DDA_OK;
     DDA_API_END

@@ -34,18 +34,19 @@ bool fft_length_supported(int L);
 // system (energy) of a slot; D and 1/alpha are per system: Dptr[sys] points to
 // [6][mz][my][mx], ainv + sys * n_occ to the dipoles' 1/alpha.
 // With fuse_r != NULL the kernel first updates the input in place,
-// x <- fuse_r + beta x with beta = st[slot].beta (the COCG direction update),
-// and transforms the updated vector.
+// x <- fuse_r + beta x with beta = f.st[slot].beta (the COCG direction update;
+// x <- fuse_r when the slot's reset_p is set), and transforms the updated
+// vector.  Every kernel of the chain skips the slots the filter rejects.
 template <typename T>
 void launch_unpack_xfft(cx<T>* xin, const int* map, cx<T>* G, const cx<T>* tw_x, const Geo& g,
-                        const int* act, int n_act, const cx<T>* fuse_r, const BicgSlot* st,
+                        const int* act, int n_act, const cx<T>* fuse_r, SlotFilter f,
                         hipStream_t s);
 template <typename T>
 void launch_fft_mid(cx<T>* data, const cx<T>* tw, int L, bool inverse, int64_t n_outer,
                     int64_t inner, int n_in, int n_out, int64_t outer_stride, hipStream_t s);
 template <typename T>
 void launch_zconv(cx<T>* G, const cx<T>* const* Dptr, const cx<T>* tw_z, const Geo& g,
-                  const int* act, const int* slot_sys, int n_act, hipStream_t s);
+                  const int* act, const int* slot_sys, int n_act, SlotFilter f, hipStream_t s);
 // mode PACK_AX: y = x/alpha - G_off x; PACK_GX: y = G_off x; PACK_AX_COCG:
 // y = A x and, fused, the partial rows of mu = x^T y per slot in `red`
 // (pack_blocks_per_slot rows, which must not exceed max_blocks); the caller
@@ -55,7 +56,7 @@ int pack_blocks_per_slot(const Geo& g);
 template <typename T>
 void launch_ixfft_pack(const cx<T>* G, const cx<T>* xin, const cx<T>* ainv, cx<T>* yout,
                        const int* map, const cx<T>* tw_x, const Geo& g, const int* act,
-                       const int* slot_sys, int n_act, int mode, BicgSlot* st, RedScratch red,
+                       const int* slot_sys, int n_act, int mode, SlotFilter f, RedScratch red,
                        hipStream_t s);
 
 // Interaction spectrum: D = FFT3(G_tilde on the embedding grid) / (mx my mz),
@@ -78,15 +79,16 @@ bool yz_fused_ok(const Geo& g, int csize);
 int yz_pack_blocks_per_slot(const Geo& g);
 template <typename T>
 void launch_xfft_t(cx<T>* xin, const int* map, cx<T>* Tb, const cx<T>* tw_x, const Geo& g,
-                   const int* act, int n_act, const cx<T>* fuse_r, const BicgSlot* st,
-                   hipStream_t s);
+                   const int* act, int n_act, const cx<T>* fuse_r, SlotFilter f, hipStream_t s);
 template <typename T>
 void launch_yzconv(cx<T>* Tb, const cx<T>* const* Dptr, const cx<T>* tw_y, const cx<T>* tw_z,
-                   const Geo& g, const int* act, const int* slot_sys, int n_act, hipStream_t s);
+                   const Geo& g, const int* act, const int* slot_sys, int n_act, SlotFilter f,
+                   hipStream_t s);
 template <typename T>
 void launch_ixfft_t(const cx<T>* Tb, const cx<T>* xin, const cx<T>* ainv, cx<T>* yout,
                     const int* map, const cx<T>* tw_x, const Geo& g, const int* act,
-                    const int* slot_sys, int n_act, int mode, RedScratch red, hipStream_t s);
+                    const int* slot_sys, int n_act, int mode, SlotFilter f, RedScratch red,
+                    hipStream_t s);
 void launch_convert_z128_to_z64(const z128* in, z64* out, int64_t n, hipStream_t s);
 void launch_convert_z64_to_z128(const z64* in, z128* out, int64_t n, hipStream_t s);
 
@@ -99,6 +101,23 @@ struct EincSys {   // per energy
 void launch_einc(z128* einc, const int* occ_lin, const Geo& g, double d, double beta,
                  const EincSys* sys /*device [n_energy]*/, const double* r0 /*device [n_traj][3]*/,
                  int n_energy, int n_traj, hipStream_t s);
+
+// Material terms (material.hip), FP64: for system s < ns and dipole i < n,
+// from eps[s][i] (absolute permittivity) and the host wavenumber sys[s].k,
+// 1/alpha into ainv128[s][i] (and rounded into ainv64) and the absorption
+// weight into w[s][i]; any output may be NULL.  err[0] becomes non-zero for a
+// non-finite permittivity (1) or a zero or infinite polarizability (2); the
+// caller clears it first.
+struct MatSys {
+    double k_re, k_im;
+};
+struct MatParams {
+    int kind;       // 0 LDR, 1 CM, 2 RR
+    int real_host;  // Im m_h == 0: radiative-reaction form of the weight
+    double mh_re, mh_im, d;
+};
+void launch_material(const z128* eps, const MatSys* sys, int64_t n, int ns, MatParams mp,
+                     z128* ainv128, z64* ainv64, double* w, int* err, hipStream_t s);
 
 // Debug/test helper: K0, K1 at n complex points (device arrays).
 void launch_besselk01(const z128* z, z128* k0, z128* k1, int64_t n, hipStream_t s);

@@ -8,10 +8,10 @@ namespace dda {
 
 // Vectors are [slot][nv] (nv = 3 n_occ); `act` lists the slots to process
 // (n_act of them).  Each launcher is one kernel.
-// bnorm2 = ||b||^2; also sets tol2, upd2 and zeroes the iteration counter
+// bnorm2 = ||b||^2; also sets tol2, upd2, maxit and zeroes the counters
 template <typename T>
 void bicg_norm_b(const cx<T>* b, BicgSlot* st, const int* act, int n_act, int64_t nv,
-                 double tol2, double upd2, RedScratch red, hipStream_t s);
+                 double tol2, double upd2, int maxit, RedScratch red, hipStream_t s);
 template <typename T>
 void bicg_reset(const cx<T>* r, cx<T>* rhat, cx<T>* p, cx<T>* v, BicgSlot* st, const int* act,
                 int n_act, int64_t nv, RedScratch red, hipStream_t s);
@@ -50,17 +50,27 @@ void cocg_alpha(const cx<T>* p, const cx<T>* q, BicgSlot* st, const int* act, in
 void cocg_alpha_finalize(BicgSlot* st, const int* act, int n_act, RedScratch red, int nblk,
                          hipStream_t s);
 // x += alpha p; r -= alpha q; rho' = r^T r; beta = rho'/rho; convergence,
-// reliable-update and breakdown flags
+// reliable-update, breakdown and iteration-limit flags (slots in SLOT_ACTIVE
+// only)
 template <typename T>
 void cocg_update_xr(cx<T>* x, cx<T>* r, const cx<T>* p, const cx<T>* q, BicgSlot* st,
                     const int* act, int n_act, int64_t nv, RedScratch red, hipStream_t s);
-// FP64 residual pass: r = b - y (FP64), r_lo = r rounded to T, rho = r_lo^T
-// r_lo, rnorm2 = ||r||^2, rmax2 = rnorm2; status from the FP64 norm.
+// FP64 residual passes: r = b - y (FP64), r_lo = r rounded to T, rho =
+// r_lo^T r_lo, rnorm2 = rmax2 = ||r||^2.
+//   cocg_start: every listed slot, from x0 = 0 (y = 0); p = r on the first
+//     direction update; SLOT_DONE if b already meets the tolerance.
+//   cocg_check: only slots with needs_check(); decides SLOT_DONE,
+//     SLOT_FAIL_NOCONV, SLOT_FAIL_BREAKDOWN (after max_restarts restarts) or
+//     a restart / reliable update that returns the slot to SLOT_ACTIVE.
 template <typename T>
-void true_residual(const z128* b, const z128* y, cx<T>* r_lo, BicgSlot* st, const int* act,
-                   int n_act, int64_t nv, RedScratch red, hipStream_t s);
-// x64 += x_lo; x_lo = 0
-void accumulate_lo(z128* x, z64* x_lo, const int* act, int n_act, int64_t nv, hipStream_t s);
+void cocg_start(const z128* b, const z128* y, cx<T>* r_lo, BicgSlot* st, const int* act,
+                int n_act, int64_t nv, RedScratch red, hipStream_t s);
+template <typename T>
+void cocg_check(const z128* b, const z128* y, cx<T>* r_lo, BicgSlot* st, const int* act,
+                int n_act, int64_t nv, int max_restarts, RedScratch red, hipStream_t s);
+// x64 += x_lo; x_lo = 0 (slots the filter accepts)
+void accumulate_lo(z128* x, z64* x_lo, const int* act, int n_act, int64_t nv, SlotFilter f,
+                   hipStream_t s);
 
 // Mixed precision helpers: r32 = r64 / sqrt(rnorm2); x64 += sqrt(rnorm2) * d32.
 void scale_down(const z128* r, z64* r32, const BicgSlot* st, const int* act, int n_act,

@@ -71,13 +71,17 @@ __global__ __launch_bounds__(NT) void k_norm_b(const cx<T>* __restrict__ b,
     block_partial<1, NT>(v, red, slot, blockIdx.x);
 }
 __global__ __launch_bounds__(NT) void k_fin_norm_b(BicgSlot* st, const int* act, RedScratch red,
-                                                   int nblk, double tol2, double upd2) {
+                                                   int nblk, double tol2, double upd2, int maxit) {
     FIN_PROLOGUE(1)
     S.bnorm2 = tot[0];
     S.tol2 = tol2;
     S.upd2 = upd2;
     S.iters = 0;
     S.want_update = 0;
+    S.matvecs = 0;
+    S.restarts = 0;
+    S.reset_p = 0;
+    S.maxit = maxit;
 }
 
 // ------------------------------------------------------------ BiCGStab ----
@@ -351,6 +355,8 @@ __global__ __launch_bounds__(NT) void k_fin_cocg_xr(BicgSlot* st, const int* act
     if (st[act[blockIdx.x]].status != SLOT_ACTIVE) return;
     FIN_PROLOGUE(3)
     S.iters += 1;
+    S.matvecs += 1;
+    S.reset_p = 0;
     S.rnorm2 = tot[2];
     if (!all_finite(tot, 3)) {
         S.status = SLOT_BREAKDOWN;
@@ -366,6 +372,7 @@ __global__ __launch_bounds__(NT) void k_fin_cocg_xr(BicgSlot* st, const int* act
     if (S.upd2 > 0.0 && tot[2] < S.upd2 * S.rmax2) S.want_update = 1;
     if (conv) S.status = SLOT_CONVERGED;
     else if (rho0 || rhon0) S.status = SLOT_BREAKDOWN;
+    else if (S.iters >= S.maxit) S.status = SLOT_MAXIT;
 }
 
 template <typename T>
@@ -373,8 +380,9 @@ __global__ __launch_bounds__(NT) void k_true_residual(const z128* __restrict__ b
                                                       const z128* __restrict__ y,
                                                       cx<T>* __restrict__ r_lo,
                                                       const int* __restrict__ act, int64_t nv,
-                                                      RedScratch red) {
+                                                      SlotFilter f, RedScratch red) {
     SLOT_PROLOGUE
+    if (!slot_live(f, slot)) return;
     double s[3] = {0.0, 0.0, 0.0};
     for (int64_t i = i0; i < nv; i += stride) {
         const z128 ri = b[base + i] - y[base + i];
@@ -385,19 +393,62 @@ __global__ __launch_bounds__(NT) void k_true_residual(const z128* __restrict__ b
     }
     block_partial<3, NT>(s, red, slot, blockIdx.x);
 }
-__global__ __launch_bounds__(NT) void k_fin_true_residual(BicgSlot* st, const int* act,
-                                                          RedScratch red, int nblk) {
+// Start of COCG from x0 = 0 (r = b): rho = r^T r, p = r on the first
+// direction update, done at once if b meets the tolerance.
+__global__ __launch_bounds__(NT) void k_fin_cocg_start(BicgSlot* st, const int* act,
+                                                       RedScratch red, int nblk) {
     FIN_PROLOGUE(3)
     S.rho = z128{tot[0], tot[1]};
+    S.beta = z128{0.0, 0.0};
     S.rnorm2 = tot[2];
     S.rmax2 = tot[2];
     S.want_update = 0;
-    S.status = (tot[2] <= S.tol2 * S.bnorm2) ? SLOT_CONVERGED : SLOT_ACTIVE;
+    S.reset_p = 1;
+    S.status = (tot[2] <= S.tol2 * S.bnorm2) ? SLOT_DONE : SLOT_ACTIVE;
+}
+
+// FP64 residual check of a slot that asked for one (needs_check): the FP64
+// residual decides convergence; otherwise the iteration limit ends the slot, a
+// breakdown restarts the recursion from the true residual (p = r), and a
+// reliable update continues it with the recomputed residual (p, beta kept).
+__global__ __launch_bounds__(NT) void k_fin_check(BicgSlot* st, const int* act, RedScratch red,
+                                                  int nblk, int max_restarts) {
+    if (!needs_check(st[act[blockIdx.x]])) return;
+    FIN_PROLOGUE(3)
+    S.matvecs += 1;
+    S.rnorm2 = tot[2];
+    S.rmax2 = tot[2];
+    S.want_update = 0;
+    if (!all_finite(tot, 3)) {
+        S.status = SLOT_FAIL_BREAKDOWN;
+        return;
+    }
+    if (tot[2] <= S.tol2 * S.bnorm2) {
+        S.status = SLOT_DONE;
+        return;
+    }
+    if (S.status == SLOT_MAXIT || S.iters >= S.maxit) {
+        S.status = SLOT_FAIL_NOCONV;
+        return;
+    }
+    if (S.status == SLOT_BREAKDOWN) {
+        if (S.restarts >= max_restarts) {
+            S.status = SLOT_FAIL_BREAKDOWN;
+            return;
+        }
+        S.restarts += 1;
+        S.reset_p = 1;
+        S.beta = z128{0.0, 0.0};
+    }
+    S.rho = z128{tot[0], tot[1]};
+    S.status = SLOT_ACTIVE;
 }
 
 __global__ __launch_bounds__(NT) void k_accumulate_lo(z128* __restrict__ x, z64* __restrict__ x_lo,
-                                                      const int* __restrict__ act, int64_t nv) {
+                                                      const int* __restrict__ act, int64_t nv,
+                                                      SlotFilter f) {
     SLOT_PROLOGUE
+    if (!slot_live(f, slot)) return;
     for (int64_t i = i0; i < nv; i += stride) {
         x[base + i] = x[base + i] + cvt<double>(x_lo[base + i]);
         x_lo[base + i] = z64{0.f, 0.f};
@@ -472,11 +523,11 @@ __global__ __launch_bounds__(NT) void k_fin_loss(double* __restrict__ out, RedSc
 
 template <typename T>
 void bicg_norm_b(const cx<T>* b, BicgSlot* st, const int* act, int n_act, int64_t nv, double tol2,
-                 double upd2, RedScratch red, hipStream_t s) {
+                 double upd2, int maxit, RedScratch red, hipStream_t s) {
     if (n_act == 0) return;
     k_norm_b<T><<<GRID(nv), NT, 0, s>>>(b, act, nv, red);
     DDA_LAUNCH_CHECK();
-    FIN(k_fin_norm_b, tol2, upd2);
+    FIN(k_fin_norm_b, tol2, upd2, maxit);
 }
 template <typename T>
 void bicg_reset(const cx<T>* r, cx<T>* rhat, cx<T>* p, cx<T>* v, BicgSlot* st, const int* act,
@@ -566,17 +617,28 @@ void cocg_update_xr(cx<T>* x, cx<T>* r, const cx<T>* p, const cx<T>* q, BicgSlot
     FIN(k_fin_cocg_xr);
 }
 template <typename T>
-void true_residual(const z128* b, const z128* y, cx<T>* r_lo, BicgSlot* st, const int* act,
-                   int n_act, int64_t nv, RedScratch red, hipStream_t s) {
+void cocg_start(const z128* b, const z128* y, cx<T>* r_lo, BicgSlot* st, const int* act,
+                int n_act, int64_t nv, RedScratch red, hipStream_t s) {
     if (n_act == 0) return;
-    k_true_residual<T><<<GRID(nv), NT, 0, s>>>(b, y, r_lo, act, nv, red);
+    k_true_residual<T><<<GRID(nv), NT, 0, s>>>(b, y, r_lo, act, nv, SlotFilter{st, FILTER_ALL},
+                                               red);
     DDA_LAUNCH_CHECK();
-    FIN(k_fin_true_residual);
+    FIN(k_fin_cocg_start);
 }
-void accumulate_lo(z128* x, z64* x_lo, const int* act, int n_act, int64_t nv, hipStream_t s) {
+template <typename T>
+void cocg_check(const z128* b, const z128* y, cx<T>* r_lo, BicgSlot* st, const int* act,
+                int n_act, int64_t nv, int max_restarts, RedScratch red, hipStream_t s) {
+    if (n_act == 0) return;
+    k_true_residual<T><<<GRID(nv), NT, 0, s>>>(b, y, r_lo, act, nv,
+                                               SlotFilter{st, FILTER_CHECK}, red);
+    DDA_LAUNCH_CHECK();
+    FIN(k_fin_check, max_restarts);
+}
+void accumulate_lo(z128* x, z64* x_lo, const int* act, int n_act, int64_t nv, SlotFilter f,
+                   hipStream_t s) {
     if (n_act == 0) return;
     dim3 grid(blocks_for(nv, 1 << 20), n_act);
-    k_accumulate_lo<<<grid, NT, 0, s>>>(x, x_lo, act, nv);
+    k_accumulate_lo<<<grid, NT, 0, s>>>(x, x_lo, act, nv, f);
     DDA_LAUNCH_CHECK();
 }
 void scale_down(const z128* r, z64* r32, const BicgSlot* st, const int* act, int n_act, int64_t nv,
@@ -608,7 +670,7 @@ void loss_sums(const z128* einc, const z128* p, const z128* y, const double* w, 
 
 #define DDA_INST(T)                                                                              \
     template void bicg_norm_b<T>(const cx<T>*, BicgSlot*, const int*, int, int64_t, double,      \
-                                 double, RedScratch, hipStream_t);                               \
+                                 double, int, RedScratch, hipStream_t);                          \
     template void bicg_reset<T>(const cx<T>*, cx<T>*, cx<T>*, cx<T>*, BicgSlot*, const int*, int, \
                                 int64_t, RedScratch, hipStream_t);                               \
     template void bicg_update_p<T>(const cx<T>*, cx<T>*, const cx<T>*, BicgSlot*, const int*,    \
@@ -630,8 +692,10 @@ void loss_sums(const z128* einc, const z128* p, const z128* y, const double* w, 
                                 RedScratch, hipStream_t);                                        \
     template void cocg_update_xr<T>(cx<T>*, cx<T>*, const cx<T>*, const cx<T>*, BicgSlot*,       \
                                     const int*, int, int64_t, RedScratch, hipStream_t);          \
-    template void true_residual<T>(const z128*, const z128*, cx<T>*, BicgSlot*, const int*, int, \
-                                   int64_t, RedScratch, hipStream_t);
+    template void cocg_start<T>(const z128*, const z128*, cx<T>*, BicgSlot*, const int*, int,    \
+                                int64_t, RedScratch, hipStream_t);                               \
+    template void cocg_check<T>(const z128*, const z128*, cx<T>*, BicgSlot*, const int*, int,    \
+                                int64_t, int, RedScratch, hipStream_t);
 DDA_INST(double)
 DDA_INST(float)
 

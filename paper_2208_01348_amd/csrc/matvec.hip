@@ -68,19 +68,24 @@ __global__ __launch_bounds__(NTHR) void k_unpack_xfft(cx<T>* __restrict__ xin,
                                                       const cx<T>* __restrict__ tw, Geo g,
                                                       const int* __restrict__ act,
                                                       const cx<T>* __restrict__ fuse_r,
-                                                      const BicgSlot* __restrict__ st) {
+                                                      SlotFilter f) {
     constexpr int NL = rows_nl<T, L>();
     __shared__ cx<T> lds[NL * L];
     const int tid = threadIdx.x;
     const int c = blockIdx.y;
     const int pos = blockIdx.z;
     const int64_t slot = act ? act[pos] : pos;
+    if (!slot_live(f, slot)) return;
     const int nrows = g.nz * g.ny;
     const int row0 = blockIdx.x * NL;
     cx<T>* src = xin + (slot * 3 + c) * g.n_occ;
     const cx<T>* rsrc = FUSE_P ? fuse_r + (slot * 3 + c) * g.n_occ : nullptr;
     cx<T> beta{T(0), T(0)};
-    if (FUSE_P) beta = cvt<T>(st[slot].beta);
+    bool reset = false;
+    if (FUSE_P) {
+        beta = cvt<T>(f.st[slot].beta);
+        reset = f.st[slot].reset_p != 0;
+    }
     for (int e = tid; e < NL * L; e += NTHR) {
         const int rr = e / L, x = e % L;
         const int row = row0 + rr;
@@ -90,7 +95,7 @@ __global__ __launch_bounds__(NTHR) void k_unpack_xfft(cx<T>* __restrict__ xin,
             if (idx >= 0) {
                 v = src[idx];
                 if (FUSE_P) {  // each occupied element is visited by exactly one thread
-                    v = rsrc[idx] + beta * v;
+                    v = reset ? rsrc[idx] : rsrc[idx] + beta * v;
                     src[idx] = v;
                 }
             }
@@ -150,7 +155,7 @@ __global__ __launch_bounds__(NTHR) void k_zconv(cx<T>* __restrict__ G,
                                                 const cx<T>* const* __restrict__ Dptr,
                                                 const cx<T>* __restrict__ tw, Geo g,
                                                 const int* __restrict__ act,
-                                                const int* __restrict__ slot_sys) {
+                                                const int* __restrict__ slot_sys, SlotFilter f) {
     constexpr int TX = zconv_tx<T, L>();
     constexpr int W = 6 * TX;  // lines per tile: (mirror set, component, column)
     __shared__ cx<T> lds[L * W];
@@ -161,6 +166,7 @@ __global__ __launch_bounds__(NTHR) void k_zconv(cx<T>* __restrict__ G,
     const bool pair = ky1 != ky0;
     const int pos = blockIdx.z;
     const int slot = act ? act[pos] : pos;
+    if (!slot_live(f, slot)) return;
     const int sys = slot_sys[slot];
     const int64_t plane = int64_t(g.my) * g.mx;
     cx<T>* gb = G + int64_t(pos) * 3 * g.nz * plane + col0;
@@ -226,13 +232,14 @@ __global__ __launch_bounds__(NTHR) void k_ixfft_pack(const cx<T>* __restrict__ G
                                                      const cx<T>* __restrict__ tw, Geo g,
                                                      const int* __restrict__ act,
                                                      const int* __restrict__ slot_sys,
-                                                     BicgSlot* st, RedScratch red) {
+                                                     SlotFilter f, RedScratch red) {
     constexpr int NL = rows_nl<T, L>();
     __shared__ cx<T> lds[NL * L];
     const int tid = threadIdx.x;
     const int c = blockIdx.y;
     const int pos = blockIdx.z;
     const int64_t slot = act ? act[pos] : pos;
+    if (!slot_live(f, slot)) return;
     const int64_t sys = slot_sys[slot];
     const int nrows = g.nz * g.ny;
     const int row0 = blockIdx.x * NL;
@@ -287,7 +294,7 @@ int pack_blocks_per_slot(const Geo& g) {
 
 template <typename T>
 void launch_unpack_xfft(cx<T>* xin, const int* map, cx<T>* G, const cx<T>* tw_x, const Geo& g,
-                        const int* act, int n_act, const cx<T>* fuse_r, const BicgSlot* st,
+                        const int* act, int n_act, const cx<T>* fuse_r, SlotFilter f,
                         hipStream_t s) {
     if (n_act == 0) return;
     const int64_t nrows = int64_t(g.nz) * g.ny;
@@ -297,10 +304,10 @@ void launch_unpack_xfft(cx<T>* xin, const int* map, cx<T>* G, const cx<T>* tw_x,
         dim3 grid(nblk(nrows, rows_nl<T, N>()), 3, n_act);                             \
         if (fuse_r)                                                                    \
             k_unpack_xfft<T, N, true><<<grid, NTHR, 0, s>>>(xin, map, G, tw_x, g, act,  \
-                                                            fuse_r, st);               \
+                                                            fuse_r, f);                \
         else                                                                           \
             k_unpack_xfft<T, N, false><<<grid, NTHR, 0, s>>>(xin, map, G, tw_x, g, act, \
-                                                             nullptr, nullptr);        \
+                                                             nullptr, f);              \
         break;                                                                         \
     }
         DDA_FOR_EACH_L(DDA_CASE)
@@ -337,13 +344,13 @@ void launch_fft_mid(cx<T>* data, const cx<T>* tw, int L, bool inverse, int64_t n
 
 template <typename T>
 void launch_zconv(cx<T>* G, const cx<T>* const* Dptr, const cx<T>* tw_z, const Geo& g,
-                  const int* act, const int* slot_sys, int n_act, hipStream_t s) {
+                  const int* act, const int* slot_sys, int n_act, SlotFilter f, hipStream_t s) {
     if (n_act == 0) return;
     switch (g.mz) {
 #define DDA_CASE(N)                                                                    \
     case N: {                                                                          \
         dim3 grid(nblk(g.mx, zconv_tx<T, N>()), g.my / 2 + 1, n_act);                   \
-        k_zconv<T, N><<<grid, NTHR, 0, s>>>(G, Dptr, tw_z, g, act, slot_sys);           \
+        k_zconv<T, N><<<grid, NTHR, 0, s>>>(G, Dptr, tw_z, g, act, slot_sys, f);        \
         break;                                                                         \
     }
         DDA_FOR_EACH_L(DDA_CASE)
@@ -357,7 +364,7 @@ void launch_zconv(cx<T>* G, const cx<T>* const* Dptr, const cx<T>* tw_z, const G
 template <typename T>
 void launch_ixfft_pack(const cx<T>* G, const cx<T>* xin, const cx<T>* ainv, cx<T>* yout,
                        const int* map, const cx<T>* tw_x, const Geo& g, const int* act,
-                       const int* slot_sys, int n_act, int mode, BicgSlot* st, RedScratch red,
+                       const int* slot_sys, int n_act, int mode, SlotFilter f, RedScratch red,
                        hipStream_t s) {
     if (n_act == 0) return;
     if (mode == PACK_AX_COCG && pack_blocks_per_slot(g) > red.max_blocks)
@@ -369,13 +376,13 @@ void launch_ixfft_pack(const cx<T>* G, const cx<T>* xin, const cx<T>* ainv, cx<T
         dim3 grid(nblk(nrows, rows_nl<T, N>()), 3, n_act);                                 \
         if (mode == PACK_GX)                                                               \
             k_ixfft_pack<T, N, PACK_GX><<<grid, NTHR, 0, s>>>(G, xin, ainv, yout, map, tw_x,\
-                                                              g, act, slot_sys, st, red);  \
+                                                              g, act, slot_sys, f, red);  \
         else if (mode == PACK_AX)                                                          \
             k_ixfft_pack<T, N, PACK_AX><<<grid, NTHR, 0, s>>>(G, xin, ainv, yout, map, tw_x,\
-                                                              g, act, slot_sys, st, red);  \
+                                                              g, act, slot_sys, f, red);  \
         else                                                                               \
             k_ixfft_pack<T, N, PACK_AX_COCG><<<grid, NTHR, 0, s>>>(G, xin, ainv, yout, map, \
-                                                       tw_x, g, act, slot_sys, st, red);   \
+                                                       tw_x, g, act, slot_sys, f, red);   \
         break;                                                                             \
     }
         DDA_FOR_EACH_L(DDA_CASE)
@@ -387,24 +394,23 @@ void launch_ixfft_pack(const cx<T>* G, const cx<T>* xin, const cx<T>* ainv, cx<T
 }
 
 template void launch_unpack_xfft<double>(z128*, const int*, z128*, const z128*, const Geo&,
-                                         const int*, int, const z128*, const BicgSlot*,
-                                         hipStream_t);
+                                         const int*, int, const z128*, SlotFilter, hipStream_t);
 template void launch_unpack_xfft<float>(z64*, const int*, z64*, const z64*, const Geo&, const int*,
-                                        int, const z64*, const BicgSlot*, hipStream_t);
+                                        int, const z64*, SlotFilter, hipStream_t);
 template void launch_fft_mid<double>(z128*, const z128*, int, bool, int64_t, int64_t, int, int,
                                      int64_t, hipStream_t);
 template void launch_fft_mid<float>(z64*, const z64*, int, bool, int64_t, int64_t, int, int,
                                     int64_t, hipStream_t);
 template void launch_zconv<double>(z128*, const z128* const*, const z128*, const Geo&, const int*,
-                                   const int*, int, hipStream_t);
+                                   const int*, int, SlotFilter, hipStream_t);
 template void launch_zconv<float>(z64*, const z64* const*, const z64*, const Geo&, const int*,
-                                  const int*, int, hipStream_t);
+                                  const int*, int, SlotFilter, hipStream_t);
 template void launch_ixfft_pack<double>(const z128*, const z128*, const z128*, z128*,
                                         const int*, const z128*, const Geo&, const int*,
-                                        const int*, int, int, BicgSlot*, RedScratch, hipStream_t);
+                                        const int*, int, int, SlotFilter, RedScratch, hipStream_t);
 template void launch_ixfft_pack<float>(const z64*, const z64*, const z64*, z64*, const int*,
                                        const z64*, const Geo&, const int*, const int*, int, int,
-                                       BicgSlot*, RedScratch, hipStream_t);
+                                       SlotFilter, RedScratch, hipStream_t);
 
 // ------------------------------------------------------------ D build -----
 // G_tilde(R) = exp(ikR)/R^3 [(k^2R^2 + ikR - 1) I + (3 - 3ikR - k^2R^2) Rh Rh]

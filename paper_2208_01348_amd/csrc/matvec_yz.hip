@@ -65,14 +65,15 @@ __global__ __launch_bounds__(NT) void k_xfft_t(cx<T>* __restrict__ xin,
                                                cx<T>* __restrict__ Tb,
                                                const cx<T>* __restrict__ tw, Geo g,
                                                const int* __restrict__ act,
-                                               const cx<T>* __restrict__ fuse_r,
-                                               const BicgSlot* __restrict__ st, int ngroups) {
+                                               const cx<T>* __restrict__ fuse_r, SlotFilter f,
+                                               int ngroups) {
     constexpr int NR = xrows<LX>();
     constexpr int LP = LX + 1;  // padded LDS row: the transposed read below hits spread banks
     __shared__ cx<T> lds[NR * LP];
     const int tid = threadIdx.x;
     const int pos = blockIdx.y;
     const int64_t slot = act ? act[pos] : pos;
+    if (!slot_live(f, slot)) return;
     const int grp = blockIdx.x % ngroups;
     const int cz = blockIdx.x / ngroups;
     const int c = cz / g.nz, z = cz - (cz / g.nz) * g.nz;
@@ -80,7 +81,11 @@ __global__ __launch_bounds__(NT) void k_xfft_t(cx<T>* __restrict__ xin,
     cx<T>* src = xin + (slot * 3 + c) * g.n_occ;
     const cx<T>* rsrc = FUSE_P ? fuse_r + (slot * 3 + c) * g.n_occ : nullptr;
     cx<T> beta{T(0), T(0)};
-    if (FUSE_P) beta = cvt<T>(st[slot].beta);
+    bool reset = false;
+    if (FUSE_P) {
+        beta = cvt<T>(f.st[slot].beta);
+        reset = f.st[slot].reset_p != 0;
+    }
     for (int e = tid; e < NR * LX; e += NT) {
         const int r = e / LX, x = e % LX;
         const int y = y0 + r;
@@ -90,7 +95,7 @@ __global__ __launch_bounds__(NT) void k_xfft_t(cx<T>* __restrict__ xin,
             if (idx >= 0) {
                 v = src[idx];
                 if (FUSE_P) {  // each occupied element is visited by exactly one thread
-                    v = rsrc[idx] + beta * v;
+                    v = reset ? rsrc[idx] : rsrc[idx] + beta * v;
                     src[idx] = v;
                 }
             }
@@ -117,7 +122,7 @@ __global__ __launch_bounds__(NT) void k_ixfft_t(const cx<T>* __restrict__ Tb,
                                                 const int* __restrict__ map,
                                                 const cx<T>* __restrict__ tw, Geo g,
                                                 const int* __restrict__ act,
-                                                const int* __restrict__ slot_sys,
+                                                const int* __restrict__ slot_sys, SlotFilter f,
                                                 RedScratch red, int ngroups) {
     constexpr int NR = xrows<LX>();
     constexpr int LP = LX + 1;
@@ -125,6 +130,7 @@ __global__ __launch_bounds__(NT) void k_ixfft_t(const cx<T>* __restrict__ Tb,
     const int tid = threadIdx.x;
     const int pos = blockIdx.y;
     const int64_t slot = act ? act[pos] : pos;
+    if (!slot_live(f, slot)) return;
     const int64_t sys = slot_sys[slot];
     const int grp = blockIdx.x % ngroups;
     const int cz = blockIdx.x / ngroups;
@@ -178,7 +184,7 @@ __global__ __launch_bounds__(NTYZ) void k_yzconv(cx<T>* __restrict__ Tb,
                                                  const cx<T>* __restrict__ twy,
                                                  const cx<T>* __restrict__ twz, Geo g,
                                                  const int* __restrict__ act,
-                                                 const int* __restrict__ slot_sys) {
+                                                 const int* __restrict__ slot_sys, SlotFilter f) {
     constexpr int SY = L + 1;
     constexpr int H = L / 2 + 1;  // z rows that can be non-zero (nz <= H)
     constexpr int ROW = 3 * SY;   // one z row: three components
@@ -187,6 +193,7 @@ __global__ __launch_bounds__(NTYZ) void k_yzconv(cx<T>* __restrict__ Tb,
     const int kx = blockIdx.x;
     const int pos = blockIdx.y;
     const int slot = act ? act[pos] : pos;
+    if (!slot_live(f, slot)) return;
     const int sys = slot_sys[slot];
     const int64_t cplane = int64_t(3) * g.nz * g.ny;
     cx<T>* col = Tb + (int64_t(pos) * g.mx + kx) * cplane;
@@ -241,7 +248,7 @@ __global__ __launch_bounds__(NTYZ) void k_yzconv(cx<T>* __restrict__ Tb,
 
 template <typename T>
 void launch_xfft_t(cx<T>* xin, const int* map, cx<T>* Tb, const cx<T>* tw_x, const Geo& g,
-                   const int* act, int n_act, const cx<T>* fuse_r, const BicgSlot* st,
+                   const int* act, int n_act, const cx<T>* fuse_r, SlotFilter f,
                    hipStream_t s) {
     if (n_act == 0) return;
     const int ng = xgroups(g);
@@ -250,11 +257,11 @@ void launch_xfft_t(cx<T>* xin, const int* map, cx<T>* Tb, const cx<T>* tw_x, con
 #define DDA_CASE(N)                                                                         \
     case N:                                                                                 \
         if (fuse_r)                                                                         \
-            k_xfft_t<T, N, true><<<grid, NT, 0, s>>>(xin, map, Tb, tw_x, g, act, fuse_r, st, \
+            k_xfft_t<T, N, true><<<grid, NT, 0, s>>>(xin, map, Tb, tw_x, g, act, fuse_r, f,  \
                                                      ng);                                   \
         else                                                                                \
             k_xfft_t<T, N, false><<<grid, NT, 0, s>>>(xin, map, Tb, tw_x, g, act, nullptr,   \
-                                                      nullptr, ng);                         \
+                                                      f, ng);                               \
         break;
         DDA_FOR_EACH_LX(DDA_CASE)
 #undef DDA_CASE
@@ -267,7 +274,8 @@ void launch_xfft_t(cx<T>* xin, const int* map, cx<T>* Tb, const cx<T>* tw_x, con
 template <typename T>
 void launch_ixfft_t(const cx<T>* Tb, const cx<T>* xin, const cx<T>* ainv, cx<T>* yout,
                     const int* map, const cx<T>* tw_x, const Geo& g, const int* act,
-                    const int* slot_sys, int n_act, int mode, RedScratch red, hipStream_t s) {
+                    const int* slot_sys, int n_act, int mode, SlotFilter f, RedScratch red,
+                    hipStream_t s) {
     if (n_act == 0) return;
     const int ng = xgroups(g);
     if (mode == PACK_AX_COCG && 3 * g.nz * ng > red.max_blocks)
@@ -278,13 +286,13 @@ void launch_ixfft_t(const cx<T>* Tb, const cx<T>* xin, const cx<T>* ainv, cx<T>*
     case N:                                                                                  \
         if (mode == PACK_GX)                                                                 \
             k_ixfft_t<T, N, PACK_GX><<<grid, NT, 0, s>>>(Tb, xin, ainv, yout, map, tw_x, g,   \
-                                                         act, slot_sys, red, ng);            \
+                                                         act, slot_sys, f, red, ng);            \
         else if (mode == PACK_AX)                                                            \
             k_ixfft_t<T, N, PACK_AX><<<grid, NT, 0, s>>>(Tb, xin, ainv, yout, map, tw_x, g,   \
-                                                         act, slot_sys, red, ng);            \
+                                                         act, slot_sys, f, red, ng);            \
         else                                                                                 \
             k_ixfft_t<T, N, PACK_AX_COCG><<<grid, NT, 0, s>>>(Tb, xin, ainv, yout, map, tw_x, \
-                                                              g, act, slot_sys, red, ng);    \
+                                                              g, act, slot_sys, f, red, ng);    \
         break;
         DDA_FOR_EACH_LX(DDA_CASE)
 #undef DDA_CASE
@@ -296,7 +304,8 @@ void launch_ixfft_t(const cx<T>* Tb, const cx<T>* xin, const cx<T>* ainv, cx<T>*
 
 template <typename T>
 void launch_yzconv(cx<T>* Tb, const cx<T>* const* Dptr, const cx<T>* tw_y, const cx<T>* tw_z,
-                   const Geo& g, const int* act, const int* slot_sys, int n_act, hipStream_t s) {
+                   const Geo& g, const int* act, const int* slot_sys, int n_act, SlotFilter f,
+                   hipStream_t s) {
     if (n_act == 0) return;
     if (!yz_fused_ok(g, int(sizeof(cx<T>)))) throw Error(-1, "yz plane does not fit in LDS");
     dim3 grid(g.mx, n_act);
@@ -304,7 +313,7 @@ void launch_yzconv(cx<T>* Tb, const cx<T>* const* Dptr, const cx<T>* tw_y, const
 #define DDA_CASE(N)                                                                          \
     case N:                                                                                  \
         if constexpr (yz_lds_bytes<T, N>() <= (size_t(120) << 10))                           \
-            k_yzconv<T, N><<<grid, NTYZ, 0, s>>>(Tb, Dptr, tw_y, tw_z, g, act, slot_sys);      \
+            k_yzconv<T, N><<<grid, NTYZ, 0, s>>>(Tb, Dptr, tw_y, tw_z, g, act, slot_sys, f);    \
         else                                                                                 \
             throw Error(-1, "yz plane does not fit in LDS");                                 \
         break;
@@ -346,19 +355,20 @@ void launch_extract_yz(const z128* full, cx<T>* out, const Geo& g, hipStream_t s
 }
 
 template void launch_xfft_t<double>(z128*, const int*, z128*, const z128*, const Geo&, const int*,
-                                    int, const z128*, const BicgSlot*, hipStream_t);
+                                    int, const z128*, SlotFilter, hipStream_t);
 template void launch_xfft_t<float>(z64*, const int*, z64*, const z64*, const Geo&, const int*, int,
-                                   const z64*, const BicgSlot*, hipStream_t);
+                                   const z64*, SlotFilter, hipStream_t);
 template void launch_ixfft_t<double>(const z128*, const z128*, const z128*, z128*, const int*,
                                      const z128*, const Geo&, const int*, const int*, int, int,
-                                     RedScratch, hipStream_t);
+                                     SlotFilter, RedScratch, hipStream_t);
 template void launch_ixfft_t<float>(const z64*, const z64*, const z64*, z64*, const int*,
                                     const z64*, const Geo&, const int*, const int*, int, int,
-                                    RedScratch, hipStream_t);
+                                    SlotFilter, RedScratch, hipStream_t);
 template void launch_yzconv<double>(z128*, const z128* const*, const z128*, const z128*,
-                                    const Geo&, const int*, const int*, int, hipStream_t);
+                                    const Geo&, const int*, const int*, int, SlotFilter,
+                                    hipStream_t);
 template void launch_yzconv<float>(z64*, const z64* const*, const z64*, const z64*, const Geo&,
-                                   const int*, const int*, int, hipStream_t);
+                                   const int*, const int*, int, SlotFilter, hipStream_t);
 template void launch_extract_yz<double>(const z128*, z128*, const Geo&, hipStream_t);
 template void launch_extract_yz<float>(const z128*, z64*, const Geo&, hipStream_t);
 

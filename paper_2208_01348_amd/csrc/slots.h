@@ -12,6 +12,11 @@ enum SlotStatus : int {
     SLOT_CONVERGED = 1,  // the recursive residual met the tolerance
     SLOT_HALF = 2,       // BiCGStab: ||s|| met the tolerance inside an iteration
     SLOT_BREAKDOWN = 3,  // a Krylov scalar vanished or went non-finite
+    SLOT_MAXIT = 4,      // the iteration limit was reached
+    // terminal states, set by the FP64 residual check of the COCG driver
+    SLOT_DONE = 5,              // the FP64 residual met the tolerance
+    SLOT_FAIL_NOCONV = 6,       // iteration limit reached above the tolerance
+    SLOT_FAIL_BREAKDOWN = 7,    // breakdowns beyond the restart budget
 };
 
 struct BicgSlot {
@@ -27,8 +32,37 @@ struct BicgSlot {
     int status;
     int iters;
     int want_update;                  // set by the device, cleared by the FP64 residual pass
+    int matvecs;                      // matrix-vector products spent on this slot
+    int restarts;                     // breakdown restarts so far
+    int reset_p;                      // COCG: the next direction update takes p = r
+    int maxit;                        // iteration limit
     int pad_;
 };
+
+__host__ __device__ inline bool slot_terminal(int status) { return status >= SLOT_DONE; }
+
+// COCG: a slot waits for the FP64 residual check when its recursive residual
+// converged, a scalar broke down, the iteration limit was hit, or the
+// residual fell far enough below its running maximum for a reliable update.
+__device__ __forceinline__ bool needs_check(const BicgSlot& S) {
+    return S.status == SLOT_CONVERGED || S.status == SLOT_BREAKDOWN || S.status == SLOT_MAXIT ||
+           (S.status == SLOT_ACTIVE && S.want_update);
+}
+
+// Which listed slots a kernel processes: all of them, only those still
+// iterating, or only those waiting for the FP64 check.  A block whose slot is
+// filtered out returns before touching memory, so converged slots cost one
+// load of their status until the host drops them from the list.
+enum FilterMode : int { FILTER_ALL = 0, FILTER_ACTIVE = 1, FILTER_CHECK = 2 };
+struct SlotFilter {
+    const BicgSlot* st;
+    int mode;
+};
+__device__ __forceinline__ bool slot_live(SlotFilter f, int64_t slot) {
+    if (f.mode == FILTER_ALL) return true;
+    const BicgSlot& S = f.st[slot];
+    return f.mode == FILTER_ACTIVE ? S.status == SLOT_ACTIVE : needs_check(S);
+}
 
 // Reduction scratch: per slot, up to `max_blocks` partial rows of up to 8
 // doubles.  A reduction is two kernels: the work kernel writes one row per

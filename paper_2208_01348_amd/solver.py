@@ -4,10 +4,16 @@ Torch provides device memory and the stream; every step of the path (the
 electron field, the FFT matvecs, the Krylov iterations and the loss sums)
 runs in libdda's HIP kernels.  This module only allocates tensors and passes
 their pointers.
+
+By default a solver runs on a stream of its own (default priority), so that
+the library can capture its iteration intervals as HIP graphs; every call is
+ordered after the work already queued on torch's current stream, and the
+current stream waits for the call's work before torch touches the outputs.
 """
 
 from __future__ import annotations
 
+import contextlib
 from dataclasses import dataclass
 from typing import List, Optional, Sequence
 
@@ -35,7 +41,8 @@ class DDASolver:
     def __init__(self, mask: np.ndarray, d_nm: float, m_h: complex, polarizability: str = "ldr",
                  precision: str = "fp64", tol: float = 1e-10, maxit: int = 100000,
                  solver: str = "bicgstab",
-                 check_every: int = 16, stream: Optional[torch.cuda.Stream] = None):
+                 check_every: int = 16, stream: Optional[torch.cuda.Stream] = None,
+                 use_graphs: bool = True):
         m = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8))
         if m.ndim != 3:
             raise ValueError("mask must be [nz][ny][nx]")
@@ -43,7 +50,7 @@ class DDASolver:
         self.d = float(d_nm)
         self.m_h = complex(m_h)
         self.device = torch.device("cuda", torch.cuda.current_device())
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
         opt = L.dda_default_options()
         opt.polarizability = _POL[polarizability]
         opt.precision = _PREC[precision]
@@ -51,6 +58,7 @@ class DDASolver:
         opt.tol = float(tol)
         opt.maxit = int(maxit)
         opt.check_every = int(check_every)
+        opt.use_graphs = 1 if use_graphs else 0
         self.ctx = L.dda_setup(m, self.nx, self.ny, self.nz, self.d, self.m_h.real,
                                self.m_h.imag, opt, self.stream.cuda_stream)
         self.n_occ = L.dda_n_occ(self.ctx)
@@ -67,6 +75,17 @@ class DDASolver:
         except Exception:
             pass
 
+    @contextlib.contextmanager
+    def _ordered(self):
+        cur = torch.cuda.current_stream(self.device)
+        if cur.cuda_stream != self.stream.cuda_stream:
+            self.stream.wait_stream(cur)
+        try:
+            yield
+        finally:
+            if cur.cuda_stream != self.stream.cuda_stream:
+                cur.wait_stream(self.stream)
+
     def _field(self, nrhs: int, dtype=torch.complex128) -> torch.Tensor:
         return torch.empty((nrhs, 3, self.n_occ), dtype=dtype, device=self.device)
 
@@ -75,7 +94,8 @@ class DDASolver:
         E = np.atleast_1d(np.asarray(energies, dtype=np.float64))
         R = np.asarray(r0, dtype=np.float64).reshape(-1, 3)
         e = out if out is not None else self._field(E.size * R.shape[0])
-        L.dda_einc_electron(self.ctx, E, beta, R, e.data_ptr())
+        with self._ordered():
+            L.dda_einc_electron(self.ctx, E, beta, R, e.data_ptr())
         return e
 
     def solve(self, energies: Sequence[float], eps: np.ndarray, einc: torch.Tensor,
@@ -84,22 +104,25 @@ class DDASolver:
         E = np.atleast_1d(np.asarray(energies, dtype=np.float64))
         p = out if out is not None else self._field(E.size * n_traj)
         eps = np.asarray(eps, dtype=np.complex128).reshape(E.size, self.n_occ)
-        st, info = L.dda_solve(self.ctx, E, eps, einc.data_ptr(), n_traj, p.data_ptr(),
-                               raise_on_error=raise_on_error)
+        with self._ordered():
+            st, info = L.dda_solve(self.ctx, E, eps, einc.data_ptr(), n_traj, p.data_ptr(),
+                                   raise_on_error=raise_on_error)
         return p, [SolveInfo(*i) for i in info], st
 
     def losses(self, energies: Sequence[float], beta: float, eps: np.ndarray, r0: np.ndarray,
                einc: torch.Tensor, p: torch.Tensor) -> np.ndarray:
         E = np.atleast_1d(np.asarray(energies, dtype=np.float64))
         eps = np.asarray(eps, dtype=np.complex128).reshape(E.size, self.n_occ)
-        return L.dda_eels_cl(self.ctx, E, beta, eps, r0, einc.data_ptr(), p.data_ptr())
+        with self._ordered():
+            return L.dda_eels_cl(self.ctx, E, beta, eps, r0, einc.data_ptr(), p.data_ptr())
 
     def matvec(self, energy: float, eps: Optional[np.ndarray], x: torch.Tensor,
                precision: str = "fp64", interaction_only: bool = False,
                out: Optional[torch.Tensor] = None) -> torch.Tensor:
         y = out if out is not None else torch.empty_like(x)
-        L.dda_matvec(self.ctx, energy, eps, _PREC[precision], interaction_only, x.data_ptr(),
-                     y.data_ptr(), x.shape[0])
+        with self._ordered():
+            L.dda_matvec(self.ctx, energy, eps, _PREC[precision], interaction_only,
+                         x.data_ptr(), y.data_ptr(), x.shape[0])
         return y
 
     def spectrum(self, energies: Sequence[float], beta: float, eps: np.ndarray, r0: np.ndarray):
