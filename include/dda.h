@@ -130,6 +130,14 @@ int dda_setup(const uint8_t* mask, int nx, int ny, int nz, double d_nm,
               double mh_re, double mh_im, const dda_options* opt,
               void* hip_stream, dda_ctx** out);
 
+/*
+ * Changes the host index of a context (passive: Re m_h > 0, Im m_h >= 0).
+ * Later calls use it; the cached interaction spectra stay valid (they are
+ * keyed by the wavenumber m_h omega/c), and systems already submitted to the
+ * engine keep the host index they were submitted with.
+ */
+int dda_set_host(dda_ctx* ctx, double mh_re, double mh_im);
+
 /* Number of occupied cells (dipoles). */
 int dda_n_occ(const dda_ctx* ctx, int64_t* n_occ);
 
@@ -193,6 +201,58 @@ int dda_eels_cl(dda_ctx* ctx, int n_energy, const double* energy_eV, double beta
  */
 int dda_matvec(dda_ctx* ctx, double energy_eV, const double* eps_dipole, int precision,
                int interaction_only, const void* x_dev, void* y_dev, int nrhs);
+
+/*
+ * Continuous batching (COCG only; serving many requests on one lattice).
+ * Device bytes an engine with n_slots slots holds, counting one interaction
+ * spectrum D per slot (the worst case: every slot at a distinct energy):
+ * per-slot Krylov vectors, 1/alpha, the FFT work buffer and D in the
+ * context's precision.  A server admits lattices by this footprint.
+ */
+int dda_workspace_bytes(const dda_ctx* ctx, int n_slots, size_t* bytes);
+
+/*
+ * Opens the context's slot pool (at most one per context; max_slots in
+ * [1, 4096]) and allocates everything dda_workspace_bytes counts except the
+ * D entries, which come from the context's cache as systems are admitted and
+ * stay resident while any slot solves at their wavenumber.
+ * Errors: DDA_EINVAL when the solver is not COCG, the lattice is empty or an
+ * engine is already open; DDA_ENOMEM.
+ */
+int dda_engine_open(dda_ctx* ctx, int max_slots);
+
+/*
+ * Queues one system at the context's current host index (dda_set_host):
+ * energy, eps_dipole [n_occ][2] host (copied), einc_dev
+ * complex128 [3][n_occ] (one right-hand side as written by
+ * dda_einc_electron) and p_dev complex128 [3][n_occ] for the solution; the
+ * device buffers must stay valid until the tag comes back from
+ * dda_engine_poll and the caller's later work on the stream has used them.
+ * May be called from another thread than the one polling.
+ * Errors: DDA_EINVAL for a non-positive energy or a non-finite permittivity.
+ */
+int dda_engine_submit(dda_ctx* ctx, int64_t tag, double energy_eV, const double* eps_dipole,
+                      const void* einc_dev, void* p_dev);
+
+/*
+ * Runs up to max_intervals COCG intervals.  Before each one it harvests the
+ * slots that finished (their p_dev copy is queued on the stream) and admits
+ * queued systems into free slots; systems admitted while others are halfway
+ * through their iterations join the same kernel launches.  Returns at once
+ * when nothing is queued or running.  Up to `capacity` finished systems are
+ * returned in tags / info (the rest on later calls); *n_done says how many.
+ * A system whose permittivity gives a vanishing or infinite polarizability
+ * comes back with status DDA_EINVAL.  Each system's arithmetic does not
+ * depend on what shares the slots: its result equals a dda_solve of it alone.
+ */
+int dda_engine_poll(dda_ctx* ctx, int max_intervals, int64_t* tags, dda_solve_info* info,
+                    int capacity, int* n_done);
+
+/* Systems queued, in slots, and finished but not yet returned. */
+int dda_engine_status(dda_ctx* ctx, int* queued, int* running, int* finished);
+
+/* Waits for the stream and frees the slot pool (queued systems are dropped). */
+int dda_engine_close(dda_ctx* ctx);
 
 /* Per-kernel timing of the matvec chain, measured with HIP events recorded on
  * the context's stream around every launch while timing is enabled

@@ -24,7 +24,9 @@ DDA_PREC_FP64, DDA_PREC_MIXED = 0, 1
 EXPORTED = ["dda_default_options", "dda_beta_from_keV", "dda_setup", "dda_n_occ",
             "dda_grid_dims", "dda_einc_electron", "dda_solve", "dda_eels_cl", "dda_matvec",
             "dda_set_timing", "dda_kernel_time", "dda_drop_cache", "dda_destroy",
-            "dda_last_error", "dda_debug_besselk01"]
+            "dda_last_error", "dda_debug_besselk01", "dda_workspace_bytes", "dda_engine_open",
+            "dda_engine_submit", "dda_engine_poll", "dda_engine_status", "dda_engine_close",
+            "dda_set_host"]
 
 
 class DDAError(RuntimeError):
@@ -82,6 +84,13 @@ def load() -> ctypes.CDLL:
         "dda_destroy": (_i, [_vp]),
         "dda_last_error": (ctypes.c_char_p, []),
         "dda_debug_besselk01": (_i, [_vp, _i64, _vp]),
+        "dda_workspace_bytes": (_i, [_vp, _i, _vp]),
+        "dda_engine_open": (_i, [_vp, _i]),
+        "dda_engine_submit": (_i, [_vp, _i64, _d, _vp, _vp, _vp]),
+        "dda_engine_poll": (_i, [_vp, _i, _vp, _vp, _i, _vp]),
+        "dda_engine_status": (_i, [_vp, _vp, _vp, _vp]),
+        "dda_engine_close": (_i, [_vp]),
+        "dda_set_host": (_i, [_vp, _d, _d]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -130,6 +139,10 @@ def dda_setup(mask: np.ndarray, nx: int, ny: int, nz: int, d_nm: float, mh_re: f
                             ctypes.byref(opt), ctypes.c_void_p(hip_stream or None),
                             ctypes.byref(ctx)))
     return ctx
+
+
+def dda_set_host(ctx, mh_re: float, mh_im: float) -> None:
+    _check(load().dda_set_host(ctx, float(mh_re), float(mh_im)))
 
 
 def dda_n_occ(ctx) -> int:
@@ -207,6 +220,46 @@ def dda_kernel_time(ctx, name: str):
     _check(load().dda_kernel_time(ctx, name.encode(), ctypes.byref(ms), ctypes.byref(n),
                                   ctypes.byref(u)))
     return float(ms.value), int(n.value), float(u.value)
+
+
+def dda_workspace_bytes(ctx, n_slots: int) -> int:
+    b = ctypes.c_size_t()
+    _check(load().dda_workspace_bytes(ctx, int(n_slots), ctypes.byref(b)))
+    return int(b.value)
+
+
+def dda_engine_open(ctx, max_slots: int) -> None:
+    _check(load().dda_engine_open(ctx, int(max_slots)))
+
+
+def dda_engine_submit(ctx, tag: int, energy_eV: float, eps_dipole, einc_dev: int,
+                      p_dev: int) -> None:
+    """eps_dipole: complex [n_occ] for this energy."""
+    eps = _eps_pairs(eps_dipole)
+    _check(load().dda_engine_submit(ctx, int(tag), float(energy_eV), _ptr(eps),
+                                    ctypes.c_void_p(einc_dev), ctypes.c_void_p(p_dev)))
+
+
+def dda_engine_poll(ctx, max_intervals: int, capacity: int = 256):
+    """Returns [(tag, (iters, matvecs, rel_residual, status)), ...] of finished systems."""
+    tags = (ctypes.c_int64 * max(1, capacity))()
+    info = (SolveInfo * max(1, capacity))()
+    n = ctypes.c_int()
+    _check(load().dda_engine_poll(ctx, int(max_intervals), tags, info, int(capacity),
+                                  ctypes.byref(n)))
+    return [(int(tags[k]), (info[k].iters, info[k].matvecs, info[k].rel_residual,
+                            info[k].status)) for k in range(n.value)]
+
+
+def dda_engine_status(ctx):
+    """(queued, running, finished-not-returned)."""
+    q, r, f = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    _check(load().dda_engine_status(ctx, ctypes.byref(q), ctypes.byref(r), ctypes.byref(f)))
+    return q.value, r.value, f.value
+
+
+def dda_engine_close(ctx) -> None:
+    _check(load().dda_engine_close(ctx))
 
 
 def dda_drop_cache(ctx) -> None:

@@ -8,9 +8,11 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <deque>
 #include <list>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -82,6 +84,7 @@ struct DEntry {
     DevBuf d128, d64;
     bool has64 = false;
     uint64_t last_use = 0;
+    int refs = 0;  // engine slots solving at this wavenumber
 };
 
 struct Timer {
@@ -132,6 +135,104 @@ cplx gamma_h_of(double beta, cplx mh) {
     return cplx(0.0, 1.0) / sq;
 }
 
+// Spins until an event has completed (an event never recorded counts as
+// complete).
+void wait_event(hipEvent_t e) {
+    hipError_t r;
+    while ((r = hipEventQuery(e)) == hipErrorNotReady) {
+    }
+    DDA_HIP_CHECK(r);
+}
+
+// Pinned staging with kRing regions, so that an upload or a state snapshot
+// can be in flight while the host fills the next region.
+constexpr int kRing = 4;
+
+// Active lists uploaded in stream order; a region is refilled only after its
+// previous copy has run.
+struct ActRing {
+    DevBuf dev;  // the list the kernels read
+    PinnedBuf host;
+    hipEvent_t ev[kRing] = {};
+    int seq = 0, cap = 0;
+    ActRing() = default;
+    ActRing(const ActRing&) = delete;
+    ~ActRing() {
+        for (auto e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+    void ensure(int n) {
+        dev.ensure(size_t(n) * sizeof(int));
+        if (n > cap) {
+            for (auto e : ev)
+                if (e) wait_event(e);  // copies in flight read the old buffer
+            cap = n;
+        }
+        host.ensure(size_t(kRing) * cap * sizeof(int));
+    }
+    void upload(hipStream_t s, const std::vector<int>& act) {
+        if (act.empty()) return;
+        if (int(act.size()) > cap) throw Error(DDA_EDEVICE, "active list larger than its buffer");
+        const int r = seq++ % kRing;
+        if (!ev[r]) DDA_HIP_CHECK(hipEventCreateWithFlags(&ev[r], hipEventDisableTiming));
+        wait_event(ev[r]);
+        int* h = host.as<int>() + size_t(r) * cap;
+        std::memcpy(h, act.data(), act.size() * sizeof(int));
+        DDA_HIP_CHECK(hipMemcpyAsync(dev.p, h, act.size() * sizeof(int), hipMemcpyHostToDevice, s));
+        DDA_HIP_CHECK(hipEventRecord(ev[r], s));
+    }
+    const int* ptr() const { return dev.as<int>(); }
+};
+
+// Slot states copied to pinned memory after every interval k (region
+// k mod kRing); read back kLag intervals later without stalling the stream.
+struct StateRing {
+    PinnedBuf host;
+    hipEvent_t ev[kRing] = {};
+    int cap = 0;
+    StateRing() = default;
+    StateRing(const StateRing&) = delete;
+    ~StateRing() {
+        for (auto e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+    void ensure(int n) {
+        if (n > cap) {
+            for (auto e : ev)
+                if (e) wait_event(e);
+            cap = n;
+        }
+        host.ensure(size_t(kRing) * cap * sizeof(dda::BicgSlot));
+        for (auto& e : ev)
+            if (!e) DDA_HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    void snapshot(hipStream_t s, const dda::BicgSlot* st, int n, int64_t k) {
+        const int r = int(k % kRing);
+        DDA_HIP_CHECK(hipMemcpyAsync(host.as<dda::BicgSlot>() + size_t(r) * cap, st,
+                                     size_t(n) * sizeof(dda::BicgSlot), hipMemcpyDeviceToHost, s));
+        DDA_HIP_CHECK(hipEventRecord(ev[r], s));
+    }
+    const dda::BicgSlot* wait(int64_t k) {
+        const int r = int(k % kRing);
+        wait_event(ev[r]);
+        return host.as<dda::BicgSlot>() + size_t(r) * cap;
+    }
+};
+
+// A captured interval, replayed while its key (the active-list length) holds.
+struct GraphCache {
+    hipGraphExec_t exec = nullptr;
+    int key = -1;
+    GraphCache() = default;
+    GraphCache(const GraphCache&) = delete;
+    ~GraphCache() { drop(); }
+    void drop() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        exec = nullptr;
+        key = -1;
+    }
+};
+
 }  // namespace
 
 struct dda_ctx {
@@ -148,18 +249,16 @@ struct dda_ctx {
     uint64_t pin_clock = 0;   // entries used at or after this tick are in use
     size_t dcache_limit = size_t(64) << 30;
     // work space
-    DevBuf G, vec128, vec64, st, partial, act, slot_sys, dptr, ainv128, ainv64, misc;
+    DevBuf G, vec128, vec64, st, partial, slot_sys, dptr, ainv128, ainv64, misc;
     DevBuf dfull;  // scratch of the full-grid transform during a D build
     DevBuf eps_dev, matsys;  // permittivities and wavenumbers of a chunk
-    PinnedBuf host_st, host_act, host_misc;
-    int slot_cap = 0;                   // slots per region of host_st / host_act
-    int act_seq = 0;                    // next host_act region
-    hipEvent_t act_ev[4] = {};          // per host_act region: its last upload
-    hipEvent_t ring_ev[4] = {};         // per host_st region: its last state snapshot
+    PinnedBuf host_st, host_misc;
+    ActRing act;
+    StateRing ring;
     // Captured COCG interval (not used while kernels are timed: events
     // recorded by graph nodes carry no timestamps)
-    hipGraphExec_t graph_exec = nullptr;
-    int graph_key = -1;  // active-list length it was captured for
+    GraphCache graph;
+    std::unique_ptr<struct Engine> engine;  // continuous batching, when open
     int max_blocks = 1024;
     bool timing = false;
     unsigned timing_mask = 0x3f;  // which matvec kernels are timed
@@ -193,15 +292,6 @@ void wait_stream(dda_ctx* c) {
     while ((e = hipEventQuery(c->sync_ev)) == hipErrorNotReady) {
     }
     DDA_HIP_CHECK(e);
-}
-
-// Spins until an event has completed (an event never recorded counts as
-// complete).
-void wait_event(hipEvent_t e) {
-    hipError_t r;
-    while ((r = hipEventQuery(e)) == hipErrorNotReady) {
-    }
-    DDA_HIP_CHECK(r);
 }
 
 // Copies a pageable host array to the device in the order of the context's
@@ -247,19 +337,13 @@ void flush_timer(dda_ctx* c) {
     c->timer.pending.clear();
 }
 
-void drop_graph(dda_ctx* c) {
-    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
-    c->graph_exec = nullptr;
-    c->graph_key = -1;
-}
-
-// Launches body() on the context's stream through a captured graph: replayed
-// while `key` is unchanged, captured again otherwise (the executable is
-// updated in place when the topology allows it, else instantiated anew).
+// Launches body() on the context's stream through the captured graph in gc:
+// replayed while `key` is unchanged, captured again otherwise (the executable
+// is updated in place when the topology allows it, else instantiated anew).
 template <typename F>
-void launch_captured(dda_ctx* c, int key, F&& body) {
+void launch_captured(dda_ctx* c, GraphCache& gc, int key, F&& body) {
     hipStream_t s = c->stream;
-    if (!c->graph_exec || c->graph_key != key) {
+    if (!gc.exec || gc.key != key) {
         hipGraph_t gr = nullptr;
         DDA_HIP_CHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         try {
@@ -272,28 +356,37 @@ void launch_captured(dda_ctx* c, int key, F&& body) {
         }
         DDA_HIP_CHECK(hipStreamEndCapture(s, &gr));
         bool updated = false;
-        if (c->graph_exec) {
+        if (gc.exec) {
             hipGraphNode_t bad = nullptr;
             hipGraphExecUpdateResult res;
-            updated = hipGraphExecUpdate(c->graph_exec, gr, &bad, &res) == hipSuccess &&
+            updated = hipGraphExecUpdate(gc.exec, gr, &bad, &res) == hipSuccess &&
                       res == hipGraphExecUpdateSuccess;
             if (!updated) {
                 (void)hipGetLastError();
-                drop_graph(c);
+                gc.drop();
             }
         }
         hipError_t e = hipSuccess;
-        if (!updated) e = hipGraphInstantiate(&c->graph_exec, gr, nullptr, nullptr, 0);
+        if (!updated) e = hipGraphInstantiate(&gc.exec, gr, nullptr, nullptr, 0);
         (void)hipGraphDestroy(gr);
         DDA_HIP_CHECK(e);
-        c->graph_key = key;
+        gc.key = key;
     }
-    DDA_HIP_CHECK(hipGraphLaunch(c->graph_exec, s));
+    DDA_HIP_CHECK(hipGraphLaunch(gc.exec, s));
 }
 
 dda::RedScratch red_of(dda_ctx* c) {
     return dda::RedScratch{c->partial.as<double>(), c->max_blocks};
 }
+
+// Buffers a solver driver works in: slot states, reduction rows and the grid
+// work buffer of the matvec (indexed by active-list position).
+struct Work {
+    dda::BicgSlot* st;
+    dda::RedScratch red;
+    void* G;
+};
+Work ctx_work(dda_ctx* c) { return Work{c->st.as<dda::BicgSlot>(), red_of(c), c->G.p}; }
 
 // One FFT matvec for the slots listed in act (device) / n_act:
 // mode PACK_AX (y = A x), PACK_GX (y = G_off x) or PACK_AX_COCG (y = A x with
@@ -305,7 +398,7 @@ int pack_blocks(const dda_ctx* c, int csize) {
 }
 
 template <typename T>
-void matvec(dda_ctx* c, dda::cx<T>* x, dda::cx<T>* y, const int* act, int n_act,
+void matvec(dda_ctx* c, const Work& w, dda::cx<T>* x, dda::cx<T>* y, const int* act, int n_act,
             const dda::cx<T>* const* dptr, const int* slot_sys, const dda::cx<T>* ainv, int mode,
             const dda::cx<T>* fuse_r = nullptr,
             dda::SlotFilter f = dda::SlotFilter{nullptr, dda::FILTER_ALL}) {
@@ -313,9 +406,9 @@ void matvec(dda_ctx* c, dda::cx<T>* x, dda::cx<T>* y, const int* act, int n_act,
     if ((fuse_r || f.mode != dda::FILTER_ALL) && !f.st)
         throw Error(DDA_EDEVICE, "slot filter without slot states");
     const dda::Geo& g = c->g;
-    auto* G = c->G.as<dda::cx<T>>();
+    auto* G = static_cast<dda::cx<T>*>(w.G);
     hipStream_t s = c->stream;
-    auto* st = c->st.as<dda::BicgSlot>();
+    auto* st = w.st;
     constexpr int csize = int(sizeof(dda::cx<T>));
     if (dda::yz_fused_ok(g, csize)) {
         {
@@ -331,7 +424,7 @@ void matvec(dda_ctx* c, dda::cx<T>* x, dda::cx<T>* y, const int* act, int n_act,
         {
             Tic t(c, 4, n_act);
             dda::launch_ixfft_t<T>(G, x, ainv, y, c->map.as<int>(), tw_of<T>(c, 0), g, act,
-                                   slot_sys, n_act, mode, f, red_of(c), s);
+                                   slot_sys, n_act, mode, f, w.red, s);
         }
     } else {
         const int64_t plane = int64_t(g.my) * g.mx;
@@ -357,11 +450,19 @@ void matvec(dda_ctx* c, dda::cx<T>* x, dda::cx<T>* y, const int* act, int n_act,
         {
             Tic t(c, 4, n_act);
             dda::launch_ixfft_pack<T>(G, x, ainv, y, c->map.as<int>(), tw_of<T>(c, 0), g, act,
-                                      slot_sys, n_act, mode, f, red_of(c), s);
+                                      slot_sys, n_act, mode, f, w.red, s);
         }
     }
     if (mode == dda::PACK_AX_COCG)
-        dda::cocg_alpha_finalize(st, act, n_act, red_of(c), pack_blocks(c, csize), s);
+        dda::cocg_alpha_finalize(st, act, n_act, w.red, pack_blocks(c, csize), s);
+}
+
+template <typename T>
+void matvec(dda_ctx* c, dda::cx<T>* x, dda::cx<T>* y, const int* act, int n_act,
+            const dda::cx<T>* const* dptr, const int* slot_sys, const dda::cx<T>* ainv, int mode,
+            const dda::cx<T>* fuse_r = nullptr,
+            dda::SlotFilter f = dda::SlotFilter{nullptr, dda::FILTER_ALL}) {
+    matvec<T>(c, ctx_work(c), x, y, act, n_act, dptr, slot_sys, ainv, mode, fuse_r, f);
 }
 
 // ------------------------------------------------------------ D cache
@@ -387,8 +488,8 @@ void extract_D(dda_ctx* c, dda::cx<T>* out) {
         dda::launch_extract_corner<T>(c->dfull.as<z128>(), out, c->g, c->stream);
 }
 
-DEntry* get_D(dda_ctx* c, double energy, bool need64) {
-    const cplx k = c->mh * (energy / kHbarC);
+// D(k) from the cache, built on a miss (and its FP32 copy if need64).
+DEntry* get_D_k(dda_ctx* c, cplx k, bool need64) {
     auto key = std::make_pair(k.real(), k.imag());
     auto it = c->dcache.find(key);
     DEntry* e;
@@ -401,7 +502,7 @@ DEntry* get_D(dda_ctx* c, double energy, bool need64) {
         while (used + b128 * 2 > c->dcache_limit) {
             auto victim = c->dcache.end();
             for (auto i2 = c->dcache.begin(); i2 != c->dcache.end(); ++i2)
-                if (i2->second->last_use < c->pin_clock &&
+                if (i2->second->last_use < c->pin_clock && i2->second->refs == 0 &&
                     (victim == c->dcache.end() || i2->second->last_use < victim->second->last_use))
                     victim = i2;
             if (victim == c->dcache.end()) break;  // everything cached is in use
@@ -428,6 +529,10 @@ DEntry* get_D(dda_ctx* c, double energy, bool need64) {
     return e;
 }
 
+DEntry* get_D(dda_ctx* c, double energy, bool need64) {
+    return get_D_k(c, c->mh * (energy / kHbarC), need64);
+}
+
 // ------------------------------------------------------------ material terms
 // Copies the permittivities of systems [e0, e0 + ns) to the device and
 // evaluates there, per dipole, 1/alpha (FP64 if need128, FP32 if need64) and,
@@ -443,30 +548,32 @@ void compute_material(dda_ctx* c, const double* energy, const double* eps, int e
     std::vector<dda::MatSys> hs(ns);
     for (int i = 0; i < ns; ++i) {
         const cplx k = c->mh * (energy[e0 + i] / kHbarC);
-        hs[i] = dda::MatSys{k.real(), k.imag()};
+        hs[i] = dda::MatSys{k.real(), k.imag(), c->mh.real(), c->mh.imag()};
     }
     const size_t sb = hs.size() * sizeof(dda::MatSys);
     const size_t sb_al = (sb + 255) / 256 * 256;
-    c->matsys.ensure(sb_al + 256);
+    c->matsys.ensure(sb_al + size_t(ns) * sizeof(int));
     int* err = reinterpret_cast<int*>(c->matsys.as<char>() + sb_al);
     DDA_HIP_CHECK(hipMemcpyAsync(c->eps_dev.p, eps + 2 * int64_t(e0) * n, cnt * sizeof(z128),
                                  hipMemcpyHostToDevice, c->stream));
     DDA_HIP_CHECK(hipMemcpyAsync(c->matsys.p, hs.data(), sb, hipMemcpyHostToDevice, c->stream));
-    DDA_HIP_CHECK(hipMemsetAsync(err, 0, sizeof(int), c->stream));
+    DDA_HIP_CHECK(hipMemsetAsync(err, 0, size_t(ns) * sizeof(int), c->stream));
     if (need128) c->ainv128.ensure(cnt * sizeof(z128));
     if (need64) c->ainv64.ensure(cnt * sizeof(z64));
-    dda::MatParams mp{c->opt.polarizability, c->mh.imag() == 0.0 ? 1 : 0, c->mh.real(),
-                      c->mh.imag(), c->d};
-    dda::launch_material(c->eps_dev.as<z128>(), c->matsys.as<dda::MatSys>(), n, ns, mp,
+    dda::MatParams mp{c->opt.polarizability, c->d};
+    dda::launch_material(c->eps_dev.as<z128>(), c->matsys.as<dda::MatSys>(), n, ns, mp, nullptr,
                          need128 ? c->ainv128.as<z128>() : nullptr,
                          need64 ? c->ainv64.as<z64>() : nullptr, w_dev, err, c->stream);
-    c->host_misc.ensure(256);
-    DDA_HIP_CHECK(hipMemcpyAsync(c->host_misc.p, err, sizeof(int), hipMemcpyDeviceToHost,
-                                 c->stream));
+    c->host_misc.ensure(size_t(ns) * sizeof(int));
+    DDA_HIP_CHECK(hipMemcpyAsync(c->host_misc.p, err, size_t(ns) * sizeof(int),
+                                 hipMemcpyDeviceToHost, c->stream));
     wait_stream(c);  // also keeps hs alive until its copy has run
-    const int herr = *c->host_misc.as<int>();
-    if (herr == 1) throw Error(DDA_EINVAL, "permittivity is not finite");
-    if (herr != 0) throw Error(DDA_EINVAL, "permittivity gives a zero or infinite polarizability");
+    for (int i = 0; i < ns; ++i) {
+        const int herr = c->host_misc.as<int>()[i];
+        if (herr == 1) throw Error(DDA_EINVAL, "permittivity is not finite");
+        if (herr != 0)
+            throw Error(DDA_EINVAL, "permittivity gives a zero or infinite polarizability");
+    }
 }
 
 // Per-chunk device tables: slot -> system, system -> D pointer.
@@ -491,39 +598,16 @@ const z64* const* upload_dptrs<float>(dda_ctx* c, const std::vector<DEntry*>& en
 }
 
 
-// Pinned staging: host_act and host_st hold kRing regions of slot_cap
-// entries each, so that an upload or a state snapshot can be in flight while
-// the host fills the next region.
-constexpr int kRing = 4;
-
 void ensure_slots(dda_ctx* c, int nslots) {
     c->st.ensure(size_t(nslots) * sizeof(dda::BicgSlot));
     c->partial.ensure(size_t(nslots) * c->max_blocks * 8 * sizeof(double));
-    c->act.ensure(size_t(nslots) * sizeof(int));
     c->slot_sys.ensure(size_t(nslots) * sizeof(int));
-    if (nslots > c->slot_cap) {
-        // earlier uploads and snapshots read the old pinned buffers
-        for (auto e : c->act_ev) if (e) wait_event(e);
-        for (auto e : c->ring_ev) if (e) wait_event(e);
-        c->slot_cap = nslots;
-    }
-    c->host_st.ensure(size_t(kRing) * c->slot_cap * sizeof(dda::BicgSlot));
-    c->host_act.ensure(size_t(kRing) * c->slot_cap * sizeof(int));
+    c->act.ensure(nslots);
+    c->ring.ensure(nslots);
+    c->host_st.ensure(size_t(nslots) * sizeof(dda::BicgSlot));
 }
 
-// Stream-ordered upload of an active list into c->act.  The staging region
-// is reused only after its previous copy has run.
-void upload_act(dda_ctx* c, const std::vector<int>& act) {
-    if (act.empty()) return;
-    const int r = c->act_seq++ % kRing;
-    if (!c->act_ev[r]) DDA_HIP_CHECK(hipEventCreateWithFlags(&c->act_ev[r], hipEventDisableTiming));
-    wait_event(c->act_ev[r]);
-    int* h = c->host_act.as<int>() + size_t(r) * c->slot_cap;
-    std::memcpy(h, act.data(), act.size() * sizeof(int));
-    DDA_HIP_CHECK(hipMemcpyAsync(c->act.p, h, act.size() * sizeof(int), hipMemcpyHostToDevice,
-                                 c->stream));
-    DDA_HIP_CHECK(hipEventRecord(c->act_ev[r], c->stream));
-}
+void upload_act(dda_ctx* c, const std::vector<int>& act) { c->act.upload(c->stream, act); }
 
 std::vector<dda::BicgSlot> read_states(dda_ctx* c, int nslots) {
     DDA_HIP_CHECK(hipMemcpyAsync(c->host_st.p, c->st.p, size_t(nslots) * sizeof(dda::BicgSlot),
@@ -557,7 +641,7 @@ void run_bicgstab(dda_ctx* c, int nslots, const dda::cx<T>* b, dda::cx<T>* x, Ve
     std::vector<int> act(nslots);
     for (int i = 0; i < nslots; ++i) act[i] = i;
     upload_act(c, act);
-    const int* dact = c->act.as<int>();
+    const int* dact = c->act.ptr();
     dda::bicg_norm_b<T>(b, st, dact, nslots, nv, tol * tol, 0.0, maxit, red, s);
     DDA_HIP_CHECK(hipMemsetAsync(x, 0, size_t(nslots) * nv * sizeof(dda::cx<T>), s));
     DDA_HIP_CHECK(hipMemcpyAsync(w.r, b, size_t(nslots) * nv * sizeof(dda::cx<T>),
@@ -668,7 +752,7 @@ void run_mixed(dda_ctx* c, int nslots, const z128* b, z128* x, const z128* const
     std::vector<int> all(nslots);
     for (int i = 0; i < nslots; ++i) all[i] = i;
     upload_act(c, all);
-    dda::bicg_norm_b<double>(b, st, c->act.as<int>(), nslots, nv, tol * tol, 0.0, c->opt.maxit,
+    dda::bicg_norm_b<double>(b, st, c->act.ptr(), nslots, nv, tol * tol, 0.0, c->opt.maxit,
                              red, c->stream);
     std::vector<double> bn(nslots), rn(nslots);
     {
@@ -691,7 +775,7 @@ void run_mixed(dda_ctx* c, int nslots, const z128* b, z128* x, const z128* const
         // (a zero right-hand side converges at once, with no iteration)
         set_rnorm2(c, nslots, rn);
         upload_act(c, need);
-        dda::scale_down(r64, r32, st, c->act.as<int>(), int(need.size()), nv, c->stream);
+        dda::scale_down(r64, r32, st, c->act.ptr(), int(need.size()), nv, c->stream);
         for (int i = 0; i < nslots; ++i)
             if (!isneed[i])
                 DDA_HIP_CHECK(hipMemsetAsync(r32 + size_t(i) * nv, 0, nv * sizeof(z64), c->stream));
@@ -701,10 +785,10 @@ void run_mixed(dda_ctx* c, int nslots, const z128* b, z128* x, const z128* const
                             c->ainv64.as<z64>(), it_in, mv_in, st_in, rr_in);
         set_rnorm2(c, nslots, rn);
         upload_act(c, need);
-        dda::accumulate_up(x, d32, st, c->act.as<int>(), int(need.size()), nv, c->stream);
-        matvec<double>(c, x, y64, c->act.as<int>(), int(need.size()), dptr64,
+        dda::accumulate_up(x, d32, st, c->act.ptr(), int(need.size()), nv, c->stream);
+        matvec<double>(c, x, y64, c->act.ptr(), int(need.size()), dptr64,
                        c->slot_sys.as<int>(), c->ainv128.as<z128>(), dda::PACK_AX);
-        dda::residual<double>(b, y64, r64, st, c->act.as<int>(), int(need.size()), nv, red,
+        dda::residual<double>(b, y64, r64, st, c->act.ptr(), int(need.size()), nv, red,
                               c->stream);
         auto S = read_states(c, nslots);
         for (int i : need) {
@@ -722,14 +806,13 @@ void run_mixed(dda_ctx* c, int nslots, const z128* b, z128* x, const z128* const
 }
 
 // COCG (conjugate-orthogonal CG: CG with the bilinear product x^T y, for
-// the complex-symmetric DDA matrix) over the slots of a chunk, from x0 = 0.
-// b and x are FP64 and slot-indexed; r, p, q are in T.  One matvec per
-// iteration; the direction update and p^T q are fused into the matvec.
-// For T = float the steps accumulate in x_lo (FP32) and a reliable update
-// (x += x_lo, r = b - A x in FP64, rho from the new r) is made whenever the
-// recursive residual fell by kUpdateDrop since the last one, and whenever it
-// reports convergence; for T = double only the convergence is verified that
-// way.
+// the complex-symmetric DDA matrix), from x0 = 0.  b and x are FP64 and
+// slot-indexed; r, p, q are in T.  One matvec per iteration; the direction
+// update and p^T q are fused into the matvec.  For T = float the steps
+// accumulate in x_lo (FP32) and a reliable update (x += x_lo, r = b - A x in
+// FP64, rho from the new r) is made whenever the recursive residual fell by
+// kUpdateDrop since the last one, and whenever it reports convergence; for
+// T = double only the convergence is verified that way.
 //
 // The device drives the iteration.  Work goes out in intervals: a check
 // phase (the FP64 residual of every slot that asked for one decides
@@ -744,54 +827,87 @@ void run_mixed(dda_ctx* c, int nslots, const z128* b, z128* x, const z128* const
 constexpr double kUpdateDrop = 0.1;
 constexpr int kLag = 2;
 
+// Buffers of one COCG driver (a dda_solve chunk, or an engine's slot pool).
 template <typename T>
-void run_cocg(dda_ctx* c, int nslots, const z128* b, z128* x, dda::cx<T>* r, dda::cx<T>* p,
-              dda::cx<T>* q, z64* x_lo, z128* y64, const dda::cx<T>* const* dptr,
-              const dda::cx<T>* ainv, const z128* const* dptr64, const z128* ainv64, double tol,
-              int maxit, std::vector<int>& iters, std::vector<int>& matvecs,
-              std::vector<int>& status, std::vector<double>& relres) {
+struct CocgBufs {
+    Work w;
+    const int* act;       // device active list
+    const int* slot_sys;  // slot -> system (D and 1/alpha row)
+    const z128* b;
+    z128* x;
+    dda::cx<T>*r, *p, *q;
+    z64* x_lo;  // FP32 step accumulator (T = float)
+    z128* y64;  // FP64 matvec output of the check phase
+    const dda::cx<T>* const* dptr;
+    const dda::cx<T>* ainv;
+    const z128* const* dptr64;
+    const z128* ainv64;
+};
+
+// x = 0, r = b, scalars for the n listed slots (device list act).
+template <typename T>
+void cocg_init(dda_ctx* c, const CocgBufs<T>& B, const int* act, int n, double tol, int maxit) {
+    constexpr bool mixed = std::is_same<T, float>::value;
+    const int64_t nv = c->nv();
+    dda::bicg_norm_b<double>(B.b, B.w.st, act, n, nv, tol * tol,
+                             mixed ? kUpdateDrop * kUpdateDrop : 0.0, maxit, B.w.red, c->stream);
+    dda::cocg_zero(B.x, mixed ? B.x_lo : nullptr, act, n, nv, c->stream);
+    dda::cocg_start<T>(B.b, nullptr, B.r, B.w.st, act, n, nv, B.w.red, c->stream);
+}
+
+// One interval over the n_act slots of B.act.
+template <typename T>
+void cocg_interval(dda_ctx* c, const CocgBufs<T>& B, int n_act) {
     constexpr bool mixed = std::is_same<T, float>::value;
     const int64_t nv = c->nv();
     hipStream_t s = c->stream;
-    auto* st = c->st.as<dda::BicgSlot>();
-    const int* slot_sys = c->slot_sys.as<int>();
-    const int* dact = c->act.as<int>();
-    auto red = red_of(c);
-    const size_t q128 = size_t(nslots) * nv;
+    const dda::SlotFilter fchk{B.w.st, dda::FILTER_CHECK}, fact{B.w.st, dda::FILTER_ACTIVE};
+    auto* xs = mixed ? reinterpret_cast<dda::cx<T>*>(B.x_lo) : reinterpret_cast<dda::cx<T>*>(B.x);
+    if (mixed) dda::accumulate_lo(B.x, B.x_lo, B.act, n_act, nv, fchk, s);
+    matvec<double>(c, B.w, B.x, B.y64, B.act, n_act, B.dptr64, B.slot_sys, B.ainv64, dda::PACK_AX,
+                   nullptr, fchk);
+    dda::cocg_check<T>(B.b, B.y64, B.r, B.w.st, B.act, n_act, nv, kMaxRestarts, B.w.red, s);
+    const int check = std::max(1, c->opt.check_every);
+    for (int k = 0; k < check; ++k) {
+        matvec<T>(c, B.w, B.p, B.q, B.act, n_act, B.dptr, B.slot_sys, B.ainv, dda::PACK_AX_COCG,
+                  B.r, fact);
+        dda::cocg_update_xr<T>(xs, B.r, B.p, B.q, B.w.st, B.act, n_act, nv, B.w.red, s);
+    }
+}
+
+bool use_graphs(const dda_ctx* c) {
+    return c->opt.use_graphs != 0 && c->stream != nullptr && !c->timing;
+}
+
+int status_of(int slot_status) {
+    switch (slot_status) {
+        case dda::SLOT_DONE: return DDA_OK;
+        case dda::SLOT_FAIL_NOCONV: return DDA_ENOCONV;
+        case dda::SLOT_FAIL_BREAKDOWN: return DDA_EBREAKDOWN;
+        case dda::SLOT_FAIL_INVALID: return DDA_EINVAL;
+        default: throw Error(DDA_EDEVICE, "COCG slot left in a non-terminal state");
+    }
+}
+
+dda_solve_info info_of(const dda::BicgSlot& S) {
+    const double rr = S.bnorm2 > 0 ? std::sqrt(S.rnorm2 / S.bnorm2) : 0.0;
+    return dda_solve_info{S.iters, S.matvecs, rr, status_of(S.status)};
+}
+
+// Solves every slot of a dda_solve chunk.
+template <typename T>
+void run_cocg(dda_ctx* c, int nslots, const CocgBufs<T>& B, double tol, int maxit,
+              std::vector<dda_solve_info>& info) {
     std::vector<int> act(nslots);
     for (int i = 0; i < nslots; ++i) act[i] = i;
     upload_act(c, act);
-    dda::bicg_norm_b<double>(b, st, dact, nslots, nv, tol * tol,
-                             mixed ? kUpdateDrop * kUpdateDrop : 0.0, maxit, red, s);
-    DDA_HIP_CHECK(hipMemsetAsync(x, 0, q128 * sizeof(z128), s));
-    if (mixed) DDA_HIP_CHECK(hipMemsetAsync(x_lo, 0, q128 * sizeof(z64), s));
-    DDA_HIP_CHECK(hipMemsetAsync(y64, 0, q128 * sizeof(z128), s));
-    dda::cocg_start<T>(b, y64, r, st, dact, nslots, nv, red, s);  // r = b
-
-    const int check = std::max(1, c->opt.check_every);
-    const dda::SlotFilter fchk{st, dda::FILTER_CHECK}, fact{st, dda::FILTER_ACTIVE};
-    dda::cx<T>* xs = mixed ? reinterpret_cast<dda::cx<T>*>(x_lo) : reinterpret_cast<dda::cx<T>*>(x);
-    auto interval = [&](int n_act) {
-        if (mixed) dda::accumulate_lo(x, x_lo, dact, n_act, nv, fchk, s);
-        matvec<double>(c, x, y64, dact, n_act, dptr64, slot_sys, ainv64, dda::PACK_AX, nullptr,
-                       fchk);
-        dda::cocg_check<T>(b, y64, r, st, dact, n_act, nv, kMaxRestarts, red, s);
-        for (int k = 0; k < check; ++k) {
-            matvec<T>(c, p, q, dact, n_act, dptr, slot_sys, ainv, dda::PACK_AX_COCG, r, fact);
-            dda::cocg_update_xr<T>(xs, r, p, q, st, dact, n_act, nv, red, s);
-        }
-    };
-    const bool graphs = c->opt.use_graphs != 0 && s != nullptr && !c->timing;
-    for (auto& e : c->ring_ev)
-        if (!e) DDA_HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    auto* ring = c->host_st.as<dda::BicgSlot>();
-    drop_graph(c);
+    cocg_init<T>(c, B, B.act, nslots, tol, maxit);
+    const bool graphs = use_graphs(c);
+    c->graph.drop();
     try {
         for (int64_t k = 0;; ++k) {
             if (k >= kLag) {
-                const int rk = int((k - kLag) % kRing);
-                wait_event(c->ring_ev[rk]);
-                const dda::BicgSlot* S = ring + size_t(rk) * c->slot_cap;
+                const dda::BicgSlot* S = c->ring.wait(k - kLag);
                 std::vector<int> next;
                 next.reserve(act.size());
                 for (int i : act)
@@ -803,39 +919,19 @@ void run_cocg(dda_ctx* c, int nslots, const z128* b, z128* x, dda::cx<T>* r, dda
                 }
             }
             const int n_act = int(act.size());
-            if (graphs) {
-                launch_captured(c, n_act, [&] { interval(n_act); });
-            } else {
-                interval(n_act);
-            }
-            const int wk = int(k % kRing);
-            DDA_HIP_CHECK(hipMemcpyAsync(ring + size_t(wk) * c->slot_cap, st,
-                                         size_t(nslots) * sizeof(dda::BicgSlot),
-                                         hipMemcpyDeviceToHost, s));
-            DDA_HIP_CHECK(hipEventRecord(c->ring_ev[wk], s));
+            if (graphs) launch_captured(c, c->graph, n_act, [&] { cocg_interval<T>(c, B, n_act); });
+            else cocg_interval<T>(c, B, n_act);
+            c->ring.snapshot(c->stream, B.w.st, nslots, k);
         }
     } catch (...) {
-        (void)hipStreamSynchronize(s);
-        drop_graph(c);
+        (void)hipStreamSynchronize(c->stream);
+        c->graph.drop();
         throw;
     }
-    drop_graph(c);  // the graph holds this chunk's buffer addresses
+    c->graph.drop();  // the graph holds this chunk's buffer addresses
     auto S = read_states(c, nslots);
-    status.assign(nslots, DDA_OK);
-    iters.assign(nslots, 0);
-    matvecs.assign(nslots, 0);
-    relres.assign(nslots, 0.0);
-    for (int i = 0; i < nslots; ++i) {
-        iters[i] = S[i].iters;
-        matvecs[i] = S[i].matvecs;
-        relres[i] = S[i].bnorm2 > 0 ? std::sqrt(S[i].rnorm2 / S[i].bnorm2) : 0.0;
-        switch (S[i].status) {
-            case dda::SLOT_DONE: status[i] = DDA_OK; break;
-            case dda::SLOT_FAIL_NOCONV: status[i] = DDA_ENOCONV; break;
-            case dda::SLOT_FAIL_BREAKDOWN: status[i] = DDA_EBREAKDOWN; break;
-            default: throw Error(DDA_EDEVICE, "COCG slot left in a non-terminal state");
-        }
-    }
+    info.resize(nslots);
+    for (int i = 0; i < nslots; ++i) info[i] = info_of(S[i]);
 }
 
 // Sizes of the per-slot work space, in bytes.
@@ -892,6 +988,260 @@ int systems_per_chunk(dda_ctx* c, int n_energy, int n_traj, bool mixed) {
     ns = std::min(ns, n_energy);
     ns = std::min(ns, std::max(1, 65535 / std::max(1, n_traj)));
     return std::max(ns, 1);
+}
+
+}  // namespace
+
+
+// ==================================================== continuous batching
+// A slot pool over one lattice.  Systems (one energy, one right-hand side)
+// are submitted at any time; between intervals the engine admits queued
+// systems into free slots (material terms, D from the context's cache,
+// initial state), runs the same device-driven COCG intervals as dda_solve
+// over every occupied slot, and harvests the slots whose lagged state
+// snapshot shows them finished (final iterate copied to the caller's buffer,
+// slot freed).  All its buffers are its own, so other calls on the context
+// (dda_eels_cl for finished requests) may run between polls.
+struct Pending {
+    int64_t tag;
+    double energy;
+    cplx mh;  // host index of the context when the system was submitted
+    std::vector<double> eps;  // [n_occ][2]
+    const z128* einc;
+    z128* out;
+};
+
+struct SlotRec {
+    bool busy = false;
+    int64_t tag = 0;
+    int64_t admitted = 0;  // first interval the system takes part in
+    DEntry* d = nullptr;
+    z128* out = nullptr;
+};
+
+struct Engine {
+    int cap = 0;
+    bool mixed = false;
+    DevBuf st, partial, slot_sys, G, b, x, r, p, q, xlo, y64, ainv128, ainv64, dtab, eps, msys, err;
+    PinnedBuf h_eps, h_small;        // staging of admitted permittivities and tables
+    hipEvent_t stage_ev = nullptr;   // the last copy out of the staging buffers
+    ActRing act, adm;                // interval list; list of slots being admitted
+    StateRing ring;
+    GraphCache graph;
+    std::vector<SlotRec> slots;
+    std::vector<const void*> dtab_h;  // [2][cap]: FP64 D pointers, then FP32
+    std::vector<int> running;         // occupied slots, sorted
+    bool act_dirty = true;
+    std::deque<Pending> queue;
+    std::mutex mu;  // guards queue: dda_engine_submit may run on another thread
+    int64_t sent = 0;  // intervals sent
+    std::deque<std::pair<int64_t, dda_solve_info>> done;
+    Engine() = default;
+    Engine(const Engine&) = delete;
+    ~Engine() {
+        if (stage_ev) (void)hipEventDestroy(stage_ev);
+    }
+};
+
+namespace {
+
+// Device bytes of one engine slot, counting the D of a distinct energy.
+size_t engine_slot_bytes(const dda_ctx* c, bool mixed) {
+    const size_t nv = size_t(c->nv()), n = size_t(c->g.n_occ);
+    const size_t ge = size_t(dda::grid_elems(c->g));
+    size_t b = 3 * nv * sizeof(z128);                                   // b, x, y64
+    b += mixed ? 4 * nv * sizeof(z64) : 3 * nv * sizeof(z128);          // r, p, q (x_lo)
+    b += n * (sizeof(z128) + (mixed ? sizeof(z64) : 0));                // 1/alpha
+    b += n * sizeof(z128);                                              // eps staging
+    b += ge * sizeof(z128);                                             // grid work buffer
+    b += size_t(c->max_blocks) * 8 * sizeof(double) + sizeof(dda::BicgSlot) + 64;
+    b += d_elems(c, 16) * sizeof(z128) + (mixed ? d_elems(c, 8) * sizeof(z64) : 0);
+    return b;
+}
+
+template <typename T>
+CocgBufs<T> engine_bufs(dda_ctx* c, Engine& E, const int* act) {
+    const size_t nv = size_t(c->nv());
+    const Work w{E.st.as<dda::BicgSlot>(), dda::RedScratch{E.partial.as<double>(), c->max_blocks},
+                 E.G.p};
+    auto** tab = reinterpret_cast<const void**>(E.dtab.p);
+    constexpr bool mixed = std::is_same<T, float>::value;
+    CocgBufs<T> B{w, act, E.slot_sys.as<int>(), E.b.as<z128>(), E.x.as<z128>(),
+                  nullptr, nullptr, nullptr, mixed ? E.xlo.as<z64>() : nullptr, E.y64.as<z128>(),
+                  nullptr, nullptr,
+                  reinterpret_cast<const z128* const*>(tab), E.ainv128.as<z128>()};
+    auto* R = static_cast<dda::cx<T>*>(E.r.p);
+    B.r = R;
+    B.p = R + nv * E.cap;
+    B.q = R + 2 * nv * E.cap;
+    if constexpr (mixed) {
+        B.dptr = reinterpret_cast<const z64* const*>(tab + E.cap);
+        B.ainv = E.ainv64.as<z64>();
+    } else {
+        B.dptr = reinterpret_cast<const z128* const*>(tab);
+        B.ainv = E.ainv128.as<z128>();
+    }
+    return B;
+}
+
+void engine_open(dda_ctx* c, int cap) {
+    if (c->opt.solver != DDA_SOLVER_COCG)
+        throw Error(DDA_EINVAL, "the batching engine runs the COCG solver");
+    if (c->g.n_occ == 0) throw Error(DDA_EINVAL, "the lattice has no dipoles");
+    if (cap < 1 || cap > 4096) throw Error(DDA_EINVAL, "max_slots must lie in [1, 4096]");
+    auto E = std::make_unique<Engine>();
+    E->cap = cap;
+    E->mixed = c->opt.precision == DDA_PREC_MIXED;
+    const size_t nv = size_t(c->nv()), n = size_t(c->g.n_occ), k = size_t(cap);
+    E->st.ensure(k * sizeof(dda::BicgSlot));
+    E->partial.ensure(k * c->max_blocks * 8 * sizeof(double));
+    E->slot_sys.ensure(k * sizeof(int));
+    E->G.ensure(k * size_t(dda::grid_elems(c->g)) * sizeof(z128));
+    E->b.ensure(k * nv * sizeof(z128));
+    E->x.ensure(k * nv * sizeof(z128));
+    E->y64.ensure(k * nv * sizeof(z128));
+    E->r.ensure(3 * k * nv * (E->mixed ? sizeof(z64) : sizeof(z128)));
+    if (E->mixed) E->xlo.ensure(k * nv * sizeof(z64));
+    E->ainv128.ensure(k * n * sizeof(z128));
+    if (E->mixed) E->ainv64.ensure(k * n * sizeof(z64));
+    E->dtab.ensure(2 * k * sizeof(void*));
+    E->eps.ensure(k * n * sizeof(z128));
+    E->msys.ensure(k * sizeof(dda::MatSys));
+    E->err.ensure(k * sizeof(int));
+    E->h_eps.ensure(k * n * sizeof(z128));
+    E->h_small.ensure(k * (sizeof(dda::MatSys) + 2 * sizeof(void*)));
+    DDA_HIP_CHECK(hipEventCreateWithFlags(&E->stage_ev, hipEventDisableTiming));
+    E->act.ensure(cap);
+    E->adm.ensure(cap);
+    E->ring.ensure(cap);
+    E->slots.resize(cap);
+    E->dtab_h.assign(2 * k, nullptr);
+    std::vector<int> ident(cap);
+    for (int i = 0; i < cap; ++i) ident[i] = i;
+    upload(c, E->slot_sys.p, ident.data(), k * sizeof(int));
+    // slot states start terminal: a snapshot of a never-used slot reads as free
+    std::vector<dda::BicgSlot> init(cap);
+    for (auto& S : init) {
+        std::memset(&S, 0, sizeof(S));
+        S.status = dda::SLOT_DONE;
+    }
+    upload(c, E->st.p, init.data(), k * sizeof(dda::BicgSlot));
+    c->engine = std::move(E);
+}
+
+void engine_release(dda_ctx* c, SlotRec& sr) {
+    if (sr.d) sr.d->refs -= 1;
+    sr = SlotRec{};
+    (void)c;
+}
+
+// Slots whose snapshot after interval j shows them finished.
+void engine_harvest(dda_ctx* c, Engine& E, int64_t j) {
+    const dda::BicgSlot* S = E.ring.wait(j);
+    const size_t nv = size_t(c->nv());
+    std::vector<int> keep;
+    keep.reserve(E.running.size());
+    for (int s : E.running) {
+        SlotRec& sr = E.slots[s];
+        if (sr.admitted <= j && dda::slot_terminal(S[s].status)) {
+            DDA_HIP_CHECK(hipMemcpyAsync(sr.out, E.x.as<z128>() + size_t(s) * nv,
+                                         nv * sizeof(z128), hipMemcpyDeviceToDevice, c->stream));
+            E.done.emplace_back(sr.tag, info_of(S[s]));
+            engine_release(c, sr);
+        } else {
+            keep.push_back(s);
+        }
+    }
+    if (keep.size() != E.running.size()) {
+        E.running.swap(keep);
+        E.act_dirty = true;
+    }
+}
+
+template <typename T>
+void engine_admit(dda_ctx* c, Engine& E) {
+    constexpr bool mixed = std::is_same<T, float>::value;
+    std::vector<int> free_slots;
+    for (int s = 0; s < E.cap; ++s)
+        if (!E.slots[s].busy) free_slots.push_back(s);
+    std::vector<Pending> take;
+    {
+        std::lock_guard<std::mutex> lk(E.mu);
+        while (!E.queue.empty() && take.size() < free_slots.size()) {
+            take.push_back(std::move(E.queue.front()));
+            E.queue.pop_front();
+        }
+    }
+    if (take.empty()) return;
+    const int na = int(take.size());
+    const size_t n = size_t(c->g.n_occ), nv = size_t(c->nv());
+    wait_event(E.stage_ev);  // the previous admission's copies have run
+    auto* heps = E.h_eps.as<double>();
+    auto* hsys = E.h_small.as<dda::MatSys>();
+    auto** htab = reinterpret_cast<const void**>(hsys + E.cap);
+    std::vector<int> adm(na);
+    c->pin_clock = c->use_clock + 1;
+    for (int i = 0; i < na; ++i) {
+        const int s = free_slots[i];
+        adm[i] = s;
+        Pending& pd = take[i];
+        DEntry* d = get_D_k(c, pd.mh * (pd.energy / kHbarC), mixed);
+        d->refs += 1;
+        SlotRec& sr = E.slots[s];
+        sr.busy = true;
+        sr.tag = pd.tag;
+        sr.admitted = E.sent;
+        sr.d = d;
+        sr.out = pd.out;
+        E.dtab_h[s] = d->d128.p;
+        E.dtab_h[E.cap + s] = mixed ? d->d64.p : nullptr;
+        std::memcpy(heps + 2 * n * size_t(i), pd.eps.data(), n * sizeof(z128));
+        const cplx k = pd.mh * (pd.energy / kHbarC);
+        hsys[i] = dda::MatSys{k.real(), k.imag(), pd.mh.real(), pd.mh.imag()};
+        DDA_HIP_CHECK(hipMemcpyAsync(E.b.as<z128>() + size_t(s) * nv, pd.einc, nv * sizeof(z128),
+                                     hipMemcpyDeviceToDevice, c->stream));
+    }
+    std::memcpy(htab, E.dtab_h.data(), E.dtab_h.size() * sizeof(void*));
+    hipStream_t st = c->stream;
+    DDA_HIP_CHECK(hipMemcpyAsync(E.eps.p, heps, size_t(na) * n * sizeof(z128),
+                                 hipMemcpyHostToDevice, st));
+    DDA_HIP_CHECK(hipMemcpyAsync(E.msys.p, hsys, size_t(na) * sizeof(dda::MatSys),
+                                 hipMemcpyHostToDevice, st));
+    DDA_HIP_CHECK(hipMemcpyAsync(E.dtab.p, htab, E.dtab_h.size() * sizeof(void*),
+                                 hipMemcpyHostToDevice, st));
+    DDA_HIP_CHECK(hipEventRecord(E.stage_ev, st));
+    E.adm.upload(st, adm);
+    DDA_HIP_CHECK(hipMemsetAsync(E.err.p, 0, size_t(na) * sizeof(int), st));
+    const dda::MatParams mp{c->opt.polarizability, c->d};
+    dda::launch_material(E.eps.as<z128>(), E.msys.as<dda::MatSys>(), int64_t(n), na, mp,
+                         E.adm.ptr(), E.ainv128.as<z128>(), mixed ? E.ainv64.as<z64>() : nullptr,
+                         nullptr, E.err.as<int>(), st);
+    const auto B = engine_bufs<T>(c, E, E.adm.ptr());
+    cocg_init<T>(c, B, E.adm.ptr(), na, c->opt.tol, c->opt.maxit);
+    dda::mark_invalid(B.w.st, E.adm.ptr(), E.err.as<int>(), na, st);
+    E.running.insert(E.running.end(), adm.begin(), adm.end());
+    std::sort(E.running.begin(), E.running.end());
+    E.act_dirty = true;
+}
+
+template <typename T>
+void engine_poll(dda_ctx* c, Engine& E, int max_intervals) {
+    const auto B = engine_bufs<T>(c, E, E.act.ptr());
+    const bool graphs = use_graphs(c);
+    for (int it = 0; it < max_intervals; ++it) {
+        if (E.sent >= kLag && !E.running.empty()) engine_harvest(c, E, E.sent - kLag);
+        engine_admit<T>(c, E);
+        if (E.running.empty()) break;
+        if (E.act_dirty) {
+            E.act.upload(c->stream, E.running);
+            E.act_dirty = false;
+        }
+        const int n_act = int(E.running.size());
+        if (graphs) launch_captured(c, E.graph, n_act, [&] { cocg_interval<T>(c, B, n_act); });
+        else cocg_interval<T>(c, B, n_act);
+        E.ring.snapshot(c->stream, B.w.st, E.cap, E.sent);
+        E.sent += 1;
+    }
 }
 
 }  // namespace
@@ -1004,6 +1354,18 @@ int dda_setup(const uint8_t* mask, int nx, int ny, int nz, double d_nm, double m
     DDA_API_END
 }
 
+int dda_set_host(dda_ctx* c, double mh_re, double mh_im) {
+    DDA_API_BEGIN
+    if (!c) throw Error(DDA_EINVAL, "ctx is NULL");
+    check_finite(mh_re, "Re m_h");
+    check_finite(mh_im, "Im m_h");
+    if (!(mh_re > 0.0) || mh_im < 0.0)
+        throw Error(DDA_EINVAL, "host must be passive: Re m_h > 0, Im m_h >= 0");
+    c->mh = cplx(mh_re, mh_im);
+    return DDA_OK;
+    DDA_API_END
+}
+
 int dda_n_occ(const dda_ctx* ctx, int64_t* n_occ) {
     if (!ctx || !n_occ) { g_last_error = "NULL argument"; return DDA_EINVAL; }
     *n_occ = ctx->g.n_occ;
@@ -1087,21 +1449,29 @@ int dda_solve(dda_ctx* c, int n_energy, const double* energy_eV, const double* e
         const size_t q = size_t(nslots) * nv;
         if (c->opt.solver == DDA_SOLVER_COCG) {
             auto dptr64 = upload_dptrs<double>(c, ents);
+            std::vector<dda_solve_info> inf;
             if (!mixed) {
                 c->vec128.ensure(4 * q * sizeof(z128));
                 auto* V = c->vec128.as<z128>();
-                run_cocg<double>(c, nslots, b, x, V, V + q, V + 2 * q, nullptr, V + 3 * q, dptr64,
-                                 c->ainv128.as<z128>(), dptr64, c->ainv128.as<z128>(), c->opt.tol,
-                                 c->opt.maxit, iters, mvs, status, relres);
+                CocgBufs<double> B{ctx_work(c), c->act.ptr(), c->slot_sys.as<int>(), b, x, V,
+                                   V + q, V + 2 * q, nullptr, V + 3 * q, dptr64,
+                                   c->ainv128.as<z128>(), dptr64, c->ainv128.as<z128>()};
+                run_cocg<double>(c, nslots, B, c->opt.tol, c->opt.maxit, inf);
             } else {
                 c->vec128.ensure(q * sizeof(z128));
                 c->vec64.ensure(4 * q * sizeof(z64));
                 auto* U = c->vec64.as<z64>();
                 auto dptr32 = upload_dptrs<float>(c, ents);
-                run_cocg<float>(c, nslots, b, x, U, U + q, U + 2 * q, U + 3 * q,
-                                c->vec128.as<z128>(), dptr32, c->ainv64.as<z64>(), dptr64,
-                                c->ainv128.as<z128>(), c->opt.tol, c->opt.maxit, iters, mvs,
-                                status, relres);
+                CocgBufs<float> B{ctx_work(c), c->act.ptr(), c->slot_sys.as<int>(), b, x, U,
+                                  U + q, U + 2 * q, U + 3 * q, c->vec128.as<z128>(), dptr32,
+                                  c->ainv64.as<z64>(), dptr64, c->ainv128.as<z128>()};
+                run_cocg<float>(c, nslots, B, c->opt.tol, c->opt.maxit, inf);
+            }
+            for (const auto& i : inf) {
+                iters.push_back(i.iters);
+                mvs.push_back(i.matvecs);
+                relres.push_back(i.rel_residual);
+                status.push_back(i.status);
             }
         } else if (!mixed) {
             c->vec128.ensure(size_t(6) * q * sizeof(z128));
@@ -1251,6 +1621,88 @@ int dda_matvec(dda_ctx* c, double energy_eV, const double* eps_dipole, int preci
     DDA_API_END
 }
 
+int dda_workspace_bytes(const dda_ctx* c, int n_slots, size_t* bytes) {
+    DDA_API_BEGIN
+    if (!c || !bytes) throw Error(DDA_EINVAL, "NULL argument");
+    if (n_slots < 0) throw Error(DDA_EINVAL, "n_slots < 0");
+    *bytes = size_t(n_slots) * engine_slot_bytes(c, c->opt.precision == DDA_PREC_MIXED);
+    return DDA_OK;
+    DDA_API_END
+}
+
+int dda_engine_open(dda_ctx* c, int max_slots) {
+    DDA_API_BEGIN
+    if (!c) throw Error(DDA_EINVAL, "ctx is NULL");
+    if (c->engine) throw Error(DDA_EINVAL, "an engine is already open on this context");
+    engine_open(c, max_slots);
+    return DDA_OK;
+    DDA_API_END
+}
+
+int dda_engine_submit(dda_ctx* c, int64_t tag, double energy_eV, const double* eps_dipole,
+                      const void* einc_dev, void* p_dev) {
+    DDA_API_BEGIN
+    if (!c || !c->engine) throw Error(DDA_EINVAL, "no engine open on this context");
+    if (!eps_dipole || !einc_dev || !p_dev) throw Error(DDA_EINVAL, "NULL argument");
+    check_energies(1, &energy_eV);
+    const size_t n = size_t(c->g.n_occ);
+    Pending pd{tag, energy_eV, c->mh, std::vector<double>(eps_dipole, eps_dipole + 2 * n),
+               static_cast<const z128*>(einc_dev), static_cast<z128*>(p_dev)};
+    for (double v : pd.eps)
+        if (!std::isfinite(v)) throw Error(DDA_EINVAL, "permittivity is not finite");
+    std::lock_guard<std::mutex> lk(c->engine->mu);
+    c->engine->queue.push_back(std::move(pd));
+    return DDA_OK;
+    DDA_API_END
+}
+
+int dda_engine_poll(dda_ctx* c, int max_intervals, int64_t* tags, dda_solve_info* info,
+                    int capacity, int* n_done) {
+    DDA_API_BEGIN
+    if (!c || !c->engine) throw Error(DDA_EINVAL, "no engine open on this context");
+    if (!n_done || (capacity > 0 && (!tags || !info)) || capacity < 0 || max_intervals < 0)
+        throw Error(DDA_EINVAL, "bad arguments");
+    Engine& E = *c->engine;
+    if (E.mixed) engine_poll<float>(c, E, max_intervals);
+    else engine_poll<double>(c, E, max_intervals);
+    int k = 0;
+    while (k < capacity && !E.done.empty()) {
+        tags[k] = E.done.front().first;
+        info[k] = E.done.front().second;
+        E.done.pop_front();
+        ++k;
+    }
+    *n_done = k;
+    return DDA_OK;
+    DDA_API_END
+}
+
+int dda_engine_status(dda_ctx* c, int* queued, int* running, int* finished) {
+    DDA_API_BEGIN
+    if (!c || !c->engine || !queued || !running || !finished)
+        throw Error(DDA_EINVAL, "bad arguments");
+    Engine& E = *c->engine;
+    {
+        std::lock_guard<std::mutex> lk(E.mu);
+        *queued = int(E.queue.size());
+    }
+    *running = int(E.running.size());
+    *finished = int(E.done.size());
+    return DDA_OK;
+    DDA_API_END
+}
+
+int dda_engine_close(dda_ctx* c) {
+    DDA_API_BEGIN
+    if (!c) throw Error(DDA_EINVAL, "ctx is NULL");
+    if (!c->engine) return DDA_OK;
+    DDA_HIP_CHECK(hipStreamSynchronize(c->stream));
+    for (auto& sr : c->engine->slots) engine_release(c, sr);
+    c->engine.reset();
+    return DDA_OK;
+    DDA_API_END
+}
+
 int dda_set_timing(dda_ctx* c, int enabled) {
     DDA_API_BEGIN
     if (!c) throw Error(DDA_EINVAL, "ctx is NULL");
@@ -1299,9 +1751,9 @@ int dda_destroy(dda_ctx* c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     else (void)hipDeviceSynchronize();
     if (c->sync_ev) (void)hipEventDestroy(c->sync_ev);
-    for (auto e : c->act_ev) if (e) (void)hipEventDestroy(e);
-    for (auto e : c->ring_ev) if (e) (void)hipEventDestroy(e);
-    drop_graph(c);
+    if (c->engine)
+        for (auto& sr : c->engine->slots) engine_release(c, sr);
+    c->engine.reset();
     delete c;
     return DDA_OK;
     DDA_API_END

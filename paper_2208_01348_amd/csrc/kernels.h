@@ -103,21 +103,23 @@ void launch_einc(z128* einc, const int* occ_lin, const Geo& g, double d, double 
                  int n_energy, int n_traj, hipStream_t s);
 
 // Material terms (material.hip), FP64: for system s < ns and dipole i < n,
-// from eps[s][i] (absolute permittivity) and the host wavenumber sys[s].k,
-// 1/alpha into ainv128[s][i] (and rounded into ainv64) and the absorption
-// weight into w[s][i]; any output may be NULL.  err[0] becomes non-zero for a
-// non-finite permittivity (1) or a zero or infinite polarizability (2); the
-// caller clears it first.
+// from eps[s][i] (absolute permittivity), the host index sys[s].mh and the
+// host wavenumber sys[s].k,
+// 1/alpha into ainv128[o][i] (and rounded into ainv64) and the absorption
+// weight into w[o][i], with o = out_row[s] (o = s when out_row is NULL); any
+// output may be NULL.  err[s] becomes non-zero for a non-finite permittivity
+// (1) or a zero or infinite polarizability (2); the caller clears err[0..ns).
 struct MatSys {
-    double k_re, k_im;
+    double k_re, k_im;    // m_h omega / c
+    double mh_re, mh_im;  // host index (Im m_h == 0: radiative-reaction form of w)
 };
 struct MatParams {
-    int kind;       // 0 LDR, 1 CM, 2 RR
-    int real_host;  // Im m_h == 0: radiative-reaction form of the weight
-    double mh_re, mh_im, d;
+    int kind;  // 0 LDR, 1 CM, 2 RR
+    double d;
 };
 void launch_material(const z128* eps, const MatSys* sys, int64_t n, int ns, MatParams mp,
-                     z128* ainv128, z64* ainv64, double* w, int* err, hipStream_t s);
+                     const int* out_row, z128* ainv128, z64* ainv64, double* w, int* err,
+                     hipStream_t s);
 
 // Debug/test helper: K0, K1 at n complex points (device arrays).
 void launch_besselk01(const z128* z, z128* k0, z128* k1, int64_t n, hipStream_t s);

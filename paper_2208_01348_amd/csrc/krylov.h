@@ -55,8 +55,8 @@ void cocg_alpha_finalize(BicgSlot* st, const int* act, int n_act, RedScratch red
 template <typename T>
 void cocg_update_xr(cx<T>* x, cx<T>* r, const cx<T>* p, const cx<T>* q, BicgSlot* st,
                     const int* act, int n_act, int64_t nv, RedScratch red, hipStream_t s);
-// FP64 residual passes: r = b - y (FP64), r_lo = r rounded to T, rho =
-// r_lo^T r_lo, rnorm2 = rmax2 = ||r||^2.
+// FP64 residual passes: r = b - y (FP64; y == NULL stands for 0), r_lo = r
+// rounded to T, rho = r_lo^T r_lo, rnorm2 = rmax2 = ||r||^2.
 //   cocg_start: every listed slot, from x0 = 0 (y = 0); p = r on the first
 //     direction update; SLOT_DONE if b already meets the tolerance.
 //   cocg_check: only slots with needs_check(); decides SLOT_DONE,
@@ -68,6 +68,10 @@ void cocg_start(const z128* b, const z128* y, cx<T>* r_lo, BicgSlot* st, const i
 template <typename T>
 void cocg_check(const z128* b, const z128* y, cx<T>* r_lo, BicgSlot* st, const int* act,
                 int n_act, int64_t nv, int max_restarts, RedScratch red, hipStream_t s);
+// x = 0 and x_lo = 0 (if not NULL) on the listed slots
+void cocg_zero(z128* x, z64* x_lo, const int* act, int n_act, int64_t nv, hipStream_t s);
+// slot act[i] becomes SLOT_FAIL_INVALID where err[i] != 0 (i < n)
+void mark_invalid(BicgSlot* st, const int* act, const int* err, int n, hipStream_t s);
 // x64 += x_lo; x_lo = 0 (slots the filter accepts)
 void accumulate_lo(z128* x, z64* x_lo, const int* act, int n_act, int64_t nv, SlotFilter f,
                    hipStream_t s);

@@ -385,7 +385,7 @@ __global__ __launch_bounds__(NT) void k_true_residual(const z128* __restrict__ b
     if (!slot_live(f, slot)) return;
     double s[3] = {0.0, 0.0, 0.0};
     for (int64_t i = i0; i < nv; i += stride) {
-        const z128 ri = b[base + i] - y[base + i];
+        const z128 ri = y ? b[base + i] - y[base + i] : b[base + i];
         const cx<T> rl = cvt<T>(ri);
         r_lo[base + i] = rl;
         acc_bdot(s[0], s[1], rl, rl);
@@ -404,8 +404,18 @@ __global__ __launch_bounds__(NT) void k_fin_cocg_start(BicgSlot* st, const int* 
     S.rmax2 = tot[2];
     S.want_update = 0;
     S.reset_p = 1;
+    S.best2 = tot[2];
+    S.stall = 0;
     S.status = (tot[2] <= S.tol2 * S.bnorm2) ? SLOT_DONE : SLOT_ACTIVE;
 }
+
+// Mixed precision: the recursion runs on the FP32 operator, and near a
+// resonance (large condition number) its directions can lose conjugacy with
+// respect to the FP64 one; the FP64 residual then stalls while the recursive
+// one keeps falling.  A slot whose FP64 residual has not halved over
+// kStallChecks checks restarts its recursion from the FP64 residual.
+constexpr double kStallDrop = 0.5;
+constexpr int kStallChecks = 3;
 
 // FP64 residual check of a slot that asked for one (needs_check): the FP64
 // residual decides convergence; otherwise the iteration limit ends the slot, a
@@ -439,9 +449,35 @@ __global__ __launch_bounds__(NT) void k_fin_check(BicgSlot* st, const int* act, 
         S.restarts += 1;
         S.reset_p = 1;
         S.beta = z128{0.0, 0.0};
+    } else if (S.upd2 > 0.0) {
+        if (tot[2] < kStallDrop * S.best2) {
+            S.best2 = tot[2];
+            S.stall = 0;
+        } else if (++S.stall >= kStallChecks) {
+            S.stall = 0;
+            S.best2 = tot[2];
+            S.reset_p = 1;
+            S.beta = z128{0.0, 0.0};
+        }
     }
     S.rho = z128{tot[0], tot[1]};
     S.status = SLOT_ACTIVE;
+}
+
+__global__ __launch_bounds__(NT) void k_cocg_zero(z128* __restrict__ x, z64* __restrict__ x_lo,
+                                                  const int* __restrict__ act, int64_t nv) {
+    SLOT_PROLOGUE
+    for (int64_t i = i0; i < nv; i += stride) {
+        x[base + i] = z128{0.0, 0.0};
+        if (x_lo) x_lo[base + i] = z64{0.f, 0.f};
+    }
+}
+
+// err[i] != 0 (per listed position) ends slot act[i] as invalid.
+__global__ __launch_bounds__(NT) void k_mark_invalid(BicgSlot* st, const int* __restrict__ act,
+                                                     const int* __restrict__ err, int n) {
+    const int i = blockIdx.x * NT + threadIdx.x;
+    if (i < n && err[i] != 0) st[act[i]].status = SLOT_FAIL_INVALID;
 }
 
 __global__ __launch_bounds__(NT) void k_accumulate_lo(z128* __restrict__ x, z64* __restrict__ x_lo,
@@ -633,6 +669,17 @@ void cocg_check(const z128* b, const z128* y, cx<T>* r_lo, BicgSlot* st, const i
                                                SlotFilter{st, FILTER_CHECK}, red);
     DDA_LAUNCH_CHECK();
     FIN(k_fin_check, max_restarts);
+}
+void cocg_zero(z128* x, z64* x_lo, const int* act, int n_act, int64_t nv, hipStream_t s) {
+    if (n_act == 0) return;
+    dim3 grid(blocks_for(nv, 1 << 20), n_act);
+    k_cocg_zero<<<grid, NT, 0, s>>>(x, x_lo, act, nv);
+    DDA_LAUNCH_CHECK();
+}
+void mark_invalid(BicgSlot* st, const int* act, const int* err, int n, hipStream_t s) {
+    if (n == 0) return;
+    k_mark_invalid<<<(n + NT - 1) / NT, NT, 0, s>>>(st, act, err, n);
+    DDA_LAUNCH_CHECK();
 }
 void accumulate_lo(z128* x, z64* x_lo, const int* act, int n_act, int64_t nv, SlotFilter f,
                    hipStream_t s) {

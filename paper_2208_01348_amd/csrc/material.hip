@@ -8,10 +8,12 @@
 //   RR:  alpha_CM / (1 - (2/3) i k^3 alpha_CM)
 //   LDR: alpha_CM / (1 + (alpha_CM/d^3) [(b1 + m^2 b2) (kd)^2 - (2/3) i (kd)^3])
 //        (Draine & Goodman 1993 with S = 0 for propagation along z)
-// with k = m_h omega/c the host wavenumber.
+// with k = m_h omega/c the host wavenumber; m_h and k are per system.
 // Absorption weights w_i, used as P_abs ~ sum_i w_i |p_i|^2:
 //   real host:    w = -Im(1/alpha) - (2/3) k^3   (radiative part removed)
 //   complex host: w = 4 pi Im(m_h^2 m^2) / (|m^2 - 1|^2 d^3)   (eq. 18)
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace dda {
@@ -34,17 +36,20 @@ constexpr double kB1 = -1.8915316, kB2 = 0.1648469;
 __global__ __launch_bounds__(256) void k_material(const z128* __restrict__ eps,
                                                   const MatSys* __restrict__ sys, int64_t n,
                                                   int64_t total, MatParams mp,
+                                                  const int* __restrict__ out_row,
                                                   z128* __restrict__ ainv128,
                                                   z64* __restrict__ ainv64,
                                                   double* __restrict__ w, int* __restrict__ err) {
-    const z128 mh2 = z128{mp.mh_re, mp.mh_im} * z128{mp.mh_re, mp.mh_im};
     const double d3 = mp.d * mp.d * mp.d;
     for (int64_t t = blockIdx.x * int64_t(256) + threadIdx.x; t < total;
          t += int64_t(gridDim.x) * 256) {
         const int64_t s = t / n;
+        const z128 mh{sys[s].mh_re, sys[s].mh_im};
+        const z128 mh2 = mh * mh;
+        const int64_t o = out_row ? int64_t(out_row[s]) * n + (t - s * n) : t;
         const z128 ep = eps[t];
         if (!isfinite(ep.x) || !isfinite(ep.y)) {
-            err[0] = 1;  // non-finite permittivity
+            err[s] = 1;  // non-finite permittivity
             continue;
         }
         const z128 m2 = cdiv(ep, mh2);
@@ -64,19 +69,19 @@ __global__ __launch_bounds__(256) void k_material(const z128* __restrict__ eps,
         }
         const double an = a.x * a.x + a.y * a.y;
         if (!(an > 0.0) || !isfinite(an)) {
-            err[0] = 2;  // zero or infinite polarizability
+            err[s] = 2;  // zero or infinite polarizability
             continue;
         }
         const z128 ai = cdiv(one, a);
-        if (ainv128) ainv128[t] = ai;
-        if (ainv64) ainv64[t] = cvt<float>(ai);
+        if (ainv128) ainv128[o] = ai;
+        if (ainv64) ainv64[o] = cvt<float>(ai);
         if (w) {
-            if (mp.real_host) {
+            if (mh.y == 0.0) {
                 const double kr = k.x;
-                w[t] = -ai.y - (2.0 / 3.0) * kr * kr * kr;
+                w[o] = -ai.y - (2.0 / 3.0) * kr * kr * kr;
             } else {
                 const z128 dm = m2 - one;
-                w[t] = 4.0 * kPi * (mh2 * m2).y / ((dm.x * dm.x + dm.y * dm.y) * d3);
+                w[o] = 4.0 * kPi * (mh2 * m2).y / ((dm.x * dm.x + dm.y * dm.y) * d3);
             }
         }
     }
@@ -85,11 +90,12 @@ __global__ __launch_bounds__(256) void k_material(const z128* __restrict__ eps,
 }  // namespace
 
 void launch_material(const z128* eps, const MatSys* sys, int64_t n, int ns, MatParams mp,
-                     z128* ainv128, z64* ainv64, double* w, int* err, hipStream_t s) {
+                     const int* out_row, z128* ainv128, z64* ainv64, double* w, int* err,
+                     hipStream_t s) {
     const int64_t total = n * ns;
     if (total == 0) return;
     const unsigned b = unsigned(std::min<int64_t>((total + 255) / 256, 8192));
-    k_material<<<b, 256, 0, s>>>(eps, sys, n, total, mp, ainv128, ainv64, w, err);
+    k_material<<<b, 256, 0, s>>>(eps, sys, n, total, mp, out_row, ainv128, ainv64, w, err);
     DDA_LAUNCH_CHECK();
 }
 

@@ -17,6 +17,7 @@ enum SlotStatus : int {
     SLOT_DONE = 5,              // the FP64 residual met the tolerance
     SLOT_FAIL_NOCONV = 6,       // iteration limit reached above the tolerance
     SLOT_FAIL_BREAKDOWN = 7,    // breakdowns beyond the restart budget
+    SLOT_FAIL_INVALID = 8,      // the system's permittivity was rejected
 };
 
 struct BicgSlot {
@@ -27,6 +28,7 @@ struct BicgSlot {
     double bnorm2;                    // ||b||^2
     double rnorm2;                    // ||r||^2 (recursive, or true after a residual pass)
     double rmax2;                     // largest ||r||^2 since the last FP64 residual
+    double best2;                     // smallest FP64 ||r||^2 of the mixed-precision checks
     double tol2;                      // tol^2
     double upd2;                      // reliable update when rnorm2 < upd2 * rmax2 (0: never)
     int status;
@@ -36,7 +38,7 @@ struct BicgSlot {
     int restarts;                     // breakdown restarts so far
     int reset_p;                      // COCG: the next direction update takes p = r
     int maxit;                        // iteration limit
-    int pad_;
+    int stall;                        // FP64 checks since best2 last halved
 };
 
 __host__ __device__ inline bool slot_terminal(int status) { return status >= SLOT_DONE; }

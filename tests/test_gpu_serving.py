@@ -1,0 +1,143 @@
+"""Continuous batching on the GPU: systems admitted into the engine's slots
+while others iterate give the same iterates as a dda_solve of each system
+alone, and served requests give the same loss probabilities as a spectrum
+solved alone (the stated bar is 1e-5 relative for the mixed path and 1e-9
+for FP64; the arithmetic of a slot does not depend on its neighbours, so
+the results agree to the last bit)."""
+
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from paper_2208_01348_amd import _lib as L
+from paper_2208_01348_amd.serving import Request, Server, replay
+from paper_2208_01348_amd.solver import DDASolver
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def _rod():
+    return W.capped_rod_mask(12, 6, 6, 2.0, 6.0, 24.0), 2.0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_engine_admits_midway_and_matches_solve_alone(precision):
+    say("engine vs solve alone", precision)
+    mask, d = _rod()
+    n = int(mask.sum())
+    E = np.linspace(1.4, 2.8, 6)
+    eps_t = W.drude_eps(E)
+    r0 = np.array([[16.0, 1.0, 0.0]])
+    opts = dict(tol=1e-11, maxit=20000, solver="cocg", precision=precision, check_every=4)
+    ref = DDASolver(mask, d, 1.45, **opts)
+    e = ref.einc(E, 0.55, r0)
+    p_ref, info_ref = [], []
+    for i in range(E.size):
+        p, info, st = ref.solve([E[i]], np.full((1, n), eps_t[i]), e[i:i + 1], 1)
+        assert st == L.DDA_OK
+        p_ref.append(p.cpu().numpy())
+        info_ref.append((info[0].iters, info[0].matvecs, info[0].status))
+    srv = DDASolver(mask, d, 1.45, **opts)
+    L.dda_engine_open(srv.ctx, 4)  # fewer slots than systems: some wait for a free slot
+    e2 = srv.einc(E, 0.55, r0)
+    p2 = torch.zeros_like(e2)
+    stride = 16 * 3 * n
+    for i in range(3):
+        L.dda_engine_submit(srv.ctx, i, float(E[i]), np.full(n, eps_t[i]),
+                            e2.data_ptr() + stride * i, p2.data_ptr() + stride * i)
+    got = {}
+    for _ in range(3):  # the first systems are halfway when the others arrive
+        for tag, inf in L.dda_engine_poll(srv.ctx, 2):
+            got[tag] = inf
+    for i in range(3, E.size):
+        L.dda_engine_submit(srv.ctx, i, float(E[i]), np.full(n, eps_t[i]),
+                            e2.data_ptr() + stride * i, p2.data_ptr() + stride * i)
+    for _ in range(100000):
+        for tag, inf in L.dda_engine_poll(srv.ctx, 8):
+            got[tag] = inf
+        if len(got) == E.size:
+            break
+    assert sorted(got) == list(range(E.size))
+    assert L.dda_engine_status(srv.ctx) == (0, 0, 0)
+    torch.cuda.synchronize()
+    P2 = p2.cpu().numpy()
+    for i in range(E.size):
+        assert (got[i][0], got[i][1], got[i][3]) == info_ref[i], i
+        assert np.array_equal(P2[i], p_ref[i][0]), i
+    L.dda_engine_close(srv.ctx)
+    srv.close()
+    ref.close()
+
+
+def test_engine_reports_a_rejected_permittivity_per_system():
+    mask, d = _rod()
+    n = int(mask.sum())
+    s = DDASolver(mask, d, 1.45, tol=1e-10, solver="cocg", precision="mixed")
+    L.dda_engine_open(s.ctx, 2)
+    e = s.einc([2.0, 2.2], 0.55, np.array([[16.0, 1.0, 0.0]]))
+    p = torch.zeros_like(e)
+    stride = 16 * 3 * n
+    # eps = m_h^2: the dipoles match the host and alpha vanishes
+    L.dda_engine_submit(s.ctx, 7, 2.0, np.full(n, 1.45 ** 2 + 0j), e.data_ptr(), p.data_ptr())
+    L.dda_engine_submit(s.ctx, 8, 2.2, np.full(n, -10 + 1j), e.data_ptr() + stride,
+                        p.data_ptr() + stride)
+    with pytest.raises(L.DDAError):
+        L.dda_engine_submit(s.ctx, 9, 2.2, np.full(n, np.nan + 0j), e.data_ptr(), p.data_ptr())
+    got = {}
+    for _ in range(100000):
+        for tag, inf in L.dda_engine_poll(s.ctx, 8):
+            got[tag] = inf
+        if len(got) == 2:
+            break
+    assert got[7][3] == L.DDA_EINVAL
+    assert got[8][3] == L.DDA_OK
+    L.dda_engine_close(s.ctx)
+    s.close()
+
+
+def _requests():
+    rod, d_rod = _rod()
+    sph = W.sphere_mask(8, 1.5, 5.5)
+    specs = [  # lattice, d, m_h, beta, n_E, r0
+        (rod, d_rod, 1.45 + 0j, 0.55, 5, (16.0, 1.0, 0.0)),
+        (sph, 1.5, 1.0 + 0j, 0.6, 4, (8.0, 0.5, 0.0)),
+        (rod, d_rod, 1.30 + 0j, 0.45, 3, (15.0, -1.0, 0.0)),
+        (rod, d_rod, 2.0 + 0.01j, 0.7, 4, (16.0, 1.0, 0.0)),  # absorbing Cherenkov host
+        (sph, 1.5, 1.45 + 0j, 0.55, 6, (7.5, 0.0, 0.0)),
+        (rod, d_rod, 1.45 + 0j, 0.55, 5, (17.0, 2.0, 0.0)),
+    ]
+    out = []
+    for i, (m, d, mh, b, ne, r0) in enumerate(specs):
+        E = np.linspace(1.2 + 0.1 * i, 3.0, ne)
+        out.append(Request(rid=i, arrival=0.03 * i, mask=m, d=d, m_h=mh, beta=b, energies=E,
+                           eps=W.drude_eps(E), r0=np.array(r0)))
+    return out
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_served_requests_equal_their_spectra_alone(precision):
+    say("serving mix vs alone", precision)
+    reqs = _requests()
+    opts = dict(precision=precision, tol=1e-10, maxit=20000, check_every=4)
+    srv = Server(hbm_budget_bytes=64 << 30, slots=8, **opts)
+    comps, lat, span = replay(srv, reqs, timeout_s=240)
+    srv.close()
+    assert len(comps) == len(reqs)
+    say(f"served {len(reqs)} requests in {span:.2f} s; latencies "
+        + " ".join(f"{lat[c.rid]:.3f}" for c in comps))
+    for c in comps:
+        r = reqs[c.rid]
+        assert all(i[3] == L.DDA_OK for i in c.info), c.info
+        alone = DDASolver(r.mask, r.d, r.m_h, solver="cocg", precision=opts["precision"],
+                          tol=opts["tol"], maxit=opts["maxit"], check_every=opts["check_every"])
+        n = alone.n_occ
+        P, info = alone.spectrum(r.energies, r.beta, np.repeat(r.eps[:, None], n, axis=1),
+                                 r.r0.reshape(1, 3))
+        alone.close()
+        assert [i.iters for i in info] == [i[0] for i in c.info], c.rid
+        assert np.allclose(c.P, P, rtol=1e-13, atol=0), (c.rid, c.P, P)
