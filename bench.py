@@ -109,6 +109,12 @@ def main():
                          "HIP graphs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=12,
+                    help="requests of the seeded serving stream to replay (0: skip)")
+    ap.add_argument("--c4-energies", type=int, default=2,
+                    help="energies of the impact-map workload (x 256 impacts; 0: skip)")
+    ap.add_argument("--c3-energies", type=int, default=2,
+                    help="energies of the Cherenkov 64^3 workload (x 2 trajectories; 0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 256 MiB device copy (for scaling rocprofv3 "
                          "FETCH_SIZE/WRITE_SIZE counters)")
@@ -201,6 +207,14 @@ def main():
     extras = {}
     if not args.no_extras:
         extras = measure_extras(torch, W, DDASolver, log)
+        if args.serve_requests > 0:
+            extras["serving_c5"] = measure_serving(torch, W, DDASolver, args.serve_requests, log)
+        if args.c4_energies > 0:
+            extras["impact_map_c4"] = measure_batch(torch, W, DDASolver, "c4",
+                                                    args.c4_energies, log)
+        if args.c3_energies > 0:
+            extras["cherenkov_c3"] = measure_batch(torch, W, DDASolver, "c3",
+                                                   args.c3_energies, log)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -293,9 +307,100 @@ def measure_extras(torch, W, DDASolver, log):
     s1.close()
     res["solve_latency_c1_ms"] = {"p50": round(1e3 * float(np.percentile(lat, 50)), 3),
                                   "p99": round(1e3 * float(np.percentile(lat, 99)), 3),
-                                  "solves": len(lat), "precision": "fp64"}
+                                  "solves": len(lat), "precision": "fp64", "solver": "bicgstab"}
     log(f"c1 latency p50 {res['solve_latency_c1_ms']['p50']} ms")
+    # the same solve with FP64 COCG (device-driven intervals, captured graphs)
+    s1 = DDASolver(w1.mask, w1.d, w1.m_h, tol=w1.tol, solver="cocg", check_every=8)
+    lat = []
+    for i in range(11):
+        s1.drop_cache()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        s1.spectrum(w1.energies, w1.beta, eps1, w1.r0)
+        torch.cuda.synchronize()
+        if i:
+            lat.append(time.perf_counter() - t)
+    s1.close()
+    res["solve_latency_c1_cocg_ms"] = {"p50": round(1e3 * float(np.percentile(lat, 50)), 3),
+                                       "p99": round(1e3 * float(np.percentile(lat, 99)), 3),
+                                       "solves": len(lat), "precision": "fp64", "solver": "cocg"}
+    log(f"c1 COCG latency p50 {res['solve_latency_c1_cocg_ms']['p50']} ms")
     return res
+
+
+def measure_serving(torch, W, DDASolver, n_req, log):
+    """Replays the first n_req requests of the seeded Poisson stream (mean
+    200 requests/s; sphere / capped rod / ellipsoid on 24-96 cells per side;
+    host 1-2; beta 0.4-0.8; 8-64 energies; tol 1e-8) at their arrival times:
+    served (mixed precision, continuous batching, one engine per lattice),
+    then through the plain FP64 path (one dda_solve per request, COCG, in
+    arrival order on one stream).  Latency runs from a request's arrival to
+    its last loss probability."""
+    from paper_2208_01348_amd.serving import Server, replay, requests_from_stream
+    reqs = requests_from_stream(W.c5_request_stream(n_requests=n_req))
+    points = sum(len(r.energies) for r in reqs)
+    srv = Server(hbm_budget_bytes=160 << 30, slots=64, precision="mixed", tol=1e-8,
+                 check_every=8)
+    t = time.perf_counter()
+    comps, lat, span = replay(srv, reqs, timeout_s=900)
+    srv.close()
+    ok = all(i[3] == 0 for c in comps for i in c.info)
+    L = np.array([lat[c.rid] for c in comps])
+    served = {"p50_s": round(float(np.percentile(L, 50)), 4),
+              "p99_s": round(float(np.percentile(L, 99)), 4),
+              "points_per_s": round(points / span, 2), "makespan_s": round(span, 3),
+              "all_converged": bool(ok), "lattices": len(set(c.lattice for c in comps))}
+    log(f"serving {n_req} requests ({points} points): {span:.2f} s, p50 {served['p50_s']} s, "
+        f"p99 {served['p99_s']} s ({time.perf_counter() - t:.1f} s wall)")
+    # plain FP64: requests one after another in arrival order
+    t0 = time.perf_counter()
+    lat64 = []
+    for r in sorted(reqs, key=lambda r: r.arrival):
+        wait = t0 + r.arrival - time.perf_counter()
+        if wait > 0:
+            time.sleep(wait)
+        s = DDASolver(r.mask, r.d, r.m_h, solver="cocg", precision="fp64", tol=1e-8,
+                      maxit=50000, check_every=8)
+        n = s.n_occ
+        s.spectrum(r.energies, r.beta, np.repeat(r.eps[:, None], n, axis=1), r.r0.reshape(1, 3))
+        s.close()
+        lat64.append(time.perf_counter() - (t0 + r.arrival))
+    span64 = time.perf_counter() - t0
+    L64 = np.array(lat64)
+    plain = {"p50_s": round(float(np.percentile(L64, 50)), 4),
+             "p99_s": round(float(np.percentile(L64, 99)), 4),
+             "points_per_s": round(points / span64, 2), "makespan_s": round(span64, 3)}
+    log(f"plain FP64 per request: {span64:.2f} s, p50 {plain['p50_s']} s, p99 {plain['p99_s']} s")
+    return {"requests": n_req, "points": points, "arrival_rate_per_s": 200.0,
+            "served_mixed": served, "plain_fp64": plain,
+            "note": "first requests of the seeded stream (default_rng(5)); tol 1e-8"}
+
+
+def measure_batch(torch, W, DDASolver, which, n_energy, log):
+    """Points/s of a multi-right-hand-side batch: the impact map (48^3
+    ellipsoid, 16 x 16 impacts per energy sharing one D) or the Cherenkov
+    sphere (64^3, absorbing host 2 + 0.01i, two trajectories), mixed COCG."""
+    w = W.c4_impact_map(n_energy=n_energy) if which == "c4" else W.c3_cherenkov(n_energy=n_energy)
+    n = w.n_occ
+    eps = np.repeat(w.eps_table()[:, None], n, axis=1)
+    s = DDASolver(w.mask, w.d, w.m_h, precision="mixed", tol=w.tol, maxit=50000, solver="cocg",
+                  check_every=16)
+    s.spectrum(w.energies[:1], w.beta, eps[:1], w.r0[:1])  # warm-up (builds, first launches)
+    s.drop_cache()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    P, info = s.spectrum(w.energies, w.beta, eps, w.r0)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    s.close()
+    pts = len(info)
+    its = [i.iters for i in info]
+    log(f"{which}: {pts} points in {dt:.2f} s ({pts / dt:.1f} points/s), iterations "
+        f"median {int(np.median(its))} max {max(its)}")
+    return {"points": pts, "seconds": round(dt, 3), "points_per_s": round(pts / dt, 2),
+            "n_occ": n, "fft_grid": list(s.grid), "iterations_median": int(np.median(its)),
+            "iterations_max": max(its), "tol": w.tol, "precision": "mixed",
+            "all_converged": all(i.status == 0 for i in info)}
 
 
 def cpu_baseline(w, gpu_matvecs, log):

@@ -131,6 +131,15 @@ int dda_setup(const uint8_t* mask, int nx, int ny, int nz, double d_nm,
               void* hip_stream, dda_ctx** out);
 
 /*
+ * A non-blocking HIP stream of default priority, for a context of its own:
+ * graph capture on it (see use_graphs) cannot collide with work other
+ * threads put on the legacy default stream.  Destroy it after the contexts
+ * that use it.
+ */
+int dda_stream_create(void** stream);
+int dda_stream_destroy(void* stream);
+
+/*
  * Changes the host index of a context (passive: Re m_h > 0, Im m_h >= 0).
  * Later calls use it; the cached interaction spectra stay valid (they are
  * keyed by the wavenumber m_h omega/c), and systems already submitted to the

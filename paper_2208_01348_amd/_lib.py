@@ -26,7 +26,7 @@ EXPORTED = ["dda_default_options", "dda_beta_from_keV", "dda_setup", "dda_n_occ"
             "dda_set_timing", "dda_kernel_time", "dda_drop_cache", "dda_destroy",
             "dda_last_error", "dda_debug_besselk01", "dda_workspace_bytes", "dda_engine_open",
             "dda_engine_submit", "dda_engine_poll", "dda_engine_status", "dda_engine_close",
-            "dda_set_host"]
+            "dda_set_host", "dda_stream_create", "dda_stream_destroy"]
 
 
 class DDAError(RuntimeError):
@@ -91,6 +91,8 @@ def load() -> ctypes.CDLL:
         "dda_engine_status": (_i, [_vp, _vp, _vp, _vp]),
         "dda_engine_close": (_i, [_vp]),
         "dda_set_host": (_i, [_vp, _d, _d]),
+        "dda_stream_create": (_i, [_vp]),
+        "dda_stream_destroy": (_i, [_vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -139,6 +141,16 @@ def dda_setup(mask: np.ndarray, nx: int, ny: int, nz: int, d_nm: float, mh_re: f
                             ctypes.byref(opt), ctypes.c_void_p(hip_stream or None),
                             ctypes.byref(ctx)))
     return ctx
+
+
+def dda_stream_create() -> int:
+    s = ctypes.c_void_p()
+    _check(load().dda_stream_create(ctypes.byref(s)))
+    return int(s.value)
+
+
+def dda_stream_destroy(stream: int) -> None:
+    _check(load().dda_stream_destroy(ctypes.c_void_p(stream)))
 
 
 def dda_set_host(ctx, mh_re: float, mh_im: float) -> None:

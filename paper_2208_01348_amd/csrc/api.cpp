@@ -1328,12 +1328,12 @@ int dda_setup(const uint8_t* mask, int nx, int ny, int nz, double d_nm, double m
     g.n_occ = int64_t(c->occ_lin.size());
     c->max_blocks = std::max(1024, std::max(dda::pack_blocks_per_slot(g),
                                             dda::yz_pack_blocks_per_slot(g)));
+    // uploads go through the context's stream (never the legacy stream, which
+    // must not touch a stream another thread is capturing)
     c->map.ensure(size_t(N) * sizeof(int));
-    DDA_HIP_CHECK(hipMemcpy(c->map.p, hmap.data(), size_t(N) * sizeof(int), hipMemcpyHostToDevice));
+    upload(c.get(), c->map.p, hmap.data(), size_t(N) * sizeof(int));
     c->occ.ensure(std::max<size_t>(1, c->occ_lin.size()) * sizeof(int));
-    if (!c->occ_lin.empty())
-        DDA_HIP_CHECK(hipMemcpy(c->occ.p, c->occ_lin.data(), c->occ_lin.size() * sizeof(int),
-                                hipMemcpyHostToDevice));
+    upload(c.get(), c->occ.p, c->occ_lin.data(), c->occ_lin.size() * sizeof(int));
     const int Ls[3] = {g.mx, g.my, g.mz};
     for (int a = 0; a < 3; ++a) {
         const int L = Ls[a];
@@ -1346,10 +1346,27 @@ int dda_setup(const uint8_t* mask, int nx, int ny, int nz, double d_nm, double m
         }
         c->tw128[a].ensure(L * sizeof(z128));
         c->tw64[a].ensure(L * sizeof(z64));
-        DDA_HIP_CHECK(hipMemcpy(c->tw128[a].p, t128.data(), L * sizeof(z128), hipMemcpyHostToDevice));
-        DDA_HIP_CHECK(hipMemcpy(c->tw64[a].p, t64.data(), L * sizeof(z64), hipMemcpyHostToDevice));
+        upload(c.get(), c->tw128[a].p, t128.data(), L * sizeof(z128));
+        upload(c.get(), c->tw64[a].p, t64.data(), L * sizeof(z64));
     }
     *out = c.release();
+    return DDA_OK;
+    DDA_API_END
+}
+
+int dda_stream_create(void** stream) {
+    DDA_API_BEGIN
+    if (!stream) throw Error(DDA_EINVAL, "stream is NULL");
+    hipStream_t s = nullptr;
+    DDA_HIP_CHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    *stream = s;
+    return DDA_OK;
+    DDA_API_END
+}
+
+int dda_stream_destroy(void* stream) {
+    DDA_API_BEGIN
+    if (stream) DDA_HIP_CHECK(hipStreamDestroy(static_cast<hipStream_t>(stream)));
     return DDA_OK;
     DDA_API_END
 }

@@ -415,7 +415,7 @@ __global__ __launch_bounds__(NT) void k_fin_cocg_start(BicgSlot* st, const int* 
 // one keeps falling.  A slot whose FP64 residual has not halved over
 // kStallChecks checks restarts its recursion from the FP64 residual.
 constexpr double kStallDrop = 0.5;
-constexpr int kStallChecks = 3;
+constexpr int kStallChecks = 8;
 
 // FP64 residual check of a slot that asked for one (needs_check): the FP64
 // residual decides convergence; otherwise the iteration limit ends the slot, a

@@ -5,10 +5,12 @@ electron field, the FFT matvecs, the Krylov iterations and the loss sums)
 runs in libdda's HIP kernels.  This module only allocates tensors and passes
 their pointers.
 
-By default a solver runs on a stream of its own (default priority), so that
-the library can capture its iteration intervals as HIP graphs; every call is
-ordered after the work already queued on torch's current stream, and the
-current stream waits for the call's work before torch touches the outputs.
+By default a solver runs on a non-blocking stream of its own (default
+priority, created by the library), so that the library can capture its
+iteration intervals as HIP graphs while other threads keep using the legacy
+default stream; every call is ordered after the work already queued on
+torch's current stream, and the current stream waits for the call's work
+before torch touches the outputs.
 """
 
 from __future__ import annotations
@@ -50,7 +52,11 @@ class DDASolver:
         self.d = float(d_nm)
         self.m_h = complex(m_h)
         self.device = torch.device("cuda", torch.cuda.current_device())
-        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        self._own_stream = None
+        if stream is None:
+            self._own_stream = L.dda_stream_create()
+            stream = torch.cuda.ExternalStream(self._own_stream, device=self.device)
+        self.stream = stream
         opt = L.dda_default_options()
         opt.polarizability = _POL[polarizability]
         opt.precision = _PREC[precision]
@@ -68,6 +74,9 @@ class DDASolver:
         if self.ctx is not None:
             L.dda_destroy(self.ctx)
             self.ctx = None
+        if self._own_stream is not None:
+            L.dda_stream_destroy(self._own_stream)
+            self._own_stream = None
 
     def __del__(self):
         try:
