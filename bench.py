@@ -203,6 +203,10 @@ def main():
                 "timing": "HIP events per launch, one instrumented step after the timed ones",
                 "rhs_per_launch": round(rhs, 2), "bytes_per_launch": round(per_launch)}
     solver.set_timing(False)
+    from paper_2208_01348_amd import _lib as L
+    tuning = {"fp32": L.dda_tuning(solver.ctx, L.DDA_PREC_MIXED),
+              "fp64": L.dda_tuning(solver.ctx, L.DDA_PREC_FP64)}
+    log(f"autotuned tiles: {tuning}")
 
     extras = {}
     if not args.no_extras:
@@ -244,6 +248,7 @@ def main():
                   "iterations_max": max(iters), "matvecs_total": int(sum(mvs)),
                   "max_rel_residual": max(x.rel_residual for x in info), "statuses": statuses},
         "roofline": roofline,
+        "autotune": tuning,
         "cpu_baseline": cpu,
     }
     out.update(extras)
@@ -392,6 +397,9 @@ def measure_batch(torch, W, DDASolver, which, n_energy, log):
     P, info = s.spectrum(w.energies, w.beta, eps, w.r0)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
+    from paper_2208_01348_amd import _lib as L
+    tuning = {"fp32": L.dda_tuning(s.ctx, L.DDA_PREC_MIXED),
+              "fp64": L.dda_tuning(s.ctx, L.DDA_PREC_FP64)}
     s.close()
     pts = len(info)
     its = [i.iters for i in info]
@@ -400,7 +408,7 @@ def measure_batch(torch, W, DDASolver, which, n_energy, log):
     return {"points": pts, "seconds": round(dt, 3), "points_per_s": round(pts / dt, 2),
             "n_occ": n, "fft_grid": list(s.grid), "iterations_median": int(np.median(its)),
             "iterations_max": max(its), "tol": w.tol, "precision": "mixed",
-            "all_converged": all(i.status == 0 for i in info)}
+            "all_converged": all(i.status == 0 for i in info), "autotune": tuning}
 
 
 def cpu_baseline(w, gpu_matvecs, log):

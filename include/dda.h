@@ -263,6 +263,29 @@ int dda_engine_status(dda_ctx* ctx, int* queued, int* running, int* finished);
 /* Waits for the stream and frees the slot pool (queued systems are dropped). */
 int dda_engine_close(dda_ctx* ctx);
 
+/*
+ * Tile choices of the autotuner for the FFT matvec chain of one precision
+ * (DDA_PREC_FP64 or DDA_PREC_MIXED = the FP32 chain).  Before a context's
+ * first matvec of a precision (outside any graph capture) the candidates are
+ * timed on the actual batch with HIP events: threads per block of the fused
+ * yz kernel (three-pass chain), or columns per block of the z-convolution and
+ * y passes (five-pass chain); the choice is kept for every context of the
+ * process with the same lattice and grid.  The candidates only regroup lines
+ * into blocks, so the choice never changes a result.  0 means the default
+ * width stood; t_default_ms / t_best_ms time the tuned kernel with the
+ * default and the chosen width.  Returns 1 (and zeros) if no matvec of that
+ * precision has run yet.
+ */
+int dda_tuning(const dda_ctx* ctx, int precision, int* zconv_tx, int* mid_tx, int* yz_threads,
+               double* t_default_ms, double* t_best_ms);
+
+/*
+ * Pins the tile choices of one precision's chain for this context (0 = the
+ * default width), bypassing the autotuner.  Errors: DDA_EINVAL for a value
+ * that is not a candidate for the context's grid.
+ */
+int dda_set_tuning(dda_ctx* ctx, int precision, int zconv_tx, int mid_tx, int yz_threads);
+
 /* Per-kernel timing of the matvec chain, measured with HIP events recorded on
  * the context's stream around every launch while timing is enabled
  * (dda_set_timing resets the counters).  enabled: 0 off, 1 all kernels,

@@ -26,7 +26,8 @@ EXPORTED = ["dda_default_options", "dda_beta_from_keV", "dda_setup", "dda_n_occ"
             "dda_set_timing", "dda_kernel_time", "dda_drop_cache", "dda_destroy",
             "dda_last_error", "dda_debug_besselk01", "dda_workspace_bytes", "dda_engine_open",
             "dda_engine_submit", "dda_engine_poll", "dda_engine_status", "dda_engine_close",
-            "dda_set_host", "dda_stream_create", "dda_stream_destroy"]
+            "dda_set_host", "dda_stream_create", "dda_stream_destroy", "dda_tuning",
+            "dda_set_tuning"]
 
 
 class DDAError(RuntimeError):
@@ -93,6 +94,8 @@ def load() -> ctypes.CDLL:
         "dda_set_host": (_i, [_vp, _d, _d]),
         "dda_stream_create": (_i, [_vp]),
         "dda_stream_destroy": (_i, [_vp]),
+        "dda_tuning": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp]),
+        "dda_set_tuning": (_i, [_vp, _i, _i, _i, _i]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -141,6 +144,26 @@ def dda_setup(mask: np.ndarray, nx: int, ny: int, nz: int, d_nm: float, mh_re: f
                             ctypes.byref(opt), ctypes.c_void_p(hip_stream or None),
                             ctypes.byref(ctx)))
     return ctx
+
+
+def dda_tuning(ctx, precision: int):
+    """Autotuned tiles of one precision's matvec chain, or None before tuning:
+    {zconv_tx, mid_tx, yz_threads, t_default_ms, t_best_ms}."""
+    a, b, c = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+    t0, t1 = ctypes.c_double(), ctypes.c_double()
+    st = load().dda_tuning(ctx, int(precision), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                           ctypes.byref(t0), ctypes.byref(t1))
+    if st == 1:
+        return None
+    _check(st)
+    return {"zconv_tx": a.value, "mid_tx": b.value, "yz_threads": c.value,
+            "t_default_ms": round(t0.value, 5), "t_best_ms": round(t1.value, 5)}
+
+
+def dda_set_tuning(ctx, precision: int, zconv_tx: int = 0, mid_tx: int = 0,
+                   yz_threads: int = 0) -> None:
+    _check(load().dda_set_tuning(ctx, int(precision), int(zconv_tx), int(mid_tx),
+                                 int(yz_threads)))
 
 
 def dda_stream_create() -> int:

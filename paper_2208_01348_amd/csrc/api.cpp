@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <complex>
 #include <cstring>
@@ -219,6 +220,19 @@ struct StateRing {
     }
 };
 
+// Tile choices of the matvec chain for one precision, picked by timing the
+// candidates (autotune); 0 means the compiled-in default.
+struct TuneVal {
+    bool done = false;
+    int zconv_tx = 0, mid_tx = 0, yz_threads = 0;
+    double t_default_ms = 0.0, t_best_ms = 0.0;  // the tuned kernel, default vs chosen
+};
+
+// Choices shared by every context of the process with the same lattice and
+// FFT grid, so that they all run the same kernels.
+std::mutex g_tune_mu;
+std::map<std::array<int, 7>, TuneVal> g_tune;
+
 // A captured interval, replayed while its key (the active-list length) holds.
 struct GraphCache {
     hipGraphExec_t exec = nullptr;
@@ -258,6 +272,7 @@ struct dda_ctx {
     // Captured COCG interval (not used while kernels are timed: events
     // recorded by graph nodes carry no timestamps)
     GraphCache graph;
+    TuneVal tune[2];  // [0] FP32, [1] FP64 matvec chain
     std::unique_ptr<struct Engine> engine;  // continuous batching, when open
     int max_blocks = 1024;
     bool timing = false;
@@ -388,6 +403,109 @@ struct Work {
 };
 Work ctx_work(dda_ctx* c) { return Work{c->st.as<dda::BicgSlot>(), red_of(c), c->G.p}; }
 
+// Picks the tile widths of the chain for precision T by timing every
+// candidate on up to 8 of the listed right-hand sides (HIP events, best of
+// three after a warm-up): the threads per block of the fused yz kernel, or
+// the columns per block of the z-convolution and y passes of the five-pass
+// chain.  The candidates differ only in how lines are grouped into blocks, so
+// the choice never changes a result.  Runs once per process and geometry
+// (never inside a stream capture: there the defaults stand until tuning has
+// run outside one); it writes only the grid work buffer, which every matvec
+// rewrites before reading.
+template <typename T>
+void autotune(dda_ctx* c, const Work& w, const int* act, int n_act,
+              const dda::cx<T>* const* dptr, const int* slot_sys) {
+    constexpr int csize = int(sizeof(dda::cx<T>));
+    TuneVal& tv = c->tune[csize == 16 ? 1 : 0];
+    if (tv.done || n_act == 0 || c->g.n_occ == 0) return;
+    const dda::Geo& g = c->g;
+    const std::array<int, 7> key{g.nx, g.ny, g.nz, g.mx, g.my, g.mz, csize};
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) {
+            tv = it->second;
+            return;
+        }
+    }
+    hipStream_t s = c->stream;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    DDA_HIP_CHECK(hipStreamIsCapturing(s, &cs));
+    if (cs != hipStreamCaptureStatusNone) return;
+    const int n = std::min(n_act, 8);
+    auto* G = static_cast<dda::cx<T>*>(w.G);
+    const dda::SlotFilter all{nullptr, dda::FILTER_ALL};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    DDA_HIP_CHECK(hipEventCreate(&e0));
+    DDA_HIP_CHECK(hipEventCreate(&e1));
+    auto time_of = [&](auto&& launch) {
+        launch();
+        float best = 1e30f;
+        for (int r = 0; r < 3; ++r) {
+            DDA_HIP_CHECK(hipEventRecord(e0, s));
+            launch();
+            DDA_HIP_CHECK(hipEventRecord(e1, s));
+            DDA_HIP_CHECK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            DDA_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+            best = std::min(best, ms);
+        }
+        return double(best);
+    };
+    // the fastest candidate; returns {choice, default width's time, best time}
+    // (choice 0 keeps the default: no candidate beat it)
+    auto pick = [&](const std::vector<int>& cands, auto&& launch_with) {
+        const double t_def = time_of([&] { launch_with(0); });
+        int best_v = 0;
+        double best_t = t_def;
+        for (int v : cands) {
+            const double t = time_of([&] { launch_with(v); });
+            if (t < best_t) {
+                best_t = t;
+                best_v = v;
+            }
+        }
+        return std::array<double, 3>{double(best_v), t_def, best_t};
+    };
+    TuneVal r;
+    r.done = true;
+    try {
+        if (dda::yz_fused_ok(g, csize)) {
+            const auto res = pick(dda::yz_thread_candidates(g.my), [&](int nt) {
+                dda::launch_yzconv<T>(G, dptr, tw_of<T>(c, 1), tw_of<T>(c, 2), g, act, slot_sys, n,
+                                      all, nt, s);
+            });
+            r.yz_threads = int(res[0]);
+            r.t_default_ms = res[1];
+            r.t_best_ms = res[2];
+        } else {
+            const auto rz = pick(dda::zconv_tx_candidates<T>(g.mz), [&](int tx) {
+                dda::launch_zconv<T>(G, dptr, tw_of<T>(c, 2), g, act, slot_sys, n, all, tx, s);
+            });
+            const int64_t plane = int64_t(g.my) * g.mx;
+            const auto rm = pick(dda::mid_tx_candidates<T>(g.my), [&](int tx) {
+                dda::launch_fft_mid<T>(G, tw_of<T>(c, 1), g.my, false, int64_t(n) * 3 * g.nz,
+                                       g.mx, g.ny, g.my, plane, tx, s);
+            });
+            r.zconv_tx = int(rz[0]);
+            r.mid_tx = int(rm[0]);
+            r.t_default_ms = rz[1];
+            r.t_best_ms = rz[2];
+        }
+    } catch (...) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune.emplace(key, r);
+    }
+    tv = r;
+}
+
 // One FFT matvec for the slots listed in act (device) / n_act:
 // mode PACK_AX (y = A x), PACK_GX (y = G_off x) or PACK_AX_COCG (y = A x with
 // the COCG scalars fused; then fuse_r gives the direction update
@@ -410,6 +528,8 @@ void matvec(dda_ctx* c, const Work& w, dda::cx<T>* x, dda::cx<T>* y, const int* 
     hipStream_t s = c->stream;
     auto* st = w.st;
     constexpr int csize = int(sizeof(dda::cx<T>));
+    autotune<T>(c, w, act, n_act, dptr, slot_sys);
+    const TuneVal& tn = c->tune[csize == 16 ? 1 : 0];
     if (dda::yz_fused_ok(g, csize)) {
         {
             Tic t(c, 0, n_act);
@@ -419,7 +539,7 @@ void matvec(dda_ctx* c, const Work& w, dda::cx<T>* x, dda::cx<T>* y, const int* 
         {
             Tic t(c, 5, n_act);
             dda::launch_yzconv<T>(G, dptr, tw_of<T>(c, 1), tw_of<T>(c, 2), g, act, slot_sys, n_act,
-                                  f, s);
+                                  f, tn.yz_threads, s);
         }
         {
             Tic t(c, 4, n_act);
@@ -436,16 +556,17 @@ void matvec(dda_ctx* c, const Work& w, dda::cx<T>* x, dda::cx<T>* y, const int* 
         {
             Tic t(c, 1, n_act);
             dda::launch_fft_mid<T>(G, tw_of<T>(c, 1), g.my, false, int64_t(n_act) * 3 * g.nz,
-                                   g.mx, g.ny, g.my, plane, s);
+                                   g.mx, g.ny, g.my, plane, tn.mid_tx, s);
         }
         {
             Tic t(c, 2, n_act);
-            dda::launch_zconv<T>(G, dptr, tw_of<T>(c, 2), g, act, slot_sys, n_act, f, s);
+            dda::launch_zconv<T>(G, dptr, tw_of<T>(c, 2), g, act, slot_sys, n_act, f, tn.zconv_tx,
+                                 s);
         }
         {
             Tic t(c, 3, n_act);
             dda::launch_fft_mid<T>(G, tw_of<T>(c, 1), g.my, true, int64_t(n_act) * 3 * g.nz,
-                                   g.mx, g.my, g.ny, plane, s);
+                                   g.mx, g.my, g.ny, plane, tn.mid_tx, s);
         }
         {
             Tic t(c, 4, n_act);
@@ -902,6 +1023,8 @@ void run_cocg(dda_ctx* c, int nslots, const CocgBufs<T>& B, double tol, int maxi
     for (int i = 0; i < nslots; ++i) act[i] = i;
     upload_act(c, act);
     cocg_init<T>(c, B, B.act, nslots, tol, maxit);
+    autotune<T>(c, B.w, B.act, nslots, B.dptr, B.slot_sys);  // outside any capture
+    autotune<double>(c, B.w, B.act, nslots, B.dptr64, B.slot_sys);
     const bool graphs = use_graphs(c);
     c->graph.drop();
     try {
@@ -1237,6 +1360,8 @@ void engine_poll(dda_ctx* c, Engine& E, int max_intervals) {
             E.act_dirty = false;
         }
         const int n_act = int(E.running.size());
+        autotune<T>(c, B.w, B.act, n_act, B.dptr, B.slot_sys);  // once, outside any capture
+        autotune<double>(c, B.w, B.act, n_act, B.dptr64, B.slot_sys);
         if (graphs) launch_captured(c, E.graph, n_act, [&] { cocg_interval<T>(c, B, n_act); });
         else cocg_interval<T>(c, B, n_act);
         E.ring.snapshot(c->stream, B.w.st, E.cap, E.sent);
@@ -1716,6 +1841,52 @@ int dda_engine_close(dda_ctx* c) {
     DDA_HIP_CHECK(hipStreamSynchronize(c->stream));
     for (auto& sr : c->engine->slots) engine_release(c, sr);
     c->engine.reset();
+    return DDA_OK;
+    DDA_API_END
+}
+
+int dda_tuning(const dda_ctx* c, int precision, int* zconv_tx, int* mid_tx, int* yz_threads,
+               double* t_default_ms, double* t_best_ms) {
+    DDA_API_BEGIN
+    if (!c || !zconv_tx || !mid_tx || !yz_threads || !t_default_ms || !t_best_ms)
+        throw Error(DDA_EINVAL, "NULL argument");
+    if (precision != DDA_PREC_FP64 && precision != DDA_PREC_MIXED)
+        throw Error(DDA_EINVAL, "bad precision");
+    const TuneVal& tv = c->tune[precision == DDA_PREC_FP64 ? 1 : 0];
+    *zconv_tx = tv.zconv_tx;
+    *mid_tx = tv.mid_tx;
+    *yz_threads = tv.yz_threads;
+    *t_default_ms = tv.t_default_ms;
+    *t_best_ms = tv.t_best_ms;
+    return tv.done ? DDA_OK : 1;
+    DDA_API_END
+}
+
+int dda_set_tuning(dda_ctx* c, int precision, int zconv_tx, int mid_tx, int yz_threads) {
+    DDA_API_BEGIN
+    if (!c) throw Error(DDA_EINVAL, "ctx is NULL");
+    if (precision != DDA_PREC_FP64 && precision != DDA_PREC_MIXED)
+        throw Error(DDA_EINVAL, "bad precision");
+    const int csize = precision == DDA_PREC_FP64 ? 16 : 8;
+    const dda::Geo& g = c->g;
+    auto allowed = [](int v, const std::vector<int>& cands) {
+        return v == 0 || std::find(cands.begin(), cands.end(), v) != cands.end();
+    };
+    const bool ok =
+        csize == 16
+            ? allowed(zconv_tx, dda::zconv_tx_candidates<double>(g.mz)) &&
+                  allowed(mid_tx, dda::mid_tx_candidates<double>(g.my))
+            : allowed(zconv_tx, dda::zconv_tx_candidates<float>(g.mz)) &&
+                  allowed(mid_tx, dda::mid_tx_candidates<float>(g.my));
+    if (!ok || !allowed(yz_threads, dda::yz_thread_candidates(g.my)))
+        throw Error(DDA_EINVAL, "tile choice not among the candidates for this grid");
+    TuneVal& tv = c->tune[csize == 16 ? 1 : 0];
+    tv = TuneVal{};
+    tv.done = true;
+    tv.zconv_tx = zconv_tx;
+    tv.mid_tx = mid_tx;
+    tv.yz_threads = yz_threads;
+    c->graph.drop();
     return DDA_OK;
     DDA_API_END
 }

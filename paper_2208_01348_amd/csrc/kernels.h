@@ -1,6 +1,8 @@
 // Host-side launchers of the gfx950 kernels (implemented in the .hip files).
 #pragma once
 
+#include <vector>
+
 #include "common.h"
 #include "slots.h"
 
@@ -41,12 +43,22 @@ template <typename T>
 void launch_unpack_xfft(cx<T>* xin, const int* map, cx<T>* G, const cx<T>* tw_x, const Geo& g,
                         const int* act, int n_act, const cx<T>* fuse_r, SlotFilter f,
                         hipStream_t s);
+// tx: columns per block (0: the default width; see mid_tx_candidates).
 template <typename T>
 void launch_fft_mid(cx<T>* data, const cx<T>* tw, int L, bool inverse, int64_t n_outer,
-                    int64_t inner, int n_in, int n_out, int64_t outer_stride, hipStream_t s);
+                    int64_t inner, int n_in, int n_out, int64_t outer_stride, int tx,
+                    hipStream_t s);
+// tx: columns per block (0: the default width; see zconv_tx_candidates).
 template <typename T>
 void launch_zconv(cx<T>* G, const cx<T>* const* Dptr, const cx<T>* tw_z, const Geo& g,
-                  const int* act, const int* slot_sys, int n_act, SlotFilter f, hipStream_t s);
+                  const int* act, const int* slot_sys, int n_act, SlotFilter f, int tx,
+                  hipStream_t s);
+// Tile widths the autotuner may try for a transform length L; all of them
+// give bit-identical results.
+template <typename T>
+std::vector<int> mid_tx_candidates(int L);
+template <typename T>
+std::vector<int> zconv_tx_candidates(int L);
 // mode PACK_AX: y = x/alpha - G_off x; PACK_GX: y = G_off x; PACK_AX_COCG:
 // y = A x and, fused, the partial rows of mu = x^T y per slot in `red`
 // (pack_blocks_per_slot rows, which must not exceed max_blocks); the caller
@@ -80,10 +92,12 @@ int yz_pack_blocks_per_slot(const Geo& g);
 template <typename T>
 void launch_xfft_t(cx<T>* xin, const int* map, cx<T>* Tb, const cx<T>* tw_x, const Geo& g,
                    const int* act, int n_act, const cx<T>* fuse_r, SlotFilter f, hipStream_t s);
+// nthreads: threads per block (0: the default; see yz_thread_candidates)
 template <typename T>
 void launch_yzconv(cx<T>* Tb, const cx<T>* const* Dptr, const cx<T>* tw_y, const cx<T>* tw_z,
                    const Geo& g, const int* act, const int* slot_sys, int n_act, SlotFilter f,
-                   hipStream_t s);
+                   int nthreads, hipStream_t s);
+std::vector<int> yz_thread_candidates(int L);
 template <typename T>
 void launch_ixfft_t(const cx<T>* Tb, const cx<T>* xin, const cx<T>* ainv, cx<T>* yout,
                     const int* map, const cx<T>* tw_x, const Geo& g, const int* act,

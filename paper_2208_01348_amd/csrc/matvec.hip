@@ -36,15 +36,24 @@ constexpr int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi 
 // rows per block for row kernels (about 2048 elements per block)
 template <typename T, int L>
 constexpr int rows_nl() { return L >= 2048 ? 1 : 2048 / L; }
-// columns per block for strided-axis kernels
+// columns per block for strided-axis kernels (default; the autotuner may
+// pick another width for L >= kTuneMinL)
 template <typename T, int L>
 constexpr int mid_tx() { return clampi(pow2floor(2048 / L), 1, sizeof(T) == 8 ? 16 : 32); }
 // columns per z-conv block: two mirror sets x 3 components x TX lines of
-// length L within about 64 KB of LDS
+// length L (default: within 32 KB of LDS)
 template <typename T, int L>
 constexpr int zconv_tx() {
     return clampi(pow2floor(32768 / (6 * L * int(2 * sizeof(T)))), 1, sizeof(T) == 8 ? 4 : 8);
 }
+// Tile widths the autotuner may choose (at most 64 KB of LDS per block).
+// The width only changes how many lines share a block; every line's
+// arithmetic is the same, so all widths give identical results.
+constexpr int kTuneMinL = 24;
+template <typename T, int L, int TX>
+constexpr bool mid_fits() { return size_t(L) * TX * 2 * sizeof(T) <= (size_t(64) << 10); }
+template <typename T, int L, int TX>
+constexpr bool zconv_fits() { return size_t(6) * L * TX * 2 * sizeof(T) <= (size_t(64) << 10); }
 
 #define DDA_FOR_EACH_L(X) \
     X(1) X(2) X(3) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
@@ -118,12 +127,11 @@ __global__ __launch_bounds__(NTHR) void k_unpack_xfft(cx<T>* __restrict__ xin,
 // ------------------------------------------------------------ K2 / K4 -----
 // FFT along the middle axis of data[outer][L][inner]: the first n_in rows are
 // read (the rest are zero), the first n_out rows are written.
-template <typename T, int L, bool INV>
+template <typename T, int L, bool INV, int TX>
 __global__ __launch_bounds__(NTHR) void k_fft_mid(cx<T>* __restrict__ data,
                                                   const cx<T>* __restrict__ tw, int64_t inner,
                                                   int n_in, int n_out, int64_t outer_stride,
                                                   int64_t tiles_per_outer) {
-    constexpr int TX = mid_tx<T, L>();
     __shared__ cx<T> lds[L * TX];
     const int tid = threadIdx.x;
     const int64_t o = blockIdx.x / tiles_per_outer;
@@ -150,13 +158,12 @@ __global__ __launch_bounds__(NTHR) void k_fft_mid(cx<T>* __restrict__ data,
 // value it loads from the stored corner serves the four frequencies
 // (+-kx fixed by the column, ky or my - ky, kz or mz - kz) that share it,
 // with the sign flips of the odd components: four times fewer D loads.
-template <typename T, int L>
+template <typename T, int L, int TX>
 __global__ __launch_bounds__(NTHR) void k_zconv(cx<T>* __restrict__ G,
                                                 const cx<T>* const* __restrict__ Dptr,
                                                 const cx<T>* __restrict__ tw, Geo g,
                                                 const int* __restrict__ act,
                                                 const int* __restrict__ slot_sys, SlotFilter f) {
-    constexpr int TX = zconv_tx<T, L>();
     constexpr int W = 6 * TX;  // lines per tile: (mirror set, component, column)
     __shared__ cx<T> lds[L * W];
     const int tid = threadIdx.x;
@@ -318,22 +325,41 @@ void launch_unpack_xfft(cx<T>* xin, const int* map, cx<T>* G, const cx<T>* tw_x,
     DDA_LAUNCH_CHECK();
 }
 
+template <typename T, int L, bool INV, int TX>
+void run_fft_mid(cx<T>* data, const cx<T>* tw, int64_t n_outer, int64_t inner, int n_in, int n_out,
+                 int64_t outer_stride, hipStream_t s) {
+    const int64_t tiles = (inner + TX - 1) / TX;
+    k_fft_mid<T, L, INV, TX><<<unsigned(tiles * n_outer), NTHR, 0, s>>>(data, tw, inner, n_in,
+                                                                       n_out, outer_stride, tiles);
+}
+
+template <typename T, int L, bool INV>
+void fft_mid_tx(int tx, cx<T>* data, const cx<T>* tw, int64_t n_outer, int64_t inner, int n_in,
+                int n_out, int64_t outer_stride, hipStream_t s) {
+    if constexpr (L >= kTuneMinL) {
+#define DDA_TX(W)                                                                          \
+    if constexpr (mid_fits<T, L, W>())                                                     \
+        if (tx == W)                                                                       \
+            return run_fft_mid<T, L, INV, W>(data, tw, n_outer, inner, n_in, n_out,        \
+                                             outer_stride, s);
+        DDA_TX(4) DDA_TX(8) DDA_TX(16) DDA_TX(32)
+#undef DDA_TX
+    }
+    run_fft_mid<T, L, INV, mid_tx<T, L>()>(data, tw, n_outer, inner, n_in, n_out, outer_stride, s);
+}
+
 template <typename T>
 void launch_fft_mid(cx<T>* data, const cx<T>* tw, int L, bool inverse, int64_t n_outer,
-                    int64_t inner, int n_in, int n_out, int64_t outer_stride, hipStream_t s) {
+                    int64_t inner, int n_in, int n_out, int64_t outer_stride, int tx,
+                    hipStream_t s) {
     switch (L) {
 #define DDA_CASE(N)                                                                        \
-    case N: {                                                                              \
-        const int64_t tiles = (inner + mid_tx<T, N>() - 1) / mid_tx<T, N>();               \
-        dim3 grid(unsigned(tiles * n_outer));                                              \
+    case N:                                                                                \
         if (inverse)                                                                       \
-            k_fft_mid<T, N, true><<<grid, NTHR, 0, s>>>(data, tw, inner, n_in, n_out,      \
-                                                        outer_stride, tiles);              \
+            fft_mid_tx<T, N, true>(tx, data, tw, n_outer, inner, n_in, n_out, outer_stride, s); \
         else                                                                               \
-            k_fft_mid<T, N, false><<<grid, NTHR, 0, s>>>(data, tw, inner, n_in, n_out,     \
-                                                         outer_stride, tiles);             \
-        break;                                                                             \
-    }
+            fft_mid_tx<T, N, false>(tx, data, tw, n_outer, inner, n_in, n_out, outer_stride, s); \
+        break;
         DDA_FOR_EACH_L(DDA_CASE)
 #undef DDA_CASE
         default:
@@ -342,23 +368,86 @@ void launch_fft_mid(cx<T>* data, const cx<T>* tw, int L, bool inverse, int64_t n
     DDA_LAUNCH_CHECK();
 }
 
+template <typename T, int L, int TX>
+void run_zconv(cx<T>* G, const cx<T>* const* Dptr, const cx<T>* tw_z, const Geo& g,
+               const int* act, const int* slot_sys, int n_act, SlotFilter f, hipStream_t s) {
+    dim3 grid(nblk(g.mx, TX), g.my / 2 + 1, n_act);
+    k_zconv<T, L, TX><<<grid, NTHR, 0, s>>>(G, Dptr, tw_z, g, act, slot_sys, f);
+}
+
+template <typename T, int L>
+void zconv_tx_run(int tx, cx<T>* G, const cx<T>* const* Dptr, const cx<T>* tw_z, const Geo& g,
+                  const int* act, const int* slot_sys, int n_act, SlotFilter f, hipStream_t s) {
+    if constexpr (L >= kTuneMinL) {
+#define DDA_TX(W)                                                                        \
+    if constexpr (zconv_fits<T, L, W>())                                                 \
+        if (tx == W) return run_zconv<T, L, W>(G, Dptr, tw_z, g, act, slot_sys, n_act, f, s);
+        DDA_TX(1) DDA_TX(2) DDA_TX(4) DDA_TX(8)
+#undef DDA_TX
+    }
+    run_zconv<T, L, zconv_tx<T, L>()>(G, Dptr, tw_z, g, act, slot_sys, n_act, f, s);
+}
+
 template <typename T>
 void launch_zconv(cx<T>* G, const cx<T>* const* Dptr, const cx<T>* tw_z, const Geo& g,
-                  const int* act, const int* slot_sys, int n_act, SlotFilter f, hipStream_t s) {
+                  const int* act, const int* slot_sys, int n_act, SlotFilter f, int tx,
+                  hipStream_t s) {
     if (n_act == 0) return;
     switch (g.mz) {
 #define DDA_CASE(N)                                                                    \
-    case N: {                                                                          \
-        dim3 grid(nblk(g.mx, zconv_tx<T, N>()), g.my / 2 + 1, n_act);                   \
-        k_zconv<T, N><<<grid, NTHR, 0, s>>>(G, Dptr, tw_z, g, act, slot_sys, f);        \
-        break;                                                                         \
-    }
+    case N:                                                                            \
+        zconv_tx_run<T, N>(tx, G, Dptr, tw_z, g, act, slot_sys, n_act, f, s);           \
+        break;
         DDA_FOR_EACH_L(DDA_CASE)
 #undef DDA_CASE
         default:
             throw Error(-1, "unsupported FFT length along z");
     }
     DDA_LAUNCH_CHECK();
+}
+
+template <typename T>
+std::vector<int> mid_tx_candidates(int L) {
+    std::vector<int> v;
+    switch (L) {
+#define DDA_CASE(N)                                                                    \
+    case N:                                                                            \
+        if (N >= kTuneMinL) {                                                          \
+            if (mid_fits<T, N, 4>()) v.push_back(4);                                   \
+            if (mid_fits<T, N, 8>()) v.push_back(8);                                   \
+            if (mid_fits<T, N, 16>()) v.push_back(16);                                 \
+            if (mid_fits<T, N, 32>()) v.push_back(32);                                 \
+        }                                                                              \
+        if (v.empty()) v.push_back(mid_tx<T, N>());                                    \
+        break;
+        DDA_FOR_EACH_L(DDA_CASE)
+#undef DDA_CASE
+        default:
+            break;
+    }
+    return v;
+}
+
+template <typename T>
+std::vector<int> zconv_tx_candidates(int L) {
+    std::vector<int> v;
+    switch (L) {
+#define DDA_CASE(N)                                                                    \
+    case N:                                                                            \
+        if (N >= kTuneMinL) {                                                          \
+            if (zconv_fits<T, N, 1>()) v.push_back(1);                                 \
+            if (zconv_fits<T, N, 2>()) v.push_back(2);                                 \
+            if (zconv_fits<T, N, 4>()) v.push_back(4);                                 \
+            if (zconv_fits<T, N, 8>()) v.push_back(8);                                 \
+        }                                                                              \
+        if (v.empty()) v.push_back(zconv_tx<T, N>());                                  \
+        break;
+        DDA_FOR_EACH_L(DDA_CASE)
+#undef DDA_CASE
+        default:
+            break;
+    }
+    return v;
 }
 
 template <typename T>
@@ -398,13 +487,17 @@ template void launch_unpack_xfft<double>(z128*, const int*, z128*, const z128*, 
 template void launch_unpack_xfft<float>(z64*, const int*, z64*, const z64*, const Geo&, const int*,
                                         int, const z64*, SlotFilter, hipStream_t);
 template void launch_fft_mid<double>(z128*, const z128*, int, bool, int64_t, int64_t, int, int,
-                                     int64_t, hipStream_t);
+                                     int64_t, int, hipStream_t);
 template void launch_fft_mid<float>(z64*, const z64*, int, bool, int64_t, int64_t, int, int,
-                                    int64_t, hipStream_t);
+                                    int64_t, int, hipStream_t);
 template void launch_zconv<double>(z128*, const z128* const*, const z128*, const Geo&, const int*,
-                                   const int*, int, SlotFilter, hipStream_t);
+                                   const int*, int, SlotFilter, int, hipStream_t);
 template void launch_zconv<float>(z64*, const z64* const*, const z64*, const Geo&, const int*,
-                                  const int*, int, SlotFilter, hipStream_t);
+                                  const int*, int, SlotFilter, int, hipStream_t);
+template std::vector<int> mid_tx_candidates<double>(int);
+template std::vector<int> mid_tx_candidates<float>(int);
+template std::vector<int> zconv_tx_candidates<double>(int);
+template std::vector<int> zconv_tx_candidates<float>(int);
 template void launch_ixfft_pack<double>(const z128*, const z128*, const z128*, z128*,
                                         const int*, const z128*, const Geo&, const int*,
                                         const int*, int, int, SlotFilter, RedScratch, hipStream_t);
@@ -528,8 +621,8 @@ void launch_build_D(z128* D, const Geo& g, double d, double k_re, double k_im,
             throw Error(-1, "unsupported FFT length along x");
     }
     DDA_LAUNCH_CHECK();
-    launch_fft_mid<double>(D, tw_y, g.my, false, 6 * int64_t(g.mz), g.mx, g.my, g.my, plane, s);
-    launch_fft_mid<double>(D, tw_z, g.mz, false, 6, plane, g.mz, g.mz, total, s);
+    launch_fft_mid<double>(D, tw_y, g.my, false, 6 * int64_t(g.mz), g.mx, g.my, g.my, plane, 0, s);
+    launch_fft_mid<double>(D, tw_z, g.mz, false, 6, plane, g.mz, g.mz, total, 0, s);
 }
 
 __global__ void k_z128_to_z64(const z128* __restrict__ in, z64* __restrict__ out, int64_t n) {

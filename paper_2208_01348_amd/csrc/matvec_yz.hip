@@ -21,7 +21,9 @@ namespace dda {
 namespace {
 
 constexpr int NT = 256;    // x kernels
-constexpr int NTYZ = 512;  // yz kernel
+constexpr int NTYZ = 512;  // yz kernel, default threads per block (the autotuner
+                           // may pick 256 or 1024 for L >= 24; the butterflies
+                           // are the same whichever thread computes them)
 
 // rows of one (component, z) plane per x-kernel block
 template <int LX>
@@ -178,8 +180,8 @@ __global__ __launch_bounds__(NT) void k_ixfft_t(const cx<T>* __restrict__ Tb,
 // [kx' <= mx/2][6][kz' <= L/2][ky' <= L/2]; one load serves the (up to) four
 // frequencies (ky or L - ky) x (kz or L - kz) that share it, with the sign
 // flips of the odd components.
-template <typename T, int L>
-__global__ __launch_bounds__(NTYZ) void k_yzconv(cx<T>* __restrict__ Tb,
+template <typename T, int L, int NTY>
+__global__ __launch_bounds__(NTY) void k_yzconv(cx<T>* __restrict__ Tb,
                                                  const cx<T>* const* __restrict__ Dptr,
                                                  const cx<T>* __restrict__ twy,
                                                  const cx<T>* __restrict__ twz, Geo g,
@@ -197,18 +199,18 @@ __global__ __launch_bounds__(NTYZ) void k_yzconv(cx<T>* __restrict__ Tb,
     const int sys = slot_sys[slot];
     const int64_t cplane = int64_t(3) * g.nz * g.ny;
     cx<T>* col = Tb + (int64_t(pos) * g.mx + kx) * cplane;
-    for (int e = tid; e < L * ROW; e += NTYZ) {
+    for (int e = tid; e < L * ROW; e += NTY) {
         const int z = e / ROW, rem = e % ROW, c = rem / SY, y = rem % SY;
         lds[e] = (z < g.nz && y < g.ny) ? col[(int64_t(c) * g.nz + z) * g.ny + y]
                                         : cx<T>{T(0), T(0)};
     }
     __syncthreads();
-    fft_tile<T, L, false, 3 * H, SY, 1, NTYZ>(lds, twy, tid);    // y: lines (z < H, c)
-    fft_tile<T, L, false, 3 * SY, 1, ROW, NTYZ>(lds, twz, tid);  // z: lines (c, ky)
+    fft_tile<T, L, false, 3 * H, SY, 1, NTY>(lds, twy, tid);    // y: lines (z < H, c)
+    fft_tile<T, L, false, 3 * SY, 1, ROW, NTY>(lds, twz, tid);  // z: lines (c, ky)
     const bool fx = kx > g.mx / 2;
     const int kxr = fx ? g.mx - kx : kx;
     const cx<T>* dslab = Dptr[sys] + int64_t(kxr) * 6 * H * H;
-    for (int e = tid; e < H * H; e += NTYZ) {
+    for (int e = tid; e < H * H; e += NTY) {
         const int kzp = e / H, kyp = e % H;
         const cx<T>* dp = dslab + e;
         const cx<T> dxx = dp[0], dxy0 = dp[H * H], dxz0 = dp[2 * H * H];
@@ -233,9 +235,9 @@ __global__ __launch_bounds__(NTYZ) void k_yzconv(cx<T>* __restrict__ Tb,
         }
     }
     __syncthreads();
-    fft_tile<T, L, true, 3 * SY, 1, ROW, NTYZ>(lds, twz, tid);
-    fft_tile<T, L, true, 3 * H, SY, 1, NTYZ>(lds, twy, tid);
-    for (int e = tid; e < 3 * g.nz * g.ny; e += NTYZ) {
+    fft_tile<T, L, true, 3 * SY, 1, ROW, NTY>(lds, twz, tid);
+    fft_tile<T, L, true, 3 * H, SY, 1, NTY>(lds, twy, tid);
+    for (int e = tid; e < 3 * g.nz * g.ny; e += NTY) {
         const int y = e % g.ny, cz = e / g.ny, z = cz % g.nz, c = cz / g.nz;
         col[e] = lds[z * ROW + c * SY + y];
     }
@@ -305,17 +307,31 @@ void launch_ixfft_t(const cx<T>* Tb, const cx<T>* xin, const cx<T>* ainv, cx<T>*
 template <typename T>
 void launch_yzconv(cx<T>* Tb, const cx<T>* const* Dptr, const cx<T>* tw_y, const cx<T>* tw_z,
                    const Geo& g, const int* act, const int* slot_sys, int n_act, SlotFilter f,
-                   hipStream_t s) {
+                   int nthreads, hipStream_t s) {
     if (n_act == 0) return;
     if (!yz_fused_ok(g, int(sizeof(cx<T>)))) throw Error(-1, "yz plane does not fit in LDS");
     dim3 grid(g.mx, n_act);
     switch (g.my) {
 #define DDA_CASE(N)                                                                          \
     case N:                                                                                  \
-        if constexpr (yz_lds_bytes<T, N>() <= (size_t(120) << 10))                           \
-            k_yzconv<T, N><<<grid, NTYZ, 0, s>>>(Tb, Dptr, tw_y, tw_z, g, act, slot_sys, f);    \
-        else                                                                                 \
+        if constexpr (yz_lds_bytes<T, N>() <= (size_t(120) << 10)) {                         \
+            if constexpr (N >= 24) {                                                         \
+                if (nthreads == 256) {                                                       \
+                    k_yzconv<T, N, 256><<<grid, 256, 0, s>>>(Tb, Dptr, tw_y, tw_z, g, act,   \
+                                                             slot_sys, f);                   \
+                    break;                                                                   \
+                }                                                                            \
+                if (nthreads == 1024) {                                                      \
+                    k_yzconv<T, N, 1024><<<grid, 1024, 0, s>>>(Tb, Dptr, tw_y, tw_z, g, act, \
+                                                               slot_sys, f);                 \
+                    break;                                                                   \
+                }                                                                            \
+            }                                                                                \
+            k_yzconv<T, N, NTYZ><<<grid, NTYZ, 0, s>>>(Tb, Dptr, tw_y, tw_z, g, act,         \
+                                                       slot_sys, f);                         \
+        } else {                                                                             \
             throw Error(-1, "yz plane does not fit in LDS");                                 \
+        }                                                                                    \
         break;
         DDA_FOR_EACH_LYZ(DDA_CASE)
 #undef DDA_CASE
@@ -365,10 +381,15 @@ template void launch_ixfft_t<float>(const z64*, const z64*, const z64*, z64*, co
                                     const z64*, const Geo&, const int*, const int*, int, int,
                                     SlotFilter, RedScratch, hipStream_t);
 template void launch_yzconv<double>(z128*, const z128* const*, const z128*, const z128*,
-                                    const Geo&, const int*, const int*, int, SlotFilter,
+                                    const Geo&, const int*, const int*, int, SlotFilter, int,
                                     hipStream_t);
 template void launch_yzconv<float>(z64*, const z64* const*, const z64*, const z64*, const Geo&,
-                                   const int*, const int*, int, SlotFilter, hipStream_t);
+                                   const int*, const int*, int, SlotFilter, int, hipStream_t);
+
+std::vector<int> yz_thread_candidates(int L) {
+    if (L >= 24) return {256, 512, 1024};
+    return {NTYZ};
+}
 template void launch_extract_yz<double>(const z128*, z128*, const Geo&, hipStream_t);
 template void launch_extract_yz<float>(const z128*, z64*, const Geo&, hipStream_t);
 

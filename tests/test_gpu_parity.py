@@ -297,6 +297,43 @@ def test_cocg_graph_replay_equals_direct_launches(precision, timing):
         assert np.array_equal(pk, out[0][0])
 
 
+@pytest.mark.parametrize("shape", [(12, 12, 12), (12, 12, 16)])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_every_autotuner_candidate_gives_identical_matvecs(shape, precision):
+    """The autotuner only regroups lines into blocks: every candidate tile of
+    the fused yz kernel (cubic grid) and of the five-pass z and y passes
+    (my != mz) gives the same matvec to the last bit."""
+    nx, ny, nz = shape
+    mask = np.ones((nz, ny, nx), np.uint8)
+    s = DDASolver(mask, 1.0, 1.45)
+    n = s.n_occ
+    eps = np.full(n, -8 + 0.7j)
+    dt = torch.complex128 if precision == "fp64" else torch.complex64
+    prec = L.DDA_PREC_FP64 if precision == "fp64" else L.DDA_PREC_MIXED
+    x = torch.randn((5, 3, n), dtype=dt, device="cuda")
+    mx, my, mz = s.grid
+    yzc = [0, 256, 512, 1024] if my == mz else [0]
+    zc = [0] if my == mz else [0, 1, 2, 4, 8]
+    mc = [0] if my == mz else [0, 4, 8, 16, 32]
+    ref = None
+    tried = 0
+    for yt in yzc:
+        for zt in zc:
+            for mt in mc:
+                try:
+                    L.dda_set_tuning(s.ctx, prec, zt, mt, yt)
+                except L.DDAError:
+                    continue  # not a candidate for this grid and precision
+                y = s.matvec(2.2, eps, x, precision=precision).cpu().numpy()
+                tried += 1
+                if ref is None:
+                    ref = y
+                else:
+                    assert np.array_equal(y, ref), (yt, zt, mt)
+    assert tried >= 3
+    s.close()
+
+
 # ------------------------------------------------------------ edge cases
 def test_errors_and_degenerate_inputs():
     mask = W.sphere_mask(6, 1.0, 3.0)
