@@ -60,7 +60,7 @@ def kernel_bytes(name: str, nx, ny, nz, mx, my, mz, n_occ, c: int) -> float:
 
 def source_hash() -> str:
     h = hashlib.sha256()
-    for f in ["fft_core.h", "matvec.hip"]:
+    for f in ["fft_core.h", "matvec.hip", "matvec_yz.hip"]:
         with open(os.path.join(ROOT, "paper_2208_01348_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
