@@ -175,8 +175,9 @@ int dda_einc_electron(dda_ctx* ctx, int n_energy, const double* energy_eV, doubl
  *   G(R) = (k^2 I + grad grad) exp(ikR)/R (eq. 5 times 4 pi k^2),
  * with the matvec done as a zero-padded 3D FFT convolution (block-Toeplitz
  * embedding) and alpha_i from m_i^2 = eps_i / m_h^2 (eq. 2) by the chosen
- * polarizability.  eps_dipole [n_energy][n_occ][2] host: absolute particle
- * permittivity per dipole per energy.  einc_dev as written by
+ * polarizability.  eps_dipole [n_energy][n_occ][2]: absolute particle
+ * permittivity per dipole per energy, in host memory (copied in stream order)
+ * or device memory (read in place; the runtime's pointer attributes decide).  einc_dev as written by
  * dda_einc_electron; p_dev complex128 [n_energy*n_traj][3][n_occ] out;
  * info [n_energy*n_traj] host out (may be NULL).
  * Returns DDA_OK when every right-hand side met the tolerance, else the

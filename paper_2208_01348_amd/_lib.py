@@ -124,6 +124,17 @@ def _eps_pairs(eps) -> np.ndarray:
     return e.view(np.float64)
 
 
+def _eps_ptr(eps):
+    """(pointer, keep-alive) for a permittivity array: a contiguous complex128
+    device tensor is passed in place; anything else becomes a host array."""
+    if getattr(eps, "is_cuda", False):
+        if str(eps.dtype) != "torch.complex128" or not eps.is_contiguous():
+            raise ValueError("device permittivities must be contiguous complex128")
+        return eps.data_ptr(), eps
+    e = _eps_pairs(eps)
+    return _ptr(e), e
+
+
 def dda_default_options() -> Options:
     o = Options()
     load().dda_default_options(ctypes.byref(o))
@@ -203,10 +214,10 @@ def dda_solve(ctx, energy_eV, eps_dipole, einc_dev: int, n_traj: int, p_dev: int
               raise_on_error: bool = True):
     """eps_dipole: complex [n_energy][n_occ].  Returns (status, info array)."""
     E = _f64(energy_eV).ravel()
-    eps = _eps_pairs(eps_dipole)
+    eps, keep = _eps_ptr(eps_dipole)
     info = (SolveInfo * max(1, E.size * n_traj))()
-    st = load().dda_solve(ctx, E.size, _ptr(E), _ptr(eps), ctypes.c_void_p(einc_dev), n_traj,
-                          ctypes.c_void_p(p_dev), info)
+    st = load().dda_solve(ctx, E.size, _ptr(E), ctypes.c_void_p(eps), ctypes.c_void_p(einc_dev),
+                          n_traj, ctypes.c_void_p(p_dev), info)
     if raise_on_error and st not in (DDA_OK,):
         _check(st)
     return st, [(i.iters, i.matvecs, i.rel_residual, i.status) for i in info[:E.size * n_traj]]
@@ -217,10 +228,11 @@ def dda_eels_cl(ctx, energy_eV, beta: float, eps_dipole, r0_nm, einc_dev: int,
     """Returns float64 [n_energy * n_traj][4]: P_EELS, P_ext, P_abs, P_CL (1/eV)."""
     E = _f64(energy_eV).ravel()
     R = _f64(r0_nm).reshape(-1, 3)
-    eps = _eps_pairs(eps_dipole)
+    eps, keep = _eps_ptr(eps_dipole)
     out = np.zeros((E.size * R.shape[0], 4), dtype=np.float64)
-    _check(load().dda_eels_cl(ctx, E.size, _ptr(E), float(beta), _ptr(eps), _ptr(R), R.shape[0],
-                              ctypes.c_void_p(einc_dev), ctypes.c_void_p(p_dev), _ptr(out)))
+    _check(load().dda_eels_cl(ctx, E.size, _ptr(E), float(beta), ctypes.c_void_p(eps), _ptr(R),
+                              R.shape[0], ctypes.c_void_p(einc_dev), ctypes.c_void_p(p_dev),
+                              _ptr(out)))
     return out
 
 

@@ -655,6 +655,17 @@ DEntry* get_D(dda_ctx* c, double energy, bool need64) {
 }
 
 // ------------------------------------------------------------ material terms
+// True when p points to device memory (a pageable host pointer is unknown to
+// the runtime and counts as host memory).
+bool is_device_ptr(const void* p) {
+    hipPointerAttribute_t a{};
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice;
+}
+
 // Copies the permittivities of systems [e0, e0 + ns) to the device and
 // evaluates there, per dipole, 1/alpha (FP64 if need128, FP32 if need64) and,
 // if w_dev is given, the absorption weight [ns][n_occ].  A non-finite
@@ -665,7 +676,7 @@ void compute_material(dda_ctx* c, const double* energy, const double* eps, int e
     const int64_t n = c->g.n_occ;
     const size_t cnt = size_t(ns) * size_t(n);
     if (cnt == 0) return;
-    c->eps_dev.ensure(cnt * sizeof(z128));
+    c->eps_dev.ensure(cnt * sizeof(z128));  // staging for a host array
     std::vector<dda::MatSys> hs(ns);
     for (int i = 0; i < ns; ++i) {
         const cplx k = c->mh * (energy[e0 + i] / kHbarC);
@@ -675,14 +686,18 @@ void compute_material(dda_ctx* c, const double* energy, const double* eps, int e
     const size_t sb_al = (sb + 255) / 256 * 256;
     c->matsys.ensure(sb_al + size_t(ns) * sizeof(int));
     int* err = reinterpret_cast<int*>(c->matsys.as<char>() + sb_al);
-    DDA_HIP_CHECK(hipMemcpyAsync(c->eps_dev.p, eps + 2 * int64_t(e0) * n, cnt * sizeof(z128),
-                                 hipMemcpyHostToDevice, c->stream));
+    const z128* eps_dev = reinterpret_cast<const z128*>(eps) + int64_t(e0) * n;
+    if (!is_device_ptr(eps)) {  // host array: upload the chunk
+        DDA_HIP_CHECK(hipMemcpyAsync(c->eps_dev.p, eps + 2 * int64_t(e0) * n, cnt * sizeof(z128),
+                                     hipMemcpyHostToDevice, c->stream));
+        eps_dev = c->eps_dev.as<z128>();
+    }
     DDA_HIP_CHECK(hipMemcpyAsync(c->matsys.p, hs.data(), sb, hipMemcpyHostToDevice, c->stream));
     DDA_HIP_CHECK(hipMemsetAsync(err, 0, size_t(ns) * sizeof(int), c->stream));
     if (need128) c->ainv128.ensure(cnt * sizeof(z128));
     if (need64) c->ainv64.ensure(cnt * sizeof(z64));
     dda::MatParams mp{c->opt.polarizability, c->d};
-    dda::launch_material(c->eps_dev.as<z128>(), c->matsys.as<dda::MatSys>(), n, ns, mp, nullptr,
+    dda::launch_material(eps_dev, c->matsys.as<dda::MatSys>(), n, ns, mp, nullptr,
                          need128 ? c->ainv128.as<z128>() : nullptr,
                          need64 ? c->ainv64.as<z64>() : nullptr, w_dev, err, c->stream);
     c->host_misc.ensure(size_t(ns) * sizeof(int));

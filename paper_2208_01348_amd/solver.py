@@ -95,6 +95,13 @@ class DDASolver:
             if cur.cuda_stream != self.stream.cuda_stream:
                 cur.wait_stream(self.stream)
 
+    def _eps(self, eps, n_energy: int):
+        if isinstance(eps, torch.Tensor) and eps.is_cuda:
+            if eps.numel() != n_energy * self.n_occ:
+                raise ValueError("eps must hold n_energy x n_occ values")
+            return eps.contiguous()
+        return np.asarray(eps, dtype=np.complex128).reshape(n_energy, self.n_occ)
+
     def _field(self, nrhs: int, dtype=torch.complex128) -> torch.Tensor:
         return torch.empty((nrhs, 3, self.n_occ), dtype=dtype, device=self.device)
 
@@ -109,10 +116,11 @@ class DDASolver:
 
     def solve(self, energies: Sequence[float], eps: np.ndarray, einc: torch.Tensor,
               n_traj: int, out: Optional[torch.Tensor] = None, raise_on_error: bool = True):
-        """eps: complex [n_energy][n_occ] (absolute permittivity per dipole)."""
+        """eps: complex [n_energy][n_occ] (absolute permittivity per dipole), a
+        host array or a contiguous complex128 tensor on the device."""
         E = np.atleast_1d(np.asarray(energies, dtype=np.float64))
         p = out if out is not None else self._field(E.size * n_traj)
-        eps = np.asarray(eps, dtype=np.complex128).reshape(E.size, self.n_occ)
+        eps = self._eps(eps, E.size)
         with self._ordered():
             st, info = L.dda_solve(self.ctx, E, eps, einc.data_ptr(), n_traj, p.data_ptr(),
                                    raise_on_error=raise_on_error)
@@ -121,7 +129,7 @@ class DDASolver:
     def losses(self, energies: Sequence[float], beta: float, eps: np.ndarray, r0: np.ndarray,
                einc: torch.Tensor, p: torch.Tensor) -> np.ndarray:
         E = np.atleast_1d(np.asarray(energies, dtype=np.float64))
-        eps = np.asarray(eps, dtype=np.complex128).reshape(E.size, self.n_occ)
+        eps = self._eps(eps, E.size)
         with self._ordered():
             return L.dda_eels_cl(self.ctx, E, beta, eps, r0, einc.data_ptr(), p.data_ptr())
 

@@ -334,6 +334,22 @@ def test_every_autotuner_candidate_gives_identical_matvecs(shape, precision):
     s.close()
 
 
+def test_device_resident_permittivities_equal_host_ones():
+    """Permittivities passed in device memory are read in place and give the
+    same solution and probabilities as the same values passed from the host."""
+    mask, d, r0 = _small_particle()
+    n = int(mask.sum())
+    E = np.array([1.6, 2.4])
+    eps = np.repeat(W.drude_eps(E)[:, None], n, axis=1)
+    eps[:, ::7] *= 1.3  # not homogeneous
+    s = DDASolver(mask, d, 1.45, tol=1e-10, solver="cocg", precision="mixed")
+    P_h, info_h = s.spectrum(E, 0.55, eps, r0)
+    P_d, info_d = s.spectrum(E, 0.55, torch.from_numpy(eps).cuda(), r0)
+    assert [i.iters for i in info_h] == [i.iters for i in info_d]
+    assert np.array_equal(P_h, P_d)
+    s.close()
+
+
 # ------------------------------------------------------------ edge cases
 def test_errors_and_degenerate_inputs():
     mask = W.sphere_mask(6, 1.0, 3.0)
