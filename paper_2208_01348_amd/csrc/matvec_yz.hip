@@ -243,6 +243,245 @@ __global__ __launch_bounds__(NTY) void k_yzconv(cx<T>* __restrict__ Tb,
     }
 }
 
+// ------------------------------------------------------ YZ (registers) -----
+// The same column pass for L = 16 ... 64 (L divisible by 8) with the line
+// transforms held in registers.  A line of length L belongs to a quad of
+// adjacent lanes: lane n2 holds the L/4 points x[4 n1 + n2] and takes their
+// L/4-point DFT in registers (compile-time Stockham stages); after the twiddle
+// W_L^{n2 k1} the four lanes finish with a radix-4 butterfly through quad DPP
+// moves, lane n2 ending with X[k1 + (L/4) rev2(n2)] (rev2 swaps the two bits).
+// LDS only carries the transposes between the y and z passes: the plane as
+// rows [c][ky] of length L + 1, over z.
+//   phase 1: y-FFT of the lines (c, z < nz), loaded straight from HBM (the
+//            zero padding y >= ny is never read), stored to LDS by ky;
+//   phase 2: one quad per (c, ky): z-FFT back into its row; then D u over
+//            all (ky, kz) by every thread; then one quad per (c, ky) again for
+//            the z-iFFT (quad_fft_blk), keeping z < nz;
+//   phase 3: y-iFFT of the lines (c, z < nz), y < ny stored straight to HBM.
+template <int L>
+constexpr bool yzr_ok() { return L % 8 == 0 && L >= 16 && L <= 64; }
+template <int L>
+constexpr int yzr_threads() { return (12 * L + 63) / 64 * 64; }  // a quad per (c, ky)
+
+// Quad lane exchange (every lane of a quad is active): bound_ctrl set and a
+// zero old value let the compiler fold the move into the consuming add.
+__device__ __forceinline__ float dpp_x1(float v) {  // value of lane ^ 1 (quad_perm 1,0,3,2)
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float dpp_x2(float v) {  // value of lane ^ 2 (quad_perm 2,3,0,1)
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, true));
+}
+__device__ __forceinline__ double dpp_x1(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, int(b), 0xB1, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), 0xB1, 0xF, 0xF, true);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+__device__ __forceinline__ double dpp_x2(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, int(b), 0x4E, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), 0x4E, 0xF, 0xF, true);
+    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+
+// Q-point DFT of v in registers, natural order in and out; the stage plan is
+// the Stockham plan of fft_core.h with twiddles W_Q^t = tw[t L/Q].
+template <typename T, int L, int Q, int NS, bool INV>
+__device__ __forceinline__ void reg_stages(cx<T> (&v)[Q], const cx<T>* __restrict__ tw) {
+    if constexpr (NS < Q) {
+        constexpr int R = pick_radix(Q / NS);
+        static_assert(R > 1, "line length must be 2^a 3^b");
+        constexpr int QR = Q / R;
+        cx<T> w[Q];
+#pragma unroll
+        for (int j = 0; j < QR; ++j) {
+            cx<T> a[R];
+#pragma unroll
+            for (int m = 0; m < R; ++m) a[m] = v[j + m * QR];
+            const int k = j % NS;
+            if (NS > 1 && k != 0) {
+#pragma unroll
+                for (int m = 1; m < R; ++m) {
+                    cx<T> t = tw[(m * k * (Q / (NS * R))) * (L / Q)];
+                    if (INV) t.y = -t.y;
+                    a[m] = a[m] * t;
+                }
+            }
+            dft<R, INV>(a);
+            const int base = (j / NS) * NS * R + k;
+#pragma unroll
+            for (int m = 0; m < R; ++m) w[base + m * NS] = a[m];
+        }
+#pragma unroll
+        for (int i = 0; i < Q; ++i) v[i] = w[i];
+        reg_stages<T, L, Q, NS * R, INV>(v, tw);
+    }
+}
+
+// DFT of one line of length L spread over a lane quad (see above).
+template <typename T, int L, bool INV>
+__device__ __forceinline__ void quad_fft(cx<T> (&v)[L / 4], int n2, const cx<T>* __restrict__ tw) {
+    constexpr int Q = L / 4;
+    reg_stages<T, L, Q, 1, INV>(v, tw);
+#pragma unroll
+    for (int k1 = 1; k1 < Q; ++k1) {
+        cx<T> t = tw[n2 * k1];
+        if (INV) t.y = -t.y;
+        v[k1] = v[k1] * t;
+    }
+    // butterflies as partner + sign * own: the lower lane of a pair adds,
+    // the upper one subtracts, with no select
+    const bool hi = (n2 & 2) != 0, odd = (n2 & 1) != 0;
+    const T s2 = hi ? T(-1) : T(1), s1 = odd ? T(-1) : T(1);
+#pragma unroll
+    for (int k1 = 0; k1 < Q; ++k1) {  // pairs (n2, n2 ^ 2); W_4 on lane 3
+        cx<T> r{dpp_x2(v[k1].x) + s2 * v[k1].x, dpp_x2(v[k1].y) + s2 * v[k1].y};
+        if (hi && odd) r = mul_mi<INV>(r);
+        v[k1] = r;
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < Q; ++k1)  // pairs (n2, n2 ^ 1)
+        v[k1] = cx<T>{dpp_x1(v[k1].x) + s1 * v[k1].x, dpp_x1(v[k1].y) + s1 * v[k1].y};
+}
+
+// The mirror image of quad_fft: input in the layout quad_fft leaves (lane l
+// holds X[k1 + (L/4) rev2(l)]), output decimated (lane n2 holds
+// y[4 n1 + n2], n1 in natural order).  Radix-4 across the quad first (pairs
+// l ^ 1, the factor W_4 on lane 3, pairs l ^ 2), then the twiddle
+// W_L^{n2 k1} and the L/4-point DFT in registers.
+template <typename T, int L, bool INV>
+__device__ __forceinline__ void quad_fft_blk(cx<T> (&v)[L / 4], int n2,
+                                             const cx<T>* __restrict__ tw) {
+    constexpr int Q = L / 4;
+    const bool hi = (n2 & 2) != 0, odd = (n2 & 1) != 0;
+    const T s2 = hi ? T(-1) : T(1), s1 = odd ? T(-1) : T(1);
+#pragma unroll
+    for (int k1 = 0; k1 < Q; ++k1) {
+        cx<T> r{dpp_x1(v[k1].x) + s1 * v[k1].x, dpp_x1(v[k1].y) + s1 * v[k1].y};
+        if (hi && odd) r = mul_mi<INV>(r);
+        v[k1] = r;
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < Q; ++k1)
+        v[k1] = cx<T>{dpp_x2(v[k1].x) + s2 * v[k1].x, dpp_x2(v[k1].y) + s2 * v[k1].y};
+#pragma unroll
+    for (int k1 = 1; k1 < Q; ++k1) {
+        cx<T> t = tw[n2 * k1];
+        if (INV) t.y = -t.y;
+        v[k1] = v[k1] * t;
+    }
+    reg_stages<T, L, Q, 1, INV>(v, tw);
+}
+
+template <typename T, int L>
+__global__ __launch_bounds__(yzr_threads<L>()) void k_yzconv_r(
+    cx<T>* __restrict__ Tb, const cx<T>* const* __restrict__ Dptr, const cx<T>* __restrict__ twy,
+    const cx<T>* __restrict__ twz, Geo g, const int* __restrict__ act,
+    const int* __restrict__ slot_sys, SlotFilter f) {
+    constexpr int Q = L / 4;
+    constexpr int ZS = L + 1;      // LDS row stride over z / kz
+    constexpr int HD = L / 2 + 1;  // D slab corner
+    constexpr int NTR = yzr_threads<L>();
+    __shared__ cx<T> lds[3 * L * ZS];
+    const int tid = threadIdx.x;
+    const int grp = tid >> 2, n2 = tid & 3;
+    const int rb = ((n2 & 1) << 1) | (n2 >> 1);  // rev2(n2)
+    const int kx = blockIdx.x;
+    const int pos = blockIdx.y;
+    const int slot = act ? act[pos] : pos;
+    if (!slot_live(f, slot)) return;
+    const int sys = slot_sys[slot];
+    const int nz = g.nz, ny = g.ny;
+    cx<T>* col = Tb + (int64_t(pos) * g.mx + kx) * (int64_t(3) * nz * ny);
+    const cx<T> zero{T(0), T(0)};
+
+    // phase 1: y-FFT of the lines (c, z)
+    for (int line = grp; line < 3 * nz; line += NTR / 4) {
+        const int c = line / nz, z = line - (line / nz) * nz;
+        const cx<T>* src = col + int64_t(line) * ny;
+        cx<T> v[Q];
+#pragma unroll
+        for (int n1 = 0; n1 < Q; ++n1) {
+            const int y = 4 * n1 + n2;
+            v[n1] = (n1 < Q / 2 && y < ny) ? src[y] : zero;
+        }
+        quad_fft<T, L, false>(v, n2, twy);
+#pragma unroll
+        for (int k1 = 0; k1 < Q; ++k1) lds[(c * L + k1 + Q * rb) * ZS + z] = v[k1];
+    }
+    __syncthreads();
+
+    // phase 2a: z-FFT of the rows (c, ky), spectrum back into the row
+    if (grp < 3 * L) {
+        cx<T>* row = lds + grp * ZS;
+        cx<T> u[Q];
+#pragma unroll
+        for (int n1 = 0; n1 < Q; ++n1) {
+            const int z = 4 * n1 + n2;
+            u[n1] = (n1 < Q / 2 && z < nz) ? row[z] : zero;
+        }
+        quad_fft<T, L, false>(u, n2, twz);
+#pragma unroll
+        for (int k1 = 0; k1 < Q; ++k1) row[k1 + Q * rb] = u[k1];
+    }
+    __syncthreads();
+    // phase 2b: D u at every (ky, kz); consecutive lanes take consecutive ky,
+    // the fastest index of the D slab (coalesced loads; LDS rows at an odd
+    // stride keep the accesses in distinct banks).  One D load serves the
+    // mirrored frequencies through the parity of each component.
+    {
+        const bool fx = kx > g.mx / 2;
+        const int kxr = fx ? g.mx - kx : kx;
+        const cx<T>* __restrict__ dslab = Dptr[sys] + int64_t(kxr) * 6 * HD * HD;
+        for (int e = tid; e < L * L; e += NTR) {
+            const int kz = e / L, ky = e - (e / L) * L;
+            const bool fy = ky > L / 2, fz = kz > L / 2;
+            const int o = (fz ? L - kz : kz) * HD + (fy ? L - ky : ky);
+            const cx<T> dxx = dslab[o], dyy = dslab[o + 3 * HD * HD], dzz = dslab[o + 5 * HD * HD];
+            cx<T> dxy = dslab[o + HD * HD], dxz = dslab[o + 2 * HD * HD];
+            cx<T> dyz = dslab[o + 4 * HD * HD];
+            if (fx != fy) dxy = -dxy;
+            if (fx != fz) dxz = -dxz;
+            if (fy != fz) dyz = -dyz;
+            cx<T>* u = lds + ky * ZS + kz;
+            const cx<T> ux = u[0], uy = u[L * ZS], uz = u[2 * L * ZS];
+            u[0] = dxx * ux + dxy * uy + dxz * uz;
+            u[L * ZS] = dxy * ux + dyy * uy + dyz * uz;
+            u[2 * L * ZS] = dxz * ux + dyz * uy + dzz * uz;
+        }
+    }
+    __syncthreads();
+    // phase 2c: z-iFFT of the rows (c, ky), keeping z < nz
+    if (grp < 3 * L) {
+        cx<T>* row = lds + grp * ZS;
+        cx<T> u[Q];
+#pragma unroll
+        for (int k1 = 0; k1 < Q; ++k1) u[k1] = row[k1 + Q * rb];
+        quad_fft_blk<T, L, true>(u, n2, twz);
+#pragma unroll
+        for (int n1 = 0; n1 < Q / 2; ++n1) {  // z = 4 n1 + n2 < nz <= L/2
+            const int z = 4 * n1 + n2;
+            if (z < nz) row[z] = u[n1];
+        }
+    }
+    __syncthreads();
+
+    // phase 3: y-iFFT of the lines (c, z), y < ny back to HBM
+    for (int line = grp; line < 3 * nz; line += NTR / 4) {
+        const int c = line / nz, z = line - (line / nz) * nz;
+        cx<T> v[Q];
+#pragma unroll
+        for (int n1 = 0; n1 < Q; ++n1) v[n1] = lds[(c * L + 4 * n1 + n2) * ZS + z];
+        quad_fft<T, L, true>(v, n2, twy);
+        cx<T>* dst = col + int64_t(line) * ny;
+#pragma unroll
+        for (int k1 = 0; k1 < Q; ++k1) {
+            const int y = k1 + Q * rb;
+            if (y < ny) dst[y] = v[k1];
+        }
+    }
+}
+
 // ------------------------------------------------------------ launchers ----
 #define DDA_FOR_EACH_LX(X) \
     X(1) X(2) X(3) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512)
@@ -314,19 +553,11 @@ void launch_yzconv(cx<T>* Tb, const cx<T>* const* Dptr, const cx<T>* tw_y, const
     switch (g.my) {
 #define DDA_CASE(N)                                                                          \
     case N:                                                                                  \
-        if constexpr (yz_lds_bytes<T, N>() <= (size_t(120) << 10)) {                         \
-            if constexpr (N >= 24) {                                                         \
-                if (nthreads == 256) {                                                       \
-                    k_yzconv<T, N, 256><<<grid, 256, 0, s>>>(Tb, Dptr, tw_y, tw_z, g, act,   \
-                                                             slot_sys, f);                   \
-                    break;                                                                   \
-                }                                                                            \
-                if (nthreads == 1024) {                                                      \
-                    k_yzconv<T, N, 1024><<<grid, 1024, 0, s>>>(Tb, Dptr, tw_y, tw_z, g, act, \
+        if constexpr (yzr_ok<N>() && yz_lds_bytes<T, N>() <= (size_t(120) << 10)) {        \
+            (void)nthreads;                                                                  \
+            k_yzconv_r<T, N><<<grid, yzr_threads<N>(), 0, s>>>(Tb, Dptr, tw_y, tw_z, g, act, \
                                                                slot_sys, f);                 \
-                    break;                                                                   \
-                }                                                                            \
-            }                                                                                \
+        } else if constexpr (yz_lds_bytes<T, N>() <= (size_t(120) << 10)) {                  \
             k_yzconv<T, N, NTYZ><<<grid, NTYZ, 0, s>>>(Tb, Dptr, tw_y, tw_z, g, act,         \
                                                        slot_sys, f);                         \
         } else {                                                                             \
@@ -387,7 +618,7 @@ template void launch_yzconv<float>(z64*, const z64* const*, const z64*, const z6
                                    const int*, const int*, int, SlotFilter, int, hipStream_t);
 
 std::vector<int> yz_thread_candidates(int L) {
-    if (L >= 24) return {256, 512, 1024};
+    (void)L;  // the register kernel has one shape per L
     return {NTYZ};
 }
 template void launch_extract_yz<double>(const z128*, z128*, const Geo&, hipStream_t);

@@ -301,8 +301,8 @@ def test_cocg_graph_replay_equals_direct_launches(precision, timing):
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_every_autotuner_candidate_gives_identical_matvecs(shape, precision):
     """The autotuner only regroups lines into blocks: every candidate tile of
-    the fused yz kernel (cubic grid) and of the five-pass z and y passes
-    (my != mz) gives the same matvec to the last bit."""
+    the five-pass z and y passes (my != mz) gives the same matvec to the last
+    bit (the fused yz kernel of a cubic grid has a single shape per length)."""
     nx, ny, nz = shape
     mask = np.ones((nz, ny, nx), np.uint8)
     s = DDASolver(mask, 1.0, 1.45)
@@ -330,7 +330,7 @@ def test_every_autotuner_candidate_gives_identical_matvecs(shape, precision):
                     ref = y
                 else:
                     assert np.array_equal(y, ref), (yt, zt, mt)
-    assert tried >= 3
+    assert tried >= (1 if my == mz else 3)
     s.close()
 
 
