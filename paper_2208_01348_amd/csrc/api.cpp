@@ -511,7 +511,7 @@ void autotune(dda_ctx* c, const Work& w, const int* act, int n_act,
 // the COCG scalars fused; then fuse_r gives the direction update
 // x <- fuse_r + beta x done in place by the first kernel).
 int pack_blocks(const dda_ctx* c, int csize) {
-    return dda::yz_fused_ok(c->g, csize) ? dda::yz_pack_blocks_per_slot(c->g)
+    return dda::yz_fused_ok(c->g, csize) ? dda::yz_pack_blocks_per_slot(c->g, csize)
                                          : dda::pack_blocks_per_slot(c->g);
 }
 
@@ -1467,7 +1467,8 @@ int dda_setup(const uint8_t* mask, int nx, int ny, int nz, double d_nm, double m
     }
     g.n_occ = int64_t(c->occ_lin.size());
     c->max_blocks = std::max(1024, std::max(dda::pack_blocks_per_slot(g),
-                                            dda::yz_pack_blocks_per_slot(g)));
+                                            std::max(dda::yz_pack_blocks_per_slot(g, 8),
+                                                     dda::yz_pack_blocks_per_slot(g, 16))));
     // uploads go through the context's stream (never the legacy stream, which
     // must not touch a stream another thread is capturing)
     c->map.ensure(size_t(N) * sizeof(int));

@@ -103,16 +103,18 @@ __device__ __forceinline__ void dft(cx<T>* a) {
 }
 
 template <typename T, int L, int R, int NS, bool INV, int NLINES, int LS, int ES, int NTHR>
-__device__ __forceinline__ void fft_stage(cx<T>* lds, const cx<T>* __restrict__ tw, int tid) {
+__device__ __forceinline__ void fft_stage(cx<T>* lds, const cx<T>* __restrict__ tw, int tid,
+                                          int nl) {
     constexpr int LR = L / R;
     constexpr int NB = NLINES * LR;
     constexpr int NQ = (NB + NTHR - 1) / NTHR;
     constexpr bool LINE_FAST = (ES != 1);
+    const int nb = nl * LR;  // nl <= NLINES lines are live
     cx<T> v[NQ][R];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         const int b = tid + q * NTHR;
-        if ((NB % NTHR == 0) || b < NB) {
+        if (b < nb) {
             const int line = LINE_FAST ? b % NLINES : b / LR;
             const int j = LINE_FAST ? b / NLINES : b % LR;
 #pragma unroll
@@ -123,7 +125,7 @@ __device__ __forceinline__ void fft_stage(cx<T>* lds, const cx<T>* __restrict__ 
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         const int b = tid + q * NTHR;
-        if ((NB % NTHR == 0) || b < NB) {
+        if (b < nb) {
             const int line = LINE_FAST ? b % NLINES : b / LR;
             const int j = LINE_FAST ? b / NLINES : b % LR;
             const int k = j % NS;
@@ -145,22 +147,25 @@ __device__ __forceinline__ void fft_stage(cx<T>* lds, const cx<T>* __restrict__ 
 }
 
 template <typename T, int L, int NS, bool INV, int NLINES, int LS, int ES, int NTHR>
-__device__ __forceinline__ void fft_stages(cx<T>* lds, const cx<T>* __restrict__ tw, int tid) {
+__device__ __forceinline__ void fft_stages(cx<T>* lds, const cx<T>* __restrict__ tw, int tid,
+                                           int nl) {
     if constexpr (NS < L) {
         constexpr int R = pick_radix(L / NS);
         static_assert(R > 1, "FFT length must be 2^a 3^b");
-        fft_stage<T, L, R, NS, INV, NLINES, LS, ES, NTHR>(lds, tw, tid);
-        fft_stages<T, L, NS * R, INV, NLINES, LS, ES, NTHR>(lds, tw, tid);
+        fft_stage<T, L, R, NS, INV, NLINES, LS, ES, NTHR>(lds, tw, tid, nl);
+        fft_stages<T, L, NS * R, INV, NLINES, LS, ES, NTHR>(lds, tw, tid, nl);
     }
 }
 
 // Unnormalised DFT (forward: exp(-2 pi i jk/L); inverse: exp(+2 pi i jk/L))
 // of NLINES lines held in LDS.  tw[t] = exp(-2 pi i t / L), t < L.
-// Must be called by all NTHR threads of the block; ends with a barrier.
+// Must be called by all NTHR threads of the block; ends with a barrier.  Only
+// the first nl lines are transformed (nl <= NLINES; ES == 1 when nl < NLINES).
 template <typename T, int L, bool INV, int NLINES, int LS, int ES, int NTHR>
-__device__ __forceinline__ void fft_tile(cx<T>* lds, const cx<T>* __restrict__ tw, int tid) {
+__device__ __forceinline__ void fft_tile(cx<T>* lds, const cx<T>* __restrict__ tw, int tid,
+                                         int nl = NLINES) {
     static_assert(fft_size_ok(L), "FFT length must be 2^a 3^b");
-    fft_stages<T, L, 1, INV, NLINES, LS, ES, NTHR>(lds, tw, tid);
+    fft_stages<T, L, 1, INV, NLINES, LS, ES, NTHR>(lds, tw, tid, nl);
 }
 
 }  // namespace dda

@@ -88,7 +88,8 @@ int64_t dyz_elems(const Geo& g);
 // components fits in LDS (my == mz, see yz_fused_ok).  The work buffer holds
 // T[pos][kx][3][nz][ny] (at most grid_elems).
 bool yz_fused_ok(const Geo& g, int csize);
-int yz_pack_blocks_per_slot(const Geo& g);
+// partial reduction rows per slot of the fused pack kernel (csize: 8 or 16)
+int yz_pack_blocks_per_slot(const Geo& g, int csize);
 template <typename T>
 void launch_xfft_t(cx<T>* xin, const int* map, cx<T>* Tb, const cx<T>* tw_x, const Geo& g,
                    const int* act, int n_act, const cx<T>* fuse_r, SlotFilter f, hipStream_t s);

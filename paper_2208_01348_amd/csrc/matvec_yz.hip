@@ -25,9 +25,14 @@ constexpr int NTYZ = 512;  // yz kernel, default threads per block (the autotune
                            // may pick 256 or 1024 for L >= 24; the butterflies
                            // are the same whichever thread computes them)
 
-// rows of one (component, z) plane per x-kernel block
-template <int LX>
-constexpr int xrows() { return LX >= 1024 ? 2 : 2048 / LX; }
+// At most this many rows of one (component, z) plane per x-kernel block
+// (about 37 KB of LDS); the rows of a plane are split evenly over
+// ceil(ny / max) blocks.
+template <typename T, int LX>
+constexpr int xrows_max() {
+    constexpr int r = (sizeof(T) == 4 ? 4608 : 2304) / LX;
+    return r < 1 ? 1 : r > 64 ? 64 : r;
+}
 
 template <typename T, int L>
 constexpr size_t yz_lds_bytes() { return size_t(L) * 3 * (L + 1) * 2 * sizeof(T); }
@@ -41,12 +46,14 @@ bool yz_fused_ok(const Geo& g, int csize) {
     return L * 3 * (L + 1) * size_t(csize) <= size_t(120) << 10;
 }
 
-static int xgroups(const Geo& g) {
-    int nr = 0;
+// (row groups per plane, rows per group) of the x kernels
+template <typename T>
+static void xsplit(const Geo& g, int& ng, int& nr) {
+    int rmax = 0;
     switch (g.mx) {
-#define DDA_CASE(N) \
-    case N:         \
-        nr = xrows<N>(); \
+#define DDA_CASE(N)                   \
+    case N:                           \
+        rmax = xrows_max<T, N>();     \
         break;
         DDA_CASE(1) DDA_CASE(2) DDA_CASE(3) DDA_CASE(4) DDA_CASE(6) DDA_CASE(8) DDA_CASE(12)
         DDA_CASE(16) DDA_CASE(24) DDA_CASE(32) DDA_CASE(48) DDA_CASE(64) DDA_CASE(96)
@@ -55,12 +62,25 @@ static int xgroups(const Geo& g) {
         default:
             throw Error(-1, "unsupported FFT length along x");
     }
-    return (g.ny + nr - 1) / nr;
+    ng = (g.ny + rmax - 1) / rmax;
+    nr = (g.ny + ng - 1) / ng;
 }
 
-int yz_pack_blocks_per_slot(const Geo& g) { return 3 * g.nz * xgroups(g); }
+static int xgroups(const Geo& g, int csize) {
+    int ng, nr;
+    if (csize == int(sizeof(cx<float>))) xsplit<float>(g, ng, nr);
+    else xsplit<double>(g, ng, nr);
+    return ng;
+}
+
+int yz_pack_blocks_per_slot(const Geo& g, int csize) { return 3 * g.nz * xgroups(g, csize); }
 
 // ------------------------------------------------------------------ X1 -----
+// One block: rows y0 .. y0 + nrow - 1 of the (component c, z) plane.  The
+// gather issues every index load of a thread before any data load, and every
+// data load before the first use, so a block waits for memory twice rather
+// than once per element.  Only x < HX = ceil(LX / 2) can be occupied
+// (LX >= 2 nx - 1).
 template <typename T, int LX, bool FUSE_P>
 __global__ __launch_bounds__(NT) void k_xfft_t(cx<T>* __restrict__ xin,
                                                const int* __restrict__ map,
@@ -68,9 +88,11 @@ __global__ __launch_bounds__(NT) void k_xfft_t(cx<T>* __restrict__ xin,
                                                const cx<T>* __restrict__ tw, Geo g,
                                                const int* __restrict__ act,
                                                const cx<T>* __restrict__ fuse_r, SlotFilter f,
-                                               int ngroups) {
-    constexpr int NR = xrows<LX>();
-    constexpr int LP = LX + 1;  // padded LDS row: the transposed read below hits spread banks
+                                               int ngroups, int nr) {
+    constexpr int NR = xrows_max<T, LX>();
+    constexpr int LP = LX + 1;  // padded LDS row: the transposed accesses hit spread banks
+    constexpr int HX = (LX + 1) / 2;
+    constexpr int NE = (NR * HX + NT - 1) / NT;
     __shared__ cx<T> lds[NR * LP];
     const int tid = threadIdx.x;
     const int pos = blockIdx.y;
@@ -79,7 +101,8 @@ __global__ __launch_bounds__(NT) void k_xfft_t(cx<T>* __restrict__ xin,
     const int grp = blockIdx.x % ngroups;
     const int cz = blockIdx.x / ngroups;
     const int c = cz / g.nz, z = cz - (cz / g.nz) * g.nz;
-    const int y0 = grp * NR;
+    const int y0 = grp * nr;
+    const int nrow = min(nr, g.ny - y0);
     cx<T>* src = xin + (slot * 3 + c) * g.n_occ;
     const cx<T>* rsrc = FUSE_P ? fuse_r + (slot * 3 + c) * g.n_occ : nullptr;
     cx<T> beta{T(0), T(0)};
@@ -88,30 +111,48 @@ __global__ __launch_bounds__(NT) void k_xfft_t(cx<T>* __restrict__ xin,
         beta = cvt<T>(f.st[slot].beta);
         reset = f.st[slot].reset_p != 0;
     }
-    for (int e = tid; e < NR * LX; e += NT) {
-        const int r = e / LX, x = e % LX;
-        const int y = y0 + r;
-        cx<T> v{T(0), T(0)};
-        if (y < g.ny && x < g.nx) {
-            const int idx = map[(int64_t(z) * g.ny + y) * g.nx + x];
-            if (idx >= 0) {
-                v = src[idx];
-                if (FUSE_P) {  // each occupied element is visited by exactly one thread
-                    v = reset ? rsrc[idx] : rsrc[idx] + beta * v;
-                    src[idx] = v;
-                }
-            }
+    // loads use clamped (always valid) addresses and are masked afterwards, so
+    // that none of them sits behind a branch and all can be in flight at once
+    const int* mrow = map + (int64_t(z) * g.ny + y0) * g.nx;
+    int idx[NE];
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+        const int e = tid + q * NT;
+        const int r = e / HX, x = e - (e / HX) * HX;
+        const int m = mrow[min(r, nrow - 1) * g.nx + min(x, g.nx - 1)];
+        idx[q] = (r < nrow && x < g.nx) ? m : -1;
+    }
+    cx<T> v[NE], w[NE];
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+        const int i = max(idx[q], 0);
+        v[q] = src[i];
+        if (FUSE_P) w[q] = rsrc[i];
+    }
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+        if (idx[q] < 0) v[q] = cx<T>{T(0), T(0)};
+    }
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+        const int e = tid + q * NT;
+        const int r = e / HX, x = e - (e / HX) * HX;
+        if (FUSE_P && idx[q] >= 0) {  // each occupied element is visited by exactly one thread
+            v[q] = reset ? w[q] : w[q] + beta * v[q];
+            src[idx[q]] = v[q];
         }
-        lds[r * LP + x] = v;
+        if (r < nrow) {
+            lds[r * LP + x] = v[q];
+            if (x + HX < LX) lds[r * LP + x + HX] = cx<T>{T(0), T(0)};
+        }
     }
     __syncthreads();
-    fft_tile<T, LX, false, NR, LP, 1, NT>(lds, tw, tid);
+    fft_tile<T, LX, false, NR, LP, 1, NT>(lds, tw, tid, nrow);
     const int64_t cplane = int64_t(3) * g.nz * g.ny;  // one kx column
-    cx<T>* dst = Tb + int64_t(pos) * g.mx * cplane + (int64_t(c) * g.nz + z) * g.ny;
-    for (int e = tid; e < NR * LX; e += NT) {
-        const int kx = e / NR, r = e % NR;
-        const int y = y0 + r;
-        if (y < g.ny) dst[kx * cplane + y] = lds[r * LP + kx];
+    cx<T>* dst = Tb + int64_t(pos) * g.mx * cplane + (int64_t(c) * g.nz + z) * g.ny + y0;
+    for (int e = tid; e < nrow * LX; e += NT) {
+        const int kx = e / nrow, r = e - (e / nrow) * nrow;
+        dst[kx * cplane + r] = lds[r * LP + kx];
     }
 }
 
@@ -125,9 +166,12 @@ __global__ __launch_bounds__(NT) void k_ixfft_t(const cx<T>* __restrict__ Tb,
                                                 const cx<T>* __restrict__ tw, Geo g,
                                                 const int* __restrict__ act,
                                                 const int* __restrict__ slot_sys, SlotFilter f,
-                                                RedScratch red, int ngroups) {
-    constexpr int NR = xrows<LX>();
+                                                RedScratch red, int ngroups, int nr) {
+    constexpr int NR = xrows_max<T, LX>();
     constexpr int LP = LX + 1;
+    constexpr int HX = (LX + 1) / 2;
+    constexpr int NL = (NR * LX + NT - 1) / NT;
+    constexpr int NE = (NR * HX + NT - 1) / NT;
     __shared__ cx<T> lds[NR * LP];
     const int tid = threadIdx.x;
     const int pos = blockIdx.y;
@@ -137,36 +181,62 @@ __global__ __launch_bounds__(NT) void k_ixfft_t(const cx<T>* __restrict__ Tb,
     const int grp = blockIdx.x % ngroups;
     const int cz = blockIdx.x / ngroups;
     const int c = cz / g.nz, z = cz - (cz / g.nz) * g.nz;
-    const int y0 = grp * NR;
+    const int y0 = grp * nr;
+    const int nrow = min(nr, g.ny - y0);
     const int64_t cplane = int64_t(3) * g.nz * g.ny;
-    const cx<T>* src = Tb + int64_t(pos) * g.mx * cplane + (int64_t(c) * g.nz + z) * g.ny;
-    for (int e = tid; e < NR * LX; e += NT) {
-        const int kx = e / NR, r = e % NR;
-        const int y = y0 + r;
-        lds[r * LP + kx] = (y < g.ny) ? src[kx * cplane + y] : cx<T>{T(0), T(0)};
+    const cx<T>* src = Tb + int64_t(pos) * g.mx * cplane + (int64_t(c) * g.nz + z) * g.ny + y0;
+    {
+        const int n = nrow * LX;
+        cx<T> t[NL];
+#pragma unroll
+        for (int q = 0; q < NL; ++q) {
+            const int e = min(tid + q * NT, n - 1);
+            const int kx = e / nrow, r = e - (e / nrow) * nrow;
+            t[q] = src[kx * cplane + r];
+        }
+#pragma unroll
+        for (int q = 0; q < NL; ++q) {
+            const int e = tid + q * NT;
+            const int kx = e / nrow, r = e - (e / nrow) * nrow;
+            if (e < n) lds[r * LP + kx] = t[q];
+        }
     }
     __syncthreads();
-    fft_tile<T, LX, true, NR, LP, 1, NT>(lds, tw, tid);
+    fft_tile<T, LX, true, NR, LP, 1, NT>(lds, tw, tid, nrow);
     const int64_t voff = (slot * 3 + c) * g.n_occ;
+    const int* mrow = map + (int64_t(z) * g.ny + y0) * g.nx;
+    int idx[NE];
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+        const int e = tid + q * NT;
+        const int r = e / HX, x = e - (e / HX) * HX;
+        const int m = mrow[min(r, nrow - 1) * g.nx + min(x, g.nx - 1)];
+        idx[q] = (r < nrow && x < g.nx) ? m : -1;
+    }
+    cx<T> xv[NE], av[NE];
+    if (MODE != PACK_GX) {
+#pragma unroll
+        for (int q = 0; q < NE; ++q) {
+            const int i = max(idx[q], 0);
+            xv[q] = xin[voff + i];
+            av[q] = ainv[sys * g.n_occ + i];
+        }
+    }
     double mu[2] = {0.0, 0.0};
-    for (int e = tid; e < NR * LX; e += NT) {
-        const int r = e / LX, x = e % LX;
-        const int y = y0 + r;
-        if (y < g.ny && x < g.nx) {
-            const int idx = map[(int64_t(z) * g.ny + y) * g.nx + x];
-            if (idx >= 0) {
-                const cx<T> conv = lds[r * LP + x];
-                if (MODE == PACK_GX) {
-                    yout[voff + idx] = conv;
-                } else {
-                    const cx<T> xi = xin[voff + idx];
-                    const cx<T> yi = xi * ainv[sys * g.n_occ + idx] - conv;
-                    yout[voff + idx] = yi;
-                    if (MODE == PACK_AX_COCG) {  // bilinear x^T y
-                        mu[0] += double(xi.x) * yi.x - double(xi.y) * yi.y;
-                        mu[1] += double(xi.x) * yi.y + double(xi.y) * yi.x;
-                    }
-                }
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+        if (idx[q] < 0) continue;
+        const int e = tid + q * NT;
+        const int r = e / HX, x = e - (e / HX) * HX;
+        const cx<T> conv = lds[r * LP + x];
+        if (MODE == PACK_GX) {
+            yout[voff + idx[q]] = conv;
+        } else {
+            const cx<T> yi = xv[q] * av[q] - conv;
+            yout[voff + idx[q]] = yi;
+            if (MODE == PACK_AX_COCG) {  // bilinear x^T y
+                mu[0] += double(xv[q].x) * yi.x - double(xv[q].y) * yi.y;
+                mu[1] += double(xv[q].x) * yi.y + double(xv[q].y) * yi.x;
             }
         }
     }
@@ -492,17 +562,19 @@ void launch_xfft_t(cx<T>* xin, const int* map, cx<T>* Tb, const cx<T>* tw_x, con
                    const int* act, int n_act, const cx<T>* fuse_r, SlotFilter f,
                    hipStream_t s) {
     if (n_act == 0) return;
-    const int ng = xgroups(g);
+    if (2 * g.nx - 1 > g.mx) throw Error(-1, "x grid shorter than 2 nx - 1");
+    int ng, nr;
+    xsplit<T>(g, ng, nr);
     dim3 grid(3 * g.nz * ng, n_act);
     switch (g.mx) {
 #define DDA_CASE(N)                                                                         \
     case N:                                                                                 \
         if (fuse_r)                                                                         \
             k_xfft_t<T, N, true><<<grid, NT, 0, s>>>(xin, map, Tb, tw_x, g, act, fuse_r, f,  \
-                                                     ng);                                   \
+                                                     ng, nr);                               \
         else                                                                                \
             k_xfft_t<T, N, false><<<grid, NT, 0, s>>>(xin, map, Tb, tw_x, g, act, nullptr,   \
-                                                      f, ng);                               \
+                                                      f, ng, nr);                           \
         break;
         DDA_FOR_EACH_LX(DDA_CASE)
 #undef DDA_CASE
@@ -518,7 +590,9 @@ void launch_ixfft_t(const cx<T>* Tb, const cx<T>* xin, const cx<T>* ainv, cx<T>*
                     const int* slot_sys, int n_act, int mode, SlotFilter f, RedScratch red,
                     hipStream_t s) {
     if (n_act == 0) return;
-    const int ng = xgroups(g);
+    if (2 * g.nx - 1 > g.mx) throw Error(-1, "x grid shorter than 2 nx - 1");
+    int ng, nr;
+    xsplit<T>(g, ng, nr);
     if (mode == PACK_AX_COCG && 3 * g.nz * ng > red.max_blocks)
         throw Error(-3, "reduction scratch too small for the fused pack kernel");
     dim3 grid(3 * g.nz * ng, n_act);
@@ -527,13 +601,13 @@ void launch_ixfft_t(const cx<T>* Tb, const cx<T>* xin, const cx<T>* ainv, cx<T>*
     case N:                                                                                  \
         if (mode == PACK_GX)                                                                 \
             k_ixfft_t<T, N, PACK_GX><<<grid, NT, 0, s>>>(Tb, xin, ainv, yout, map, tw_x, g,   \
-                                                         act, slot_sys, f, red, ng);            \
+                                                         act, slot_sys, f, red, ng, nr);            \
         else if (mode == PACK_AX)                                                            \
             k_ixfft_t<T, N, PACK_AX><<<grid, NT, 0, s>>>(Tb, xin, ainv, yout, map, tw_x, g,   \
-                                                         act, slot_sys, f, red, ng);            \
+                                                         act, slot_sys, f, red, ng, nr);            \
         else                                                                                 \
             k_ixfft_t<T, N, PACK_AX_COCG><<<grid, NT, 0, s>>>(Tb, xin, ainv, yout, map, tw_x, \
-                                                              g, act, slot_sys, f, red, ng);    \
+                                                              g, act, slot_sys, f, red, ng, nr);    \
         break;
         DDA_FOR_EACH_LX(DDA_CASE)
 #undef DDA_CASE

@@ -108,10 +108,14 @@ MATVEC_LATTICES = [
     ("rod_24x6x6", W.capped_rod_mask(24, 6, 6, 1.0, 3.0, 24.0), 1.0),
     ("sphere_16", W.sphere_mask(16, 1.0, 8.0), 1.0),
     ("random_9x4x13", W.random_mask(9, 4, 13, 0.5, seed=3), 2.0),
-    # y, z grids of 64: FP32 takes the three-pass (yz plane in LDS) chain,
-    # FP64 the five-pass one
+    # y, z grids of 48: both precisions take the three-pass (yz plane in LDS)
+    # chain
     ("random_5x17x17", W.random_mask(5, 17, 17, 0.6, seed=9), 1.3),
     ("sphere_32", W.sphere_mask(32, 1.0, 16.0), 1.0),
+    # the x kernels split a plane's rows into uneven groups: 19 rows over two
+    # blocks in FP64 (x grid 128), 25 rows over two in FP32 (x grid 192)
+    ("random_64x19x19", W.random_mask(64, 19, 19, 0.25, seed=4), 1.0),
+    ("random_96x25x25", W.random_mask(96, 25, 25, 0.08, seed=6), 1.0),
 ]
 
 
