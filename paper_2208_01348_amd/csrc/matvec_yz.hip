@@ -25,6 +25,15 @@ constexpr int NTYZ = 512;  // yz kernel, default threads per block (the autotune
                            // may pick 256 or 1024 for L >= 24; the butterflies
                            // are the same whichever thread computes them)
 
+// Position of y inside one line (c, z) of the T buffer.  When ny is a
+// multiple of 8 every block of 8 is stored in the order (y mod 4, bit 2 of
+// y): the pair y = 8j + n2, 8j + 4 + n2 that lane n2 of a quad holds in the
+// decimated layout of the register line transforms is then contiguous, and
+// a quad reads or writes 64 contiguous bytes (FP32).  Otherwise natural order.
+__device__ __forceinline__ int tpos(int y, bool perm) {
+    return perm ? (y & ~7) | ((y & 3) << 1) | ((y >> 2) & 1) : y;
+}
+
 // At most this many rows of one (component, z) plane per x-kernel block
 // (about 37 KB of LDS); the rows of a plane are split evenly over
 // ceil(ny / max) blocks.
@@ -149,10 +158,11 @@ __global__ __launch_bounds__(NT) void k_xfft_t(cx<T>* __restrict__ xin,
     __syncthreads();
     fft_tile<T, LX, false, NR, LP, 1, NT>(lds, tw, tid, nrow);
     const int64_t cplane = int64_t(3) * g.nz * g.ny;  // one kx column
-    cx<T>* dst = Tb + int64_t(pos) * g.mx * cplane + (int64_t(c) * g.nz + z) * g.ny + y0;
+    cx<T>* dst = Tb + int64_t(pos) * g.mx * cplane + (int64_t(c) * g.nz + z) * g.ny;
+    const bool perm = (g.ny & 7) == 0;
     for (int e = tid; e < nrow * LX; e += NT) {
         const int kx = e / nrow, r = e - (e / nrow) * nrow;
-        dst[kx * cplane + r] = lds[r * LP + kx];
+        dst[kx * cplane + tpos(y0 + r, perm)] = lds[r * LP + kx];
     }
 }
 
@@ -184,7 +194,8 @@ __global__ __launch_bounds__(NT) void k_ixfft_t(const cx<T>* __restrict__ Tb,
     const int y0 = grp * nr;
     const int nrow = min(nr, g.ny - y0);
     const int64_t cplane = int64_t(3) * g.nz * g.ny;
-    const cx<T>* src = Tb + int64_t(pos) * g.mx * cplane + (int64_t(c) * g.nz + z) * g.ny + y0;
+    const cx<T>* src = Tb + int64_t(pos) * g.mx * cplane + (int64_t(c) * g.nz + z) * g.ny;
+    const bool perm = (g.ny & 7) == 0;
     {
         const int n = nrow * LX;
         cx<T> t[NL];
@@ -192,7 +203,7 @@ __global__ __launch_bounds__(NT) void k_ixfft_t(const cx<T>* __restrict__ Tb,
         for (int q = 0; q < NL; ++q) {
             const int e = min(tid + q * NT, n - 1);
             const int kx = e / nrow, r = e - (e / nrow) * nrow;
-            t[q] = src[kx * cplane + r];
+            t[q] = src[kx * cplane + tpos(y0 + r, perm)];
         }
 #pragma unroll
         for (int q = 0; q < NL; ++q) {
@@ -269,9 +280,10 @@ __global__ __launch_bounds__(NTY) void k_yzconv(cx<T>* __restrict__ Tb,
     const int sys = slot_sys[slot];
     const int64_t cplane = int64_t(3) * g.nz * g.ny;
     cx<T>* col = Tb + (int64_t(pos) * g.mx + kx) * cplane;
+    const bool perm = (g.ny & 7) == 0;
     for (int e = tid; e < L * ROW; e += NTY) {
         const int z = e / ROW, rem = e % ROW, c = rem / SY, y = rem % SY;
-        lds[e] = (z < g.nz && y < g.ny) ? col[(int64_t(c) * g.nz + z) * g.ny + y]
+        lds[e] = (z < g.nz && y < g.ny) ? col[(int64_t(c) * g.nz + z) * g.ny + tpos(y, perm)]
                                         : cx<T>{T(0), T(0)};
     }
     __syncthreads();
@@ -309,7 +321,7 @@ __global__ __launch_bounds__(NTY) void k_yzconv(cx<T>* __restrict__ Tb,
     fft_tile<T, L, true, 3 * H, SY, 1, NTY>(lds, twy, tid);
     for (int e = tid; e < 3 * g.nz * g.ny; e += NTY) {
         const int y = e % g.ny, cz = e / g.ny, z = cz % g.nz, c = cz / g.nz;
-        col[e] = lds[z * ROW + c * SY + y];
+        col[int64_t(cz) * g.ny + tpos(y, perm)] = lds[z * ROW + c * SY + y];
     }
 }
 
@@ -443,6 +455,25 @@ __device__ __forceinline__ void quad_fft_blk(cx<T> (&v)[L / 4], int n2,
     reg_stages<T, L, Q, 1, INV>(v, tw);
 }
 
+// Two adjacent complex values of a T line (16-byte aligned for FP32 when the
+// line is permuted: ny is then a multiple of 8).
+__device__ __forceinline__ void load_pair(const cx<float>* p, cx<float>& a, cx<float>& b) {
+    const float4 t = *reinterpret_cast<const float4*>(p);
+    a = cx<float>{t.x, t.y};
+    b = cx<float>{t.z, t.w};
+}
+__device__ __forceinline__ void load_pair(const cx<double>* p, cx<double>& a, cx<double>& b) {
+    a = p[0];
+    b = p[1];
+}
+__device__ __forceinline__ void store_pair(cx<float>* p, cx<float> a, cx<float> b) {
+    *reinterpret_cast<float4*>(p) = float4{a.x, a.y, b.x, b.y};
+}
+__device__ __forceinline__ void store_pair(cx<double>* p, cx<double> a, cx<double> b) {
+    p[0] = a;
+    p[1] = b;
+}
+
 template <typename T, int L>
 __global__ __launch_bounds__(yzr_threads<L>()) void k_yzconv_r(
     cx<T>* __restrict__ Tb, const cx<T>* const* __restrict__ Dptr, const cx<T>* __restrict__ twy,
@@ -466,14 +497,24 @@ __global__ __launch_bounds__(yzr_threads<L>()) void k_yzconv_r(
     const cx<T> zero{T(0), T(0)};
 
     // phase 1: y-FFT of the lines (c, z)
+    const bool perm = (ny & 7) == 0;
     for (int line = grp; line < 3 * nz; line += NTR / 4) {
         const int c = line / nz, z = line - (line / nz) * nz;
         const cx<T>* src = col + int64_t(line) * ny;
         cx<T> v[Q];
 #pragma unroll
-        for (int n1 = 0; n1 < Q; ++n1) {
-            const int y = 4 * n1 + n2;
-            v[n1] = (n1 < Q / 2 && y < ny) ? src[y] : zero;
+        for (int n1 = 0; n1 < Q; ++n1) v[n1] = zero;
+        if (perm) {  // whole blocks of 8: lane n2 reads its pair at 8j + 2 n2
+#pragma unroll
+            for (int j = 0; 2 * j + 1 < Q / 2 + 1; ++j) {
+                if (8 * j + 8 <= ny) load_pair(src + 8 * j + 2 * n2, v[2 * j], v[2 * j + 1]);
+            }
+        } else {
+#pragma unroll
+            for (int n1 = 0; n1 < Q / 2; ++n1) {
+                const int y = 4 * n1 + n2;
+                if (y < ny) v[n1] = src[y];
+            }
         }
         quad_fft<T, L, false>(v, n2, twy);
 #pragma unroll
@@ -498,26 +539,47 @@ __global__ __launch_bounds__(yzr_threads<L>()) void k_yzconv_r(
     // phase 2b: D u at every (ky, kz); consecutive lanes take consecutive ky,
     // the fastest index of the D slab (coalesced loads; LDS rows at an odd
     // stride keep the accesses in distinct banks).  One D load serves the
-    // mirrored frequencies through the parity of each component.
+    // mirrored frequencies through the parity of each component.  The D
+    // loads of a thread's next frequency are issued before the current one
+    // is processed (software pipelining: one wait on memory per thread
+    // instead of one per frequency).
     {
+        constexpr int NIT = (L * L + NTR - 1) / NTR;
+        constexpr int H2 = HD * HD;
         const bool fx = kx > g.mx / 2;
         const int kxr = fx ? g.mx - kx : kx;
-        const cx<T>* __restrict__ dslab = Dptr[sys] + int64_t(kxr) * 6 * HD * HD;
-        for (int e = tid; e < L * L; e += NTR) {
+        const cx<T>* __restrict__ dslab = Dptr[sys] + int64_t(kxr) * 6 * H2;
+        auto dload = [&](int e, cx<T> (&d)[6]) {
+            e = min(e, L * L - 1);  // clamped: always a valid address
             const int kz = e / L, ky = e - (e / L) * L;
-            const bool fy = ky > L / 2, fz = kz > L / 2;
-            const int o = (fz ? L - kz : kz) * HD + (fy ? L - ky : ky);
-            const cx<T> dxx = dslab[o], dyy = dslab[o + 3 * HD * HD], dzz = dslab[o + 5 * HD * HD];
-            cx<T> dxy = dslab[o + HD * HD], dxz = dslab[o + 2 * HD * HD];
-            cx<T> dyz = dslab[o + 4 * HD * HD];
-            if (fx != fy) dxy = -dxy;
-            if (fx != fz) dxz = -dxz;
-            if (fy != fz) dyz = -dyz;
-            cx<T>* u = lds + ky * ZS + kz;
-            const cx<T> ux = u[0], uy = u[L * ZS], uz = u[2 * L * ZS];
-            u[0] = dxx * ux + dxy * uy + dxz * uz;
-            u[L * ZS] = dxy * ux + dyy * uy + dyz * uz;
-            u[2 * L * ZS] = dxz * ux + dyz * uy + dzz * uz;
+            const int o = (kz > L / 2 ? L - kz : kz) * HD + (ky > L / 2 ? L - ky : ky);
+#pragma unroll
+            for (int q = 0; q < 6; ++q) d[q] = dslab[o + q * H2];
+        };
+        cx<T> dc[6];
+        dload(tid, dc);
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int e = tid + it * NTR;
+            cx<T> dn[6];
+            if (it + 1 < NIT) dload(e + NTR, dn);
+            if (e < L * L) {
+                const int kz = e / L, ky = e - (e / L) * L;
+                const bool fy = ky > L / 2, fz = kz > L / 2;
+                cx<T> dxy = dc[1], dxz = dc[2], dyz = dc[4];
+                if (fx != fy) dxy = -dxy;
+                if (fx != fz) dxz = -dxz;
+                if (fy != fz) dyz = -dyz;
+                cx<T>* u = lds + ky * ZS + kz;
+                const cx<T> ux = u[0], uy = u[L * ZS], uz = u[2 * L * ZS];
+                u[0] = dc[0] * ux + dxy * uy + dxz * uz;
+                u[L * ZS] = dxy * ux + dc[3] * uy + dyz * uz;
+                u[2 * L * ZS] = dxz * ux + dyz * uy + dc[5] * uz;
+            }
+            if (it + 1 < NIT) {
+#pragma unroll
+                for (int q = 0; q < 6; ++q) dc[q] = dn[q];
+            }
         }
     }
     __syncthreads();
@@ -536,18 +598,27 @@ __global__ __launch_bounds__(yzr_threads<L>()) void k_yzconv_r(
     }
     __syncthreads();
 
-    // phase 3: y-iFFT of the lines (c, z), y < ny back to HBM
+    // phase 3: y-iFFT of the lines (c, z) from the blocked spectrum (lane n2
+    // reads ky = k1 + (L/4) rev2(n2)), output decimated (lane n2 holds
+    // y = 4 n1 + n2); y < ny back to HBM, in pairs when the line is permuted
     for (int line = grp; line < 3 * nz; line += NTR / 4) {
         const int c = line / nz, z = line - (line / nz) * nz;
         cx<T> v[Q];
 #pragma unroll
-        for (int n1 = 0; n1 < Q; ++n1) v[n1] = lds[(c * L + 4 * n1 + n2) * ZS + z];
-        quad_fft<T, L, true>(v, n2, twy);
+        for (int k1 = 0; k1 < Q; ++k1) v[k1] = lds[(c * L + k1 + Q * rb) * ZS + z];
+        quad_fft_blk<T, L, true>(v, n2, twy);
         cx<T>* dst = col + int64_t(line) * ny;
+        if (perm) {
 #pragma unroll
-        for (int k1 = 0; k1 < Q; ++k1) {
-            const int y = k1 + Q * rb;
-            if (y < ny) dst[y] = v[k1];
+            for (int j = 0; 2 * j + 1 < Q / 2 + 1; ++j) {
+                if (8 * j + 8 <= ny) store_pair(dst + 8 * j + 2 * n2, v[2 * j], v[2 * j + 1]);
+            }
+        } else {
+#pragma unroll
+            for (int n1 = 0; n1 < Q / 2; ++n1) {
+                const int y = 4 * n1 + n2;
+                if (y < ny) dst[y] = v[n1];
+            }
         }
     }
 }
