@@ -121,7 +121,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solve shards by "
-              "energy across GPUs with no communication, which this build does not run.",
+              "energy across GPUs with no communication; only the one-GPU path exists.",
               file=sys.stderr)
         sys.exit(2)
 

@@ -13,8 +13,8 @@ relative refractive index of eq. (2).
                                    - (2/3) i (kd)^3 ]),
   b1 = -1.8915316, b2 = 0.1648469, b3 = -1.7700004.  S = sum_mu a_mu^2 e_mu^2
   for propagation a and polarisation e; for the electron moving along the
-  lattice z axis with its transverse field, S = 0 (the reading this build
-  takes).  The coefficient values are literature constants: parity unpinned
+  lattice z axis with its transverse field, S = 0 (the reading taken
+  here).  The coefficient values are literature constants: parity unpinned
   for the values themselves.
 """
 
