@@ -455,6 +455,17 @@ __device__ __forceinline__ void quad_fft_blk(cx<T> (&v)[L / 4], int n2,
     reg_stages<T, L, Q, 1, INV>(v, tw);
 }
 
+// u <- D u for the three components of one frequency (component stride CS)
+// with the symmetric tensor D = [xx xy xz; xy yy yz; xz yz zz].
+template <typename T, int CS>
+__device__ __forceinline__ void dmul3(cx<T>* u, cx<T> dxx, cx<T> dxy, cx<T> dxz, cx<T> dyy,
+                                      cx<T> dyz, cx<T> dzz) {
+    const cx<T> ux = u[0], uy = u[CS], uz = u[2 * CS];
+    u[0] = dxx * ux + dxy * uy + dxz * uz;
+    u[CS] = dxy * ux + dyy * uy + dyz * uz;
+    u[2 * CS] = dxz * ux + dyz * uy + dzz * uz;
+}
+
 // Two adjacent complex values of a T line (16-byte aligned for FP32 when the
 // line is permuted: ny is then a multiple of 8).
 __device__ __forceinline__ void load_pair(const cx<float>* p, cx<float>& a, cx<float>& b) {
@@ -536,49 +547,83 @@ __global__ __launch_bounds__(yzr_threads<L>()) void k_yzconv_r(
         for (int k1 = 0; k1 < Q; ++k1) row[k1 + Q * rb] = u[k1];
     }
     __syncthreads();
-    // phase 2b: D u at every (ky, kz); consecutive lanes take consecutive ky,
-    // the fastest index of the D slab (coalesced loads; LDS rows at an odd
-    // stride keep the accesses in distinct banks).  One D load serves the
-    // mirrored frequencies through the parity of each component.  The D
-    // loads of a thread's next frequency are issued before the current one
-    // is processed (software pipelining: one wait on memory per thread
-    // instead of one per frequency).
+    // phase 2b: D u at every (ky, kz).  The slab holds the corner
+    // ky', kz' <= L/2, and one entry serves the frequencies (ky' or L - ky') x
+    // (kz' or L - kz') through the parity of each component.  Interior
+    // entries (0 < ky', kz' < L/2) give one work item of four frequencies for
+    // six loads; consecutive lanes take consecutive ky', the fastest slab
+    // index (coalesced).  The 4L - 4 frequencies on the lines ky or kz in
+    // {0, L/2} are one item each.  All D loads of a thread are issued before
+    // its first product.  LDS rows at an odd stride keep accesses in distinct
+    // banks.
     {
-        constexpr int NIT = (L * L + NTR - 1) / NTR;
+        constexpr int HI = L / 2 - 1;
+        constexpr int NI = HI * HI;
+        constexpr int NEG = 4 * L - 4;
+        constexpr int NII = (NI + NTR - 1) / NTR;
+        constexpr int NIE = (NEG + NTR - 1) / NTR;
         constexpr int H2 = HD * HD;
         const bool fx = kx > g.mx / 2;
         const int kxr = fx ? g.mx - kx : kx;
         const cx<T>* __restrict__ dslab = Dptr[sys] + int64_t(kxr) * 6 * H2;
-        auto dload = [&](int e, cx<T> (&d)[6]) {
-            e = min(e, L * L - 1);  // clamped: always a valid address
-            const int kz = e / L, ky = e - (e / L) * L;
+        const T sx = fx ? T(-1) : T(1);
+        // edge frequency p: kz = 0 and kz = L/2 (all ky), then ky = 0 and
+        // ky = L/2 (kz off those two)
+        auto edge = [](int p, int& ky, int& kz) {
+            if (p < 2 * L) {
+                kz = p < L ? 0 : L / 2;
+                ky = p < L ? p : p - L;
+            } else {
+                const int q = p - 2 * L;
+                ky = q < L - 2 ? 0 : L / 2;
+                kz = 1 + (q < L - 2 ? q : q - (L - 2));
+                if (kz >= L / 2) ++kz;
+            }
+        };
+        cx<T> di[NII][6], de[NIE][6];
+#pragma unroll
+        for (int it = 0; it < NII; ++it) {
+            const int t = min(tid + it * NTR, NI - 1);
+            const int kzp = 1 + t / HI, kyp = 1 + (t - (t / HI) * HI);
+#pragma unroll
+            for (int q = 0; q < 6; ++q) di[it][q] = dslab[kzp * HD + kyp + q * H2];
+        }
+#pragma unroll
+        for (int it = 0; it < NIE; ++it) {
+            int ky, kz;
+            edge(min(tid + it * NTR, NEG - 1), ky, kz);
             const int o = (kz > L / 2 ? L - kz : kz) * HD + (ky > L / 2 ? L - ky : ky);
 #pragma unroll
-            for (int q = 0; q < 6; ++q) d[q] = dslab[o + q * H2];
-        };
-        cx<T> dc[6];
-        dload(tid, dc);
+            for (int q = 0; q < 6; ++q) de[it][q] = dslab[o + q * H2];
+        }
 #pragma unroll
-        for (int it = 0; it < NIT; ++it) {
-            const int e = tid + it * NTR;
-            cx<T> dn[6];
-            if (it + 1 < NIT) dload(e + NTR, dn);
-            if (e < L * L) {
-                const int kz = e / L, ky = e - (e / L) * L;
-                const bool fy = ky > L / 2, fz = kz > L / 2;
-                cx<T> dxy = dc[1], dxz = dc[2], dyz = dc[4];
-                if (fx != fy) dxy = -dxy;
-                if (fx != fz) dxz = -dxz;
-                if (fy != fz) dyz = -dyz;
-                cx<T>* u = lds + ky * ZS + kz;
-                const cx<T> ux = u[0], uy = u[L * ZS], uz = u[2 * L * ZS];
-                u[0] = dc[0] * ux + dxy * uy + dxz * uz;
-                u[L * ZS] = dxy * ux + dc[3] * uy + dyz * uz;
-                u[2 * L * ZS] = dxz * ux + dyz * uy + dc[5] * uz;
+        for (int it = 0; it < NII; ++it) {
+            const int t = tid + it * NTR;
+            if (t < NI) {
+                const int kzp = 1 + t / HI, kyp = 1 + (t - (t / HI) * HI);
+                const cx<T>* d = di[it];
+                const cx<T> dxy = sx * d[1], dxz = sx * d[2];  // parities at ky', kz'
+                dmul3<T, L * ZS>(lds + kyp * ZS + kzp, d[0], dxy, dxz, d[3], d[4], d[5]);
+                dmul3<T, L * ZS>(lds + (L - kyp) * ZS + kzp, d[0], -dxy, dxz, d[3], -d[4],
+                                 d[5]);
+                dmul3<T, L * ZS>(lds + kyp * ZS + (L - kzp), d[0], dxy, -dxz, d[3], -d[4],
+                                 d[5]);
+                dmul3<T, L * ZS>(lds + (L - kyp) * ZS + (L - kzp), d[0], -dxy, -dxz, d[3],
+                                 d[4], d[5]);
             }
-            if (it + 1 < NIT) {
+        }
 #pragma unroll
-                for (int q = 0; q < 6; ++q) dc[q] = dn[q];
+        for (int it = 0; it < NIE; ++it) {
+            const int p = tid + it * NTR;
+            if (p < NEG) {
+                int ky, kz;
+                edge(p, ky, kz);
+                const bool fy = ky > L / 2, fz = kz > L / 2;
+                const cx<T>* d = de[it];
+                const cx<T> dxy = (fx != fy) ? -d[1] : d[1];
+                const cx<T> dxz = (fx != fz) ? -d[2] : d[2];
+                const cx<T> dyz = (fy != fz) ? -d[4] : d[4];
+                dmul3<T, L * ZS>(lds + ky * ZS + kz, d[0], dxy, dxz, d[3], dyz, d[5]);
             }
         }
     }
