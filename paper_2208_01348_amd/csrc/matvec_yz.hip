@@ -20,7 +20,7 @@ namespace dda {
 
 namespace {
 
-constexpr int NT = 256;    // x kernels
+constexpr int NT = 512;    // x kernels (measured best of 192 ... 1024 on the nanorod lattice)
 constexpr int NTYZ = 512;  // yz kernel, default threads per block (the autotuner
                            // may pick 256 or 1024 for L >= 24; the butterflies
                            // are the same whichever thread computes them)
