@@ -227,6 +227,33 @@ def test_losses_when_precisions_use_different_chains(solver, precision, bar):
     s.close()
 
 
+@pytest.mark.parametrize("nx", [32, 33, 64])
+@pytest.mark.parametrize("solver,precision,bar", [("cocg", "mixed", 1e-5), ("bicgstab", "mixed", 1e-5),
+                                                  ("cocg", "fp64", 1e-9)])
+def test_losses_on_long_x_grids(nx, solver, precision, bar):
+    """Rods with x grids of 64, 96 and 128 on a 12 x 12 yz grid (three-pass
+    chain with the LDS-tiled yz kernel; the fused direction update and the
+    x^T y rows of COCG included) against dense LU."""
+    mask = W.capped_rod_mask(nx, 6, 6, 1.0, 3.0, float(nx))
+    n = int(mask.sum())
+    energies = np.array([2.3])
+    eps = np.repeat(W.drude_eps(energies)[:, None], n, axis=1)
+    r0 = np.array([[nx / 2 + 2.0, 0.5, 0.0]])
+    say("register x passes", nx, solver, precision, "n_occ", n)
+    s = DDASolver(mask, 1.0, 1.45, precision=precision, solver=solver,
+                  tol=1e-12 if precision == "fp64" else 1e-10, maxit=20000)
+    P, info = s.spectrum(energies, 0.55, eps, r0)
+    assert info[0].status == 0, info[0]
+    ref = solve_point(mask, 1.0, eps[0], 1.45, 0.55, r0[0], energies[0], method="lu")
+    vals = [ref.p_eels, ref.p_ext, ref.p_abs, ref.p_cl]
+    scale = max(abs(v) for v in vals)
+    for g, v, nm in zip(P[0], vals, ["eels", "ext", "abs", "cl"]):
+        err = abs(g - v) / max(abs(v), 1e-3 * scale)
+        say(f"  {nm}: gpu={g:.15e} oracle={v:.15e} rel={err:.2e}")
+        assert err <= bar, (nx, nm, err)
+    s.close()
+
+
 @pytest.mark.parametrize("solver,precision", [("bicgstab", "fp64"), ("cocg", "fp64"),
                                               ("cocg", "mixed")])
 def test_c1_full_size_matches_oracle_golden(solver, precision):
