@@ -119,6 +119,36 @@ void dda_default_options(dda_options* opt);
 double dda_beta_from_keV(double kinetic_keV);
 
 /*
+ * Free-space loss of the electron per unit path length and energy, eq. (29)
+ * through eq. (36) (Frank-Tamm): d Gamma_0/dz = alpha_fs (1 - 1/beta_h^2) /
+ * (hbar c) in eV^-1 nm^-1 when beta_h = beta m_h > 1, else 0.  Host only.
+ * Errors: DDA_EINVAL for beta outside (0, 1), Re m_h <= 0, non-finite input,
+ * or an absorbing host (Im m_h != 0), where W_0 is undefined (section 2.3).
+ */
+int dda_free_space_loss(double beta, double mh_re, double mh_im, double* dgamma_dz);
+
+/*
+ * Total particle-related CL probability, eq. (41): out[i] = P_EELS - P_ext +
+ * P_CL of res[i] (the cross sections C_enh - C_ext + C_sca share the
+ * prefactor of eqs. 37, 42, 48); equal to P_CL when beta_h < 1.  Host only;
+ * res and out are host arrays of n.  Errors: DDA_EINVAL for bad arguments or
+ * an absorbing host (Im m_h != 0), where the far-field powers it rests on are
+ * not defined (section 2.6).
+ */
+int dda_cl_total(const dda_result* res, int n, double mh_im, double* out);
+
+/*
+ * Spectrum convolved with a Gaussian point-spread function of unit area and
+ * full width at half maximum fwhm_eV (the instrumental broadening applied to
+ * measured spectra, section 3.4): out_i = sum_j p_j g(E_i - E_j) dE on a
+ * uniform energy grid, the spectrum taken as zero outside the grid.  Host
+ * arrays of n; out may alias p.  Errors: DDA_EINVAL for n < 1, fwhm <= 0, or
+ * energies that are not an increasing uniform grid.
+ */
+int dda_psf_gauss(const double* energy_eV, const double* p, int n, double fwhm_eV,
+                  double* out);
+
+/*
  * Builds a context for one lattice and host medium.  Copies the mask, builds
  * the index maps on the host and uploads them.  `hip_stream` is a hipStream_t
  * (NULL = the default stream) on which every later call is ordered.

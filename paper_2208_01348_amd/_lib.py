@@ -27,7 +27,7 @@ EXPORTED = ["dda_default_options", "dda_beta_from_keV", "dda_setup", "dda_n_occ"
             "dda_last_error", "dda_debug_besselk01", "dda_workspace_bytes", "dda_engine_open",
             "dda_engine_submit", "dda_engine_poll", "dda_engine_status", "dda_engine_close",
             "dda_set_host", "dda_stream_create", "dda_stream_destroy", "dda_tuning",
-            "dda_set_tuning"]
+            "dda_set_tuning", "dda_free_space_loss", "dda_cl_total", "dda_psf_gauss"]
 
 
 class DDAError(RuntimeError):
@@ -96,6 +96,9 @@ def load() -> ctypes.CDLL:
         "dda_stream_destroy": (_i, [_vp]),
         "dda_tuning": (_i, [_vp, _i, _vp, _vp, _vp, _vp, _vp]),
         "dda_set_tuning": (_i, [_vp, _i, _i, _i, _i]),
+        "dda_free_space_loss": (_i, [_d, _d, _d, _vp]),
+        "dda_cl_total": (_i, [_vp, _i, _d, _vp]),
+        "dda_psf_gauss": (_i, [_vp, _vp, _i, _d, _vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -143,6 +146,33 @@ def dda_default_options() -> Options:
 
 def dda_beta_from_keV(kinetic_keV: float) -> float:
     return float(load().dda_beta_from_keV(float(kinetic_keV)))
+
+
+def dda_free_space_loss(beta: float, m_h: complex) -> float:
+    """d Gamma_0 / dz in eV^-1 nm^-1 (host closed form)."""
+    out = ctypes.c_double()
+    _check(load().dda_free_space_loss(float(beta), float(m_h.real), float(m_h.imag),
+                                      ctypes.byref(out)))
+    return out.value
+
+
+def dda_cl_total(P: np.ndarray, m_h: complex) -> np.ndarray:
+    """P_CL^tot from rows (P_EELS, P_ext, P_abs, P_CL) (host closed form)."""
+    rows = np.ascontiguousarray(np.asarray(P, dtype=np.float64).reshape(-1, 4))
+    out = np.empty(rows.shape[0])
+    _check(load().dda_cl_total(_ptr(rows), rows.shape[0], float(complex(m_h).imag), _ptr(out)))
+    return out
+
+
+def dda_psf_gauss(energy_eV, p, fwhm_eV: float) -> np.ndarray:
+    """Spectrum convolved with a unit-area Gaussian of the given FWHM (host)."""
+    E = _f64(energy_eV)
+    v = _f64(p)
+    if E.shape != v.shape or E.ndim != 1:
+        raise ValueError("energies and spectrum must be 1-D of one length")
+    out = np.empty_like(v)
+    _check(load().dda_psf_gauss(_ptr(E), _ptr(v), E.size, float(fwhm_eV), _ptr(out)))
+    return out
 
 
 def dda_setup(mask: np.ndarray, nx: int, ny: int, nz: int, d_nm: float, mh_re: float,

@@ -1424,6 +1424,73 @@ double dda_beta_from_keV(double kinetic_keV) {
 
 const char* dda_last_error(void) { return g_last_error.c_str(); }
 
+// ----------------------------------------------------- total-loss helpers -----
+// Closed forms on the host; no device work.
+
+int dda_free_space_loss(double beta, double mh_re, double mh_im, double* dgamma_dz) {
+    DDA_API_BEGIN
+    if (!dgamma_dz) throw Error(DDA_EINVAL, "dgamma_dz is NULL");
+    if (!std::isfinite(beta) || !std::isfinite(mh_re) || !std::isfinite(mh_im) || beta <= 0.0 ||
+        beta >= 1.0 || mh_re <= 0.0)
+        throw Error(DDA_EINVAL, "need 0 < beta < 1 and a finite host index with Re m_h > 0");
+    if (mh_im != 0.0)
+        throw Error(DDA_EINVAL,
+                    "the free-space loss W_0 is undefined in an absorbing host (section 2.3)");
+    // eq. (29) per unit energy through eq. (36): d Gamma_0/dz = alpha_fs (1 - 1/beta_h^2)
+    // / (hbar c) above the Cherenkov threshold beta_h = beta m_h > 1, zero below
+    const double bh = beta * mh_re;
+    *dgamma_dz = bh > 1.0 ? kAlphaFs * (1.0 - 1.0 / (bh * bh)) / kHbarC : 0.0;
+    return DDA_OK;
+    DDA_API_END
+}
+
+int dda_cl_total(const dda_result* res, int n, double mh_im, double* out) {
+    DDA_API_BEGIN
+    if (n < 0 || (n > 0 && (!res || !out))) throw Error(DDA_EINVAL, "bad arguments");
+    if (mh_im != 0.0)
+        throw Error(DDA_EINVAL,
+                    "P_CL^tot rests on far-field powers that an absorbing host does not "
+                    "define (section 2.6)");
+    // eq. (41): P_CL^tot is proportional to C_enh - C_ext + C_sca, with the same
+    // prefactor as P_EELS (37), P_ext (48) and P_CL (42)
+    for (int i = 0; i < n; ++i) out[i] = res[i].p_eels - res[i].p_ext + res[i].p_cl;
+    return DDA_OK;
+    DDA_API_END
+}
+
+int dda_psf_gauss(const double* energy_eV, const double* p, int n, double fwhm_eV,
+                  double* out) {
+    DDA_API_BEGIN
+    if (n < 1 || !energy_eV || !p || !out) throw Error(DDA_EINVAL, "bad arguments");
+    if (!(fwhm_eV > 0.0) || !std::isfinite(fwhm_eV)) throw Error(DDA_EINVAL, "fwhm must be > 0");
+    if (n == 1) {
+        out[0] = p[0];
+        return DDA_OK;
+    }
+    const double de = (energy_eV[n - 1] - energy_eV[0]) / (n - 1);
+    if (!(de > 0.0)) throw Error(DDA_EINVAL, "energies must increase");
+    for (int i = 0; i < n; ++i)
+        if (std::abs(energy_eV[i] - (energy_eV[0] + i * de)) > 1e-9 * std::abs(de) * n)
+            throw Error(DDA_EINVAL, "energies must lie on a uniform grid");
+    // Gaussian of unit area and the given full width at half maximum, sampled on
+    // the grid; the spectrum is taken as zero outside it (no renormalisation at
+    // the ends)
+    const double sigma = fwhm_eV / (2.0 * std::sqrt(2.0 * std::log(2.0)));
+    const double norm = de / (sigma * std::sqrt(2.0 * kPi));
+    std::vector<double> tmp(size_t(n), 0.0);
+    for (int i = 0; i < n; ++i) {
+        double acc = 0.0;
+        for (int j = 0; j < n; ++j) {
+            const double u = (i - j) * de / sigma;
+            acc += p[j] * std::exp(-0.5 * u * u);
+        }
+        tmp[size_t(i)] = norm * acc;
+    }
+    for (int i = 0; i < n; ++i) out[i] = tmp[size_t(i)];
+    return DDA_OK;
+    DDA_API_END
+}
+
 int dda_setup(const uint8_t* mask, int nx, int ny, int nz, double d_nm, double mh_re,
               double mh_im, const dda_options* opt, void* hip_stream, dda_ctx** out) {
     DDA_API_BEGIN
