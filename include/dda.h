@@ -234,6 +234,28 @@ int dda_eels_cl(dda_ctx* ctx, int n_energy, const double* energy_eV, double beta
                 const void* einc_dev, const void* p_dev, dda_result* out);
 
 /*
+ * CL resolved over directions (eq. 42 and section 2.6: a detector collects the
+ * scattered light over some solid angle).  For every right-hand side
+ * (energy e, trajectory t; p_dev as dda_solve leaves it, [e][t][3][n_occ]
+ * complex128, device) and unit direction n_q (dir_xyz [n_dir][3], host):
+ *   A_q = sum_j p_j exp(-i k n_q . r_j),  k = m_h k0 (non-absorbing host),
+ *   dp_domega[rhs][q] = Pi/(m_h^2 |gamma_h|^2) k^3/(4 pi) |(I - n_q n_q) A_q|^2
+ *                       (CL probability per unit solid angle, 1/(eV sr)),
+ *   p_cl[rhs] = sum_q weight[q] dp_domega[rhs][q].
+ * With weights of a rule exact on the sphere, p_cl equals P_CL of
+ * dda_eels_cl (the angular integral of Im G); with weights over a detector's
+ * directions it is the collected signal.  The dipole sum runs on the FP64
+ * matrix cores, one complex product (directions x dipoles) x (dipoles x
+ * 3 n_traj) per energy.  dp_domega and p_cl are host arrays (either may be
+ * NULL; p_cl needs weight).  Blocks until the results are on the host.
+ * Errors: DDA_EINVAL for an absorbing host, non-unit directions, bad sizes,
+ * or lattice sides summing to more than 256.
+ */
+int dda_cl_directions(dda_ctx* ctx, int n_energy, const double* energy_eV, double beta,
+                      int n_traj, const void* p_dev, int n_dir, const double* dir_xyz,
+                      const double* weight, double* dp_domega, double* p_cl);
+
+/*
  * One FFT matvec y = A x (or y = sum_{j!=i} G x_j when interaction_only) for
  * nrhs vectors of one energy, in the given precision.  x_dev and y_dev are
  * complex128 [nrhs][3][n_occ]; for DDA_PREC_MIXED they are complex64 and the

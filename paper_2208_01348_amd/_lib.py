@@ -27,7 +27,8 @@ EXPORTED = ["dda_default_options", "dda_beta_from_keV", "dda_setup", "dda_n_occ"
             "dda_last_error", "dda_debug_besselk01", "dda_workspace_bytes", "dda_engine_open",
             "dda_engine_submit", "dda_engine_poll", "dda_engine_status", "dda_engine_close",
             "dda_set_host", "dda_stream_create", "dda_stream_destroy", "dda_tuning",
-            "dda_set_tuning", "dda_free_space_loss", "dda_cl_total", "dda_psf_gauss"]
+            "dda_set_tuning", "dda_free_space_loss", "dda_cl_total", "dda_psf_gauss",
+            "dda_cl_directions"]
 
 
 class DDAError(RuntimeError):
@@ -99,6 +100,7 @@ def load() -> ctypes.CDLL:
         "dda_free_space_loss": (_i, [_d, _d, _d, _vp]),
         "dda_cl_total": (_i, [_vp, _i, _d, _vp]),
         "dda_psf_gauss": (_i, [_vp, _vp, _i, _d, _vp]),
+        "dda_cl_directions": (_i, [_vp, _i, _vp, _d, _i, _vp, _i, _vp, _vp, _vp, _vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -173,6 +175,23 @@ def dda_psf_gauss(energy_eV, p, fwhm_eV: float) -> np.ndarray:
     out = np.empty_like(v)
     _check(load().dda_psf_gauss(_ptr(E), _ptr(v), E.size, float(fwhm_eV), _ptr(out)))
     return out
+
+
+def dda_cl_directions(ctx, energies, beta: float, n_traj: int, p_ptr: int, dirs, weights=None,
+                      want_dp: bool = True):
+    """(dP/dOmega [rhs][n_dir] or None, P_CL over the weights [rhs] or None)."""
+    E = _f64(energies).reshape(-1)
+    D = _f64(dirs).reshape(-1, 3)
+    nrhs = E.size * n_traj
+    dp = np.empty((nrhs, D.shape[0])) if want_dp else None
+    w = None if weights is None else _f64(weights).reshape(-1)
+    pcl = np.empty(nrhs) if w is not None else None
+    _check(load().dda_cl_directions(ctx, E.size, _ptr(E), float(beta), n_traj,
+                                    ctypes.c_void_p(p_ptr), D.shape[0], _ptr(D),
+                                    None if w is None else _ptr(w),
+                                    None if dp is None else _ptr(dp),
+                                    None if pcl is None else _ptr(pcl)))
+    return dp, pcl
 
 
 def dda_setup(mask: np.ndarray, nx: int, ny: int, nz: int, d_nm: float, mh_re: float,

@@ -266,6 +266,7 @@ struct dda_ctx {
     DevBuf G, vec128, vec64, st, partial, slot_sys, dptr, ainv128, ainv64, misc;
     DevBuf dfull;  // scratch of the full-grid transform during a D build
     DevBuf eps_dev, matsys;  // permittivities and wavenumbers of a chunk
+    DevBuf ff_coord, ff_buf;  // far-field: packed dipole coordinates, work space
     PinnedBuf host_st, host_misc;
     ActRing act;
     StateRing ring;
@@ -1423,6 +1424,89 @@ double dda_beta_from_keV(double kinetic_keV) {
 }
 
 const char* dda_last_error(void) { return g_last_error.c_str(); }
+
+// ------------------------------------------------------- far-field CL -----
+
+int dda_cl_directions(dda_ctx* c, int n_energy, const double* energy_eV, double beta,
+                      int n_traj, const void* p_dev, int n_dir, const double* dir_xyz,
+                      const double* weight, double* dp_domega, double* p_cl) {
+    DDA_API_BEGIN
+    if (!c) throw Error(DDA_EINVAL, "ctx is NULL");
+    if (n_energy < 0 || n_traj < 0 || n_dir < 0) throw Error(DDA_EINVAL, "negative size");
+    const int64_t nrhs = int64_t(n_energy) * n_traj;
+    if (nrhs == 0 || n_dir == 0) return DDA_OK;
+    if (!energy_eV || !p_dev || !dir_xyz) throw Error(DDA_EINVAL, "NULL argument");
+    if (p_cl && !weight) throw Error(DDA_EINVAL, "p_cl needs the direction weights");
+    if (c->mh.imag() != 0.0)
+        throw Error(DDA_EINVAL, "far-field CL needs a non-absorbing host (section 2.6)");
+    check_energies(n_energy, energy_eV);
+    check_beta(c, beta);
+    for (int q = 0; q < n_dir; ++q) {
+        const double* n = dir_xyz + 3 * q;
+        const double r2 = n[0] * n[0] + n[1] * n[1] + n[2] * n[2];
+        if (!std::isfinite(r2) || std::abs(r2 - 1.0) > 1e-9)
+            throw Error(DDA_EINVAL, "directions must be unit vectors");
+        if (weight) check_finite(weight[q], "weight");
+    }
+    const dda::Geo& g = c->g;
+    if (g.n_occ == 0) {
+        if (dp_domega) std::fill(dp_domega, dp_domega + nrhs * n_dir, 0.0);
+        if (p_cl) std::fill(p_cl, p_cl + nrhs, 0.0);
+        return DDA_OK;
+    }
+    if (dda::ff_lds_bytes(g.nx, g.ny, g.nz) > (size_t(64) << 10))
+        throw Error(DDA_EINVAL, "lattice sides too long for the far-field phase tables");
+    if (!c->ff_coord.p) {
+        std::vector<int> pc(c->occ_lin.size());
+        for (size_t j = 0; j < pc.size(); ++j) {
+            const int lin = c->occ_lin[j];
+            const int ix = lin % g.nx, iy = (lin / g.nx) % g.ny, iz = lin / (g.nx * g.ny);
+            pc[j] = ix | (iy << 10) | (iz << 20);
+        }
+        c->ff_coord.ensure(pc.size() * sizeof(int));
+        upload(c, c->ff_coord.p, pc.data(), pc.size() * sizeof(int));
+    }
+    const cplx gam = gamma_h_of(beta, c->mh);
+    const double mh = c->mh.real();
+    std::vector<double> kd(static_cast<size_t>(n_energy)), scale(static_cast<size_t>(nrhs));
+    for (int e = 0; e < n_energy; ++e) {
+        const double k0 = energy_eV[e] / kHbarC, k = mh * k0;
+        kd[size_t(e)] = k * c->d;
+        const double Pi = 4.0 * kAlphaFs * k0 * k0 / (kPi * kHbarC * std::pow(beta, 4));
+        const double sc = Pi / (mh * mh * std::norm(gam)) * k * k * k / (4.0 * kPi);
+        for (int t = 0; t < n_traj; ++t) scale[size_t(e) * n_traj + t] = sc;
+    }
+    // work space: dirs, weights, kd, scale, dP/dOmega, P_CL, amplitudes
+    const size_t bd = size_t(n_dir) * 3 * sizeof(double), bw = size_t(n_dir) * sizeof(double);
+    const size_t bk = kd.size() * sizeof(double), bs = scale.size() * sizeof(double);
+    const size_t bp = size_t(nrhs) * n_dir * sizeof(double), bc = size_t(nrhs) * sizeof(double);
+    const size_t ba = size_t(nrhs) * n_dir * 3 * sizeof(z128);
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    c->ff_buf.ensure(up(bd) + up(bw) + up(bk) + up(bs) + up(bp) + up(bc) + up(ba));
+    char* base = c->ff_buf.as<char>();
+    double* ddir = reinterpret_cast<double*>(base);
+    double* dw = reinterpret_cast<double*>(base + up(bd));
+    double* dkd = reinterpret_cast<double*>(base + up(bd) + up(bw));
+    double* dsc = reinterpret_cast<double*>(base + up(bd) + up(bw) + up(bk));
+    double* ddp = reinterpret_cast<double*>(base + up(bd) + up(bw) + up(bk) + up(bs));
+    double* dpc = reinterpret_cast<double*>(base + up(bd) + up(bw) + up(bk) + up(bs) + up(bp));
+    z128* damp = reinterpret_cast<z128*>(base + up(bd) + up(bw) + up(bk) + up(bs) + up(bp) +
+                                         up(bc));
+    upload(c, ddir, dir_xyz, bd);
+    if (weight) upload(c, dw, weight, bw);
+    upload(c, dkd, kd.data(), bk);
+    upload(c, dsc, scale.data(), bs);
+    dda::launch_ff_amp(static_cast<const z128*>(p_dev), c->ff_coord.as<int>(), g.n_occ, g.nx,
+                       g.ny, g.nz, ddir, n_dir, dkd, n_energy, n_traj, damp, c->stream);
+    dda::launch_ff_power(damp, ddir, weight ? dw : nullptr, n_dir, dsc, nrhs,
+                         dp_domega ? ddp : nullptr, p_cl ? dpc : nullptr, c->stream);
+    if (dp_domega)
+        DDA_HIP_CHECK(hipMemcpyAsync(dp_domega, ddp, bp, hipMemcpyDeviceToHost, c->stream));
+    if (p_cl) DDA_HIP_CHECK(hipMemcpyAsync(p_cl, dpc, bc, hipMemcpyDeviceToHost, c->stream));
+    wait_stream(c);
+    return DDA_OK;
+    DDA_API_END
+}
 
 // ----------------------------------------------------- total-loss helpers -----
 // Closed forms on the host; no device work.

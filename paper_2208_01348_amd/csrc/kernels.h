@@ -82,6 +82,17 @@ template <typename T>
 void launch_extract_corner(const z128* full, cx<T>* out, const Geo& g, hipStream_t s);
 template <typename T>
 void launch_extract_yz(const z128* full, cx<T>* out, const Geo& g, hipStream_t s);
+// Far-field amplitudes (farfield.hip).  p [e][t][3][n_occ], coord packed
+// ix | iy << 10 | iz << 20 per dipole, dirs [n_dir][3], kd [e] = k d;
+// amp [e][t][n_dir][3].  Then dP/dOmega [rhs][n_dir] = scale[rhs] |(I - nn) A|^2
+// and pcl[rhs] = sum_q w_q dP/dOmega (either output may be NULL).
+size_t ff_lds_bytes(int nx, int ny, int nz);
+void launch_ff_amp(const z128* p, const int* coord, int64_t n_occ, int nx, int ny, int nz,
+                   const double* dirs, int n_dir, const double* kd, int n_energy, int n_traj,
+                   z128* amp, hipStream_t s);
+void launch_ff_power(const z128* amp, const double* dirs, const double* w, int n_dir,
+                     const double* scale, int64_t nrhs, double* dp, double* pcl, hipStream_t s);
+
 int64_t dyz_elems(const Geo& g);
 
 // Three-pass chain (matvec_yz.hip), used when the padded yz plane of the three

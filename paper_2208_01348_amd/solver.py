@@ -133,6 +133,18 @@ class DDASolver:
         with self._ordered():
             return L.dda_eels_cl(self.ctx, E, beta, eps, r0, einc.data_ptr(), p.data_ptr())
 
+    def cl_directions(self, energies: Sequence[float], beta: float, n_traj: int,
+                      p: torch.Tensor, dirs: np.ndarray, weights: Optional[np.ndarray] = None,
+                      want_dp: bool = True):
+        """CL per unit solid angle [rhs][n_dir] in 1/(eV sr) for the solution p
+        (as solve() returns it), and its weighted sum over the directions."""
+        E = np.atleast_1d(np.asarray(energies, dtype=np.float64))
+        if p.dtype != torch.complex128 or not p.is_contiguous():
+            raise ValueError("p must be a contiguous complex128 tensor")
+        with self._ordered():
+            return L.dda_cl_directions(self.ctx, E, beta, n_traj, p.data_ptr(), dirs, weights,
+                                       want_dp)
+
     def matvec(self, energy: float, eps: Optional[np.ndarray], x: torch.Tensor,
                precision: str = "fp64", interaction_only: bool = False,
                out: Optional[torch.Tensor] = None) -> torch.Tensor:
