@@ -28,6 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_MFMA_PEAK_TFS = 78.6  # MI355X dense FP64 matrix peak
 KERNELS = ["unpack_xfft", "yfft", "zconv", "iyfft", "ixfft_pack", "yzconv"]
 # the costliest kernel of the matvec chain: the fused yz kernel on lattices
 # whose padded yz plane fits in LDS, the z pass otherwise (profiles/)
@@ -220,6 +221,7 @@ def main():
         if args.c3_energies > 0:
             extras["cherenkov_c3"] = measure_batch(torch, W, DDASolver, "c3",
                                                    args.c3_energies, log)
+        extras["far_field_cl"] = measure_farfield(torch, W, DDASolver, log)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -410,6 +412,54 @@ def measure_batch(torch, W, DDASolver, which, n_energy, log):
             "n_occ": n, "fft_grid": list(s.grid), "iterations_median": int(np.median(its)),
             "iterations_max": max(its), "tol": w.tol, "precision": "mixed",
             "all_converged": all(i.status == 0 for i in info), "autotune": tuning}
+
+
+def _sphere_directions(n_theta, n_phi):
+    """Gauss-Legendre in cos(theta) x equispaced phi: unit directions and
+    solid-angle weights (sum 4 pi)."""
+    x, wx = np.polynomial.legendre.leggauss(n_theta)
+    phi = 2.0 * np.pi * np.arange(n_phi) / n_phi
+    st = np.sqrt(1.0 - x * x)
+    d = np.stack([np.outer(st, np.cos(phi)), np.outer(st, np.sin(phi)),
+                  np.outer(x, np.ones(n_phi))], axis=-1).reshape(-1, 3)
+    return d, np.outer(wx, np.full(n_phi, 2.0 * np.pi / n_phi)).reshape(-1)
+
+
+def measure_farfield(torch, W, DDASolver, log):
+    """CL over 2,048 directions on the FP64 matrix cores: the impact-map
+    lattice (48^3 ellipsoid) with its 256 trajectories at one energy (one
+    product of 2,048 x n_occ phases by n_occ x 768 moments), and the nanorod
+    spectrum (128 energies x 1 trajectory).  Seeded random moments stand in
+    for solutions (the arithmetic does not depend on their values)."""
+    out = {}
+    dirs, wts = _sphere_directions(32, 64)
+    for name, w, E, nt in [("impact_map_c4", W.c4_impact_map(n_energy=1), None, 256),
+                           ("spectrum_c2", W.c2_nanorod_spectrum(), None, 1)]:
+        n = w.n_occ
+        energies = w.energies[:1] if nt > 1 else w.energies
+        nrhs = len(energies) * nt
+        g = torch.Generator(device="cuda").manual_seed(5)
+        p = torch.randn((nrhs, 3, n), dtype=torch.complex128, device="cuda", generator=g)
+        s = DDASolver(w.mask, w.d, w.m_h)
+        s.cl_directions(energies, w.beta, nt, p, dirs[:64], wts[:64], want_dp=False)  # warm-up
+        times = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            s.cl_directions(energies, w.beta, nt, p, dirs, wts, want_dp=False)
+            times.append(time.perf_counter() - t)
+        s.close()
+        dt = min(times)
+        flops = 8.0 * dirs.shape[0] * n * 3 * nrhs
+        tf = flops / dt / 1e12
+        log(f"far field {name}: {nrhs} rhs x {dirs.shape[0]} directions in {dt * 1e3:.2f} ms, "
+            f"{tf:.1f} TFLOP/s FP64 matrix ({tf / FP64_MFMA_PEAK_TFS:.1%} of peak)")
+        out[name] = {"rhs": nrhs, "directions": int(dirs.shape[0]), "n_occ": n,
+                     "ms": round(dt * 1e3, 3), "tflops": round(tf, 2),
+                     "frac_of_fp64_matrix_peak": round(tf / FP64_MFMA_PEAK_TFS, 4),
+                     "note": "whole call: phase tables, matrix-core product, |A_perp|^2 and "
+                             "the weighted sum; 8 flops per complex multiply-add"}
+    return out
 
 
 def cpu_baseline(w, gpu_matvecs, log):
