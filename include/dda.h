@@ -128,6 +128,18 @@ double dda_beta_from_keV(double kinetic_keV);
 int dda_free_space_loss(double beta, double mh_re, double mh_im, double* dgamma_dz);
 
 /*
+ * Richardson extrapolation to zero dipole size (section 3.2): a weighted
+ * least-squares quadratic a + b d + c d^2 through (d_nm[i], value[i]), i < n,
+ * the errors of the points taken to scale as d^3 (weights d^-6).  at_zero =
+ * a; ci95 (may be NULL) = twice the standard error of a, the residual
+ * variance estimated from the n - 3 degrees of freedom (NaN for n = 3).  Host
+ * only.  Errors: DDA_EINVAL for n < 3, d <= 0, non-finite values, or sizes
+ * that do not determine a quadratic (fewer than three distinct).
+ */
+int dda_richardson(const double* d_nm, const double* value, int n, double* at_zero,
+                   double* ci95);
+
+/*
  * Total particle-related CL probability, eq. (41): out[i] = P_EELS - P_ext +
  * P_CL of res[i] (the cross sections C_enh - C_ext + C_sca share the
  * prefactor of eqs. 37, 42, 48); equal to P_CL when beta_h < 1.  Host only;

@@ -28,7 +28,7 @@ EXPORTED = ["dda_default_options", "dda_beta_from_keV", "dda_setup", "dda_n_occ"
             "dda_engine_submit", "dda_engine_poll", "dda_engine_status", "dda_engine_close",
             "dda_set_host", "dda_stream_create", "dda_stream_destroy", "dda_tuning",
             "dda_set_tuning", "dda_free_space_loss", "dda_cl_total", "dda_psf_gauss",
-            "dda_cl_directions"]
+            "dda_cl_directions", "dda_richardson"]
 
 
 class DDAError(RuntimeError):
@@ -101,6 +101,7 @@ def load() -> ctypes.CDLL:
         "dda_cl_total": (_i, [_vp, _i, _d, _vp]),
         "dda_psf_gauss": (_i, [_vp, _vp, _i, _d, _vp]),
         "dda_cl_directions": (_i, [_vp, _i, _vp, _d, _i, _vp, _i, _vp, _vp, _vp, _vp]),
+        "dda_richardson": (_i, [_vp, _vp, _i, _vp, _vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -175,6 +176,18 @@ def dda_psf_gauss(energy_eV, p, fwhm_eV: float) -> np.ndarray:
     out = np.empty_like(v)
     _check(load().dda_psf_gauss(_ptr(E), _ptr(v), E.size, float(fwhm_eV), _ptr(out)))
     return out
+
+
+def dda_richardson(d_nm, values):
+    """(extrapolated value at d = 0, 95 % half-width) of one quantity."""
+    d = _f64(d_nm).reshape(-1)
+    v = _f64(values).reshape(-1)
+    if d.shape != v.shape:
+        raise ValueError("one value per dipole size")
+    a = ctypes.c_double()
+    ci = ctypes.c_double()
+    _check(load().dda_richardson(_ptr(d), _ptr(v), d.size, ctypes.byref(a), ctypes.byref(ci)))
+    return a.value, ci.value
 
 
 def dda_cl_directions(ctx, energies, beta: float, n_traj: int, p_ptr: int, dirs, weights=None,

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <limits>
 #include <complex>
 #include <cstring>
 #include <deque>
@@ -1524,6 +1525,65 @@ int dda_free_space_loss(double beta, double mh_re, double mh_im, double* dgamma_
     // / (hbar c) above the Cherenkov threshold beta_h = beta m_h > 1, zero below
     const double bh = beta * mh_re;
     *dgamma_dz = bh > 1.0 ? kAlphaFs * (1.0 - 1.0 / (bh * bh)) / kHbarC : 0.0;
+    return DDA_OK;
+    DDA_API_END
+}
+
+int dda_richardson(const double* d_nm, const double* value, int n, double* at_zero,
+                   double* ci95) {
+    DDA_API_BEGIN
+    if (n < 3 || !d_nm || !value || !at_zero) throw Error(DDA_EINVAL, "need n >= 3 points");
+    double dmax = 0.0;
+    for (int i = 0; i < n; ++i) {
+        if (!(d_nm[i] > 0.0) || !std::isfinite(d_nm[i]) || !std::isfinite(value[i]))
+            throw Error(DDA_EINVAL, "dipole sizes must be > 0 and values finite");
+        dmax = std::max(dmax, d_nm[i]);
+    }
+    // weighted normal equations for a + b t + c t^2, t = d / dmax (scaled for
+    // conditioning), weights t^-6 (errors ~ d^3)
+    double M[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, r[3] = {0, 0, 0};
+    for (int i = 0; i < n; ++i) {
+        const double t = d_nm[i] / dmax, w = 1.0 / (t * t * t * t * t * t);
+        const double x[3] = {1.0, t, t * t};
+        for (int a = 0; a < 3; ++a) {
+            r[a] += w * x[a] * value[i];
+            for (int b = 0; b < 3; ++b) M[a][b] += w * x[a] * x[b];
+        }
+    }
+    // inverse of the symmetric 3 x 3 matrix by cofactors
+    const double c00 = M[1][1] * M[2][2] - M[1][2] * M[2][1];
+    const double c01 = M[1][2] * M[2][0] - M[1][0] * M[2][2];
+    const double c02 = M[1][0] * M[2][1] - M[1][1] * M[2][0];
+    const double det = M[0][0] * c00 + M[0][1] * c01 + M[0][2] * c02;
+    if (!(std::abs(det) > 0.0) || !std::isfinite(det))
+        throw Error(DDA_EINVAL, "the dipole sizes do not determine a quadratic");
+    double Mi[3][3];
+    Mi[0][0] = c00 / det;
+    Mi[0][1] = (M[0][2] * M[2][1] - M[0][1] * M[2][2]) / det;
+    Mi[0][2] = (M[0][1] * M[1][2] - M[0][2] * M[1][1]) / det;
+    Mi[1][0] = c01 / det;
+    Mi[1][1] = (M[0][0] * M[2][2] - M[0][2] * M[2][0]) / det;
+    Mi[1][2] = (M[0][2] * M[1][0] - M[0][0] * M[1][2]) / det;
+    Mi[2][0] = c02 / det;
+    Mi[2][1] = (M[0][1] * M[2][0] - M[0][0] * M[2][1]) / det;
+    Mi[2][2] = (M[0][0] * M[1][1] - M[0][1] * M[1][0]) / det;
+    double coef[3];
+    for (int a = 0; a < 3; ++a) coef[a] = Mi[a][0] * r[0] + Mi[a][1] * r[1] + Mi[a][2] * r[2];
+    *at_zero = coef[0];
+    if (ci95) {
+        if (n == 3) {
+            *ci95 = std::numeric_limits<double>::quiet_NaN();
+        } else {
+            double s2 = 0.0;
+            for (int i = 0; i < n; ++i) {
+                const double t = d_nm[i] / dmax, w = 1.0 / (t * t * t * t * t * t);
+                const double res = value[i] - (coef[0] + coef[1] * t + coef[2] * t * t);
+                s2 += w * res * res;
+            }
+            s2 /= (n - 3);
+            *ci95 = 2.0 * std::sqrt(s2 * Mi[0][0]);
+        }
+    }
     return DDA_OK;
     DDA_API_END
 }

@@ -1,0 +1,51 @@
+"""Lattice series and Richardson extrapolation on the GPU (section 3.2): every
+lattice's probabilities against dense LU, and the extrapolation of the GPU
+values against the oracle's fit."""
+
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+import workloads as W  # noqa: E402
+from oracle import extrapolate as X  # noqa: E402
+from oracle.dda import solve_point  # noqa: E402
+from paper_2208_01348_amd.series import lattice_series  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def test_sphere_series_matches_oracle_and_extrapolates():
+    R = 6.0
+    n_list = [12, 10, 8, 7, 6]
+    E = np.array([2.3])
+    r0 = np.array([[9.0, 0.0, 0.0]])
+    ds, P, ext, ci, infos = lattice_series(
+        lambda n, d: W.sphere_mask(n, d, R), 2 * R, n_list, 1.45, 0.55, E,
+        lambda e: W.drude_eps(e), r0, precision="mixed", tol=1e-10)
+    assert all(i.status == 0 for info in infos for i in info)
+    for k, (n, d) in enumerate(zip(n_list, ds)):
+        mask = W.sphere_mask(n, d, R)
+        eps = np.full(int(mask.sum()), W.drude_eps(E)[0])
+        ref = solve_point(mask, d, eps, 1.45, 0.55, r0[0], E[0], method="lu")
+        vals = [ref.p_eels, ref.p_ext, ref.p_abs, ref.p_cl]
+        scale = max(abs(v) for v in vals)
+        for q in range(4):
+            err = abs(P[k, 0, q] - vals[q]) / max(abs(vals[q]), 1e-3 * scale)
+            assert err <= 1e-5, (n, q, err)
+        say(f"  n_x={n} d={d:.3f}: P_EELS {P[k, 0, 0]:.6e}")
+    for q in range(4):
+        a_o, ci_o = X.richardson(ds, P[:, 0, q])
+        assert ext[0, q] == pytest.approx(a_o, rel=1e-10)
+        assert ci[0, q] == pytest.approx(ci_o, rel=1e-8)
+    say(f"  extrapolated P_EELS {ext[0, 0]:.6e} +- {ci[0, 0]:.2e}")
+    # the extrapolated value lies within a few per cent of the finest lattice
+    assert abs(ext[0, 0] - P[0, 0, 0]) <= 0.05 * abs(P[0, 0, 0])
