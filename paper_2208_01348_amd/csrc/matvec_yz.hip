@@ -103,10 +103,12 @@ __global__ __launch_bounds__(NT) void k_xfft_t(cx<T>* __restrict__ xin,
     constexpr int HX = (LX + 1) / 2;
     constexpr int NE = (NR * HX + NT - 1) / NT;
     __shared__ cx<T> lds[NR * LP];
+    __shared__ cx<T> twl[LX];  // twiddles in LDS: the stage loads index them per lane
     const int tid = threadIdx.x;
     const int pos = blockIdx.y;
     const int64_t slot = act ? act[pos] : pos;
     if (!slot_live(f, slot)) return;
+    for (int t = tid; t < LX; t += NT) twl[t] = tw[t];
     const int grp = blockIdx.x % ngroups;
     const int cz = blockIdx.x / ngroups;
     const int c = cz / g.nz, z = cz - (cz / g.nz) * g.nz;
@@ -156,7 +158,7 @@ __global__ __launch_bounds__(NT) void k_xfft_t(cx<T>* __restrict__ xin,
         }
     }
     __syncthreads();
-    fft_tile<T, LX, false, NR, LP, 1, NT>(lds, tw, tid, nrow);
+    fft_tile<T, LX, false, NR, LP, 1, NT>(lds, twl, tid, nrow);
     const int64_t cplane = int64_t(3) * g.nz * g.ny;  // one kx column
     cx<T>* dst = Tb + int64_t(pos) * g.mx * cplane + (int64_t(c) * g.nz + z) * g.ny;
     const bool perm = (g.ny & 7) == 0;
@@ -183,10 +185,12 @@ __global__ __launch_bounds__(NT) void k_ixfft_t(const cx<T>* __restrict__ Tb,
     constexpr int NL = (NR * LX + NT - 1) / NT;
     constexpr int NE = (NR * HX + NT - 1) / NT;
     __shared__ cx<T> lds[NR * LP];
+    __shared__ cx<T> twl[LX];
     const int tid = threadIdx.x;
     const int pos = blockIdx.y;
     const int64_t slot = act ? act[pos] : pos;
     if (!slot_live(f, slot)) return;
+    for (int t = tid; t < LX; t += NT) twl[t] = tw[t];
     const int64_t sys = slot_sys[slot];
     const int grp = blockIdx.x % ngroups;
     const int cz = blockIdx.x / ngroups;
@@ -213,7 +217,7 @@ __global__ __launch_bounds__(NT) void k_ixfft_t(const cx<T>* __restrict__ Tb,
         }
     }
     __syncthreads();
-    fft_tile<T, LX, true, NR, LP, 1, NT>(lds, tw, tid, nrow);
+    fft_tile<T, LX, true, NR, LP, 1, NT>(lds, twl, tid, nrow);
     const int64_t voff = (slot * 3 + c) * g.n_occ;
     const int* mrow = map + (int64_t(z) * g.ny + y0) * g.nx;
     int idx[NE];
