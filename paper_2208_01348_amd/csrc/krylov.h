@@ -37,14 +37,7 @@ void residual(const cx<T>* b, const cx<T>* y, cx<T>* r, BicgSlot* st, const int*
               int64_t nv, RedScratch red, hipStream_t s);
 
 // COCG (conjugate-orthogonal CG for complex-symmetric A, bilinear products
-// x^T y): p = r, rho = r^T r, beta = 0.
-template <typename T>
-void cocg_reset(const cx<T>* r, cx<T>* p, BicgSlot* st, const int* act, int n_act, int64_t nv,
-                RedScratch red, hipStream_t s);
-// mu = p^T q, alpha = rho / mu (used when the matvec does not fuse it)
-template <typename T>
-void cocg_alpha(const cx<T>* p, const cx<T>* q, BicgSlot* st, const int* act, int n_act,
-                int64_t nv, RedScratch red, hipStream_t s);
+// x^T y).  The matvec's pack kernel writes the partial rows of mu = p^T q.
 // alpha = rho / mu from the partial rows the fused pack kernel wrote (nblk
 // rows per slot)
 void cocg_alpha_finalize(BicgSlot* st, const int* act, int n_act, RedScratch red, int nblk,

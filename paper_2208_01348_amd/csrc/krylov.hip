@@ -285,42 +285,6 @@ __global__ __launch_bounds__(NT) void k_accumulate_up(z128* __restrict__ x,
 }
 
 // ---------------------------------------------------------------- COCG ----
-template <typename T>
-__global__ __launch_bounds__(NT) void k_cocg_reset(const cx<T>* __restrict__ r,
-                                                   cx<T>* __restrict__ p,
-                                                   const int* __restrict__ act, int64_t nv,
-                                                   RedScratch red) {
-    SLOT_PROLOGUE
-    double s[3] = {0.0, 0.0, 0.0};
-    for (int64_t i = i0; i < nv; i += stride) {
-        const cx<T> ri = r[base + i];
-        p[base + i] = ri;
-        acc_bdot(s[0], s[1], ri, ri);
-        s[2] += double(norm2(ri));
-    }
-    block_partial<3, NT>(s, red, slot, blockIdx.x);
-}
-__global__ __launch_bounds__(NT) void k_fin_cocg_reset(BicgSlot* st, const int* act,
-                                                       RedScratch red, int nblk) {
-    FIN_PROLOGUE(3)
-    S.rho = z128{tot[0], tot[1]};
-    S.beta = z128{0.0, 0.0};
-    S.rnorm2 = tot[2];
-    S.rmax2 = tot[2];
-    S.want_update = 0;
-    S.status = (tot[2] <= S.tol2 * S.bnorm2) ? SLOT_CONVERGED : SLOT_ACTIVE;
-}
-
-template <typename T>
-__global__ __launch_bounds__(NT) void k_cocg_alpha(const cx<T>* __restrict__ p,
-                                                   const cx<T>* __restrict__ q,
-                                                   const int* __restrict__ act, int64_t nv,
-                                                   RedScratch red) {
-    SLOT_PROLOGUE
-    double s[2] = {0.0, 0.0};
-    for (int64_t i = i0; i < nv; i += stride) acc_bdot(s[0], s[1], p[base + i], q[base + i]);
-    block_partial<2, NT>(s, red, slot, blockIdx.x);
-}
 __global__ __launch_bounds__(NT) void k_fin_cocg_alpha(BicgSlot* st, const int* act,
                                                        RedScratch red, int nblk) {
     FIN_PROLOGUE(2)
@@ -622,22 +586,6 @@ void residual(const cx<T>* b, const cx<T>* y, cx<T>* r, BicgSlot* st, const int*
     DDA_LAUNCH_CHECK();
     FIN(k_fin_residual);
 }
-template <typename T>
-void cocg_reset(const cx<T>* r, cx<T>* p, BicgSlot* st, const int* act, int n_act, int64_t nv,
-                RedScratch red, hipStream_t s) {
-    if (n_act == 0) return;
-    k_cocg_reset<T><<<GRID(nv), NT, 0, s>>>(r, p, act, nv, red);
-    DDA_LAUNCH_CHECK();
-    FIN(k_fin_cocg_reset);
-}
-template <typename T>
-void cocg_alpha(const cx<T>* p, const cx<T>* q, BicgSlot* st, const int* act, int n_act,
-                int64_t nv, RedScratch red, hipStream_t s) {
-    if (n_act == 0) return;
-    k_cocg_alpha<T><<<GRID(nv), NT, 0, s>>>(p, q, act, nv, red);
-    DDA_LAUNCH_CHECK();
-    FIN(k_fin_cocg_alpha);
-}
 void cocg_alpha_finalize(BicgSlot* st, const int* act, int n_act, RedScratch red, int nblk,
                          hipStream_t s) {
     if (n_act == 0) return;
@@ -733,10 +681,6 @@ void loss_sums(const z128* einc, const z128* p, const z128* y, const double* w, 
                                     RedScratch, hipStream_t);                                    \
     template void residual<T>(const cx<T>*, const cx<T>*, cx<T>*, BicgSlot*, const int*, int,    \
                               int64_t, RedScratch, hipStream_t);                                 \
-    template void cocg_reset<T>(const cx<T>*, cx<T>*, BicgSlot*, const int*, int, int64_t,       \
-                                RedScratch, hipStream_t);                                        \
-    template void cocg_alpha<T>(const cx<T>*, const cx<T>*, BicgSlot*, const int*, int, int64_t, \
-                                RedScratch, hipStream_t);                                        \
     template void cocg_update_xr<T>(cx<T>*, cx<T>*, const cx<T>*, const cx<T>*, BicgSlot*,       \
                                     const int*, int, int64_t, RedScratch, hipStream_t);          \
     template void cocg_start<T>(const z128*, const z128*, cx<T>*, BicgSlot*, const int*, int,    \
