@@ -528,7 +528,6 @@ void matvec(dda_ctx* c, const Work& w, dda::cx<T>* x, dda::cx<T>* y, const int* 
     const dda::Geo& g = c->g;
     auto* G = static_cast<dda::cx<T>*>(w.G);
     hipStream_t s = c->stream;
-    auto* st = w.st;
     constexpr int csize = int(sizeof(dda::cx<T>));
     autotune<T>(c, w, act, n_act, dptr, slot_sys);
     const TuneVal& tn = c->tune[csize == 16 ? 1 : 0];
@@ -576,8 +575,6 @@ void matvec(dda_ctx* c, const Work& w, dda::cx<T>* x, dda::cx<T>* y, const int* 
                                       slot_sys, n_act, mode, f, w.red, s);
         }
     }
-    if (mode == dda::PACK_AX_COCG)
-        dda::cocg_alpha_finalize(st, act, n_act, w.red, pack_blocks(c, csize), s);
 }
 
 template <typename T>
@@ -1009,7 +1006,8 @@ void cocg_interval(dda_ctx* c, const CocgBufs<T>& B, int n_act) {
     for (int k = 0; k < check; ++k) {
         matvec<T>(c, B.w, B.p, B.q, B.act, n_act, B.dptr, B.slot_sys, B.ainv, dda::PACK_AX_COCG,
                   B.r, fact);
-        dda::cocg_update_xr<T>(xs, B.r, B.p, B.q, B.w.st, B.act, n_act, nv, B.w.red, s);
+        dda::cocg_update_xr<T>(xs, B.r, B.p, B.q, B.w.st, B.act, n_act, nv, B.w.red,
+                               pack_blocks(c, int(sizeof(dda::cx<T>))), s);
     }
 }
 

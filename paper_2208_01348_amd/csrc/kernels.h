@@ -62,7 +62,7 @@ std::vector<int> zconv_tx_candidates(int L);
 // mode PACK_AX: y = x/alpha - G_off x; PACK_GX: y = G_off x; PACK_AX_COCG:
 // y = A x and, fused, the partial rows of mu = x^T y per slot in `red`
 // (pack_blocks_per_slot rows, which must not exceed max_blocks); the caller
-// then runs cocg_alpha_finalize.
+// then runs cocg_update_xr, which reads them.
 enum PackMode { PACK_AX = 0, PACK_GX = 1, PACK_AX_COCG = 2 };
 int pack_blocks_per_slot(const Geo& g);
 template <typename T>

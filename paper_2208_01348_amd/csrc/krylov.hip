@@ -285,24 +285,43 @@ __global__ __launch_bounds__(NT) void k_accumulate_up(z128* __restrict__ x,
 }
 
 // ---------------------------------------------------------------- COCG ----
-__global__ __launch_bounds__(NT) void k_fin_cocg_alpha(BicgSlot* st, const int* act,
-                                                       RedScratch red, int nblk) {
-    FIN_PROLOGUE(2)
-    if (S.status != SLOT_ACTIVE) return;
-    S.rv = z128{tot[0], tot[1]};
-    if ((tot[0] == 0.0 && tot[1] == 0.0) || !all_finite(tot, 2)) S.status = SLOT_BREAKDOWN;
-    else S.alpha = zdiv(S.rho, S.rv);
-}
-
+// alpha = rho / mu from the pack kernel's partial rows (doubles 0, 1 of each
+// row; every block sums them in the same fixed order, block 0 records the
+// result or the breakdown), then x += alpha p, r -= alpha q and the partial
+// rows of r^T r and ||r||^2 (doubles 4..6, so the mu rows stay intact while
+// other blocks of the slot still read them).
 template <typename T>
 __global__ __launch_bounds__(NT) void k_cocg_xr(cx<T>* __restrict__ x, cx<T>* __restrict__ r,
                                                 const cx<T>* __restrict__ p,
-                                                const cx<T>* __restrict__ q, const BicgSlot* st,
+                                                const cx<T>* __restrict__ q, BicgSlot* st,
                                                 const int* __restrict__ act, int64_t nv,
-                                                RedScratch red) {
+                                                RedScratch red, int nblk_mu) {
     SLOT_PROLOGUE
     if (st[slot].status != SLOT_ACTIVE) return;
-    const z128 al = st[slot].alpha;
+    __shared__ double mu_sh[2];
+    {
+        double mu[2];
+        sum_rows<2, NT>(red, slot, nblk_mu, mu);
+        if (threadIdx.x == 0) {
+            mu_sh[0] = mu[0];
+            mu_sh[1] = mu[1];
+        }
+    }
+    __syncthreads();
+    const z128 rv{mu_sh[0], mu_sh[1]};
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if ((rv.x == 0.0 && rv.y == 0.0) || !isfinite(rv.x) || !isfinite(rv.y)) {
+        if (lead) {
+            st[slot].rv = rv;
+            st[slot].status = SLOT_BREAKDOWN;
+        }
+        return;
+    }
+    const z128 al = zdiv(st[slot].rho, rv);
+    if (lead) {
+        st[slot].rv = rv;
+        st[slot].alpha = al;
+    }
     const cx<T> a{T(al.x), T(al.y)};
     double s[3] = {0.0, 0.0, 0.0};
     for (int64_t i = i0; i < nv; i += stride) {
@@ -312,12 +331,16 @@ __global__ __launch_bounds__(NT) void k_cocg_xr(cx<T>* __restrict__ x, cx<T>* __
         acc_bdot(s[0], s[1], ri, ri);
         s[2] += double(norm2(ri));
     }
-    block_partial<3, NT>(s, red, slot, blockIdx.x);
+    block_partial<3, NT, 4>(s, red, slot, blockIdx.x);
 }
 __global__ __launch_bounds__(NT) void k_fin_cocg_xr(BicgSlot* st, const int* act, RedScratch red,
                                                     int nblk) {
     if (st[act[blockIdx.x]].status != SLOT_ACTIVE) return;
-    FIN_PROLOGUE(3)
+    const int slot = act[blockIdx.x];
+    double tot[3];
+    sum_rows<3, NT, 4>(red, slot, nblk, tot);
+    if (threadIdx.x != 0) return;
+    BicgSlot& S = st[slot];
     S.iters += 1;
     S.matvecs += 1;
     S.reset_p = 0;
@@ -586,17 +609,13 @@ void residual(const cx<T>* b, const cx<T>* y, cx<T>* r, BicgSlot* st, const int*
     DDA_LAUNCH_CHECK();
     FIN(k_fin_residual);
 }
-void cocg_alpha_finalize(BicgSlot* st, const int* act, int n_act, RedScratch red, int nblk,
-                         hipStream_t s) {
-    if (n_act == 0) return;
-    k_fin_cocg_alpha<<<n_act, NT, 0, s>>>(st, act, red, nblk);
-    DDA_LAUNCH_CHECK();
-}
 template <typename T>
 void cocg_update_xr(cx<T>* x, cx<T>* r, const cx<T>* p, const cx<T>* q, BicgSlot* st,
-                    const int* act, int n_act, int64_t nv, RedScratch red, hipStream_t s) {
+                    const int* act, int n_act, int64_t nv, RedScratch red, int nblk_mu,
+                    hipStream_t s) {
     if (n_act == 0) return;
-    k_cocg_xr<T><<<GRID(nv), NT, 0, s>>>(x, r, p, q, st, act, nv, red);
+    if (nblk_mu < 1 || nblk_mu > red.max_blocks) throw Error(-1, "bad partial row count");
+    k_cocg_xr<T><<<GRID(nv), NT, 0, s>>>(x, r, p, q, st, act, nv, red, nblk_mu);
     DDA_LAUNCH_CHECK();
     FIN(k_fin_cocg_xr);
 }
@@ -682,7 +701,7 @@ void loss_sums(const z128* einc, const z128* p, const z128* y, const double* w, 
     template void residual<T>(const cx<T>*, const cx<T>*, cx<T>*, BicgSlot*, const int*, int,    \
                               int64_t, RedScratch, hipStream_t);                                 \
     template void cocg_update_xr<T>(cx<T>*, cx<T>*, const cx<T>*, const cx<T>*, BicgSlot*,       \
-                                    const int*, int, int64_t, RedScratch, hipStream_t);          \
+                                    const int*, int, int64_t, RedScratch, int, hipStream_t);     \
     template void cocg_start<T>(const z128*, const z128*, cx<T>*, BicgSlot*, const int*, int,    \
                                 int64_t, RedScratch, hipStream_t);                               \
     template void cocg_check<T>(const z128*, const z128*, cx<T>*, BicgSlot*, const int*, int,    \

@@ -92,8 +92,9 @@ __device__ __forceinline__ void wave_sum(double (&v)[K]) {
 
 // Block-reduces K values (blockDim.x == NT) and stores them as partial row
 // `blk` of `slot`.  Must be called by every thread of the block.
-template <int K, int NT>
+template <int K, int NT, int OFF = 0>
 __device__ __forceinline__ void block_partial(double (&v)[K], RedScratch red, int slot, int blk) {
+    static_assert(OFF + K <= 8, "a partial row holds 8 doubles");
     __shared__ double sm[NT / 64][K];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     wave_sum<K>(v);
@@ -105,14 +106,14 @@ __device__ __forceinline__ void block_partial(double (&v)[K], RedScratch red, in
         for (int k = 0; k < K; ++k) {
             double s = 0.0;
             for (int q = 0; q < NT / 64; ++q) s += sm[q][k];
-            row[k] = s;
+            row[OFF + k] = s;
         }
     }
 }
 
 // Sums rows 0..nblk-1 of `slot` in a fixed order; the totals are valid in
 // thread 0.  Must be called by every thread of the block.
-template <int K, int NT>
+template <int K, int NT, int OFF = 0>
 __device__ __forceinline__ void sum_rows(RedScratch red, int slot, int nblk, double (&tot)[K]) {
     __shared__ double sm[NT / 64][K];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -122,7 +123,7 @@ __device__ __forceinline__ void sum_rows(RedScratch red, int slot, int nblk, dou
     for (int k = 0; k < K; ++k) acc[k] = 0.0;
     for (int b = tid; b < nblk; b += NT) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) acc[k] += rows[int64_t(b) * 8 + k];
+        for (int k = 0; k < K; ++k) acc[k] += rows[int64_t(b) * 8 + OFF + k];
     }
     wave_sum<K>(acc);
     if (lane == 0)
