@@ -489,6 +489,16 @@ __device__ __forceinline__ void store_pair(cx<double>* p, cx<double> a, cx<doubl
     p[1] = b;
 }
 
+// The D slabs come through a table of pointers, so the compiler sees
+// generic pointers and emits flat loads, which also count against the LDS
+// wait counter; these loads go through the global address space instead.
+template <typename T>
+__device__ __forceinline__ cx<T> gload(const cx<T>* p) {
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    const v2 v = *(const __attribute__((address_space(1))) v2*)(p);
+    return cx<T>{v.x, v.y};
+}
+
 template <typename T, int L>
 __global__ __launch_bounds__(yzr_threads<L>()) void k_yzconv_r(
     cx<T>* __restrict__ Tb, const cx<T>* const* __restrict__ Dptr, const cx<T>* __restrict__ twy,
@@ -590,7 +600,7 @@ __global__ __launch_bounds__(yzr_threads<L>()) void k_yzconv_r(
             const int t = min(tid + it * NTR, NI - 1);
             const int kzp = 1 + t / HI, kyp = 1 + (t - (t / HI) * HI);
 #pragma unroll
-            for (int q = 0; q < 6; ++q) di[it][q] = dslab[kzp * HD + kyp + q * H2];
+            for (int q = 0; q < 6; ++q) di[it][q] = gload(dslab + kzp * HD + kyp + q * H2);
         }
 #pragma unroll
         for (int it = 0; it < NIE; ++it) {
@@ -598,7 +608,7 @@ __global__ __launch_bounds__(yzr_threads<L>()) void k_yzconv_r(
             edge(min(tid + it * NTR, NEG - 1), ky, kz);
             const int o = (kz > L / 2 ? L - kz : kz) * HD + (ky > L / 2 ? L - ky : ky);
 #pragma unroll
-            for (int q = 0; q < 6; ++q) de[it][q] = dslab[o + q * H2];
+            for (int q = 0; q < 6; ++q) de[it][q] = gload(dslab + o + q * H2);
         }
 #pragma unroll
         for (int it = 0; it < NII; ++it) {
