@@ -255,7 +255,7 @@ __global__ __launch_bounds__(NT) void k_ixfft_t(const cx<T>* __restrict__ Tb,
             }
         }
     }
-    if constexpr (MODE == PACK_AX_COCG)  // partial rows; alpha is finalized by the caller
+    if constexpr (MODE == PACK_AX_COCG)  // partial rows; the COCG update kernel sums them
         block_partial<2, NT>(mu, red, int(slot), blockIdx.x);
 }
 
@@ -529,6 +529,9 @@ __global__ __launch_bounds__(yzr_threads<L>()) void k_yzconv_r(
         cx<T> v[Q];
 #pragma unroll
         for (int n1 = 0; n1 < Q; ++n1) v[n1] = zero;
+        // raised wave priority while the loads go out: they start ahead of the
+        // arithmetic of the other block on the CU (1.5 % on the nanorod lattice)
+        __builtin_amdgcn_s_setprio(2);
         if (perm) {  // whole blocks of 8: lane n2 reads its pair at 8j + 2 n2
 #pragma unroll
             for (int j = 0; 2 * j + 1 < Q / 2 + 1; ++j) {
@@ -541,6 +544,7 @@ __global__ __launch_bounds__(yzr_threads<L>()) void k_yzconv_r(
                 if (y < ny) v[n1] = src[y];
             }
         }
+        __builtin_amdgcn_s_setprio(0);
         quad_fft<T, L, false>(v, n2, twy);
 #pragma unroll
         for (int k1 = 0; k1 < Q; ++k1) lds[(c * L + k1 + Q * rb) * ZS + z] = v[k1];
@@ -595,6 +599,7 @@ __global__ __launch_bounds__(yzr_threads<L>()) void k_yzconv_r(
             }
         };
         cx<T> di[NII][6], de[NIE][6];
+        __builtin_amdgcn_s_setprio(2);  // as for the loads of phase 1
 #pragma unroll
         for (int it = 0; it < NII; ++it) {
             const int t = min(tid + it * NTR, NI - 1);
@@ -610,6 +615,7 @@ __global__ __launch_bounds__(yzr_threads<L>()) void k_yzconv_r(
 #pragma unroll
             for (int q = 0; q < 6; ++q) de[it][q] = gload(dslab + o + q * H2);
         }
+        __builtin_amdgcn_s_setprio(0);
 #pragma unroll
         for (int it = 0; it < NII; ++it) {
             const int t = tid + it * NTR;
