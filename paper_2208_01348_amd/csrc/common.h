@@ -46,6 +46,16 @@ __host__ __device__ __forceinline__ T norm2(cx<T> a) { return a.x * a.x + a.y * 
 template <typename TO, typename TI>
 __host__ __device__ __forceinline__ cx<TO> cvt(cx<TI> a) { return {TO(a.x), TO(a.y)}; }
 
+// Load through a global-address-space pointer.  Pointers read from a table
+// in memory (the per-system D spectra) are generic to the compiler, whose
+// flat loads also count against the LDS wait counter; these do not.
+template <typename T>
+__device__ __forceinline__ cx<T> gload(const cx<T>* p) {
+    typedef T v2 __attribute__((ext_vector_type(2)));
+    const v2 v = *(const __attribute__((address_space(1))) v2*)(p);
+    return cx<T>{v.x, v.y};
+}
+
 // Error carried from the host orchestration to the C ABI boundary.
 struct Error : std::runtime_error {
     int status;

@@ -489,16 +489,6 @@ __device__ __forceinline__ void store_pair(cx<double>* p, cx<double> a, cx<doubl
     p[1] = b;
 }
 
-// The D slabs come through a table of pointers, so the compiler sees
-// generic pointers and emits flat loads, which also count against the LDS
-// wait counter; these loads go through the global address space instead.
-template <typename T>
-__device__ __forceinline__ cx<T> gload(const cx<T>* p) {
-    typedef T v2 __attribute__((ext_vector_type(2)));
-    const v2 v = *(const __attribute__((address_space(1))) v2*)(p);
-    return cx<T>{v.x, v.y};
-}
-
 template <typename T, int L>
 __global__ __launch_bounds__(yzr_threads<L>()) void k_yzconv_r(
     cx<T>* __restrict__ Tb, const cx<T>* const* __restrict__ Dptr, const cx<T>* __restrict__ twy,
