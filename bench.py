@@ -121,6 +121,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 256 MiB device copy (for scaling rocprofv3 "
                          "FETCH_SIZE/WRITE_SIZE counters)")
+    ap.add_argument("--matvec64-only", action="store_true",
+                    help="measure only the 64^3 FFT matvec (one JSON line) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the solve shards by "
@@ -136,6 +138,17 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+
+    if args.matvec64_only:
+        log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
+        if args.calibrate_copy:
+            a = torch.empty(256 << 20, dtype=torch.uint8, device=dev).fill_(1)
+            torch.empty_like(a).copy_(a)
+            torch.cuda.synchronize()
+            del a
+        print(json.dumps({"matvec_64cubed": measure_matvec64(torch, W, DDASolver, log)}),
+              flush=True)
+        return
 
     if args.calibrate_copy:
         a = torch.empty(256 << 20, dtype=torch.uint8, device=dev).fill_(1)
@@ -268,9 +281,9 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def measure_extras(torch, W, DDASolver, log):
-    """FFT matvec GB/s on the 64^3 lattice and single-solve latency (c1)."""
-    res = {}
+def measure_matvec64(torch, W, DDASolver, log):
+    """FFT matvec GB/s on the 64^3 lattice (five-pass chain), FP64 and FP32,
+    one and eight right-hand sides."""
     w3 = W.c3_cherenkov()
     n3 = w3.n_occ
     Em = float(w3.energies[len(w3.energies) // 2])
@@ -308,7 +321,12 @@ def measure_extras(torch, W, DDASolver, log):
             log(f"matvec 64^3 {prec} nrhs={nrhs}: {dt_s * 1e3:.3f} ms, "
                 f"{model / dt_s / 1e9:.0f} GB/s (model)")
     s3.close()
-    res["matvec_64cubed"] = mv
+    return mv
+
+
+def measure_extras(torch, W, DDASolver, log):
+    """FFT matvec GB/s on the 64^3 lattice and single-solve latency (c1)."""
+    res = {"matvec_64cubed": measure_matvec64(torch, W, DDASolver, log)}
     # single-solve latency, c1 (FP64 BiCGStab to 1e-10), 10 solves
     w1 = W.c1_single_solve()
     s1 = DDASolver(w1.mask, w1.d, w1.m_h, tol=w1.tol, solver="bicgstab")
