@@ -202,12 +202,21 @@ __global__ __launch_bounds__(NTHR) void k_zconv(cx<T>* __restrict__ G,
     const int64_t plane = int64_t(g.my) * g.mx;
     cx<T>* gb = G + int64_t(pos) * 3 * g.nz * plane + col0;
     cx<T>* gset[2] = {gb + int64_t(ky0) * g.mx, gb + int64_t(ky1) * g.mx};
-    for (int e = tid; e < L * W; e += NTHR) {
-        const int z = e / W, rem = e % W, set = rem / (3 * TX), c = (rem / TX) % 3, col = rem % TX;
-        cx<T> v{T(0), T(0)};
-        if (z < g.nz && col0 + col < g.mx && (set == 0 || pair))
-            v = gset[set][(int64_t(c) * g.nz + z) * plane + col];
-        lds[e] = v;
+    // each thread keeps one line (set, component, column) and walks z: the
+    // index arithmetic is done once, and consecutive threads still read
+    // consecutive columns
+    static_assert(W <= NTHR, "a block must cover every line");
+    constexpr int ZT = NTHR / W;  // threads per line
+    const int lrem = tid % W, z0 = tid / W;
+    const int lset = lrem / (3 * TX), lc = (lrem / TX) % 3, lcol = lrem % TX;
+    const bool lok = tid < ZT * W && col0 + lcol < g.mx && (lset == 0 || pair);
+    if (tid < ZT * W) {
+        const cx<T>* src = gset[lset] + int64_t(lc) * g.nz * plane + lcol;
+        for (int z = z0; z < L; z += ZT) {
+            cx<T> v{T(0), T(0)};
+            if (lok && z < g.nz) v = src[int64_t(z) * plane];
+            lds[z * W + lrem] = v;
+        }
     }
     __syncthreads();
     fft_tile<T, L, false, W, 1, W, NTHR>(lds, tw, tid);
@@ -246,10 +255,9 @@ __global__ __launch_bounds__(NTHR) void k_zconv(cx<T>* __restrict__ G,
     }
     __syncthreads();
     fft_tile<T, L, true, W, 1, W, NTHR>(lds, tw, tid);
-    for (int e = tid; e < g.nz * W; e += NTHR) {
-        const int z = e / W, rem = e % W, set = rem / (3 * TX), c = (rem / TX) % 3, col = rem % TX;
-        if (col0 + col < g.mx && (set == 0 || pair))
-            gset[set][(int64_t(c) * g.nz + z) * plane + col] = lds[e];
+    if (lok) {
+        cx<T>* dst = gset[lset] + int64_t(lc) * g.nz * plane + lcol;
+        for (int z = z0; z < g.nz; z += ZT) dst[int64_t(z) * plane] = lds[z * W + lrem];
     }
 }
 
