@@ -80,11 +80,13 @@ __global__ __launch_bounds__(NTHR) void k_unpack_xfft(cx<T>* __restrict__ xin,
                                                       SlotFilter f) {
     constexpr int NL = rows_nl<T, L>();
     __shared__ cx<T> lds[NL * L];
+    __shared__ cx<T> twl[L];
     const int tid = threadIdx.x;
     const int c = blockIdx.y;
     const int pos = blockIdx.z;
     const int64_t slot = act ? act[pos] : pos;
     if (!slot_live(f, slot)) return;
+    for (int t = tid; t < L; t += NTHR) twl[t] = tw[t];
     const int nrows = g.nz * g.ny;
     const int row0 = blockIdx.x * NL;
     cx<T>* src = xin + (slot * 3 + c) * g.n_occ;
@@ -112,7 +114,7 @@ __global__ __launch_bounds__(NTHR) void k_unpack_xfft(cx<T>* __restrict__ xin,
         lds[e] = v;
     }
     __syncthreads();
-    fft_tile<T, L, false, NL, L, 1, NTHR>(lds, tw, tid);
+    fft_tile<T, L, false, NL, L, 1, NTHR>(lds, twl, tid);
     cx<T>* dst = G + (int64_t(pos) * 3 + c) * g.nz * g.my * int64_t(g.mx);
     for (int e = tid; e < NL * L; e += NTHR) {
         const int rr = e / L, x = e % L;
@@ -133,7 +135,9 @@ __global__ __launch_bounds__(NTHR) void k_fft_mid(cx<T>* __restrict__ data,
                                                   int n_in, int n_out, int64_t outer_stride,
                                                   int64_t tiles_per_outer) {
     __shared__ cx<T> lds[L * TX];
+    __shared__ cx<T> twl[L];  // twiddles in LDS (51 against 55 us, FP32 y pass on 64^3)
     const int tid = threadIdx.x;
+    for (int t = tid; t < L; t += NTHR) twl[t] = tw[t];
     const int64_t o = blockIdx.x / tiles_per_outer;
     const int64_t col0 = (blockIdx.x - o * tiles_per_outer) * TX;
     cx<T>* base = data + o * outer_stride + col0;
@@ -144,7 +148,7 @@ __global__ __launch_bounds__(NTHR) void k_fft_mid(cx<T>* __restrict__ data,
         lds[e] = v;
     }
     __syncthreads();
-    fft_tile<T, L, INV, TX, 1, TX, NTHR>(lds, tw, tid);
+    fft_tile<T, L, INV, TX, 1, TX, NTHR>(lds, twl, tid);
     for (int e = tid; e < n_out * TX; e += NTHR) {
         const int row = e / TX, col = e % TX;
         if (col0 + col < inner) base[int64_t(row) * inner + col] = lds[e];
@@ -190,6 +194,10 @@ __global__ __launch_bounds__(NTHR) void k_zconv(cx<T>* __restrict__ G,
                                                 const int* __restrict__ slot_sys, SlotFilter f) {
     constexpr int W = 6 * TX;  // lines per tile: (mirror set, component, column)
     __shared__ cx<T> lds[L * W];
+    // FP32: twiddles in LDS, which the FFT stages index per lane (190 against
+    // 217 us on the 64^3 lattice); FP64 measured slower with them (534 against 524)
+    constexpr bool TWL = sizeof(T) == 4;
+    __shared__ cx<T> twl[TWL ? L : 1];
     const int tid = threadIdx.x;
     int tile, ky0, pos;
     zconv_block_map<T, TX>(tile, ky0, pos);
@@ -210,6 +218,9 @@ __global__ __launch_bounds__(NTHR) void k_zconv(cx<T>* __restrict__ G,
     const int lrem = tid % W, z0 = tid / W;
     const int lset = lrem / (3 * TX), lc = (lrem / TX) % 3, lcol = lrem % TX;
     const bool lok = tid < ZT * W && col0 + lcol < g.mx && (lset == 0 || pair);
+    if (TWL)
+        for (int t = tid; t < L; t += NTHR) twl[t] = tw[t];
+    const cx<T>* twp = TWL ? twl : tw;
     if (tid < ZT * W) {
         const cx<T>* src = gset[lset] + int64_t(lc) * g.nz * plane + lcol;
         for (int z = z0; z < L; z += ZT) {
@@ -219,7 +230,7 @@ __global__ __launch_bounds__(NTHR) void k_zconv(cx<T>* __restrict__ G,
         }
     }
     __syncthreads();
-    fft_tile<T, L, false, W, 1, W, NTHR>(lds, tw, tid);
+    fft_tile<T, L, false, W, 1, W, NTHR>(lds, twp, tid);
     // D from its stored corner [0, M/2]^3: index M - k reads k, odd
     // components flip sign (xy: x and y, xz: x and z, yz: y and z)
     const int mxh = g.mx / 2 + 1, myh = g.my / 2 + 1, mzh = g.mz / 2 + 1;
@@ -254,7 +265,7 @@ __global__ __launch_bounds__(NTHR) void k_zconv(cx<T>* __restrict__ G,
         }
     }
     __syncthreads();
-    fft_tile<T, L, true, W, 1, W, NTHR>(lds, tw, tid);
+    fft_tile<T, L, true, W, 1, W, NTHR>(lds, twp, tid);
     if (lok) {
         cx<T>* dst = gset[lset] + int64_t(lc) * g.nz * plane + lcol;
         for (int z = z0; z < g.nz; z += ZT) dst[int64_t(z) * plane] = lds[z * W + lrem];
@@ -274,11 +285,13 @@ __global__ __launch_bounds__(NTHR) void k_ixfft_pack(const cx<T>* __restrict__ G
                                                      SlotFilter f, RedScratch red) {
     constexpr int NL = rows_nl<T, L>();
     __shared__ cx<T> lds[NL * L];
+    __shared__ cx<T> twl[L];
     const int tid = threadIdx.x;
     const int c = blockIdx.y;
     const int pos = blockIdx.z;
     const int64_t slot = act ? act[pos] : pos;
     if (!slot_live(f, slot)) return;
+    for (int t = tid; t < L; t += NTHR) twl[t] = tw[t];
     const int64_t sys = slot_sys[slot];
     const int nrows = g.nz * g.ny;
     const int row0 = blockIdx.x * NL;
@@ -294,7 +307,7 @@ __global__ __launch_bounds__(NTHR) void k_ixfft_pack(const cx<T>* __restrict__ G
         lds[e] = v;
     }
     __syncthreads();
-    fft_tile<T, L, true, NL, L, 1, NTHR>(lds, tw, tid);
+    fft_tile<T, L, true, NL, L, 1, NTHR>(lds, twl, tid);
     const int64_t voff = (slot * 3 + c) * g.n_occ;
     double mu[2] = {0.0, 0.0};
     for (int e = tid; e < NL * L; e += NTHR) {
