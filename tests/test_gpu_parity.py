@@ -108,6 +108,9 @@ MATVEC_LATTICES = [
     ("rod_24x6x6", W.capped_rod_mask(24, 6, 6, 1.0, 3.0, 24.0), 1.0),
     ("sphere_16", W.sphere_mask(16, 1.0, 8.0), 1.0),
     ("random_9x4x13", W.random_mask(9, 4, 13, 0.5, seed=3), 2.0),
+    # five-pass chain (y grid 16, z grid 24) with an x grid of 32: the z-conv
+    # blocks take their XCD-grouped order, with whole runs and a ragged tail
+    ("random_16x8x12", W.random_mask(16, 8, 12, 0.7, seed=5), 1.1),
     # y, z grids of 48: both precisions take the three-pass (yz plane in LDS)
     # chain
     ("random_5x17x17", W.random_mask(5, 17, 17, 0.6, seed=9), 1.3),
@@ -328,7 +331,7 @@ def test_cocg_graph_replay_equals_direct_launches(precision, timing):
         assert np.array_equal(pk, out[0][0])
 
 
-@pytest.mark.parametrize("shape", [(12, 12, 12), (12, 12, 16)])
+@pytest.mark.parametrize("shape", [(12, 12, 12), (12, 12, 16), (16, 8, 12)])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_every_autotuner_candidate_gives_identical_matvecs(shape, precision):
     """The autotuner only regroups lines into blocks: every candidate tile of
