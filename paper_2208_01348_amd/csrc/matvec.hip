@@ -97,21 +97,40 @@ __global__ __launch_bounds__(NTHR) void k_unpack_xfft(cx<T>* __restrict__ xin,
         beta = cvt<T>(f.st[slot].beta);
         reset = f.st[slot].reset_p != 0;
     }
-    for (int e = tid; e < NL * L; e += NTHR) {
-        const int rr = e / L, x = e % L;
+    // only x < (L+1)/2 can be occupied; every index load, then every data
+    // load, is issued before the first use (clamped addresses, masked after)
+    constexpr int HX = (L + 1) / 2;
+    constexpr int NE = (NL * HX + NTHR - 1) / NTHR;
+    const cx<T> zero{T(0), T(0)};
+    int idx[NE];
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+        const int e = tid + q * NTHR;
+        const int rr = e / HX, x = e - (e / HX) * HX;
         const int row = row0 + rr;
-        cx<T> v{T(0), T(0)};
-        if (row < nrows && x < g.nx) {
-            const int idx = map[int64_t(row) * g.nx + x];
-            if (idx >= 0) {
-                v = src[idx];
-                if (FUSE_P) {  // each occupied element is visited by exactly one thread
-                    v = reset ? rsrc[idx] : rsrc[idx] + beta * v;
-                    src[idx] = v;
-                }
-            }
+        const int m = map[int64_t(min(row, nrows - 1)) * g.nx + min(x, g.nx - 1)];
+        idx[q] = (rr < NL && row < nrows && x < g.nx) ? m : -1;
+    }
+    cx<T> v[NE], w[FUSE_P ? NE : 1];
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+        const int i = max(idx[q], 0);
+        v[q] = src[i];
+        if constexpr (FUSE_P) w[q] = rsrc[i];
+    }
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+        const int e = tid + q * NTHR;
+        const int rr = e / HX, x = e - (e / HX) * HX;
+        const bool occ = idx[q] >= 0;
+        cx<T> vq = v[q];
+        if constexpr (FUSE_P) vq = reset ? w[q] : w[q] + beta * vq;
+        vq = occ ? vq : zero;
+        if (FUSE_P && occ) src[idx[q]] = vq;  // each occupied element: exactly one thread
+        if (rr < NL) {
+            lds[rr * L + x] = vq;
+            if (x + HX < L) lds[rr * L + x + HX] = zero;
         }
-        lds[e] = v;
     }
     __syncthreads();
     fft_tile<T, L, false, NL, L, 1, NTHR>(lds, twl, tid);
@@ -296,42 +315,64 @@ __global__ __launch_bounds__(NTHR) void k_ixfft_pack(const cx<T>* __restrict__ G
     const int nrows = g.nz * g.ny;
     const int row0 = blockIdx.x * NL;
     const cx<T>* gsrc = G + (int64_t(pos) * 3 + c) * g.nz * g.my * int64_t(g.mx);
-    for (int e = tid; e < NL * L; e += NTHR) {
-        const int rr = e / L, x = e % L;
-        const int row = row0 + rr;
-        cx<T> v{T(0), T(0)};
-        if (row < nrows) {
+    {
+        constexpr int NLD = (NL * L + NTHR - 1) / NTHR;
+        cx<T> t[NLD];
+#pragma unroll
+        for (int q = 0; q < NLD; ++q) {  // all loads first (clamped rows)
+            const int e = tid + q * NTHR;
+            const int row = min(row0 + min(e / L, NL - 1), nrows - 1);
             const int z = row / g.ny, y = row - z * g.ny;
-            v = gsrc[(int64_t(z) * g.my + y) * g.mx + x];
+            t[q] = gsrc[(int64_t(z) * g.my + y) * g.mx + (e % L)];
         }
-        lds[e] = v;
+#pragma unroll
+        for (int q = 0; q < NLD; ++q) {
+            const int e = tid + q * NTHR;
+            if (e < NL * L) lds[e] = (row0 + e / L < nrows) ? t[q] : cx<T>{T(0), T(0)};
+        }
     }
     __syncthreads();
     fft_tile<T, L, true, NL, L, 1, NTHR>(lds, twl, tid);
     const int64_t voff = (slot * 3 + c) * g.n_occ;
-    double mu[2] = {0.0, 0.0};
-    for (int e = tid; e < NL * L; e += NTHR) {
-        const int rr = e / L, x = e % L;
+    constexpr int HX = (L + 1) / 2;  // x < (L+1)/2 holds every occupied cell
+    constexpr int NE = (NL * HX + NTHR - 1) / NTHR;
+    int idx[NE];
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+        const int e = tid + q * NTHR;
+        const int rr = e / HX, x = e - (e / HX) * HX;
         const int row = row0 + rr;
-        if (row < nrows && x < g.nx) {
-            const int idx = map[int64_t(row) * g.nx + x];
-            if (idx >= 0) {
-                const cx<T> conv = lds[e];
-                if (MODE == PACK_GX) {
-                    yout[voff + idx] = conv;
-                } else {
-                    const cx<T> xi = xin[voff + idx];
-                    const cx<T> yi = xi * ainv[sys * g.n_occ + idx] - conv;
-                    yout[voff + idx] = yi;
-                    if (MODE == PACK_AX_COCG) {  // bilinear x^T y
-                        mu[0] += double(xi.x) * yi.x - double(xi.y) * yi.y;
-                        mu[1] += double(xi.x) * yi.y + double(xi.y) * yi.x;
-                    }
-                }
+        const int m = map[int64_t(min(row, nrows - 1)) * g.nx + min(x, g.nx - 1)];
+        idx[q] = (rr < NL && row < nrows && x < g.nx) ? m : -1;
+    }
+    cx<T> xv[NE], av[NE];
+    if (MODE != PACK_GX) {
+#pragma unroll
+        for (int q = 0; q < NE; ++q) {
+            const int i = max(idx[q], 0);
+            xv[q] = xin[voff + i];
+            av[q] = ainv[sys * g.n_occ + i];
+        }
+    }
+    double mu[2] = {0.0, 0.0};
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+        if (idx[q] < 0) continue;
+        const int e = tid + q * NTHR;
+        const int rr = e / HX, x = e - (e / HX) * HX;
+        const cx<T> conv = lds[rr * L + x];
+        if (MODE == PACK_GX) {
+            yout[voff + idx[q]] = conv;
+        } else {
+            const cx<T> yi = xv[q] * av[q] - conv;
+            yout[voff + idx[q]] = yi;
+            if (MODE == PACK_AX_COCG) {  // bilinear x^T y
+                mu[0] += double(xv[q].x) * yi.x - double(xv[q].y) * yi.y;
+                mu[1] += double(xv[q].x) * yi.y + double(xv[q].y) * yi.x;
             }
         }
     }
-    if constexpr (MODE == PACK_AX_COCG)  // partial rows; alpha is finalized by the caller
+    if constexpr (MODE == PACK_AX_COCG)  // partial rows; the COCG update kernel sums them
         block_partial<2, NTHR>(mu, red, int(slot), blockIdx.y * gridDim.x + blockIdx.x);
 }
 
