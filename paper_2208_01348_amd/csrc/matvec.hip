@@ -241,12 +241,19 @@ __global__ __launch_bounds__(NTHR) void k_zconv(cx<T>* __restrict__ G,
         for (int t = tid; t < L; t += NTHR) twl[t] = tw[t];
     const cx<T>* twp = TWL ? twl : tw;
     if (tid < ZT * W) {
-        const cx<T>* src = gset[lset] + int64_t(lc) * g.nz * plane + lcol;
-        for (int z = z0; z < L; z += ZT) {
-            cx<T> v{T(0), T(0)};
-            if (lok && z < g.nz) v = src[int64_t(z) * plane];
-            lds[z * W + lrem] = v;
+        // the z < nz <= (L+1)/2 loads of the line are all issued first (clamped
+        // addresses), then stored; the rest of the line is zero
+        constexpr int NZ = ((L + 1) / 2 + ZT - 1) / ZT;
+        const cx<T>* src = gset[lset] + int64_t(lc) * g.nz * plane + min(lcol, g.mx - 1 - col0);
+        cx<T> tv[NZ];
+#pragma unroll
+        for (int k = 0; k < NZ; ++k) tv[k] = src[int64_t(min(z0 + k * ZT, g.nz - 1)) * plane];
+#pragma unroll
+        for (int k = 0; k < NZ; ++k) {
+            const int z = z0 + k * ZT;
+            if (z < L) lds[z * W + lrem] = (lok && z < g.nz) ? tv[k] : cx<T>{T(0), T(0)};
         }
+        for (int z = z0 + NZ * ZT; z < L; z += ZT) lds[z * W + lrem] = cx<T>{T(0), T(0)};
     }
     __syncthreads();
     fft_tile<T, L, false, W, 1, W, NTHR>(lds, twp, tid);
