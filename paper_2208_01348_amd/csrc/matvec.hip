@@ -160,11 +160,21 @@ __global__ __launch_bounds__(NTHR) void k_fft_mid(cx<T>* __restrict__ data,
     const int64_t o = blockIdx.x / tiles_per_outer;
     const int64_t col0 = (blockIdx.x - o * tiles_per_outer) * TX;
     cx<T>* base = data + o * outer_stride + col0;
-    for (int e = tid; e < L * TX; e += NTHR) {
-        const int row = e / TX, col = e % TX;
-        cx<T> v{T(0), T(0)};
-        if (row < n_in && col0 + col < inner) v = base[int64_t(row) * inner + col];
-        lds[e] = v;
+    {
+        constexpr int NLD = (L * TX + NTHR - 1) / NTHR;
+        cx<T> t[NLD];
+#pragma unroll
+        for (int q = 0; q < NLD; ++q) {  // every load issued before the first store
+            const int e = tid + q * NTHR;
+            const int row = e / TX, col = e % TX;
+            t[q] = cx<T>{T(0), T(0)};
+            if (row < n_in && col0 + col < inner) t[q] = base[int64_t(row) * inner + col];
+        }
+#pragma unroll
+        for (int q = 0; q < NLD; ++q) {
+            const int e = tid + q * NTHR;
+            if (e < L * TX) lds[e] = t[q];
+        }
     }
     __syncthreads();
     fft_tile<T, L, INV, TX, 1, TX, NTHR>(lds, twl, tid);
