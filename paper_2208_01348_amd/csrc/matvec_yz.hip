@@ -162,9 +162,23 @@ __global__ __launch_bounds__(NT) void k_xfft_t(cx<T>* __restrict__ xin,
     const int64_t cplane = int64_t(3) * g.nz * g.ny;  // one kx column
     cx<T>* dst = Tb + int64_t(pos) * g.mx * cplane + (int64_t(c) * g.nz + z) * g.ny;
     const bool perm = (g.ny & 7) == 0;
-    for (int e = tid; e < nrow * LX; e += NT) {
-        const int kx = e / nrow, r = e - (e / nrow) * nrow;
-        dst[kx * cplane + tpos(y0 + r, perm)] = lds[r * LP + kx];
+    {
+        // element e = (kx, r) with the compile-time row count NR (rows r >= nrow
+        // idle): no run-time division; every LDS read before the first store
+        constexpr int NS = (NR * LX + NT - 1) / NT;
+        cx<T> t[NS];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            const int e = tid + q * NT;
+            const int kx = e / NR, r = e - (e / NR) * NR;
+            t[q] = lds[min(r, nrow - 1) * LP + min(kx, LX - 1)];
+        }
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            const int e = tid + q * NT;
+            const int kx = e / NR, r = e - (e / NR) * NR;
+            if (kx < LX && r < nrow) dst[kx * cplane + tpos(y0 + r, perm)] = t[q];
+        }
     }
 }
 
@@ -201,19 +215,20 @@ __global__ __launch_bounds__(NT) void k_ixfft_t(const cx<T>* __restrict__ Tb,
     const cx<T>* src = Tb + int64_t(pos) * g.mx * cplane + (int64_t(c) * g.nz + z) * g.ny;
     const bool perm = (g.ny & 7) == 0;
     {
-        const int n = nrow * LX;
+        // element e = (kx, r) with the compile-time row count NR (rows r >= nrow
+        // idle), so no run-time division
         cx<T> t[NL];
 #pragma unroll
         for (int q = 0; q < NL; ++q) {
-            const int e = min(tid + q * NT, n - 1);
-            const int kx = e / nrow, r = e - (e / nrow) * nrow;
-            t[q] = src[kx * cplane + tpos(y0 + r, perm)];
+            const int e = tid + q * NT;
+            const int kx = e / NR, r = e - (e / NR) * NR;
+            t[q] = src[min(kx, LX - 1) * cplane + tpos(y0 + min(r, nrow - 1), perm)];
         }
 #pragma unroll
         for (int q = 0; q < NL; ++q) {
             const int e = tid + q * NT;
-            const int kx = e / nrow, r = e - (e / nrow) * nrow;
-            if (e < n) lds[r * LP + kx] = t[q];
+            const int kx = e / NR, r = e - (e / NR) * NR;
+            if (kx < LX && r < nrow) lds[r * LP + kx] = t[q];
         }
     }
     __syncthreads();
