@@ -124,8 +124,13 @@ __global__ __launch_bounds__(NTHR) void k_unpack_xfft(cx<T>* __restrict__ xin,
         const int rr = e / HX, x = e - (e / HX) * HX;
         const bool occ = idx[q] >= 0;
         cx<T> vq = v[q];
-        if constexpr (FUSE_P) vq = reset ? w[q] : w[q] + beta * vq;
-        vq = occ ? vq : zero;
+        if constexpr (FUSE_P) {
+            const cx<T> upd = w[q] + beta * vq;
+            vq.x = reset ? w[q].x : upd.x;  // component selects: a select of the
+            vq.y = reset ? w[q].y : upd.y;  // whole FP64 pair goes through scratch
+        }
+        vq.x = occ ? vq.x : T(0);
+        vq.y = occ ? vq.y : T(0);
         if (FUSE_P && occ) src[idx[q]] = vq;  // each occupied element: exactly one thread
         if (rr < NL) {
             lds[rr * L + x] = vq;
