@@ -354,6 +354,11 @@ void flush_timer(dda_ctx* c) {
     c->timer.pending.clear();
 }
 
+// Graph capture is used when enabled and no per-kernel timing is requested.
+bool use_graphs(const dda_ctx* c) {
+    return c->opt.use_graphs != 0 && c->stream != nullptr && !c->timing;
+}
+
 // Launches body() on the context's stream through the captured graph in gc:
 // replayed while `key` is unchanged, captured again otherwise (the executable
 // is updated in place when the topology allows it, else instantiated anew).
@@ -788,56 +793,11 @@ void run_bicgstab(dda_ctx* c, int nslots, const dda::cx<T>* b, dda::cx<T>* x, Ve
     matvecs.assign(nslots, 0);
     relres.assign(nslots, 0.0);
     const int check = std::max(1, c->opt.check_every);
-    while (true) {
-        auto S = read_states(c, nslots);
-        std::vector<int> verify, next;
-        for (int i : act) {
-            iters[i] = S[i].iters;  // device counter, cumulative over restarts
-            if (S[i].status == dda::SLOT_CONVERGED || S[i].status == dda::SLOT_BREAKDOWN) {
-                verify.push_back(i);
-            } else if (iters[i] >= maxit) {
-                status[i] = DDA_ENOCONV;
-                relres[i] = S[i].bnorm2 > 0 ? std::sqrt(S[i].rnorm2 / S[i].bnorm2) : 0.0;
-            } else {
-                next.push_back(i);
-            }
-        }
-        if (!verify.empty() && !true_check) {
-            for (int i : verify) {
-                relres[i] = S[i].bnorm2 > 0 ? std::sqrt(S[i].rnorm2 / S[i].bnorm2) : 0.0;
-                status[i] = S[i].status == dda::SLOT_BREAKDOWN ? DDA_EBREAKDOWN : DDA_OK;
-            }
-        } else if (!verify.empty()) {
-            // true residual: y = A x into w.t, r = b - y (rnorm2)
-            upload_act(c, verify);
-            matvec<T>(c, x, w.t, dact, int(verify.size()), dptr, slot_sys, ainv, dda::PACK_AX);
-            dda::residual<T>(b, w.t, w.r, st, dact, int(verify.size()), nv, red, s);
-            auto S2 = read_states(c, nslots);
-            std::vector<int> again;
-            for (int i : verify) {
-                matvecs[i] += 1;
-                const double rr = S2[i].bnorm2 > 0 ? std::sqrt(S2[i].rnorm2 / S2[i].bnorm2) : 0.0;
-                relres[i] = rr;
-                if (rr <= tol) {
-                    status[i] = DDA_OK;
-                } else if (restarts[i] >= kMaxRestarts || iters[i] >= maxit) {
-                    status[i] = S[i].status == dda::SLOT_BREAKDOWN ? DDA_EBREAKDOWN : DDA_ENOCONV;
-                } else {
-                    restarts[i] += 1;
-                    again.push_back(i);
-                }
-            }
-            if (!again.empty()) {
-                upload_act(c, again);
-                dda::bicg_reset<T>(w.r, w.rhat, w.p, w.v, st, dact, int(again.size()), nv, red, s);
-                next.insert(next.end(), again.begin(), again.end());
-            }
-        }
-        std::sort(next.begin(), next.end());
-        act = next;
-        const int n_act = int(act.size());
-        if (n_act == 0) break;
-        upload_act(c, act);
+    autotune<T>(c, ctx_work(c), dact, nslots, dptr, slot_sys);  // outside any capture
+    const bool graphs = use_graphs(c);
+    c->graph.drop();
+    // One interval of `check` iterations over the n_act slots listed in dact.
+    auto interval = [&](int n_act) {
         for (int k = 0; k < check; ++k) {
             dda::bicg_update_p<T>(w.r, w.p, w.v, st, dact, n_act, nv, s);
             matvec<T>(c, w.p, w.v, dact, n_act, dptr, slot_sys, ainv, dda::PACK_AX);
@@ -846,9 +806,69 @@ void run_bicgstab(dda_ctx* c, int nslots, const dda::cx<T>* b, dda::cx<T>* x, Ve
             matvec<T>(c, w.s, w.t, dact, n_act, dptr, slot_sys, ainv, dda::PACK_AX);
             dda::bicg_omega<T>(w.t, w.s, st, dact, n_act, nv, red, s);
             dda::bicg_update_xr<T>(x, w.r, w.rhat, w.p, w.s, w.t, st, dact, n_act, nv, red, s);
-            for (int i : act) matvecs[i] += 2;
         }
+    };
+    try {
+        while (true) {
+            auto S = read_states(c, nslots);
+            std::vector<int> verify, next;
+            for (int i : act) {
+                iters[i] = S[i].iters;  // device counter, cumulative over restarts
+                if (S[i].status == dda::SLOT_CONVERGED || S[i].status == dda::SLOT_BREAKDOWN) {
+                    verify.push_back(i);
+                } else if (iters[i] >= maxit) {
+                    status[i] = DDA_ENOCONV;
+                    relres[i] = S[i].bnorm2 > 0 ? std::sqrt(S[i].rnorm2 / S[i].bnorm2) : 0.0;
+                } else {
+                    next.push_back(i);
+                }
+            }
+            if (!verify.empty() && !true_check) {
+                for (int i : verify) {
+                    relres[i] = S[i].bnorm2 > 0 ? std::sqrt(S[i].rnorm2 / S[i].bnorm2) : 0.0;
+                    status[i] = S[i].status == dda::SLOT_BREAKDOWN ? DDA_EBREAKDOWN : DDA_OK;
+                }
+            } else if (!verify.empty()) {
+                // true residual: y = A x into w.t, r = b - y (rnorm2)
+                upload_act(c, verify);
+                matvec<T>(c, x, w.t, dact, int(verify.size()), dptr, slot_sys, ainv, dda::PACK_AX);
+                dda::residual<T>(b, w.t, w.r, st, dact, int(verify.size()), nv, red, s);
+                auto S2 = read_states(c, nslots);
+                std::vector<int> again;
+                for (int i : verify) {
+                    matvecs[i] += 1;
+                    const double rr = S2[i].bnorm2 > 0 ? std::sqrt(S2[i].rnorm2 / S2[i].bnorm2) : 0.0;
+                    relres[i] = rr;
+                    if (rr <= tol) {
+                        status[i] = DDA_OK;
+                    } else if (restarts[i] >= kMaxRestarts || iters[i] >= maxit) {
+                        status[i] = S[i].status == dda::SLOT_BREAKDOWN ? DDA_EBREAKDOWN : DDA_ENOCONV;
+                    } else {
+                        restarts[i] += 1;
+                        again.push_back(i);
+                    }
+                }
+                if (!again.empty()) {
+                    upload_act(c, again);
+                    dda::bicg_reset<T>(w.r, w.rhat, w.p, w.v, st, dact, int(again.size()), nv, red, s);
+                    next.insert(next.end(), again.begin(), again.end());
+                }
+            }
+            std::sort(next.begin(), next.end());
+            act = next;
+            const int n_act = int(act.size());
+            if (n_act == 0) break;
+            upload_act(c, act);
+            if (graphs) launch_captured(c, c->graph, n_act, [&] { interval(n_act); });
+            else interval(n_act);
+            for (int i : act) matvecs[i] += 2 * check;
+        }
+    } catch (...) {
+        (void)hipStreamSynchronize(c->stream);
+        c->graph.drop();
+        throw;
     }
+    c->graph.drop();  // the graph holds this call's buffer addresses
 }
 
 // Writes rnorm2 = rn[i]^2 into the device scalars of every slot.
@@ -1009,10 +1029,6 @@ void cocg_interval(dda_ctx* c, const CocgBufs<T>& B, int n_act) {
         dda::cocg_update_xr<T>(xs, B.r, B.p, B.q, B.w.st, B.act, n_act, nv, B.w.red,
                                pack_blocks(c, int(sizeof(dda::cx<T>))), s);
     }
-}
-
-bool use_graphs(const dda_ctx* c) {
-    return c->opt.use_graphs != 0 && c->stream != nullptr && !c->timing;
 }
 
 int status_of(int slot_status) {
