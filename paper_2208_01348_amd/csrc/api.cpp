@@ -799,7 +799,7 @@ void run_bicgstab(dda_ctx* c, int nslots, const dda::cx<T>* b, dda::cx<T>* x, Ve
     // One interval of `check` iterations over the n_act slots listed in dact.
     auto interval = [&](int n_act) {
         for (int k = 0; k < check; ++k) {
-            dda::bicg_update_p<T>(w.r, w.p, w.v, st, dact, n_act, nv, s);
+            dda::bicg_update_p<T>(w.r, w.p, w.v, st, dact, n_act, nv, red, k > 0, s);
             matvec<T>(c, w.p, w.v, dact, n_act, dptr, slot_sys, ainv, dda::PACK_AX);
             dda::bicg_alpha<T>(w.rhat, w.v, st, dact, n_act, nv, red, s);
             dda::bicg_update_s<T>(w.r, w.v, w.s, st, dact, n_act, nv, red, s);
@@ -807,6 +807,7 @@ void run_bicgstab(dda_ctx* c, int nslots, const dda::cx<T>* b, dda::cx<T>* x, Ve
             dda::bicg_omega<T>(w.t, w.s, st, dact, n_act, nv, red, s);
             dda::bicg_update_xr<T>(x, w.r, w.rhat, w.p, w.s, w.t, st, dact, n_act, nv, red, s);
         }
+        dda::bicg_finish(st, dact, n_act, nv, red, s);
     };
     try {
         while (true) {

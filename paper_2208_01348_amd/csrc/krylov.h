@@ -15,9 +15,14 @@ void bicg_norm_b(const cx<T>* b, BicgSlot* st, const int* act, int n_act, int64_
 template <typename T>
 void bicg_reset(const cx<T>* r, cx<T>* rhat, cx<T>* p, cx<T>* v, BicgSlot* st, const int* act,
                 int n_act, int64_t nv, RedScratch red, hipStream_t s);
+// One iteration: update_p, v = A p, alpha, update_s, t = A s, omega,
+// update_xr.  Each kernel takes the scalar it needs from the partial rows of
+// the one before; update_p with fin_prev closes the previous iteration, and
+// bicg_finish closes the last one of a sequence (before the host reads the
+// slot states).
 template <typename T>
 void bicg_update_p(const cx<T>* r, cx<T>* p, const cx<T>* v, BicgSlot* st, const int* act,
-                   int n_act, int64_t nv, hipStream_t s);
+                   int n_act, int64_t nv, RedScratch red, bool fin_prev, hipStream_t s);
 template <typename T>
 void bicg_alpha(const cx<T>* rhat, const cx<T>* v, BicgSlot* st, const int* act, int n_act,
                 int64_t nv, RedScratch red, hipStream_t s);
@@ -31,6 +36,8 @@ template <typename T>
 void bicg_update_xr(cx<T>* x, cx<T>* r, const cx<T>* rhat, const cx<T>* p, const cx<T>* sv,
                     const cx<T>* t, BicgSlot* st, const int* act, int n_act, int64_t nv,
                     RedScratch red, hipStream_t s);
+void bicg_finish(BicgSlot* st, const int* act, int n_act, int64_t nv, RedScratch red,
+                 hipStream_t s);
 // r = b - y, rnorm2 = ||r||^2 (true residual after y = A x)
 template <typename T>
 void residual(const cx<T>* b, const cx<T>* y, cx<T>* r, BicgSlot* st, const int* act, int n_act,

@@ -5,10 +5,11 @@
 //
 // One grid covers every active slot: blockIdx.y picks the slot from the
 // active list, blockIdx.x a contiguous piece of its vector.  Each dot product
-// is a work kernel that writes one partial row per block and a finalize
-// kernel (one block per slot) that sums the rows in index order and updates
-// the slot's scalars: deterministic, without atomics or fences.  The host
-// never synchronises inside an iteration.
+// is a work kernel that writes one partial row per block; the rows are summed
+// in index order, by a finalize kernel (one block per slot) or by every block
+// of the next kernel, which then updates the slot's scalars: deterministic,
+// without atomics or fences.  The host never synchronises inside an
+// iteration.
 #include "krylov.h"
 
 namespace dda {
@@ -113,14 +114,77 @@ __global__ __launch_bounds__(NT) void k_fin_reset(BicgSlot* st, const int* act, 
     S.status = (tot[0] <= S.tol2 * S.bnorm2) ? SLOT_CONVERGED : SLOT_ACTIVE;
 }
 
-template <typename T>
+// One BiCGStab iteration is five vector kernels around the two matvecs:
+//   update_p  [FIN: sums the rows at 0..2 of the previous update_xr]
+//   v = A p
+//   alpha     (writes <rhat, v> rows at 0..1)
+//   update_s  (sums rows 0..1 -> alpha; writes ||s||^2 rows at 2)
+//   t = A s
+//   omega     (sums row 2 -> the half-step test; writes <t, s>, ||t||^2 rows at 3..5)
+//   update_xr (sums rows 3..5 -> omega; writes <rhat, r>, ||r||^2 rows at 0..2)
+// and k_fin_xr closes the last iteration of an interval.  A kernel that
+// needs a scalar sums the rows itself in every block (the same fixed order,
+// so every block gets the same value); block 0 stores it in the slot state.
+// Rows read and rows written by one kernel never overlap, and no block reads
+// a state field that another block of the same kernel writes, except the
+// status: a block that sees the status another block just set takes the
+// decision that block took.
+
+// Sums K rows at OFF for `slot` and returns the totals in every thread.
+template <int K, int OFF>
+__device__ __forceinline__ void slot_totals(RedScratch red, int slot, int nblk, double (&v)[K]) {
+    __shared__ double sh[K];
+    double tot[K];
+    sum_rows<K, NT, OFF>(red, slot, nblk, tot);
+    if (threadIdx.x == 0)
+        for (int k = 0; k < K; ++k) sh[k] = tot[k];
+    __syncthreads();
+    for (int k = 0; k < K; ++k) v[k] = sh[k];
+}
+
+// End of an iteration from the rows <rhat, r>, ||r||^2 at 0..2: the new rho,
+// the residual norm, the iteration count and the status.  Returns the new
+// status; the state is stored by `lead` only.
+__device__ __forceinline__ int finish_iteration(BicgSlot& S, int status, const double (&tot)[3],
+                                                bool lead) {
+    int ns = status;
+    if (!all_finite(tot, 3)) {
+        ns = SLOT_BREAKDOWN;
+    } else if (status == SLOT_HALF || tot[2] <= S.tol2 * S.bnorm2) {
+        ns = SLOT_CONVERGED;
+    } else if ((tot[0] == 0.0 && tot[1] == 0.0) || (S.omega.x == 0.0 && S.omega.y == 0.0)) {
+        ns = SLOT_BREAKDOWN;
+    }
+    if (lead) {
+        S.iters += 1;
+        S.rho = z128{tot[0], tot[1]};
+        S.rnorm2 = tot[2];
+        if (ns != status) S.status = ns;
+    }
+    return ns;
+}
+
+template <typename T, bool FIN>
 __global__ __launch_bounds__(NT) void k_update_p(const cx<T>* __restrict__ r, cx<T>* __restrict__ p,
-                                                 const cx<T>* __restrict__ v, const BicgSlot* st,
-                                                 const int* __restrict__ act, int64_t nv) {
+                                                 const cx<T>* __restrict__ v, BicgSlot* st,
+                                                 const int* __restrict__ act, int64_t nv,
+                                                 RedScratch red, int nblk) {
     SLOT_PROLOGUE
-    const BicgSlot& S = st[slot];
-    if (S.status != SLOT_ACTIVE) return;
-    const z128 beta = zdiv(S.rho, S.rho_old) * zdiv(S.alpha, S.omega);
+    BicgSlot& S = st[slot];
+    const int status = S.status;
+    z128 rho;
+    if constexpr (FIN) {
+        if (status != SLOT_ACTIVE && status != SLOT_HALF) return;  // uniform per block
+        double tot[3];
+        slot_totals<3, 0>(red, slot, nblk, tot);
+        const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+        if (finish_iteration(S, status, tot, lead) != SLOT_ACTIVE) return;
+        rho = z128{tot[0], tot[1]};
+    } else {
+        if (status != SLOT_ACTIVE) return;
+        rho = S.rho;
+    }
+    const z128 beta = zdiv(rho, S.rho_old) * zdiv(S.alpha, S.omega);
     const cx<T> bt{T(beta.x), T(beta.y)};
     const cx<T> om{T(S.omega.x), T(S.omega.y)};
     for (int64_t i = i0; i < nv; i += stride) {
@@ -138,25 +202,32 @@ __global__ __launch_bounds__(NT) void k_alpha(const cx<T>* __restrict__ rhat,
     if (st[slot].status != SLOT_ACTIVE) return;
     double s[2] = {0.0, 0.0};
     for (int64_t i = i0; i < nv; i += stride) acc_cdot(s[0], s[1], rhat[base + i], v[base + i]);
-    block_partial<2, NT>(s, red, slot, blockIdx.x);
-}
-__global__ __launch_bounds__(NT) void k_fin_alpha(BicgSlot* st, const int* act, RedScratch red,
-                                                  int nblk) {
-    if (st[act[blockIdx.x]].status != SLOT_ACTIVE) return;  // uniform per block
-    FIN_PROLOGUE(2)
-    S.rv = z128{tot[0], tot[1]};
-    if ((tot[0] == 0.0 && tot[1] == 0.0) || !all_finite(tot, 2)) S.status = SLOT_BREAKDOWN;
-    else S.alpha = zdiv(S.rho, S.rv);
+    block_partial<2, NT, 0>(s, red, slot, blockIdx.x);
 }
 
 template <typename T>
 __global__ __launch_bounds__(NT) void k_update_s(const cx<T>* __restrict__ r,
                                                  const cx<T>* __restrict__ v, cx<T>* __restrict__ sv,
-                                                 const BicgSlot* st, const int* __restrict__ act,
+                                                 BicgSlot* st, const int* __restrict__ act,
                                                  int64_t nv, RedScratch red) {
     SLOT_PROLOGUE
-    if (st[slot].status != SLOT_ACTIVE) return;
-    const z128 al = st[slot].alpha;
+    BicgSlot& S = st[slot];
+    if (S.status != SLOT_ACTIVE) return;
+    double rv[2];
+    slot_totals<2, 0>(red, slot, gridDim.x, rv);
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    if ((rv[0] == 0.0 && rv[1] == 0.0) || !all_finite(rv, 2)) {
+        if (lead) {
+            S.rv = z128{rv[0], rv[1]};
+            S.status = SLOT_BREAKDOWN;
+        }
+        return;
+    }
+    const z128 al = zdiv(S.rho, z128{rv[0], rv[1]});
+    if (lead) {
+        S.rv = z128{rv[0], rv[1]};
+        S.alpha = al;
+    }
     const cx<T> a{T(al.x), T(al.y)};
     double s[1] = {0.0};
     for (int64_t i = i0; i < nv; i += stride) {
@@ -164,43 +235,33 @@ __global__ __launch_bounds__(NT) void k_update_s(const cx<T>* __restrict__ r,
         sv[base + i] = si;
         s[0] += double(norm2(si));
     }
-    block_partial<1, NT>(s, red, slot, blockIdx.x);
-}
-__global__ __launch_bounds__(NT) void k_fin_s(BicgSlot* st, const int* act, RedScratch red,
-                                              int nblk) {
-    if (st[act[blockIdx.x]].status != SLOT_ACTIVE) return;
-    FIN_PROLOGUE(1)
-    if (tot[0] <= S.tol2 * S.bnorm2) S.status = SLOT_HALF;
+    block_partial<1, NT, 2>(s, red, slot, blockIdx.x);
 }
 
 template <typename T>
 __global__ __launch_bounds__(NT) void k_omega(const cx<T>* __restrict__ t,
-                                              const cx<T>* __restrict__ sv, const BicgSlot* st,
+                                              const cx<T>* __restrict__ sv, BicgSlot* st,
                                               const int* __restrict__ act, int64_t nv,
                                               RedScratch red) {
     SLOT_PROLOGUE
-    if (st[slot].status != SLOT_ACTIVE) return;
+    BicgSlot& S = st[slot];
+    if (S.status != SLOT_ACTIVE) return;
+    double ss[1];
+    slot_totals<1, 2>(red, slot, gridDim.x, ss);
+    if (ss[0] <= S.tol2 * S.bnorm2) {  // ||s|| met the tolerance: x += alpha p ends the solve
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            S.omega = z128{0.0, 0.0};
+            S.status = SLOT_HALF;
+        }
+        return;
+    }
     double s[3] = {0.0, 0.0, 0.0};
     for (int64_t i = i0; i < nv; i += stride) {
         const cx<T> ti = t[base + i];
         acc_cdot(s[0], s[1], ti, sv[base + i]);
         s[2] += double(norm2(ti));
     }
-    block_partial<3, NT>(s, red, slot, blockIdx.x);
-}
-__global__ __launch_bounds__(NT) void k_fin_omega(BicgSlot* st, const int* act, RedScratch red,
-                                                  int nblk) {
-    const int sl = act[blockIdx.x];
-    const int status = st[sl].status;
-    if (status == SLOT_HALF) {
-        if (threadIdx.x == 0) st[sl].omega = z128{0.0, 0.0};
-        return;
-    }
-    if (status != SLOT_ACTIVE) return;
-    FIN_PROLOGUE(3)
-    S.ts = z128{tot[0], tot[1]};
-    S.tt = tot[2];
-    S.omega = tot[2] > 0.0 ? z128{tot[0] / tot[2], tot[1] / tot[2]} : z128{0.0, 0.0};
+    block_partial<3, NT, 3>(s, red, slot, blockIdx.x);
 }
 
 template <typename T>
@@ -208,13 +269,27 @@ __global__ __launch_bounds__(NT) void k_update_xr(cx<T>* __restrict__ x, cx<T>* 
                                                   const cx<T>* __restrict__ rhat,
                                                   const cx<T>* __restrict__ p,
                                                   const cx<T>* __restrict__ sv,
-                                                  const cx<T>* __restrict__ t, const BicgSlot* st,
+                                                  const cx<T>* __restrict__ t, BicgSlot* st,
                                                   const int* __restrict__ act, int64_t nv,
                                                   RedScratch red) {
     SLOT_PROLOGUE
-    const int status = st[slot].status;
+    BicgSlot& S = st[slot];
+    const int status = S.status;
     if (status != SLOT_ACTIVE && status != SLOT_HALF) return;
-    const z128 al = st[slot].alpha, om = st[slot].omega;
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    z128 om{0.0, 0.0};
+    if (status == SLOT_ACTIVE) {
+        double ts[3];
+        slot_totals<3, 3>(red, slot, gridDim.x, ts);
+        if (ts[2] > 0.0) om = z128{ts[0] / ts[2], ts[1] / ts[2]};
+        if (lead) {
+            S.ts = z128{ts[0], ts[1]};
+            S.tt = ts[2];
+            S.omega = om;
+        }
+    }
+    if (lead) S.rho_old = S.rho;
+    const z128 al = S.alpha;
     const cx<T> a{T(al.x), T(al.y)}, o{T(om.x), T(om.y)};
     double s[3] = {0.0, 0.0, 0.0};
     for (int64_t i = i0; i < nv; i += stride) {
@@ -225,24 +300,14 @@ __global__ __launch_bounds__(NT) void k_update_xr(cx<T>* __restrict__ x, cx<T>* 
         acc_cdot(s[0], s[1], rhat[base + i], ri);
         s[2] += double(norm2(ri));
     }
-    block_partial<3, NT>(s, red, slot, blockIdx.x);
+    block_partial<3, NT, 0>(s, red, slot, blockIdx.x);
 }
 __global__ __launch_bounds__(NT) void k_fin_xr(BicgSlot* st, const int* act, RedScratch red,
                                                int nblk) {
     const int status = st[act[blockIdx.x]].status;
     if (status != SLOT_ACTIVE && status != SLOT_HALF) return;
     FIN_PROLOGUE(3)
-    S.iters += 1;
-    S.rho_old = S.rho;
-    S.rho = z128{tot[0], tot[1]};
-    S.rnorm2 = tot[2];
-    if (!all_finite(tot, 3)) {
-        S.status = SLOT_BREAKDOWN;
-    } else if (status == SLOT_HALF || tot[2] <= S.tol2 * S.bnorm2) {
-        S.status = SLOT_CONVERGED;
-    } else if ((tot[0] == 0.0 && tot[1] == 0.0) || (S.omega.x == 0.0 && S.omega.y == 0.0)) {
-        S.status = SLOT_BREAKDOWN;
-    }
+    finish_iteration(S, status, tot, true);
 }
 
 template <typename T>
@@ -562,10 +627,12 @@ void bicg_reset(const cx<T>* r, cx<T>* rhat, cx<T>* p, cx<T>* v, BicgSlot* st, c
 }
 template <typename T>
 void bicg_update_p(const cx<T>* r, cx<T>* p, const cx<T>* v, BicgSlot* st, const int* act,
-                   int n_act, int64_t nv, hipStream_t s) {
+                   int n_act, int64_t nv, RedScratch red, bool fin_prev, hipStream_t s) {
     if (n_act == 0) return;
     dim3 grid(blocks_for(nv, 1 << 20), n_act);
-    k_update_p<T><<<grid, NT, 0, s>>>(r, p, v, st, act, nv);
+    const int nblk = blocks_for(nv, red.max_blocks);
+    if (fin_prev) k_update_p<T, true><<<grid, NT, 0, s>>>(r, p, v, st, act, nv, red, nblk);
+    else k_update_p<T, false><<<grid, NT, 0, s>>>(r, p, v, st, act, nv, red, nblk);
     DDA_LAUNCH_CHECK();
 }
 template <typename T>
@@ -574,7 +641,6 @@ void bicg_alpha(const cx<T>* rhat, const cx<T>* v, BicgSlot* st, const int* act,
     if (n_act == 0) return;
     k_alpha<T><<<GRID(nv), NT, 0, s>>>(rhat, v, st, act, nv, red);
     DDA_LAUNCH_CHECK();
-    FIN(k_fin_alpha);
 }
 template <typename T>
 void bicg_update_s(const cx<T>* r, const cx<T>* v, cx<T>* sv, BicgSlot* st, const int* act,
@@ -582,7 +648,6 @@ void bicg_update_s(const cx<T>* r, const cx<T>* v, cx<T>* sv, BicgSlot* st, cons
     if (n_act == 0) return;
     k_update_s<T><<<GRID(nv), NT, 0, s>>>(r, v, sv, st, act, nv, red);
     DDA_LAUNCH_CHECK();
-    FIN(k_fin_s);
 }
 template <typename T>
 void bicg_omega(const cx<T>* t, const cx<T>* sv, BicgSlot* st, const int* act, int n_act,
@@ -590,7 +655,6 @@ void bicg_omega(const cx<T>* t, const cx<T>* sv, BicgSlot* st, const int* act, i
     if (n_act == 0) return;
     k_omega<T><<<GRID(nv), NT, 0, s>>>(t, sv, st, act, nv, red);
     DDA_LAUNCH_CHECK();
-    FIN(k_fin_omega);
 }
 template <typename T>
 void bicg_update_xr(cx<T>* x, cx<T>* r, const cx<T>* rhat, const cx<T>* p, const cx<T>* sv,
@@ -599,6 +663,10 @@ void bicg_update_xr(cx<T>* x, cx<T>* r, const cx<T>* rhat, const cx<T>* p, const
     if (n_act == 0) return;
     k_update_xr<T><<<GRID(nv), NT, 0, s>>>(x, r, rhat, p, sv, t, st, act, nv, red);
     DDA_LAUNCH_CHECK();
+}
+void bicg_finish(BicgSlot* st, const int* act, int n_act, int64_t nv, RedScratch red,
+                 hipStream_t s) {
+    if (n_act == 0) return;
     FIN(k_fin_xr);
 }
 template <typename T>
@@ -688,7 +756,7 @@ void loss_sums(const z128* einc, const z128* p, const z128* y, const double* w, 
     template void bicg_reset<T>(const cx<T>*, cx<T>*, cx<T>*, cx<T>*, BicgSlot*, const int*, int, \
                                 int64_t, RedScratch, hipStream_t);                               \
     template void bicg_update_p<T>(const cx<T>*, cx<T>*, const cx<T>*, BicgSlot*, const int*,    \
-                                   int, int64_t, hipStream_t);                                   \
+                                   int, int64_t, RedScratch, bool, hipStream_t);                 \
     template void bicg_alpha<T>(const cx<T>*, const cx<T>*, BicgSlot*, const int*, int, int64_t, \
                                 RedScratch, hipStream_t);                                        \
     template void bicg_update_s<T>(const cx<T>*, const cx<T>*, cx<T>*, BicgSlot*, const int*,    \
