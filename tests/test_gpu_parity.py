@@ -331,6 +331,36 @@ def test_cocg_graph_replay_equals_direct_launches(precision, timing):
         assert np.array_equal(pk, out[0][0])
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_bicgstab_same_iterates_for_any_interval_and_graphs(precision):
+    """BiCGStab closes an iteration either in the next iteration's direction
+    update or, at the end of an interval, in a finalize kernel.  Both forms run
+    the same arithmetic in the same order, so the solution, the iteration count
+    and the residual are bit-identical for check intervals of 1 (every
+    iteration closed by the finalize kernel), 5 and 16, with captured graphs
+    and without.  Energies converge at different iterations, so slots go
+    quiet inside intervals."""
+    mask, d, r0 = _small_particle()
+    n = int(mask.sum())
+    energies = np.linspace(1.2, 3.0, 5)
+    eps = np.repeat(W.drude_eps(energies)[:, None], n, axis=1)
+    out = []
+    for check, graphs in ((1, False), (5, True), (16, True), (16, False)):
+        s = DDASolver(mask, d, 1.45, tol=1e-11, maxit=20000, solver="bicgstab",
+                      precision=precision, check_every=check, use_graphs=graphs)
+        e = s.einc(energies, 0.55, r0)
+        p, info, st = s.solve(energies, eps, e, r0.shape[0])
+        assert st == L.DDA_OK
+        torch.cuda.synchronize()
+        out.append((from_dev(p), [(i.iters, i.rel_residual, i.status) for i in info]))
+        s.close()
+    iters = [i[0] for i in out[0][1]]
+    assert len(set(iters)) > 1, iters
+    for pk, ik in out[1:]:
+        assert ik == out[0][1]
+        assert np.array_equal(pk, out[0][0])
+
+
 @pytest.mark.parametrize("shape", [(12, 12, 12), (12, 12, 16), (16, 8, 12)])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_every_autotuner_candidate_gives_identical_matvecs(shape, precision):
