@@ -526,7 +526,8 @@ template <typename T>
 void matvec(dda_ctx* c, const Work& w, dda::cx<T>* x, dda::cx<T>* y, const int* act, int n_act,
             const dda::cx<T>* const* dptr, const int* slot_sys, const dda::cx<T>* ainv, int mode,
             const dda::cx<T>* fuse_r = nullptr,
-            dda::SlotFilter f = dda::SlotFilter{nullptr, dda::FILTER_ALL}) {
+            dda::SlotFilter f = dda::SlotFilter{nullptr, dda::FILTER_ALL},
+            const dda::cx<T>* dotw = nullptr) {
     if (n_act == 0 || c->g.n_occ == 0) return;
     if ((fuse_r || f.mode != dda::FILTER_ALL) && !f.st)
         throw Error(DDA_EDEVICE, "slot filter without slot states");
@@ -550,7 +551,7 @@ void matvec(dda_ctx* c, const Work& w, dda::cx<T>* x, dda::cx<T>* y, const int* 
         {
             Tic t(c, 4, n_act);
             dda::launch_ixfft_t<T>(G, x, ainv, y, c->map.as<int>(), tw_of<T>(c, 0), g, act,
-                                   slot_sys, n_act, mode, f, w.red, s);
+                                   slot_sys, n_act, mode, f, w.red, s, dotw);
         }
     } else {
         const int64_t plane = int64_t(g.my) * g.mx;
@@ -577,7 +578,7 @@ void matvec(dda_ctx* c, const Work& w, dda::cx<T>* x, dda::cx<T>* y, const int* 
         {
             Tic t(c, 4, n_act);
             dda::launch_ixfft_pack<T>(G, x, ainv, y, c->map.as<int>(), tw_of<T>(c, 0), g, act,
-                                      slot_sys, n_act, mode, f, w.red, s);
+                                      slot_sys, n_act, mode, f, w.red, s, dotw);
         }
     }
 }
@@ -586,8 +587,9 @@ template <typename T>
 void matvec(dda_ctx* c, dda::cx<T>* x, dda::cx<T>* y, const int* act, int n_act,
             const dda::cx<T>* const* dptr, const int* slot_sys, const dda::cx<T>* ainv, int mode,
             const dda::cx<T>* fuse_r = nullptr,
-            dda::SlotFilter f = dda::SlotFilter{nullptr, dda::FILTER_ALL}) {
-    matvec<T>(c, ctx_work(c), x, y, act, n_act, dptr, slot_sys, ainv, mode, fuse_r, f);
+            dda::SlotFilter f = dda::SlotFilter{nullptr, dda::FILTER_ALL},
+            const dda::cx<T>* dotw = nullptr) {
+    matvec<T>(c, ctx_work(c), x, y, act, n_act, dptr, slot_sys, ainv, mode, fuse_r, f, dotw);
 }
 
 // ------------------------------------------------------------ D cache
@@ -797,15 +799,17 @@ void run_bicgstab(dda_ctx* c, int nslots, const dda::cx<T>* b, dda::cx<T>* x, Ve
     const bool graphs = use_graphs(c);
     c->graph.drop();
     // One interval of `check` iterations over the n_act slots listed in dact.
+    const int nblk_mv = pack_blocks(c, int(sizeof(dda::cx<T>)));
+    const dda::SlotFilter all{nullptr, dda::FILTER_ALL};
     auto interval = [&](int n_act) {
         for (int k = 0; k < check; ++k) {
             dda::bicg_update_p<T>(w.r, w.p, w.v, st, dact, n_act, nv, red, k > 0, s);
-            matvec<T>(c, w.p, w.v, dact, n_act, dptr, slot_sys, ainv, dda::PACK_AX);
-            dda::bicg_alpha<T>(w.rhat, w.v, st, dact, n_act, nv, red, s);
-            dda::bicg_update_s<T>(w.r, w.v, w.s, st, dact, n_act, nv, red, s);
-            matvec<T>(c, w.s, w.t, dact, n_act, dptr, slot_sys, ainv, dda::PACK_AX);
-            dda::bicg_omega<T>(w.t, w.s, st, dact, n_act, nv, red, s);
-            dda::bicg_update_xr<T>(x, w.r, w.rhat, w.p, w.s, w.t, st, dact, n_act, nv, red, s);
+            matvec<T>(c, w.p, w.v, dact, n_act, dptr, slot_sys, ainv, dda::PACK_AX_DOTW, nullptr,
+                      all, w.rhat);
+            dda::bicg_update_s<T>(w.r, w.v, w.s, st, dact, n_act, nv, red, nblk_mv, s);
+            matvec<T>(c, w.s, w.t, dact, n_act, dptr, slot_sys, ainv, dda::PACK_AX_TS);
+            dda::bicg_update_xr<T>(x, w.r, w.rhat, w.p, w.s, w.t, st, dact, n_act, nv, red,
+                                   nblk_mv, s);
         }
         dda::bicg_finish(st, dact, n_act, nv, red, s);
     };

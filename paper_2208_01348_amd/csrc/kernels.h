@@ -62,14 +62,54 @@ std::vector<int> zconv_tx_candidates(int L);
 // mode PACK_AX: y = x/alpha - G_off x; PACK_GX: y = G_off x; PACK_AX_COCG:
 // y = A x and, fused, the partial rows of mu = x^T y per slot in `red`
 // (pack_blocks_per_slot rows, which must not exceed max_blocks); the caller
-// then runs cocg_update_xr, which reads them.
-enum PackMode { PACK_AX = 0, PACK_GX = 1, PACK_AX_COCG = 2 };
+// then runs cocg_update_xr, which reads them.  PACK_AX_DOTW: y = A x and the
+// rows of <w, y> = sum conj(w) y at offset 0 (w given per slot like x);
+// PACK_AX_TS: y = A x and the rows of <y, x> and ||y||^2 at offset 3 (the
+// BiCGStab products <rhat, v> and <t, s>, ||t||^2).
+enum PackMode { PACK_AX = 0, PACK_GX = 1, PACK_AX_COCG = 2, PACK_AX_DOTW = 3, PACK_AX_TS = 4 };
+inline bool pack_fused(int mode) { return mode >= PACK_AX_COCG; }
+
+// Per-element products of the fused pack modes (x the input, y = A x, w the
+// extra vector), accumulated in FP64.
+template <typename T, int MODE>
+__device__ __forceinline__ void pack_dots(double (&mu)[3], cx<T> x, cx<T> y, cx<T> w) {
+    if constexpr (MODE == PACK_AX_COCG) {  // bilinear x^T y
+        if constexpr (sizeof(T) == 8) {
+            // the contraction written out, so that it does not depend on how
+            // the compiler orders the expression in each kernel
+            mu[0] += fma(x.x, y.x, -(x.y * y.y));
+            mu[1] += fma(x.x, y.y, x.y * y.x);
+        } else {
+            mu[0] += double(x.x) * y.x - double(x.y) * y.y;
+            mu[1] += double(x.x) * y.y + double(x.y) * y.x;
+        }
+    } else if constexpr (MODE == PACK_AX_DOTW) {  // conj(w) y
+        const double wx = w.x, wy = w.y, yx = y.x, yy = y.y;
+        mu[0] += wx * yx + wy * yy;
+        mu[1] += wx * yy - wy * yx;
+    } else if constexpr (MODE == PACK_AX_TS) {  // conj(y) x and |y|^2
+        const double xx = x.x, xy = x.y, yx = y.x, yy = y.y;
+        mu[0] += yx * xx + yy * xy;
+        mu[1] += yx * xy - yy * xx;
+        mu[2] += yx * yx + yy * yy;
+    }
+}
+// Stores a pack block's partial row of the fused mode (every thread calls it).
+template <int MODE, int NT>
+__device__ __forceinline__ void pack_rows(double (&mu)[3], RedScratch red, int slot, int blk) {
+    if constexpr (MODE == PACK_AX_COCG || MODE == PACK_AX_DOTW) {
+        double m2[2] = {mu[0], mu[1]};
+        block_partial<2, NT, 0>(m2, red, slot, blk);
+    } else if constexpr (MODE == PACK_AX_TS) {
+        block_partial<3, NT, 3>(mu, red, slot, blk);
+    }
+}
 int pack_blocks_per_slot(const Geo& g);
 template <typename T>
 void launch_ixfft_pack(const cx<T>* G, const cx<T>* xin, const cx<T>* ainv, cx<T>* yout,
                        const int* map, const cx<T>* tw_x, const Geo& g, const int* act,
                        const int* slot_sys, int n_act, int mode, SlotFilter f, RedScratch red,
-                       hipStream_t s);
+                       hipStream_t s, const cx<T>* wv = nullptr);
 
 // Interaction spectrum: D = FFT3(G_tilde on the embedding grid) / (mx my mz),
 // FP64 over the full grid (dgrid_elems), for one host wavenumber k.  The
@@ -114,7 +154,7 @@ template <typename T>
 void launch_ixfft_t(const cx<T>* Tb, const cx<T>* xin, const cx<T>* ainv, cx<T>* yout,
                     const int* map, const cx<T>* tw_x, const Geo& g, const int* act,
                     const int* slot_sys, int n_act, int mode, SlotFilter f, RedScratch red,
-                    hipStream_t s);
+                    hipStream_t s, const cx<T>* wv = nullptr);
 void launch_convert_z128_to_z64(const z128* in, z64* out, int64_t n, hipStream_t s);
 void launch_convert_z64_to_z128(const z64* in, z128* out, int64_t n, hipStream_t s);
 

@@ -15,27 +15,22 @@ void bicg_norm_b(const cx<T>* b, BicgSlot* st, const int* act, int n_act, int64_
 template <typename T>
 void bicg_reset(const cx<T>* r, cx<T>* rhat, cx<T>* p, cx<T>* v, BicgSlot* st, const int* act,
                 int n_act, int64_t nv, RedScratch red, hipStream_t s);
-// One iteration: update_p, v = A p, alpha, update_s, t = A s, omega,
-// update_xr.  Each kernel takes the scalar it needs from the partial rows of
-// the one before; update_p with fin_prev closes the previous iteration, and
-// bicg_finish closes the last one of a sequence (before the host reads the
-// slot states).
+// One iteration: update_p, v = A p (pack mode PACK_AX_DOTW with w = rhat),
+// update_s, t = A s (PACK_AX_TS), update_xr.  Each kernel takes the scalar
+// it needs from the partial rows of the one before (nblk_mv: the matvec
+// pack kernel's rows per slot); update_p with fin_prev closes the previous
+// iteration, and bicg_finish closes the last one of a sequence (before the
+// host reads the slot states).
 template <typename T>
 void bicg_update_p(const cx<T>* r, cx<T>* p, const cx<T>* v, BicgSlot* st, const int* act,
                    int n_act, int64_t nv, RedScratch red, bool fin_prev, hipStream_t s);
 template <typename T>
-void bicg_alpha(const cx<T>* rhat, const cx<T>* v, BicgSlot* st, const int* act, int n_act,
-                int64_t nv, RedScratch red, hipStream_t s);
-template <typename T>
 void bicg_update_s(const cx<T>* r, const cx<T>* v, cx<T>* sv, BicgSlot* st, const int* act,
-                   int n_act, int64_t nv, RedScratch red, hipStream_t s);
-template <typename T>
-void bicg_omega(const cx<T>* t, const cx<T>* sv, BicgSlot* st, const int* act, int n_act,
-                int64_t nv, RedScratch red, hipStream_t s);
+                   int n_act, int64_t nv, RedScratch red, int nblk_mv, hipStream_t s);
 template <typename T>
 void bicg_update_xr(cx<T>* x, cx<T>* r, const cx<T>* rhat, const cx<T>* p, const cx<T>* sv,
                     const cx<T>* t, BicgSlot* st, const int* act, int n_act, int64_t nv,
-                    RedScratch red, hipStream_t s);
+                    RedScratch red, int nblk_mv, hipStream_t s);
 void bicg_finish(BicgSlot* st, const int* act, int n_act, int64_t nv, RedScratch red,
                  hipStream_t s);
 // r = b - y, rnorm2 = ||r||^2 (true residual after y = A x)

@@ -114,14 +114,14 @@ __global__ __launch_bounds__(NT) void k_fin_reset(BicgSlot* st, const int* act, 
     S.status = (tot[0] <= S.tol2 * S.bnorm2) ? SLOT_CONVERGED : SLOT_ACTIVE;
 }
 
-// One BiCGStab iteration is five vector kernels around the two matvecs:
+// One BiCGStab iteration is three vector kernels around the two matvecs,
+// whose pack kernels write the dot products of their output:
 //   update_p  [FIN: sums the rows at 0..2 of the previous update_xr]
-//   v = A p
-//   alpha     (writes <rhat, v> rows at 0..1)
-//   update_s  (sums rows 0..1 -> alpha; writes ||s||^2 rows at 2)
-//   t = A s
-//   omega     (sums row 2 -> the half-step test; writes <t, s>, ||t||^2 rows at 3..5)
-//   update_xr (sums rows 3..5 -> omega; writes <rhat, r>, ||r||^2 rows at 0..2)
+//   v = A p   (pack rows of <rhat, v> at 0..1)
+//   update_s  (sums those rows -> alpha; writes ||s||^2 rows at 2)
+//   t = A s   (pack rows of <t, s>, ||t||^2 at 3..5)
+//   update_xr (sums row 2 -> the half-step test, rows 3..5 -> omega; writes
+//              <rhat, r>, ||r||^2 rows at 0..2)
 // and k_fin_xr closes the last iteration of an interval.  A kernel that
 // needs a scalar sums the rows itself in every block (the same fixed order,
 // so every block gets the same value); block 0 stores it in the slot state.
@@ -194,27 +194,15 @@ __global__ __launch_bounds__(NT) void k_update_p(const cx<T>* __restrict__ r, cx
 }
 
 template <typename T>
-__global__ __launch_bounds__(NT) void k_alpha(const cx<T>* __restrict__ rhat,
-                                              const cx<T>* __restrict__ v, const BicgSlot* st,
-                                              const int* __restrict__ act, int64_t nv,
-                                              RedScratch red) {
-    SLOT_PROLOGUE
-    if (st[slot].status != SLOT_ACTIVE) return;
-    double s[2] = {0.0, 0.0};
-    for (int64_t i = i0; i < nv; i += stride) acc_cdot(s[0], s[1], rhat[base + i], v[base + i]);
-    block_partial<2, NT, 0>(s, red, slot, blockIdx.x);
-}
-
-template <typename T>
 __global__ __launch_bounds__(NT) void k_update_s(const cx<T>* __restrict__ r,
                                                  const cx<T>* __restrict__ v, cx<T>* __restrict__ sv,
                                                  BicgSlot* st, const int* __restrict__ act,
-                                                 int64_t nv, RedScratch red) {
+                                                 int64_t nv, RedScratch red, int nblk_mv) {
     SLOT_PROLOGUE
     BicgSlot& S = st[slot];
     if (S.status != SLOT_ACTIVE) return;
     double rv[2];
-    slot_totals<2, 0>(red, slot, gridDim.x, rv);
+    slot_totals<2, 0>(red, slot, nblk_mv, rv);
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     if ((rv[0] == 0.0 && rv[1] == 0.0) || !all_finite(rv, 2)) {
         if (lead) {
@@ -239,39 +227,13 @@ __global__ __launch_bounds__(NT) void k_update_s(const cx<T>* __restrict__ r,
 }
 
 template <typename T>
-__global__ __launch_bounds__(NT) void k_omega(const cx<T>* __restrict__ t,
-                                              const cx<T>* __restrict__ sv, BicgSlot* st,
-                                              const int* __restrict__ act, int64_t nv,
-                                              RedScratch red) {
-    SLOT_PROLOGUE
-    BicgSlot& S = st[slot];
-    if (S.status != SLOT_ACTIVE) return;
-    double ss[1];
-    slot_totals<1, 2>(red, slot, gridDim.x, ss);
-    if (ss[0] <= S.tol2 * S.bnorm2) {  // ||s|| met the tolerance: x += alpha p ends the solve
-        if (blockIdx.x == 0 && threadIdx.x == 0) {
-            S.omega = z128{0.0, 0.0};
-            S.status = SLOT_HALF;
-        }
-        return;
-    }
-    double s[3] = {0.0, 0.0, 0.0};
-    for (int64_t i = i0; i < nv; i += stride) {
-        const cx<T> ti = t[base + i];
-        acc_cdot(s[0], s[1], ti, sv[base + i]);
-        s[2] += double(norm2(ti));
-    }
-    block_partial<3, NT, 3>(s, red, slot, blockIdx.x);
-}
-
-template <typename T>
 __global__ __launch_bounds__(NT) void k_update_xr(cx<T>* __restrict__ x, cx<T>* __restrict__ r,
                                                   const cx<T>* __restrict__ rhat,
                                                   const cx<T>* __restrict__ p,
                                                   const cx<T>* __restrict__ sv,
                                                   const cx<T>* __restrict__ t, BicgSlot* st,
                                                   const int* __restrict__ act, int64_t nv,
-                                                  RedScratch red) {
+                                                  RedScratch red, int nblk_mv) {
     SLOT_PROLOGUE
     BicgSlot& S = st[slot];
     const int status = S.status;
@@ -279,13 +241,22 @@ __global__ __launch_bounds__(NT) void k_update_xr(cx<T>* __restrict__ x, cx<T>* 
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     z128 om{0.0, 0.0};
     if (status == SLOT_ACTIVE) {
-        double ts[3];
-        slot_totals<3, 3>(red, slot, gridDim.x, ts);
-        if (ts[2] > 0.0) om = z128{ts[0] / ts[2], ts[1] / ts[2]};
-        if (lead) {
-            S.ts = z128{ts[0], ts[1]};
-            S.tt = ts[2];
-            S.omega = om;
+        double ss[1];
+        slot_totals<1, 2>(red, slot, gridDim.x, ss);
+        if (ss[0] <= S.tol2 * S.bnorm2) {  // ||s|| met the tolerance: x += alpha p ends the solve
+            if (lead) {
+                S.omega = om;
+                S.status = SLOT_HALF;
+            }
+        } else {
+            double ts[3];
+            slot_totals<3, 3>(red, slot, nblk_mv, ts);
+            if (ts[2] > 0.0) om = z128{ts[0] / ts[2], ts[1] / ts[2]};
+            if (lead) {
+                S.ts = z128{ts[0], ts[1]};
+                S.tt = ts[2];
+                S.omega = om;
+            }
         }
     }
     if (lead) S.rho_old = S.rho;
@@ -636,32 +607,20 @@ void bicg_update_p(const cx<T>* r, cx<T>* p, const cx<T>* v, BicgSlot* st, const
     DDA_LAUNCH_CHECK();
 }
 template <typename T>
-void bicg_alpha(const cx<T>* rhat, const cx<T>* v, BicgSlot* st, const int* act, int n_act,
-                int64_t nv, RedScratch red, hipStream_t s) {
-    if (n_act == 0) return;
-    k_alpha<T><<<GRID(nv), NT, 0, s>>>(rhat, v, st, act, nv, red);
-    DDA_LAUNCH_CHECK();
-}
-template <typename T>
 void bicg_update_s(const cx<T>* r, const cx<T>* v, cx<T>* sv, BicgSlot* st, const int* act,
-                   int n_act, int64_t nv, RedScratch red, hipStream_t s) {
+                   int n_act, int64_t nv, RedScratch red, int nblk_mv, hipStream_t s) {
     if (n_act == 0) return;
-    k_update_s<T><<<GRID(nv), NT, 0, s>>>(r, v, sv, st, act, nv, red);
-    DDA_LAUNCH_CHECK();
-}
-template <typename T>
-void bicg_omega(const cx<T>* t, const cx<T>* sv, BicgSlot* st, const int* act, int n_act,
-                int64_t nv, RedScratch red, hipStream_t s) {
-    if (n_act == 0) return;
-    k_omega<T><<<GRID(nv), NT, 0, s>>>(t, sv, st, act, nv, red);
+    if (nblk_mv < 1 || nblk_mv > red.max_blocks) throw Error(-3, "bad matvec row count");
+    k_update_s<T><<<GRID(nv), NT, 0, s>>>(r, v, sv, st, act, nv, red, nblk_mv);
     DDA_LAUNCH_CHECK();
 }
 template <typename T>
 void bicg_update_xr(cx<T>* x, cx<T>* r, const cx<T>* rhat, const cx<T>* p, const cx<T>* sv,
                     const cx<T>* t, BicgSlot* st, const int* act, int n_act, int64_t nv,
-                    RedScratch red, hipStream_t s) {
+                    RedScratch red, int nblk_mv, hipStream_t s) {
     if (n_act == 0) return;
-    k_update_xr<T><<<GRID(nv), NT, 0, s>>>(x, r, rhat, p, sv, t, st, act, nv, red);
+    if (nblk_mv < 1 || nblk_mv > red.max_blocks) throw Error(-3, "bad matvec row count");
+    k_update_xr<T><<<GRID(nv), NT, 0, s>>>(x, r, rhat, p, sv, t, st, act, nv, red, nblk_mv);
     DDA_LAUNCH_CHECK();
 }
 void bicg_finish(BicgSlot* st, const int* act, int n_act, int64_t nv, RedScratch red,
@@ -757,15 +716,11 @@ void loss_sums(const z128* einc, const z128* p, const z128* y, const double* w, 
                                 int64_t, RedScratch, hipStream_t);                               \
     template void bicg_update_p<T>(const cx<T>*, cx<T>*, const cx<T>*, BicgSlot*, const int*,    \
                                    int, int64_t, RedScratch, bool, hipStream_t);                 \
-    template void bicg_alpha<T>(const cx<T>*, const cx<T>*, BicgSlot*, const int*, int, int64_t, \
-                                RedScratch, hipStream_t);                                        \
     template void bicg_update_s<T>(const cx<T>*, const cx<T>*, cx<T>*, BicgSlot*, const int*,    \
-                                   int, int64_t, RedScratch, hipStream_t);                       \
-    template void bicg_omega<T>(const cx<T>*, const cx<T>*, BicgSlot*, const int*, int, int64_t, \
-                                RedScratch, hipStream_t);                                        \
+                                   int, int64_t, RedScratch, int, hipStream_t);                  \
     template void bicg_update_xr<T>(cx<T>*, cx<T>*, const cx<T>*, const cx<T>*, const cx<T>*,    \
                                     const cx<T>*, BicgSlot*, const int*, int, int64_t,           \
-                                    RedScratch, hipStream_t);                                    \
+                                    RedScratch, int, hipStream_t);                               \
     template void residual<T>(const cx<T>*, const cx<T>*, cx<T>*, BicgSlot*, const int*, int,    \
                               int64_t, RedScratch, hipStream_t);                                 \
     template void cocg_update_xr<T>(cx<T>*, cx<T>*, const cx<T>*, const cx<T>*, BicgSlot*,       \

@@ -356,7 +356,8 @@ __global__ __launch_bounds__(NTHR) void k_ixfft_pack(const cx<T>* __restrict__ G
                                                      const cx<T>* __restrict__ tw, Geo g,
                                                      const int* __restrict__ act,
                                                      const int* __restrict__ slot_sys,
-                                                     SlotFilter f, RedScratch red) {
+                                                     SlotFilter f, RedScratch red,
+                                                     const cx<T>* __restrict__ wv) {
     constexpr int NL = rows_nl<T, L>();
     __shared__ cx<T> lds[NL * L];
     __shared__ cx<T> twl[L];
@@ -400,16 +401,17 @@ __global__ __launch_bounds__(NTHR) void k_ixfft_pack(const cx<T>* __restrict__ G
         const int m = map[int64_t(min(row, nrows - 1)) * g.nx + min(x, g.nx - 1)];
         idx[q] = (rr < NL && row < nrows && x < g.nx) ? m : -1;
     }
-    cx<T> xv[NE], av[NE];
+    cx<T> xv[NE], av[NE], wq[MODE == PACK_AX_DOTW ? NE : 1];
     if (MODE != PACK_GX) {
 #pragma unroll
         for (int q = 0; q < NE; ++q) {
             const int i = max(idx[q], 0);
             xv[q] = xin[voff + i];
             av[q] = ainv[sys * g.n_occ + i];
+            if constexpr (MODE == PACK_AX_DOTW) wq[q] = wv[voff + i];
         }
     }
-    double mu[2] = {0.0, 0.0};
+    double mu[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int q = 0; q < NE; ++q) {
         if (idx[q] < 0) continue;
@@ -421,14 +423,12 @@ __global__ __launch_bounds__(NTHR) void k_ixfft_pack(const cx<T>* __restrict__ G
         } else {
             const cx<T> yi = xv[q] * av[q] - conv;
             yout[voff + idx[q]] = yi;
-            if (MODE == PACK_AX_COCG) {  // bilinear x^T y
-                mu[0] += double(xv[q].x) * yi.x - double(xv[q].y) * yi.y;
-                mu[1] += double(xv[q].x) * yi.y + double(xv[q].y) * yi.x;
-            }
+            if constexpr (MODE == PACK_AX_DOTW) pack_dots<T, MODE>(mu, xv[q], yi, wq[q]);
+            else pack_dots<T, MODE>(mu, xv[q], yi, yi);
         }
     }
-    if constexpr (MODE == PACK_AX_COCG)  // partial rows; the COCG update kernel sums them
-        block_partial<2, NTHR>(mu, red, int(slot), blockIdx.y * gridDim.x + blockIdx.x);
+    // partial rows; the Krylov update kernels sum them
+    pack_rows<MODE, NTHR>(mu, red, int(slot), blockIdx.y * gridDim.x + blockIdx.x);
 }
 
 // ------------------------------------------------------------ launchers ---
@@ -595,28 +595,32 @@ template <typename T>
 void launch_ixfft_pack(const cx<T>* G, const cx<T>* xin, const cx<T>* ainv, cx<T>* yout,
                        const int* map, const cx<T>* tw_x, const Geo& g, const int* act,
                        const int* slot_sys, int n_act, int mode, SlotFilter f, RedScratch red,
-                       hipStream_t s) {
+                       hipStream_t s, const cx<T>* wv) {
     if (n_act == 0) return;
-    if (mode == PACK_AX_COCG && pack_blocks_per_slot(g) > red.max_blocks)
+    if (pack_fused(mode) && pack_blocks_per_slot(g) > red.max_blocks)
         throw Error(-3, "reduction scratch too small for the fused pack kernel");
+    if (mode == PACK_AX_DOTW && !wv) throw Error(-1, "PACK_AX_DOTW needs the vector w");
     const int64_t nrows = int64_t(g.nz) * g.ny;
     switch (g.mx) {
+#define DDA_IXP(N, M)                                                                      \
+    k_ixfft_pack<T, N, M><<<grid, NTHR, 0, s>>>(G, xin, ainv, yout, map, tw_x, g, act,        \
+                                                slot_sys, f, red, wv)
 #define DDA_CASE(N)                                                                        \
     case N: {                                                                              \
         dim3 grid(nblk(nrows, rows_nl<T, N>()), 3, n_act);                                 \
-        if (mode == PACK_GX)                                                               \
-            k_ixfft_pack<T, N, PACK_GX><<<grid, NTHR, 0, s>>>(G, xin, ainv, yout, map, tw_x,\
-                                                              g, act, slot_sys, f, red);  \
-        else if (mode == PACK_AX)                                                          \
-            k_ixfft_pack<T, N, PACK_AX><<<grid, NTHR, 0, s>>>(G, xin, ainv, yout, map, tw_x,\
-                                                              g, act, slot_sys, f, red);  \
-        else                                                                               \
-            k_ixfft_pack<T, N, PACK_AX_COCG><<<grid, NTHR, 0, s>>>(G, xin, ainv, yout, map, \
-                                                       tw_x, g, act, slot_sys, f, red);   \
+        switch (mode) {                                                                    \
+            case PACK_GX: DDA_IXP(N, PACK_GX); break;                                      \
+            case PACK_AX: DDA_IXP(N, PACK_AX); break;                                      \
+            case PACK_AX_COCG: DDA_IXP(N, PACK_AX_COCG); break;                            \
+            case PACK_AX_DOTW: DDA_IXP(N, PACK_AX_DOTW); break;                            \
+            case PACK_AX_TS: DDA_IXP(N, PACK_AX_TS); break;                                \
+            default: throw Error(-1, "unknown pack mode");                                 \
+        }                                                                                  \
         break;                                                                             \
     }
         DDA_FOR_EACH_L(DDA_CASE)
 #undef DDA_CASE
+#undef DDA_IXP
         default:
             throw Error(-1, "unsupported FFT length along x");
     }
@@ -641,10 +645,11 @@ template std::vector<int> zconv_tx_candidates<double>(int);
 template std::vector<int> zconv_tx_candidates<float>(int);
 template void launch_ixfft_pack<double>(const z128*, const z128*, const z128*, z128*,
                                         const int*, const z128*, const Geo&, const int*,
-                                        const int*, int, int, SlotFilter, RedScratch, hipStream_t);
+                                        const int*, int, int, SlotFilter, RedScratch, hipStream_t,
+                                        const z128*);
 template void launch_ixfft_pack<float>(const z64*, const z64*, const z64*, z64*, const int*,
                                        const z64*, const Geo&, const int*, const int*, int, int,
-                                       SlotFilter, RedScratch, hipStream_t);
+                                       SlotFilter, RedScratch, hipStream_t, const z64*);
 
 // ------------------------------------------------------------ D build -----
 // G_tilde(R) = exp(ikR)/R^3 [(k^2R^2 + ikR - 1) I + (3 - 3ikR - k^2R^2) Rh Rh]

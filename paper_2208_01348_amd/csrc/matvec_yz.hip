@@ -192,7 +192,8 @@ __global__ __launch_bounds__(NT) void k_ixfft_t(const cx<T>* __restrict__ Tb,
                                                 const cx<T>* __restrict__ tw, Geo g,
                                                 const int* __restrict__ act,
                                                 const int* __restrict__ slot_sys, SlotFilter f,
-                                                RedScratch red, int ngroups, int nr) {
+                                                RedScratch red, int ngroups, int nr,
+                                                const cx<T>* __restrict__ wv) {
     constexpr int NR = xrows_max<T, LX>();
     constexpr int LP = LX + 1;
     constexpr int HX = (LX + 1) / 2;
@@ -243,16 +244,17 @@ __global__ __launch_bounds__(NT) void k_ixfft_t(const cx<T>* __restrict__ Tb,
         const int m = mrow[min(r, nrow - 1) * g.nx + min(x, g.nx - 1)];
         idx[q] = (r < nrow && x < g.nx) ? m : -1;
     }
-    cx<T> xv[NE], av[NE];
+    cx<T> xv[NE], av[NE], wq[MODE == PACK_AX_DOTW ? NE : 1];
     if (MODE != PACK_GX) {
 #pragma unroll
         for (int q = 0; q < NE; ++q) {
             const int i = max(idx[q], 0);
             xv[q] = xin[voff + i];
             av[q] = ainv[sys * g.n_occ + i];
+            if constexpr (MODE == PACK_AX_DOTW) wq[q] = wv[voff + i];
         }
     }
-    double mu[2] = {0.0, 0.0};
+    double mu[3] = {0.0, 0.0, 0.0};
 #pragma unroll
     for (int q = 0; q < NE; ++q) {
         if (idx[q] < 0) continue;
@@ -264,14 +266,12 @@ __global__ __launch_bounds__(NT) void k_ixfft_t(const cx<T>* __restrict__ Tb,
         } else {
             const cx<T> yi = xv[q] * av[q] - conv;
             yout[voff + idx[q]] = yi;
-            if (MODE == PACK_AX_COCG) {  // bilinear x^T y
-                mu[0] += double(xv[q].x) * yi.x - double(xv[q].y) * yi.y;
-                mu[1] += double(xv[q].x) * yi.y + double(xv[q].y) * yi.x;
-            }
+            if constexpr (MODE == PACK_AX_DOTW) pack_dots<T, MODE>(mu, xv[q], yi, wq[q]);
+            else pack_dots<T, MODE>(mu, xv[q], yi, yi);
         }
     }
-    if constexpr (MODE == PACK_AX_COCG)  // partial rows; the COCG update kernel sums them
-        block_partial<2, NT>(mu, red, int(slot), blockIdx.x);
+    // partial rows; the Krylov update kernels sum them
+    pack_rows<MODE, NT>(mu, red, int(slot), blockIdx.x);
 }
 
 // ------------------------------------------------------------------ YZ -----
@@ -729,29 +729,33 @@ template <typename T>
 void launch_ixfft_t(const cx<T>* Tb, const cx<T>* xin, const cx<T>* ainv, cx<T>* yout,
                     const int* map, const cx<T>* tw_x, const Geo& g, const int* act,
                     const int* slot_sys, int n_act, int mode, SlotFilter f, RedScratch red,
-                    hipStream_t s) {
+                    hipStream_t s, const cx<T>* wv) {
     if (n_act == 0) return;
     if (2 * g.nx - 1 > g.mx) throw Error(-1, "x grid shorter than 2 nx - 1");
+    if (mode == PACK_AX_DOTW && !wv) throw Error(-1, "PACK_AX_DOTW needs the vector w");
     int ng, nr;
     xsplit<T>(g, ng, nr);
-    if (mode == PACK_AX_COCG && 3 * g.nz * ng > red.max_blocks)
+    if (pack_fused(mode) && 3 * g.nz * ng > red.max_blocks)
         throw Error(-3, "reduction scratch too small for the fused pack kernel");
     dim3 grid(3 * g.nz * ng, n_act);
     switch (g.mx) {
+#define DDA_IXT(N, M)                                                                        \
+    k_ixfft_t<T, N, M><<<grid, NT, 0, s>>>(Tb, xin, ainv, yout, map, tw_x, g, act, slot_sys, f, \
+                                           red, ng, nr, wv)
 #define DDA_CASE(N)                                                                          \
     case N:                                                                                  \
-        if (mode == PACK_GX)                                                                 \
-            k_ixfft_t<T, N, PACK_GX><<<grid, NT, 0, s>>>(Tb, xin, ainv, yout, map, tw_x, g,   \
-                                                         act, slot_sys, f, red, ng, nr);            \
-        else if (mode == PACK_AX)                                                            \
-            k_ixfft_t<T, N, PACK_AX><<<grid, NT, 0, s>>>(Tb, xin, ainv, yout, map, tw_x, g,   \
-                                                         act, slot_sys, f, red, ng, nr);            \
-        else                                                                                 \
-            k_ixfft_t<T, N, PACK_AX_COCG><<<grid, NT, 0, s>>>(Tb, xin, ainv, yout, map, tw_x, \
-                                                              g, act, slot_sys, f, red, ng, nr);    \
+        switch (mode) {                                                                      \
+            case PACK_GX: DDA_IXT(N, PACK_GX); break;                                        \
+            case PACK_AX: DDA_IXT(N, PACK_AX); break;                                        \
+            case PACK_AX_COCG: DDA_IXT(N, PACK_AX_COCG); break;                              \
+            case PACK_AX_DOTW: DDA_IXT(N, PACK_AX_DOTW); break;                              \
+            case PACK_AX_TS: DDA_IXT(N, PACK_AX_TS); break;                                  \
+            default: throw Error(-1, "unknown pack mode");                                   \
+        }                                                                                    \
         break;
         DDA_FOR_EACH_LX(DDA_CASE)
 #undef DDA_CASE
+#undef DDA_IXT
         default:
             throw Error(-1, "unsupported FFT length along x");
     }
@@ -822,10 +826,10 @@ template void launch_xfft_t<float>(z64*, const int*, z64*, const z64*, const Geo
                                    const z64*, SlotFilter, hipStream_t);
 template void launch_ixfft_t<double>(const z128*, const z128*, const z128*, z128*, const int*,
                                      const z128*, const Geo&, const int*, const int*, int, int,
-                                     SlotFilter, RedScratch, hipStream_t);
+                                     SlotFilter, RedScratch, hipStream_t, const z128*);
 template void launch_ixfft_t<float>(const z64*, const z64*, const z64*, z64*, const int*,
                                     const z64*, const Geo&, const int*, const int*, int, int,
-                                    SlotFilter, RedScratch, hipStream_t);
+                                    SlotFilter, RedScratch, hipStream_t, const z64*);
 template void launch_yzconv<double>(z128*, const z128* const*, const z128*, const z128*,
                                     const Geo&, const int*, const int*, int, SlotFilter, int,
                                     hipStream_t);
