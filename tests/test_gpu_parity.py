@@ -207,7 +207,9 @@ def test_losses_match_oracle(name, m_h, beta, precision, bar, solver):
     s.close()
 
 
-@pytest.mark.parametrize("solver,precision,bar", [("cocg", "mixed", 1e-5), ("cocg", "fp64", 1e-9)])
+@pytest.mark.parametrize("solver,precision,bar", [("cocg", "mixed", 1e-5), ("cocg", "fp64", 1e-9),
+                                                  ("bicgstab", "mixed", 1e-5),
+                                                  ("bicgstab", "fp64", 1e-9)])
 def test_losses_when_precisions_use_different_chains(solver, precision, bar):
     """A 5 x 17 x 17 lattice (FFT grid 12 x 64 x 64): the FP32 matvecs of the
     mixed path run the three-pass chain, its FP64 reliable updates and the
@@ -227,6 +229,36 @@ def test_losses_when_precisions_use_different_chains(solver, precision, bar):
     vals = [ref.p_eels, ref.p_ext, ref.p_abs, ref.p_cl]
     for g, v in zip(P[0], vals):
         assert abs(g - v) <= bar * abs(v), (g, v)
+    s.close()
+
+
+@pytest.mark.parametrize("solver,precision,bar", [("bicgstab", "mixed", 1e-5),
+                                                  ("bicgstab", "fp64", 1e-9),
+                                                  ("cocg", "mixed", 1e-5)])
+def test_losses_when_every_precision_uses_the_five_pass_chain(solver, precision, bar):
+    """A sparse 3 x 33 x 33 lattice: its yz grid is longer than 64, so the
+    FP32 matvecs run the five-pass chain too, with the fused partial rows of
+    the pack kernel (COCG x^T y, BiCGStab <rhat, v> and <t, s>, ||t||^2) in
+    both precisions; against dense LU."""
+    mask = W.random_mask(3, 33, 33, 0.3, seed=11)
+    d = 1.2
+    n = int(mask.sum())
+    energies = np.array([2.2])
+    eps = np.repeat(W.drude_eps(energies)[:, None], n, axis=1)
+    r0 = np.array([[6.0, 0.6, 0.0]])
+    say("five-pass chains", solver, precision, "n_occ", n)
+    s = DDASolver(mask, d, 1.45, precision=precision, solver=solver,
+                  tol=1e-12 if precision == "fp64" else 1e-10, maxit=20000)
+    assert s.grid[1] > 64 and s.grid[2] > 64, s.grid
+    P, info = s.spectrum(energies, 0.55, eps, r0)
+    assert info[0].status == 0, info[0]
+    ref = solve_point(mask, d, eps[0], 1.45, 0.55, r0[0], energies[0], method="lu")
+    vals = [ref.p_eels, ref.p_ext, ref.p_abs, ref.p_cl]
+    scale = max(abs(v) for v in vals)
+    for g, v, nm in zip(P[0], vals, ["eels", "ext", "abs", "cl"]):
+        err = abs(g - v) / max(abs(v), 1e-3 * scale)
+        say(f"  {nm}: gpu={g:.15e} oracle={v:.15e} rel={err:.2e}")
+        assert err <= bar, (nm, err)
     s.close()
 
 
