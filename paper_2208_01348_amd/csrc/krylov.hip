@@ -61,6 +61,17 @@ __device__ __forceinline__ bool all_finite(const double* t, int k) {
     return true;
 }
 
+// The slot status as one thread of the block read it, for every wave of the
+// block.  Kernels whose block 0 may change the status while other blocks run
+// take their decisions from this single read, so the waves of a block cannot
+// disagree and reach different barriers.  Every thread must call it.
+__device__ __forceinline__ int block_status(const BicgSlot& S) {
+    __shared__ int sh;
+    if (threadIdx.x == 0) sh = S.status;
+    __syncthreads();
+    return sh;
+}
+
 // ------------------------------------------------------------- ||b||^2 ----
 template <typename T>
 __global__ __launch_bounds__(NT) void k_norm_b(const cx<T>* __restrict__ b,
@@ -127,8 +138,8 @@ __global__ __launch_bounds__(NT) void k_fin_reset(BicgSlot* st, const int* act, 
 // so every block gets the same value); block 0 stores it in the slot state.
 // Rows read and rows written by one kernel never overlap, and no block reads
 // a state field that another block of the same kernel writes, except the
-// status: a block that sees the status another block just set takes the
-// decision that block took.
+// status: it is read once per block (block_status), and a block that sees
+// the status another block just set takes the decision that block took.
 
 // Sums K rows at OFF for `slot` and returns the totals in every thread.
 template <int K, int OFF>
@@ -171,7 +182,7 @@ __global__ __launch_bounds__(NT) void k_update_p(const cx<T>* __restrict__ r, cx
                                                  RedScratch red, int nblk) {
     SLOT_PROLOGUE
     BicgSlot& S = st[slot];
-    const int status = S.status;
+    const int status = block_status(S);
     z128 rho;
     if constexpr (FIN) {
         if (status != SLOT_ACTIVE && status != SLOT_HALF) return;  // uniform per block
@@ -200,7 +211,7 @@ __global__ __launch_bounds__(NT) void k_update_s(const cx<T>* __restrict__ r,
                                                  int64_t nv, RedScratch red, int nblk_mv) {
     SLOT_PROLOGUE
     BicgSlot& S = st[slot];
-    if (S.status != SLOT_ACTIVE) return;
+    if (block_status(S) != SLOT_ACTIVE) return;
     double rv[2];
     slot_totals<2, 0>(red, slot, nblk_mv, rv);
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
@@ -236,7 +247,7 @@ __global__ __launch_bounds__(NT) void k_update_xr(cx<T>* __restrict__ x, cx<T>* 
                                                   RedScratch red, int nblk_mv) {
     SLOT_PROLOGUE
     BicgSlot& S = st[slot];
-    const int status = S.status;
+    const int status = block_status(S);
     if (status != SLOT_ACTIVE && status != SLOT_HALF) return;
     const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
     z128 om{0.0, 0.0};
@@ -333,7 +344,7 @@ __global__ __launch_bounds__(NT) void k_cocg_xr(cx<T>* __restrict__ x, cx<T>* __
                                                 const int* __restrict__ act, int64_t nv,
                                                 RedScratch red, int nblk_mu) {
     SLOT_PROLOGUE
-    if (st[slot].status != SLOT_ACTIVE) return;
+    if (block_status(st[slot]) != SLOT_ACTIVE) return;
     __shared__ double mu_sh[2];
     {
         double mu[2];
