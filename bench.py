@@ -346,7 +346,7 @@ def measure_extras(torch, W, DDASolver, log):
                                   "solves": len(lat), "precision": "fp64", "solver": "bicgstab"}
     log(f"c1 latency p50 {res['solve_latency_c1_ms']['p50']} ms")
     # the same solve with FP64 COCG (device-driven intervals, captured graphs)
-    s1 = DDASolver(w1.mask, w1.d, w1.m_h, tol=w1.tol, solver="cocg", check_every=8)
+    s1 = DDASolver(w1.mask, w1.d, w1.m_h, tol=w1.tol, solver="cocg")
     lat = []
     for i in range(11):
         s1.drop_cache()
