@@ -121,6 +121,8 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 256 MiB device copy (for scaling rocprofv3 "
                          "FETCH_SIZE/WRITE_SIZE counters)")
+    ap.add_argument("--latency-only", action="store_true",
+                    help="only the c1 single-solve latency lines (FP64 BiCGStab and COCG)")
     ap.add_argument("--matvec64-only", action="store_true",
                     help="measure only the 64^3 FFT matvec (one JSON line) and exit")
     args = ap.parse_args()
@@ -139,6 +141,10 @@ def main():
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
 
+    if args.latency_only:
+        log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
+        print(json.dumps(measure_latency(torch, W, DDASolver, log)), flush=True)
+        return
     if args.matvec64_only:
         log = lambda *a: print(*a, file=sys.stderr, flush=True)  # noqa: E731
         if args.calibrate_copy:
@@ -327,6 +333,14 @@ def measure_matvec64(torch, W, DDASolver, log):
 def measure_extras(torch, W, DDASolver, log):
     """FFT matvec GB/s on the 64^3 lattice and single-solve latency (c1)."""
     res = {"matvec_64cubed": measure_matvec64(torch, W, DDASolver, log)}
+    res.update(measure_latency(torch, W, DDASolver, log))
+    return res
+
+
+def measure_latency(torch, W, DDASolver, log):
+    """Single-solve latency percentiles on c1 (16^3 sphere, one energy, FP64
+    to 1e-10): BiCGStab as specified, and COCG."""
+    res = {}
     # single-solve latency, c1 (FP64 BiCGStab to 1e-10), 10 solves
     w1 = W.c1_single_solve()
     s1 = DDASolver(w1.mask, w1.d, w1.m_h, tol=w1.tol, solver="bicgstab")
