@@ -129,9 +129,9 @@ __global__ __launch_bounds__(NT) void k_fin_reset(BicgSlot* st, const int* act, 
 // whose pack kernels write the dot products of their output:
 //   update_p  [FIN: sums the rows at 0..2 of the previous update_xr]
 //   v = A p   (pack rows of <rhat, v> at 0..1)
-//   update_s  (sums those rows -> alpha; writes ||s||^2 rows at 2)
+//   update_s  (sums those rows -> alpha; writes ||s||^2 rows at 6)
 //   t = A s   (pack rows of <t, s>, ||t||^2 at 3..5)
-//   update_xr (sums row 2 -> the half-step test, rows 3..5 -> omega; writes
+//   update_xr (sums row 6 -> the half-step test, rows 3..5 -> omega; writes
 //              <rhat, r>, ||r||^2 rows at 0..2)
 // and k_fin_xr closes the last iteration of an interval.  A kernel that
 // needs a scalar sums the rows itself in every block (the same fixed order,
@@ -234,7 +234,7 @@ __global__ __launch_bounds__(NT) void k_update_s(const cx<T>* __restrict__ r,
         sv[base + i] = si;
         s[0] += double(norm2(si));
     }
-    block_partial<1, NT, 2>(s, red, slot, blockIdx.x);
+    block_partial<1, NT, 6>(s, red, slot, blockIdx.x);
 }
 
 template <typename T>
@@ -253,7 +253,7 @@ __global__ __launch_bounds__(NT) void k_update_xr(cx<T>* __restrict__ x, cx<T>* 
     z128 om{0.0, 0.0};
     if (status == SLOT_ACTIVE) {
         double ss[1];
-        slot_totals<1, 2>(red, slot, gridDim.x, ss);
+        slot_totals<1, 6>(red, slot, gridDim.x, ss);
         if (ss[0] <= S.tol2 * S.bnorm2) {  // ||s|| met the tolerance: x += alpha p ends the solve
             if (lead) {
                 S.omega = om;
