@@ -108,7 +108,7 @@ typedef struct {
 typedef struct {
     double p_eels;  /* particle-induced loss probability, eqs. (32), (34), (37)   */
     double p_ext;   /* extinction probability, eqs. (17), (48)                    */
-    double p_abs;   /* absorption probability, eq. (18) / discrete DDA absorption */
+    double p_abs;   /* absorption probability, eq. (18) in discrete form          */
     double p_cl;    /* cathodoluminescence probability, eq. (42)                  */
 } dda_result;
 
@@ -233,8 +233,14 @@ int dda_solve(dda_ctx* ctx, int n_energy, const double* energy_eV, const double*
  *   P_EELS = -Pi Im[ sum_i g_i . p_i / (m_h gamma_h)^2 ],  g the auxiliary
  *            field of the conjugate source, eq. (34), built on the fly;
  *   P_ext  =  Pi Im[ m_h^2 sum_i conj(e_i) . p_i ] / (|m_h|^4 |gamma_h|^2);
- *   P_abs  =  real m_h: Pi/(m_h^2|gamma_h|^2) sum_i [-Im(1/alpha_i) - 2k^3/3]|p_i|^2;
- *             complex m_h: eq. (18) with P = (eps - eps_h) E per cell;
+ *   P_abs  =  Pi/(|m_h|^4|gamma_h|^2) sum_i w_i |p_i|^2, one formula for every host:
+ *             w_i = 4 pi Im(m_h^2 m_i^2)/(|m_i^2 - 1|^2 d^3)      (eq. 18 with the
+ *                   cell field of eq. 7, E_i = 4 pi p_i/((m_i^2 - 1) d^3))
+ *                 + Im(m_h^2 conj(1/alpha_i - 1/alpha_CM,i))  (the polarizability's
+ *                   change to the exciting field's work)
+ *                 - Re(m_h^2) (2/3) Re(k)^3                   (self-radiated part);
+ *             continuous in m_h; in a real host m_h^2 [-Im(1/alpha_i) - 2k^3/3], so
+ *             that P_ext = P_abs + P_CL exactly there;
  *   P_CL   =  Pi Re(m_h^2)/(|m_h|^4|gamma_h|^2) [Im(p^H G_off p) + 2 Re(k)^3 ||p||^2/3]
  *             (eq. 42; nominal in an absorbing host),
  *   Pi = 4 alpha_fs k0^2 / (pi hbar c beta^4).

@@ -24,7 +24,8 @@ What it computes, step by step, each function citing the passage it follows:
                       large to store the matrix.
 * solve.py         -- dense LU for small systems, BiCGStab otherwise.
 * losses.py        -- P_EELS (eqs. 32, 34, 37, 38), P_ext (eqs. 17, 48),
-                      P_abs (eq. 18 / the DDA's discrete absorption) and P_CL
+                      P_abs (eq. 18 with the cell field, in the discrete
+                      form that closes the real-host budget) and P_CL
                       (eq. 42).
 * dda.py           -- the whole path for one (energy, trajectory).
 

@@ -1906,7 +1906,6 @@ int dda_eels_cl(dda_ctx* c, int n_energy, const double* energy_eV, double beta,
     check_beta(c, beta);
     const cplx gam = gamma_h_of(beta, c->mh);
     const cplx mh = c->mh;
-    const bool real_host = mh.imag() == 0.0;
     const int64_t n = c->g.n_occ, nv = c->nv();
     const int spc = systems_per_chunk(c, n_energy, n_traj, false);
     for (int e0 = 0; e0 < n_energy; e0 += spc) {
@@ -1960,8 +1959,7 @@ int dda_eels_cl(dda_ctx* c, int n_energy, const double* energy_eV, double beta,
             dda_result r;
             r.p_eels = -Pi * (Sa / ((mh * gam) * (mh * gam))).imag();
             r.p_ext = Pi * (mh * mh * Se).imag() / (mh4 * g2);
-            if (real_host) r.p_abs = Pi / (mh.real() * mh.real() * g2) * Sw;
-            else r.p_abs = Pi / (mh4 * g2) * Sw;
+            r.p_abs = Pi / (mh4 * g2) * Sw;
             const double kr = (mh * k0).real();
             r.p_cl = Pi * (mh * mh).real() / (mh4 * g2) * (Spy.imag() + (2.0 / 3.0) * kr * kr * kr * Spp);
             out[int64_t(e0) * n_traj + i] = r;

@@ -9,9 +9,14 @@
 //   LDR: alpha_CM / (1 + (alpha_CM/d^3) [(b1 + m^2 b2) (kd)^2 - (2/3) i (kd)^3])
 //        (Draine & Goodman 1993 with S = 0 for propagation along z)
 // with k = m_h omega/c the host wavenumber; m_h and k are per system.
-// Absorption weights w_i, used as P_abs ~ sum_i w_i |p_i|^2:
-//   real host:    w = -Im(1/alpha) - (2/3) k^3   (radiative part removed)
-//   complex host: w = 4 pi Im(m_h^2 m^2) / (|m^2 - 1|^2 d^3)   (eq. 18)
+// Absorption weight w_i, used as P_abs ~ sum_i w_i |p_i|^2 / |m_h|^4: eq. (18)
+// with the cell field of eq. (7), E_i = 4 pi p_i / ((m^2 - 1) d^3), plus the
+// change the polarizability prescription makes to the exciting field's work
+// on the dipole and less the nominal self-radiated power,
+//   w = 4 pi Im(m_h^2 m^2) / (|m^2 - 1|^2 d^3)
+//       + Im(m_h^2 conj(1/alpha - 1/alpha_CM)) - Re(m_h^2) (2/3) Re(k)^3,
+// one formula for every host (in a real host it is m_h^2 times Draine's
+// discrete absorption -Im(1/alpha) - (2/3) k^3).
 #include <algorithm>
 
 #include "kernels.h"
@@ -76,13 +81,12 @@ __global__ __launch_bounds__(256) void k_material(const z128* __restrict__ eps,
         if (ainv128) ainv128[o] = ai;
         if (ainv64) ainv64[o] = cvt<float>(ai);
         if (w) {
-            if (mh.y == 0.0) {
-                const double kr = k.x;
-                w[o] = -ai.y - (2.0 / 3.0) * kr * kr * kr;
-            } else {
-                const z128 dm = m2 - one;
-                w[o] = 4.0 * kPi * (mh2 * m2).y / ((dm.x * dm.x + dm.y * dm.y) * d3);
-            }
+            const z128 dm = m2 - one;
+            const double w18 = 4.0 * kPi * (mh2 * m2).y / ((dm.x * dm.x + dm.y * dm.y) * d3);
+            const z128 aicm = (4.0 * kPi / (3.0 * d3)) * cdiv(m2 + z128{2.0, 0.0}, dm);
+            const z128 dc{ai.x - aicm.x, aicm.y - ai.y};  // conj(1/alpha - 1/alpha_CM)
+            const double kr = k.x;
+            w[o] = w18 + (mh2 * dc).y - mh2.x * (2.0 / 3.0) * kr * kr * kr;
         }
     }
 }

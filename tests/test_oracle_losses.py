@@ -165,3 +165,129 @@ def test_reciprocity_of_solutions():
     x1 = np.linalg.solve(A, e1.ravel())
     x2 = np.linalg.solve(A, e2.ravel())
     assert np.sum(e2.ravel() * x1) == pytest.approx(np.sum(e1.ravel() * x2), rel=1e-12)
+
+
+# ---------------------------------------------------------------- P_abs ----
+# P_abs is one formula for every host (eq. 18 with the cell relation of
+# eq. 7, plus the polarizability's corrections).  These pins fix it from
+# outside the formula: continuity across the real axis of m_h, the
+# coincidences with eq. (18) written out from the cell field, and the
+# closed-form budget defect in an absorbing host.
+
+def _lu_point(pol, m_h, eps=-10.0 + 1.0j, beta=0.55, E=2.5, n=6, d=2.0):
+    mask = sphere_mask(n, d, n * d / 2)
+    r0 = (n * d / 2 + 2.0, 0.3, 0.0)
+    nn = int(mask.sum())
+    return solve_point(mask, d, [eps] * nn, m_h, beta, r0, E, pol=pol, method="lu"), mask, d
+
+
+@pytest.mark.parametrize("pol", ["ldr", "cm", "rr"])
+def test_p_abs_and_p_cl_continuous_across_the_real_axis(pol):
+    """Im m_h -> 0+ changes every probability by O(Im m_h): the absorbing-host
+    branch of P_abs and of the nominal P_CL joins the real-host one (the
+    earlier split jumped by 6e-4 relative with LDR)."""
+    a, _, _ = _lu_point(pol, 1.45)
+    b, _, _ = _lu_point(pol, 1.45 + 1e-10j)
+    for f in ["p_eels", "p_ext", "p_abs", "p_cl"]:
+        assert getattr(b, f) == pytest.approx(getattr(a, f), rel=1e-8), f
+    # and the discrete budget holds in that limit
+    assert b.p_abs + b.p_cl == pytest.approx(b.p_ext, rel=1e-8)
+
+
+def _eq18_cell_form(res, mask, d, eps, m_h, beta, E):
+    """Eq. (18) written out: W_abs ~ sum over cells of Im(eps_p) |E_i|^2 d^3 with
+    E_i from P = (eps_p - eps_h) E (eq. 7), in the units of P_* (1/eV)."""
+    mh = complex(m_h)
+    m2 = eps / mh ** 2
+    p = res.p_hat
+    E_cell = 4.0 * np.pi * p / ((m2 - 1.0) * d ** 3)           # field per cell
+    s = np.sum(np.imag(eps) * np.sum(np.abs(E_cell) ** 2, axis=1)) * d ** 3 / (4.0 * np.pi)
+    g = el.gamma_h(beta, m_h)
+    Pi = 4 * ALPHA * (E / HBARC) ** 2 / (np.pi * HBARC * beta ** 4)
+    return Pi * s / (abs(mh) ** 4 * abs(g) ** 2)
+
+
+def test_p_abs_rr_real_host_is_eq18():
+    """With the radiative-reaction polarizability in a real host the dipole's
+    work less its radiation is exactly the cell form of eq. (18)."""
+    eps, m_h, beta, E = -10.0 + 1.0j, 1.45, 0.55, 2.5
+    res, mask, d = _lu_point("rr", m_h, eps=eps, beta=beta, E=E)
+    ref = _eq18_cell_form(res, mask, d, eps, m_h, beta, E)
+    assert res.p_abs == pytest.approx(ref, rel=1e-11)
+
+
+@pytest.mark.parametrize("m_h", [1.45, 2.0 + 0.01j, 1.3 + 0.2j])
+def test_p_abs_cm_is_eq18_less_self_radiation(m_h):
+    """Clausius-Mossotti has no radiative correction: P_abs is eq. (18)'s cell
+    form less the nominal self-radiated power (2/3) Re(k)^3 ||p||^2 weighted
+    by Re(m_h^2), on real and absorbing hosts."""
+    eps, beta, E = -10.0 + 1.0j, 0.55, 2.5
+    res, mask, d = _lu_point("cm", m_h, eps=eps, beta=beta, E=E)
+    ref = _eq18_cell_form(res, mask, d, eps, m_h, beta, E)
+    mh = complex(m_h)
+    kr = (mh * E / HBARC).real
+    g = el.gamma_h(beta, m_h)
+    Pi = 4 * ALPHA * (E / HBARC) ** 2 / (np.pi * HBARC * beta ** 4)
+    rad = Pi * (mh * mh).real / (abs(mh) ** 4 * abs(g) ** 2) * (2.0 / 3.0) * kr ** 3 * \
+        np.sum(np.abs(res.p_hat) ** 2)
+    assert res.p_abs == pytest.approx(ref - rad, rel=1e-11)
+
+
+@pytest.mark.parametrize("m_h", [1.45, 2.0 + 0.01j])
+def test_p_abs_ldr_tends_to_eq18_as_d_shrinks(m_h):
+    """The LDR corrections to the weight are O((kd)^2): halving d at fixed k
+    divides their share of the eq. (18) weight by about four."""
+    from oracle.losses import absorption_weight
+    from oracle.polarizability import alpha_ldr
+    eps, E = np.array([-10.0 + 1.0j, 3.0 + 0.5j]), 2.5
+    mh = complex(m_h)
+    m2 = eps / mh ** 2
+    k = mh * E / HBARC
+    shares = []
+    for d in [2.0, 1.0, 0.5, 0.25]:
+        w = absorption_weight(alpha_ldr(m2, d, k), m2, d, E, m_h)
+        w18 = 4.0 * np.pi * np.imag(mh * mh * m2) / (np.abs(m2 - 1.0) ** 2 * d ** 3)
+        shares.append(np.abs(w / w18 - 1.0))
+    for a, b in zip(shares, shares[1:]):
+        assert np.all(b < a / 3.5) and np.all(b > a / 4.5)
+
+
+@pytest.mark.parametrize("pol,m_h", [("ldr", 2.0 + 0.01j), ("cm", 1.3 + 0.2j), ("rr", 1.5 + 0.05j)])
+def test_absorbing_host_budget_defect_closed_form(pol, m_h):
+    """In an absorbing host P_ext - P_abs - P_CL is not zero; from A p = e it
+    equals Pi Im(m_h^2)/(|m_h|^4 |gamma_h|^2) [(4 pi/d^3) sum_i (1/3 -
+    1/|m_i^2-1|^2) |p_i|^2 - Re(p^H G_off p)], with G_off from the explicit
+    interaction matrix here."""
+    from oracle.interaction import interaction_matrix
+    eps, beta, E = -10.0 + 1.0j, 0.6, 2.5
+    res, mask, d = _lu_point(pol, m_h, eps=eps, beta=beta, E=E)
+    mh = complex(m_h)
+    centres, _, k, m2 = system(mask, d, [eps] * int(mask.sum()), m_h, E, pol)
+    G = interaction_matrix(centres, k)
+    p = res.p_hat.ravel()
+    X = np.vdot(p, G @ p)
+    p2 = np.sum(np.abs(res.p_hat) ** 2, axis=1)
+    g = el.gamma_h(beta, m_h)
+    Pi = 4 * ALPHA * (E / HBARC) ** 2 / (np.pi * HBARC * beta ** 4)
+    defect = Pi * (mh * mh).imag / (abs(mh) ** 4 * abs(g) ** 2) * (
+        4.0 * np.pi / d ** 3 * np.sum((1.0 / 3.0 - 1.0 / np.abs(m2 - 1.0) ** 2) * p2) - X.real)
+    assert res.p_ext - res.p_abs - res.p_cl == pytest.approx(defect, rel=1e-9, abs=1e-12 * abs(res.p_ext))
+    assert abs(defect) > 1e-6 * abs(res.p_ext)  # the case does test something
+
+
+def test_dense_rows_equal_rows_of_the_full_product():
+    """oracle_dense_matvec_rows (the reference of the sampled full-size GPU
+    checks) returns exactly the chosen rows of the full C product, for both
+    modes and an absorbing host."""
+    from oracle import cdense
+    rng = np.random.default_rng(7)
+    for n, k in [(50, 0.05), (173, 0.04 + 0.003j)]:
+        c = rng.uniform(-6, 6, size=(n, 3))
+        alpha = rng.uniform(0.1, 1, n) + 1j * rng.uniform(0, 1, n)
+        x = rng.standard_normal((n, 3)) + 1j * rng.standard_normal((n, 3))
+        rows = np.sort(rng.choice(n, size=min(n, 37), replace=False))
+        rows = np.concatenate([rows, [0, n - 1]])
+        for io in (False, True):
+            full = cdense.matvec(c, alpha, k, x, interaction_only=io)
+            part = cdense.matvec_rows(c, alpha, k, x, rows, interaction_only=io)
+            assert np.array_equal(part, full[rows])
