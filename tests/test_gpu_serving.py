@@ -141,3 +141,32 @@ def test_served_requests_equal_their_spectra_alone(precision):
         alone.close()
         assert [i.iters for i in info] == [i[0] for i in c.info], c.rid
         assert np.allclose(c.P, P, rtol=1e-13, atol=0), (c.rid, c.P, P)
+
+
+@pytest.mark.parametrize("precision,bar", [("mixed", 1e-5), ("fp64", 1e-9)])
+def test_served_requests_match_the_oracle(precision, bar):
+    """Every served spectrum point (two lattices, four hosts including an
+    absorbing Cherenkov one, requests overlapping in the slots) against the
+    FP64 CPU oracle's dense LU solve of the same point."""
+    from oracle.dda import solve_point
+    say("serving vs oracle", precision)
+    reqs = _requests()
+    srv = Server(hbm_budget_bytes=64 << 30, slots=8, precision=precision,
+                 tol=1e-12 if precision == "fp64" else 1e-10, maxit=20000, check_every=4)
+    comps, _, _ = replay(srv, reqs, timeout_s=240)
+    srv.close()
+    assert len(comps) == len(reqs)
+    worst = 0.0
+    for c in comps:
+        r = reqs[c.rid]
+        n = int(np.asarray(r.mask).sum())
+        for ie, E in enumerate(r.energies):
+            ref = solve_point(r.mask, r.d, np.full(n, r.eps[ie]), r.m_h, r.beta, r.r0, float(E),
+                              method="lu")
+            vals = [ref.p_eels, ref.p_ext, ref.p_abs, ref.p_cl]
+            scale = max(abs(v) for v in vals)
+            for g, v in zip(c.P[ie], vals):
+                err = abs(g - v) / max(abs(v), 1e-3 * scale)
+                worst = max(worst, err)
+                assert err <= bar, (c.rid, E, g, v, err)
+    say(f"  worst relative error {worst:.2e}")
