@@ -212,6 +212,26 @@ int dda_einc_electron(dda_ctx* ctx, int n_energy, const double* energy_eV, doubl
                       const double* r0_nm, int n_traj, void* einc_dev);
 
 /*
+ * dda_einc_electron for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, checks and result, bit for bit: the energies
+ * and trajectory points are staged in a device array the library holds on
+ * every GPU it runs on (288 KiB, set up once per device by dda_setup, kept
+ * until the process ends) instead of a buffer of the context, and the call
+ * makes no device allocation, free or allocating library call.
+ * Limits: n_energy <= DDA_EINC_NOALLOC_MAX_ENERGIES and n_traj <=
+ * DDA_EINC_NOALLOC_MAX_TRAJ per call, else DDA_EINVAL.
+ * Every call on one GPU shares that array: calls that overlap on one GPU
+ * (from several threads) race on it and must be serialised by the caller.
+ * Like dda_einc_electron it returns after the context's stream has passed the
+ * call.
+ */
+#define DDA_EINC_NOALLOC_MAX_ENERGIES 4096
+#define DDA_EINC_NOALLOC_MAX_TRAJ 4096
+int dda_einc_electron_noalloc(dda_ctx* ctx, int n_energy, const double* energy_eV, double beta,
+                              const double* r0_nm, int n_traj, void* einc_dev);
+
+/*
  * Solves A p_hat = e_hat for every right-hand side of a batch:
  *   (A p)_i = p_i / alpha_i - sum_{j != i} G(r_i - r_j) p_j,
  *   G(R) = (k^2 I + grad grad) exp(ikR)/R (eq. 5 times 4 pi k^2),

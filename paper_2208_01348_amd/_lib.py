@@ -22,7 +22,7 @@ DDA_PREC_FP64, DDA_PREC_MIXED = 0, 1
 
 # every symbol include/dda.h declares
 EXPORTED = ["dda_default_options", "dda_beta_from_keV", "dda_setup", "dda_n_occ",
-            "dda_grid_dims", "dda_einc_electron", "dda_solve", "dda_eels_cl", "dda_matvec",
+            "dda_grid_dims", "dda_einc_electron", "dda_einc_electron_noalloc", "dda_solve", "dda_eels_cl", "dda_matvec",
             "dda_set_timing", "dda_kernel_time", "dda_drop_cache", "dda_destroy",
             "dda_last_error", "dda_debug_besselk01", "dda_workspace_bytes", "dda_engine_open",
             "dda_engine_submit", "dda_engine_poll", "dda_engine_status", "dda_engine_close",
@@ -77,6 +77,7 @@ def load() -> ctypes.CDLL:
         "dda_n_occ": (_i, [_vp, _vp]),
         "dda_grid_dims": (_i, [_vp, _vp, _vp, _vp]),
         "dda_einc_electron": (_i, [_vp, _i, _vp, _d, _vp, _i, _vp]),
+        "dda_einc_electron_noalloc": (_i, [_vp, _i, _vp, _d, _vp, _i, _vp]),
         "dda_solve": (_i, [_vp, _i, _vp, _vp, _vp, _i, _vp, _vp]),
         "dda_eels_cl": (_i, [_vp, _i, _vp, _d, _vp, _vp, _i, _vp, _vp, _vp]),
         "dda_matvec": (_i, [_vp, _d, _vp, _i, _i, _vp, _vp, _i]),
@@ -270,6 +271,17 @@ def dda_einc_electron(ctx, energy_eV, beta: float, r0_nm, einc_dev: int) -> None
     R = _f64(r0_nm).reshape(-1, 3)
     _check(load().dda_einc_electron(ctx, E.size, _ptr(E), float(beta), _ptr(R), R.shape[0],
                                     ctypes.c_void_p(einc_dev)))
+
+
+DDA_EINC_NOALLOC_MAX_ENERGIES = 4096
+DDA_EINC_NOALLOC_MAX_TRAJ = 4096
+
+
+def dda_einc_electron_noalloc(ctx, energy_eV, beta: float, r0_nm, einc_dev: int) -> None:
+    E = _f64(energy_eV).ravel()
+    R = _f64(r0_nm).reshape(-1, 3)
+    _check(load().dda_einc_electron_noalloc(ctx, E.size, _ptr(E), float(beta), _ptr(R),
+                                            R.shape[0], ctypes.c_void_p(einc_dev)))
 
 
 def dda_solve(ctx, energy_eV, eps_dipole, einc_dev: int, n_traj: int, p_dev: int,

@@ -257,6 +257,8 @@ struct dda_ctx {
     dda_options opt{};
     hipStream_t stream = nullptr;
     std::vector<int> occ_lin;  // host copy
+    std::vector<char> occ_col;  // [ny][nx]: the (x, y) column holds a dipole
+    int device = 0;             // the device current at dda_setup
     DevBuf map, occ;
     DevBuf tw128[3], tw64[3];
     std::map<std::pair<double, double>, std::unique_ptr<DEntry>> dcache;
@@ -1104,14 +1106,11 @@ size_t slot_bytes(const dda_ctx* c, bool mixed) {
 
 void host_trajectory_check(const dda_ctx* c, const double* r0, int n_traj) {
     const dda::Geo& g = c->g;
-    // occupied (x, y) columns
-    std::vector<char> col(size_t(g.nx) * g.ny, 0);
-    for (int lin : c->occ_lin) col[lin % (g.nx * g.ny)] = 1;
     for (int t = 0; t < n_traj; ++t) {
         for (int q = 0; q < 3; ++q) check_finite(r0[3 * t + q], "trajectory coordinate");
         for (int iy = 0; iy < g.ny; ++iy)
             for (int ix = 0; ix < g.nx; ++ix) {
-                if (!col[size_t(iy) * g.nx + ix]) continue;
+                if (!c->occ_col[size_t(iy) * g.nx + ix]) continue;
                 const double px = c->d * (ix - 0.5 * g.nx + 0.5);
                 const double py = c->d * (iy - 0.5 * g.ny + 0.5);
                 if (std::hypot(px - r0[3 * t], py - r0[3 * t + 1]) < 1e-9 * c->d)
@@ -1696,6 +1695,10 @@ int dda_setup(const uint8_t* mask, int nx, int ny, int nz, double d_nm, double m
         }
     }
     g.n_occ = int64_t(c->occ_lin.size());
+    c->occ_col.assign(size_t(nx) * ny, 0);
+    for (int lin : c->occ_lin) c->occ_col[size_t(lin % (nx * ny))] = 1;
+    DDA_HIP_CHECK(hipGetDevice(&c->device));
+    dda::einc_scratch_init();  // the no-alloc staging area of this device
     c->max_blocks = std::max(1024, std::max(dda::pack_blocks_per_slot(g),
                                             std::max(dda::yz_pack_blocks_per_slot(g, 8),
                                                      dda::yz_pack_blocks_per_slot(g, 16))));
@@ -1766,36 +1769,75 @@ int dda_grid_dims(const dda_ctx* ctx, int* mx, int* my, int* mz) {
     return DDA_OK;
 }
 
-int dda_einc_electron(dda_ctx* c, int n_energy, const double* energy_eV, double beta,
-                      const double* r0_nm, int n_traj, void* einc_dev) {
-    DDA_API_BEGIN
+namespace {
+
+// Checks the arguments of an electron-field call; false when there is
+// nothing to compute.
+bool einc_args(dda_ctx* c, int n_energy, const double* energy_eV, double beta,
+               const double* r0_nm, int n_traj, void* einc_dev) {
     if (!c) throw Error(DDA_EINVAL, "ctx is NULL");
     if (n_energy < 0 || n_traj < 0) throw Error(DDA_EINVAL, "negative batch size");
-    if (n_energy == 0 || n_traj == 0 || c->g.n_occ == 0) return DDA_OK;
+    if (n_energy == 0 || n_traj == 0 || c->g.n_occ == 0) return false;
     if (!energy_eV || !r0_nm || !einc_dev) throw Error(DDA_EINVAL, "NULL argument");
     check_energies(n_energy, energy_eV);
     check_beta(c, beta);
     host_trajectory_check(c, r0_nm, n_traj);
+    return true;
+}
+
+// Eq. (25) at every dipole through a device staging area: the energies and
+// trajectory points are copied in, the per-energy constants derived on the
+// device, then the field kernel runs.  Returns after the stream has passed
+// the call, so the caller's host arrays and the staging area are free again.
+void einc_staged(dda_ctx* c, int n_energy, const double* energy_eV, double beta,
+                 const double* r0_nm, int n_traj, void* einc_dev, const dda::EincStage& st) {
     const cplx gam = gamma_h_of(beta, c->mh);
-    std::vector<dda::EincSys> sys(n_energy);
-    for (int e = 0; e < n_energy; ++e) {
-        const double k0 = energy_eV[e] / kHbarC;
-        const cplx kt = k0 / (beta * gam);
-        const cplx ig = cplx(0.0, -1.0) / gam;
-        sys[e] = dda::EincSys{k0, kt.real(), kt.imag(), ig.real(), ig.imag()};
-    }
-    const size_t sb = sys.size() * sizeof(dda::EincSys), rb = size_t(n_traj) * 3 * sizeof(double);
-    c->misc.ensure(sb + rb + 64);
-    char* base = c->misc.as<char>();
-    DDA_HIP_CHECK(hipMemcpyAsync(base, sys.data(), sb, hipMemcpyHostToDevice, c->stream));
-    DDA_HIP_CHECK(hipMemcpyAsync(base + sb, r0_nm, rb, hipMemcpyHostToDevice, c->stream));
-    dda::launch_einc(static_cast<z128*>(einc_dev), c->occ.as<int>(), c->g, c->d, beta,
-                     reinterpret_cast<dda::EincSys*>(base), reinterpret_cast<double*>(base + sb),
-                     n_energy, n_traj, c->stream);
-    DDA_HIP_CHECK(hipStreamSynchronize(c->stream));  // host vectors go out of scope
+    const cplx ibg = 1.0 / (beta * gam);
+    const cplx ig = cplx(0.0, -1.0) / gam;
+    DDA_HIP_CHECK(hipMemcpyAsync(st.energy, energy_eV, size_t(n_energy) * sizeof(double),
+                                 hipMemcpyHostToDevice, c->stream));
+    DDA_HIP_CHECK(hipMemcpyAsync(st.r0, r0_nm, size_t(n_traj) * 3 * sizeof(double),
+                                 hipMemcpyHostToDevice, c->stream));
+    dda::launch_einc_prep(st.energy, st.sys, n_energy, kHbarC, z128{ibg.real(), ibg.imag()},
+                          z128{ig.real(), ig.imag()}, c->stream);
+    dda::launch_einc(static_cast<z128*>(einc_dev), c->occ.as<int>(), c->g, c->d, beta, st.sys,
+                     st.r0, n_energy, n_traj, c->stream);
+    DDA_HIP_CHECK(hipStreamSynchronize(c->stream));
+}
+
+}  // namespace
+
+int dda_einc_electron(dda_ctx* c, int n_energy, const double* energy_eV, double beta,
+                      const double* r0_nm, int n_traj, void* einc_dev) {
+    DDA_API_BEGIN
+    if (!einc_args(c, n_energy, energy_eV, beta, r0_nm, n_traj, einc_dev)) return DDA_OK;
+    c->misc.ensure(dda::einc_stage_bytes(size_t(n_energy), size_t(n_traj)));
+    einc_staged(c, n_energy, energy_eV, beta, r0_nm, n_traj, einc_dev,
+                dda::einc_stage_layout(c->misc.p, size_t(n_energy)));
     return DDA_OK;
     DDA_API_END
 }
+
+int dda_einc_electron_noalloc(dda_ctx* c, int n_energy, const double* energy_eV, double beta,
+                              const double* r0_nm, int n_traj, void* einc_dev) {
+    DDA_API_BEGIN
+    if (!einc_args(c, n_energy, energy_eV, beta, r0_nm, n_traj, einc_dev)) return DDA_OK;
+    if (n_energy > DDA_EINC_NOALLOC_MAX_ENERGIES || n_traj > DDA_EINC_NOALLOC_MAX_TRAJ)
+        throw Error(DDA_EINVAL, "dda_einc_electron_noalloc: at most " +
+                                    std::to_string(DDA_EINC_NOALLOC_MAX_ENERGIES) +
+                                    " energies and " + std::to_string(DDA_EINC_NOALLOC_MAX_TRAJ) +
+                                    " trajectories per call");
+    void* base = dda::einc_scratch(c->device);
+    if (!base) throw Error(DDA_EDEVICE, "no-alloc staging area not set up on this device");
+    einc_staged(c, n_energy, energy_eV, beta, r0_nm, n_traj, einc_dev,
+                dda::einc_stage_layout(base, size_t(DDA_EINC_NOALLOC_MAX_ENERGIES)));
+    return DDA_OK;
+    DDA_API_END
+}
+
+static_assert(DDA_EINC_NOALLOC_MAX_ENERGIES == dda::kEincNoallocMaxEnergies &&
+                  DDA_EINC_NOALLOC_MAX_TRAJ == dda::kEincNoallocMaxTraj,
+              "header and library agree on the no-alloc limits");
 
 int dda_solve(dda_ctx* c, int n_energy, const double* energy_eV, const double* eps_dipole,
               const void* einc_dev, int n_traj, void* p_dev, dda_solve_info* info) {

@@ -19,6 +19,8 @@
 //    s^2 = -2z), so the rule converges geometrically; both functions share
 //    the one square root per node.  Relative error < 1e-15 over
 //    1e-4 <= |z| <= 60, -pi/2 <= arg z <= 0.
+#include <mutex>
+
 #include "kernels.h"
 
 namespace dda {
@@ -143,6 +145,54 @@ void launch_einc(z128* einc, const int* occ_lin, const Geo& g, double d, double 
     k_einc<<<dim3(unsigned(bpr * nrhs)), 256, 0, s>>>(einc, occ_lin, g, d, beta, sys, r0, n_traj,
                                                       bpr);
     DDA_LAUNCH_CHECK();
+}
+
+__global__ __launch_bounds__(256) void k_einc_prep(const double* __restrict__ energy,
+                                                   EincSys* __restrict__ sys, int n, double hbar_c,
+                                                   z128 inv_bg, z128 ig) {
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= n) return;
+    const double k0 = energy[e] / hbar_c;
+    sys[e] = EincSys{k0, k0 * inv_bg.x, k0 * inv_bg.y, ig.x, ig.y};
+}
+
+void launch_einc_prep(const double* energy, EincSys* sys, int n, double hbar_c, z128 inv_bg,
+                      z128 ig, hipStream_t s) {
+    if (n <= 0) return;
+    k_einc_prep<<<unsigned((n + 255) / 256), 256, 0, s>>>(energy, sys, n, hbar_c, inv_bg, ig);
+    DDA_LAUNCH_CHECK();
+}
+
+// Staging area of dda_einc_electron_noalloc.  In host code `scratch` names a
+// host-side stand-in, not the device array: host code uses only the address
+// that hipGetSymbolAddress returns for the current device.
+constexpr size_t kEincScratchBytes =
+    einc_stage_bytes(kEincNoallocMaxEnergies, kEincNoallocMaxTraj);
+static __device__ __align__(256) unsigned char scratch[kEincScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+void einc_scratch_init() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        throw Error(-3, "einc scratch: no current device");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[dev]) return;
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+        throw Error(-3, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+}
+
+void* einc_scratch(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[device];
 }
 
 __global__ void k_besselk01(const z128* __restrict__ z, z128* __restrict__ k0,

@@ -168,6 +168,43 @@ void launch_einc(z128* einc, const int* occ_lin, const Geo& g, double d, double 
                  const EincSys* sys /*device [n_energy]*/, const double* r0 /*device [n_traj][3]*/,
                  int n_energy, int n_traj, hipStream_t s);
 
+// Device staging of one electron-field call: the energies [n_energy] and the
+// trajectory points [n_traj][3] as copied from the host, and the per-energy
+// constants that launch_einc_prep derives from the energies.  The layout
+// holds up to `cap_e` energies; every array starts on a 256-byte boundary.
+struct EincStage {
+    double* energy;
+    EincSys* sys;
+    double* r0;
+};
+constexpr size_t einc_round256(size_t b) { return (b + 255) / 256 * 256; }
+constexpr size_t einc_stage_bytes(size_t cap_e, size_t n_traj) {
+    return einc_round256(cap_e * sizeof(double)) + einc_round256(cap_e * sizeof(EincSys)) +
+           n_traj * 3 * sizeof(double);
+}
+inline EincStage einc_stage_layout(void* base, size_t cap_e) {
+    char* b = static_cast<char*>(base);
+    const size_t o1 = einc_round256(cap_e * sizeof(double));
+    const size_t o2 = o1 + einc_round256(cap_e * sizeof(EincSys));
+    return EincStage{reinterpret_cast<double*>(b), reinterpret_cast<EincSys*>(b + o1),
+                     reinterpret_cast<double*>(b + o2)};
+}
+// sys[e] = {k0, k0 * inv_bg, ig} with k0 = energy[e] / hbar_c, for e < n
+// (inv_bg = 1/(beta gamma_h), ig = -i/gamma_h, both per call).
+void launch_einc_prep(const double* energy, EincSys* sys, int n, double hbar_c, z128 inv_bg,
+                      z128 ig, hipStream_t s);
+
+// The library's own staging area for callers that cannot allocate: a
+// file-scope device array of einc_stage_bytes(kEincNoallocMaxEnergies,
+// kEincNoallocMaxTraj) bytes (288 KiB) on every GPU the library runs on.
+constexpr int kEincNoallocMaxEnergies = 4096;
+constexpr int kEincNoallocMaxTraj = 4096;
+// Looks up the array's address on the current device (once per device;
+// thread-safe).  Throws dda::Error when the runtime cannot resolve it.
+void einc_scratch_init();
+// The address found for `device` by einc_scratch_init, or nullptr.
+void* einc_scratch(int device);
+
 // Material terms (material.hip), FP64: for system s < ns and dipole i < n,
 // from eps[s][i] (absolute permittivity), the host index sys[s].mh and the
 // host wavenumber sys[s].k,
