@@ -157,6 +157,41 @@ __device__ __forceinline__ void fft_stages(cx<T>* lds, const cx<T>* __restrict__
     }
 }
 
+// Q-point DFT of v held in registers, natural order in and out, by the same
+// Stockham stages (radices from pick_radix) with every index known at compile
+// time.  The twiddle W_Q^t is read as tw[t * TS] (tw holds W_{Q TS}^t).
+template <typename T, int Q, int NS, bool INV, int TS>
+__device__ __forceinline__ void reg_dft(cx<T> (&v)[Q], const cx<T>* __restrict__ tw) {
+    if constexpr (NS < Q) {
+        constexpr int R = pick_radix(Q / NS);
+        static_assert(R > 1, "line length must be 2^a 3^b");
+        constexpr int QR = Q / R;
+        cx<T> w[Q];
+#pragma unroll
+        for (int j = 0; j < QR; ++j) {
+            cx<T> a[R];
+#pragma unroll
+            for (int m = 0; m < R; ++m) a[m] = v[j + m * QR];
+            const int k = j % NS;
+            if (NS > 1 && k != 0) {
+#pragma unroll
+                for (int m = 1; m < R; ++m) {
+                    cx<T> t = tw[(m * k * (Q / (NS * R))) * TS];
+                    if (INV) t.y = -t.y;
+                    a[m] = a[m] * t;
+                }
+            }
+            dft<R, INV>(a);
+            const int base = (j / NS) * NS * R + k;
+#pragma unroll
+            for (int m = 0; m < R; ++m) w[base + m * NS] = a[m];
+        }
+#pragma unroll
+        for (int i = 0; i < Q; ++i) v[i] = w[i];
+        reg_dft<T, Q, NS * R, INV, TS>(v, tw);
+    }
+}
+
 // Unnormalised DFT (forward: exp(-2 pi i jk/L); inverse: exp(+2 pi i jk/L))
 // of NLINES lines held in LDS.  tw[t] = exp(-2 pi i t / L), t < L.
 // Must be called by all NTHR threads of the block; ends with a barrier.  Only

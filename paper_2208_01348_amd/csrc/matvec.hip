@@ -346,6 +346,188 @@ __global__ __launch_bounds__(NTHR) void k_zconv(cx<T>* __restrict__ G,
     }
 }
 
+// ------------------------------------------------------- K3 (two-stage) ----
+// The same column pass with each z transform done as two register stages,
+// L = R1 * R2 (Stockham: first R1-point DFTs of the inputs z = j + m R2, then
+// after the twiddle W_L^{m j} R2-point DFTs that read and write the same
+// indices j + m R1).  The first stage reads its inputs straight from global
+// memory (only z < nz <= L/2, so half its inputs are the known zero padding)
+// and the last inverse stage writes z < nz straight back; LDS carries one
+// transpose per direction and the D product (the spectrum of the block's
+// lines as [kz][line]), with five barriers per block.  Lines are
+// (mirror set, component, column), consecutive lanes taking consecutive
+// columns, so every global access is a run of TX columns.
+template <int L, int CS = 8>
+constexpr int zc2_r1() {
+    return L == 48 ? 8 : L == 64 ? 8 : L == 96 ? 16 : L == 128 ? 16 : L == 192 ? 16
+         : L == 256 ? 16 : 0;
+}
+template <int L>
+constexpr bool zc2_ok() { return zc2_r1<L>() > 0; }
+template <typename T, int L, int TX>
+constexpr size_t zc2_lds_bytes() { return size_t(L) * (6 * TX) * sizeof(cx<T>) + L * sizeof(cx<T>); }
+
+template <typename T, int L, int TX, int NT>
+__global__ __launch_bounds__(NT) void k_zconv2(cx<T>* __restrict__ G,
+                                               const cx<T>* const* __restrict__ Dptr,
+                                               const cx<T>* __restrict__ tw, Geo g,
+                                               const int* __restrict__ act,
+                                               const int* __restrict__ slot_sys, SlotFilter f) {
+    constexpr int R1 = zc2_r1<L, int(sizeof(cx<T>))>();
+    constexpr int R2 = L / R1;
+    constexpr int W = 6 * TX;  // lines: (mirror set, component, column)
+    static_assert(R1 % 2 == 0, "the first radix must be even");
+    __shared__ cx<T> lds[L * W];
+    __shared__ cx<T> twl[L];
+    const int tid = threadIdx.x;
+    int tile, ky0, pos;
+    zconv_block_map<T, TX>(tile, ky0, pos);
+    const int col0 = tile * TX;
+    const int ky1 = (g.my - ky0) % g.my;
+    const bool pair = ky1 != ky0;
+    const int slot = act ? act[pos] : pos;
+    if (!slot_live(f, slot)) return;
+    const int sys = slot_sys[slot];
+    for (int t = tid; t < L; t += NT) twl[t] = tw[t];
+    const int64_t plane = int64_t(g.my) * g.mx;
+    cx<T>* gb = G + int64_t(pos) * 3 * g.nz * plane + col0;
+    const int nz = g.nz;
+    const cx<T> zero{T(0), T(0)};
+    auto line_ptr = [&](int line, bool& ok) {
+        const int lset = line / (3 * TX), lc = (line / TX) % 3, lcol = line % TX;
+        ok = col0 + lcol < g.mx && (lset == 0 || pair);
+        return gb + int64_t(lset ? ky1 : ky0) * g.mx + int64_t(lc) * nz * plane +
+               min(lcol, g.mx - 1 - col0);
+    };
+    // forward stage 1: R1-point DFTs of x[j + m R2] (m < R1/2 can be non-zero)
+    constexpr int NB1 = W * R2;
+    for (int b = tid; b < NB1; b += NT) {
+        const int line = b % W, j = b / W;
+        bool ok;
+        const cx<T>* src = line_ptr(line, ok);
+        cx<T> a[R1];
+#pragma unroll
+        for (int m = 0; m < R1 / 2; ++m) {
+            const int z = j + m * R2;
+            a[m] = gload(src + int64_t(min(z, nz - 1)) * plane);
+        }
+#pragma unroll
+        for (int m = 0; m < R1 / 2; ++m) {
+            const int z = j + m * R2;
+            if (!ok || z >= nz) a[m] = zero;
+        }
+#pragma unroll
+        for (int m = R1 / 2; m < R1; ++m) a[m] = zero;
+        reg_dft<T, R1, 1, false, L / R1>(a, tw);
+#pragma unroll
+        for (int m = 0; m < R1; ++m) lds[(j * R1 + m) * W + line] = a[m];
+    }
+    __syncthreads();
+    // forward stage 2: twiddle W_L^{m j}, R2-point DFTs in place (each thread
+    // reads and writes only the indices j + m R1 of its line)
+    constexpr int NB2 = W * R1;
+    for (int b = tid; b < NB2; b += NT) {
+        const int line = b % W, j = b / W;
+        cx<T> a[R2];
+#pragma unroll
+        for (int m = 0; m < R2; ++m) a[m] = lds[(j + m * R1) * W + line];
+#pragma unroll
+        for (int m = 1; m < R2; ++m) a[m] = a[m] * twl[m * j];
+        reg_dft<T, R2, 1, false, L / R2>(a, twl);
+#pragma unroll
+        for (int m = 0; m < R2; ++m) lds[(j + m * R1) * W + line] = a[m];
+    }
+    __syncthreads();
+    // D from its stored corner [0, M/2]^3 (index M - k reads k; the odd
+    // components flip sign), one load for the four frequencies
+    // (ky0 or ky1) x (kz or mz - kz) of a column
+    {
+        const int mxh = g.mx / 2 + 1, myh = g.my / 2 + 1, mzh = g.mz / 2 + 1;
+        const int64_t dcomp = int64_t(mzh) * myh * mxh;
+        const cx<T>* dbase = Dptr[sys] + int64_t(ky0) * mxh;
+        for (int e = tid; e < mzh * TX; e += NT) {
+            const int kzp = e / TX, col = e % TX;
+            const int kx = col0 + col;
+            if (kx >= g.mx) continue;
+            const bool fx = kx > g.mx / 2;
+            const int kxr = fx ? g.mx - kx : kx;
+            const cx<T>* dp = dbase + int64_t(kzp) * myh * mxh + kxr;
+            const cx<T> dxx = gload(dp), dxy0 = gload(dp + dcomp), dxz0 = gload(dp + 2 * dcomp);
+            const cx<T> dyy = gload(dp + 3 * dcomp), dyz0 = gload(dp + 4 * dcomp);
+            const cx<T> dzz = gload(dp + 5 * dcomp);
+            const int kz1 = (g.mz - kzp) % g.mz;
+            const int nzs = (kz1 != kzp) ? 2 : 1;
+            const int nset = pair ? 2 : 1;
+            for (int zi = 0; zi < nzs; ++zi) {
+                const int kz = zi ? kz1 : kzp;
+                const bool fz = zi != 0;
+                for (int set = 0; set < nset; ++set) {
+                    const bool fy = set != 0;
+                    const cx<T> dxy = (fx != fy) ? -dxy0 : dxy0;
+                    const cx<T> dxz = (fx != fz) ? -dxz0 : dxz0;
+                    const cx<T> dyz = (fy != fz) ? -dyz0 : dyz0;
+                    cx<T>* u = lds + kz * W + set * 3 * TX + col;
+                    const cx<T> ux = u[0], uy = u[TX], uz = u[2 * TX];
+                    u[0] = dxx * ux + dxy * uy + dxz * uz;
+                    u[TX] = dxy * ux + dyy * uy + dyz * uz;
+                    u[2 * TX] = dxz * ux + dyz * uy + dzz * uz;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // inverse stage 1: R1-point DFTs of X[j + m R2] -> [j R1 + m]; every read
+    // of the block before any write
+    constexpr int NQ1 = (NB1 + NT - 1) / NT;
+    {
+        cx<T> a[NQ1][R1];
+#pragma unroll
+        for (int q = 0; q < NQ1; ++q) {
+            const int b = tid + q * NT;
+            if (b < NB1) {
+                const int line = b % W, j = b / W;
+#pragma unroll
+                for (int m = 0; m < R1; ++m) a[q][m] = lds[(j + m * R2) * W + line];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < NQ1; ++q) {
+            const int b = tid + q * NT;
+            if (b < NB1) {
+                const int line = b % W, j = b / W;
+                reg_dft<T, R1, 1, true, L / R1>(a[q], twl);
+#pragma unroll
+                for (int m = 0; m < R1; ++m) lds[(j * R1 + m) * W + line] = a[q][m];
+            }
+        }
+    }
+    __syncthreads();
+    // inverse stage 2: twiddle, R2-point DFTs; z = j + m R1 < nz back to memory
+    for (int b = tid; b < NB2; b += NT) {
+        const int line = b % W, j = b / W;
+        bool ok;
+        cx<T>* dst = const_cast<cx<T>*>(line_ptr(line, ok));
+        cx<T> a[R2];
+#pragma unroll
+        for (int m = 0; m < R2; ++m) a[m] = lds[(j + m * R1) * W + line];
+#pragma unroll
+        for (int m = 1; m < R2; ++m) {
+            cx<T> t = twl[m * j];
+            t.y = -t.y;
+            a[m] = a[m] * t;
+        }
+        reg_dft<T, R2, 1, true, L / R2>(a, twl);
+        if (ok) {
+#pragma unroll
+            for (int m = 0; m < R2; ++m) {
+                const int z = j + m * R1;
+                if ((2 * m < R2 || (R2 & 1)) && z < nz) dst[int64_t(z) * plane] = a[m];
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------- K5 ------
 template <typename T, int L, int MODE>
 __global__ __launch_bounds__(NTHR) void k_ixfft_pack(const cx<T>* __restrict__ G,
@@ -516,17 +698,51 @@ void run_zconv(cx<T>* G, const cx<T>* const* Dptr, const cx<T>* tw_z, const Geo&
     k_zconv<T, L, TX><<<grid, NTHR, 0, s>>>(G, Dptr, tw_z, g, act, slot_sys, f);
 }
 
+// Tile codes of the two-stage z pass: TX columns per block and NT threads,
+// code = TX | (NT / 64) << 6.  Candidates keep the block's LDS within 100 KB;
+// 512 threads only where every thread has a second-stage butterfly.
+constexpr int zc2_code(int tx, int nt) { return tx | ((nt / 64) << 6); }
+template <typename T, int L, int TX, int NT>
+constexpr bool zc2_fits() {
+    return zc2_ok<L>() && zc2_lds_bytes<T, L, TX>() <= (size_t(100) << 10) &&
+           (NT <= 256 || 6 * TX * zc2_r1<L, int(sizeof(cx<T>))>() >= NT);
+}
+template <typename T, int L>
+constexpr int zc2_default() {
+    return sizeof(T) == 4 ? (zc2_fits<T, L, 8, 256>() ? zc2_code(8, 256) : zc2_code(4, 256))
+                          : (zc2_fits<T, L, 4, 256>() ? zc2_code(4, 256) : zc2_code(2, 256));
+}
+#define DDA_ZC2_TILES(X) X(4, 256) X(4, 512) X(8, 256) X(8, 512) X(16, 256) X(16, 512) X(2, 256)
+
+template <typename T, int L, int TX, int NT>
+void run_zconv2(cx<T>* G, const cx<T>* const* Dptr, const cx<T>* tw_z, const Geo& g,
+                const int* act, const int* slot_sys, int n_act, SlotFilter f, hipStream_t s) {
+    dim3 grid(nblk(g.mx, TX), g.my / 2 + 1, n_act);
+    k_zconv2<T, L, TX, NT><<<grid, NT, 0, s>>>(G, Dptr, tw_z, g, act, slot_sys, f);
+}
+
 template <typename T, int L>
 void zconv_tx_run(int tx, cx<T>* G, const cx<T>* const* Dptr, const cx<T>* tw_z, const Geo& g,
                   const int* act, const int* slot_sys, int n_act, SlotFilter f, hipStream_t s) {
-    if constexpr (L >= kTuneMinL) {
+    if constexpr (zc2_ok<L>()) {
+        const int code = tx ? tx : zc2_default<T, L>();
+#define DDA_TX(W, N)                                                                      \
+    if constexpr (zc2_fits<T, L, W, N>())                                                 \
+        if (code == zc2_code(W, N))                                                       \
+            return run_zconv2<T, L, W, N>(G, Dptr, tw_z, g, act, slot_sys, n_act, f, s);
+        DDA_ZC2_TILES(DDA_TX)
+#undef DDA_TX
+        throw Error(-1, "z pass: not a tile of this length");
+    } else {
+        if constexpr (L >= kTuneMinL) {
 #define DDA_TX(W)                                                                        \
     if constexpr (zconv_fits<T, L, W>())                                                 \
         if (tx == W) return run_zconv<T, L, W>(G, Dptr, tw_z, g, act, slot_sys, n_act, f, s);
-        DDA_TX(1) DDA_TX(2) DDA_TX(4) DDA_TX(8)
+            DDA_TX(1) DDA_TX(2) DDA_TX(4) DDA_TX(8)
 #undef DDA_TX
+        }
+        run_zconv<T, L, zconv_tx<T, L>()>(G, Dptr, tw_z, g, act, slot_sys, n_act, f, s);
     }
-    run_zconv<T, L, zconv_tx<T, L>()>(G, Dptr, tw_z, g, act, slot_sys, n_act, f, s);
 }
 
 template <typename T>
@@ -573,18 +789,25 @@ template <typename T>
 std::vector<int> zconv_tx_candidates(int L) {
     std::vector<int> v;
     switch (L) {
+#define DDA_ZC2C(W, N) \
+    if constexpr (zc2_fits<T, LL, W, N>()) v.push_back(zc2_code(W, N));
 #define DDA_CASE(N)                                                                    \
-    case N:                                                                            \
-        if (N >= kTuneMinL) {                                                          \
+    case N: {                                                                          \
+        constexpr int LL = N;                                                          \
+        if constexpr (zc2_ok<LL>()) {                                                  \
+            DDA_ZC2_TILES(DDA_ZC2C)                                                    \
+        } else if (N >= kTuneMinL) {                                                   \
             if (zconv_fits<T, N, 1>()) v.push_back(1);                                 \
             if (zconv_fits<T, N, 2>()) v.push_back(2);                                 \
             if (zconv_fits<T, N, 4>()) v.push_back(4);                                 \
             if (zconv_fits<T, N, 8>()) v.push_back(8);                                 \
         }                                                                              \
         if (v.empty()) v.push_back(zconv_tx<T, N>());                                  \
-        break;
+        break;                                                                         \
+    }
         DDA_FOR_EACH_L(DDA_CASE)
 #undef DDA_CASE
+#undef DDA_ZC2C
         default:
             break;
     }

@@ -385,38 +385,11 @@ __device__ __forceinline__ double dpp_x2(double v) {
     return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
 }
 
-// Q-point DFT of v in registers, natural order in and out; the stage plan is
-// the Stockham plan of fft_core.h with twiddles W_Q^t = tw[t L/Q].
+// Q-point DFT of v in registers (reg_dft of fft_core.h with the L-entry
+// twiddle table, W_Q^t = tw[t L/Q]).
 template <typename T, int L, int Q, int NS, bool INV>
 __device__ __forceinline__ void reg_stages(cx<T> (&v)[Q], const cx<T>* __restrict__ tw) {
-    if constexpr (NS < Q) {
-        constexpr int R = pick_radix(Q / NS);
-        static_assert(R > 1, "line length must be 2^a 3^b");
-        constexpr int QR = Q / R;
-        cx<T> w[Q];
-#pragma unroll
-        for (int j = 0; j < QR; ++j) {
-            cx<T> a[R];
-#pragma unroll
-            for (int m = 0; m < R; ++m) a[m] = v[j + m * QR];
-            const int k = j % NS;
-            if (NS > 1 && k != 0) {
-#pragma unroll
-                for (int m = 1; m < R; ++m) {
-                    cx<T> t = tw[(m * k * (Q / (NS * R))) * (L / Q)];
-                    if (INV) t.y = -t.y;
-                    a[m] = a[m] * t;
-                }
-            }
-            dft<R, INV>(a);
-            const int base = (j / NS) * NS * R + k;
-#pragma unroll
-            for (int m = 0; m < R; ++m) w[base + m * NS] = a[m];
-        }
-#pragma unroll
-        for (int i = 0; i < Q; ++i) v[i] = w[i];
-        reg_stages<T, L, Q, NS * R, INV>(v, tw);
-    }
+    reg_dft<T, Q, NS, INV, L / Q>(v, tw);
 }
 
 // DFT of one line of length L spread over a lane quad (see above).

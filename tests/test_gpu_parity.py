@@ -393,12 +393,18 @@ def test_bicgstab_same_iterates_for_any_interval_and_graphs(precision):
         assert np.array_equal(pk, out[0][0])
 
 
-@pytest.mark.parametrize("shape", [(12, 12, 12), (12, 12, 16), (16, 8, 12)])
+ZC2_CODES = [tx | ((nt // 64) << 6) for tx in (2, 4, 8, 16) for nt in (256, 512)]
+
+
+@pytest.mark.parametrize("shape", [(12, 12, 12), (12, 12, 16), (16, 8, 12), (16, 12, 24),
+                                   (8, 20, 40)])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_every_autotuner_candidate_gives_identical_matvecs(shape, precision):
     """The autotuner only regroups lines into blocks: every candidate tile of
     the five-pass z and y passes (my != mz) gives the same matvec to the last
-    bit (the fused yz kernel of a cubic grid has a single shape per length)."""
+    bit (the fused yz kernel of a cubic grid has a single shape per length).
+    z grids of 48 and 96 take the two-stage z pass, whose tile codes are
+    TX | (threads / 64) << 6."""
     nx, ny, nz = shape
     mask = np.ones((nz, ny, nx), np.uint8)
     s = DDASolver(mask, 1.0, 1.45)
@@ -409,7 +415,7 @@ def test_every_autotuner_candidate_gives_identical_matvecs(shape, precision):
     x = torch.randn((5, 3, n), dtype=dt, device="cuda")
     mx, my, mz = s.grid
     yzc = [0, 256, 512, 1024] if my == mz else [0]
-    zc = [0] if my == mz else [0, 1, 2, 4, 8]
+    zc = [0] if my == mz else [0, 1, 2, 4, 8] + ZC2_CODES
     mc = [0] if my == mz else [0, 4, 8, 16, 32]
     ref = None
     tried = 0
