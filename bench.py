@@ -35,27 +35,32 @@ KERNELS = ["unpack_xfft", "yfft", "zconv", "iyfft", "ixfft_pack", "yzconv"]
 CONV_KERNELS = ["yzconv", "zconv"]
 
 
-def kernel_bytes(name: str, nx, ny, nz, mx, my, mz, n_occ, c: int) -> float:
-    """Algorithmic HBM bytes of one right-hand side through one matvec kernel
-    (complex size c; the index map is 4-byte ints).  The zero-padded rows the
-    kernels never touch are not counted."""
+def kernel_bytes(name: str, nx, ny, nz, mx, my, mz, n_occ, c: int, nrhs: float = 1.0,
+                 n_d: float = None) -> float:
+    """Algorithmic HBM bytes of one launch of a matvec kernel over nrhs
+    right-hand sides that use n_d distinct interaction spectra D (n_d = nrhs
+    when every right-hand side has its own energy; a D shared by a batch is
+    read once).  Complex size c; the index map is 4-byte ints.  The
+    zero-padded rows the kernels never touch are not counted."""
+    if n_d is None:
+        n_d = nrhs
     N = nx * ny * nz
     row_x = 3 * nz * ny * mx            # x-transformed rows (y < ny, z < nz)
     full_y = 3 * nz * my * mx           # after the y pass
     if name == "unpack_xfft":
-        return 3 * n_occ * c + 4 * N + row_x * c
+        return (3 * n_occ * c + 4 * N + row_x * c) * nrhs
     if name == "yfft":
-        return (row_x + full_y) * c
+        return (row_x + full_y) * c * nrhs
     if name == "zconv":
         # D is stored as its [0, M/2] corner per axis (even/odd symmetry)
-        return (2 * full_y + 6 * (mz // 2 + 1) * (my // 2 + 1) * (mx // 2 + 1)) * c
+        return 2 * full_y * c * nrhs + 6 * (mz // 2 + 1) * (my // 2 + 1) * (mx // 2 + 1) * c * n_d
     if name == "iyfft":
-        return (full_y + row_x) * c
+        return (full_y + row_x) * c * nrhs
     if name == "ixfft_pack":
-        return row_x * c + 4 * N + (3 + 1 + 3) * n_occ * c
+        return (row_x * c + 4 * N + (3 + 1 + 3) * n_occ * c) * nrhs
     if name == "yzconv":
         # T[kx][3][nz][ny] in and out, D as kx slabs of its [0, L/2]^2 corner
-        return (2 * row_x + 6 * (mx // 2 + 1) * (my // 2 + 1) * (mz // 2 + 1)) * c
+        return 2 * row_x * c * nrhs + 6 * (mx // 2 + 1) * (my // 2 + 1) * (mz // 2 + 1) * c * n_d
     raise KeyError(name)
 
 
@@ -227,7 +232,7 @@ def main():
     # once.  The right-hand sides a launch works on are counted from the
     # systems' matvec counts (each matvec passes the convolution kernel once).
     rhs = sum(x.matvecs for x in info_t) / max(launches, 1)
-    per_launch = kernel_bytes(dom, w.nx, w.ny, w.nz, mx, my, mz, n, c) * rhs
+    per_launch = kernel_bytes(dom, w.nx, w.ny, w.nz, mx, my, mz, n, c, nrhs=rhs)  # one D each
     achieved = per_launch / (ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -306,16 +311,16 @@ def rel_err_per_point(P, R):
 def measure_plain_fp64(torch, W, DDASolver, w, eps, P_mixed, info_mixed, steps, check_every,
                        log):
     """The same nanorod spectrum through the plain FP64 path (complex128
-    matvecs and vectors, no refinement), COCG and BiCGStab, timed like the
+    matvecs and vectors, no refinement), COCG, BiCGStab and QMR, timed like the
     headline; and the largest per-point difference between the mixed
     spectrum and the FP64 one.  Both meet the FP64 residual tolerance for
     every point; the FP64 path matches the FP64 CPU oracle to 1e-9 in the
     GPU parity tests."""
     out = {}
     P_ref = None
-    for solver in ("cocg", "bicgstab"):
+    for solver in ("cocg", "bicgstab", "qmr"):
         s = DDASolver(w.mask, w.d, w.m_h, precision="fp64", tol=w.tol, maxit=50000,
-                      solver=solver, check_every=check_every if solver == "cocg" else 16)
+                      solver=solver, check_every=check_every if solver != "bicgstab" else 16)
 
         def step():
             s.drop_cache()
@@ -333,8 +338,8 @@ def measure_plain_fp64(torch, W, DDASolver, w, eps, P_mixed, info_mixed, steps, 
         mvs = [i.matvecs for i in info]
         its = [i.iters for i in info]
         res = {"points_per_s": round(rate, 3), "steps": steps, "ms_per_step": round(1e3 * T / steps, 2),
-               "matvecs_total": int(sum(mvs)), "iterations_median": int(np.median(its)),
-               "iterations_max": int(max(its)),
+               "matvecs_total": int(sum(mvs)), "matvecs_max": int(max(mvs)),
+               "iterations_median": int(np.median(its)), "iterations_max": int(max(its)),
                "max_rel_residual": max(i.rel_residual for i in info),
                "all_converged": all(i.status == 0 for i in info)}
         if P_ref is None:
@@ -385,17 +390,20 @@ def measure_matvec64(torch, W, DDASolver, log):
             kt = {k: s3.kernel_time(k)[0] for k in KERNELS if s3.kernel_time(k)[1] > 0}
             dt_s = sum(kt.values()) * 1e-3
             s3.set_timing(False)
-            per_rhs = sum(kernel_bytes(k, w3.nx, w3.ny, w3.nz, mx, my, mz, n3, c) for k in kt)
+            per_launch = sum(kernel_bytes(k, w3.nx, w3.ny, w3.nz, mx, my, mz, n3, c, nrhs, 1)
+                             for k in kt)
             d_red = 6 * (mz // 2 + 1) * (my // 2 + 1) * (mx // 2 + 1)
             model = ((72 * N + 10 * n3) * nrhs + d_red) * c  # one D shared by the batch
             mv[f"{prec}_nrhs{nrhs}"] = {
                 "ms": round(dt_s * 1e3, 4),
                 "model_bytes_per_matvec": int(model),
                 "GBps_model": round(model / dt_s / 1e9, 1),
-                "GBps_kernels": round(per_rhs * nrhs / dt_s / 1e9, 1),
+                "GBps_kernels": round(per_launch / dt_s / 1e9, 1),
                 "frac_of_hbm_peak": round(model / dt_s / 1e9 / HBM_PEAK_GBS, 4),
-                "kernels_GBps": {k: round(kernel_bytes(k, w3.nx, w3.ny, w3.nz, mx, my, mz, n3, c)
-                                          * nrhs / (kt[k] * 1e-3) / 1e9, 1) for k in kt}}
+                "kernels_GBps": {k: round(kernel_bytes(k, w3.nx, w3.ny, w3.nz, mx, my, mz, n3, c,
+                                                       nrhs, 1) / (kt[k] * 1e-3) / 1e9, 1)
+                                 for k in kt},
+                "kernels_ms": {k: round(kt[k], 4) for k in kt}}
             log(f"matvec 64^3 {prec} nrhs={nrhs}: {dt_s * 1e3:.3f} ms, "
                 f"{model / dt_s / 1e9:.0f} GB/s (model)")
     s3.close()

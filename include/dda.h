@@ -68,15 +68,23 @@ typedef enum {
 } dda_status;
 
 enum { DDA_POL_LDR = 0, DDA_POL_CM = 1, DDA_POL_RR = 2 };
-enum { DDA_SOLVER_BICGSTAB = 0, DDA_SOLVER_COCG = 1 };
+enum { DDA_SOLVER_BICGSTAB = 0, DDA_SOLVER_COCG = 1, DDA_SOLVER_QMR = 2 };
 enum { DDA_PREC_FP64 = 0, DDA_PREC_MIXED = 1 };
 
 typedef struct {
     int polarizability;   /* DDA_POL_*; lattice dispersion relation by default      */
-    int solver;           /* DDA_SOLVER_BICGSTAB (two matvecs per iteration) or
+    int solver;           /* DDA_SOLVER_BICGSTAB (two matvecs per iteration),
                              DDA_SOLVER_COCG: conjugate-orthogonal CG for the
                              complex-symmetric DDA matrix (reciprocity, section
-                             2.4), one matvec per iteration                        */
+                             2.4), one matvec per iteration, or
+                             DDA_SOLVER_QMR: QMR for complex-symmetric matrices
+                             (the solver family of section S5; Lanczos of the
+                             bilinear form with unit-norm vectors, quasi-minimal
+                             residual by Givens rotations), one matvec per
+                             iteration; it restarts from the FP64 residual when
+                             its residual bound sqrt(n+1)|tau| meets tol but the
+                             FP64 residual does not (in MIXED precision, the
+                             FP32 cycles are refined this way)              */
     int precision;        /* DDA_PREC_FP64: complex128 throughout.
                              DDA_PREC_MIXED: complex64 FFT matvecs and Krylov vectors
                              with FP64 refinement: BiCGStab restarts from the FP64

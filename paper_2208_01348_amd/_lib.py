@@ -17,7 +17,7 @@ DDA_OK, DDA_EINVAL, DDA_ENOMEM, DDA_EDEVICE, DDA_ENOCONV, DDA_EBREAKDOWN, DDA_ES
 STATUS_NAMES = {0: "DDA_OK", -1: "DDA_EINVAL", -2: "DDA_ENOMEM", -3: "DDA_EDEVICE",
                 -4: "DDA_ENOCONV", -5: "DDA_EBREAKDOWN", -6: "DDA_ESINGULAR"}
 DDA_POL_LDR, DDA_POL_CM, DDA_POL_RR = 0, 1, 2
-DDA_SOLVER_BICGSTAB, DDA_SOLVER_COCG = 0, 1
+DDA_SOLVER_BICGSTAB, DDA_SOLVER_COCG, DDA_SOLVER_QMR = 0, 1, 2
 DDA_PREC_FP64, DDA_PREC_MIXED = 0, 1
 
 # every symbol include/dda.h declares

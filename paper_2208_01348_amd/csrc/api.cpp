@@ -39,6 +39,10 @@ constexpr int kMaxSide = 256;
 constexpr int kMaxRestarts = 20;
 constexpr double kInnerTol = 1e-4;   // relative tolerance of the FP32 inner solves
 constexpr int kMaxOuter = 60;
+// QMR in FP32: a cycle stops when its residual bound has fallen this far below
+// the residual it started from (the FP32 recursion resolves no more); the FP64
+// check then restarts it from the new residual.
+constexpr double kQmrInner = 1e-4;
 
 // ------------------------------------------------------------------ memory
 struct DevBuf {
@@ -1004,6 +1008,11 @@ struct CocgBufs {
     const dda::cx<T>* ainv;
     const z128* const* dptr64;
     const z128* ainv64;
+    // QMR (solver DDA_SOLVER_QMR): r holds u = A v_n (and the check's
+    // residual), p and q the Lanczos vectors, pa and pb the directions
+    dda::cx<T>* pa = nullptr;
+    dda::cx<T>* pb = nullptr;
+    bool qmr = false;
 };
 
 // x = 0, r = b, scalars for the n listed slots (device list act).
@@ -1012,7 +1021,8 @@ void cocg_init(dda_ctx* c, const CocgBufs<T>& B, const int* act, int n, double t
     constexpr bool mixed = std::is_same<T, float>::value;
     const int64_t nv = c->nv();
     dda::bicg_norm_b<double>(B.b, B.w.st, act, n, nv, tol * tol,
-                             mixed ? kUpdateDrop * kUpdateDrop : 0.0, maxit, B.w.red, c->stream);
+                             mixed && !B.qmr ? kUpdateDrop * kUpdateDrop : 0.0, maxit, B.w.red,
+                             c->stream);
     dda::cocg_zero(B.x, mixed ? B.x_lo : nullptr, act, n, nv, c->stream);
     dda::cocg_start<T>(B.b, nullptr, B.r, B.w.st, act, n, nv, B.w.red, c->stream);
 }
@@ -1028,7 +1038,29 @@ void cocg_interval(dda_ctx* c, const CocgBufs<T>& B, int n_act) {
     if (mixed) dda::accumulate_lo(B.x, B.x_lo, B.act, n_act, nv, fchk, s);
     matvec<double>(c, B.w, B.x, B.y64, B.act, n_act, B.dptr64, B.slot_sys, B.ainv64, dda::PACK_AX,
                    nullptr, fchk);
-    dda::cocg_check<T>(B.b, B.y64, B.r, B.w.st, B.act, n_act, nv, kMaxRestarts, B.w.red, s);
+    dda::cocg_check<T>(B.b, B.y64, B.r, B.w.st, B.act, n_act, nv, kMaxRestarts, B.w.red, s,
+                       B.qmr);
+    if (B.qmr) {
+        // a cycle starts from the residual of every slot the check left
+        // iterating; an even number of steps brings the roles of the vectors
+        // and of the scalar copies back to where the next interval expects them
+        dda::qmr_start<T>(B.r, B.p, B.q, B.pa, B.pb, B.w.st, B.act, n_act, nv,
+                          mixed ? kQmrInner : 0.0, s);
+        const int steps = std::max(2, (c->opt.check_every + 1) / 2 * 2);
+        const int nblk = pack_blocks(c, int(sizeof(dda::cx<T>)));
+        for (int k = 0; k < steps; ++k) {
+            const int par = k & 1;
+            dda::cx<T>* vc = par ? B.q : B.p;
+            dda::cx<T>* vo = par ? B.p : B.q;
+            dda::cx<T>* p1 = par ? B.pa : B.pb;
+            dda::cx<T>* p2 = par ? B.pb : B.pa;
+            matvec<T>(c, B.w, vc, B.r, B.act, n_act, B.dptr, B.slot_sys, B.ainv,
+                      dda::PACK_AX_COCG, nullptr, fact);
+            dda::qmr_step<T>(xs, B.r, vc, vo, p1, p2, B.w.st, B.act, n_act, nv, B.w.red, nblk,
+                             par, s);
+        }
+        return;
+    }
     const int check = std::max(1, c->opt.check_every);
     for (int k = 0; k < check; ++k) {
         matvec<T>(c, B.w, B.p, B.q, B.act, n_act, B.dptr, B.slot_sys, B.ainv, dda::PACK_AX_COCG,
@@ -1100,6 +1132,8 @@ size_t slot_bytes(const dda_ctx* c, bool mixed) {
     const size_t ge = size_t(dda::grid_elems(c->g));
     const size_t nv = size_t(c->nv());
     const size_t red = size_t(c->max_blocks) * 8 * sizeof(double) + sizeof(dda::BicgSlot);
+    // BiCGStab: six vectors (FP64), or two FP64 and eight FP32 (mixed); COCG
+    // and QMR (six vectors at most) fit in the same
     if (!mixed) return ge * sizeof(z128) + 6 * nv * sizeof(z128) + red;
     return ge * sizeof(z128) + 2 * nv * sizeof(z128) + 8 * nv * sizeof(z64) + red;
 }
@@ -1672,7 +1706,8 @@ int dda_setup(const uint8_t* mask, int nx, int ny, int nz, double d_nm, double m
     if (opt) c->opt = *opt; else dda_default_options(&c->opt);
     if (c->opt.polarizability < 0 || c->opt.polarizability > 2)
         throw Error(DDA_EINVAL, "unknown polarizability");
-    if (c->opt.solver != DDA_SOLVER_BICGSTAB && c->opt.solver != DDA_SOLVER_COCG)
+    if (c->opt.solver != DDA_SOLVER_BICGSTAB && c->opt.solver != DDA_SOLVER_COCG &&
+        c->opt.solver != DDA_SOLVER_QMR)
         throw Error(DDA_EINVAL, "unknown solver");
     if (c->opt.precision != DDA_PREC_FP64 && c->opt.precision != DDA_PREC_MIXED)
         throw Error(DDA_EINVAL, "unknown precision");
@@ -1877,24 +1912,36 @@ int dda_solve(dda_ctx* c, int n_energy, const double* energy_eV, const double* e
         std::vector<int> iters, mvs, status;
         std::vector<double> relres;
         const size_t q = size_t(nslots) * nv;
-        if (c->opt.solver == DDA_SOLVER_COCG) {
+        if (c->opt.solver == DDA_SOLVER_COCG || c->opt.solver == DDA_SOLVER_QMR) {
+            const bool qmr = c->opt.solver == DDA_SOLVER_QMR;
+            const size_t extra = qmr ? 2 : 0;  // QMR keeps two direction vectors more
             auto dptr64 = upload_dptrs<double>(c, ents);
             std::vector<dda_solve_info> inf;
             if (!mixed) {
-                c->vec128.ensure(4 * q * sizeof(z128));
+                c->vec128.ensure((4 + extra) * q * sizeof(z128));
                 auto* V = c->vec128.as<z128>();
                 CocgBufs<double> B{ctx_work(c), c->act.ptr(), c->slot_sys.as<int>(), b, x, V,
                                    V + q, V + 2 * q, nullptr, V + 3 * q, dptr64,
                                    c->ainv128.as<z128>(), dptr64, c->ainv128.as<z128>()};
+                if (qmr) {
+                    B.pa = V + 4 * q;
+                    B.pb = V + 5 * q;
+                    B.qmr = true;
+                }
                 run_cocg<double>(c, nslots, B, c->opt.tol, c->opt.maxit, inf);
             } else {
                 c->vec128.ensure(q * sizeof(z128));
-                c->vec64.ensure(4 * q * sizeof(z64));
+                c->vec64.ensure((4 + extra) * q * sizeof(z64));
                 auto* U = c->vec64.as<z64>();
                 auto dptr32 = upload_dptrs<float>(c, ents);
                 CocgBufs<float> B{ctx_work(c), c->act.ptr(), c->slot_sys.as<int>(), b, x, U,
                                   U + q, U + 2 * q, U + 3 * q, c->vec128.as<z128>(), dptr32,
                                   c->ainv64.as<z64>(), dptr64, c->ainv128.as<z128>()};
+                if (qmr) {
+                    B.pa = U + 4 * q;
+                    B.pb = U + 5 * q;
+                    B.qmr = true;
+                }
                 run_cocg<float>(c, nslots, B, c->opt.tol, c->opt.maxit, inf);
             }
             for (const auto& i : inf) {

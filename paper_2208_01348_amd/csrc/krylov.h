@@ -61,7 +61,27 @@ void cocg_start(const z128* b, const z128* y, cx<T>* r_lo, BicgSlot* st, const i
                 int n_act, int64_t nv, RedScratch red, hipStream_t s);
 template <typename T>
 void cocg_check(const z128* b, const z128* y, cx<T>* r_lo, BicgSlot* st, const int* act,
-                int n_act, int64_t nv, int max_restarts, RedScratch red, hipStream_t s);
+                int n_act, int64_t nv, int max_restarts, RedScratch red, hipStream_t s,
+                bool always_reset = false);
+
+// QMR for complex-symmetric A (Freund 1992), on the same driver as COCG:
+// qmr_start begins a cycle (v_1 = r / ||r||, v_0 = p_{-1} = p_0 = 0 and the
+// scalars of step 1) on the listed slots whose reset_p is set; qmr_step is
+// one Lanczos step after the matvec u = A vc (pack mode PACK_AX_COCG: rows of
+// vc^T u), with the roles of the vectors and of the two scalar copies given
+// by the step's parity `par` in its interval (vc, vo: v_n and v_{n-1}; p1,
+// p2: p_{n-1} and p_{n-2}; p_n is written over p2 and v_{n+1} over vo).
+// x accumulates in T.  The slot status becomes SLOT_CONVERGED when
+// sqrt(n+1) |tau| meets the tolerance (an FP64 check then decides),
+// SLOT_BREAKDOWN or SLOT_MAXIT.
+// A cycle ends when its residual bound falls to max(tol ||b||, inner ||r_0||).
+template <typename T>
+void qmr_start(const cx<T>* r, cx<T>* va, cx<T>* vb, cx<T>* p1, cx<T>* p2, BicgSlot* st,
+               const int* act, int n_act, int64_t nv, double inner, hipStream_t s);
+template <typename T>
+void qmr_step(cx<T>* x, const cx<T>* u, cx<T>* vc, cx<T>* vo, cx<T>* p1, cx<T>* p2,
+              BicgSlot* st, const int* act, int n_act, int64_t nv, RedScratch red, int nblk_mu,
+              int par, hipStream_t s);
 // x = 0 and x_lo = 0 (if not NULL) on the listed slots
 void cocg_zero(z128* x, z64* x_lo, const int* act, int n_act, int64_t nv, hipStream_t s);
 // slot act[i] becomes SLOT_FAIL_INVALID where err[i] != 0 (i < n)

@@ -456,7 +456,7 @@ constexpr int kStallChecks = 8;
 // breakdown restarts the recursion from the true residual (p = r), and a
 // reliable update continues it with the recomputed residual (p, beta kept).
 __global__ __launch_bounds__(NT) void k_fin_check(BicgSlot* st, const int* act, RedScratch red,
-                                                  int nblk, int max_restarts) {
+                                                  int nblk, int max_restarts, int always_reset) {
     if (!needs_check(st[act[blockIdx.x]])) return;
     FIN_PROLOGUE(3)
     S.matvecs += 1;
@@ -496,6 +496,7 @@ __global__ __launch_bounds__(NT) void k_fin_check(BicgSlot* st, const int* act, 
     }
     S.rho = z128{tot[0], tot[1]};
     S.status = SLOT_ACTIVE;
+    if (always_reset) S.reset_p = 1;  // QMR restarts its Lanczos process from the new residual
 }
 
 __global__ __launch_bounds__(NT) void k_cocg_zero(z128* __restrict__ x, z64* __restrict__ x_lo,
@@ -523,6 +524,232 @@ __global__ __launch_bounds__(NT) void k_accumulate_lo(z128* __restrict__ x, z64*
         x[base + i] = x[base + i] + cvt<double>(x_lo[base + i]);
         x_lo[base + i] = z64{0.f, 0.f};
     }
+}
+
+// ----------------------------------------------------------------- QMR ----
+// QMR for complex-symmetric matrices (Freund 1992): the Lanczos process of
+// the bilinear form x^T y with vectors of unit 2-norm, and the quasi-minimal
+// residual iterate from Givens rotations of its tridiagonal matrix H (column
+// n: beta_n, alpha_n, rho_{n+1}).  Per step, around the matvec u = A v_n
+// (whose pack kernel writes the partial rows of v_n^T u at 0..1):
+//   k_qmr_lanczos  alpha_n = v_n^T u / delta_n, beta_n = rho_n delta_n /
+//                  delta_{n-1}; w = u - alpha_n v_n - beta_n v_{n-1} (into
+//                  the v_{n-1} buffer); rows of ||w||^2 at 4, w^T w at 5..6
+//   k_qmr_update   rho_{n+1}, delta_{n+1}; the column through G_{n-2},
+//                  G_{n-1} and the new rotation G_n; p_n = (v_n - d2 p_{n-1}
+//                  - eps p_{n-2}) / r_n (into the p_{n-2} buffer); x += c_n
+//                  tau_n p_n; v_{n+1} = w / rho_{n+1}; tau_{n+1} = -conj(s_n)
+//                  tau_n; the scalars for step n+1 into the other copy
+//   k_qmr_fin      the copy's flag becomes the slot status (converged when
+//                  sqrt(n+1) |tau_{n+1}|, which bounds the residual, meets
+//                  the cycle's threshold: the tolerance, or in FP32 a fixed
+//                  fraction of the cycle's starting residual, since the
+//                  FP32 recursion cannot resolve more; breakdown when delta
+//                  or r_n vanishes)
+// Both vector kernels take the step's scalars from the same sums in every
+// block; only block 0 stores them.
+
+constexpr int kQmrStagSteps = 256;
+
+__device__ __forceinline__ z128 zmul(z128 a, z128 b) {
+    return z128{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+__device__ __forceinline__ z128 zconj(z128 a) { return z128{a.x, -a.y}; }
+
+// alpha_n and beta_n of step `Q` from the mu rows; false on a breakdown
+// (delta_n = 0, or a non-finite product), which every block detects alike.
+__device__ __forceinline__ bool qmr_ab(const QmrScalars& Q, const double (&mu)[2], z128& a,
+                                       z128& b) {
+    if (!isfinite(mu[0]) || !isfinite(mu[1])) return false;
+    if (Q.delta.x == 0.0 && Q.delta.y == 0.0) return false;
+    a = zdiv(z128{mu[0], mu[1]}, Q.delta);
+    b = Q.n > 1 ? Q.rho * zdiv(Q.delta, Q.delta_prev) : z128{0.0, 0.0};
+    return isfinite(a.x) && isfinite(a.y) && isfinite(b.x) && isfinite(b.y);
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_qmr_lanczos(const cx<T>* __restrict__ vc,
+                                                    cx<T>* __restrict__ vo,
+                                                    const cx<T>* __restrict__ u, BicgSlot* st,
+                                                    const int* __restrict__ act, int64_t nv,
+                                                    RedScratch red, int nblk_mu, int par) {
+    SLOT_PROLOGUE
+    BicgSlot& S = st[slot];
+    if (block_status(S) != SLOT_ACTIVE) return;
+    double mu[2];
+    slot_totals<2, 0>(red, slot, nblk_mu, mu);
+    z128 a, b;
+    if (!qmr_ab(S.qmr[par], mu, a, b)) return;  // k_qmr_update flags it
+    const cx<T> at{T(a.x), T(a.y)}, bt{T(b.x), T(b.y)};
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = i0; i < nv; i += stride) {
+        const cx<T> w = u[base + i] - at * vc[base + i] - bt * vo[base + i];
+        vo[base + i] = w;
+        s[0] += double(norm2(w));
+        acc_bdot(s[1], s[2], w, w);
+    }
+    block_partial<3, NT, 4>(s, red, slot, blockIdx.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_qmr_update(cx<T>* __restrict__ x,
+                                                   const cx<T>* __restrict__ vc,
+                                                   cx<T>* __restrict__ vo,
+                                                   const cx<T>* __restrict__ p1,
+                                                   cx<T>* __restrict__ p2, BicgSlot* st,
+                                                   const int* __restrict__ act, int64_t nv,
+                                                   RedScratch red, int nblk_mu, int par) {
+    SLOT_PROLOGUE
+    BicgSlot& S = st[slot];
+    if (block_status(S) != SLOT_ACTIVE) return;
+    const QmrScalars& Q = S.qmr[par];
+    QmrScalars& N = S.qmr[par ^ 1];
+    const bool lead = blockIdx.x == 0 && threadIdx.x == 0;
+    double mu[2];
+    slot_totals<2, 0>(red, slot, nblk_mu, mu);
+    z128 a, b;
+    if (!qmr_ab(Q, mu, a, b)) {
+        if (lead) {
+            N = Q;
+            N.flag = QMR_BREAKDOWN;
+        }
+        return;
+    }
+    double ws[3];
+    slot_totals<3, 4>(red, slot, gridDim.x, ws);
+    const double rho1 = sqrt(ws[0]);
+    // column n of H through G_{n-2} and G_{n-1}; no entry above the diagonal
+    // in the first column of a cycle
+    const z128 th = Q.n > 1 ? b : z128{0.0, 0.0};
+    const z128 eps = zmul(Q.s2, th);
+    const z128 th2 = Q.c2 * th;
+    const z128 d2 = Q.c1 * th2 + zmul(Q.s1, a);
+    const z128 gam = Q.c1 * a - zmul(zconj(Q.s1), th2);
+    // G_n zeroes rho_{n+1} below gam: c real, r = (gam/|gam|) nu
+    double c;
+    z128 sn, r;
+    const double ag = hypot(gam.x, gam.y);
+    if (ag == 0.0) {
+        c = 0.0;
+        sn = z128{1.0, 0.0};
+        r = z128{rho1, 0.0};
+    } else {
+        const double nu = hypot(ag, rho1);
+        const z128 ph{gam.x / ag, gam.y / ag};
+        c = ag / nu;
+        sn = (rho1 / nu) * ph;
+        r = nu * ph;
+    }
+    const bool bad = !(r.x != 0.0 || r.y != 0.0) || !isfinite(r.x) || !isfinite(r.y) ||
+                     !isfinite(ws[0]) || !isfinite(ws[1]) || !isfinite(ws[2]);
+    if (bad) {
+        if (lead) {
+            N = Q;
+            N.flag = QMR_BREAKDOWN;
+        }
+        return;
+    }
+    const z128 phi = c * Q.tau;
+    const z128 ri = zdiv(z128{1.0, 0.0}, r);
+    const cx<T> rit{T(ri.x), T(ri.y)}, d2t{T(d2.x), T(d2.y)}, et{T(eps.x), T(eps.y)};
+    const cx<T> pht{T(phi.x), T(phi.y)};
+    const T iw = rho1 > 0.0 ? T(1.0 / rho1) : T(0);
+    for (int64_t i = i0; i < nv; i += stride) {
+        const cx<T> pn = rit * (vc[base + i] - d2t * p1[base + i] - et * p2[base + i]);
+        p2[base + i] = pn;
+        x[base + i] = x[base + i] + pht * pn;
+        vo[base + i] = iw * vo[base + i];
+    }
+    if (lead) {
+        const z128 tau1 = -1.0 * zmul(zconj(sn), Q.tau);
+        const z128 del1 = rho1 > 0.0 ? (1.0 / ws[0]) * z128{ws[1], ws[2]} : z128{0.0, 0.0};
+        N.delta_prev = Q.delta;
+        N.delta = del1;
+        N.s2 = Q.s1;
+        N.c2 = Q.c1;
+        N.s1 = sn;
+        N.c1 = c;
+        N.tau = tau1;
+        N.rho = rho1;
+        N.stop2 = Q.stop2;
+        N.n = Q.n + 1;
+        const double t2 = tau1.x * tau1.x + tau1.y * tau1.y;
+        const double est2 = double(Q.n + 1) * t2;
+        // FP32 cycles: a quasi-residual that fell by less than a tenth over
+        // kQmrStagSteps steps has stagnated (the FP32 Lanczos vectors lost
+        // their bi-orthogonality); the cycle ends and restarts from the
+        // FP64 residual
+        bool stagnated = false;
+        N.mark2 = Q.mark2;
+        N.mark = Q.mark;
+        if (Q.mark2 > 0.0 && N.n - Q.mark >= kQmrStagSteps) {
+            stagnated = t2 > 0.81 * Q.mark2;
+            N.mark2 = t2;
+            N.mark = N.n;
+        }
+        S.iters += 1;
+        S.matvecs += 1;
+        S.rnorm2 = est2;
+        N.flag = (rho1 == 0.0 || est2 <= Q.stop2 || stagnated) ? QMR_CONVERGED
+                 : (del1.x == 0.0 && del1.y == 0.0)         ? QMR_BREAKDOWN
+                 : (S.iters >= S.maxit)                     ? QMR_MAXIT
+                                                            : QMR_GO;
+    }
+}
+
+// The flag of the copy just written becomes the slot status.
+__global__ __launch_bounds__(NT) void k_qmr_fin(BicgSlot* st, const int* act, int par) {
+    if (threadIdx.x != 0) return;
+    BicgSlot& S = st[act[blockIdx.x]];
+    if (S.status != SLOT_ACTIVE) return;
+    const int fl = S.qmr[par].flag;
+    if (fl == QMR_CONVERGED) S.status = SLOT_CONVERGED;
+    else if (fl == QMR_BREAKDOWN) S.status = SLOT_BREAKDOWN;
+    else if (fl == QMR_MAXIT) S.status = SLOT_MAXIT;
+}
+
+// Start of a QMR cycle from the residual r (the T vector the FP64 check or
+// the start wrote; rho_1 = sqrt(rnorm2), delta_1 = r^T r / rho_1^2): v_1 =
+// r / rho_1 into va, zero vb, p1, p2.  Only slots with reset_p set.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_qmr_start(const cx<T>* __restrict__ r,
+                                                  cx<T>* __restrict__ va, cx<T>* __restrict__ vb,
+                                                  cx<T>* __restrict__ p1, cx<T>* __restrict__ p2,
+                                                  const BicgSlot* st, const int* __restrict__ act,
+                                                  int64_t nv) {
+    SLOT_PROLOGUE
+    const BicgSlot& S = st[slot];
+    if (S.status != SLOT_ACTIVE || !S.reset_p) return;  // not changed by this kernel
+    const double rn = sqrt(S.rnorm2);
+    const T sc = rn > 0.0 ? T(1.0 / rn) : T(0);
+    const cx<T> zero{T(0), T(0)};
+    for (int64_t i = i0; i < nv; i += stride) {
+        va[base + i] = sc * r[base + i];
+        vb[base + i] = zero;
+        p1[base + i] = zero;
+        p2[base + i] = zero;
+    }
+}
+__global__ __launch_bounds__(NT) void k_qmr_start_fin(BicgSlot* st, const int* act,
+                                                       double inner2) {
+    if (threadIdx.x != 0) return;
+    BicgSlot& S = st[act[blockIdx.x]];
+    if (S.status != SLOT_ACTIVE || !S.reset_p) return;
+    const double rn = sqrt(S.rnorm2);
+    QmrScalars& Q = S.qmr[0];
+    Q.rho = rn;
+    Q.delta = rn > 0.0 ? (1.0 / S.rnorm2) * S.rho : z128{0.0, 0.0};
+    Q.delta_prev = z128{1.0, 0.0};
+    Q.s1 = Q.s2 = z128{0.0, 0.0};
+    Q.c1 = Q.c2 = 1.0;
+    Q.tau = z128{rn, 0.0};
+    Q.stop2 = fmax(S.tol2 * S.bnorm2, inner2 * S.rnorm2);
+    Q.mark2 = inner2 > 0.0 ? S.rnorm2 : 0.0;
+    Q.mark = 1;
+    Q.n = 1;
+    Q.flag = rn > 0.0 ? QMR_GO : QMR_CONVERGED;
+    S.reset_p = 0;
+    if (rn == 0.0) S.status = SLOT_CONVERGED;
 }
 
 // --------------------------------------------------------- loss sums ------
@@ -668,12 +895,36 @@ void cocg_start(const z128* b, const z128* y, cx<T>* r_lo, BicgSlot* st, const i
 }
 template <typename T>
 void cocg_check(const z128* b, const z128* y, cx<T>* r_lo, BicgSlot* st, const int* act,
-                int n_act, int64_t nv, int max_restarts, RedScratch red, hipStream_t s) {
+                int n_act, int64_t nv, int max_restarts, RedScratch red, hipStream_t s,
+                bool always_reset) {
     if (n_act == 0) return;
     k_true_residual<T><<<GRID(nv), NT, 0, s>>>(b, y, r_lo, act, nv,
                                                SlotFilter{st, FILTER_CHECK}, red);
     DDA_LAUNCH_CHECK();
-    FIN(k_fin_check, max_restarts);
+    FIN(k_fin_check, max_restarts, always_reset ? 1 : 0);
+}
+template <typename T>
+void qmr_start(const cx<T>* r, cx<T>* va, cx<T>* vb, cx<T>* p1, cx<T>* p2, BicgSlot* st,
+               const int* act, int n_act, int64_t nv, double inner, hipStream_t s) {
+    if (n_act == 0) return;
+    dim3 grid(blocks_for(nv, 1 << 20), n_act);
+    k_qmr_start<T><<<grid, NT, 0, s>>>(r, va, vb, p1, p2, st, act, nv);
+    DDA_LAUNCH_CHECK();
+    k_qmr_start_fin<<<n_act, NT, 0, s>>>(st, act, inner * inner);
+    DDA_LAUNCH_CHECK();
+}
+template <typename T>
+void qmr_step(cx<T>* x, const cx<T>* u, cx<T>* vc, cx<T>* vo, cx<T>* p1, cx<T>* p2,
+              BicgSlot* st, const int* act, int n_act, int64_t nv, RedScratch red, int nblk_mu,
+              int par, hipStream_t s) {
+    if (n_act == 0) return;
+    if (nblk_mu < 1 || nblk_mu > red.max_blocks) throw Error(-1, "bad partial row count");
+    k_qmr_lanczos<T><<<GRID(nv), NT, 0, s>>>(vc, vo, u, st, act, nv, red, nblk_mu, par);
+    DDA_LAUNCH_CHECK();
+    k_qmr_update<T><<<GRID(nv), NT, 0, s>>>(x, vc, vo, p1, p2, st, act, nv, red, nblk_mu, par);
+    DDA_LAUNCH_CHECK();
+    k_qmr_fin<<<n_act, NT, 0, s>>>(st, act, par ^ 1);
+    DDA_LAUNCH_CHECK();
 }
 void cocg_zero(z128* x, z64* x_lo, const int* act, int n_act, int64_t nv, hipStream_t s) {
     if (n_act == 0) return;
@@ -739,7 +990,11 @@ void loss_sums(const z128* einc, const z128* p, const z128* y, const double* w, 
     template void cocg_start<T>(const z128*, const z128*, cx<T>*, BicgSlot*, const int*, int,    \
                                 int64_t, RedScratch, hipStream_t);                               \
     template void cocg_check<T>(const z128*, const z128*, cx<T>*, BicgSlot*, const int*, int,    \
-                                int64_t, int, RedScratch, hipStream_t);
+                                int64_t, int, RedScratch, hipStream_t, bool);                    \
+    template void qmr_start<T>(const cx<T>*, cx<T>*, cx<T>*, cx<T>*, cx<T>*, BicgSlot*,          \
+                               const int*, int, int64_t, double, hipStream_t);                   \
+    template void qmr_step<T>(cx<T>*, const cx<T>*, cx<T>*, cx<T>*, cx<T>*, cx<T>*, BicgSlot*,   \
+                              const int*, int, int64_t, RedScratch, int, int, hipStream_t);
 DDA_INST(double)
 DDA_INST(float)
 

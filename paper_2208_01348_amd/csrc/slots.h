@@ -20,6 +20,24 @@ enum SlotStatus : int {
     SLOT_FAIL_INVALID = 8,      // the system's permittivity was rejected
 };
 
+// QMR for complex-symmetric systems: the scalars one Lanczos step reads.
+// Every step reads one copy and writes the other (by the parity of its index
+// in the interval), so the blocks of a launch never see a value another block
+// of the same launch has just written.
+struct QmrScalars {
+    z128 delta, delta_prev;  // v_n^T v_n and v_{n-1}^T v_{n-1} (bilinear)
+    z128 s1, s2;             // sines of the rotations G_{n-1}, G_{n-2}
+    z128 tau;                // quasi-residual
+    double rho;              // ||w_n||: v_n = w_n / rho_n
+    double c1, c2;           // cosines of G_{n-1}, G_{n-2}
+    double stop2;            // the cycle ends when (n+1)|tau|^2 falls to this
+    double mark2;            // |tau|^2 at step `mark` (stagnation test; 0: off)
+    int mark;
+    int n;                   // Lanczos step of the cycle (1-based)
+    int flag;                // QMR_GO, QMR_CONVERGED, QMR_BREAKDOWN, QMR_MAXIT
+};
+enum QmrFlag : int { QMR_GO = 0, QMR_CONVERGED = 1, QMR_BREAKDOWN = 2, QMR_MAXIT = 3 };
+
 struct BicgSlot {
     z128 rho, rho_old, alpha, omega;  // BiCGStab; COCG uses rho and alpha
     z128 rv, ts;                      // BiCGStab <rhat, v>, <t, s>; COCG: rv = p^T q
@@ -39,6 +57,7 @@ struct BicgSlot {
     int reset_p;                      // COCG: the next direction update takes p = r
     int maxit;                        // iteration limit
     int stall;                        // FP64 checks since best2 last halved
+    QmrScalars qmr[2];                // QMR: the two alternating copies
 };
 
 __host__ __device__ inline bool slot_terminal(int status) { return status >= SLOT_DONE; }

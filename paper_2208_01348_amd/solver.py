@@ -26,7 +26,7 @@ from . import _lib as L
 
 _POL = {"ldr": L.DDA_POL_LDR, "cm": L.DDA_POL_CM, "rr": L.DDA_POL_RR}
 _PREC = {"fp64": L.DDA_PREC_FP64, "mixed": L.DDA_PREC_MIXED}
-_SOLVER = {"bicgstab": L.DDA_SOLVER_BICGSTAB, "cocg": L.DDA_SOLVER_COCG}
+_SOLVER = {"bicgstab": L.DDA_SOLVER_BICGSTAB, "cocg": L.DDA_SOLVER_COCG, "qmr": L.DDA_SOLVER_QMR}
 
 
 @dataclass

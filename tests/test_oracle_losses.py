@@ -291,3 +291,71 @@ def test_dense_rows_equal_rows_of_the_full_product():
             full = cdense.matvec(c, alpha, k, x, interaction_only=io)
             part = cdense.matvec_rows(c, alpha, k, x, rows, interaction_only=io)
             assert np.array_equal(part, full[rows])
+
+
+# ------------------------------------------------------------------ QMR ----
+@pytest.mark.parametrize("m_h", [1.45, 2.0 + 0.01j])
+def test_qmr_cs_matches_lu(m_h):
+    """QMR for the complex-symmetric DDA system (section S5) reaches the dense
+    LU solution."""
+    from oracle.solve import qmr_cs
+    mask = capped_rod_mask(12, 4, 4, 1.0, radius=2.0, length=12.0)
+    d, E, beta = 1.0, 2.0, 0.6
+    n = int(mask.sum())
+    centres, alpha, k, _ = system(mask, d, [-6.0 + 0.6j] * n, m_h, E)
+    e = el.incident_field(centres, E, beta, m_h, (8.0, 0.0, 0.0))
+    p_lu = lu_solve(centres, alpha, k, e)
+    p_q, it, res = qmr_cs(centres, alpha, k, e, tol=1e-13)
+    assert res <= 1e-13 and it > 10
+    assert np.max(np.abs(p_q - p_lu)) <= 1e-10 * np.max(np.abs(p_lu))
+
+
+def test_qmr_cs_is_minres_for_a_real_symmetric_matrix():
+    """For a real symmetric matrix the bilinear form is the inner product, the
+    Lanczos vectors are orthonormal and the quasi-minimal residual is the
+    minimal one: QMR-CS's iterates are MINRES's (scipy, Paige-Saunders),
+    iteration by iteration; an indefinite matrix makes it non-trivial."""
+    from scipy.sparse.linalg import minres
+    from oracle.solve import qmr_cs
+    rng = np.random.default_rng(3)
+    n = 40
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    lam = np.concatenate([rng.uniform(1.0, 5.0, 30), rng.uniform(-3.0, -0.5, 10)])
+    A = (Q * lam) @ Q.T
+    A = 0.5 * (A + A.T)
+    b = rng.standard_normal(n)
+    ours = {}
+
+    def cb(it, x, tau):
+        ours[it] = np.real(x).copy()
+
+    qmr_cs(None, None, None, b.astype(np.complex128), tol=1e-300, maxit=25,
+           matvec=lambda v: A @ v, callback=cb)
+    theirs = []
+    minres(A, b, rtol=1e-300, maxiter=25, callback=lambda xk: theirs.append(xk.copy()))
+    for i in range(1, 21):
+        assert np.linalg.norm(ours[i] - theirs[i - 1]) <= 1e-9 * np.linalg.norm(theirs[i - 1]), i
+
+
+def test_qmr_cs_quasi_residual_bounds_the_residual_and_decreases():
+    """|tau| never increases within a cycle, and with unit-norm Lanczos
+    vectors the true residual never exceeds sqrt(n + 1) |tau_{n+1}| (up to
+    the rounding floor of the residual, ~1e-15 ||b||, below which the
+    recursion's quasi-residual keeps falling while the true one cannot)."""
+    from oracle.interaction import dense_matrix
+    from oracle.solve import qmr_cs
+    mask = random_mask(5, 4, 3, 0.7, seed=11)
+    centres, alpha, k, _ = system(mask, 1.7, [2.0 + 0.3j] * int(mask.sum()), 1.3 + 0.02j, 2.7)
+    A = dense_matrix(centres, alpha, k)
+    rng = np.random.default_rng(5)
+    b = rng.standard_normal((len(alpha), 3)) + 1j * rng.standard_normal((len(alpha), 3))
+    taus, ok = [], []
+
+    def cb(it, x, tau):
+        r = np.linalg.norm(b.ravel() - A @ x.ravel())
+        ok.append(r <= np.sqrt(it + 1) * abs(tau) * (1 + 1e-9) + 1e-13 * np.linalg.norm(b))
+        taus.append(abs(tau))
+
+    qmr_cs(centres, alpha, k, b, tol=1e-300, maxit=40, callback=cb)
+    assert all(ok)
+    assert all(t1 <= t0 * (1 + 1e-12) for t0, t1 in zip(taus, taus[1:]))
