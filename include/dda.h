@@ -70,6 +70,7 @@ typedef enum {
 enum { DDA_POL_LDR = 0, DDA_POL_CM = 1, DDA_POL_RR = 2 };
 enum { DDA_SOLVER_BICGSTAB = 0, DDA_SOLVER_COCG = 1, DDA_SOLVER_QMR = 2 };
 enum { DDA_PREC_FP64 = 0, DDA_PREC_MIXED = 1 };
+enum { DDA_INT_POINT = 0, DDA_INT_IGT = 1 };
 
 typedef struct {
     int polarizability;   /* DDA_POL_*; lattice dispersion relation by default      */
@@ -104,6 +105,16 @@ typedef struct {
                              right-hand sides keeps its size); 0 launches kernels
                              one by one, and so does a context whose kernel timing
                              is on (dda_set_timing).  Results are identical.       */
+    int interaction;      /* DDA_INT_POINT: the point-dipole Green's tensor G(R)
+                             between every pair of dipoles.  DDA_INT_IGT: the
+                             interaction the paper recommends (section S5),
+                             read as the Green's tensor of eq. (5) integrated
+                             over the source cell (the VIE of eqs. 4 and 8 with
+                             the polarization constant in each cell):
+                             for |R| <= 3 d the cell average
+                             d^-3 int_cube G(R + s) d^3 s (24-point Gauss-
+                             Legendre rule per axis, FP64), beyond it G(R).
+                             The self term stays with the polarizability.     */
 } dda_options;
 
 typedef struct {

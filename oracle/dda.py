@@ -42,7 +42,9 @@ def system(mask, d, eps_dipoles, m_h, energy_eV, pol="ldr"):
 
 
 def solve_point(mask, d, eps_dipoles, m_h, beta, r0, energy_eV, pol="ldr", tol=1e-12,
-                method="auto", maxit=100000) -> PointResult:
+                method="auto", maxit=100000, interaction="point") -> PointResult:
+    """interaction: "point" (the point-dipole G_tilde) or "igt" (the cell
+    average of G_tilde for near offsets, dense LU only)."""
     centres, alpha, k, m2 = system(mask, d, eps_dipoles, m_h, energy_eV, pol)
     n = centres.shape[0]
     e = incident_field(centres, energy_eV, beta, m_h, r0)
@@ -50,6 +52,19 @@ def solve_point(mask, d, eps_dipoles, m_h, beta, r0, energy_eV, pol="ldr", tol=1
     if n == 0:
         z = np.zeros((0, 3), dtype=np.complex128)
         return PointResult(0.0, 0.0, 0.0, 0.0, z, z, 0, 0.0)
+    if interaction == "igt":
+        from .interaction import dense_matrix_igt, interaction_matrix_igt
+        A = dense_matrix_igt(centres, alpha, k, d)
+        p = np.linalg.solve(A, e.reshape(-1)).reshape(n, 3)
+        res = float(np.linalg.norm(e.reshape(-1) - A @ p.reshape(-1)) / np.linalg.norm(e))
+        Gp = (interaction_matrix_igt(centres, k, d) @ p.reshape(-1)).reshape(n, 3)
+        return PointResult(
+            p_eels=p_eels(g, p, energy_eV, beta, m_h),
+            p_ext=p_ext(e, p, energy_eV, beta, m_h),
+            p_abs=p_abs(p, alpha, m2, d, energy_eV, beta, m_h),
+            p_cl=p_cl(p, Gp, energy_eV, beta, m_h),
+            p_hat=p, e_hat=e, iters=0, residual=res,
+        )
     if method == "lu" or (method == "auto" and n <= LU_MAX_DIPOLES):
         p = lu_solve(centres, alpha, k, e)
         r = e - cdense.matvec(centres, alpha, k, p)

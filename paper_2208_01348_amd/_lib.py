@@ -18,6 +18,7 @@ STATUS_NAMES = {0: "DDA_OK", -1: "DDA_EINVAL", -2: "DDA_ENOMEM", -3: "DDA_EDEVIC
                 -4: "DDA_ENOCONV", -5: "DDA_EBREAKDOWN", -6: "DDA_ESINGULAR"}
 DDA_POL_LDR, DDA_POL_CM, DDA_POL_RR = 0, 1, 2
 DDA_SOLVER_BICGSTAB, DDA_SOLVER_COCG, DDA_SOLVER_QMR = 0, 1, 2
+DDA_INT_POINT, DDA_INT_IGT = 0, 1
 DDA_PREC_FP64, DDA_PREC_MIXED = 0, 1
 
 # every symbol include/dda.h declares
@@ -41,7 +42,7 @@ class Options(ctypes.Structure):
     _fields_ = [("polarizability", ctypes.c_int), ("solver", ctypes.c_int),
                 ("precision", ctypes.c_int), ("tol", ctypes.c_double),
                 ("maxit", ctypes.c_int), ("check_every", ctypes.c_int),
-                ("use_graphs", ctypes.c_int)]
+                ("use_graphs", ctypes.c_int), ("interaction", ctypes.c_int)]
 
 
 class SolveInfo(ctypes.Structure):

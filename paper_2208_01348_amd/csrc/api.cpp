@@ -272,6 +272,8 @@ struct dda_ctx {
     // work space
     DevBuf G, vec128, vec64, st, partial, slot_sys, dptr, ainv128, ainv64, misc;
     DevBuf dfull;  // scratch of the full-grid transform during a D build
+    DevBuf igt_buf;      // integrated interaction: near offsets and the cubature rule
+    dda::IgtTable igt{};
     DevBuf eps_dev, matsys;  // permittivities and wavenumbers of a chunk
     DevBuf ff_coord, ff_buf;  // far-field: packed dipole coordinates, work space
     PinnedBuf host_st, host_misc;
@@ -608,9 +610,26 @@ size_t d_elems(const dda_ctx* c, int csize) {
 
 void build_full_D(dda_ctx* c, cplx k) {
     c->dfull.ensure(size_t(dda::dgrid_elems(c->g)) * sizeof(z128));
+    const dda::IgtTable* igt = nullptr;
+    if (c->opt.interaction == DDA_INT_IGT) {
+        if (!c->igt.rule) {
+            std::vector<int> off;
+            std::vector<double> rule;
+            dda::igt_host_tables(c->g, off, rule);
+            const size_t ob = off.size() * sizeof(int), rb = rule.size() * sizeof(double);
+            c->igt_buf.ensure(ob + rb + 256);
+            char* base = c->igt_buf.as<char>();
+            upload(c, base, rule.data(), rb);
+            if (ob) upload(c, base + rb, off.data(), ob);
+            c->igt.rule = reinterpret_cast<const double*>(base);
+            c->igt.off = reinterpret_cast<const int*>(base + rb);
+            c->igt.n = int(off.size() / 4);
+        }
+        igt = &c->igt;
+    }
     dda::launch_build_D(c->dfull.as<z128>(), c->g, c->d, k.real(), k.imag(),
                         c->tw128[0].as<z128>(), c->tw128[1].as<z128>(), c->tw128[2].as<z128>(),
-                        c->stream);
+                        c->stream, igt);
 }
 
 template <typename T>
@@ -1469,6 +1488,7 @@ void dda_default_options(dda_options* opt) {
     opt->maxit = 100000;
     opt->check_every = 16;
     opt->use_graphs = 1;
+    opt->interaction = DDA_INT_POINT;
 }
 
 double dda_beta_from_keV(double kinetic_keV) {
@@ -1704,6 +1724,8 @@ int dda_setup(const uint8_t* mask, int nx, int ny, int nz, double d_nm, double m
         throw Error(DDA_EINVAL, "host must be passive: Re m_h > 0, Im m_h >= 0");
     auto c = std::make_unique<dda_ctx>();
     if (opt) c->opt = *opt; else dda_default_options(&c->opt);
+    if (c->opt.interaction != DDA_INT_POINT && c->opt.interaction != DDA_INT_IGT)
+        throw Error(DDA_EINVAL, "unknown interaction");
     if (c->opt.polarizability < 0 || c->opt.polarizability > 2)
         throw Error(DDA_EINVAL, "unknown polarizability");
     if (c->opt.solver != DDA_SOLVER_BICGSTAB && c->opt.solver != DDA_SOLVER_COCG &&

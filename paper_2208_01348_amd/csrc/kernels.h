@@ -116,8 +116,23 @@ void launch_ixfft_pack(const cx<T>* G, const cx<T>* xin, const cx<T>* ainv, cx<T
 // matvec reads one of two stored layouts, extracted from it:
 //   corner [6][mz/2+1][my/2+1][mx/2+1]           (five-pass chain, dred_elems)
 //   kx slabs [mx/2+1][6][L/2+1][L/2+1], L = my = mz (three-pass chain, dyz_elems)
+// Integrated interaction (DDA_INT_IGT): near offsets o (|o| <= kIgtRadius,
+// o != 0, inside the embedding) take the average of G_tilde over the source
+// cell, d^-3 int_cube G_tilde(R + s) d^3 s, by a kIgtNodes-point
+// Gauss-Legendre rule per axis; every other offset keeps the point value.
+constexpr int kIgtNodes = 24;
+constexpr double kIgtRadius = 3.0;
+struct IgtTable {
+    int n = 0;                     // near offsets
+    const int* off = nullptr;      // device [n][4]: ox, oy, oz, linear index in the grid
+    const double* rule = nullptr;  // device [2][kIgtNodes]: nodes on [-1, 1], weights
+};
+// Host tables for IgtTable: offsets [n][4] and the rule [2][kIgtNodes]
+// (Legendre nodes by Newton's method on the three-term recurrence).
+void igt_host_tables(const Geo& g, std::vector<int>& off, std::vector<double>& rule);
 void launch_build_D(z128* full, const Geo& g, double d, double k_re, double k_im,
-                    const z128* tw_x, const z128* tw_y, const z128* tw_z, hipStream_t s);
+                    const z128* tw_x, const z128* tw_y, const z128* tw_z, hipStream_t s,
+                    const IgtTable* igt = nullptr);
 template <typename T>
 void launch_extract_corner(const z128* full, cx<T>* out, const Geo& g, hipStream_t s);
 template <typename T>

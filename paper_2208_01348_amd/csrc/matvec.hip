@@ -18,6 +18,7 @@
 // (coalesced), and transformed there by the compile-time planned Stockham
 // kernels of fft_core.h.
 #include <algorithm>
+#include <cmath>
 
 #include "fft_core.h"
 #include "kernels.h"
@@ -886,6 +887,31 @@ __device__ __forceinline__ bool embed_offset(int m, int n, int M, int& off) {
     return false;
 }
 
+// The six components xx, xy, xz, yy, yz, zz of G_tilde(R), R != 0.
+__device__ __forceinline__ void gtilde6(double rx, double ry, double rz, double k_re,
+                                        double k_im, z128 (&v)[6]) {
+    const double r2 = rx * rx + ry * ry + rz * rz;
+    const double r = sqrt(r2);
+    const double hx = rx / r, hy = ry / r, hz = rz / r;
+    // kr = k r (complex), e = exp(i k r) / r^3
+    const z128 kr{k_re * r, k_im * r};
+    double sn, cs;
+    sincos(kr.x, &sn, &cs);
+    const double mag = exp(-kr.y) / (r2 * r);
+    const z128 e{mag * cs, mag * sn};
+    const z128 kr2 = kr * kr;
+    const z128 a = e * z128{kr2.x - 1.0 - kr.y, kr2.y + kr.x};          // k2r2 + ikr - 1
+    const z128 b = e * z128{3.0 - kr2.x + 3.0 * kr.y, -3.0 * kr.x - kr2.y};  // 3 - 3ikr - k2r2
+    const double h[3] = {hx, hy, hz};
+    int q = 0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = i; j < 3; ++j) {
+            z128 val = (h[i] * h[j]) * b;
+            if (i == j) val = val + a;
+            v[q++] = val;
+        }
+}
+
 __global__ __launch_bounds__(NTHR) void k_gtens(z128* __restrict__ D, Geo g, double d,
                                                 double k_re, double k_im, double scale) {
     const int64_t plane = int64_t(g.my) * g.mx;
@@ -900,30 +926,95 @@ __global__ __launch_bounds__(NTHR) void k_gtens(z128* __restrict__ D, Geo g, dou
         for (int q = 0; q < 6; ++q) v[q] = z128{0.0, 0.0};
         if (embed_offset(mx, g.nx, g.mx, ox) && embed_offset(my, g.ny, g.my, oy) &&
             embed_offset(mz, g.nz, g.mz, oz) && (ox | oy | oz) != 0) {
-            const double rx = d * ox, ry = d * oy, rz = d * oz;
-            const double r2 = rx * rx + ry * ry + rz * rz;
-            const double r = sqrt(r2);
-            const double hx = rx / r, hy = ry / r, hz = rz / r;
-            // kr = k r (complex), e = exp(i k r) / r^3
-            const z128 kr{k_re * r, k_im * r};
-            double sn, cs;
-            sincos(kr.x, &sn, &cs);
-            const double mag = exp(-kr.y) / (r2 * r);
-            const z128 e{mag * cs, mag * sn};
-            const z128 kr2 = kr * kr;
-            const z128 a = e * z128{kr2.x - 1.0 - kr.y, kr2.y + kr.x};          // k2r2 + ikr - 1
-            const z128 b = e * z128{3.0 - kr2.x + 3.0 * kr.y, -3.0 * kr.x - kr2.y};  // 3 - 3ikr - k2r2
-            const double h[3] = {hx, hy, hz};
-            int q = 0;
-            for (int i = 0; i < 3; ++i)
-                for (int j = i; j < 3; ++j) {
-                    z128 val = (h[i] * h[j]) * b;
-                    if (i == j) val = val + a;
-                    v[q++] = scale * val;
-                }
+            gtilde6(d * ox, d * oy, d * oz, k_re, k_im, v);
+            for (int q = 0; q < 6; ++q) v[q] = scale * v[q];
         }
         for (int q = 0; q < 6; ++q) D[q * total + t] = v[q];
     }
+}
+
+// Near offsets of the integrated interaction: one block per offset averages
+// G_tilde over the source cell with the tensor Gauss-Legendre rule (FP64,
+// each thread a fixed share of the nodes, the block's sums added in a fixed
+// order) and overwrites the point value at that offset.
+__global__ __launch_bounds__(NTHR) void k_gtens_igt(z128* __restrict__ D, Geo g, double d,
+                                                    double k_re, double k_im, double scale,
+                                                    const int* __restrict__ off,
+                                                    const double* __restrict__ rule) {
+    constexpr int NG = kIgtNodes, NN = NG * NG * NG;
+    __shared__ double sm[NTHR / 64][12];
+    __shared__ double ru[2 * NG];
+    const int tid = threadIdx.x;
+    if (tid < 2 * NG) ru[tid] = rule[tid];
+    __syncthreads();
+    const int* o = off + 4 * blockIdx.x;
+    const double rx = d * o[0], ry = d * o[1], rz = d * o[2];
+    double acc[12];
+    for (int q = 0; q < 12; ++q) acc[q] = 0.0;
+    for (int p = tid; p < NN; p += NTHR) {
+        const int a = p / (NG * NG), b = (p / NG) % NG, c = p % NG;
+        const double w = 0.125 * ru[NG + a] * ru[NG + b] * ru[NG + c];
+        z128 v[6];
+        gtilde6(rx + 0.5 * d * ru[a], ry + 0.5 * d * ru[b], rz + 0.5 * d * ru[c], k_re, k_im, v);
+        for (int q = 0; q < 6; ++q) {
+            acc[2 * q] += w * v[q].x;
+            acc[2 * q + 1] += w * v[q].y;
+        }
+    }
+    for (int q = 0; q < 12; ++q) {
+        double x = acc[q];
+        for (int s = 32; s > 0; s >>= 1) x += __shfl_down(x, s, 64);
+        acc[q] = x;
+    }
+    if ((tid & 63) == 0)
+        for (int q = 0; q < 12; ++q) sm[tid >> 6][q] = acc[q];
+    __syncthreads();
+    if (tid < 6) {
+        double re = 0.0, im = 0.0;
+        for (int w = 0; w < NTHR / 64; ++w) {
+            re += sm[w][2 * tid];
+            im += sm[w][2 * tid + 1];
+        }
+        const int64_t total = int64_t(g.mx) * g.my * g.mz;
+        D[tid * total + o[3]] = z128{scale * re, scale * im};
+    }
+}
+
+void igt_host_tables(const Geo& g, std::vector<int>& off, std::vector<double>& rule) {
+    constexpr int NG = kIgtNodes;
+    rule.assign(2 * NG, 0.0);
+    for (int i = 0; i < NG; ++i) {
+        // Newton's method on P_NG from the Chebyshev-like first guess
+        double x = std::cos(3.14159265358979323846 * (i + 0.75) / (NG + 0.5));
+        double dp = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = x;
+            for (int n = 2; n <= NG; ++n) {
+                const double p2 = ((2.0 * n - 1.0) * x * p1 - (n - 1.0) * p0) / n;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = NG * (x * p1 - p0) / (x * x - 1.0);
+            const double dx = p1 / dp;
+            x -= dx;
+            if (std::fabs(dx) < 1e-16) break;
+        }
+        rule[i] = x;
+        rule[NG + i] = 2.0 / ((1.0 - x * x) * dp * dp);
+    }
+    off.clear();
+    const int r = int(kIgtRadius);
+    for (int oz = -r; oz <= r; ++oz)
+        for (int oy = -r; oy <= r; ++oy)
+            for (int ox = -r; ox <= r; ++ox) {
+                const int q = ox * ox + oy * oy + oz * oz;
+                if (q == 0 || q > int(kIgtRadius * kIgtRadius + 1e-9)) continue;
+                if (std::abs(ox) > g.nx - 1 || std::abs(oy) > g.ny - 1 || std::abs(oz) > g.nz - 1)
+                    continue;
+                const int64_t ix = ox >= 0 ? ox : g.mx + ox, iy = oy >= 0 ? oy : g.my + oy;
+                const int64_t iz = oz >= 0 ? oz : g.mz + oz;
+                off.insert(off.end(), {ox, oy, oz, int((iz * g.my + iy) * g.mx + ix)});
+            }
 }
 
 template <int L>
@@ -972,12 +1063,17 @@ template void launch_extract_corner<double>(const z128*, z128*, const Geo&, hipS
 template void launch_extract_corner<float>(const z128*, z64*, const Geo&, hipStream_t);
 
 void launch_build_D(z128* D, const Geo& g, double d, double k_re, double k_im,
-                    const z128* tw_x, const z128* tw_y, const z128* tw_z, hipStream_t s) {
+                    const z128* tw_x, const z128* tw_y, const z128* tw_z, hipStream_t s,
+                    const IgtTable* igt) {
     const int64_t plane = int64_t(g.my) * g.mx;
     const int64_t total = plane * g.mz;
     const double scale = 1.0 / double(total);
     k_gtens<<<nblk(total, NTHR), NTHR, 0, s>>>(D, g, d, k_re, k_im, scale);
     DDA_LAUNCH_CHECK();
+    if (igt && igt->n > 0) {
+        k_gtens_igt<<<igt->n, NTHR, 0, s>>>(D, g, d, k_re, k_im, scale, igt->off, igt->rule);
+        DDA_LAUNCH_CHECK();
+    }
     const int64_t nrows = 6 * int64_t(g.mz) * g.my;
     switch (g.mx) {
 #define DDA_CASE(N)                                                                \

@@ -44,7 +44,7 @@ class DDASolver:
                  precision: str = "fp64", tol: float = 1e-10, maxit: int = 100000,
                  solver: str = "bicgstab",
                  check_every: int = 16, stream: Optional[torch.cuda.Stream] = None,
-                 use_graphs: bool = True):
+                 use_graphs: bool = True, interaction: str = "point"):
         m = np.ascontiguousarray(np.asarray(mask, dtype=np.uint8))
         if m.ndim != 3:
             raise ValueError("mask must be [nz][ny][nx]")
@@ -65,6 +65,7 @@ class DDASolver:
         opt.maxit = int(maxit)
         opt.check_every = int(check_every)
         opt.use_graphs = 1 if use_graphs else 0
+        opt.interaction = {"point": L.DDA_INT_POINT, "igt": L.DDA_INT_IGT}[interaction]
         self.ctx = L.dda_setup(m, self.nx, self.ny, self.nz, self.d, self.m_h.real,
                                self.m_h.imag, opt, self.stream.cuda_stream)
         self.n_occ = L.dda_n_occ(self.ctx)

@@ -359,3 +359,16 @@ def test_qmr_cs_quasi_residual_bounds_the_residual_and_decreases():
     qmr_cs(centres, alpha, k, b, tol=1e-300, maxit=40, callback=cb)
     assert all(ok)
     assert all(t1 <= t0 * (1 + 1e-12) for t0, t1 in zip(taus, taus[1:]))
+
+
+def test_igt_interaction_keeps_the_budget_and_changes_the_result():
+    """With the cell-averaged near interaction the matrix is still complex
+    symmetric, so the discrete budget P_ext = P_abs + P_CL (real host) still
+    holds; the near-field change moves the result by far more than rounding."""
+    mask, d, eps, m_h, beta, r0, E, pol = _small_case()
+    n = int(mask.sum())
+    a = solve_point(mask, d, [eps] * n, m_h, beta, r0, E, pol=pol, interaction="igt")
+    b = solve_point(mask, d, [eps] * n, m_h, beta, r0, E, pol=pol, method="lu")
+    assert a.p_eels == pytest.approx(a.p_ext, rel=1e-11)
+    assert a.p_abs + a.p_cl == pytest.approx(a.p_ext, rel=1e-11)
+    assert abs(a.p_eels - b.p_eels) > 1e-3 * abs(b.p_eels)
