@@ -470,6 +470,7 @@ void autotune(dda_ctx* c, const Work& w, const int* act, int n_act,
     // the fastest candidate; returns {choice, default width's time, best time}
     // (choice 0 keeps the default: no candidate beat it)
     auto pick = [&](const std::vector<int>& cands, auto&& launch_with) {
+        if (cands.empty()) return std::array<double, 3>{0.0, 0.0, 0.0};  // nothing to choose
         const double t_def = time_of([&] { launch_with(0); });
         int best_v = 0;
         double best_t = t_def;

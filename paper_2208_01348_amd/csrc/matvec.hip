@@ -358,7 +358,7 @@ __global__ __launch_bounds__(NTHR) void k_zconv(cx<T>* __restrict__ G,
 // lines as [kz][line]), with five barriers per block.  Lines are
 // (mirror set, component, column), consecutive lanes taking consecutive
 // columns, so every global access is a run of TX columns.
-template <int L, int CS = 8>
+template <int L>
 constexpr int zc2_r1() {
     return L == 48 ? 8 : L == 64 ? 8 : L == 96 ? 16 : L == 128 ? 16 : L == 192 ? 16
          : L == 256 ? 16 : 0;
@@ -368,13 +368,12 @@ constexpr bool zc2_ok() { return zc2_r1<L>() > 0; }
 template <typename T, int L, int TX>
 constexpr size_t zc2_lds_bytes() { return size_t(L) * (6 * TX) * sizeof(cx<T>) + L * sizeof(cx<T>); }
 
-template <typename T, int L, int TX, int NT>
+template <typename T, int L, int TX, int NT, int R1>
 __global__ __launch_bounds__(NT) void k_zconv2(cx<T>* __restrict__ G,
                                                const cx<T>* const* __restrict__ Dptr,
                                                const cx<T>* __restrict__ tw, Geo g,
                                                const int* __restrict__ act,
                                                const int* __restrict__ slot_sys, SlotFilter f) {
-    constexpr int R1 = zc2_r1<L, int(sizeof(cx<T>))>();
     constexpr int R2 = L / R1;
     constexpr int W = 6 * TX;  // lines: (mirror set, component, column)
     static_assert(R1 % 2 == 0, "the first radix must be even");
@@ -701,25 +700,35 @@ void run_zconv(cx<T>* G, const cx<T>* const* Dptr, const cx<T>* tw_z, const Geo&
 
 // Tile codes of the two-stage z pass: TX columns per block and NT threads,
 // code = TX | (NT / 64) << 6.  Candidates keep the block's LDS within 100 KB;
-// 512 threads only where every thread has a second-stage butterfly.
-constexpr int zc2_code(int tx, int nt) { return tx | ((nt / 64) << 6); }
-template <typename T, int L, int TX, int NT>
+// 512 threads only where every thread has a second-stage butterfly.  All codes
+// of one radix plan give the same result bit for bit (they only regroup lines);
+// the two plans of a length round differently.
+// The radix plan is a tuning dimension too: ALT takes R1 = 8 (R2 = L/8 in the
+// second stage) where the default first radix is 16 and L/8 <= 24; code bit 12.
+constexpr int zc2_code(int tx, int nt, int alt = 0) { return tx | ((nt / 64) << 6) | (alt << 12); }
+template <int L, int ALT>
+constexpr int zc2_r1_of() { return ALT ? 8 : zc2_r1<L>(); }
+template <typename T, int L, int TX, int NT, int ALT = 0>
 constexpr bool zc2_fits() {
     return zc2_ok<L>() && zc2_lds_bytes<T, L, TX>() <= (size_t(100) << 10) &&
-           (NT <= 256 || 6 * TX * zc2_r1<L, int(sizeof(cx<T>))>() >= NT);
+           (NT <= 256 || 6 * TX * zc2_r1_of<L, ALT>() >= NT) &&
+           (!ALT || (zc2_r1<L>() == 16 && L / 8 <= 24));
 }
 template <typename T, int L>
 constexpr int zc2_default() {
     return sizeof(T) == 4 ? (zc2_fits<T, L, 8, 256>() ? zc2_code(8, 256) : zc2_code(4, 256))
                           : (zc2_fits<T, L, 4, 256>() ? zc2_code(4, 256) : zc2_code(2, 256));
 }
-#define DDA_ZC2_TILES(X) X(4, 256) X(4, 512) X(8, 256) X(8, 512) X(16, 256) X(16, 512) X(2, 256)
+#define DDA_ZC2_TILES(X)                                                                   \
+    X(4, 256, 0) X(4, 512, 0) X(8, 256, 0) X(8, 512, 0) X(16, 256, 0) X(16, 512, 0)       \
+    X(2, 256, 0) X(4, 256, 1) X(8, 256, 1) X(8, 512, 1)
 
-template <typename T, int L, int TX, int NT>
+template <typename T, int L, int TX, int NT, int ALT>
 void run_zconv2(cx<T>* G, const cx<T>* const* Dptr, const cx<T>* tw_z, const Geo& g,
                 const int* act, const int* slot_sys, int n_act, SlotFilter f, hipStream_t s) {
     dim3 grid(nblk(g.mx, TX), g.my / 2 + 1, n_act);
-    k_zconv2<T, L, TX, NT><<<grid, NT, 0, s>>>(G, Dptr, tw_z, g, act, slot_sys, f);
+    k_zconv2<T, L, TX, NT, zc2_r1_of<L, ALT>()><<<grid, NT, 0, s>>>(G, Dptr, tw_z, g, act,
+                                                                    slot_sys, f);
 }
 
 template <typename T, int L>
@@ -727,10 +736,10 @@ void zconv_tx_run(int tx, cx<T>* G, const cx<T>* const* Dptr, const cx<T>* tw_z,
                   const int* act, const int* slot_sys, int n_act, SlotFilter f, hipStream_t s) {
     if constexpr (zc2_ok<L>()) {
         const int code = tx ? tx : zc2_default<T, L>();
-#define DDA_TX(W, N)                                                                      \
-    if constexpr (zc2_fits<T, L, W, N>())                                                 \
-        if (code == zc2_code(W, N))                                                       \
-            return run_zconv2<T, L, W, N>(G, Dptr, tw_z, g, act, slot_sys, n_act, f, s);
+#define DDA_TX(W, N, A)                                                                   \
+    if constexpr (zc2_fits<T, L, W, N, A>())                                              \
+        if (code == zc2_code(W, N, A))                                                    \
+            return run_zconv2<T, L, W, N, A>(G, Dptr, tw_z, g, act, slot_sys, n_act, f, s);
         DDA_ZC2_TILES(DDA_TX)
 #undef DDA_TX
         throw Error(-1, "z pass: not a tile of this length");
@@ -790,8 +799,8 @@ template <typename T>
 std::vector<int> zconv_tx_candidates(int L) {
     std::vector<int> v;
     switch (L) {
-#define DDA_ZC2C(W, N) \
-    if constexpr (zc2_fits<T, LL, W, N>()) v.push_back(zc2_code(W, N));
+#define DDA_ZC2C(W, N, A) \
+    if constexpr (zc2_fits<T, LL, W, N, A>()) v.push_back(zc2_code(W, N, A));
 #define DDA_CASE(N)                                                                    \
     case N: {                                                                          \
         constexpr int LL = N;                                                          \

@@ -810,8 +810,8 @@ template void launch_yzconv<float>(z64*, const z64* const*, const z64*, const z6
                                    const int*, const int*, int, SlotFilter, int, hipStream_t);
 
 std::vector<int> yz_thread_candidates(int L) {
-    (void)L;  // the register kernel has one shape per L
-    return {NTYZ};
+    (void)L;  // the register kernel has one shape per L: nothing to tune
+    return {};
 }
 template void launch_extract_yz<double>(const z128*, z128*, const Geo&, hipStream_t);
 template void launch_extract_yz<float>(const z128*, z64*, const Geo&, hipStream_t);

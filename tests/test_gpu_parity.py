@@ -393,18 +393,21 @@ def test_bicgstab_same_iterates_for_any_interval_and_graphs(precision):
         assert np.array_equal(pk, out[0][0])
 
 
-ZC2_CODES = [tx | ((nt // 64) << 6) for tx in (2, 4, 8, 16) for nt in (256, 512)]
+ZC2_CODES = [tx | ((nt // 64) << 6) | (alt << 12) for tx in (2, 4, 8, 16) for nt in (256, 512)
+             for alt in (0, 1)]
 
 
 @pytest.mark.parametrize("shape", [(12, 12, 12), (12, 12, 16), (16, 8, 12), (16, 12, 24),
-                                   (8, 20, 40)])
+                                   (8, 20, 40), (6, 20, 64)])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_every_autotuner_candidate_gives_identical_matvecs(shape, precision):
-    """The autotuner only regroups lines into blocks: every candidate tile of
-    the five-pass z and y passes (my != mz) gives the same matvec to the last
-    bit (the fused yz kernel of a cubic grid has a single shape per length).
-    z grids of 48 and 96 take the two-stage z pass, whose tile codes are
-    TX | (threads / 64) << 6."""
+    """The autotuner's tile candidates only regroup lines into blocks: every
+    candidate of the five-pass z and y passes (my != mz) gives the same matvec
+    to the last bit (the fused yz kernel of a cubic grid has a single shape
+    per length).  z grids of 48 and 96 take the two-stage z pass, whose codes
+    are TX | (threads / 64) << 6 | plan << 12; the two radix plans of a length
+    (first radix 16 or 8) round differently, so results are bit-identical
+    within a plan and agree to rounding across plans."""
     nx, ny, nz = shape
     mask = np.ones((nz, ny, nx), np.uint8)
     s = DDASolver(mask, 1.0, 1.45)
@@ -417,7 +420,7 @@ def test_every_autotuner_candidate_gives_identical_matvecs(shape, precision):
     yzc = [0, 256, 512, 1024] if my == mz else [0]
     zc = [0] if my == mz else [0, 1, 2, 4, 8] + ZC2_CODES
     mc = [0] if my == mz else [0, 4, 8, 16, 32]
-    ref = None
+    ref = {}
     tried = 0
     for yt in yzc:
         for zt in zc:
@@ -428,11 +431,15 @@ def test_every_autotuner_candidate_gives_identical_matvecs(shape, precision):
                     continue  # not a candidate for this grid and precision
                 y = s.matvec(2.2, eps, x, precision=precision).cpu().numpy()
                 tried += 1
-                if ref is None:
-                    ref = y
+                plan = (zt >> 12) & 1
+                if plan not in ref:
+                    ref[plan] = y
                 else:
-                    assert np.array_equal(y, ref), (yt, zt, mt)
+                    assert np.array_equal(y, ref[plan]), (yt, zt, mt)
     assert tried >= (1 if my == mz else 3)
+    if len(ref) == 2:
+        bar = 1e-13 if precision == "fp64" else 1e-6
+        assert np.linalg.norm(ref[0] - ref[1]) <= bar * np.linalg.norm(ref[0])
     s.close()
 
 
