@@ -322,11 +322,17 @@ int dda_matvec(dda_ctx* ctx, double energy_eV, const double* eps_dipole, int pre
                int interaction_only, const void* x_dev, void* y_dev, int nrhs);
 
 /*
- * Continuous batching (COCG only; serving many requests on one lattice).
+ * Continuous batching (COCG only): many systems of one box of lattice cells
+ * iterate in the slots of one engine.  The interaction spectrum D depends only
+ * on the box, the dipole size and the host wavenumber (the Green's tensor of
+ * eq. (5) on the embedding grid), not on which cells are occupied, so every
+ * lattice in the box can share the engine: each slot carries its lattice's
+ * index map (dda_engine_submit_lattice).
  * Device bytes an engine with n_slots slots holds, counting one interaction
  * spectrum D per slot (the worst case: every slot at a distinct energy):
- * per-slot Krylov vectors, 1/alpha, the FFT work buffer and D in the
- * context's precision.  A server admits lattices by this footprint.
+ * per-slot Krylov vectors, 1/alpha, the FFT work buffer, the slot's index map
+ * and D in the context's precision, plus the full-grid scratch of a D build.
+ * A server admits engines by this footprint.
  */
 int dda_workspace_bytes(const dda_ctx* ctx, int n_slots, size_t* bytes);
 
@@ -354,6 +360,24 @@ int dda_engine_submit(dda_ctx* ctx, int64_t tag, double energy_eV, const double*
                       const void* einc_dev, void* p_dev);
 
 /*
+ * dda_engine_submit for a system of another lattice `lat` in the engine
+ * context's box: lat must have the same nx, ny, nz, dipole size,
+ * polarizability and interaction as ctx and at most as many dipoles (an
+ * engine opened on a context whose mask fills the box takes every lattice of
+ * that box).  The host index is lat's (dda_set_host on lat); eps_dipole
+ * [n][2], einc_dev and p_dev [3][n] with n = lat's dipole count, in lat's
+ * ordering.  The slot fills the first n of its entries and keeps the rest
+ * zero, so the system's iterates are those of a dda_solve on lat alone.  The
+ * call waits for lat's stream (the field written there is read at
+ * admission), and lat's stream waits for the copy of the solution into p_dev.
+ * lat must stay alive until the tag comes back.
+ * Errors: DDA_EINVAL for a lattice that does not fit the engine, as well as
+ * dda_engine_submit's.
+ */
+int dda_engine_submit_lattice(dda_ctx* ctx, dda_ctx* lat, int64_t tag, double energy_eV,
+                              const double* eps_dipole, const void* einc_dev, void* p_dev);
+
+/*
  * Runs up to max_intervals COCG intervals.  Before each one it harvests the
  * slots that finished (their p_dev copy is queued on the stream) and admits
  * queued systems into free slots; systems admitted while others are halfway
@@ -367,7 +391,9 @@ int dda_engine_submit(dda_ctx* ctx, int64_t tag, double energy_eV, const double*
 int dda_engine_poll(dda_ctx* ctx, int max_intervals, int64_t* tags, dda_solve_info* info,
                     int capacity, int* n_done);
 
-/* Systems queued, in slots, and finished but not yet returned. */
+/* Systems queued, in slots, and finished but not yet returned (the last two
+ * as the polling thread last left them); may be called from another thread
+ * than the one polling. */
 int dda_engine_status(dda_ctx* ctx, int* queued, int* running, int* finished);
 
 /* Waits for the stream and frees the slot pool (queued systems are dropped). */
@@ -410,9 +436,10 @@ int dda_set_timing(dda_ctx* ctx, int enabled);
 int dda_kernel_time(dda_ctx* ctx, const char* name, double* avg_ms, int64_t* launches,
                     double* avg_rhs);
 
-/* Frees the cached interaction spectra D(k) (they are rebuilt on demand).
- * The context keeps one D per host wavenumber it has seen, up to a memory
- * limit; callers that sweep many energies once can release them here. */
+/* Frees the cached interaction spectra D(k) (they are rebuilt on demand),
+ * except those a system in the context's engine still solves with.  The
+ * context keeps one D per host wavenumber it has seen, up to a memory limit;
+ * callers that sweep many energies once can release them here. */
 int dda_drop_cache(dda_ctx* ctx);
 
 int dda_destroy(dda_ctx* ctx);

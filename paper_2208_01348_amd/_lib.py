@@ -26,7 +26,7 @@ EXPORTED = ["dda_default_options", "dda_beta_from_keV", "dda_setup", "dda_n_occ"
             "dda_grid_dims", "dda_einc_electron", "dda_einc_electron_noalloc", "dda_solve", "dda_eels_cl", "dda_matvec",
             "dda_set_timing", "dda_kernel_time", "dda_drop_cache", "dda_destroy",
             "dda_last_error", "dda_debug_besselk01", "dda_workspace_bytes", "dda_engine_open",
-            "dda_engine_submit", "dda_engine_poll", "dda_engine_status", "dda_engine_close",
+            "dda_engine_submit", "dda_engine_submit_lattice", "dda_engine_poll", "dda_engine_status", "dda_engine_close",
             "dda_set_host", "dda_stream_create", "dda_stream_destroy", "dda_tuning",
             "dda_set_tuning", "dda_free_space_loss", "dda_cl_total", "dda_psf_gauss",
             "dda_cl_directions", "dda_richardson"]
@@ -91,6 +91,7 @@ def load() -> ctypes.CDLL:
         "dda_workspace_bytes": (_i, [_vp, _i, _vp]),
         "dda_engine_open": (_i, [_vp, _i]),
         "dda_engine_submit": (_i, [_vp, _i64, _d, _vp, _vp, _vp]),
+        "dda_engine_submit_lattice": (_i, [_vp, _vp, _i64, _d, _vp, _vp, _vp]),
         "dda_engine_poll": (_i, [_vp, _i, _vp, _vp, _i, _vp]),
         "dda_engine_status": (_i, [_vp, _vp, _vp, _vp]),
         "dda_engine_close": (_i, [_vp]),
@@ -360,6 +361,15 @@ def dda_engine_submit(ctx, tag: int, energy_eV: float, eps_dipole, einc_dev: int
     eps = _eps_pairs(eps_dipole)
     _check(load().dda_engine_submit(ctx, int(tag), float(energy_eV), _ptr(eps),
                                     ctypes.c_void_p(einc_dev), ctypes.c_void_p(p_dev)))
+
+
+def dda_engine_submit_lattice(ctx, lat, tag: int, energy_eV: float, eps_dipole, einc_dev: int,
+                              p_dev: int) -> None:
+    """A system of lattice context `lat` (same box) in ctx's engine;
+    eps_dipole: complex [n_occ(lat)]."""
+    eps = _eps_pairs(eps_dipole)
+    _check(load().dda_engine_submit_lattice(ctx, lat, int(tag), float(energy_eV), _ptr(eps),
+                                            ctypes.c_void_p(einc_dev), ctypes.c_void_p(p_dev)))
 
 
 def dda_engine_poll(ctx, max_intervals: int, capacity: int = 256):

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <array>
 #include <cmath>
 #include <limits>
@@ -266,6 +267,11 @@ struct dda_ctx {
     DevBuf map, occ;
     DevBuf tw128[3], tw64[3];
     std::map<std::pair<double, double>, std::unique_ptr<DEntry>> dcache;
+    // evicted entries whose buffers the next misses reuse: freeing device
+    // memory waits for the whole device, which stalls every other stream's
+    // host thread in a multi-lattice server; every reader of a D is on this
+    // context's stream, so a reused buffer is rewritten only after them
+    std::vector<std::unique_ptr<DEntry>> dspare;
     uint64_t use_clock = 0;
     uint64_t pin_clock = 0;   // entries used at or after this tick are in use
     size_t dcache_limit = size_t(64) << 30;
@@ -415,6 +421,8 @@ struct Work {
     dda::BicgSlot* st;
     dda::RedScratch red;
     void* G;
+    const int* map = nullptr;  // per-slot index maps (slot s at map + s * map_stride), or
+    int64_t map_stride = 0;    // nullptr: the context's own map for every slot
 };
 Work ctx_work(dda_ctx* c) { return Work{c->st.as<dda::BicgSlot>(), red_of(c), c->G.p}; }
 
@@ -540,7 +548,12 @@ void matvec(dda_ctx* c, const Work& w, dda::cx<T>* x, dda::cx<T>* y, const int* 
     if (n_act == 0 || c->g.n_occ == 0) return;
     if ((fuse_r || f.mode != dda::FILTER_ALL) && !f.st)
         throw Error(DDA_EDEVICE, "slot filter without slot states");
-    const dda::Geo& g = c->g;
+    dda::Geo g = c->g;
+    const int* map = c->map.as<int>();
+    if (w.map) {
+        map = w.map;
+        g.map_stride = w.map_stride;
+    }
     auto* G = static_cast<dda::cx<T>*>(w.G);
     hipStream_t s = c->stream;
     constexpr int csize = int(sizeof(dda::cx<T>));
@@ -549,7 +562,7 @@ void matvec(dda_ctx* c, const Work& w, dda::cx<T>* x, dda::cx<T>* y, const int* 
     if (dda::yz_fused_ok(g, csize)) {
         {
             Tic t(c, 0, n_act);
-            dda::launch_xfft_t<T>(x, c->map.as<int>(), G, tw_of<T>(c, 0), g, act, n_act, fuse_r,
+            dda::launch_xfft_t<T>(x, map, G, tw_of<T>(c, 0), g, act, n_act, fuse_r,
                                   f, s);
         }
         {
@@ -559,14 +572,14 @@ void matvec(dda_ctx* c, const Work& w, dda::cx<T>* x, dda::cx<T>* y, const int* 
         }
         {
             Tic t(c, 4, n_act);
-            dda::launch_ixfft_t<T>(G, x, ainv, y, c->map.as<int>(), tw_of<T>(c, 0), g, act,
+            dda::launch_ixfft_t<T>(G, x, ainv, y, map, tw_of<T>(c, 0), g, act,
                                    slot_sys, n_act, mode, f, w.red, s, dotw);
         }
     } else {
         const int64_t plane = int64_t(g.my) * g.mx;
         {
             Tic t(c, 0, n_act);
-            dda::launch_unpack_xfft<T>(x, c->map.as<int>(), G, tw_of<T>(c, 0), g, act, n_act,
+            dda::launch_unpack_xfft<T>(x, map, G, tw_of<T>(c, 0), g, act, n_act,
                                        fuse_r, f, s);
         }
         {
@@ -586,7 +599,7 @@ void matvec(dda_ctx* c, const Work& w, dda::cx<T>* x, dda::cx<T>* y, const int* 
         }
         {
             Tic t(c, 4, n_act);
-            dda::launch_ixfft_pack<T>(G, x, ainv, y, c->map.as<int>(), tw_of<T>(c, 0), g, act,
+            dda::launch_ixfft_pack<T>(G, x, ainv, y, map, tw_of<T>(c, 0), g, act,
                                       slot_sys, n_act, mode, f, w.red, s, dotw);
         }
     }
@@ -660,9 +673,18 @@ DEntry* get_D_k(dda_ctx* c, cplx k, bool need64) {
                     victim = i2;
             if (victim == c->dcache.end()) break;  // everything cached is in use
             used -= victim->second->d128.bytes + victim->second->d64.bytes;
+            if (c->dspare.size() < 2) c->dspare.push_back(std::move(victim->second));
             c->dcache.erase(victim);
         }
-        auto ne = std::make_unique<DEntry>();
+        std::unique_ptr<DEntry> ne;
+        if (!c->dspare.empty()) {
+            ne = std::move(c->dspare.back());
+            c->dspare.pop_back();
+            ne->has64 = false;
+            ne->refs = 0;
+        } else {
+            ne = std::make_unique<DEntry>();
+        }
         ne->d128.ensure(b128);
         build_full_D(c, k);
         full_ready = true;
@@ -1217,10 +1239,11 @@ int systems_per_chunk(dda_ctx* c, int n_energy, int n_traj, bool mixed) {
 struct Pending {
     int64_t tag;
     double energy;
-    cplx mh;  // host index of the context when the system was submitted
-    std::vector<double> eps;  // [n_occ][2]
-    const z128* einc;
-    z128* out;
+    cplx mh;  // host index of the lattice's context when the system was submitted
+    std::vector<double> eps;  // [n][2]
+    const z128* einc;         // [3][n]
+    z128* out;                // [3][n]
+    const dda_ctx* lat;       // the system's lattice (its index map, n dipoles)
 };
 
 struct SlotRec {
@@ -1229,14 +1252,17 @@ struct SlotRec {
     int64_t admitted = 0;  // first interval the system takes part in
     DEntry* d = nullptr;
     z128* out = nullptr;
+    const dda_ctx* lat = nullptr;
 };
 
 struct Engine {
     int cap = 0;
     bool mixed = false;
     DevBuf st, partial, slot_sys, G, b, x, r, p, q, xlo, y64, ainv128, ainv64, dtab, eps, msys, err;
+    DevBuf maps;                     // [cap][nx ny nz]: each slot's lattice index map
     PinnedBuf h_eps, h_small;        // staging of admitted permittivities and tables
     hipEvent_t stage_ev = nullptr;   // the last copy out of the staging buffers
+    hipEvent_t out_ev = nullptr;     // a harvest copy, for the stream of another lattice
     ActRing act, adm;                // interval list; list of slots being admitted
     StateRing ring;
     GraphCache graph;
@@ -1248,10 +1274,18 @@ struct Engine {
     std::mutex mu;  // guards queue: dda_engine_submit may run on another thread
     int64_t sent = 0;  // intervals sent
     std::deque<std::pair<int64_t, dda_solve_info>> done;
+    // sizes of running and done as the polling thread last left them, for
+    // dda_engine_status from other threads
+    std::atomic<int> n_running{0}, n_done{0};
+    void publish() {
+        n_running.store(int(running.size()), std::memory_order_relaxed);
+        n_done.store(int(done.size()), std::memory_order_relaxed);
+    }
     Engine() = default;
     Engine(const Engine&) = delete;
     ~Engine() {
         if (stage_ev) (void)hipEventDestroy(stage_ev);
+        if (out_ev) (void)hipEventDestroy(out_ev);
     }
 };
 
@@ -1266,6 +1300,7 @@ size_t engine_slot_bytes(const dda_ctx* c, bool mixed) {
     b += n * (sizeof(z128) + (mixed ? sizeof(z64) : 0));                // 1/alpha
     b += n * sizeof(z128);                                              // eps staging
     b += ge * sizeof(z128);                                             // grid work buffer
+    b += size_t(c->g.nx) * c->g.ny * c->g.nz * sizeof(int);            // index map
     b += size_t(c->max_blocks) * 8 * sizeof(double) + sizeof(dda::BicgSlot) + 64;
     b += d_elems(c, 16) * sizeof(z128) + (mixed ? d_elems(c, 8) * sizeof(z64) : 0);
     return b;
@@ -1274,8 +1309,9 @@ size_t engine_slot_bytes(const dda_ctx* c, bool mixed) {
 template <typename T>
 CocgBufs<T> engine_bufs(dda_ctx* c, Engine& E, const int* act) {
     const size_t nv = size_t(c->nv());
+    const int64_t cells = int64_t(c->g.nx) * c->g.ny * c->g.nz;
     const Work w{E.st.as<dda::BicgSlot>(), dda::RedScratch{E.partial.as<double>(), c->max_blocks},
-                 E.G.p};
+                 E.G.p, E.maps.as<int>(), cells};
     auto** tab = reinterpret_cast<const void**>(E.dtab.p);
     constexpr bool mixed = std::is_same<T, float>::value;
     CocgBufs<T> B{w, act, E.slot_sys.as<int>(), E.b.as<z128>(), E.x.as<z128>(),
@@ -1304,6 +1340,11 @@ void engine_open(dda_ctx* c, int cap) {
     auto E = std::make_unique<Engine>();
     E->cap = cap;
     E->mixed = c->opt.precision == DDA_PREC_MIXED;
+    // D entries beyond one per slot (dda_workspace_bytes counts those) are
+    // evicted, their buffers reused by the next wavenumber
+    c->dcache_limit = std::min(c->dcache_limit,
+                               size_t(cap) * (d_elems(c, 16) * sizeof(z128) +
+                                              (E->mixed ? d_elems(c, 8) * sizeof(z64) : 0)));
     const size_t nv = size_t(c->nv()), n = size_t(c->g.n_occ), k = size_t(cap);
     E->st.ensure(k * sizeof(dda::BicgSlot));
     E->partial.ensure(k * c->max_blocks * 8 * sizeof(double));
@@ -1322,7 +1363,9 @@ void engine_open(dda_ctx* c, int cap) {
     E->err.ensure(k * sizeof(int));
     E->h_eps.ensure(k * n * sizeof(z128));
     E->h_small.ensure(k * (sizeof(dda::MatSys) + 2 * sizeof(void*)));
+    E->maps.ensure(k * size_t(c->g.nx) * c->g.ny * c->g.nz * sizeof(int));
     DDA_HIP_CHECK(hipEventCreateWithFlags(&E->stage_ev, hipEventDisableTiming));
+    DDA_HIP_CHECK(hipEventCreateWithFlags(&E->out_ev, hipEventDisableTiming));
     E->act.ensure(cap);
     E->adm.ensure(cap);
     E->ring.ensure(cap);
@@ -1356,8 +1399,16 @@ void engine_harvest(dda_ctx* c, Engine& E, int64_t j) {
     for (int s : E.running) {
         SlotRec& sr = E.slots[s];
         if (sr.admitted <= j && dda::slot_terminal(S[s].status)) {
-            DDA_HIP_CHECK(hipMemcpyAsync(sr.out, E.x.as<z128>() + size_t(s) * nv,
-                                         nv * sizeof(z128), hipMemcpyDeviceToDevice, c->stream));
+            const size_t n = size_t(sr.lat->g.n_occ), cap_n = size_t(c->g.n_occ);
+            // [3][n] out of the slot's [3][cap_n]
+            DDA_HIP_CHECK(hipMemcpy2DAsync(sr.out, n * sizeof(z128),
+                                           E.x.as<z128>() + size_t(s) * nv, cap_n * sizeof(z128),
+                                           n * sizeof(z128), 3, hipMemcpyDeviceToDevice,
+                                           c->stream));
+            if (sr.lat != c) {  // the lattice's own stream reads the result next
+                DDA_HIP_CHECK(hipEventRecord(E.out_ev, c->stream));
+                DDA_HIP_CHECK(hipStreamWaitEvent(sr.lat->stream, E.out_ev, 0));
+            }
             E.done.emplace_back(sr.tag, info_of(S[s]));
             engine_release(c, sr);
         } else {
@@ -1366,8 +1417,26 @@ void engine_harvest(dda_ctx* c, Engine& E, int64_t j) {
     }
     if (keep.size() != E.running.size()) {
         E.running.swap(keep);
+        E.publish();
         E.act_dirty = true;
     }
+}
+
+// Zeroes every per-slot vector of slot s (outside any capture): a matvec
+// writes only the entries of the slot's dipoles, so the entries past them
+// must start, and then stay, zero.
+template <typename T>
+void engine_clear_slot(dda_ctx* c, Engine& E, int s) {
+    const size_t nv = size_t(c->nv()), cap = size_t(E.cap);
+    hipStream_t st = c->stream;
+    for (DevBuf* v : {&E.b, &E.x, &E.y64})
+        DDA_HIP_CHECK(hipMemsetAsync(v->as<z128>() + size_t(s) * nv, 0, nv * sizeof(z128), st));
+    auto* R = static_cast<dda::cx<T>*>(E.r.p);
+    for (int j = 0; j < 3; ++j)
+        DDA_HIP_CHECK(hipMemsetAsync(R + j * nv * cap + size_t(s) * nv, 0,
+                                     nv * sizeof(dda::cx<T>), st));
+    if (E.xlo.p)
+        DDA_HIP_CHECK(hipMemsetAsync(E.xlo.as<z64>() + size_t(s) * nv, 0, nv * sizeof(z64), st));
 }
 
 template <typename T>
@@ -1387,6 +1456,7 @@ void engine_admit(dda_ctx* c, Engine& E) {
     if (take.empty()) return;
     const int na = int(take.size());
     const size_t n = size_t(c->g.n_occ), nv = size_t(c->nv());
+    const int64_t cells = int64_t(c->g.nx) * c->g.ny * c->g.nz;
     wait_event(E.stage_ev);  // the previous admission's copies have run
     auto* heps = E.h_eps.as<double>();
     auto* hsys = E.h_small.as<dda::MatSys>();
@@ -1405,13 +1475,28 @@ void engine_admit(dda_ctx* c, Engine& E) {
         sr.admitted = E.sent;
         sr.d = d;
         sr.out = pd.out;
+        sr.lat = pd.lat;
         E.dtab_h[s] = d->d128.p;
         E.dtab_h[E.cap + s] = mixed ? d->d64.p : nullptr;
-        std::memcpy(heps + 2 * n * size_t(i), pd.eps.data(), n * sizeof(z128));
+        const size_t ns = size_t(pd.lat->g.n_occ);
+        // a lattice with fewer dipoles than the slot holds fills a prefix;
+        // the padding takes its first permittivity (a finite 1/alpha that no
+        // matvec reads)
+        double* he = heps + 2 * n * size_t(i);
+        std::memcpy(he, pd.eps.data(), ns * sizeof(z128));
+        for (size_t t = ns; t < n; ++t) {
+            he[2 * t] = pd.eps[0];
+            he[2 * t + 1] = pd.eps[1];
+        }
         const cplx k = pd.mh * (pd.energy / kHbarC);
         hsys[i] = dda::MatSys{k.real(), k.imag(), pd.mh.real(), pd.mh.imag()};
-        DDA_HIP_CHECK(hipMemcpyAsync(E.b.as<z128>() + size_t(s) * nv, pd.einc, nv * sizeof(z128),
-                                     hipMemcpyDeviceToDevice, c->stream));
+        DDA_HIP_CHECK(hipMemcpyAsync(E.maps.as<int>() + size_t(s) * cells, pd.lat->map.p,
+                                     size_t(cells) * sizeof(int), hipMemcpyDeviceToDevice,
+                                     c->stream));
+        if (ns < n) engine_clear_slot<T>(c, E, s);  // padding entries stay zero in every vector
+        DDA_HIP_CHECK(hipMemcpy2DAsync(E.b.as<z128>() + size_t(s) * nv, n * sizeof(z128), pd.einc,
+                                       ns * sizeof(z128), ns * sizeof(z128), 3,
+                                       hipMemcpyDeviceToDevice, c->stream));
     }
     std::memcpy(htab, E.dtab_h.data(), E.dtab_h.size() * sizeof(void*));
     hipStream_t st = c->stream;
@@ -1433,6 +1518,7 @@ void engine_admit(dda_ctx* c, Engine& E) {
     dda::mark_invalid(B.w.st, E.adm.ptr(), E.err.as<int>(), na, st);
     E.running.insert(E.running.end(), adm.begin(), adm.end());
     std::sort(E.running.begin(), E.running.end());
+    E.publish();
     E.act_dirty = true;
 }
 
@@ -2123,7 +2209,9 @@ int dda_workspace_bytes(const dda_ctx* c, int n_slots, size_t* bytes) {
     DDA_API_BEGIN
     if (!c || !bytes) throw Error(DDA_EINVAL, "NULL argument");
     if (n_slots < 0) throw Error(DDA_EINVAL, "n_slots < 0");
-    *bytes = size_t(n_slots) * engine_slot_bytes(c, c->opt.precision == DDA_PREC_MIXED);
+    // the slots, plus the full-grid FP64 scratch of a D build (one per context)
+    *bytes = size_t(n_slots) * engine_slot_bytes(c, c->opt.precision == DDA_PREC_MIXED) +
+             (n_slots > 0 ? size_t(dda::dgrid_elems(c->g)) * sizeof(z128) : 0);
     return DDA_OK;
     DDA_API_END
 }
@@ -2137,21 +2225,40 @@ int dda_engine_open(dda_ctx* c, int max_slots) {
     DDA_API_END
 }
 
-int dda_engine_submit(dda_ctx* c, int64_t tag, double energy_eV, const double* eps_dipole,
-                      const void* einc_dev, void* p_dev) {
+int dda_engine_submit_lattice(dda_ctx* c, dda_ctx* lat, int64_t tag, double energy_eV,
+                              const double* eps_dipole, const void* einc_dev, void* p_dev) {
     DDA_API_BEGIN
     if (!c || !c->engine) throw Error(DDA_EINVAL, "no engine open on this context");
-    if (!eps_dipole || !einc_dev || !p_dev) throw Error(DDA_EINVAL, "NULL argument");
+    if (!lat || !eps_dipole || !einc_dev || !p_dev) throw Error(DDA_EINVAL, "NULL argument");
+    if (lat != c) {
+        if (lat->g.nx != c->g.nx || lat->g.ny != c->g.ny || lat->g.nz != c->g.nz ||
+            lat->d != c->d)
+            throw Error(DDA_EINVAL, "the lattice's box or dipole size differs from the engine's");
+        if (lat->opt.polarizability != c->opt.polarizability ||
+            lat->opt.interaction != c->opt.interaction)
+            throw Error(DDA_EINVAL, "the lattice's polarizability or interaction differs");
+        if (lat->g.n_occ > c->g.n_occ)
+            throw Error(DDA_EINVAL, "the lattice has more dipoles than an engine slot holds");
+        if (lat->g.n_occ == 0) throw Error(DDA_EINVAL, "the lattice has no dipoles");
+    }
     check_energies(1, &energy_eV);
-    const size_t n = size_t(c->g.n_occ);
-    Pending pd{tag, energy_eV, c->mh, std::vector<double>(eps_dipole, eps_dipole + 2 * n),
-               static_cast<const z128*>(einc_dev), static_cast<z128*>(p_dev)};
+    const size_t n = size_t(lat->g.n_occ);
+    Pending pd{tag, energy_eV, lat->mh, std::vector<double>(eps_dipole, eps_dipole + 2 * n),
+               static_cast<const z128*>(einc_dev), static_cast<z128*>(p_dev), lat};
     for (double v : pd.eps)
         if (!std::isfinite(v)) throw Error(DDA_EINVAL, "permittivity is not finite");
+    // the engine's stream copies einc at admission: what the lattice's stream
+    // queued (the field itself) must have run
+    if (lat != c) DDA_HIP_CHECK(hipStreamSynchronize(lat->stream));
     std::lock_guard<std::mutex> lk(c->engine->mu);
     c->engine->queue.push_back(std::move(pd));
     return DDA_OK;
     DDA_API_END
+}
+
+int dda_engine_submit(dda_ctx* c, int64_t tag, double energy_eV, const double* eps_dipole,
+                      const void* einc_dev, void* p_dev) {
+    return dda_engine_submit_lattice(c, c, tag, energy_eV, eps_dipole, einc_dev, p_dev);
 }
 
 int dda_engine_poll(dda_ctx* c, int max_intervals, int64_t* tags, dda_solve_info* info,
@@ -2168,6 +2275,7 @@ int dda_engine_poll(dda_ctx* c, int max_intervals, int64_t* tags, dda_solve_info
         tags[k] = E.done.front().first;
         info[k] = E.done.front().second;
         E.done.pop_front();
+        E.publish();
         ++k;
     }
     *n_done = k;
@@ -2184,8 +2292,8 @@ int dda_engine_status(dda_ctx* c, int* queued, int* running, int* finished) {
         std::lock_guard<std::mutex> lk(E.mu);
         *queued = int(E.queue.size());
     }
-    *running = int(E.running.size());
-    *finished = int(E.done.size());
+    *running = E.n_running.load(std::memory_order_relaxed);
+    *finished = E.n_done.load(std::memory_order_relaxed);
     return DDA_OK;
     DDA_API_END
 }
@@ -2284,7 +2392,12 @@ int dda_drop_cache(dda_ctx* c) {
     DDA_API_BEGIN
     if (!c) throw Error(DDA_EINVAL, "ctx is NULL");
     DDA_HIP_CHECK(hipStreamSynchronize(c->stream));
-    c->dcache.clear();
+    // entries an engine slot still solves with stay
+    c->dspare.clear();
+    for (auto it = c->dcache.begin(); it != c->dcache.end();) {
+        if (it->second->refs == 0) it = c->dcache.erase(it);
+        else ++it;
+    }
     return DDA_OK;
     DDA_API_END
 }

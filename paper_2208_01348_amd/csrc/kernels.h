@@ -12,7 +12,11 @@ namespace dda {
 struct Geo {
     int nx, ny, nz;   // lattice cells per axis
     int mx, my, mz;   // FFT grid of the block-Toeplitz embedding (>= 2n - 1)
-    int64_t n_occ;    // occupied cells
+    int64_t n_occ;    // occupied cells (the per-slot vector length)
+    // 0: one index map for every slot.  Otherwise slot s reads its own map at
+    // map + s * map_stride (lattices of one box sharing an engine; a slot's
+    // dipoles are a prefix of its n_occ entries, the rest stay zero).
+    int64_t map_stride;
 };
 
 // Grid buffer per slot: [3][nz][my][mx] complex, rows y >= ny unused before the

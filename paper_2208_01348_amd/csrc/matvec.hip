@@ -87,6 +87,7 @@ __global__ __launch_bounds__(NTHR) void k_unpack_xfft(cx<T>* __restrict__ xin,
     const int pos = blockIdx.z;
     const int64_t slot = act ? act[pos] : pos;
     if (!slot_live(f, slot)) return;
+    map += slot * g.map_stride;
     for (int t = tid; t < L; t += NTHR) twl[t] = tw[t];
     const int nrows = g.nz * g.ny;
     const int row0 = blockIdx.x * NL;
@@ -548,6 +549,7 @@ __global__ __launch_bounds__(NTHR) void k_ixfft_pack(const cx<T>* __restrict__ G
     const int pos = blockIdx.z;
     const int64_t slot = act ? act[pos] : pos;
     if (!slot_live(f, slot)) return;
+    map += slot * g.map_stride;
     for (int t = tid; t < L; t += NTHR) twl[t] = tw[t];
     const int64_t sys = slot_sys[slot];
     const int nrows = g.nz * g.ny;

@@ -108,6 +108,7 @@ __global__ __launch_bounds__(NT) void k_xfft_t(cx<T>* __restrict__ xin,
     const int pos = blockIdx.y;
     const int64_t slot = act ? act[pos] : pos;
     if (!slot_live(f, slot)) return;
+    map += slot * g.map_stride;
     for (int t = tid; t < LX; t += NT) twl[t] = tw[t];
     const int grp = blockIdx.x % ngroups;
     const int cz = blockIdx.x / ngroups;
@@ -205,6 +206,7 @@ __global__ __launch_bounds__(NT) void k_ixfft_t(const cx<T>* __restrict__ Tb,
     const int pos = blockIdx.y;
     const int64_t slot = act ? act[pos] : pos;
     if (!slot_live(f, slot)) return;
+    map += slot * g.map_stride;
     for (int t = tid; t < LX; t += NT) twl[t] = tw[t];
     const int64_t sys = slot_sys[slot];
     const int grp = blockIdx.x % ngroups;
