@@ -466,9 +466,9 @@ def measure_serving(torch, W, DDASolver, n_req, log, window_s=75.0, plain_req=12
     """The seeded Poisson stream (mean 200 requests/s; sphere / capped rod /
     ellipsoid on 24-96 cells per side; host 1-2; beta 0.4-0.8; 8-64
     energies; tol 1e-8): n_req requests submitted at their arrival times to
-    the continuous-batching server (mixed precision, one engine per lattice,
-    engines of repeated lattices shared by their requests, at most
-    max_inflight requests in the engines, the rest first come first served), served for
+    the continuous-batching server (mixed precision, one engine per box of
+    cells shared by every lattice and request in it, at most max_inflight
+    requests in the engines, the rest first come first served), served for
     window_s seconds from the first arrival with the queue depth sampled;
     then the first plain_req requests through the plain FP64 path (one
     dda_solve per request, COCG, in arrival order on one stream) for at most

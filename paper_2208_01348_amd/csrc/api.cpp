@@ -544,7 +544,7 @@ void matvec(dda_ctx* c, const Work& w, dda::cx<T>* x, dda::cx<T>* y, const int* 
             const dda::cx<T>* const* dptr, const int* slot_sys, const dda::cx<T>* ainv, int mode,
             const dda::cx<T>* fuse_r = nullptr,
             dda::SlotFilter f = dda::SlotFilter{nullptr, dda::FILTER_ALL},
-            const dda::cx<T>* dotw = nullptr) {
+            const dda::cx<T>* dotw = nullptr, dda::CocgFold fold = dda::CocgFold{}) {
     if (n_act == 0 || c->g.n_occ == 0) return;
     if ((fuse_r || f.mode != dda::FILTER_ALL) && !f.st)
         throw Error(DDA_EDEVICE, "slot filter without slot states");
@@ -563,7 +563,7 @@ void matvec(dda_ctx* c, const Work& w, dda::cx<T>* x, dda::cx<T>* y, const int* 
         {
             Tic t(c, 0, n_act);
             dda::launch_xfft_t<T>(x, map, G, tw_of<T>(c, 0), g, act, n_act, fuse_r,
-                                  f, s);
+                                  f, s, fold);
         }
         {
             Tic t(c, 5, n_act);
@@ -580,7 +580,7 @@ void matvec(dda_ctx* c, const Work& w, dda::cx<T>* x, dda::cx<T>* y, const int* 
         {
             Tic t(c, 0, n_act);
             dda::launch_unpack_xfft<T>(x, map, G, tw_of<T>(c, 0), g, act, n_act,
-                                       fuse_r, f, s);
+                                       fuse_r, f, s, fold);
         }
         {
             Tic t(c, 1, n_act);
@@ -1103,12 +1103,20 @@ void cocg_interval(dda_ctx* c, const CocgBufs<T>& B, int n_act) {
         }
         return;
     }
+    // the end of each iteration but the last is folded into the next one's
+    // direction update (one kernel less per iteration); rho alternates
+    // between two copies so that no block of that kernel reads a value
+    // another block writes
     const int check = std::max(1, c->opt.check_every);
+    const int rows = dda::cocg_rows(nv, B.w.red.max_blocks);
     for (int k = 0; k < check; ++k) {
+        const dda::CocgFold fold = k == 0 ? dda::CocgFold{}
+                                          : dda::CocgFold{B.w.st, B.w.red, rows, (k - 1) & 1};
         matvec<T>(c, B.w, B.p, B.q, B.act, n_act, B.dptr, B.slot_sys, B.ainv, dda::PACK_AX_COCG,
-                  B.r, fact);
+                  B.r, fact, nullptr, fold);
         dda::cocg_update_xr<T>(xs, B.r, B.p, B.q, B.w.st, B.act, n_act, nv, B.w.red,
-                               pack_blocks(c, int(sizeof(dda::cx<T>))), s);
+                               pack_blocks(c, int(sizeof(dda::cx<T>))), k & 1, k == check - 1,
+                               s);
     }
 }
 

@@ -42,11 +42,13 @@ bool fft_length_supported(int L);
 // With fuse_r != NULL the kernel first updates the input in place,
 // x <- fuse_r + beta x with beta = f.st[slot].beta (the COCG direction update;
 // x <- fuse_r when the slot's reset_p is set), and transforms the updated
-// vector.  Every kernel of the chain skips the slots the filter rejects.
+// vector; with fo.nblk > 0 it first ends the previous COCG iteration itself
+// (CocgFold: beta and the slot's status from that iteration's rows).  Every
+// kernel of the chain skips the slots the filter rejects.
 template <typename T>
 void launch_unpack_xfft(cx<T>* xin, const int* map, cx<T>* G, const cx<T>* tw_x, const Geo& g,
                         const int* act, int n_act, const cx<T>* fuse_r, SlotFilter f,
-                        hipStream_t s);
+                        hipStream_t s, CocgFold fo = CocgFold{});
 // tx: columns per block (0: the default width; see mid_tx_candidates).
 template <typename T>
 void launch_fft_mid(cx<T>* data, const cx<T>* tw, int L, bool inverse, int64_t n_outer,
@@ -162,7 +164,8 @@ bool yz_fused_ok(const Geo& g, int csize);
 int yz_pack_blocks_per_slot(const Geo& g, int csize);
 template <typename T>
 void launch_xfft_t(cx<T>* xin, const int* map, cx<T>* Tb, const cx<T>* tw_x, const Geo& g,
-                   const int* act, int n_act, const cx<T>* fuse_r, SlotFilter f, hipStream_t s);
+                   const int* act, int n_act, const cx<T>* fuse_r, SlotFilter f, hipStream_t s,
+                   CocgFold fo = CocgFold{});
 // nthreads: threads per block (0: the default; see yz_thread_candidates)
 template <typename T>
 void launch_yzconv(cx<T>* Tb, const cx<T>* const* Dptr, const cx<T>* tw_y, const cx<T>* tw_z,

@@ -42,13 +42,17 @@ void residual(const cx<T>* b, const cx<T>* y, cx<T>* r, BicgSlot* st, const int*
 // x^T y).  The matvec's pack kernel writes the partial rows of mu = p^T q.
 // alpha = rho / mu from the partial rows the fused pack kernel wrote
 // (nblk_mu rows per slot; mu == 0 or not finite: SLOT_BREAKDOWN), then
-// x += alpha p; r -= alpha q; rho' = r^T r; beta = rho'/rho; convergence,
+// x += alpha p; r -= alpha q and the rows of rho' = r^T r, ||r||^2; with
+// finish, then rho' (into copy 0), beta = rho'/rho and the convergence,
 // reliable-update, breakdown and iteration-limit flags (slots in SLOT_ACTIVE
-// only)
+// only).  Without finish that last step is left to the next direction update
+// (CocgFold over cocg_rows(nv) rows).  par: parity of the iteration in its
+// interval (its rho is copy par).
 template <typename T>
 void cocg_update_xr(cx<T>* x, cx<T>* r, const cx<T>* p, const cx<T>* q, BicgSlot* st,
                     const int* act, int n_act, int64_t nv, RedScratch red, int nblk_mu,
-                    hipStream_t s);
+                    int par, bool finish, hipStream_t s);
+int cocg_rows(int64_t nv, int max_blocks);
 // FP64 residual passes: r = b - y (FP64; y == NULL stands for 0), r_lo = r
 // rounded to T, rho = r_lo^T r_lo, rnorm2 = rmax2 = ||r||^2.
 //   cocg_start: every listed slot, from x0 = 0 (y = 0); p = r on the first

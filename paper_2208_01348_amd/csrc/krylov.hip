@@ -334,15 +334,16 @@ __global__ __launch_bounds__(NT) void k_accumulate_up(z128* __restrict__ x,
 // ---------------------------------------------------------------- COCG ----
 // alpha = rho / mu from the pack kernel's partial rows (doubles 0, 1 of each
 // row; every block sums them in the same fixed order, block 0 records the
-// result or the breakdown), then x += alpha p, r -= alpha q and the partial
-// rows of r^T r and ||r||^2 (doubles 4..6, so the mu rows stay intact while
-// other blocks of the slot still read them).
+// result or the breakdown, and counts the iteration), then x += alpha p,
+// r -= alpha q and the partial rows of r^T r and ||r||^2 (doubles 4..6, so
+// the mu rows stay intact while other blocks of the slot still read them).
+// rho is copy `par` (the parity of the iteration in its interval).
 template <typename T>
 __global__ __launch_bounds__(NT) void k_cocg_xr(cx<T>* __restrict__ x, cx<T>* __restrict__ r,
                                                 const cx<T>* __restrict__ p,
                                                 const cx<T>* __restrict__ q, BicgSlot* st,
                                                 const int* __restrict__ act, int64_t nv,
-                                                RedScratch red, int nblk_mu) {
+                                                RedScratch red, int nblk_mu, int par) {
     SLOT_PROLOGUE
     if (block_status(st[slot]) != SLOT_ACTIVE) return;
     __shared__ double mu_sh[2];
@@ -364,10 +365,16 @@ __global__ __launch_bounds__(NT) void k_cocg_xr(cx<T>* __restrict__ x, cx<T>* __
         }
         return;
     }
-    const z128 al = zdiv(st[slot].rho, rv);
+    const z128 al = zdiv(par ? st[slot].rho1 : st[slot].rho, rv);
     if (lead) {
         st[slot].rv = rv;
         st[slot].alpha = al;
+        // the iteration is counted here, and the direction reset (if any) is
+        // spent: the next direction update may be folded into a kernel whose
+        // blocks must all read the same values
+        st[slot].iters += 1;
+        st[slot].matvecs += 1;
+        st[slot].reset_p = 0;
     }
     const cx<T> a{T(al.x), T(al.y)};
     double s[3] = {0.0, 0.0, 0.0};
@@ -380,33 +387,22 @@ __global__ __launch_bounds__(NT) void k_cocg_xr(cx<T>* __restrict__ x, cx<T>* __
     }
     block_partial<3, NT, 4>(s, red, slot, blockIdx.x);
 }
+// The end of the last iteration of an interval (parity par), as a kernel of
+// its own: rho goes to copy 0, where the next interval starts.  Inside an
+// interval the same step is folded into the next direction update
+// (cocg_fold), which sums the rows in this kernel's order.
+static_assert(NT == kCocgFinThreads, "the folded finalizer sums like this kernel");
 __global__ __launch_bounds__(NT) void k_fin_cocg_xr(BicgSlot* st, const int* act, RedScratch red,
-                                                    int nblk) {
+                                                    int nblk, int par) {
     if (st[act[blockIdx.x]].status != SLOT_ACTIVE) return;
     const int slot = act[blockIdx.x];
     double tot[3];
     sum_rows<3, NT, 4>(red, slot, nblk, tot);
     if (threadIdx.x != 0) return;
     BicgSlot& S = st[slot];
-    S.iters += 1;
-    S.matvecs += 1;
-    S.reset_p = 0;
-    S.rnorm2 = tot[2];
-    if (!all_finite(tot, 3)) {
-        S.status = SLOT_BREAKDOWN;
-        return;
-    }
-    const z128 rho_new{tot[0], tot[1]};
-    const bool conv = tot[2] <= S.tol2 * S.bnorm2;
-    const bool rho0 = S.rho.x == 0.0 && S.rho.y == 0.0;
-    const bool rhon0 = rho_new.x == 0.0 && rho_new.y == 0.0;
-    S.beta = rho0 ? z128{0.0, 0.0} : zdiv(rho_new, S.rho);
-    S.rho = rho_new;
-    if (tot[2] > S.rmax2) S.rmax2 = tot[2];
-    if (S.upd2 > 0.0 && tot[2] < S.upd2 * S.rmax2) S.want_update = 1;
-    if (conv) S.status = SLOT_CONVERGED;
-    else if (rho0 || rhon0) S.status = SLOT_BREAKDOWN;
-    else if (S.iters >= S.maxit) S.status = SLOT_MAXIT;
+    z128 beta;
+    const int status = cocg_next(S, tot, par ? S.rho1 : S.rho, beta);
+    cocg_record(S, tot, status, beta, 0);
 }
 
 template <typename T>
@@ -877,13 +873,14 @@ void residual(const cx<T>* b, const cx<T>* y, cx<T>* r, BicgSlot* st, const int*
 template <typename T>
 void cocg_update_xr(cx<T>* x, cx<T>* r, const cx<T>* p, const cx<T>* q, BicgSlot* st,
                     const int* act, int n_act, int64_t nv, RedScratch red, int nblk_mu,
-                    hipStream_t s) {
+                    int par, bool finish, hipStream_t s) {
     if (n_act == 0) return;
     if (nblk_mu < 1 || nblk_mu > red.max_blocks) throw Error(-1, "bad partial row count");
-    k_cocg_xr<T><<<GRID(nv), NT, 0, s>>>(x, r, p, q, st, act, nv, red, nblk_mu);
+    k_cocg_xr<T><<<GRID(nv), NT, 0, s>>>(x, r, p, q, st, act, nv, red, nblk_mu, par & 1);
     DDA_LAUNCH_CHECK();
-    FIN(k_fin_cocg_xr);
+    if (finish) FIN(k_fin_cocg_xr, par & 1);
 }
+int cocg_rows(int64_t nv, int max_blocks) { return blocks_for(nv, max_blocks); }
 template <typename T>
 void cocg_start(const z128* b, const z128* y, cx<T>* r_lo, BicgSlot* st, const int* act,
                 int n_act, int64_t nv, RedScratch red, hipStream_t s) {
@@ -986,7 +983,8 @@ void loss_sums(const z128* einc, const z128* p, const z128* y, const double* w, 
     template void residual<T>(const cx<T>*, const cx<T>*, cx<T>*, BicgSlot*, const int*, int,    \
                               int64_t, RedScratch, hipStream_t);                                 \
     template void cocg_update_xr<T>(cx<T>*, cx<T>*, const cx<T>*, const cx<T>*, BicgSlot*,       \
-                                    const int*, int, int64_t, RedScratch, int, hipStream_t);     \
+                                    const int*, int, int64_t, RedScratch, int, int, bool,        \
+                                    hipStream_t);                                                \
     template void cocg_start<T>(const z128*, const z128*, cx<T>*, BicgSlot*, const int*, int,    \
                                 int64_t, RedScratch, hipStream_t);                               \
     template void cocg_check<T>(const z128*, const z128*, cx<T>*, BicgSlot*, const int*, int,    \

@@ -78,7 +78,7 @@ __global__ __launch_bounds__(NTHR) void k_unpack_xfft(cx<T>* __restrict__ xin,
                                                       const cx<T>* __restrict__ tw, Geo g,
                                                       const int* __restrict__ act,
                                                       const cx<T>* __restrict__ fuse_r,
-                                                      SlotFilter f) {
+                                                      SlotFilter f, CocgFold fo) {
     constexpr int NL = rows_nl<T, L>();
     __shared__ cx<T> lds[NL * L];
     __shared__ cx<T> twl[L];
@@ -86,7 +86,15 @@ __global__ __launch_bounds__(NTHR) void k_unpack_xfft(cx<T>* __restrict__ xin,
     const int c = blockIdx.y;
     const int pos = blockIdx.z;
     const int64_t slot = act ? act[pos] : pos;
-    if (!slot_live(f, slot)) return;
+    const bool fold = FUSE_P && fo.nblk > 0;
+    if (fold) {  // the folded finalizer may end the slot: one status read per block
+        __shared__ int live0;
+        if (tid == 0) live0 = f.st[slot].status == SLOT_ACTIVE;
+        __syncthreads();
+        if (!live0) return;
+    } else if (!slot_live(f, slot)) {
+        return;
+    }
     map += slot * g.map_stride;
     for (int t = tid; t < L; t += NTHR) twl[t] = tw[t];
     const int nrows = g.nz * g.ny;
@@ -96,7 +104,13 @@ __global__ __launch_bounds__(NTHR) void k_unpack_xfft(cx<T>* __restrict__ xin,
     cx<T> beta{T(0), T(0)};
     bool reset = false;
     if (FUSE_P) {
-        beta = cvt<T>(f.st[slot].beta);
+        if (fold) {
+            z128 b;
+            if (!cocg_fold<NTHR>(fo, int(slot), blockIdx.x == 0 && c == 0, b)) return;
+            beta = cvt<T>(b);
+        } else {
+            beta = cvt<T>(f.st[slot].beta);
+        }
         reset = f.st[slot].reset_p != 0;
     }
     // only x < (L+1)/2 can be occupied; every index load, then every data
@@ -627,7 +641,7 @@ int pack_blocks_per_slot(const Geo& g) {
 template <typename T>
 void launch_unpack_xfft(cx<T>* xin, const int* map, cx<T>* G, const cx<T>* tw_x, const Geo& g,
                         const int* act, int n_act, const cx<T>* fuse_r, SlotFilter f,
-                        hipStream_t s) {
+                        hipStream_t s, CocgFold fo) {
     if (n_act == 0) return;
     const int64_t nrows = int64_t(g.nz) * g.ny;
     switch (g.mx) {
@@ -636,10 +650,10 @@ void launch_unpack_xfft(cx<T>* xin, const int* map, cx<T>* G, const cx<T>* tw_x,
         dim3 grid(nblk(nrows, rows_nl<T, N>()), 3, n_act);                             \
         if (fuse_r)                                                                    \
             k_unpack_xfft<T, N, true><<<grid, NTHR, 0, s>>>(xin, map, G, tw_x, g, act,  \
-                                                            fuse_r, f);                \
+                                                            fuse_r, f, fo);            \
         else                                                                           \
             k_unpack_xfft<T, N, false><<<grid, NTHR, 0, s>>>(xin, map, G, tw_x, g, act, \
-                                                             nullptr, f);              \
+                                                             nullptr, f, CocgFold{});  \
         break;                                                                         \
     }
         DDA_FOR_EACH_L(DDA_CASE)
@@ -863,9 +877,10 @@ void launch_ixfft_pack(const cx<T>* G, const cx<T>* xin, const cx<T>* ainv, cx<T
 }
 
 template void launch_unpack_xfft<double>(z128*, const int*, z128*, const z128*, const Geo&,
-                                         const int*, int, const z128*, SlotFilter, hipStream_t);
+                                         const int*, int, const z128*, SlotFilter, hipStream_t,
+                                         CocgFold);
 template void launch_unpack_xfft<float>(z64*, const int*, z64*, const z64*, const Geo&, const int*,
-                                        int, const z64*, SlotFilter, hipStream_t);
+                                        int, const z64*, SlotFilter, hipStream_t, CocgFold);
 template void launch_fft_mid<double>(z128*, const z128*, int, bool, int64_t, int64_t, int, int,
                                      int64_t, int, hipStream_t);
 template void launch_fft_mid<float>(z64*, const z64*, int, bool, int64_t, int64_t, int, int,

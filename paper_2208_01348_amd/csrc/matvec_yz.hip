@@ -97,7 +97,7 @@ __global__ __launch_bounds__(NT) void k_xfft_t(cx<T>* __restrict__ xin,
                                                const cx<T>* __restrict__ tw, Geo g,
                                                const int* __restrict__ act,
                                                const cx<T>* __restrict__ fuse_r, SlotFilter f,
-                                               int ngroups, int nr) {
+                                               int ngroups, int nr, CocgFold fo) {
     constexpr int NR = xrows_max<T, LX>();
     constexpr int LP = LX + 1;  // padded LDS row: the transposed accesses hit spread banks
     constexpr int HX = (LX + 1) / 2;
@@ -107,7 +107,15 @@ __global__ __launch_bounds__(NT) void k_xfft_t(cx<T>* __restrict__ xin,
     const int tid = threadIdx.x;
     const int pos = blockIdx.y;
     const int64_t slot = act ? act[pos] : pos;
-    if (!slot_live(f, slot)) return;
+    const bool fold = FUSE_P && fo.nblk > 0;
+    if (fold) {  // the folded finalizer may end the slot: one status read per block
+        __shared__ int live0;
+        if (tid == 0) live0 = f.st[slot].status == SLOT_ACTIVE;
+        __syncthreads();
+        if (!live0) return;
+    } else if (!slot_live(f, slot)) {
+        return;
+    }
     map += slot * g.map_stride;
     for (int t = tid; t < LX; t += NT) twl[t] = tw[t];
     const int grp = blockIdx.x % ngroups;
@@ -120,7 +128,13 @@ __global__ __launch_bounds__(NT) void k_xfft_t(cx<T>* __restrict__ xin,
     cx<T> beta{T(0), T(0)};
     bool reset = false;
     if (FUSE_P) {
-        beta = cvt<T>(f.st[slot].beta);
+        if (fold) {
+            z128 b;
+            if (!cocg_fold<NT>(fo, int(slot), blockIdx.x == 0, b)) return;
+            beta = cvt<T>(b);
+        } else {
+            beta = cvt<T>(f.st[slot].beta);
+        }
         reset = f.st[slot].reset_p != 0;
     }
     // loads use clamped (always valid) addresses and are masked afterwards, so
@@ -676,7 +690,7 @@ __global__ __launch_bounds__(yzr_threads<L>()) void k_yzconv_r(
 template <typename T>
 void launch_xfft_t(cx<T>* xin, const int* map, cx<T>* Tb, const cx<T>* tw_x, const Geo& g,
                    const int* act, int n_act, const cx<T>* fuse_r, SlotFilter f,
-                   hipStream_t s) {
+                   hipStream_t s, CocgFold fo) {
     if (n_act == 0) return;
     if (2 * g.nx - 1 > g.mx) throw Error(-1, "x grid shorter than 2 nx - 1");
     int ng, nr;
@@ -687,10 +701,10 @@ void launch_xfft_t(cx<T>* xin, const int* map, cx<T>* Tb, const cx<T>* tw_x, con
     case N:                                                                                 \
         if (fuse_r)                                                                         \
             k_xfft_t<T, N, true><<<grid, NT, 0, s>>>(xin, map, Tb, tw_x, g, act, fuse_r, f,  \
-                                                     ng, nr);                               \
+                                                     ng, nr, fo);                           \
         else                                                                                \
             k_xfft_t<T, N, false><<<grid, NT, 0, s>>>(xin, map, Tb, tw_x, g, act, nullptr,   \
-                                                      f, ng, nr);                           \
+                                                      f, ng, nr, CocgFold{});               \
         break;
         DDA_FOR_EACH_LX(DDA_CASE)
 #undef DDA_CASE
@@ -796,9 +810,9 @@ void launch_extract_yz(const z128* full, cx<T>* out, const Geo& g, hipStream_t s
 }
 
 template void launch_xfft_t<double>(z128*, const int*, z128*, const z128*, const Geo&, const int*,
-                                    int, const z128*, SlotFilter, hipStream_t);
+                                    int, const z128*, SlotFilter, hipStream_t, CocgFold);
 template void launch_xfft_t<float>(z64*, const int*, z64*, const z64*, const Geo&, const int*, int,
-                                   const z64*, SlotFilter, hipStream_t);
+                                   const z64*, SlotFilter, hipStream_t, CocgFold);
 template void launch_ixfft_t<double>(const z128*, const z128*, const z128*, z128*, const int*,
                                      const z128*, const Geo&, const int*, const int*, int, int,
                                      SlotFilter, RedScratch, hipStream_t, const z128*);

@@ -42,6 +42,8 @@ struct BicgSlot {
     z128 rho, rho_old, alpha, omega;  // BiCGStab; COCG uses rho and alpha
     z128 rv, ts;                      // BiCGStab <rhat, v>, <t, s>; COCG: rv = p^T q
     z128 beta;                        // COCG: p <- r + beta p
+    z128 rho1;                        // COCG: r^T r of the odd iterations of an interval
+                                      // (rho holds the even ones; see CocgFold)
     double tt;                        // <t, t>
     double bnorm2;                    // ||b||^2
     double rnorm2;                    // ||r||^2 (recursive, or true after a residual pass)
@@ -155,6 +157,112 @@ __device__ __forceinline__ void sum_rows(RedScratch red, int slot, int nblk, dou
             tot[k] = s;
         }
     }
+}
+
+// Sums rows 0..nblk-1 of `slot` exactly as sum_rows<K, NTS, OFF> does
+// (same grouping of rows by thread, same order) in a block of NTB >= NTS
+// threads, so that a value summed by a kernel of another block size is
+// bit-identical.  Totals valid in thread 0; every thread must call it.
+template <int K, int NTS, int OFF, int NTB>
+__device__ __forceinline__ void sum_rows_as(RedScratch red, int slot, int nblk, double (&tot)[K]) {
+    static_assert(NTB >= NTS && NTS % 64 == 0, "block too small");
+    __shared__ double sm[NTS / 64][K];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const double* rows = red.partial + int64_t(slot) * red.max_blocks * 8;
+    double acc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) acc[k] = 0.0;
+    if (tid < NTS) {
+        for (int b = tid; b < nblk; b += NTS) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) acc[k] += rows[int64_t(b) * 8 + OFF + k];
+        }
+    }
+    wave_sum<K>(acc);
+    if (lane == 0 && w < NTS / 64)
+        for (int k = 0; k < K; ++k) sm[w][k] = acc[k];
+    __syncthreads();
+    if (tid == 0) {
+        for (int k = 0; k < K; ++k) {
+            double s = 0.0;
+            for (int q = 0; q < NTS / 64; ++q) s += sm[q][k];
+            tot[k] = s;
+        }
+    }
+}
+
+// ----------------------------------------------------------- COCG step ----
+// The end of a COCG iteration: from tot = (r^T r re, im, ||r||^2) of the
+// updated residual, the next status (SLOT_ACTIVE to go on) and
+// beta = rho_new / rho_old.  It reads only fields that no kernel of the
+// iteration writes, so every block evaluating it decides alike.
+__device__ __forceinline__ int cocg_next(const BicgSlot& S, const double (&tot)[3], z128 rho_old,
+                                         z128& beta) {
+    beta = z128{0.0, 0.0};
+    if (!(isfinite(tot[0]) && isfinite(tot[1]) && isfinite(tot[2]))) return SLOT_BREAKDOWN;
+    const z128 rho_new{tot[0], tot[1]};
+    const bool rho0 = rho_old.x == 0.0 && rho_old.y == 0.0;
+    const bool rhon0 = rho_new.x == 0.0 && rho_new.y == 0.0;
+    if (!rho0) beta = zdiv(rho_new, rho_old);
+    if (tot[2] <= S.tol2 * S.bnorm2) return SLOT_CONVERGED;
+    if (rho0 || rhon0) return SLOT_BREAKDOWN;
+    if (S.iters >= S.maxit) return SLOT_MAXIT;
+    return SLOT_ACTIVE;
+}
+// Its bookkeeping, by one thread: residual norms for the FP64 check, the
+// reliable-update flag, beta, rho (into copy `dst`: 0 = rho, 1 = rho1) and a
+// terminal status.
+__device__ __forceinline__ void cocg_record(BicgSlot& S, const double (&tot)[3], int status,
+                                            z128 beta, int dst) {
+    S.rnorm2 = tot[2];
+    if (!(isfinite(tot[0]) && isfinite(tot[1]) && isfinite(tot[2]))) {
+        S.status = SLOT_BREAKDOWN;
+        return;
+    }
+    S.beta = beta;
+    if (dst) S.rho1 = z128{tot[0], tot[1]};
+    else S.rho = z128{tot[0], tot[1]};
+    if (tot[2] > S.rmax2) S.rmax2 = tot[2];
+    if (S.upd2 > 0.0 && tot[2] < S.upd2 * S.rmax2) S.want_update = 1;
+    if (status != SLOT_ACTIVE) S.status = status;
+}
+
+// The end of COCG iteration k - 1 folded into the direction update of
+// iteration k (the first kernel of its matvec), instead of a kernel of its
+// own: every block sums the rows of r^T r the x, r update left (doubles 4..6,
+// nblk rows, in the finalizer's order) and takes beta and the decision
+// itself; the slot's first block records them.  Iteration k - 1 has parity
+// `par` and read its rho from copy par; the record goes to copy par ^ 1, so
+// no block of the launch reads a value another one writes.  nblk == 0: no
+// fold (beta and reset_p come from the slot state).
+struct CocgFold {
+    BicgSlot* st;
+    RedScratch red;
+    int nblk;
+    int par;
+};
+constexpr int kCocgFinThreads = 256;  // block size of the standalone finalizer
+
+// Every thread of the block calls it (after a block-uniform check that the
+// slot is active); returns false when the slot stops here.
+template <int NTB>
+__device__ __forceinline__ bool cocg_fold(CocgFold fo, int slot, bool lead, z128& beta) {
+    double tot[3];
+    sum_rows_as<3, kCocgFinThreads, 4, NTB>(fo.red, slot, fo.nblk, tot);
+    __shared__ double bc[2];
+    __shared__ int go;
+    if (threadIdx.x == 0) {
+        BicgSlot& S = fo.st[slot];
+        z128 b;
+        const int status = cocg_next(S, tot, fo.par ? S.rho1 : S.rho, b);
+        bc[0] = b.x;
+        bc[1] = b.y;
+        go = status == SLOT_ACTIVE;
+        if (lead) cocg_record(S, tot, status, b, fo.par ^ 1);
+    }
+    __syncthreads();
+    beta = z128{bc[0], bc[1]};
+    return go != 0;
 }
 
 }  // namespace dda
