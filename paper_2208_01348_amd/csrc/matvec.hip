@@ -101,18 +101,6 @@ __global__ __launch_bounds__(NTHR) void k_unpack_xfft(cx<T>* __restrict__ xin,
     const int row0 = blockIdx.x * NL;
     cx<T>* src = xin + (slot * 3 + c) * g.n_occ;
     const cx<T>* rsrc = FUSE_P ? fuse_r + (slot * 3 + c) * g.n_occ : nullptr;
-    cx<T> beta{T(0), T(0)};
-    bool reset = false;
-    if (FUSE_P) {
-        if (fold) {
-            z128 b;
-            if (!cocg_fold<NTHR>(fo, int(slot), blockIdx.x == 0 && c == 0, b)) return;
-            beta = cvt<T>(b);
-        } else {
-            beta = cvt<T>(f.st[slot].beta);
-        }
-        reset = f.st[slot].reset_p != 0;
-    }
     // only x < (L+1)/2 can be occupied; every index load, then every data
     // load, is issued before the first use (clamped addresses, masked after)
     constexpr int HX = (L + 1) / 2;
@@ -126,6 +114,20 @@ __global__ __launch_bounds__(NTHR) void k_unpack_xfft(cx<T>* __restrict__ xin,
         const int row = row0 + rr;
         const int m = map[int64_t(min(row, nrows - 1)) * g.nx + min(x, g.nx - 1)];
         idx[q] = (rr < NL && row < nrows && x < g.nx) ? m : -1;
+    }
+    // the direction update's scalars: the folded finalizer's row loads go
+    // out while the index loads are in flight, ahead of the data loads
+    cx<T> beta{T(0), T(0)};
+    bool reset = false;
+    if (FUSE_P) {
+        if (fold) {
+            z128 b;
+            if (!cocg_fold<NTHR>(fo, int(slot), blockIdx.x == 0 && c == 0, b)) return;
+            beta = cvt<T>(b);
+        } else {
+            beta = cvt<T>(f.st[slot].beta);
+        }
+        reset = f.st[slot].reset_p != 0;
     }
     cx<T> v[NE], w[FUSE_P ? NE : 1];
 #pragma unroll

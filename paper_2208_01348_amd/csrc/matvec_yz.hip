@@ -125,6 +125,19 @@ __global__ __launch_bounds__(NT) void k_xfft_t(cx<T>* __restrict__ xin,
     const int nrow = min(nr, g.ny - y0);
     cx<T>* src = xin + (slot * 3 + c) * g.n_occ;
     const cx<T>* rsrc = FUSE_P ? fuse_r + (slot * 3 + c) * g.n_occ : nullptr;
+    // loads use clamped (always valid) addresses and are masked afterwards, so
+    // that none of them sits behind a branch and all can be in flight at once
+    const int* mrow = map + (int64_t(z) * g.ny + y0) * g.nx;
+    int idx[NE];
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+        const int e = tid + q * NT;
+        const int r = e / HX, x = e - (e / HX) * HX;
+        const int m = mrow[min(r, nrow - 1) * g.nx + min(x, g.nx - 1)];
+        idx[q] = (r < nrow && x < g.nx) ? m : -1;
+    }
+    // the direction update's scalars: the folded finalizer's row loads go
+    // out while the index loads are in flight, ahead of the data loads
     cx<T> beta{T(0), T(0)};
     bool reset = false;
     if (FUSE_P) {
@@ -136,17 +149,6 @@ __global__ __launch_bounds__(NT) void k_xfft_t(cx<T>* __restrict__ xin,
             beta = cvt<T>(f.st[slot].beta);
         }
         reset = f.st[slot].reset_p != 0;
-    }
-    // loads use clamped (always valid) addresses and are masked afterwards, so
-    // that none of them sits behind a branch and all can be in flight at once
-    const int* mrow = map + (int64_t(z) * g.ny + y0) * g.nx;
-    int idx[NE];
-#pragma unroll
-    for (int q = 0; q < NE; ++q) {
-        const int e = tid + q * NT;
-        const int r = e / HX, x = e - (e / HX) * HX;
-        const int m = mrow[min(r, nrow - 1) * g.nx + min(x, g.nx - 1)];
-        idx[q] = (r < nrow && x < g.nx) ? m : -1;
     }
     cx<T> v[NE], w[NE];
 #pragma unroll

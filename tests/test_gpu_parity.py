@@ -312,10 +312,13 @@ def test_c1_full_size_matches_oracle_golden(solver, precision):
 def test_batch_equals_single(solver, precision):
     """Energies x trajectories as one batch give the same result as one solve
     per right-hand side (each right-hand side runs the same arithmetic in the
-    same order whatever else shares the launch)."""
+    same order whatever else shares the launch).  Twelve right-hand sides: the
+    COCG batch starts above the slot count up to which the finalizer is folded
+    into the direction update and ends below it, while each single solve
+    folds throughout."""
     mask, d, r0 = _small_particle()
     n = int(mask.sum())
-    energies = np.array([1.5, 2.0, 2.5])
+    energies = np.array([1.5, 1.8, 2.0, 2.2, 2.5, 2.8])
     eps = np.repeat(W.drude_eps(energies)[:, None], n, axis=1)
     s = DDASolver(mask, d, 1.45, tol=1e-11, maxit=20000, solver=solver, precision=precision)
     Pb, _ = s.spectrum(energies, 0.55, eps, r0)
