@@ -254,7 +254,7 @@ def main():
         extras["c2_plain_fp64"] = measure_plain_fp64(torch, W, DDASolver, w, eps, P, info,
                                                      args.fp64_steps, args.check_every, log)
     if not args.no_extras:
-        extras = measure_extras(torch, W, DDASolver, log)
+        extras.update(measure_extras(torch, W, DDASolver, log))
         if args.serve_requests > 0:
             extras["serving_c5"] = measure_serving(torch, W, DDASolver, args.serve_requests, log,
                                                    window_s=args.serve_window)
