@@ -194,3 +194,27 @@ def test_inflight_cap_serves_a_backlog_in_arrival_order():
     assert handed == list(range(12))
     assert peak[0] <= 2
     srv.close()
+
+
+def test_lattices_of_one_box_share_an_engine_by_default():
+    """Two particle shapes in the same box of cells (and dipole size) go to one
+    engine; with share_box=False each lattice gets its own."""
+    def two_shapes():
+        a = _req(0, 6)
+        b = _req(1, 6)
+        b.mask = b.mask.copy()
+        b.mask[:, :, :2] = 0  # another particle in the same 6^3 box
+        assert a.lattice_key() != b.lattice_key() and a.box_key() == b.box_key()
+        return [a, b]
+
+    fp = lambda req, slots: 1  # noqa: E731
+    for share, engines in [(True, 1), (False, 2)]:
+        FakeWorker.opened = []
+        srv = Server(hbm_budget_bytes=1e12, worker_factory=FakeWorker, footprint_fn=fp,
+                     share_box=share)
+        for r in two_shapes():
+            srv.submit(r)
+        comps = srv.drain(timeout_s=30)
+        assert sorted(c.rid for c in comps) == [0, 1]
+        assert len(FakeWorker.opened) == engines
+        srv.close()
