@@ -211,10 +211,11 @@ def test_losses_match_oracle(name, m_h, beta, precision, bar, solver):
                                                   ("bicgstab", "mixed", 1e-5),
                                                   ("bicgstab", "fp64", 1e-9)])
 def test_losses_when_precisions_use_different_chains(solver, precision, bar):
-    """A 5 x 17 x 17 lattice (FFT grid 12 x 64 x 64): the FP32 matvecs of the
-    mixed path run the three-pass chain, its FP64 reliable updates and the
-    FP64 path the five-pass one; both D layouts come from one build."""
-    mask = W.random_mask(5, 17, 17, 0.6, seed=9)
+    """A 5 x 25 x 25 lattice (FFT grid 12 x 64 x 64): the FP32 matvecs of the
+    mixed path run the three-pass chain (its 64 x 64 plane fits in LDS in
+    FP32), its FP64 reliable updates and the FP64 path the five-pass one; both
+    D layouts come from one build."""
+    mask = W.random_mask(5, 25, 25, 0.6, seed=9)
     d = 1.3
     n = int(mask.sum())
     energies = np.array([2.1])
@@ -223,8 +224,15 @@ def test_losses_when_precisions_use_different_chains(solver, precision, bar):
     say("mixed chains", precision, "n_occ", n)
     s = DDASolver(mask, d, 1.45, precision=precision, solver=solver,
                   tol=1e-12 if precision == "fp64" else 1e-10, maxit=20000)
+    assert tuple(s.grid) == (12, 64, 64)
+    s.set_timing(True)
     P, info = s.spectrum(energies, 0.55, eps, r0)
     assert info[0].status == 0
+    # the FP64 matvecs (every one on the FP64 path, the checks of the mixed
+    # one) take the five-pass chain; the FP32 ones take the fused yz kernel
+    assert s.kernel_time("zconv")[1] > 0
+    assert (s.kernel_time("yzconv")[1] > 0) == (precision == "mixed")
+    s.set_timing(False)
     ref = solve_point(mask, d, eps[0], 1.45, 0.55, r0[0], energies[0], method="lu")
     vals = [ref.p_eels, ref.p_ext, ref.p_abs, ref.p_cl]
     for g, v in zip(P[0], vals):
