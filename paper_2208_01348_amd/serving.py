@@ -30,7 +30,7 @@ from __future__ import annotations
 import hashlib
 import threading
 import time
-from collections import deque
+from collections import OrderedDict, deque
 from dataclasses import dataclass, field
 from typing import Callable, Dict, List, Optional
 
@@ -103,7 +103,7 @@ class LatticeWorker:
     def __init__(self, mask: np.ndarray, d: float, key: str, slots: int, precision: str,
                  tol: float, maxit: int, check_every: int, on_done: Callable,
                  poll_intervals: int = 4, solver: Optional[DDASolver] = None,
-                 share_box: bool = False):
+                 share_box: bool = False, max_lattices: int = 64):
         self.key = key
         self.slots = slots
         self.share_box = share_box
@@ -111,7 +111,11 @@ class LatticeWorker:
                          check_every=check_every)
         # the context may come from the server's footprint probe
         self.solver = solver or DDASolver(engine_mask(mask, share_box), d, 1.0, **self.opts)
-        self.lattices: Dict[str, DDASolver] = {}  # share_box: per lattice key
+        # share_box: a context per lattice key, least recently used first; at
+        # most max_lattices are kept (closing one waits for the whole device,
+        # so it is done only when a new lattice would exceed the bound)
+        self.lattices: "OrderedDict[str, DDASolver]" = OrderedDict()
+        self.max_lattices = max_lattices
         self.ctx = self.solver.ctx
         self.footprint = L.dda_workspace_bytes(self.ctx, slots)
         L.dda_engine_open(self.ctx, slots)
@@ -171,9 +175,17 @@ class LatticeWorker:
             return self.solver
         key = req.lattice_key()
         lat = self.lattices.get(key)
-        if lat is None:
-            lat = DDASolver(req.mask, req.d, 1.0, **self.opts)
-            self.lattices[key] = lat
+        if lat is not None:
+            self.lattices.move_to_end(key)
+            return lat
+        if len(self.lattices) >= self.max_lattices:
+            busy = {lv.req.lattice_key() for lv in self.live.values()}
+            for k in list(self.lattices):
+                if k not in busy:
+                    self.lattices.pop(k).close()
+                    break
+        lat = DDASolver(req.mask, req.d, 1.0, **self.opts)
+        self.lattices[key] = lat
         return lat
 
     def _start(self, req: Request, t_submit: float) -> None:
@@ -250,7 +262,8 @@ class Server:
                  tol: float = 1e-8, maxit: int = 50000, check_every: int = 8,
                  poll_intervals: int = 4, worker_factory: Optional[Callable] = None,
                  footprint_fn: Optional[Callable] = None,
-                 max_inflight: Optional[int] = None, share_box: bool = True):
+                 max_inflight: Optional[int] = None, share_box: bool = True,
+                 max_lattices: int = 64):
         self.budget = float(hbm_budget_bytes)
         self.share_box = share_box
         # requests handed to engines and not yet completed; beyond this many
@@ -263,6 +276,7 @@ class Server:
                          poll_intervals=poll_intervals)
         if share_box:
             self.opts["share_box"] = True
+            self.opts["max_lattices"] = max_lattices  # lattice contexts kept per engine
         self.worker_factory = worker_factory or LatticeWorker
         self.footprint_fn = footprint_fn or self._probe_footprint
         self.footprints: Dict[str, int] = {}   # per lattice key, probed once

@@ -163,14 +163,16 @@ def test_engine_reports_a_rejected_permittivity_per_system():
 
 def _requests():
     rod, d_rod = _rod()
+    ell = W.ellipsoid_mask(12, 6, 6, d_rod, 9.0, 4.0, 5.0)  # another particle in the rod's box
     sph = W.sphere_mask(8, 1.5, 5.5)
     specs = [  # lattice, d, m_h, beta, n_E, r0
         (rod, d_rod, 1.45 + 0j, 0.55, 5, (16.0, 1.0, 0.0)),
         (sph, 1.5, 1.0 + 0j, 0.6, 4, (8.0, 0.5, 0.0)),
-        (rod, d_rod, 1.30 + 0j, 0.45, 3, (15.0, -1.0, 0.0)),
+        (ell, d_rod, 1.30 + 0j, 0.45, 3, (15.0, -1.0, 0.0)),
         (rod, d_rod, 2.0 + 0.01j, 0.7, 4, (16.0, 1.0, 0.0)),  # absorbing Cherenkov host
         (sph, 1.5, 1.45 + 0j, 0.55, 6, (7.5, 0.0, 0.0)),
-        (rod, d_rod, 1.45 + 0j, 0.55, 5, (17.0, 2.0, 0.0)),
+        (ell, d_rod, 1.45 + 0j, 0.55, 5, (17.0, 2.0, 0.0)),
+        (rod, d_rod, 1.45 + 0j, 0.55, 4, (16.5, 0.0, 0.0)),
     ]
     out = []
     for i, (m, d, mh, b, ne, r0) in enumerate(specs):
@@ -189,7 +191,10 @@ def test_served_requests_equal_their_spectra_alone(precision, share_box):
     say("serving mix vs alone", precision, "box-shared" if share_box else "per lattice")
     reqs = _requests()
     opts = dict(precision=precision, tol=1e-10, maxit=20000, check_every=4)
-    srv = Server(hbm_budget_bytes=64 << 30, slots=8, share_box=share_box, **opts)
+    # one lattice context kept per engine: the rod and the ellipsoid in one box
+    # take turns, and an idle one is closed when the other arrives
+    srv = Server(hbm_budget_bytes=64 << 30, slots=8, share_box=share_box, max_lattices=1,
+                 **opts)
     comps, lat, span = replay(srv, reqs, timeout_s=240)
     srv.close()
     assert len(comps) == len(reqs)
@@ -214,9 +219,10 @@ def test_served_requests_equal_their_spectra_alone(precision, share_box):
 
 @pytest.mark.parametrize("precision,bar", [("mixed", 1e-5), ("fp64", 1e-9)])
 def test_served_requests_match_the_oracle(precision, bar):
-    """Every served spectrum point (two lattices, four hosts including an
-    absorbing Cherenkov one, requests overlapping in the slots) against the
-    FP64 CPU oracle's dense LU solve of the same point."""
+    """Every served spectrum point (three lattices, two of them sharing one
+    box and so one engine; four hosts including an absorbing Cherenkov one;
+    requests overlapping in the slots) against the FP64 CPU oracle's dense LU
+    solve of the same point."""
     from oracle.dda import solve_point
     say("serving vs oracle", precision)
     reqs = _requests()
