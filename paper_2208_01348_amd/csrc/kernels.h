@@ -45,10 +45,14 @@ bool fft_length_supported(int L);
 // vector; with fo.nblk > 0 it first ends the previous COCG iteration itself
 // (CocgFold: beta and the slot's status from that iteration's rows).  Every
 // kernel of the chain skips the slots the filter rejects.
+// With sf.nblk_mv > 0 (BiCGStab) the kernel instead forms s = fuse_r - alpha
+// sf.v for an iterating slot, writes it in place of x and transforms it
+// (BicgSFold).
+enum FuseMode { FUSE_NONE = 0, FUSE_COCG = 1, FUSE_BICG_S = 2 };
 template <typename T>
 void launch_unpack_xfft(cx<T>* xin, const int* map, cx<T>* G, const cx<T>* tw_x, const Geo& g,
                         const int* act, int n_act, const cx<T>* fuse_r, SlotFilter f,
-                        hipStream_t s, CocgFold fo = CocgFold{});
+                        hipStream_t s, CocgFold fo = CocgFold{}, BicgSFold sf = BicgSFold{});
 // tx: columns per block (0: the default width; see mid_tx_candidates).
 template <typename T>
 void launch_fft_mid(cx<T>* data, const cx<T>* tw, int L, bool inverse, int64_t n_outer,
@@ -165,7 +169,9 @@ int yz_pack_blocks_per_slot(const Geo& g, int csize);
 template <typename T>
 void launch_xfft_t(cx<T>* xin, const int* map, cx<T>* Tb, const cx<T>* tw_x, const Geo& g,
                    const int* act, int n_act, const cx<T>* fuse_r, SlotFilter f, hipStream_t s,
-                   CocgFold fo = CocgFold{});
+                   CocgFold fo = CocgFold{}, BicgSFold sf = BicgSFold{});
+// blocks per slot of the x kernel of either chain (the rows a folded s update writes)
+int xfft_blocks_per_slot(const Geo& g, int csize);
 // nthreads: threads per block (0: the default; see yz_thread_candidates)
 template <typename T>
 void launch_yzconv(cx<T>* Tb, const cx<T>* const* Dptr, const cx<T>* tw_y, const cx<T>* tw_z,

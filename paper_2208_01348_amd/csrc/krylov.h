@@ -27,10 +27,12 @@ void bicg_update_p(const cx<T>* r, cx<T>* p, const cx<T>* v, BicgSlot* st, const
 template <typename T>
 void bicg_update_s(const cx<T>* r, const cx<T>* v, cx<T>* sv, BicgSlot* st, const int* act,
                    int n_act, int64_t nv, RedScratch red, int nblk_mv, hipStream_t s);
+// nblk_s: rows of ||s||^2 (0: those of bicg_update_s; the folded s update
+// writes one per block of its x kernel)
 template <typename T>
 void bicg_update_xr(cx<T>* x, cx<T>* r, const cx<T>* rhat, const cx<T>* p, const cx<T>* sv,
                     const cx<T>* t, BicgSlot* st, const int* act, int n_act, int64_t nv,
-                    RedScratch red, int nblk_mv, hipStream_t s);
+                    RedScratch red, int nblk_mv, int nblk_s, hipStream_t s);
 void bicg_finish(BicgSlot* st, const int* act, int n_act, int64_t nv, RedScratch red,
                  hipStream_t s);
 // r = b - y, rnorm2 = ||r||^2 (true residual after y = A x)

@@ -230,12 +230,13 @@ __global__ __launch_bounds__(NT) void k_update_s(const cx<T>* __restrict__ r,
     const cx<T> a{T(al.x), T(al.y)};
     double s[1] = {0.0};
     for (int64_t i = i0; i < nv; i += stride) {
-        const cx<T> si = r[base + i] - a * v[base + i];
+        const cx<T> si = bicg_s_of(r[base + i], a, v[base + i]);
         sv[base + i] = si;
-        s[0] += double(norm2(si));
+        s[0] += bicg_norm2(si);
     }
     block_partial<1, NT, 6>(s, red, slot, blockIdx.x);
 }
+static_assert(NT == kBicgUpdateThreads, "the folded s update sums like this kernel");
 
 template <typename T>
 __global__ __launch_bounds__(NT) void k_update_xr(cx<T>* __restrict__ x, cx<T>* __restrict__ r,
@@ -244,7 +245,7 @@ __global__ __launch_bounds__(NT) void k_update_xr(cx<T>* __restrict__ x, cx<T>* 
                                                   const cx<T>* __restrict__ sv,
                                                   const cx<T>* __restrict__ t, BicgSlot* st,
                                                   const int* __restrict__ act, int64_t nv,
-                                                  RedScratch red, int nblk_mv) {
+                                                  RedScratch red, int nblk_mv, int nblk_s) {
     SLOT_PROLOGUE
     BicgSlot& S = st[slot];
     const int status = block_status(S);
@@ -253,7 +254,7 @@ __global__ __launch_bounds__(NT) void k_update_xr(cx<T>* __restrict__ x, cx<T>* 
     z128 om{0.0, 0.0};
     if (status == SLOT_ACTIVE) {
         double ss[1];
-        slot_totals<1, 6>(red, slot, gridDim.x, ss);
+        slot_totals<1, 6>(red, slot, nblk_s, ss);
         if (ss[0] <= S.tol2 * S.bnorm2) {  // ||s|| met the tolerance: x += alpha p ends the solve
             if (lead) {
                 S.omega = om;
@@ -851,10 +852,13 @@ void bicg_update_s(const cx<T>* r, const cx<T>* v, cx<T>* sv, BicgSlot* st, cons
 template <typename T>
 void bicg_update_xr(cx<T>* x, cx<T>* r, const cx<T>* rhat, const cx<T>* p, const cx<T>* sv,
                     const cx<T>* t, BicgSlot* st, const int* act, int n_act, int64_t nv,
-                    RedScratch red, int nblk_mv, hipStream_t s) {
+                    RedScratch red, int nblk_mv, int nblk_s, hipStream_t s) {
     if (n_act == 0) return;
     if (nblk_mv < 1 || nblk_mv > red.max_blocks) throw Error(-3, "bad matvec row count");
-    k_update_xr<T><<<GRID(nv), NT, 0, s>>>(x, r, rhat, p, sv, t, st, act, nv, red, nblk_mv);
+    if (nblk_s == 0) nblk_s = blocks_for(nv, red.max_blocks);  // rows of k_update_s
+    if (nblk_s < 1 || nblk_s > red.max_blocks) throw Error(-3, "bad s row count");
+    k_update_xr<T><<<GRID(nv), NT, 0, s>>>(x, r, rhat, p, sv, t, st, act, nv, red, nblk_mv,
+                                           nblk_s);
     DDA_LAUNCH_CHECK();
 }
 void bicg_finish(BicgSlot* st, const int* act, int n_act, int64_t nv, RedScratch red,
@@ -979,7 +983,7 @@ void loss_sums(const z128* einc, const z128* p, const z128* y, const double* w, 
                                    int, int64_t, RedScratch, int, hipStream_t);                  \
     template void bicg_update_xr<T>(cx<T>*, cx<T>*, const cx<T>*, const cx<T>*, const cx<T>*,    \
                                     const cx<T>*, BicgSlot*, const int*, int, int64_t,           \
-                                    RedScratch, int, hipStream_t);                               \
+                                    RedScratch, int, int, hipStream_t);                          \
     template void residual<T>(const cx<T>*, const cx<T>*, cx<T>*, BicgSlot*, const int*, int,    \
                               int64_t, RedScratch, hipStream_t);                                 \
     template void cocg_update_xr<T>(cx<T>*, cx<T>*, const cx<T>*, const cx<T>*, BicgSlot*,       \

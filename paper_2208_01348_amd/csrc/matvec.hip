@@ -71,14 +71,18 @@ bool fft_length_supported(int L) {
 }
 
 // ---------------------------------------------------------------- K1 ------
-template <typename T, int L, bool FUSE_P>
+// FUSE: as k_xfft_t (plain gather, the COCG direction update, or the
+// BiCGStab s update).
+template <typename T, int L, int FUSE>
 __global__ __launch_bounds__(NTHR) void k_unpack_xfft(cx<T>* __restrict__ xin,
                                                       const int* __restrict__ map,
                                                       cx<T>* __restrict__ G,
                                                       const cx<T>* __restrict__ tw, Geo g,
                                                       const int* __restrict__ act,
                                                       const cx<T>* __restrict__ fuse_r,
-                                                      SlotFilter f, CocgFold fo) {
+                                                      SlotFilter f, CocgFold fo, BicgSFold sf) {
+    constexpr bool FUSE_P = FUSE == FUSE_COCG;
+    constexpr bool FUSE_S = FUSE == FUSE_BICG_S;
     constexpr int NL = rows_nl<T, L>();
     __shared__ cx<T> lds[NL * L];
     __shared__ cx<T> twl[L];
@@ -87,11 +91,13 @@ __global__ __launch_bounds__(NTHR) void k_unpack_xfft(cx<T>* __restrict__ xin,
     const int pos = blockIdx.z;
     const int64_t slot = act ? act[pos] : pos;
     const bool fold = FUSE_P && fo.nblk > 0;
-    if (fold) {  // the folded finalizer may end the slot: one status read per block
+    bool sact = false;  // FUSE_S: this slot iterates, so the block forms s
+    if (fold || FUSE_S) {  // a folded step may change the status: one read per block
         __shared__ int live0;
-        if (tid == 0) live0 = f.st[slot].status == SLOT_ACTIVE;
+        if (tid == 0) live0 = (FUSE_S ? sf.st : f.st)[slot].status == SLOT_ACTIVE;
         __syncthreads();
-        if (!live0) return;
+        if (fold && !live0) return;
+        sact = live0 != 0;
     } else if (!slot_live(f, slot)) {
         return;
     }
@@ -100,7 +106,9 @@ __global__ __launch_bounds__(NTHR) void k_unpack_xfft(cx<T>* __restrict__ xin,
     const int nrows = g.nz * g.ny;
     const int row0 = blockIdx.x * NL;
     cx<T>* src = xin + (slot * 3 + c) * g.n_occ;
-    const cx<T>* rsrc = FUSE_P ? fuse_r + (slot * 3 + c) * g.n_occ : nullptr;
+    const cx<T>* rsrc = FUSE ? fuse_r + (slot * 3 + c) * g.n_occ : nullptr;
+    const cx<T>* vsrc = FUSE_S ? static_cast<const cx<T>*>(sf.v) + (slot * 3 + c) * g.n_occ
+                               : nullptr;
     // only x < (L+1)/2 can be occupied; every index load, then every data
     // load, is issued before the first use (clamped addresses, masked after)
     constexpr int HX = (L + 1) / 2;
@@ -129,19 +137,47 @@ __global__ __launch_bounds__(NTHR) void k_unpack_xfft(cx<T>* __restrict__ xin,
         }
         reset = f.st[slot].reset_p != 0;
     }
-    cx<T> v[NE], w[FUSE_P ? NE : 1];
+    cx<T> alpha{T(0), T(0)};
+    if constexpr (FUSE_S) {
+        if (sact) {  // block-uniform
+            z128 a;
+            sact = bicg_sfold<NTHR>(sf, int(slot), blockIdx.x == 0 && c == 0, a);
+            alpha = cvt<T>(a);
+        }
+    }
+    cx<T> v[NE], w[FUSE ? NE : 1], u[FUSE_S ? NE : 1];
 #pragma unroll
     for (int q = 0; q < NE; ++q) {
         const int i = max(idx[q], 0);
-        v[q] = src[i];
-        if constexpr (FUSE_P) w[q] = rsrc[i];
+        if constexpr (FUSE_S) {
+            if (sact) {
+                w[q] = rsrc[i];
+                u[q] = vsrc[i];
+            } else {
+                v[q] = src[i];
+            }
+        } else {
+            v[q] = src[i];
+            if constexpr (FUSE_P) w[q] = rsrc[i];
+        }
     }
+    double s2 = 0.0;
 #pragma unroll
     for (int q = 0; q < NE; ++q) {
         const int e = tid + q * NTHR;
         const int rr = e / HX, x = e - (e / HX) * HX;
         const bool occ = idx[q] >= 0;
-        cx<T> vq = v[q];
+        cx<T> vq;
+        if constexpr (FUSE_S) {
+            if (sact) {
+                vq = bicg_s_of(w[q], alpha, u[q]);
+                if (occ) s2 += bicg_norm2(vq);
+            } else {
+                vq = v[q];
+            }
+        } else {
+            vq = v[q];
+        }
         if constexpr (FUSE_P) {
             const cx<T> upd = w[q] + beta * vq;
             vq.x = reset ? w[q].x : upd.x;  // component selects: a select of the
@@ -149,10 +185,17 @@ __global__ __launch_bounds__(NTHR) void k_unpack_xfft(cx<T>* __restrict__ xin,
         }
         vq.x = occ ? vq.x : T(0);
         vq.y = occ ? vq.y : T(0);
-        if (FUSE_P && occ) src[idx[q]] = vq;  // each occupied element: exactly one thread
+        // each occupied element: exactly one thread
+        if ((FUSE_P || (FUSE_S && sact)) && occ) src[idx[q]] = vq;
         if (rr < NL) {
             lds[rr * L + x] = vq;
             if (x + HX < L) lds[rr * L + x + HX] = zero;
+        }
+    }
+    if constexpr (FUSE_S) {
+        if (sact) {  // ||s||^2 rows, one per block of the slot (block-uniform)
+            double pr[1] = {s2};
+            block_partial<1, NTHR, 6>(pr, sf.red, int(slot), blockIdx.x + gridDim.x * c);
         }
     }
     __syncthreads();
@@ -634,6 +677,11 @@ __global__ __launch_bounds__(NTHR) void k_ixfft_pack(const cx<T>* __restrict__ G
 // ------------------------------------------------------------ launchers ---
 static inline unsigned nblk(int64_t n, int64_t per) { return unsigned((n + per - 1) / per); }
 
+int xfft_blocks_per_slot(const Geo& g, int csize) {
+    if (yz_fused_ok(g, csize)) return yz_pack_blocks_per_slot(g, csize);  // same grid as k_xfft_t
+    return pack_blocks_per_slot(g);  // k_unpack_xfft has the grid of k_ixfft_pack
+}
+
 int pack_blocks_per_slot(const Geo& g) {
     const int64_t nrows = int64_t(g.nz) * g.ny;
     const int nl = g.mx >= 2048 ? 1 : 2048 / g.mx;  // rows_nl<T, L>() for either T
@@ -643,19 +691,22 @@ int pack_blocks_per_slot(const Geo& g) {
 template <typename T>
 void launch_unpack_xfft(cx<T>* xin, const int* map, cx<T>* G, const cx<T>* tw_x, const Geo& g,
                         const int* act, int n_act, const cx<T>* fuse_r, SlotFilter f,
-                        hipStream_t s, CocgFold fo) {
+                        hipStream_t s, CocgFold fo, BicgSFold sf) {
     if (n_act == 0) return;
     const int64_t nrows = int64_t(g.nz) * g.ny;
     switch (g.mx) {
 #define DDA_CASE(N)                                                                    \
     case N: {                                                                          \
         dim3 grid(nblk(nrows, rows_nl<T, N>()), 3, n_act);                             \
-        if (fuse_r)                                                                    \
-            k_unpack_xfft<T, N, true><<<grid, NTHR, 0, s>>>(xin, map, G, tw_x, g, act,  \
-                                                            fuse_r, f, fo);            \
+        if (fuse_r && sf.nblk_mv > 0)                                                  \
+            k_unpack_xfft<T, N, FUSE_BICG_S><<<grid, NTHR, 0, s>>>(                    \
+                xin, map, G, tw_x, g, act, fuse_r, f, CocgFold{}, sf);                 \
+        else if (fuse_r)                                                               \
+            k_unpack_xfft<T, N, FUSE_COCG><<<grid, NTHR, 0, s>>>(                      \
+                xin, map, G, tw_x, g, act, fuse_r, f, fo, BicgSFold{});                \
         else                                                                           \
-            k_unpack_xfft<T, N, false><<<grid, NTHR, 0, s>>>(xin, map, G, tw_x, g, act, \
-                                                             nullptr, f, CocgFold{});  \
+            k_unpack_xfft<T, N, FUSE_NONE><<<grid, NTHR, 0, s>>>(                      \
+                xin, map, G, tw_x, g, act, nullptr, f, CocgFold{}, BicgSFold{});       \
         break;                                                                         \
     }
         DDA_FOR_EACH_L(DDA_CASE)
@@ -880,9 +931,10 @@ void launch_ixfft_pack(const cx<T>* G, const cx<T>* xin, const cx<T>* ainv, cx<T
 
 template void launch_unpack_xfft<double>(z128*, const int*, z128*, const z128*, const Geo&,
                                          const int*, int, const z128*, SlotFilter, hipStream_t,
-                                         CocgFold);
+                                         CocgFold, BicgSFold);
 template void launch_unpack_xfft<float>(z64*, const int*, z64*, const z64*, const Geo&, const int*,
-                                        int, const z64*, SlotFilter, hipStream_t, CocgFold);
+                                        int, const z64*, SlotFilter, hipStream_t, CocgFold,
+                                        BicgSFold);
 template void launch_fft_mid<double>(z128*, const z128*, int, bool, int64_t, int64_t, int, int,
                                      int64_t, int, hipStream_t);
 template void launch_fft_mid<float>(z64*, const z64*, int, bool, int64_t, int64_t, int, int,

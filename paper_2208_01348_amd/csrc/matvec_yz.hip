@@ -90,14 +90,19 @@ int yz_pack_blocks_per_slot(const Geo& g, int csize) { return 3 * g.nz * xgroups
 // data load before the first use, so a block waits for memory twice rather
 // than once per element.  Only x < HX = ceil(LX / 2) can be occupied
 // (LX >= 2 nx - 1).
-template <typename T, int LX, bool FUSE_P>
+// FUSE: 0 plain gather; FUSE_COCG the COCG direction update p = r + beta p in
+// place (fo: its folded finalizer); FUSE_BICG_S the BiCGStab s = r - alpha v
+// (sf), written in place of the input for an iterating slot.
+template <typename T, int LX, int FUSE>
 __global__ __launch_bounds__(NT) void k_xfft_t(cx<T>* __restrict__ xin,
                                                const int* __restrict__ map,
                                                cx<T>* __restrict__ Tb,
                                                const cx<T>* __restrict__ tw, Geo g,
                                                const int* __restrict__ act,
                                                const cx<T>* __restrict__ fuse_r, SlotFilter f,
-                                               int ngroups, int nr, CocgFold fo) {
+                                               int ngroups, int nr, CocgFold fo, BicgSFold sf) {
+    constexpr bool FUSE_P = FUSE == FUSE_COCG;
+    constexpr bool FUSE_S = FUSE == FUSE_BICG_S;
     constexpr int NR = xrows_max<T, LX>();
     constexpr int LP = LX + 1;  // padded LDS row: the transposed accesses hit spread banks
     constexpr int HX = (LX + 1) / 2;
@@ -108,11 +113,13 @@ __global__ __launch_bounds__(NT) void k_xfft_t(cx<T>* __restrict__ xin,
     const int pos = blockIdx.y;
     const int64_t slot = act ? act[pos] : pos;
     const bool fold = FUSE_P && fo.nblk > 0;
-    if (fold) {  // the folded finalizer may end the slot: one status read per block
+    bool sact = false;  // FUSE_S: this slot iterates, so the block forms s
+    if (fold || FUSE_S) {  // a folded step may change the status: one read per block
         __shared__ int live0;
-        if (tid == 0) live0 = f.st[slot].status == SLOT_ACTIVE;
+        if (tid == 0) live0 = (FUSE_S ? sf.st : f.st)[slot].status == SLOT_ACTIVE;
         __syncthreads();
-        if (!live0) return;
+        if (fold && !live0) return;
+        sact = live0 != 0;
     } else if (!slot_live(f, slot)) {
         return;
     }
@@ -124,7 +131,9 @@ __global__ __launch_bounds__(NT) void k_xfft_t(cx<T>* __restrict__ xin,
     const int y0 = grp * nr;
     const int nrow = min(nr, g.ny - y0);
     cx<T>* src = xin + (slot * 3 + c) * g.n_occ;
-    const cx<T>* rsrc = FUSE_P ? fuse_r + (slot * 3 + c) * g.n_occ : nullptr;
+    const cx<T>* rsrc = FUSE ? fuse_r + (slot * 3 + c) * g.n_occ : nullptr;
+    const cx<T>* vsrc = FUSE_S ? static_cast<const cx<T>*>(sf.v) + (slot * 3 + c) * g.n_occ
+                               : nullptr;
     // loads use clamped (always valid) addresses and are masked afterwards, so
     // that none of them sits behind a branch and all can be in flight at once
     const int* mrow = map + (int64_t(z) * g.ny + y0) * g.nx;
@@ -150,15 +159,39 @@ __global__ __launch_bounds__(NT) void k_xfft_t(cx<T>* __restrict__ xin,
         }
         reset = f.st[slot].reset_p != 0;
     }
-    cx<T> v[NE], w[NE];
+    cx<T> alpha{T(0), T(0)};
+    if constexpr (FUSE_S) {
+        if (sact) {  // block-uniform
+            z128 a;
+            sact = bicg_sfold<NT>(sf, int(slot), blockIdx.x == 0, a);
+            alpha = cvt<T>(a);
+        }
+    }
+    cx<T> v[NE], w[NE], u[FUSE_S ? NE : 1];
 #pragma unroll
     for (int q = 0; q < NE; ++q) {
         const int i = max(idx[q], 0);
-        v[q] = src[i];
-        if (FUSE_P) w[q] = rsrc[i];
+        if constexpr (FUSE_S) {
+            if (sact) {
+                w[q] = rsrc[i];
+                u[q] = vsrc[i];
+            } else {
+                v[q] = src[i];
+            }
+        } else {
+            v[q] = src[i];
+            if (FUSE_P) w[q] = rsrc[i];
+        }
     }
+    double s2 = 0.0;
 #pragma unroll
     for (int q = 0; q < NE; ++q) {
+        if constexpr (FUSE_S) {
+            if (sact) {
+                v[q] = bicg_s_of(w[q], alpha, u[q]);
+                if (idx[q] >= 0) s2 += bicg_norm2(v[q]);
+            }
+        }
         if (idx[q] < 0) v[q] = cx<T>{T(0), T(0)};
     }
 #pragma unroll
@@ -169,9 +202,18 @@ __global__ __launch_bounds__(NT) void k_xfft_t(cx<T>* __restrict__ xin,
             v[q] = reset ? w[q] : w[q] + beta * v[q];
             src[idx[q]] = v[q];
         }
+        if constexpr (FUSE_S) {
+            if (sact && idx[q] >= 0) src[idx[q]] = v[q];
+        }
         if (r < nrow) {
             lds[r * LP + x] = v[q];
             if (x + HX < LX) lds[r * LP + x + HX] = cx<T>{T(0), T(0)};
+        }
+    }
+    if constexpr (FUSE_S) {
+        if (sact) {  // ||s||^2 rows, one per block of the slot (block-uniform)
+            double pr[1] = {s2};
+            block_partial<1, NT, 6>(pr, sf.red, int(slot), blockIdx.x);
         }
     }
     __syncthreads();
@@ -692,7 +734,7 @@ __global__ __launch_bounds__(yzr_threads<L>()) void k_yzconv_r(
 template <typename T>
 void launch_xfft_t(cx<T>* xin, const int* map, cx<T>* Tb, const cx<T>* tw_x, const Geo& g,
                    const int* act, int n_act, const cx<T>* fuse_r, SlotFilter f,
-                   hipStream_t s, CocgFold fo) {
+                   hipStream_t s, CocgFold fo, BicgSFold sf) {
     if (n_act == 0) return;
     if (2 * g.nx - 1 > g.mx) throw Error(-1, "x grid shorter than 2 nx - 1");
     int ng, nr;
@@ -702,11 +744,17 @@ void launch_xfft_t(cx<T>* xin, const int* map, cx<T>* Tb, const cx<T>* tw_x, con
 #define DDA_CASE(N)                                                                         \
     case N:                                                                                 \
         if (fuse_r)                                                                         \
-            k_xfft_t<T, N, true><<<grid, NT, 0, s>>>(xin, map, Tb, tw_x, g, act, fuse_r, f,  \
-                                                     ng, nr, fo);                           \
+            if (sf.nblk_mv > 0)                                                             \
+                k_xfft_t<T, N, FUSE_BICG_S><<<grid, NT, 0, s>>>(xin, map, Tb, tw_x, g, act,  \
+                                                                fuse_r, f, ng, nr,           \
+                                                                CocgFold{}, sf);             \
+            else                                                                            \
+                k_xfft_t<T, N, FUSE_COCG><<<grid, NT, 0, s>>>(xin, map, Tb, tw_x, g, act,    \
+                                                              fuse_r, f, ng, nr, fo,         \
+                                                              BicgSFold{});                  \
         else                                                                                \
-            k_xfft_t<T, N, false><<<grid, NT, 0, s>>>(xin, map, Tb, tw_x, g, act, nullptr,   \
-                                                      f, ng, nr, CocgFold{});               \
+            k_xfft_t<T, N, 0><<<grid, NT, 0, s>>>(xin, map, Tb, tw_x, g, act, nullptr, f, ng, \
+                                                  nr, CocgFold{}, BicgSFold{});             \
         break;
         DDA_FOR_EACH_LX(DDA_CASE)
 #undef DDA_CASE
@@ -812,9 +860,10 @@ void launch_extract_yz(const z128* full, cx<T>* out, const Geo& g, hipStream_t s
 }
 
 template void launch_xfft_t<double>(z128*, const int*, z128*, const z128*, const Geo&, const int*,
-                                    int, const z128*, SlotFilter, hipStream_t, CocgFold);
+                                    int, const z128*, SlotFilter, hipStream_t, CocgFold,
+                                    BicgSFold);
 template void launch_xfft_t<float>(z64*, const int*, z64*, const z64*, const Geo&, const int*, int,
-                                   const z64*, SlotFilter, hipStream_t, CocgFold);
+                                   const z64*, SlotFilter, hipStream_t, CocgFold, BicgSFold);
 template void launch_ixfft_t<double>(const z128*, const z128*, const z128*, z128*, const int*,
                                      const z128*, const Geo&, const int*, const int*, int, int,
                                      SlotFilter, RedScratch, hipStream_t, const z128*);

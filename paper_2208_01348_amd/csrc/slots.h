@@ -265,4 +265,58 @@ __device__ __forceinline__ bool cocg_fold(CocgFold fo, int slot, bool lead, z128
     return go != 0;
 }
 
+// ------------------------------------------------------- BiCGStab s ------
+// s = r - alpha v, its complex product written out with explicit fma calls so
+// that every kernel built from it rounds the same way (the s update is done
+// either by a vector kernel or by the x kernel of the matvec t = A s).
+template <typename T>
+__device__ __forceinline__ cx<T> bicg_s_of(cx<T> r, cx<T> a, cx<T> v) {
+    return cx<T>{fma(-a.x, v.x, fma(a.y, v.y, r.x)), fma(-a.x, v.y, fma(-a.y, v.x, r.y))};
+}
+template <typename T>
+__device__ __forceinline__ double bicg_norm2(cx<T> s) {
+    return double(fma(s.x, s.x, s.y * s.y));
+}
+
+// The BiCGStab s update folded into the x kernel of t = A s: every block sums
+// the <rhat, v> rows of the first matvec's pack kernel (nblk_mv rows, in the
+// vector kernel's order), forms alpha = rho / <rhat, v> and computes s = r -
+// alpha v for the elements it gathers, writing s in place of the input and
+// the partial rows of ||s||^2 (double 6 of row `blk`).  nblk_mv == 0: no fold.
+struct BicgSFold {
+    BicgSlot* st;
+    RedScratch red;
+    int nblk_mv;
+    const void* v;  // v = A p, laid out like the input
+};
+constexpr int kBicgUpdateThreads = 256;  // block size of the vector kernel that updates s
+
+// Every thread of the block calls it, for a slot that is iterating (read once
+// per block); returns false on a breakdown (<rhat, v> zero or not finite),
+// which block `lead` records.
+template <int NTB>
+__device__ __forceinline__ bool bicg_sfold(BicgSFold fo, int slot, bool lead, z128& alpha) {
+    double rv[2];
+    sum_rows_as<2, kBicgUpdateThreads, 0, NTB>(fo.red, slot, fo.nblk_mv, rv);
+    __shared__ double bc[2];
+    __shared__ int go;
+    if (threadIdx.x == 0) {
+        BicgSlot& S = fo.st[slot];
+        const z128 rvz{rv[0], rv[1]};
+        const bool bad = (rv[0] == 0.0 && rv[1] == 0.0) || !isfinite(rv[0]) || !isfinite(rv[1]);
+        const z128 al = bad ? z128{0.0, 0.0} : zdiv(S.rho, rvz);
+        if (lead) {
+            S.rv = rvz;
+            if (bad) S.status = SLOT_BREAKDOWN;
+            else S.alpha = al;
+        }
+        bc[0] = al.x;
+        bc[1] = al.y;
+        go = !bad;
+    }
+    __syncthreads();
+    alpha = z128{bc[0], bc[1]};
+    return go != 0;
+}
+
 }  // namespace dda
