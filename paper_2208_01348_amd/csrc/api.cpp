@@ -48,8 +48,8 @@ constexpr double kQmrInner = 1e-4;
 // this many slots per launch (measured: a single solve 3.7 % faster, a
 // 52-slot spectrum batch 2.5 % slower with the fold)
 constexpr int kCocgFoldMaxSlots = 8;
-// BiCGStab folds its s update into the x kernel of t = A s up to this many
-// slots per launch
+// BiCGStab folds its p and s updates into the x kernels of the two matvecs up
+// to this many slots per launch
 constexpr int kBicgFoldMaxSlots = 8;
 
 // ------------------------------------------------------------------ memory
@@ -552,9 +552,9 @@ void matvec(dda_ctx* c, const Work& w, dda::cx<T>* x, dda::cx<T>* y, const int* 
             const dda::cx<T>* fuse_r = nullptr,
             dda::SlotFilter f = dda::SlotFilter{nullptr, dda::FILTER_ALL},
             const dda::cx<T>* dotw = nullptr, dda::CocgFold fold = dda::CocgFold{},
-            dda::BicgSFold sfold = dda::BicgSFold{}) {
+            dda::BicgFold bfold = dda::BicgFold{}) {
     if (n_act == 0 || c->g.n_occ == 0) return;
-    if (((fuse_r && sfold.nblk_mv == 0) || f.mode != dda::FILTER_ALL) && !f.st)
+    if (((fuse_r && bfold.kind == dda::BICG_FOLD_NONE) || f.mode != dda::FILTER_ALL) && !f.st)
         throw Error(DDA_EDEVICE, "slot filter without slot states");
     dda::Geo g = c->g;
     const int* map = c->map.as<int>();
@@ -571,7 +571,7 @@ void matvec(dda_ctx* c, const Work& w, dda::cx<T>* x, dda::cx<T>* y, const int* 
         {
             Tic t(c, 0, n_act);
             dda::launch_xfft_t<T>(x, map, G, tw_of<T>(c, 0), g, act, n_act, fuse_r,
-                                  f, s, fold, sfold);
+                                  f, s, fold, bfold);
         }
         {
             Tic t(c, 5, n_act);
@@ -588,7 +588,7 @@ void matvec(dda_ctx* c, const Work& w, dda::cx<T>* x, dda::cx<T>* y, const int* 
         {
             Tic t(c, 0, n_act);
             dda::launch_unpack_xfft<T>(x, map, G, tw_of<T>(c, 0), g, act, n_act,
-                                       fuse_r, f, s, fold, sfold);
+                                       fuse_r, f, s, fold, bfold);
         }
         {
             Tic t(c, 1, n_act);
@@ -619,9 +619,9 @@ void matvec(dda_ctx* c, dda::cx<T>* x, dda::cx<T>* y, const int* act, int n_act,
             const dda::cx<T>* fuse_r = nullptr,
             dda::SlotFilter f = dda::SlotFilter{nullptr, dda::FILTER_ALL},
             const dda::cx<T>* dotw = nullptr, dda::CocgFold fold = dda::CocgFold{},
-            dda::BicgSFold sfold = dda::BicgSFold{}) {
+            dda::BicgFold bfold = dda::BicgFold{}) {
     matvec<T>(c, ctx_work(c), x, y, act, n_act, dptr, slot_sys, ainv, mode, fuse_r, f, dotw, fold,
-              sfold);
+              bfold);
 }
 
 // ------------------------------------------------------------ D cache
@@ -859,22 +859,30 @@ void run_bicgstab(dda_ctx* c, int nslots, const dda::cx<T>* b, dda::cx<T>* x, Ve
     // One interval of `check` iterations over the n_act slots listed in dact.
     const int nblk_mv = pack_blocks(c, int(sizeof(dda::cx<T>)));
     const dda::SlotFilter all{nullptr, dda::FILTER_ALL};
-    // For a small batch the s update is folded into the x kernel of t = A s
-    // (one vector kernel less per iteration; same s bit for bit, its norm
-    // summed over other partitions); for a large one every block of that
-    // kernel would sum the <rhat, v> rows, which costs more than it saves.
+    // For a small batch the p and s updates are folded into the x kernels of
+    // v = A p and t = A s (two vector kernels less per iteration; the same
+    // p and s bit for bit, ||s||^2 summed over another partition); for a
+    // large one the row sums in every block of those kernels cost more than
+    // the launches save.
     const int nblk_x = dda::xfft_blocks_per_slot(c->g, int(sizeof(dda::cx<T>)));
     if (nblk_x > red.max_blocks) throw Error(DDA_EDEVICE, "x kernel rows exceed the scratch");
+    const int nblk_xr = dda::cocg_rows(nv, red.max_blocks);  // rows of k_update_xr
     auto interval = [&](int n_act) {
         const bool fold_s = n_act <= kBicgFoldMaxSlots;
         for (int k = 0; k < check; ++k) {
-            dda::bicg_update_p<T>(w.r, w.p, w.v, st, dact, n_act, nv, red, k > 0, s);
-            matvec<T>(c, w.p, w.v, dact, n_act, dptr, slot_sys, ainv, dda::PACK_AX_DOTW, nullptr,
-                      all, w.rhat);
+            if (fold_s) {  // p update folded into the x kernel of v = A p
+                matvec<T>(c, w.p, w.v, dact, n_act, dptr, slot_sys, ainv, dda::PACK_AX_DOTW, w.r,
+                          all, w.rhat, dda::CocgFold{},
+                          dda::BicgFold{st, red, dda::BICG_FOLD_P, k > 0 ? nblk_xr : 0, w.v});
+            } else {
+                dda::bicg_update_p<T>(w.r, w.p, w.v, st, dact, n_act, nv, red, k > 0, s);
+                matvec<T>(c, w.p, w.v, dact, n_act, dptr, slot_sys, ainv, dda::PACK_AX_DOTW,
+                          nullptr, all, w.rhat);
+            }
             if (fold_s) {
                 matvec<T>(c, w.s, w.t, dact, n_act, dptr, slot_sys, ainv, dda::PACK_AX_TS, w.r,
                           all, nullptr, dda::CocgFold{},
-                          dda::BicgSFold{st, red, nblk_mv, w.v});
+                          dda::BicgFold{st, red, dda::BICG_FOLD_S, nblk_mv, w.v});
             } else {
                 dda::bicg_update_s<T>(w.r, w.v, w.s, st, dact, n_act, nv, red, nblk_mv, s);
                 matvec<T>(c, w.s, w.t, dact, n_act, dptr, slot_sys, ainv, dda::PACK_AX_TS);

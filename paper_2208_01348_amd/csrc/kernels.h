@@ -45,14 +45,14 @@ bool fft_length_supported(int L);
 // vector; with fo.nblk > 0 it first ends the previous COCG iteration itself
 // (CocgFold: beta and the slot's status from that iteration's rows).  Every
 // kernel of the chain skips the slots the filter rejects.
-// With sf.nblk_mv > 0 (BiCGStab) the kernel instead forms s = fuse_r - alpha
-// sf.v for an iterating slot, writes it in place of x and transforms it
-// (BicgSFold).
-enum FuseMode { FUSE_NONE = 0, FUSE_COCG = 1, FUSE_BICG_S = 2 };
+// With bf.kind set (BiCGStab) the kernel instead forms, for an iterating slot,
+// s = fuse_r - alpha bf.v or p = fuse_r + beta (x - omega bf.v), writes it in
+// place of x and transforms it (BicgFold).
+enum FuseMode { FUSE_NONE = 0, FUSE_COCG = 1, FUSE_BICG_S = 2, FUSE_BICG_P = 3 };
 template <typename T>
 void launch_unpack_xfft(cx<T>* xin, const int* map, cx<T>* G, const cx<T>* tw_x, const Geo& g,
                         const int* act, int n_act, const cx<T>* fuse_r, SlotFilter f,
-                        hipStream_t s, CocgFold fo = CocgFold{}, BicgSFold sf = BicgSFold{});
+                        hipStream_t s, CocgFold fo = CocgFold{}, BicgFold bf = BicgFold{});
 // tx: columns per block (0: the default width; see mid_tx_candidates).
 template <typename T>
 void launch_fft_mid(cx<T>* data, const cx<T>* tw, int L, bool inverse, int64_t n_outer,
@@ -169,7 +169,7 @@ int yz_pack_blocks_per_slot(const Geo& g, int csize);
 template <typename T>
 void launch_xfft_t(cx<T>* xin, const int* map, cx<T>* Tb, const cx<T>* tw_x, const Geo& g,
                    const int* act, int n_act, const cx<T>* fuse_r, SlotFilter f, hipStream_t s,
-                   CocgFold fo = CocgFold{}, BicgSFold sf = BicgSFold{});
+                   CocgFold fo = CocgFold{}, BicgFold bf = BicgFold{});
 // blocks per slot of the x kernel of either chain (the rows a folded s update writes)
 int xfft_blocks_per_slot(const Geo& g, int csize);
 // nthreads: threads per block (0: the default; see yz_thread_candidates)

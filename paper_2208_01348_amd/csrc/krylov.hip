@@ -153,28 +153,6 @@ __device__ __forceinline__ void slot_totals(RedScratch red, int slot, int nblk, 
     for (int k = 0; k < K; ++k) v[k] = sh[k];
 }
 
-// End of an iteration from the rows <rhat, r>, ||r||^2 at 0..2: the new rho,
-// the residual norm, the iteration count and the status.  Returns the new
-// status; the state is stored by `lead` only.
-__device__ __forceinline__ int finish_iteration(BicgSlot& S, int status, const double (&tot)[3],
-                                                bool lead) {
-    int ns = status;
-    if (!all_finite(tot, 3)) {
-        ns = SLOT_BREAKDOWN;
-    } else if (status == SLOT_HALF || tot[2] <= S.tol2 * S.bnorm2) {
-        ns = SLOT_CONVERGED;
-    } else if ((tot[0] == 0.0 && tot[1] == 0.0) || (S.omega.x == 0.0 && S.omega.y == 0.0)) {
-        ns = SLOT_BREAKDOWN;
-    }
-    if (lead) {
-        S.iters += 1;
-        S.rho = z128{tot[0], tot[1]};
-        S.rnorm2 = tot[2];
-        if (ns != status) S.status = ns;
-    }
-    return ns;
-}
-
 template <typename T, bool FIN>
 __global__ __launch_bounds__(NT) void k_update_p(const cx<T>* __restrict__ r, cx<T>* __restrict__ p,
                                                  const cx<T>* __restrict__ v, BicgSlot* st,
@@ -198,11 +176,10 @@ __global__ __launch_bounds__(NT) void k_update_p(const cx<T>* __restrict__ r, cx
     const z128 beta = zdiv(rho, S.rho_old) * zdiv(S.alpha, S.omega);
     const cx<T> bt{T(beta.x), T(beta.y)};
     const cx<T> om{T(S.omega.x), T(S.omega.y)};
-    for (int64_t i = i0; i < nv; i += stride) {
-        const cx<T> pi = p[base + i];
-        p[base + i] = r[base + i] + bt * (pi - om * v[base + i]);
-    }
+    for (int64_t i = i0; i < nv; i += stride)
+        p[base + i] = bicg_p_of(r[base + i], bt, p[base + i], om, v[base + i]);
 }
+static_assert(NT == kBicgUpdateThreads, "the folded p update sums like this kernel");
 
 template <typename T>
 __global__ __launch_bounds__(NT) void k_update_s(const cx<T>* __restrict__ r,

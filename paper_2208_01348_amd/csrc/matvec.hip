@@ -72,7 +72,7 @@ bool fft_length_supported(int L) {
 
 // ---------------------------------------------------------------- K1 ------
 // FUSE: as k_xfft_t (plain gather, the COCG direction update, or the
-// BiCGStab s update).
+// BiCGStab s or p update).
 template <typename T, int L, int FUSE>
 __global__ __launch_bounds__(NTHR) void k_unpack_xfft(cx<T>* __restrict__ xin,
                                                       const int* __restrict__ map,
@@ -80,9 +80,10 @@ __global__ __launch_bounds__(NTHR) void k_unpack_xfft(cx<T>* __restrict__ xin,
                                                       const cx<T>* __restrict__ tw, Geo g,
                                                       const int* __restrict__ act,
                                                       const cx<T>* __restrict__ fuse_r,
-                                                      SlotFilter f, CocgFold fo, BicgSFold sf) {
+                                                      SlotFilter f, CocgFold fo, BicgFold bf) {
     constexpr bool FUSE_P = FUSE == FUSE_COCG;
     constexpr bool FUSE_S = FUSE == FUSE_BICG_S;
+    constexpr bool FUSE_BP = FUSE == FUSE_BICG_P;
     constexpr int NL = rows_nl<T, L>();
     __shared__ cx<T> lds[NL * L];
     __shared__ cx<T> twl[L];
@@ -91,13 +92,15 @@ __global__ __launch_bounds__(NTHR) void k_unpack_xfft(cx<T>* __restrict__ xin,
     const int pos = blockIdx.z;
     const int64_t slot = act ? act[pos] : pos;
     const bool fold = FUSE_P && fo.nblk > 0;
-    bool sact = false;  // FUSE_S: this slot iterates, so the block forms s
-    if (fold || FUSE_S) {  // a folded step may change the status: one read per block
-        __shared__ int live0;
-        if (tid == 0) live0 = (FUSE_S ? sf.st : f.st)[slot].status == SLOT_ACTIVE;
+    bool sact = false;  // FUSE_S, FUSE_BP: this slot iterates, so the block updates
+    int status0 = SLOT_ACTIVE;
+    if (fold || FUSE_S || FUSE_BP) {  // a folded step may change the status: one read per block
+        __shared__ int st0;
+        if (tid == 0) st0 = (FUSE_S || FUSE_BP ? bf.st : f.st)[slot].status;
         __syncthreads();
-        if (fold && !live0) return;
-        sact = live0 != 0;
+        status0 = st0;
+        if (fold && status0 != SLOT_ACTIVE) return;
+        sact = status0 == SLOT_ACTIVE;
     } else if (!slot_live(f, slot)) {
         return;
     }
@@ -107,8 +110,9 @@ __global__ __launch_bounds__(NTHR) void k_unpack_xfft(cx<T>* __restrict__ xin,
     const int row0 = blockIdx.x * NL;
     cx<T>* src = xin + (slot * 3 + c) * g.n_occ;
     const cx<T>* rsrc = FUSE ? fuse_r + (slot * 3 + c) * g.n_occ : nullptr;
-    const cx<T>* vsrc = FUSE_S ? static_cast<const cx<T>*>(sf.v) + (slot * 3 + c) * g.n_occ
-                               : nullptr;
+    const cx<T>* vsrc = (FUSE_S || FUSE_BP)
+                            ? static_cast<const cx<T>*>(bf.v) + (slot * 3 + c) * g.n_occ
+                            : nullptr;
     // only x < (L+1)/2 can be occupied; every index load, then every data
     // load, is issued before the first use (clamped addresses, masked after)
     constexpr int HX = (L + 1) / 2;
@@ -137,15 +141,21 @@ __global__ __launch_bounds__(NTHR) void k_unpack_xfft(cx<T>* __restrict__ xin,
         }
         reset = f.st[slot].reset_p != 0;
     }
-    cx<T> alpha{T(0), T(0)};
+    cx<T> alpha{T(0), T(0)}, bt{T(0), T(0)}, om{T(0), T(0)};
     if constexpr (FUSE_S) {
         if (sact) {  // block-uniform
             z128 a;
-            sact = bicg_sfold<NTHR>(sf, int(slot), blockIdx.x == 0 && c == 0, a);
+            sact = bicg_sfold<NTHR>(bf, int(slot), blockIdx.x == 0 && c == 0, a);
             alpha = cvt<T>(a);
         }
     }
-    cx<T> v[NE], w[FUSE ? NE : 1], u[FUSE_S ? NE : 1];
+    if constexpr (FUSE_BP) {
+        z128 b, o;
+        sact = bicg_pfold<NTHR>(bf, int(slot), status0, blockIdx.x == 0 && c == 0, b, o);
+        bt = cvt<T>(b);
+        om = cvt<T>(o);
+    }
+    cx<T> v[NE], w[FUSE ? NE : 1], u[FUSE_S || FUSE_BP ? NE : 1];
 #pragma unroll
     for (int q = 0; q < NE; ++q) {
         const int i = max(idx[q], 0);
@@ -155,6 +165,12 @@ __global__ __launch_bounds__(NTHR) void k_unpack_xfft(cx<T>* __restrict__ xin,
                 u[q] = vsrc[i];
             } else {
                 v[q] = src[i];
+            }
+        } else if constexpr (FUSE_BP) {
+            v[q] = src[i];
+            if (sact) {
+                w[q] = rsrc[i];
+                u[q] = vsrc[i];
             }
         } else {
             v[q] = src[i];
@@ -175,6 +191,13 @@ __global__ __launch_bounds__(NTHR) void k_unpack_xfft(cx<T>* __restrict__ xin,
             } else {
                 vq = v[q];
             }
+        } else if constexpr (FUSE_BP) {
+            vq = v[q];
+            if (sact) {
+                const cx<T> upd = bicg_p_of(w[q], bt, vq, om, u[q]);
+                vq.x = upd.x;  // component-wise: a select of the whole FP64 pair goes
+                vq.y = upd.y;  // through scratch
+            }
         } else {
             vq = v[q];
         }
@@ -186,7 +209,7 @@ __global__ __launch_bounds__(NTHR) void k_unpack_xfft(cx<T>* __restrict__ xin,
         vq.x = occ ? vq.x : T(0);
         vq.y = occ ? vq.y : T(0);
         // each occupied element: exactly one thread
-        if ((FUSE_P || (FUSE_S && sact)) && occ) src[idx[q]] = vq;
+        if ((FUSE_P || ((FUSE_S || FUSE_BP) && sact)) && occ) src[idx[q]] = vq;
         if (rr < NL) {
             lds[rr * L + x] = vq;
             if (x + HX < L) lds[rr * L + x + HX] = zero;
@@ -195,7 +218,7 @@ __global__ __launch_bounds__(NTHR) void k_unpack_xfft(cx<T>* __restrict__ xin,
     if constexpr (FUSE_S) {
         if (sact) {  // ||s||^2 rows, one per block of the slot (block-uniform)
             double pr[1] = {s2};
-            block_partial<1, NTHR, 6>(pr, sf.red, int(slot), blockIdx.x + gridDim.x * c);
+            block_partial<1, NTHR, 6>(pr, bf.red, int(slot), blockIdx.x + gridDim.x * c);
         }
     }
     __syncthreads();
@@ -691,22 +714,25 @@ int pack_blocks_per_slot(const Geo& g) {
 template <typename T>
 void launch_unpack_xfft(cx<T>* xin, const int* map, cx<T>* G, const cx<T>* tw_x, const Geo& g,
                         const int* act, int n_act, const cx<T>* fuse_r, SlotFilter f,
-                        hipStream_t s, CocgFold fo, BicgSFold sf) {
+                        hipStream_t s, CocgFold fo, BicgFold bf) {
     if (n_act == 0) return;
     const int64_t nrows = int64_t(g.nz) * g.ny;
     switch (g.mx) {
 #define DDA_CASE(N)                                                                    \
     case N: {                                                                          \
         dim3 grid(nblk(nrows, rows_nl<T, N>()), 3, n_act);                             \
-        if (fuse_r && sf.nblk_mv > 0)                                                  \
+        if (fuse_r && bf.kind == BICG_FOLD_S)                                          \
             k_unpack_xfft<T, N, FUSE_BICG_S><<<grid, NTHR, 0, s>>>(                    \
-                xin, map, G, tw_x, g, act, fuse_r, f, CocgFold{}, sf);                 \
+                xin, map, G, tw_x, g, act, fuse_r, f, CocgFold{}, bf);                 \
+        else if (fuse_r && bf.kind == BICG_FOLD_P)                                     \
+            k_unpack_xfft<T, N, FUSE_BICG_P><<<grid, NTHR, 0, s>>>(                    \
+                xin, map, G, tw_x, g, act, fuse_r, f, CocgFold{}, bf);                 \
         else if (fuse_r)                                                               \
             k_unpack_xfft<T, N, FUSE_COCG><<<grid, NTHR, 0, s>>>(                      \
-                xin, map, G, tw_x, g, act, fuse_r, f, fo, BicgSFold{});                \
+                xin, map, G, tw_x, g, act, fuse_r, f, fo, BicgFold{});                 \
         else                                                                           \
             k_unpack_xfft<T, N, FUSE_NONE><<<grid, NTHR, 0, s>>>(                      \
-                xin, map, G, tw_x, g, act, nullptr, f, CocgFold{}, BicgSFold{});       \
+                xin, map, G, tw_x, g, act, nullptr, f, CocgFold{}, BicgFold{});        \
         break;                                                                         \
     }
         DDA_FOR_EACH_L(DDA_CASE)
@@ -931,10 +957,10 @@ void launch_ixfft_pack(const cx<T>* G, const cx<T>* xin, const cx<T>* ainv, cx<T
 
 template void launch_unpack_xfft<double>(z128*, const int*, z128*, const z128*, const Geo&,
                                          const int*, int, const z128*, SlotFilter, hipStream_t,
-                                         CocgFold, BicgSFold);
+                                         CocgFold, BicgFold);
 template void launch_unpack_xfft<float>(z64*, const int*, z64*, const z64*, const Geo&, const int*,
                                         int, const z64*, SlotFilter, hipStream_t, CocgFold,
-                                        BicgSFold);
+                                        BicgFold);
 template void launch_fft_mid<double>(z128*, const z128*, int, bool, int64_t, int64_t, int, int,
                                      int64_t, int, hipStream_t);
 template void launch_fft_mid<float>(z64*, const z64*, int, bool, int64_t, int64_t, int, int,

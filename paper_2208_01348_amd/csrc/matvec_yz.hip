@@ -91,8 +91,9 @@ int yz_pack_blocks_per_slot(const Geo& g, int csize) { return 3 * g.nz * xgroups
 // than once per element.  Only x < HX = ceil(LX / 2) can be occupied
 // (LX >= 2 nx - 1).
 // FUSE: 0 plain gather; FUSE_COCG the COCG direction update p = r + beta p in
-// place (fo: its folded finalizer); FUSE_BICG_S the BiCGStab s = r - alpha v
-// (sf), written in place of the input for an iterating slot.
+// place (fo: its folded finalizer); FUSE_BICG_S / FUSE_BICG_P the BiCGStab
+// s = r - alpha v / p = r + beta (p - omega v) (bf), written in place of the
+// input for an iterating slot.
 template <typename T, int LX, int FUSE>
 __global__ __launch_bounds__(NT) void k_xfft_t(cx<T>* __restrict__ xin,
                                                const int* __restrict__ map,
@@ -100,9 +101,10 @@ __global__ __launch_bounds__(NT) void k_xfft_t(cx<T>* __restrict__ xin,
                                                const cx<T>* __restrict__ tw, Geo g,
                                                const int* __restrict__ act,
                                                const cx<T>* __restrict__ fuse_r, SlotFilter f,
-                                               int ngroups, int nr, CocgFold fo, BicgSFold sf) {
+                                               int ngroups, int nr, CocgFold fo, BicgFold bf) {
     constexpr bool FUSE_P = FUSE == FUSE_COCG;
     constexpr bool FUSE_S = FUSE == FUSE_BICG_S;
+    constexpr bool FUSE_BP = FUSE == FUSE_BICG_P;
     constexpr int NR = xrows_max<T, LX>();
     constexpr int LP = LX + 1;  // padded LDS row: the transposed accesses hit spread banks
     constexpr int HX = (LX + 1) / 2;
@@ -113,13 +115,15 @@ __global__ __launch_bounds__(NT) void k_xfft_t(cx<T>* __restrict__ xin,
     const int pos = blockIdx.y;
     const int64_t slot = act ? act[pos] : pos;
     const bool fold = FUSE_P && fo.nblk > 0;
-    bool sact = false;  // FUSE_S: this slot iterates, so the block forms s
-    if (fold || FUSE_S) {  // a folded step may change the status: one read per block
-        __shared__ int live0;
-        if (tid == 0) live0 = (FUSE_S ? sf.st : f.st)[slot].status == SLOT_ACTIVE;
+    bool sact = false;  // FUSE_S, FUSE_BP: this slot iterates, so the block updates
+    int status0 = SLOT_ACTIVE;
+    if (fold || FUSE_S || FUSE_BP) {  // a folded step may change the status: one read per block
+        __shared__ int st0;
+        if (tid == 0) st0 = (FUSE_S || FUSE_BP ? bf.st : f.st)[slot].status;
         __syncthreads();
-        if (fold && !live0) return;
-        sact = live0 != 0;
+        status0 = st0;
+        if (fold && status0 != SLOT_ACTIVE) return;
+        sact = status0 == SLOT_ACTIVE;
     } else if (!slot_live(f, slot)) {
         return;
     }
@@ -132,8 +136,9 @@ __global__ __launch_bounds__(NT) void k_xfft_t(cx<T>* __restrict__ xin,
     const int nrow = min(nr, g.ny - y0);
     cx<T>* src = xin + (slot * 3 + c) * g.n_occ;
     const cx<T>* rsrc = FUSE ? fuse_r + (slot * 3 + c) * g.n_occ : nullptr;
-    const cx<T>* vsrc = FUSE_S ? static_cast<const cx<T>*>(sf.v) + (slot * 3 + c) * g.n_occ
-                               : nullptr;
+    const cx<T>* vsrc = (FUSE_S || FUSE_BP)
+                            ? static_cast<const cx<T>*>(bf.v) + (slot * 3 + c) * g.n_occ
+                            : nullptr;
     // loads use clamped (always valid) addresses and are masked afterwards, so
     // that none of them sits behind a branch and all can be in flight at once
     const int* mrow = map + (int64_t(z) * g.ny + y0) * g.nx;
@@ -159,15 +164,21 @@ __global__ __launch_bounds__(NT) void k_xfft_t(cx<T>* __restrict__ xin,
         }
         reset = f.st[slot].reset_p != 0;
     }
-    cx<T> alpha{T(0), T(0)};
+    cx<T> alpha{T(0), T(0)}, bt{T(0), T(0)}, om{T(0), T(0)};
     if constexpr (FUSE_S) {
         if (sact) {  // block-uniform
             z128 a;
-            sact = bicg_sfold<NT>(sf, int(slot), blockIdx.x == 0, a);
+            sact = bicg_sfold<NT>(bf, int(slot), blockIdx.x == 0, a);
             alpha = cvt<T>(a);
         }
     }
-    cx<T> v[NE], w[NE], u[FUSE_S ? NE : 1];
+    if constexpr (FUSE_BP) {
+        z128 b, o;
+        sact = bicg_pfold<NT>(bf, int(slot), status0, blockIdx.x == 0, b, o);
+        bt = cvt<T>(b);
+        om = cvt<T>(o);
+    }
+    cx<T> v[NE], w[NE], u[FUSE_S || FUSE_BP ? NE : 1];
 #pragma unroll
     for (int q = 0; q < NE; ++q) {
         const int i = max(idx[q], 0);
@@ -177,6 +188,12 @@ __global__ __launch_bounds__(NT) void k_xfft_t(cx<T>* __restrict__ xin,
                 u[q] = vsrc[i];
             } else {
                 v[q] = src[i];
+            }
+        } else if constexpr (FUSE_BP) {
+            v[q] = src[i];
+            if (sact) {
+                w[q] = rsrc[i];
+                u[q] = vsrc[i];
             }
         } else {
             v[q] = src[i];
@@ -192,6 +209,9 @@ __global__ __launch_bounds__(NT) void k_xfft_t(cx<T>* __restrict__ xin,
                 if (idx[q] >= 0) s2 += bicg_norm2(v[q]);
             }
         }
+        if constexpr (FUSE_BP) {
+            if (sact) v[q] = bicg_p_of(w[q], bt, v[q], om, u[q]);
+        }
         if (idx[q] < 0) v[q] = cx<T>{T(0), T(0)};
     }
 #pragma unroll
@@ -202,7 +222,7 @@ __global__ __launch_bounds__(NT) void k_xfft_t(cx<T>* __restrict__ xin,
             v[q] = reset ? w[q] : w[q] + beta * v[q];
             src[idx[q]] = v[q];
         }
-        if constexpr (FUSE_S) {
+        if constexpr (FUSE_S || FUSE_BP) {
             if (sact && idx[q] >= 0) src[idx[q]] = v[q];
         }
         if (r < nrow) {
@@ -213,7 +233,7 @@ __global__ __launch_bounds__(NT) void k_xfft_t(cx<T>* __restrict__ xin,
     if constexpr (FUSE_S) {
         if (sact) {  // ||s||^2 rows, one per block of the slot (block-uniform)
             double pr[1] = {s2};
-            block_partial<1, NT, 6>(pr, sf.red, int(slot), blockIdx.x);
+            block_partial<1, NT, 6>(pr, bf.red, int(slot), blockIdx.x);
         }
     }
     __syncthreads();
@@ -734,7 +754,7 @@ __global__ __launch_bounds__(yzr_threads<L>()) void k_yzconv_r(
 template <typename T>
 void launch_xfft_t(cx<T>* xin, const int* map, cx<T>* Tb, const cx<T>* tw_x, const Geo& g,
                    const int* act, int n_act, const cx<T>* fuse_r, SlotFilter f,
-                   hipStream_t s, CocgFold fo, BicgSFold sf) {
+                   hipStream_t s, CocgFold fo, BicgFold bf) {
     if (n_act == 0) return;
     if (2 * g.nx - 1 > g.mx) throw Error(-1, "x grid shorter than 2 nx - 1");
     int ng, nr;
@@ -744,17 +764,21 @@ void launch_xfft_t(cx<T>* xin, const int* map, cx<T>* Tb, const cx<T>* tw_x, con
 #define DDA_CASE(N)                                                                         \
     case N:                                                                                 \
         if (fuse_r)                                                                         \
-            if (sf.nblk_mv > 0)                                                             \
+            if (bf.kind == BICG_FOLD_S)                                                     \
                 k_xfft_t<T, N, FUSE_BICG_S><<<grid, NT, 0, s>>>(xin, map, Tb, tw_x, g, act,  \
                                                                 fuse_r, f, ng, nr,           \
-                                                                CocgFold{}, sf);             \
+                                                                CocgFold{}, bf);             \
+            else if (bf.kind == BICG_FOLD_P)                                                \
+                k_xfft_t<T, N, FUSE_BICG_P><<<grid, NT, 0, s>>>(xin, map, Tb, tw_x, g, act,  \
+                                                                fuse_r, f, ng, nr,           \
+                                                                CocgFold{}, bf);             \
             else                                                                            \
                 k_xfft_t<T, N, FUSE_COCG><<<grid, NT, 0, s>>>(xin, map, Tb, tw_x, g, act,    \
                                                               fuse_r, f, ng, nr, fo,         \
-                                                              BicgSFold{});                  \
+                                                              BicgFold{});                   \
         else                                                                                \
             k_xfft_t<T, N, 0><<<grid, NT, 0, s>>>(xin, map, Tb, tw_x, g, act, nullptr, f, ng, \
-                                                  nr, CocgFold{}, BicgSFold{});             \
+                                                  nr, CocgFold{}, BicgFold{});              \
         break;
         DDA_FOR_EACH_LX(DDA_CASE)
 #undef DDA_CASE
@@ -861,9 +885,9 @@ void launch_extract_yz(const z128* full, cx<T>* out, const Geo& g, hipStream_t s
 
 template void launch_xfft_t<double>(z128*, const int*, z128*, const z128*, const Geo&, const int*,
                                     int, const z128*, SlotFilter, hipStream_t, CocgFold,
-                                    BicgSFold);
+                                    BicgFold);
 template void launch_xfft_t<float>(z64*, const int*, z64*, const z64*, const Geo&, const int*, int,
-                                   const z64*, SlotFilter, hipStream_t, CocgFold, BicgSFold);
+                                   const z64*, SlotFilter, hipStream_t, CocgFold, BicgFold);
 template void launch_ixfft_t<double>(const z128*, const z128*, const z128*, z128*, const int*,
                                      const z128*, const Geo&, const int*, const int*, int, int,
                                      SlotFilter, RedScratch, hipStream_t, const z128*);

@@ -265,39 +265,73 @@ __device__ __forceinline__ bool cocg_fold(CocgFold fo, int slot, bool lead, z128
     return go != 0;
 }
 
-// ------------------------------------------------------- BiCGStab s ------
-// s = r - alpha v, its complex product written out with explicit fma calls so
-// that every kernel built from it rounds the same way (the s update is done
-// either by a vector kernel or by the x kernel of the matvec t = A s).
+// --------------------------------------------------- BiCGStab folds ------
+// s = r - alpha v and p = r + beta (p - omega v), their complex products
+// written out with explicit fma calls so that every kernel built from them
+// rounds the same way (each update is done either by a vector kernel or by
+// the x kernel of the next matvec).
 template <typename T>
 __device__ __forceinline__ cx<T> bicg_s_of(cx<T> r, cx<T> a, cx<T> v) {
     return cx<T>{fma(-a.x, v.x, fma(a.y, v.y, r.x)), fma(-a.x, v.y, fma(-a.y, v.x, r.y))};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> bicg_p_of(cx<T> r, cx<T> bt, cx<T> p, cx<T> om, cx<T> v) {
+    const cx<T> t{fma(-om.x, v.x, fma(om.y, v.y, p.x)), fma(-om.x, v.y, fma(-om.y, v.x, p.y))};
+    return cx<T>{fma(bt.x, t.x, fma(-bt.y, t.y, r.x)), fma(bt.x, t.y, fma(bt.y, t.x, r.y))};
 }
 template <typename T>
 __device__ __forceinline__ double bicg_norm2(cx<T> s) {
     return double(fma(s.x, s.x, s.y * s.y));
 }
 
-// The BiCGStab s update folded into the x kernel of t = A s: every block sums
-// the <rhat, v> rows of the first matvec's pack kernel (nblk_mv rows, in the
-// vector kernel's order), forms alpha = rho / <rhat, v> and computes s = r -
-// alpha v for the elements it gathers, writing s in place of the input and
-// the partial rows of ||s||^2 (double 6 of row `blk`).  nblk_mv == 0: no fold.
-struct BicgSFold {
+// End of a BiCGStab iteration from the rows <rhat, r>, ||r||^2: the new rho,
+// the residual norm, the iteration count and the status.  Returns the new
+// status; the state is stored by `lead` only, and the decision reads no field
+// that is written here, so every block evaluating it decides alike.
+__device__ __forceinline__ int finish_iteration(BicgSlot& S, int status, const double (&tot)[3],
+                                                bool lead) {
+    int ns = status;
+    if (!(isfinite(tot[0]) && isfinite(tot[1]) && isfinite(tot[2]))) {
+        ns = SLOT_BREAKDOWN;
+    } else if (status == SLOT_HALF || tot[2] <= S.tol2 * S.bnorm2) {
+        ns = SLOT_CONVERGED;
+    } else if ((tot[0] == 0.0 && tot[1] == 0.0) || (S.omega.x == 0.0 && S.omega.y == 0.0)) {
+        ns = SLOT_BREAKDOWN;
+    }
+    if (lead) {
+        S.iters += 1;
+        S.rho = z128{tot[0], tot[1]};
+        S.rnorm2 = tot[2];
+        if (ns != status) S.status = ns;
+    }
+    return ns;
+}
+
+// A BiCGStab vector update folded into the x kernel of the next matvec
+// (kind BICG_FOLD_S: s = r - alpha v before t = A s; BICG_FOLD_P: p = r +
+// beta (p - omega v) before v = A p).  Every block sums the rows the vector
+// kernel would sum, in its order (nblk rows: <rhat, v> for s; <rhat, r>,
+// ||r||^2 for p, or none when the iteration's rho is already in the state),
+// forms the scalars itself and updates the elements it gathers in place;
+// block 0 records the scalars and the status.  The s update also writes the
+// partial rows of ||s||^2 (double 6 of row `blk`).  kind 0: no fold.
+enum BicgFoldKind { BICG_FOLD_NONE = 0, BICG_FOLD_S = 1, BICG_FOLD_P = 2 };
+struct BicgFold {
     BicgSlot* st;
     RedScratch red;
-    int nblk_mv;
+    int kind;
+    int nblk;
     const void* v;  // v = A p, laid out like the input
 };
-constexpr int kBicgUpdateThreads = 256;  // block size of the vector kernel that updates s
+constexpr int kBicgUpdateThreads = 256;  // block size of the vector kernels it stands in for
 
-// Every thread of the block calls it, for a slot that is iterating (read once
-// per block); returns false on a breakdown (<rhat, v> zero or not finite),
-// which block `lead` records.
+// s update: every thread of the block calls it for a slot that is iterating
+// (status read once per block); returns false on a breakdown (<rhat, v> zero
+// or not finite), which block `lead` records.
 template <int NTB>
-__device__ __forceinline__ bool bicg_sfold(BicgSFold fo, int slot, bool lead, z128& alpha) {
+__device__ __forceinline__ bool bicg_sfold(BicgFold fo, int slot, bool lead, z128& alpha) {
     double rv[2];
-    sum_rows_as<2, kBicgUpdateThreads, 0, NTB>(fo.red, slot, fo.nblk_mv, rv);
+    sum_rows_as<2, kBicgUpdateThreads, 0, NTB>(fo.red, slot, fo.nblk, rv);
     __shared__ double bc[2];
     __shared__ int go;
     if (threadIdx.x == 0) {
@@ -316,6 +350,42 @@ __device__ __forceinline__ bool bicg_sfold(BicgSFold fo, int slot, bool lead, z1
     }
     __syncthreads();
     alpha = z128{bc[0], bc[1]};
+    return go != 0;
+}
+
+// p update: every thread of the block calls it with the block's reading of
+// the status; returns false when the slot does not go on (then the x kernel
+// transforms the old p, whose product nothing reads).  beta and omega come
+// back in every thread.
+template <int NTB>
+__device__ __forceinline__ bool bicg_pfold(BicgFold fo, int slot, int status, bool lead,
+                                           z128& beta, z128& omega) {
+    const bool fin = fo.nblk > 0;
+    if (!(status == SLOT_ACTIVE || (fin && status == SLOT_HALF))) return false;  // uniform
+    double tot[3] = {0.0, 0.0, 0.0};
+    if (fin) sum_rows_as<3, kBicgUpdateThreads, 0, NTB>(fo.red, slot, fo.nblk, tot);
+    __shared__ double bc[4];
+    __shared__ int go;
+    if (threadIdx.x == 0) {
+        BicgSlot& S = fo.st[slot];
+        z128 rho;
+        int ns = status;
+        if (fin) {
+            ns = finish_iteration(S, status, tot, lead);
+            rho = z128{tot[0], tot[1]};
+        } else {
+            rho = S.rho;
+        }
+        const z128 b = zdiv(rho, S.rho_old) * zdiv(S.alpha, S.omega);
+        bc[0] = b.x;
+        bc[1] = b.y;
+        bc[2] = S.omega.x;
+        bc[3] = S.omega.y;
+        go = ns == SLOT_ACTIVE;
+    }
+    __syncthreads();
+    beta = z128{bc[0], bc[1]};
+    omega = z128{bc[2], bc[3]};
     return go != 0;
 }
 
