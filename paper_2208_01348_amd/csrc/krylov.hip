@@ -133,7 +133,9 @@ __global__ __launch_bounds__(NT) void k_fin_reset(BicgSlot* st, const int* act, 
 //   t = A s   (pack rows of <t, s>, ||t||^2 at 3..5)
 //   update_xr (sums row 6 -> the half-step test, rows 3..5 -> omega; writes
 //              <rhat, r>, ||r||^2 rows at 0..2)
-// and k_fin_xr closes the last iteration of an interval.  A kernel that
+// and k_fin_xr closes the last iteration of an interval.  For small batches
+// update_p and update_s are folded into the x kernels of the two matvecs
+// (BicgFold), which sum the same rows in the same order.  A kernel that
 // needs a scalar sums the rows itself in every block (the same fixed order,
 // so every block gets the same value); block 0 stores it in the slot state.
 // Rows read and rows written by one kernel never overlap, and no block reads
