@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP64_MFMA_PEAK_TFS = 78.6  # MI355X dense FP64 matrix peak
-KERNELS = ["unpack_xfft", "yfft", "zconv", "iyfft", "ixfft_pack", "yzconv"]
+KERNELS = ["unpack_xfft", "yfft", "zconv", "iyfft", "ixfft_pack", "yzconv", "xyfft", "ixyfft_pack"]
 # the costliest kernel of the matvec chain: the fused yz kernel on lattices
 # whose padded yz plane fits in LDS, the z pass otherwise (profiles/)
 CONV_KERNELS = ["yzconv", "zconv"]
@@ -58,6 +58,10 @@ def kernel_bytes(name: str, nx, ny, nz, mx, my, mz, n_occ, c: int, nrhs: float =
         return (full_y + row_x) * c * nrhs
     if name == "ixfft_pack":
         return (row_x * c + 4 * N + (3 + 1 + 3) * n_occ * c) * nrhs
+    if name == "xyfft":  # the gather, x and y passes of one (component, z) plane
+        return (3 * n_occ * c + 4 * N + full_y * c) * nrhs
+    if name == "ixyfft_pack":
+        return (full_y * c + 4 * N + (3 + 1 + 3) * n_occ * c) * nrhs
     if name == "yzconv":
         # T[kx][3][nz][ny] in and out, D as kx slabs of its [0, L/2]^2 corner
         return 2 * row_x * c * nrhs + 6 * (mx // 2 + 1) * (my // 2 + 1) * (mz // 2 + 1) * c * n_d
@@ -66,7 +70,7 @@ def kernel_bytes(name: str, nx, ny, nz, mx, my, mz, n_occ, c: int, nrhs: float =
 
 def source_hash() -> str:
     h = hashlib.sha256()
-    for f in ["fft_core.h", "matvec.hip", "matvec_yz.hip"]:
+    for f in ["fft_core.h", "quad_fft.h", "matvec.hip", "matvec_yz.hip", "matvec_xy.hip"]:
         with open(os.path.join(ROOT, "paper_2208_01348_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -368,8 +372,8 @@ def measure_plain_fp64(torch, W, DDASolver, w, eps, P_mixed, info_mixed, steps, 
 
 
 def measure_matvec64(torch, W, DDASolver, log):
-    """FFT matvec GB/s on the 64^3 lattice (five-pass chain), FP64 and FP32,
-    one and eight right-hand sides."""
+    """FFT matvec GB/s on the 64^3 lattice, FP64 and FP32, one and eight
+    right-hand sides (five-pass chain) and 64 in FP32 (the fused xy chain)."""
     w3 = W.c3_cherenkov()
     n3 = w3.n_occ
     Em = float(w3.energies[len(w3.energies) // 2])
@@ -379,7 +383,9 @@ def measure_matvec64(torch, W, DDASolver, log):
     N = w3.nx * w3.ny * w3.nz
     mv = {}
     for prec, dt, c in [("fp64", torch.complex128, 16), ("fp32", torch.complex64, 8)]:
-        for nrhs in (8, 1):  # the autotuner times its candidates on the first batch it sees
+        # the autotuner times its candidates on the first batch it sees; FP32
+        # batches of 16 or more take the fused xy chain
+        for nrhs in ((8, 1, 64) if prec == "fp32" else (8, 1)):
             x = torch.randn((nrhs, 3, n3), dtype=dt, device="cuda")
             y = torch.empty_like(x)
             p = "fp64" if prec == "fp64" else "mixed"
@@ -396,8 +402,14 @@ def measure_matvec64(torch, W, DDASolver, log):
             per_launch = sum(kernel_bytes(k, w3.nx, w3.ny, w3.nz, mx, my, mz, n3, c, nrhs, 1)
                              for k in kt)
             d_red = 6 * (mz // 2 + 1) * (my // 2 + 1) * (mx // 2 + 1)
-            model = ((72 * N + 10 * n3) * nrhs + d_red) * c  # one D shared by the batch
+            # the chain that ran: the fused xy kernels stream the y-transformed
+            # grid (12N on this cube) once each way, the five-pass chain also
+            # the x-transformed rows (6N) twice each way
+            xy = "xyfft" in kt
+            per_n = 48 if xy else 72
+            model = ((per_n * N + 10 * n3) * nrhs + d_red) * c  # one D shared by the batch
             mv[f"{prec}_nrhs{nrhs}"] = {
+                "chain": "xyfft, zconv, ixyfft_pack" if xy else "five-pass",
                 "ms": round(dt_s * 1e3, 4),
                 "model_bytes_per_matvec": int(model),
                 "GBps_model": round(model / dt_s / 1e9, 1),

@@ -426,10 +426,12 @@ int dda_set_tuning(dda_ctx* ctx, int precision, int zconv_tx, int mid_tx, int yz
  * the context's stream around every launch while timing is enabled
  * (dda_set_timing resets the counters).  enabled: 0 off, 1 all kernels,
  * otherwise a bit mask of the kernels to time, bit k for the k-th name of
- * "unpack_xfft", "yfft", "zconv", "iyfft", "ixfft_pack", "yzconv" (fewer
- * events, less host work per launch).  Lattices whose padded yz plane fits in
- * LDS run a three-pass chain timed as "unpack_xfft", "yzconv", "ixfft_pack";
- * the others the five-pass chain of the first five names.
+ * "unpack_xfft", "yfft", "zconv", "iyfft", "ixfft_pack", "yzconv", "xyfft",
+ * "ixyfft_pack" (fewer events, less host work per launch).  Lattices whose
+ * padded yz plane fits in LDS run a three-pass chain timed as "unpack_xfft",
+ * "yzconv", "ixfft_pack"; FP32 matvecs on cubic x-y grids of 96 or 128 (the
+ * padded xy plane of one component fits in LDS) the chain "xyfft", "zconv",
+ * "ixyfft_pack"; the others the five-pass chain of the first five names.
  * dda_kernel_time gives, for one kernel: average device time per launch (ms),
  * number of launches, and average right-hand sides per launch. */
 int dda_set_timing(dda_ctx* ctx, int enabled);

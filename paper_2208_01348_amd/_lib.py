@@ -320,7 +320,8 @@ def dda_matvec(ctx, energy_eV: float, eps_dipole, precision: int, interaction_on
                              ctypes.c_void_p(y_dev), int(nrhs)))
 
 
-KERNEL_NAMES = ["unpack_xfft", "yfft", "zconv", "iyfft", "ixfft_pack", "yzconv"]
+KERNEL_NAMES = ["unpack_xfft", "yfft", "zconv", "iyfft", "ixfft_pack", "yzconv", "xyfft",
+                "ixyfft_pack"]
 
 
 def dda_set_timing(ctx, enabled, kernels=None) -> None:

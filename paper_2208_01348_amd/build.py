@@ -19,8 +19,8 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB_PATH = os.path.join(HERE, "libdda.so")
 
-SOURCES = ["matvec.hip", "matvec_yz.hip", "einc.hip", "material.hip", "krylov.hip", "farfield.hip",
-           "api.cpp"]
+SOURCES = ["matvec.hip", "matvec_yz.hip", "matvec_xy.hip", "einc.hip", "material.hip", "krylov.hip",
+           "farfield.hip", "api.cpp"]
 ARCH = os.environ.get("DDA_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -104,9 +104,9 @@ struct DEntry {
 struct Timer {
     std::vector<hipEvent_t> pool;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
-    double total_ms[6] = {0, 0, 0, 0, 0, 0};
-    int64_t count[6] = {0, 0, 0, 0, 0, 0};
-    int64_t units[6] = {0, 0, 0, 0, 0, 0};
+    double total_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t count[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int64_t units[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     ~Timer() {
         for (auto& e : pool) (void)hipEventDestroy(e);
         for (auto& p : pending) {
@@ -126,8 +126,10 @@ struct Timer {
     }
 };
 
-const char* const kKernelNames[6] = {"unpack_xfft", "yfft", "zconv", "iyfft", "ixfft_pack",
-                                     "yzconv"};
+constexpr int kNumKernels = 8;
+const char* const kKernelNames[kNumKernels] = {"unpack_xfft", "yfft",   "zconv",
+                                               "iyfft",       "ixfft_pack", "yzconv",
+                                               "xyfft",       "ixyfft_pack"};
 
 int choose_fft_len(int n) {
     static const int sizes[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512};
@@ -299,7 +301,7 @@ struct dda_ctx {
     std::unique_ptr<struct Engine> engine;  // continuous batching, when open
     int max_blocks = 1024;
     bool timing = false;
-    unsigned timing_mask = 0x3f;  // which matvec kernels are timed
+    unsigned timing_mask = 0xff;  // which matvec kernels are timed
     Timer timer;
     hipEvent_t sync_ev = nullptr;  // for low-latency host waits
 
@@ -437,7 +439,7 @@ Work ctx_work(dda_ctx* c) { return Work{c->st.as<dda::BicgSlot>(), red_of(c), c-
 // candidate on up to 8 of the listed right-hand sides (HIP events, best of
 // three after a warm-up): the threads per block of the fused yz kernel, or
 // the columns per block of the z-convolution and y passes of the five-pass
-// chain.  The candidates differ only in how lines are grouped into blocks, so
+// chain (whose z pass the fused xy chain shares).  The candidates differ only in how lines are grouped into blocks, so
 // the choice never changes a result.  Runs once per process and geometry
 // (never inside a stream capture: there the defaults stand until tuning has
 // run outside one); it writes only the grid work buffer, which every matvec
@@ -541,9 +543,26 @@ void autotune(dda_ctx* c, const Work& w, const int* act, int n_act,
 // mode PACK_AX (y = A x), PACK_GX (y = G_off x) or PACK_AX_COCG (y = A x with
 // the COCG scalars fused; then fuse_r gives the direction update
 // x <- fuse_r + beta x done in place by the first kernel).
-int pack_blocks(const dda_ctx* c, int csize) {
-    return dda::yz_fused_ok(c->g, csize) ? dda::yz_pack_blocks_per_slot(c->g, csize)
-                                         : dda::pack_blocks_per_slot(c->g);
+// FP32 matvecs on five-pass grids of 96 or 128 in x and y take the fused xy
+// chain for batches of at least kXyMinSlots right-hand sides; for fewer, its
+// two kernels per (component, z) plane are no faster than the five passes
+// (the 64^3 lattice: equal at 8 right-hand sides, 9 % faster at 64).  The
+// chain is chosen per matvec from n_act, so the partial-row counts below take
+// n_act too (an interval keeps one n_act).
+constexpr int kXyMinSlots = 16;
+bool use_xy(const dda::Geo& g, int csize, int n_act) {
+    return n_act >= kXyMinSlots && dda::xy_fused_ok(g, csize);
+}
+// partial rows per slot of the fused pack modes, and of the x kernel (the
+// rows of a folded BiCGStab s update)
+int pack_blocks(const dda_ctx* c, int csize, int n_act) {
+    if (dda::yz_fused_ok(c->g, csize)) return dda::yz_pack_blocks_per_slot(c->g, csize);
+    if (use_xy(c->g, csize, n_act)) return dda::xy_pack_blocks_per_slot(c->g);
+    return dda::pack_blocks_per_slot(c->g);
+}
+int x_blocks(const dda_ctx* c, int csize, int n_act) {
+    if (use_xy(c->g, csize, n_act)) return dda::xy_pack_blocks_per_slot(c->g);
+    return dda::xfft_blocks_per_slot(c->g, csize);
 }
 
 template <typename T>
@@ -582,6 +601,22 @@ void matvec(dda_ctx* c, const Work& w, dda::cx<T>* x, dda::cx<T>* y, const int* 
             Tic t(c, 4, n_act);
             dda::launch_ixfft_t<T>(G, x, ainv, y, map, tw_of<T>(c, 0), g, act,
                                    slot_sys, n_act, mode, f, w.red, s, dotw);
+        }
+    } else if (use_xy(g, csize, n_act)) {
+        {
+            Tic t(c, 6, n_act);
+            dda::launch_xyfft<T>(x, map, G, tw_of<T>(c, 0), g, act, n_act, fuse_r, f, s, fold,
+                                 bfold);
+        }
+        {
+            Tic t(c, 2, n_act);
+            dda::launch_zconv<T>(G, dptr, tw_of<T>(c, 2), g, act, slot_sys, n_act, f, tn.zconv_tx,
+                                 s);
+        }
+        {
+            Tic t(c, 7, n_act);
+            dda::launch_ixyfft_pack<T>(G, x, ainv, y, map, tw_of<T>(c, 0), g, act, slot_sys, n_act,
+                                       mode, f, w.red, s, dotw);
         }
     } else {
         const int64_t plane = int64_t(g.my) * g.mx;
@@ -857,17 +892,17 @@ void run_bicgstab(dda_ctx* c, int nslots, const dda::cx<T>* b, dda::cx<T>* x, Ve
     const bool graphs = use_graphs(c);
     c->graph.drop();
     // One interval of `check` iterations over the n_act slots listed in dact.
-    const int nblk_mv = pack_blocks(c, int(sizeof(dda::cx<T>)));
     const dda::SlotFilter all{nullptr, dda::FILTER_ALL};
     // For a small batch the p and s updates are folded into the x kernels of
     // v = A p and t = A s (two vector kernels less per iteration; the same
     // p and s bit for bit, ||s||^2 summed over another partition); for a
     // large one the row sums in every block of those kernels cost more than
     // the launches save.
-    const int nblk_x = dda::xfft_blocks_per_slot(c->g, int(sizeof(dda::cx<T>)));
-    if (nblk_x > red.max_blocks) throw Error(DDA_EDEVICE, "x kernel rows exceed the scratch");
     const int nblk_xr = dda::cocg_rows(nv, red.max_blocks);  // rows of k_update_xr
     auto interval = [&](int n_act) {
+        const int nblk_mv = pack_blocks(c, int(sizeof(dda::cx<T>)), n_act);
+        const int nblk_x = x_blocks(c, int(sizeof(dda::cx<T>)), n_act);
+        if (nblk_x > red.max_blocks) throw Error(DDA_EDEVICE, "x kernel rows exceed the scratch");
         const bool fold_s = n_act <= kBicgFoldMaxSlots;
         for (int k = 0; k < check; ++k) {
             if (fold_s) {  // p update folded into the x kernel of v = A p
@@ -1120,7 +1155,7 @@ void cocg_interval(dda_ctx* c, const CocgBufs<T>& B, int n_act) {
         dda::qmr_start<T>(B.r, B.p, B.q, B.pa, B.pb, B.w.st, B.act, n_act, nv,
                           mixed ? kQmrInner : 0.0, s);
         const int steps = std::max(2, (c->opt.check_every + 1) / 2 * 2);
-        const int nblk = pack_blocks(c, int(sizeof(dda::cx<T>)));
+        const int nblk = pack_blocks(c, int(sizeof(dda::cx<T>)), n_act);
         for (int k = 0; k < steps; ++k) {
             const int par = k & 1;
             dda::cx<T>* vc = par ? B.q : B.p;
@@ -1152,8 +1187,8 @@ void cocg_interval(dda_ctx* c, const CocgBufs<T>& B, int n_act) {
                   B.r, fact, nullptr, fold);
         const bool last = !fold_fin || k == check - 1;
         dda::cocg_update_xr<T>(xs, B.r, B.p, B.q, B.w.st, B.act, n_act, nv, B.w.red,
-                               pack_blocks(c, int(sizeof(dda::cx<T>))), fold_fin ? (k & 1) : 0,
-                               last, s);
+                               pack_blocks(c, int(sizeof(dda::cx<T>)), n_act),
+                               fold_fin ? (k & 1) : 0, last, s);
     }
 }
 
@@ -1888,9 +1923,9 @@ int dda_setup(const uint8_t* mask, int nx, int ny, int nz, double d_nm, double m
     for (int lin : c->occ_lin) c->occ_col[size_t(lin % (nx * ny))] = 1;
     DDA_HIP_CHECK(hipGetDevice(&c->device));
     dda::einc_scratch_init();  // the no-alloc staging area of this device
-    c->max_blocks = std::max(1024, std::max(dda::pack_blocks_per_slot(g),
-                                            std::max(dda::yz_pack_blocks_per_slot(g, 8),
-                                                     dda::yz_pack_blocks_per_slot(g, 16))));
+    c->max_blocks = std::max({1024, dda::pack_blocks_per_slot(g), dda::xy_pack_blocks_per_slot(g),
+                              dda::yz_pack_blocks_per_slot(g, 8),
+                              dda::yz_pack_blocks_per_slot(g, 16)});
     // uploads go through the context's stream (never the legacy stream, which
     // must not touch a stream another thread is capturing)
     c->map.ensure(size_t(N) * sizeof(int));
@@ -2405,8 +2440,8 @@ int dda_set_timing(dda_ctx* c, int enabled) {
     if (!c) throw Error(DDA_EINVAL, "ctx is NULL");
     flush_timer(c);
     c->timing = enabled != 0;
-    c->timing_mask = (enabled == 1) ? 0x3fu : unsigned(enabled) & 0x3fu;
-    for (int k = 0; k < 6; ++k) {
+    c->timing_mask = (enabled == 1) ? 0xffu : unsigned(enabled) & 0xffu;
+    for (int k = 0; k < kNumKernels; ++k) {
         c->timer.total_ms[k] = 0;
         c->timer.count[k] = 0;
         c->timer.units[k] = 0;
@@ -2420,7 +2455,7 @@ int dda_kernel_time(dda_ctx* c, const char* name, double* avg_ms, int64_t* launc
     DDA_API_BEGIN
     if (!c || !name || !avg_ms || !launches || !avg_rhs) throw Error(DDA_EINVAL, "NULL argument");
     flush_timer(c);
-    for (int k = 0; k < 6; ++k) {
+    for (int k = 0; k < kNumKernels; ++k) {
         if (std::strcmp(name, kKernelNames[k]) == 0) {
             const int64_t n = c->timer.count[k];
             *launches = n;

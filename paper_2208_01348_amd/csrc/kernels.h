@@ -170,7 +170,9 @@ template <typename T>
 void launch_xfft_t(cx<T>* xin, const int* map, cx<T>* Tb, const cx<T>* tw_x, const Geo& g,
                    const int* act, int n_act, const cx<T>* fuse_r, SlotFilter f, hipStream_t s,
                    CocgFold fo = CocgFold{}, BicgFold bf = BicgFold{});
-// blocks per slot of the x kernel of either chain (the rows a folded s update writes)
+// blocks per slot of the x kernel of the three-pass or the five-pass chain
+// (the rows a folded s update writes; the fused xy chain has
+// xy_pack_blocks_per_slot)
 int xfft_blocks_per_slot(const Geo& g, int csize);
 // nthreads: threads per block (0: the default; see yz_thread_candidates)
 template <typename T>
@@ -183,6 +185,23 @@ void launch_ixfft_t(const cx<T>* Tb, const cx<T>* xin, const cx<T>* ainv, cx<T>*
                     const int* map, const cx<T>* tw_x, const Geo& g, const int* act,
                     const int* slot_sys, int n_act, int mode, SlotFilter f, RedScratch red,
                     hipStream_t s, const cx<T>* wv = nullptr);
+// Three-kernel chain (matvec_xy.hip) for the other lattices whose zero-padded
+// xy plane of one component fits in LDS (FP32, mx == my in {96, 128}): the
+// x and y passes of the five-pass chain fused on either side of its z pass.
+// The work buffer holds G[pos][3][nz][my][mx] as in the five-pass chain.
+bool xy_fused_ok(const Geo& g, int csize);
+// blocks per slot of both kernels (one per (component, z) plane): the partial
+// rows of the fused pack modes and of a folded s update
+int xy_pack_blocks_per_slot(const Geo& g);
+template <typename T>
+void launch_xyfft(cx<T>* xin, const int* map, cx<T>* G, const cx<T>* tw, const Geo& g,
+                  const int* act, int n_act, const cx<T>* fuse_r, SlotFilter f, hipStream_t s,
+                  CocgFold fo = CocgFold{}, BicgFold bf = BicgFold{});
+template <typename T>
+void launch_ixyfft_pack(const cx<T>* G, const cx<T>* xin, const cx<T>* ainv, cx<T>* yout,
+                        const int* map, const cx<T>* tw, const Geo& g, const int* act,
+                        const int* slot_sys, int n_act, int mode, SlotFilter f, RedScratch red,
+                        hipStream_t s, const cx<T>* wv = nullptr);
 void launch_convert_z128_to_z64(const z128* in, z64* out, int64_t n, hipStream_t s);
 void launch_convert_z64_to_z128(const z64* in, z128* out, int64_t n, hipStream_t s);
 

@@ -15,6 +15,7 @@
 
 #include "fft_core.h"
 #include "kernels.h"
+#include "quad_fft.h"
 
 namespace dda {
 
@@ -444,89 +445,6 @@ constexpr bool yzr_ok() { return L % 8 == 0 && L >= 16 && L <= 64; }
 template <int L>
 constexpr int yzr_threads() { return (12 * L + 63) / 64 * 64; }  // a quad per (c, ky)
 
-// Quad lane exchange (every lane of a quad is active): bound_ctrl set and a
-// zero old value let the compiler fold the move into the consuming add.
-__device__ __forceinline__ float dpp_x1(float v) {  // value of lane ^ 1 (quad_perm 1,0,3,2)
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, true));
-}
-__device__ __forceinline__ float dpp_x2(float v) {  // value of lane ^ 2 (quad_perm 2,3,0,1)
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, true));
-}
-__device__ __forceinline__ double dpp_x1(double v) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, int(b), 0xB1, 0xF, 0xF, true);
-    const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), 0xB1, 0xF, 0xF, true);
-    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
-}
-__device__ __forceinline__ double dpp_x2(double v) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, int(b), 0x4E, 0xF, 0xF, true);
-    const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), 0x4E, 0xF, 0xF, true);
-    return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
-}
-
-// Q-point DFT of v in registers (reg_dft of fft_core.h with the L-entry
-// twiddle table, W_Q^t = tw[t L/Q]).
-template <typename T, int L, int Q, int NS, bool INV>
-__device__ __forceinline__ void reg_stages(cx<T> (&v)[Q], const cx<T>* __restrict__ tw) {
-    reg_dft<T, Q, NS, INV, L / Q>(v, tw);
-}
-
-// DFT of one line of length L spread over a lane quad (see above).
-template <typename T, int L, bool INV>
-__device__ __forceinline__ void quad_fft(cx<T> (&v)[L / 4], int n2, const cx<T>* __restrict__ tw) {
-    constexpr int Q = L / 4;
-    reg_stages<T, L, Q, 1, INV>(v, tw);
-#pragma unroll
-    for (int k1 = 1; k1 < Q; ++k1) {
-        cx<T> t = tw[n2 * k1];
-        if (INV) t.y = -t.y;
-        v[k1] = v[k1] * t;
-    }
-    // butterflies as partner + sign * own: the lower lane of a pair adds,
-    // the upper one subtracts, with no select
-    const bool hi = (n2 & 2) != 0, odd = (n2 & 1) != 0;
-    const T s2 = hi ? T(-1) : T(1), s1 = odd ? T(-1) : T(1);
-#pragma unroll
-    for (int k1 = 0; k1 < Q; ++k1) {  // pairs (n2, n2 ^ 2); W_4 on lane 3
-        cx<T> r{dpp_x2(v[k1].x) + s2 * v[k1].x, dpp_x2(v[k1].y) + s2 * v[k1].y};
-        if (hi && odd) r = mul_mi<INV>(r);
-        v[k1] = r;
-    }
-#pragma unroll
-    for (int k1 = 0; k1 < Q; ++k1)  // pairs (n2, n2 ^ 1)
-        v[k1] = cx<T>{dpp_x1(v[k1].x) + s1 * v[k1].x, dpp_x1(v[k1].y) + s1 * v[k1].y};
-}
-
-// The mirror image of quad_fft: input in the layout quad_fft leaves (lane l
-// holds X[k1 + (L/4) rev2(l)]), output decimated (lane n2 holds
-// y[4 n1 + n2], n1 in natural order).  Radix-4 across the quad first (pairs
-// l ^ 1, the factor W_4 on lane 3, pairs l ^ 2), then the twiddle
-// W_L^{n2 k1} and the L/4-point DFT in registers.
-template <typename T, int L, bool INV>
-__device__ __forceinline__ void quad_fft_blk(cx<T> (&v)[L / 4], int n2,
-                                             const cx<T>* __restrict__ tw) {
-    constexpr int Q = L / 4;
-    const bool hi = (n2 & 2) != 0, odd = (n2 & 1) != 0;
-    const T s2 = hi ? T(-1) : T(1), s1 = odd ? T(-1) : T(1);
-#pragma unroll
-    for (int k1 = 0; k1 < Q; ++k1) {
-        cx<T> r{dpp_x1(v[k1].x) + s1 * v[k1].x, dpp_x1(v[k1].y) + s1 * v[k1].y};
-        if (hi && odd) r = mul_mi<INV>(r);
-        v[k1] = r;
-    }
-#pragma unroll
-    for (int k1 = 0; k1 < Q; ++k1)
-        v[k1] = cx<T>{dpp_x2(v[k1].x) + s2 * v[k1].x, dpp_x2(v[k1].y) + s2 * v[k1].y};
-#pragma unroll
-    for (int k1 = 1; k1 < Q; ++k1) {
-        cx<T> t = tw[n2 * k1];
-        if (INV) t.y = -t.y;
-        v[k1] = v[k1] * t;
-    }
-    reg_stages<T, L, Q, 1, INV>(v, tw);
-}
-
 // u <- D u for the three components of one frequency (component stride CS)
 // with the symmetric tensor D = [xx xy xz; xy yy yz; xz yz zz].
 template <typename T, int CS>
@@ -603,7 +521,7 @@ __global__ __launch_bounds__(yzr_threads<L>()) void k_yzconv_r(
             }
         }
         __builtin_amdgcn_s_setprio(0);
-        quad_fft<T, L, false>(v, n2, twy);
+        quad_fft<T, L, false>(v, n2, twy, twy);
 #pragma unroll
         for (int k1 = 0; k1 < Q; ++k1) lds[(c * L + k1 + Q * rb) * ZS + z] = v[k1];
     }
@@ -618,7 +536,7 @@ __global__ __launch_bounds__(yzr_threads<L>()) void k_yzconv_r(
             const int z = 4 * n1 + n2;
             u[n1] = (n1 < Q / 2 && z < nz) ? row[z] : zero;
         }
-        quad_fft<T, L, false>(u, n2, twz);
+        quad_fft<T, L, false>(u, n2, twz, twz);
 #pragma unroll
         for (int k1 = 0; k1 < Q; ++k1) row[k1 + Q * rb] = u[k1];
     }
@@ -712,7 +630,7 @@ __global__ __launch_bounds__(yzr_threads<L>()) void k_yzconv_r(
         cx<T> u[Q];
 #pragma unroll
         for (int k1 = 0; k1 < Q; ++k1) u[k1] = row[k1 + Q * rb];
-        quad_fft_blk<T, L, true>(u, n2, twz);
+        quad_fft_blk<T, L, true>(u, n2, twz, twz);
 #pragma unroll
         for (int n1 = 0; n1 < Q / 2; ++n1) {  // z = 4 n1 + n2 < nz <= L/2
             const int z = 4 * n1 + n2;
@@ -729,7 +647,7 @@ __global__ __launch_bounds__(yzr_threads<L>()) void k_yzconv_r(
         cx<T> v[Q];
 #pragma unroll
         for (int k1 = 0; k1 < Q; ++k1) v[k1] = lds[(c * L + k1 + Q * rb) * ZS + z];
-        quad_fft_blk<T, L, true>(v, n2, twy);
+        quad_fft_blk<T, L, true>(v, n2, twy, twy);
         cx<T>* dst = col + int64_t(line) * ny;
         if (perm) {
 #pragma unroll

@@ -368,14 +368,13 @@ __device__ __forceinline__ bool bicg_pfold(BicgFold fo, int slot, int status, bo
     __shared__ int go;
     if (threadIdx.x == 0) {
         BicgSlot& S = fo.st[slot];
-        z128 rho;
+        // the stored rho is read before finish_iteration replaces it, and the
+        // choice is made on the values: a choice between the two addresses
+        // would put tot in scratch memory behind a flat load
+        const z128 rho_st = S.rho;
         int ns = status;
-        if (fin) {
-            ns = finish_iteration(S, status, tot, lead);
-            rho = z128{tot[0], tot[1]};
-        } else {
-            rho = S.rho;
-        }
+        if (fin) ns = finish_iteration(S, status, tot, lead);
+        const z128 rho{fin ? tot[0] : rho_st.x, fin ? tot[1] : rho_st.y};
         const z128 b = zdiv(rho, S.rho_old) * zdiv(S.alpha, S.omega);
         bc[0] = b.x;
         bc[1] = b.y;

@@ -270,6 +270,77 @@ def test_losses_when_every_precision_uses_the_five_pass_chain(solver, precision,
     s.close()
 
 
+@pytest.mark.parametrize("side,nz,frac", [(48, 3, 0.025), (64, 2, 0.02)])
+@pytest.mark.parametrize("solver", ["cocg", "bicgstab", "qmr"])
+def test_losses_on_the_fused_xy_chain(side, nz, frac, solver):
+    """Sparse side x side x nz lattices (FFT grids 96 x 96 and 128 x 128 in x
+    and y) solved at 20 energies at once: the FP32 matvecs of the mixed path
+    run the fused xy chain (xyfft, zconv, ixyfft_pack) while at least 16
+    systems iterate, with the COCG direction update in its first kernel and
+    the fused partial rows of its pack, and the five-pass chain once fewer are
+    left; against dense LU at every energy."""
+    n_energy = 20
+    mask = W.random_mask(side, side, nz, frac, seed=side + nz)
+    d = 1.1
+    n = int(mask.sum())
+    energies = np.linspace(1.7, 2.9, n_energy)
+    eps = np.repeat(W.drude_eps(energies)[:, None], n, axis=1)
+    r0 = np.array([[side * d / 2 + 0.55, side * d + 2.0, 0.0]])
+    say("fused xy chain", side, nz, solver, n_energy, "n_occ", n)
+    s = DDASolver(mask, d, 1.45, precision="mixed", solver=solver, tol=1e-10, maxit=20000)
+    assert s.grid[0] == s.grid[1] == 2 * side, s.grid
+    s.set_timing(True)
+    for nrhs, xy in ((16, True), (15, False)):
+        s.matvec(2.0, eps[0], torch.zeros((nrhs, 3, n), dtype=torch.complex64, device="cuda"),
+                 precision="mixed")
+        torch.cuda.synchronize()
+        fused = [s.kernel_time(k)[1] for k in ("xyfft", "ixyfft_pack")]
+        five = [s.kernel_time(k)[1] for k in ("unpack_xfft", "yfft", "iyfft", "ixfft_pack")]
+        assert fused == ([1, 1] if xy else [0, 0]) and five == ([0] * 4 if xy else [1] * 4)
+        assert s.kernel_time("zconv")[1] == 1
+        s.set_timing(True)  # resets the counters
+    s.set_timing(False)
+    P, info = s.spectrum(energies, 0.55, eps, r0)
+    say("  iterations", [i.iters for i in info])
+    assert all(i.status == 0 for i in info), info
+    for ie, E in enumerate(energies):
+        ref = solve_point(mask, d, eps[ie], 1.45, 0.55, r0[0], E, method="lu")
+        vals = [ref.p_eels, ref.p_ext, ref.p_abs, ref.p_cl]
+        scale = max(abs(v) for v in vals)
+        for g, v, nm in zip(P[ie], vals, ["eels", "ext", "abs", "cl"]):
+            err = abs(g - v) / max(abs(v), 1e-3 * scale)
+            assert err <= 1e-5, (side, solver, E, nm, err)
+    s.close()
+
+
+@pytest.mark.parametrize("side", [48, 64])
+def test_fused_xy_chain_matvec_matches_dense(side):
+    """The FP32 products y = A x and G_off x of the fused xy chain on a fully
+    occupied side x side x 3 lattice (FFT grid 2 side in x and y) against the
+    oracle's dense rows, for 16 right-hand sides at once (the smallest batch
+    the chain takes)."""
+    mask = np.ones((3, side, side), np.uint8)
+    n = int(mask.sum())
+    E = 2.2
+    eps = np.full(n, -6.0 + 0.9j)
+    rng = np.random.default_rng(side)
+    x = rng.standard_normal((16, n, 3)) + 1j * rng.standard_normal((16, n, 3))
+    s = DDASolver(mask, 1.0, 1.45)
+    assert s.grid[0] == s.grid[1] == 2 * side
+    xd = to_dev(x, torch.complex64)
+    y = from_dev(s.matvec(E, eps, xd, precision="mixed"))
+    yi = from_dev(s.matvec(E, None, xd, precision="mixed", interaction_only=True))
+    c, alpha, k, _ = system(mask, 1.0, eps, 1.45, E)
+    rows = np.unique(np.concatenate([[0, n - 1, n // 2], rng.integers(0, n, 125)]))
+    for r in range(x.shape[0]):
+        for got, io in ((y[r], False), (yi[r], True)):
+            ref = cdense.matvec_rows(c, alpha, k, x[r], rows, interaction_only=io)
+            err = np.max(np.abs(got[rows] - ref)) / np.max(np.abs(ref))
+            say("  xy chain side", side, "rhs", r, "G only" if io else "A", "err", err)
+            assert err <= 1e-5, (r, io, err)
+    s.close()
+
+
 @pytest.mark.parametrize("nx", [32, 33, 64])
 @pytest.mark.parametrize("solver,precision,bar", [("cocg", "mixed", 1e-5), ("bicgstab", "mixed", 1e-5),
                                                   ("cocg", "fp64", 1e-9)])
@@ -409,13 +480,14 @@ ZC2_CODES = [tx | ((nt // 64) << 6) | (alt << 12) for tx in (2, 4, 8, 16) for nt
 
 
 @pytest.mark.parametrize("shape", [(12, 12, 12), (12, 12, 16), (16, 8, 12), (16, 12, 24),
-                                   (8, 20, 40), (6, 20, 64)])
+                                   (8, 20, 40), (6, 20, 64), (48, 48, 24)])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_every_autotuner_candidate_gives_identical_matvecs(shape, precision):
     """The autotuner's tile candidates only regroup lines into blocks: every
     candidate of the five-pass z and y passes (my != mz) gives the same matvec
     to the last bit (the fused yz kernel of a cubic grid has a single shape
-    per length).  z grids of 48 and 96 take the two-stage z pass, whose codes
+    per length; on the 48 x 48 x 24 lattice the FP32 matvecs take the fused
+    xy chain, whose z pass has the same candidates).  z grids of 48 and 96 take the two-stage z pass, whose codes
     are TX | (threads / 64) << 6 | plan << 12; the two radix plans of a length
     (first radix 16 or 8) round differently, so results are bit-identical
     within a plan and agree to rounding across plans."""
