@@ -79,6 +79,34 @@ std::vector<int> zconv_tx_candidates(int L);
 enum PackMode { PACK_AX = 0, PACK_GX = 1, PACK_AX_COCG = 2, PACK_AX_DOTW = 3, PACK_AX_TS = 4 };
 inline bool pack_fused(int mode) { return mode >= PACK_AX_COCG; }
 
+// a u + b v + c w of complex values as one chain of a product and five
+// multiply-adds per part (the signs of negated operands fold into them).
+template <typename T>
+__device__ __forceinline__ cx<T> cdot3(cx<T> a, cx<T> u, cx<T> b, cx<T> v, cx<T> c, cx<T> w) {
+    T re = a.x * u.x, im = a.x * u.y;
+    re = fma(-a.y, u.y, re);
+    im = fma(a.y, u.x, im);
+    re = fma(b.x, v.x, re);
+    im = fma(b.x, v.y, im);
+    re = fma(-b.y, v.y, re);
+    im = fma(b.y, v.x, im);
+    re = fma(c.x, w.x, re);
+    im = fma(c.x, w.y, im);
+    re = fma(-c.y, w.y, re);
+    im = fma(c.y, w.x, im);
+    return cx<T>{re, im};
+}
+// u <- D u for the three components of one frequency (component stride CS)
+// with the symmetric tensor D = [xx xy xz; xy yy yz; xz yz zz].
+template <typename T, int CS>
+__device__ __forceinline__ void dmul3(cx<T>* u, cx<T> dxx, cx<T> dxy, cx<T> dxz, cx<T> dyy,
+                                      cx<T> dyz, cx<T> dzz) {
+    const cx<T> ux = u[0], uy = u[CS], uz = u[2 * CS];
+    u[0] = cdot3(dxx, ux, dxy, uy, dxz, uz);
+    u[CS] = cdot3(dxy, ux, dyy, uy, dyz, uz);
+    u[2 * CS] = cdot3(dxz, ux, dyz, uy, dzz, uz);
+}
+
 // Per-element products of the fused pack modes (x the input, y = A x, w the
 // extra vector), accumulated in FP64.
 template <typename T, int MODE>

@@ -301,21 +301,24 @@ __global__ __launch_bounds__(NTHR) void k_fft_mid(cx<T>* __restrict__ data,
 // other take the G tiles of one line.  The ids past the last whole run keep
 // the plain order.  On the 64^3 lattice (FP32, 8 right-hand sides, TX = 4)
 // this cut the kernel's fetched bytes 2.5-fold and its time from 272 to 222 us.
+// The launcher keeps the grid below 2^31 blocks, so the block id is done in
+// 32-bit arithmetic (64-bit divisions of it cost some 500 scalar
+// instructions per wave).
 template <typename T, int TX>
 __device__ __forceinline__ void zconv_block_map(int& tile, int& ky0, int& pos) {
-    constexpr int G = (128 / int(TX * sizeof(cx<T>))) > 1 ? 128 / int(TX * sizeof(cx<T>)) : 1;
-    const int nxt = gridDim.x, nky = gridDim.y;
-    const int64_t per_slot = int64_t(nxt) * nky;
-    int64_t id = blockIdx.x + int64_t(nxt) * (blockIdx.y + int64_t(nky) * blockIdx.z);
-    const int64_t run = 8 * G;
+    constexpr unsigned G = (128 / int(TX * sizeof(cx<T>))) > 1 ? 128 / int(TX * sizeof(cx<T>)) : 1;
+    const unsigned nxt = gridDim.x, nky = gridDim.y;
+    const unsigned per_slot = nxt * nky;
+    unsigned id = blockIdx.x + nxt * (blockIdx.y + nky * blockIdx.z);
+    constexpr unsigned run = 8 * G;
     if (nxt % G == 0 && id < (per_slot * gridDim.z / run) * run) {
-        const int64_t q = id / run, r = id - q * run;
+        const unsigned q = id / run, r = id - q * run;
         id = q * run + (r & 7) * G + (r >> 3);
     }
     pos = int(id / per_slot);
-    const int64_t rem = id - int64_t(pos) * per_slot;
+    const unsigned rem = id - unsigned(pos) * per_slot;
     ky0 = int(rem / nxt);
-    tile = int(rem - int64_t(ky0) * nxt);
+    tile = int(rem - unsigned(ky0) * nxt);
 }
 // Per (kx tile, ky pair, slot): z-FFT of the three components (nz non-zero
 // inputs), w = D u with D the symmetric 3x3 spectrum, z-iFFT, keep nz rows.
@@ -523,38 +526,34 @@ __global__ __launch_bounds__(NT) void k_zconv2(cx<T>* __restrict__ G,
     __syncthreads();
     // D from its stored corner [0, M/2]^3 (index M - k reads k; the odd
     // components flip sign), one load for the four frequencies
-    // (ky0 or ky1) x (kz or mz - kz) of a column
+    // (ky0 or ky1) x (kz' or L - kz') of a column.  With sx the x parity,
+    // the xy entry flips with the y mirror, xz with the z mirror and yz with
+    // either; the four products are written out so that the signs fold into
+    // the multiply-adds.
     {
-        const int mxh = g.mx / 2 + 1, myh = g.my / 2 + 1, mzh = g.mz / 2 + 1;
-        const int64_t dcomp = int64_t(mzh) * myh * mxh;
-        const cx<T>* dbase = Dptr[sys] + int64_t(ky0) * mxh;
-        for (int e = tid; e < mzh * TX; e += NT) {
-            const int kzp = e / TX, col = e % TX;
+        constexpr int MZH = L / 2 + 1;
+        const int mxh = g.mx / 2 + 1, myh = g.my / 2 + 1;
+        const int dplane = myh * mxh;  // a corner component holds < 2^31 entries
+        const int dcomp = MZH * dplane;
+        const cx<T>* dbase = Dptr[sys] + ky0 * mxh;
+        for (int e = tid; e < MZH * TX; e += NT) {
+            const int kzp = e / TX, col = e - (e / TX) * TX;
             const int kx = col0 + col;
             if (kx >= g.mx) continue;
             const bool fx = kx > g.mx / 2;
-            const int kxr = fx ? g.mx - kx : kx;
-            const cx<T>* dp = dbase + int64_t(kzp) * myh * mxh + kxr;
-            const cx<T> dxx = gload(dp), dxy0 = gload(dp + dcomp), dxz0 = gload(dp + 2 * dcomp);
-            const cx<T> dyy = gload(dp + 3 * dcomp), dyz0 = gload(dp + 4 * dcomp);
+            const cx<T>* dp = dbase + kzp * dplane + (fx ? g.mx - kx : kx);
+            const cx<T> dxx = gload(dp), dxy = gload(dp + dcomp), dxz = gload(dp + 2 * dcomp);
+            const cx<T> dyy = gload(dp + 3 * dcomp), dyz = gload(dp + 4 * dcomp);
             const cx<T> dzz = gload(dp + 5 * dcomp);
-            const int kz1 = (g.mz - kzp) % g.mz;
-            const int nzs = (kz1 != kzp) ? 2 : 1;
-            const int nset = pair ? 2 : 1;
-            for (int zi = 0; zi < nzs; ++zi) {
-                const int kz = zi ? kz1 : kzp;
-                const bool fz = zi != 0;
-                for (int set = 0; set < nset; ++set) {
-                    const bool fy = set != 0;
-                    const cx<T> dxy = (fx != fy) ? -dxy0 : dxy0;
-                    const cx<T> dxz = (fx != fz) ? -dxz0 : dxz0;
-                    const cx<T> dyz = (fy != fz) ? -dyz0 : dyz0;
-                    cx<T>* u = lds + kz * W + set * 3 * TX + col;
-                    const cx<T> ux = u[0], uy = u[TX], uz = u[2 * TX];
-                    u[0] = dxx * ux + dxy * uy + dxz * uz;
-                    u[TX] = dxy * ux + dyy * uy + dyz * uz;
-                    u[2 * TX] = dxz * ux + dyz * uy + dzz * uz;
-                }
+            const T sx = fx ? T(-1) : T(1);
+            const cx<T> axy = sx * dxy, axz = sx * dxz;
+            cx<T>* u = lds + kzp * W + col;  // kz', set 0 (ky0)
+            dmul3<T, TX>(u, dxx, axy, axz, dyy, dyz, dzz);
+            if (pair) dmul3<T, TX>(u + 3 * TX, dxx, -axy, axz, dyy, -dyz, dzz);
+            if (kzp != 0 && kzp != L / 2) {  // the mirror L - kz'
+                cx<T>* v = lds + (L - kzp) * W + col;
+                dmul3<T, TX>(v, dxx, axy, -axz, dyy, -dyz, dzz);
+                if (pair) dmul3<T, TX>(v + 3 * TX, dxx, -axy, -axz, dyy, dyz, dzz);
             }
         }
     }
@@ -790,6 +789,8 @@ template <typename T, int L, int TX>
 void run_zconv(cx<T>* G, const cx<T>* const* Dptr, const cx<T>* tw_z, const Geo& g,
                const int* act, const int* slot_sys, int n_act, SlotFilter f, hipStream_t s) {
     dim3 grid(nblk(g.mx, TX), g.my / 2 + 1, n_act);
+    if (int64_t(grid.x) * grid.y * grid.z >= (int64_t(1) << 31))
+        throw Error(-1, "z pass: grid of 2^31 blocks or more");
     k_zconv<T, L, TX><<<grid, NTHR, 0, s>>>(G, Dptr, tw_z, g, act, slot_sys, f);
 }
 
@@ -822,6 +823,8 @@ template <typename T, int L, int TX, int NT, int ALT>
 void run_zconv2(cx<T>* G, const cx<T>* const* Dptr, const cx<T>* tw_z, const Geo& g,
                 const int* act, const int* slot_sys, int n_act, SlotFilter f, hipStream_t s) {
     dim3 grid(nblk(g.mx, TX), g.my / 2 + 1, n_act);
+    if (int64_t(grid.x) * grid.y * grid.z >= (int64_t(1) << 31))
+        throw Error(-1, "z pass: grid of 2^31 blocks or more");
     k_zconv2<T, L, TX, NT, zc2_r1_of<L, ALT>()><<<grid, NT, 0, s>>>(G, Dptr, tw_z, g, act,
                                                                     slot_sys, f);
 }

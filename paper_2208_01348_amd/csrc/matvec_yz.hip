@@ -445,17 +445,6 @@ constexpr bool yzr_ok() { return L % 8 == 0 && L >= 16 && L <= 64; }
 template <int L>
 constexpr int yzr_threads() { return (12 * L + 63) / 64 * 64; }  // a quad per (c, ky)
 
-// u <- D u for the three components of one frequency (component stride CS)
-// with the symmetric tensor D = [xx xy xz; xy yy yz; xz yz zz].
-template <typename T, int CS>
-__device__ __forceinline__ void dmul3(cx<T>* u, cx<T> dxx, cx<T> dxy, cx<T> dxz, cx<T> dyy,
-                                      cx<T> dyz, cx<T> dzz) {
-    const cx<T> ux = u[0], uy = u[CS], uz = u[2 * CS];
-    u[0] = dxx * ux + dxy * uy + dxz * uz;
-    u[CS] = dxy * ux + dyy * uy + dyz * uz;
-    u[2 * CS] = dxz * ux + dyz * uy + dzz * uz;
-}
-
 // Two adjacent complex values of a T line (16-byte aligned for FP32 when the
 // line is permuted: ny is then a multiple of 8).
 __device__ __forceinline__ void load_pair(const cx<float>* p, cx<float>& a, cx<float>& b) {
