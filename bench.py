@@ -372,8 +372,8 @@ def measure_plain_fp64(torch, W, DDASolver, w, eps, P_mixed, info_mixed, steps, 
 
 
 def measure_matvec64(torch, W, DDASolver, log):
-    """FFT matvec GB/s on the 64^3 lattice, FP64 and FP32, one and eight
-    right-hand sides (five-pass chain) and 64 in FP32 (the fused xy chain)."""
+    """FFT matvec GB/s on the 64^3 lattice: FP64 (five-pass chain) and FP32
+    (the fused xy chain), one and eight right-hand sides, and 64 in FP32."""
     w3 = W.c3_cherenkov()
     n3 = w3.n_occ
     Em = float(w3.energies[len(w3.energies) // 2])
@@ -383,8 +383,7 @@ def measure_matvec64(torch, W, DDASolver, log):
     N = w3.nx * w3.ny * w3.nz
     mv = {}
     for prec, dt, c in [("fp64", torch.complex128, 16), ("fp32", torch.complex64, 8)]:
-        # the autotuner times its candidates on the first batch it sees; FP32
-        # batches of 16 or more take the fused xy chain
+        # the autotuner times its candidates on the first batch it sees
         for nrhs in ((8, 1, 64) if prec == "fp32" else (8, 1)):
             x = torch.randn((nrhs, 3, n3), dtype=dt, device="cuda")
             y = torch.empty_like(x)
@@ -408,11 +407,15 @@ def measure_matvec64(torch, W, DDASolver, log):
             xy = "xyfft" in kt
             per_n = 48 if xy else 72
             model = ((per_n * N + 10 * n3) * nrhs + d_red) * c  # one D shared by the batch
+            five = ((72 * N + 10 * n3) * nrhs + d_red) * c
             mv[f"{prec}_nrhs{nrhs}"] = {
                 "chain": "xyfft, zconv, ixyfft_pack" if xy else "five-pass",
                 "ms": round(dt_s * 1e3, 4),
                 "model_bytes_per_matvec": int(model),
                 "GBps_model": round(model / dt_s / 1e9, 1),
+                # the five-pass chain's bytes over this time: the rate that chain
+                # would need to match it (not a measured bandwidth)
+                "five_pass_bytes_over_time_GBps": round(five / dt_s / 1e9, 1),
                 "GBps_kernels": round(per_launch / dt_s / 1e9, 1),
                 "frac_of_hbm_peak": round(model / dt_s / 1e9 / HBM_PEAK_GBS, 4),
                 "kernels_GBps": {k: round(kernel_bytes(k, w3.nx, w3.ny, w3.nz, mx, my, mz, n3, c,
@@ -445,14 +448,17 @@ def measure_latency(torch, W, DDASolver, log):
         s1.drop_cache()
         torch.cuda.synchronize()
         t = time.perf_counter()
-        s1.spectrum(w1.energies, w1.beta, eps1, w1.r0)
+        _, info1 = s1.spectrum(w1.energies, w1.beta, eps1, w1.r0)
         torch.cuda.synchronize()
         if i:
             lat.append(time.perf_counter() - t)
     s1.close()
+    it = info1[0].iters
     res["solve_latency_c1_ms"] = {"p50": round(1e3 * float(np.percentile(lat, 50)), 3),
                                   "p99": round(1e3 * float(np.percentile(lat, 99)), 3),
-                                  "solves": len(lat), "precision": "fp64", "solver": "bicgstab"}
+                                  "solves": len(lat), "precision": "fp64", "solver": "bicgstab",
+                                  "iterations": it,
+                                  "us_per_iteration": round(1e6 * float(np.median(lat)) / it, 2)}
     log(f"c1 latency p50 {res['solve_latency_c1_ms']['p50']} ms")
     # the same solve with FP64 COCG (device-driven intervals, captured graphs)
     s1 = DDASolver(w1.mask, w1.d, w1.m_h, tol=w1.tol, solver="cocg")
@@ -461,14 +467,18 @@ def measure_latency(torch, W, DDASolver, log):
         s1.drop_cache()
         torch.cuda.synchronize()
         t = time.perf_counter()
-        s1.spectrum(w1.energies, w1.beta, eps1, w1.r0)
+        _, info1 = s1.spectrum(w1.energies, w1.beta, eps1, w1.r0)
         torch.cuda.synchronize()
         if i:
             lat.append(time.perf_counter() - t)
     s1.close()
+    it = info1[0].iters
     res["solve_latency_c1_cocg_ms"] = {"p50": round(1e3 * float(np.percentile(lat, 50)), 3),
                                        "p99": round(1e3 * float(np.percentile(lat, 99)), 3),
-                                       "solves": len(lat), "precision": "fp64", "solver": "cocg"}
+                                       "solves": len(lat), "precision": "fp64", "solver": "cocg",
+                                       "iterations": it,
+                                       "us_per_iteration": round(1e6 * float(np.median(lat)) / it,
+                                                                 2)}
     log(f"c1 COCG latency p50 {res['solve_latency_c1_cocg_ms']['p50']} ms")
     return res
 

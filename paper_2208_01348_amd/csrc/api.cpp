@@ -439,7 +439,7 @@ Work ctx_work(dda_ctx* c) { return Work{c->st.as<dda::BicgSlot>(), red_of(c), c-
 // candidate on up to 8 of the listed right-hand sides (HIP events, best of
 // three after a warm-up): the threads per block of the fused yz kernel, or
 // the columns per block of the z-convolution and y passes of the five-pass
-// chain (whose z pass the fused xy chain shares).  The candidates differ only in how lines are grouped into blocks, so
+// chain (the z pass alone in the fused xy chain).  The candidates differ only in how lines are grouped into blocks, so
 // the choice never changes a result.  Runs once per process and geometry
 // (never inside a stream capture: there the defaults stand until tuning has
 // run outside one); it writes only the grid work buffer, which every matvec
@@ -515,13 +515,15 @@ void autotune(dda_ctx* c, const Work& w, const int* act, int n_act,
             const auto rz = pick(dda::zconv_tx_candidates<T>(g.mz), [&](int tx) {
                 dda::launch_zconv<T>(G, dptr, tw_of<T>(c, 2), g, act, slot_sys, n, all, tx, s);
             });
-            const int64_t plane = int64_t(g.my) * g.mx;
-            const auto rm = pick(dda::mid_tx_candidates<T>(g.my), [&](int tx) {
-                dda::launch_fft_mid<T>(G, tw_of<T>(c, 1), g.my, false, int64_t(n) * 3 * g.nz,
-                                       g.mx, g.ny, g.my, plane, tx, s);
-            });
             r.zconv_tx = int(rz[0]);
-            r.mid_tx = int(rm[0]);
+            if (!dda::xy_fused_ok(g, csize)) {  // the fused xy chain has no y pass
+                const int64_t plane = int64_t(g.my) * g.mx;
+                const auto rm = pick(dda::mid_tx_candidates<T>(g.my), [&](int tx) {
+                    dda::launch_fft_mid<T>(G, tw_of<T>(c, 1), g.my, false, int64_t(n) * 3 * g.nz,
+                                           g.mx, g.ny, g.my, plane, tx, s);
+                });
+                r.mid_tx = int(rm[0]);
+            }
             r.t_default_ms = rz[1];
             r.t_best_ms = rz[2];
         }
@@ -543,25 +545,17 @@ void autotune(dda_ctx* c, const Work& w, const int* act, int n_act,
 // mode PACK_AX (y = A x), PACK_GX (y = G_off x) or PACK_AX_COCG (y = A x with
 // the COCG scalars fused; then fuse_r gives the direction update
 // x <- fuse_r + beta x done in place by the first kernel).
-// FP32 matvecs on five-pass grids of 96 or 128 in x and y take the fused xy
-// chain for batches of at least kXyMinSlots right-hand sides; for fewer, its
-// two kernels per (component, z) plane are no faster than the five passes
-// (the 64^3 lattice: equal at 8 right-hand sides, 9 % faster at 64).  The
-// chain is chosen per matvec from n_act, so the partial-row counts below take
-// n_act too (an interval keeps one n_act).
-constexpr int kXyMinSlots = 16;
-bool use_xy(const dda::Geo& g, int csize, int n_act) {
-    return n_act >= kXyMinSlots && dda::xy_fused_ok(g, csize);
-}
-// partial rows per slot of the fused pack modes, and of the x kernel (the
-// rows of a folded BiCGStab s update)
-int pack_blocks(const dda_ctx* c, int csize, int n_act) {
+// Partial rows per slot of the fused pack modes, and of the x kernel (the
+// rows of a folded BiCGStab s update), for the chain a precision runs: the
+// three-pass chain, the fused xy chain (FP32 on 96- or 128-point x-y grids)
+// or the five-pass chain.
+int pack_blocks(const dda_ctx* c, int csize) {
     if (dda::yz_fused_ok(c->g, csize)) return dda::yz_pack_blocks_per_slot(c->g, csize);
-    if (use_xy(c->g, csize, n_act)) return dda::xy_pack_blocks_per_slot(c->g);
+    if (dda::xy_fused_ok(c->g, csize)) return dda::xy_pack_blocks_per_slot(c->g);
     return dda::pack_blocks_per_slot(c->g);
 }
-int x_blocks(const dda_ctx* c, int csize, int n_act) {
-    if (use_xy(c->g, csize, n_act)) return dda::xy_pack_blocks_per_slot(c->g);
+int x_blocks(const dda_ctx* c, int csize) {
+    if (dda::xy_fused_ok(c->g, csize)) return dda::xy_pack_blocks_per_slot(c->g);
     return dda::xfft_blocks_per_slot(c->g, csize);
 }
 
@@ -602,7 +596,7 @@ void matvec(dda_ctx* c, const Work& w, dda::cx<T>* x, dda::cx<T>* y, const int* 
             dda::launch_ixfft_t<T>(G, x, ainv, y, map, tw_of<T>(c, 0), g, act,
                                    slot_sys, n_act, mode, f, w.red, s, dotw);
         }
-    } else if (use_xy(g, csize, n_act)) {
+    } else if (dda::xy_fused_ok(g, csize)) {
         {
             Tic t(c, 6, n_act);
             dda::launch_xyfft<T>(x, map, G, tw_of<T>(c, 0), g, act, n_act, fuse_r, f, s, fold,
@@ -900,8 +894,8 @@ void run_bicgstab(dda_ctx* c, int nslots, const dda::cx<T>* b, dda::cx<T>* x, Ve
     // the launches save.
     const int nblk_xr = dda::cocg_rows(nv, red.max_blocks);  // rows of k_update_xr
     auto interval = [&](int n_act) {
-        const int nblk_mv = pack_blocks(c, int(sizeof(dda::cx<T>)), n_act);
-        const int nblk_x = x_blocks(c, int(sizeof(dda::cx<T>)), n_act);
+        const int nblk_mv = pack_blocks(c, int(sizeof(dda::cx<T>)));
+        const int nblk_x = x_blocks(c, int(sizeof(dda::cx<T>)));
         if (nblk_x > red.max_blocks) throw Error(DDA_EDEVICE, "x kernel rows exceed the scratch");
         const bool fold_s = n_act <= kBicgFoldMaxSlots;
         for (int k = 0; k < check; ++k) {
@@ -1155,7 +1149,7 @@ void cocg_interval(dda_ctx* c, const CocgBufs<T>& B, int n_act) {
         dda::qmr_start<T>(B.r, B.p, B.q, B.pa, B.pb, B.w.st, B.act, n_act, nv,
                           mixed ? kQmrInner : 0.0, s);
         const int steps = std::max(2, (c->opt.check_every + 1) / 2 * 2);
-        const int nblk = pack_blocks(c, int(sizeof(dda::cx<T>)), n_act);
+        const int nblk = pack_blocks(c, int(sizeof(dda::cx<T>)));
         for (int k = 0; k < steps; ++k) {
             const int par = k & 1;
             dda::cx<T>* vc = par ? B.q : B.p;
@@ -1187,8 +1181,8 @@ void cocg_interval(dda_ctx* c, const CocgBufs<T>& B, int n_act) {
                   B.r, fact, nullptr, fold);
         const bool last = !fold_fin || k == check - 1;
         dda::cocg_update_xr<T>(xs, B.r, B.p, B.q, B.w.st, B.act, n_act, nv, B.w.red,
-                               pack_blocks(c, int(sizeof(dda::cx<T>)), n_act),
-                               fold_fin ? (k & 1) : 0, last, s);
+                               pack_blocks(c, int(sizeof(dda::cx<T>))), fold_fin ? (k & 1) : 0,
+                               last, s);
     }
 }
 

@@ -216,7 +216,8 @@ void launch_ixfft_t(const cx<T>* Tb, const cx<T>* xin, const cx<T>* ainv, cx<T>*
 // Three-kernel chain (matvec_xy.hip) for the other lattices whose zero-padded
 // xy plane of one component fits in LDS (FP32, mx == my in {96, 128}): the
 // x and y passes of the five-pass chain fused on either side of its z pass.
-// The work buffer holds G[pos][3][nz][my][mx] as in the five-pass chain.
+// The work buffer holds G[pos][3][nz][my][mx] as in the five-pass chain;
+// launch_xyfft takes the fused Krylov updates of launch_unpack_xfft.
 bool xy_fused_ok(const Geo& g, int csize);
 // blocks per slot of both kernels (one per (component, z) plane): the partial
 // rows of the fused pack modes and of a folded s update

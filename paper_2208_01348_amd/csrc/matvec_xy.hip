@@ -77,69 +77,153 @@ bool xy_fused_ok(const Geo& g, int csize) {
 int xy_pack_blocks_per_slot(const Geo& g) { return 3 * g.nz; }
 
 // Gather of the plane's rows y < ny (x < nx; the columns x >= L/2 are the
-// zero padding, never stored), with the COCG direction update x <- fuse_r +
-// beta x done in place as in k_unpack_xfft when FUSE (the chain runs for
-// batches too large for the folded forms); then the x-FFT of each row by a
-// lane quad (lane n2 holds x = 4 n1 + n2 and ends with kx = k1 + (L/4)
-// rev2(n2)), written back into the row, and the y-FFT of the L columns, one
-// quad per column, stored straight to the grid buffer.
-template <typename T, int L, bool FUSE>
+// zero padding, never stored), with the Krylov update of the mode FUSE done
+// in place as in k_unpack_xfft (the COCG direction update, with or without
+// the folded end of the previous iteration, or the BiCGStab s or p update);
+// then the x-FFT of each row by a lane quad (lane n2 holds x = 4 n1 + n2 and
+// ends with kx = k1 + (L/4) rev2(n2)), written back into the row, and the
+// y-FFT of the L columns, one quad per column, stored straight to the grid
+// buffer.  The blocks of a slot are its 3 nz planes (z fastest): the rows a
+// folded s update writes are xy_pack_blocks_per_slot of them.
+template <typename T, int L, int FUSE>
 __global__ __launch_bounds__(4 * L, kXyWavesPerEu) void k_xyfft(cx<T>* __restrict__ xin,
                                                                const int* __restrict__ map,
                                                                cx<T>* __restrict__ G,
                                                                const cx<T>* __restrict__ tw, Geo g,
                                                                const int* __restrict__ act,
                                                                const cx<T>* __restrict__ fuse_r,
-                                                               SlotFilter f) {
+                                                               SlotFilter f, CocgFold fo,
+                                                               BicgFold bf) {
     constexpr int NTB = 4 * L;
     constexpr int S = xy_stride<L>();
     constexpr int HL = L / 2;
     constexpr int Q = L / 4;
+    constexpr bool FUSE_P = FUSE == FUSE_COCG;
+    constexpr bool FUSE_S = FUSE == FUSE_BICG_S;
+    constexpr bool FUSE_BP = FUSE == FUSE_BICG_P;
     __shared__ cx<T> lds[HL * S];
     __shared__ cx<T> twl[L];
     const int tid = threadIdx.x;
     const int z = blockIdx.x, c = blockIdx.y, pos = blockIdx.z;
     const int64_t slot = act ? act[pos] : pos;
-    if (!slot_live(f, slot)) return;
+    const bool lead = z == 0 && c == 0;
+    const bool fold = FUSE_P && fo.nblk > 0;
+    bool sact = false;  // FUSE_S, FUSE_BP: this slot iterates, so the block updates
+    int status0 = SLOT_ACTIVE;
+    if (fold || FUSE_S || FUSE_BP) {  // a folded step may change the status: one read per block
+        __shared__ int st0;
+        if (tid == 0) st0 = (FUSE_S || FUSE_BP ? bf.st : f.st)[slot].status;
+        __syncthreads();
+        status0 = st0;
+        if (fold && status0 != SLOT_ACTIVE) return;
+        sact = status0 == SLOT_ACTIVE;
+    } else if (!slot_live(f, slot)) {
+        return;
+    }
     map += slot * g.map_stride;
     for (int t = tid; t < L; t += NTB) twl[t] = tw[t];
-    const int nx = g.nx, ny = g.ny;
+    const int ny = g.ny;
     cx<T>* src = xin + (slot * 3 + c) * g.n_occ;
     const cx<T>* rsrc = FUSE ? fuse_r + (slot * 3 + c) * g.n_occ : nullptr;
+    const cx<T>* vsrc = (FUSE_S || FUSE_BP)
+                            ? static_cast<const cx<T>*>(bf.v) + (slot * 3 + c) * g.n_occ
+                            : nullptr;
     // element e of the plane: row y = e / HL, column x = e % HL; every index
     // load, then every data load, is issued before the first use
     constexpr int NE = (HL * HL + NTB - 1) / NTB;
     const cx<T> zero{T(0), T(0)};
     int idx[NE];
-    xy_plane_indices<L, NE, NTB>(map, z, nx, ny, tid, idx);
+    xy_plane_indices<L, NE, NTB>(map, z, g.nx, ny, tid, idx);
+    // the update's scalars: the folded row sums go out while the index loads
+    // are in flight, ahead of the data loads
     cx<T> beta{T(0), T(0)};
     bool reset = false;
-    if (FUSE) {
-        beta = cvt<T>(f.st[slot].beta);
+    if (FUSE_P) {
+        if (fold) {
+            z128 b;
+            if (!cocg_fold<NTB>(fo, int(slot), lead, b)) return;
+            beta = cvt<T>(b);
+        } else {
+            beta = cvt<T>(f.st[slot].beta);
+        }
         reset = f.st[slot].reset_p != 0;
     }
-    cx<T> v[NE], w[FUSE ? NE : 1];
+    cx<T> alpha{T(0), T(0)}, bt{T(0), T(0)}, om{T(0), T(0)};
+    if constexpr (FUSE_S) {
+        if (sact) {  // block-uniform
+            z128 a;
+            sact = bicg_sfold<NTB>(bf, int(slot), lead, a);
+            alpha = cvt<T>(a);
+        }
+    }
+    if constexpr (FUSE_BP) {
+        z128 b, o;
+        sact = bicg_pfold<NTB>(bf, int(slot), status0, lead, b, o);
+        bt = cvt<T>(b);
+        om = cvt<T>(o);
+    }
+    cx<T> v[NE], w[FUSE ? NE : 1], u[FUSE_S || FUSE_BP ? NE : 1];
 #pragma unroll
     for (int q = 0; q < NE; ++q) {
         const int i = max(idx[q], 0);
-        v[q] = src[i];
-        if constexpr (FUSE) w[q] = rsrc[i];
+        if constexpr (FUSE_S) {
+            if (sact) {
+                w[q] = rsrc[i];
+                u[q] = vsrc[i];
+            } else {
+                v[q] = src[i];
+            }
+        } else if constexpr (FUSE_BP) {
+            v[q] = src[i];
+            if (sact) {
+                w[q] = rsrc[i];
+                u[q] = vsrc[i];
+            }
+        } else {
+            v[q] = src[i];
+            if constexpr (FUSE_P) w[q] = rsrc[i];
+        }
     }
+    double s2 = 0.0;
 #pragma unroll
     for (int q = 0; q < NE; ++q) {
         const int e = tid + q * NTB;
         const int y = e / HL, x = e - (e / HL) * HL;
         const bool occ = idx[q] >= 0;
-        cx<T> vq = v[q];
-        if constexpr (FUSE) {
+        cx<T> vq;
+        if constexpr (FUSE_S) {
+            if (sact) {
+                vq = bicg_s_of(w[q], alpha, u[q]);
+                if (occ) s2 += bicg_norm2(vq);
+            } else {
+                vq = v[q];
+            }
+        } else if constexpr (FUSE_BP) {
+            vq = v[q];
+            if (sact) {
+                const cx<T> upd = bicg_p_of(w[q], bt, vq, om, u[q]);
+                vq.x = upd.x;  // component-wise, as in k_unpack_xfft
+                vq.y = upd.y;
+            }
+        } else {
+            vq = v[q];
+        }
+        if constexpr (FUSE_P) {
             const cx<T> upd = w[q] + beta * vq;
-            vq.x = reset ? w[q].x : upd.x;  // component selects, as in k_unpack_xfft
+            vq.x = reset ? w[q].x : upd.x;
             vq.y = reset ? w[q].y : upd.y;
         }
         vq.x = occ ? vq.x : T(0);
         vq.y = occ ? vq.y : T(0);
-        if (FUSE && occ) src[idx[q]] = vq;  // each occupied element: exactly one thread
+        // each occupied element: exactly one thread
+        if ((FUSE_P || ((FUSE_S || FUSE_BP) && sact)) && occ) src[idx[q]] = vq;
         if (y < ny) lds[y * S + x] = vq;
+    }
+    if constexpr (FUSE_S) {
+        if (sact) {  // ||s||^2 rows, one per block of the slot (block-uniform)
+            double pr[1] = {s2};
+            block_partial<1, NTB, 6>(pr, bf.red, int(slot), blockIdx.x + gridDim.x * c);
+        }
     }
     __syncthreads();
     const int grp = tid >> 2, n2 = tid & 3;
@@ -207,11 +291,11 @@ __global__ __launch_bounds__(4 * L, kXyWavesPerEu) void k_ixyfft_pack(const cx<T
     for (int t = tid; t < L; t += NTB) twl[t] = tw[t];
     __syncthreads();
     quad_fft_blk<T, L, true>(a, n2, tw, twl);
+    // every row y < L/2 is stored (rows y >= ny are never read): a test per
+    // store would put each output's last butterfly in a branch of its own,
+    // and the values held across those branches spill
 #pragma unroll
-    for (int n1 = 0; n1 < Q / 2; ++n1) {
-        const int y = 4 * n1 + n2;
-        if (y < ny) lds[y * S + xy_kpos<L>(kx)] = a[n1];
-    }
+    for (int n1 = 0; n1 < Q / 2; ++n1) lds[(4 * n1 + n2) * S + xy_kpos<L>(kx)] = a[n1];
     __syncthreads();
     if (kx < ny) {  // x-iFFT of row y = kx (the quad index), in place
         cx<T>* row = lds + kx * S;
@@ -268,18 +352,19 @@ void launch_xyfft(cx<T>* xin, const int* map, cx<T>* G, const cx<T>* tw, const G
     } else {
         if (!xy_fused_ok(g, int(sizeof(cx<T>)))) throw Error(-1, "xy plane does not fit in LDS");
         const dim3 grid(unsigned(g.nz), 3, unsigned(n_act));
-        if (bf.kind != BICG_FOLD_NONE || fo.nblk > 0)
-            throw Error(-1, "the fused xy chain takes no folded Krylov step");
         switch (g.mx) {
-#define DDA_CASE(N)                                                                    \
-    case N:                                                                            \
-        if (fuse_r)                                                                    \
-            k_xyfft<T, N, true><<<grid, 4 * N, 0, s>>>(xin, map, G, tw, g, act, fuse_r, f); \
-        else                                                                           \
-            k_xyfft<T, N, false><<<grid, 4 * N, 0, s>>>(xin, map, G, tw, g, act, nullptr, f); \
+#define DDA_XY(N, M, FO, BF, R)                                                               \
+    k_xyfft<T, N, M><<<grid, 4 * N, 0, s>>>(xin, map, G, tw, g, act, R, f, FO, BF)
+#define DDA_CASE(N)                                                                           \
+    case N:                                                                                   \
+        if (fuse_r && bf.kind == BICG_FOLD_S) DDA_XY(N, FUSE_BICG_S, CocgFold{}, bf, fuse_r);   \
+        else if (fuse_r && bf.kind == BICG_FOLD_P) DDA_XY(N, FUSE_BICG_P, CocgFold{}, bf, fuse_r); \
+        else if (fuse_r) DDA_XY(N, FUSE_COCG, fo, BicgFold{}, fuse_r);                        \
+        else DDA_XY(N, FUSE_NONE, CocgFold{}, BicgFold{}, nullptr);                           \
         break;
             DDA_FOR_EACH_LXY(DDA_CASE)
 #undef DDA_CASE
+#undef DDA_XY
             default:
                 throw Error(-1, "unsupported xy plane length");
         }

@@ -620,11 +620,10 @@ __global__ __launch_bounds__(yzr_threads<L>()) void k_yzconv_r(
 #pragma unroll
         for (int k1 = 0; k1 < Q; ++k1) u[k1] = row[k1 + Q * rb];
         quad_fft_blk<T, L, true>(u, n2, twz, twz);
+        // z = 4 n1 + n2 < L/2: the row's slots z >= nz are never read again,
+        // so every one is written (no branch per store)
 #pragma unroll
-        for (int n1 = 0; n1 < Q / 2; ++n1) {  // z = 4 n1 + n2 < nz <= L/2
-            const int z = 4 * n1 + n2;
-            if (z < nz) row[z] = u[n1];
-        }
+        for (int n1 = 0; n1 < Q / 2; ++n1) row[4 * n1 + n2] = u[n1];
     }
     __syncthreads();
 

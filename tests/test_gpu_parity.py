@@ -272,14 +272,14 @@ def test_losses_when_every_precision_uses_the_five_pass_chain(solver, precision,
 
 @pytest.mark.parametrize("side,nz,frac", [(48, 3, 0.025), (64, 2, 0.02)])
 @pytest.mark.parametrize("solver", ["cocg", "bicgstab", "qmr"])
-def test_losses_on_the_fused_xy_chain(side, nz, frac, solver):
+@pytest.mark.parametrize("n_energy", [2, 20])
+def test_losses_on_the_fused_xy_chain(side, nz, frac, solver, n_energy):
     """Sparse side x side x nz lattices (FFT grids 96 x 96 and 128 x 128 in x
-    and y) solved at 20 energies at once: the FP32 matvecs of the mixed path
-    run the fused xy chain (xyfft, zconv, ixyfft_pack) while at least 16
-    systems iterate, with the COCG direction update in its first kernel and
-    the fused partial rows of its pack, and the five-pass chain once fewer are
-    left; against dense LU at every energy."""
-    n_energy = 20
+    and y): the FP32 matvecs of the mixed path run the fused xy chain
+    (xyfft, zconv, ixyfft_pack) with the Krylov updates in its first kernel
+    (folded with the end of the previous iteration for batches of at most
+    eight, as for 2 energies and the last of the 20) and the fused partial rows
+    of its pack; against dense LU at every energy."""
     mask = W.random_mask(side, side, nz, frac, seed=side + nz)
     d = 1.1
     n = int(mask.sum())
@@ -290,15 +290,11 @@ def test_losses_on_the_fused_xy_chain(side, nz, frac, solver):
     s = DDASolver(mask, d, 1.45, precision="mixed", solver=solver, tol=1e-10, maxit=20000)
     assert s.grid[0] == s.grid[1] == 2 * side, s.grid
     s.set_timing(True)
-    for nrhs, xy in ((16, True), (15, False)):
-        s.matvec(2.0, eps[0], torch.zeros((nrhs, 3, n), dtype=torch.complex64, device="cuda"),
-                 precision="mixed")
-        torch.cuda.synchronize()
-        fused = [s.kernel_time(k)[1] for k in ("xyfft", "ixyfft_pack")]
-        five = [s.kernel_time(k)[1] for k in ("unpack_xfft", "yfft", "iyfft", "ixfft_pack")]
-        assert fused == ([1, 1] if xy else [0, 0]) and five == ([0] * 4 if xy else [1] * 4)
-        assert s.kernel_time("zconv")[1] == 1
-        s.set_timing(True)  # resets the counters
+    s.matvec(2.0, eps[0], torch.zeros((3, 3, n), dtype=torch.complex64, device="cuda"),
+             precision="mixed")
+    torch.cuda.synchronize()
+    assert [s.kernel_time(k)[1] for k in ("xyfft", "zconv", "ixyfft_pack")] == [1, 1, 1]
+    assert [s.kernel_time(k)[1] for k in ("unpack_xfft", "yfft", "iyfft", "ixfft_pack")] == [0] * 4
     s.set_timing(False)
     P, info = s.spectrum(energies, 0.55, eps, r0)
     say("  iterations", [i.iters for i in info])
@@ -317,8 +313,7 @@ def test_losses_on_the_fused_xy_chain(side, nz, frac, solver):
 def test_fused_xy_chain_matvec_matches_dense(side):
     """The FP32 products y = A x and G_off x of the fused xy chain on a fully
     occupied side x side x 3 lattice (FFT grid 2 side in x and y) against the
-    oracle's dense rows, for 16 right-hand sides at once (the smallest batch
-    the chain takes)."""
+    oracle's dense rows, for 16 right-hand sides at once."""
     mask = np.ones((3, side, side), np.uint8)
     n = int(mask.sum())
     E = 2.2
