@@ -79,6 +79,30 @@ std::vector<int> zconv_tx_candidates(int L);
 enum PackMode { PACK_AX = 0, PACK_GX = 1, PACK_AX_COCG = 2, PACK_AX_DOTW = 3, PACK_AX_TS = 4 };
 inline bool pack_fused(int mode) { return mode >= PACK_AX_COCG; }
 
+// Compact-vector index of each element e = tid + q NTH (q < NE) of a block's
+// rows: row r = e / HX, column x = e % HX, rows nx apart from mrow; -1 for
+// r >= nrow, x >= nx or an empty cell.  Every load is issued before the first
+// is used: the addresses are clamped into the rows, and the mask is applied
+// afterwards in a loop of its own without a short-circuit test (next to the
+// load, `a && b ? m : -1` let the compiler move each load into a branch that
+// waited for it).
+template <int NE, int NTH, int HX>
+__device__ __forceinline__ void row_indices(const int* __restrict__ mrow, int nrow, int nx,
+                                            int tid, int (&idx)[NE]) {
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+        const int e = tid + q * NTH;
+        const int r = e / HX, x = e - (e / HX) * HX;
+        idx[q] = mrow[min(r, nrow - 1) * nx + min(x, nx - 1)];
+    }
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+        const int e = tid + q * NTH;
+        const int r = e / HX, x = e - (e / HX) * HX;
+        idx[q] = ((r < nrow) & (x < nx)) ? idx[q] : -1;
+    }
+}
+
 // a u + b v + c w of complex values as one chain of a product and five
 // multiply-adds per part (the signs of negated operands fold into them).
 template <typename T>

@@ -41,31 +41,6 @@ __device__ __forceinline__ int xy_kpos(int kx) { return kx + kx / (L / 4); }
 // plane allows (at most 128 VGPRs for L = 128).
 constexpr int kXyWavesPerEu = 4;
 
-// Index of the plane element e = tid + q NTB (row y = e / (L/2), column
-// x = e % (L/2)) in the compact vector, -1 where no dipole is.  Every load is
-// issued before the first is used: the addresses are clamped into the plane
-// and the validity is applied to the loaded values afterwards (a short-circuit
-// test around each load lets the compiler move the load into a branch that
-// waits for it).
-template <int L, int NE, int NTB>
-__device__ __forceinline__ void xy_plane_indices(const int* __restrict__ map, int z, int nx, int ny,
-                                                 int tid, int (&idx)[NE]) {
-    constexpr int HL = L / 2;
-    int m[NE];
-#pragma unroll
-    for (int q = 0; q < NE; ++q) {
-        const int e = tid + q * NTB;
-        const int y = e / HL, x = e - (e / HL) * HL;
-        m[q] = map[(int64_t(z) * ny + min(y, ny - 1)) * nx + min(x, nx - 1)];
-    }
-#pragma unroll
-    for (int q = 0; q < NE; ++q) {
-        const int e = tid + q * NTB;
-        const int y = e / HL, x = e - (e / HL) * HL;
-        idx[q] = ((y < ny) & (x < nx)) ? m[q] : -1;
-    }
-}
-
 }  // namespace
 
 bool xy_fused_ok(const Geo& g, int csize) {
@@ -133,7 +108,7 @@ __global__ __launch_bounds__(4 * L, kXyWavesPerEu) void k_xyfft(cx<T>* __restric
     constexpr int NE = (HL * HL + NTB - 1) / NTB;
     const cx<T> zero{T(0), T(0)};
     int idx[NE];
-    xy_plane_indices<L, NE, NTB>(map, z, g.nx, ny, tid, idx);
+    row_indices<NE, NTB, HL>(map + int64_t(z) * ny * g.nx, ny, g.nx, tid, idx);
     // the update's scalars: the folded row sums go out while the index loads
     // are in flight, ahead of the data loads
     cx<T> beta{T(0), T(0)};
@@ -310,7 +285,7 @@ __global__ __launch_bounds__(4 * L, kXyWavesPerEu) void k_ixyfft_pack(const cx<T
     const int64_t voff = (slot * 3 + c) * g.n_occ;
     constexpr int NE = (HL * HL + NTB - 1) / NTB;
     int idx[NE];
-    xy_plane_indices<L, NE, NTB>(map, z, nx, ny, tid, idx);
+    row_indices<NE, NTB, HL>(map + int64_t(z) * ny * nx, ny, nx, tid, idx);
     cx<T> xv[NE], av[NE], wq[MODE == PACK_AX_DOTW ? NE : 1];
     if (MODE != PACK_GX) {
 #pragma unroll

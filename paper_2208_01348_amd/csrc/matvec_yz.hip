@@ -140,17 +140,9 @@ __global__ __launch_bounds__(NT) void k_xfft_t(cx<T>* __restrict__ xin,
     const cx<T>* vsrc = (FUSE_S || FUSE_BP)
                             ? static_cast<const cx<T>*>(bf.v) + (slot * 3 + c) * g.n_occ
                             : nullptr;
-    // loads use clamped (always valid) addresses and are masked afterwards, so
-    // that none of them sits behind a branch and all can be in flight at once
-    const int* mrow = map + (int64_t(z) * g.ny + y0) * g.nx;
+    // every index load, then every data load, is in flight before the first use
     int idx[NE];
-#pragma unroll
-    for (int q = 0; q < NE; ++q) {
-        const int e = tid + q * NT;
-        const int r = e / HX, x = e - (e / HX) * HX;
-        const int m = mrow[min(r, nrow - 1) * g.nx + min(x, g.nx - 1)];
-        idx[q] = (r < nrow && x < g.nx) ? m : -1;
-    }
+    row_indices<NE, NT, HX>(map + (int64_t(z) * g.ny + y0) * g.nx, nrow, g.nx, tid, idx);
     // the direction update's scalars: the folded finalizer's row loads go
     // out while the index loads are in flight, ahead of the data loads
     cx<T> beta{T(0), T(0)};
@@ -316,15 +308,8 @@ __global__ __launch_bounds__(NT) void k_ixfft_t(const cx<T>* __restrict__ Tb,
     __syncthreads();
     fft_tile<T, LX, true, NR, LP, 1, NT>(lds, twl, tid, nrow);
     const int64_t voff = (slot * 3 + c) * g.n_occ;
-    const int* mrow = map + (int64_t(z) * g.ny + y0) * g.nx;
     int idx[NE];
-#pragma unroll
-    for (int q = 0; q < NE; ++q) {
-        const int e = tid + q * NT;
-        const int r = e / HX, x = e - (e / HX) * HX;
-        const int m = mrow[min(r, nrow - 1) * g.nx + min(x, g.nx - 1)];
-        idx[q] = (r < nrow && x < g.nx) ? m : -1;
-    }
+    row_indices<NE, NT, HX>(map + (int64_t(z) * g.ny + y0) * g.nx, nrow, g.nx, tid, idx);
     cx<T> xv[NE], av[NE], wq[MODE == PACK_AX_DOTW ? NE : 1];
     if (MODE != PACK_GX) {
 #pragma unroll
