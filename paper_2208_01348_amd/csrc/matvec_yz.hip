@@ -501,6 +501,38 @@ __global__ __launch_bounds__(yzr_threads<L>()) void k_yzconv_r(
     }
     __syncthreads();
 
+    // D slab of this kx (phase 2b).  The slab holds the corner ky', kz' <= L/2,
+    // and one entry serves the frequencies (ky' or L - ky') x (kz' or L - kz')
+    // through the parity of each component.  Interior entries
+    // (0 < ky', kz' < L/2) give one work item of four frequencies for six
+    // loads; consecutive lanes take consecutive ky', the fastest slab index
+    // (coalesced).  The 4L - 4 frequencies on the lines ky or kz in {0, L/2}
+    // are one item each.
+    constexpr int HI = L / 2 - 1;
+    constexpr int NI = HI * HI;
+    constexpr int NEG = 4 * L - 4;
+    constexpr int NII = (NI + NTR - 1) / NTR;
+    constexpr int NIE = (NEG + NTR - 1) / NTR;
+    constexpr int H2 = HD * HD;
+    const bool fx = kx > g.mx / 2;
+    const int kxr = fx ? g.mx - kx : kx;
+    const cx<T>* __restrict__ dslab = Dptr[sys] + int64_t(kxr) * 6 * H2;
+    const T sx = fx ? T(-1) : T(1);
+    // edge frequency p: kz = 0 and kz = L/2 (all ky), then ky = 0 and
+    // ky = L/2 (kz off those two)
+    auto edge = [](int p, int& ky, int& kz) {
+        if (p < 2 * L) {
+            kz = p < L ? 0 : L / 2;
+            ky = p < L ? p : p - L;
+        } else {
+            const int q = p - 2 * L;
+            ky = q < L - 2 ? 0 : L / 2;
+            kz = 1 + (q < L - 2 ? q : q - (L - 2));
+            if (kz >= L / 2) ++kz;
+        }
+    };
+    cx<T> di[NII][6], de[NIE][6];
+
     // phase 2a: z-FFT of the rows (c, ky), spectrum back into the row
     if (grp < 3 * L) {
         cx<T>* row = lds + grp * ZS;
@@ -514,41 +546,12 @@ __global__ __launch_bounds__(yzr_threads<L>()) void k_yzconv_r(
 #pragma unroll
         for (int k1 = 0; k1 < Q; ++k1) row[k1 + Q * rb] = u[k1];
     }
-    __syncthreads();
-    // phase 2b: D u at every (ky, kz).  The slab holds the corner
-    // ky', kz' <= L/2, and one entry serves the frequencies (ky' or L - ky') x
-    // (kz' or L - kz') through the parity of each component.  Interior
-    // entries (0 < ky', kz' < L/2) give one work item of four frequencies for
-    // six loads; consecutive lanes take consecutive ky', the fastest slab
-    // index (coalesced).  The 4L - 4 frequencies on the lines ky or kz in
-    // {0, L/2} are one item each.  All D loads of a thread are issued before
-    // its first product.  LDS rows at an odd stride keep accesses in distinct
-    // banks.
+    // All D loads of a thread go out here, after its row is stored (the line
+    // registers are free again) and before the barrier, so their latency
+    // overlaps the wait for the other waves' z-FFTs.  Issued before the z-FFT
+    // instead they would stay live through it and take the kernel past the
+    // registers of five waves per SIMD.
     {
-        constexpr int HI = L / 2 - 1;
-        constexpr int NI = HI * HI;
-        constexpr int NEG = 4 * L - 4;
-        constexpr int NII = (NI + NTR - 1) / NTR;
-        constexpr int NIE = (NEG + NTR - 1) / NTR;
-        constexpr int H2 = HD * HD;
-        const bool fx = kx > g.mx / 2;
-        const int kxr = fx ? g.mx - kx : kx;
-        const cx<T>* __restrict__ dslab = Dptr[sys] + int64_t(kxr) * 6 * H2;
-        const T sx = fx ? T(-1) : T(1);
-        // edge frequency p: kz = 0 and kz = L/2 (all ky), then ky = 0 and
-        // ky = L/2 (kz off those two)
-        auto edge = [](int p, int& ky, int& kz) {
-            if (p < 2 * L) {
-                kz = p < L ? 0 : L / 2;
-                ky = p < L ? p : p - L;
-            } else {
-                const int q = p - 2 * L;
-                ky = q < L - 2 ? 0 : L / 2;
-                kz = 1 + (q < L - 2 ? q : q - (L - 2));
-                if (kz >= L / 2) ++kz;
-            }
-        };
-        cx<T> di[NII][6], de[NIE][6];
         __builtin_amdgcn_s_setprio(2);  // as for the loads of phase 1
 #pragma unroll
         for (int it = 0; it < NII; ++it) {
@@ -557,15 +560,24 @@ __global__ __launch_bounds__(yzr_threads<L>()) void k_yzconv_r(
 #pragma unroll
             for (int q = 0; q < 6; ++q) di[it][q] = gload(dslab + kzp * HD + kyp + q * H2);
         }
+        const int wbase = tid & ~63;  // waves past the last edge item skip its loads
 #pragma unroll
         for (int it = 0; it < NIE; ++it) {
-            int ky, kz;
-            edge(min(tid + it * NTR, NEG - 1), ky, kz);
-            const int o = (kz > L / 2 ? L - kz : kz) * HD + (ky > L / 2 ? L - ky : ky);
+            if (wbase + it * NTR < NEG) {
+                int ky, kz;
+                edge(min(tid + it * NTR, NEG - 1), ky, kz);
+                const int o = (kz > L / 2 ? L - kz : kz) * HD + (ky > L / 2 ? L - ky : ky);
 #pragma unroll
-            for (int q = 0; q < 6; ++q) de[it][q] = gload(dslab + o + q * H2);
+                for (int q = 0; q < 6; ++q) de[it][q] = gload(dslab + o + q * H2);
+            }
         }
         __builtin_amdgcn_s_setprio(0);
+    }
+    __syncthreads();
+    // phase 2b: D u at every (ky, kz), from the slab entries loaded above (a
+    // wave that skipped the edge loads has no lane with p < NEG).  LDS rows at
+    // an odd stride keep accesses in distinct banks.
+    {
 #pragma unroll
         for (int it = 0; it < NII; ++it) {
             const int t = tid + it * NTR;
