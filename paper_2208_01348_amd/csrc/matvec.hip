@@ -523,28 +523,45 @@ __global__ __launch_bounds__(NT) void k_zconv2(cx<T>* __restrict__ G,
 #pragma unroll
         for (int m = 0; m < R2; ++m) lds[(j + m * R1) * W + line] = a[m];
     }
-    __syncthreads();
     // D from its stored corner [0, M/2]^3 (index M - k reads k; the odd
     // components flip sign), one load for the four frequencies
     // (ky0 or ky1) x (kz' or L - kz') of a column.  With sx the x parity,
     // the xy entry flips with the y mirror, xz with the z mirror and yz with
     // either; the four products are written out so that the signs fold into
-    // the multiply-adds.
+    // the multiply-adds.  A thread's D loads go out before the barrier (its
+    // stage-2 registers are free by then), so their latency overlaps the
+    // wait for the other waves.
     {
         constexpr int MZH = L / 2 + 1;
+        constexpr int ND = (MZH * TX + NT - 1) / NT;
         const int mxh = g.mx / 2 + 1, myh = g.my / 2 + 1;
         const int dplane = myh * mxh;  // a corner component holds < 2^31 entries
         const int dcomp = MZH * dplane;
         const cx<T>* dbase = Dptr[sys] + ky0 * mxh;
-        for (int e = tid; e < MZH * TX; e += NT) {
+        const int wbase = tid & ~63;
+        cx<T> dv[ND][6];
+#pragma unroll
+        for (int q = 0; q < ND; ++q) {
+            if (wbase + q * NT < MZH * TX) {  // wave-uniform
+                const int e = min(tid + q * NT, MZH * TX - 1);
+                const int kzp = e / TX, col = e - (e / TX) * TX;
+                const int kx = min(col0 + col, g.mx - 1);
+                const cx<T>* dp = dbase + kzp * dplane + (kx > g.mx / 2 ? g.mx - kx : kx);
+#pragma unroll
+                for (int c = 0; c < 6; ++c) dv[q][c] = gload(dp + c * dcomp);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < ND; ++q) {
+            const int e = tid + q * NT;
+            if (e >= MZH * TX) continue;
             const int kzp = e / TX, col = e - (e / TX) * TX;
             const int kx = col0 + col;
             if (kx >= g.mx) continue;
             const bool fx = kx > g.mx / 2;
-            const cx<T>* dp = dbase + kzp * dplane + (fx ? g.mx - kx : kx);
-            const cx<T> dxx = gload(dp), dxy = gload(dp + dcomp), dxz = gload(dp + 2 * dcomp);
-            const cx<T> dyy = gload(dp + 3 * dcomp), dyz = gload(dp + 4 * dcomp);
-            const cx<T> dzz = gload(dp + 5 * dcomp);
+            const cx<T> dxx = dv[q][0], dxy = dv[q][1], dxz = dv[q][2];
+            const cx<T> dyy = dv[q][3], dyz = dv[q][4], dzz = dv[q][5];
             const T sx = fx ? T(-1) : T(1);
             const cx<T> axy = sx * dxy, axz = sx * dxz;
             cx<T>* u = lds + kzp * W + col;  // kz', set 0 (ky0)
