@@ -119,14 +119,7 @@ __global__ __launch_bounds__(NTHR) void k_unpack_xfft(cx<T>* __restrict__ xin,
     constexpr int NE = (NL * HX + NTHR - 1) / NTHR;
     const cx<T> zero{T(0), T(0)};
     int idx[NE];
-#pragma unroll
-    for (int q = 0; q < NE; ++q) {
-        const int e = tid + q * NTHR;
-        const int rr = e / HX, x = e - (e / HX) * HX;
-        const int row = row0 + rr;
-        const int m = map[int64_t(min(row, nrows - 1)) * g.nx + min(x, g.nx - 1)];
-        idx[q] = (rr < NL && row < nrows && x < g.nx) ? m : -1;
-    }
+    row_indices<NE, NTHR, HX>(map + int64_t(row0) * g.nx, min(NL, nrows - row0), g.nx, tid, idx);
     // the direction update's scalars: the folded finalizer's row loads go
     // out while the index loads are in flight, ahead of the data loads
     cx<T> beta{T(0), T(0)};
@@ -210,7 +203,10 @@ __global__ __launch_bounds__(NTHR) void k_unpack_xfft(cx<T>* __restrict__ xin,
         vq.y = occ ? vq.y : T(0);
         // each occupied element: exactly one thread
         if ((FUSE_P || ((FUSE_S || FUSE_BP) && sact)) && occ) src[idx[q]] = vq;
-        if (rr < NL) {
+        // (no test where the elements cover the rows exactly: the compiler does
+        // not prove rr < NL from the block size, and the branch it made held back
+        // that element's index and data loads until the others had returned)
+        if (NE * NTHR <= NL * HX || rr < NL) {
             lds[rr * L + x] = vq;
             if (x + HX < L) lds[rr * L + x + HX] = zero;
         }
@@ -675,14 +671,7 @@ __global__ __launch_bounds__(NTHR) void k_ixfft_pack(const cx<T>* __restrict__ G
     constexpr int HX = (L + 1) / 2;  // x < (L+1)/2 holds every occupied cell
     constexpr int NE = (NL * HX + NTHR - 1) / NTHR;
     int idx[NE];
-#pragma unroll
-    for (int q = 0; q < NE; ++q) {
-        const int e = tid + q * NTHR;
-        const int rr = e / HX, x = e - (e / HX) * HX;
-        const int row = row0 + rr;
-        const int m = map[int64_t(min(row, nrows - 1)) * g.nx + min(x, g.nx - 1)];
-        idx[q] = (rr < NL && row < nrows && x < g.nx) ? m : -1;
-    }
+    row_indices<NE, NTHR, HX>(map + int64_t(row0) * g.nx, min(NL, nrows - row0), g.nx, tid, idx);
     cx<T> xv[NE], av[NE], wq[MODE == PACK_AX_DOTW ? NE : 1];
     if (MODE != PACK_GX) {
 #pragma unroll
