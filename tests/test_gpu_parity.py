@@ -270,25 +270,33 @@ def test_losses_when_every_precision_uses_the_five_pass_chain(solver, precision,
     s.close()
 
 
-@pytest.mark.parametrize("side,nz,frac", [(48, 3, 0.025), (64, 2, 0.02)])
+def _xy_grid(n):
+    """FFT length the library picks for n cells (the smallest supported length
+    of at least 2 n - 1)."""
+    return next(s for s in (96, 128) if s >= 2 * n - 1)
+
+
+@pytest.mark.parametrize("nx,ny,nz,frac", [(48, 48, 3, 0.025), (64, 64, 2, 0.02),
+                                           (44, 37, 3, 0.03)])
 @pytest.mark.parametrize("solver", ["cocg", "bicgstab", "qmr"])
 @pytest.mark.parametrize("n_energy", [2, 20])
-def test_losses_on_the_fused_xy_chain(side, nz, frac, solver, n_energy):
-    """Sparse side x side x nz lattices (FFT grids 96 x 96 and 128 x 128 in x
-    and y): the FP32 matvecs of the mixed path run the fused xy chain
-    (xyfft, zconv, ixyfft_pack) with the Krylov updates in its first kernel
-    (folded with the end of the previous iteration for batches of at most
-    eight, as for 2 energies and the last of the 20) and the fused partial rows
-    of its pack; against dense LU at every energy."""
-    mask = W.random_mask(side, side, nz, frac, seed=side + nz)
+def test_losses_on_the_fused_xy_chain(nx, ny, nz, frac, solver, n_energy):
+    """Sparse nx x ny x nz lattices (FFT grids 96 x 96 and 128 x 128 in x
+    and y; the last with nx != ny and ny below half the grid, so the rows past
+    ny and the columns past nx are padding): the FP32 matvecs of the mixed path
+    run the fused xy chain (xyfft, zconv, ixyfft_pack) with the Krylov updates
+    in its first kernel (folded with the end of the previous iteration for
+    batches of at most eight, as for 2 energies and the last of the 20) and the
+    fused partial rows of its pack; against dense LU at every energy."""
+    mask = W.random_mask(nx, ny, nz, frac, seed=nx + ny + nz)
     d = 1.1
     n = int(mask.sum())
     energies = np.linspace(1.7, 2.9, n_energy)
     eps = np.repeat(W.drude_eps(energies)[:, None], n, axis=1)
-    r0 = np.array([[side * d / 2 + 0.55, side * d + 2.0, 0.0]])
-    say("fused xy chain", side, nz, solver, n_energy, "n_occ", n)
+    r0 = np.array([[nx * d / 2 + 0.55, ny * d + 2.0, 0.0]])
+    say("fused xy chain", nx, ny, nz, solver, n_energy, "n_occ", n)
     s = DDASolver(mask, d, 1.45, precision="mixed", solver=solver, tol=1e-10, maxit=20000)
-    assert s.grid[0] == s.grid[1] == 2 * side, s.grid
+    assert s.grid[0] == _xy_grid(nx) and s.grid[1] == _xy_grid(ny) == s.grid[0], s.grid
     s.set_timing(True)
     s.matvec(2.0, eps[0], torch.zeros((3, 3, n), dtype=torch.complex64, device="cuda"),
              precision="mixed")
@@ -305,23 +313,31 @@ def test_losses_on_the_fused_xy_chain(side, nz, frac, solver, n_energy):
         scale = max(abs(v) for v in vals)
         for g, v, nm in zip(P[ie], vals, ["eels", "ext", "abs", "cl"]):
             err = abs(g - v) / max(abs(v), 1e-3 * scale)
-            assert err <= 1e-5, (side, solver, E, nm, err)
+            assert err <= 1e-5, (nx, ny, solver, E, nm, err)
     s.close()
 
 
-@pytest.mark.parametrize("side", [48, 64])
-def test_fused_xy_chain_matvec_matches_dense(side):
+@pytest.mark.parametrize("nx,ny", [(48, 48), (64, 64), (40, 44), (47, 34), (50, 60)])
+def test_fused_xy_chain_matvec_matches_dense(nx, ny):
     """The FP32 products y = A x and G_off x of the fused xy chain on a fully
-    occupied side x side x 3 lattice (FFT grid 2 side in x and y) against the
-    oracle's dense rows, for 16 right-hand sides at once."""
-    mask = np.ones((3, side, side), np.uint8)
+    occupied nx x ny x 3 lattice (FFT grids 96 x 96 or 128 x 128 in x and y:
+    exactly twice the box, or with padding rows and columns past ny and nx,
+    nx above or below ny) against the oracle's dense rows, for 16 right-hand
+    sides at once."""
+    mask = np.ones((3, ny, nx), np.uint8)
     n = int(mask.sum())
     E = 2.2
     eps = np.full(n, -6.0 + 0.9j)
-    rng = np.random.default_rng(side)
+    rng = np.random.default_rng(nx * 1000 + ny)
     x = rng.standard_normal((16, n, 3)) + 1j * rng.standard_normal((16, n, 3))
     s = DDASolver(mask, 1.0, 1.45)
-    assert s.grid[0] == s.grid[1] == 2 * side
+    assert s.grid[0] == _xy_grid(nx) and s.grid[1] == _xy_grid(ny) == s.grid[0], s.grid
+    s.set_timing(True)
+    s.matvec(E, eps, torch.zeros((16, n, 3), dtype=torch.complex64, device="cuda"),
+             precision="mixed")
+    torch.cuda.synchronize()
+    assert [s.kernel_time(k)[1] for k in ("xyfft", "ixyfft_pack")] == [1, 1]
+    s.set_timing(False)
     xd = to_dev(x, torch.complex64)
     y = from_dev(s.matvec(E, eps, xd, precision="mixed"))
     yi = from_dev(s.matvec(E, None, xd, precision="mixed", interaction_only=True))
@@ -331,7 +347,7 @@ def test_fused_xy_chain_matvec_matches_dense(side):
         for got, io in ((y[r], False), (yi[r], True)):
             ref = cdense.matvec_rows(c, alpha, k, x[r], rows, interaction_only=io)
             err = np.max(np.abs(got[rows] - ref)) / np.max(np.abs(ref))
-            say("  xy chain side", side, "rhs", r, "G only" if io else "A", "err", err)
+            say("  xy chain", nx, ny, "rhs", r, "G only" if io else "A", "err", err)
             assert err <= 1e-5, (r, io, err)
     s.close()
 
