@@ -119,6 +119,11 @@ MATVEC_LATTICES = [
     # blocks in FP64 (x grid 128), 25 rows over two in FP32 (x grid 192)
     ("random_64x19x19", W.random_mask(64, 19, 19, 0.25, seed=4), 1.0),
     ("random_96x25x25", W.random_mask(96, 25, 25, 0.08, seed=6), 1.0),
+    # y, z grids of 16 and 24: the register yz kernel at its smallest lengths
+    # (at 24 its blocks have threads beyond the (component, ky) quads, which
+    # take part in the D loads and product only)
+    ("random_6x8x7", W.random_mask(6, 8, 7, 0.6, seed=12), 1.2),
+    ("random_10x11x9", W.random_mask(10, 11, 9, 0.6, seed=13), 0.9),
 ]
 
 
