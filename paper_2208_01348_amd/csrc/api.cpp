@@ -552,7 +552,7 @@ void autotune(dda_ctx* c, const Work& w, const int* act, int n_act,
 int pack_blocks(const dda_ctx* c, int csize) {
     if (dda::yz_fused_ok(c->g, csize)) return dda::yz_pack_blocks_per_slot(c->g, csize);
     if (dda::xy_fused_ok(c->g, csize)) return dda::xy_pack_blocks_per_slot(c->g);
-    return dda::pack_blocks_per_slot(c->g);
+    return dda::pack_blocks_per_slot(c->g, csize);
 }
 int x_blocks(const dda_ctx* c, int csize) {
     if (dda::xy_fused_ok(c->g, csize)) return dda::xy_pack_blocks_per_slot(c->g);
@@ -1917,7 +1917,8 @@ int dda_setup(const uint8_t* mask, int nx, int ny, int nz, double d_nm, double m
     for (int lin : c->occ_lin) c->occ_col[size_t(lin % (nx * ny))] = 1;
     DDA_HIP_CHECK(hipGetDevice(&c->device));
     dda::einc_scratch_init();  // the no-alloc staging area of this device
-    c->max_blocks = std::max({1024, dda::pack_blocks_per_slot(g), dda::xy_pack_blocks_per_slot(g),
+    c->max_blocks = std::max({1024, dda::pack_blocks_per_slot(g, 8), dda::pack_blocks_per_slot(g, 16),
+                              dda::xy_pack_blocks_per_slot(g),
                               dda::yz_pack_blocks_per_slot(g, 8),
                               dda::yz_pack_blocks_per_slot(g, 16)});
     // uploads go through the context's stream (never the legacy stream, which

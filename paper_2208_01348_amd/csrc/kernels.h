@@ -166,7 +166,7 @@ __device__ __forceinline__ void pack_rows(double (&mu)[3], RedScratch red, int s
         block_partial<3, NT, 3>(mu, red, slot, blk);
     }
 }
-int pack_blocks_per_slot(const Geo& g);
+int pack_blocks_per_slot(const Geo& g, int csize);
 template <typename T>
 void launch_ixfft_pack(const cx<T>* G, const cx<T>* xin, const cx<T>* ainv, cx<T>* yout,
                        const int* map, const cx<T>* tw_x, const Geo& g, const int* act,

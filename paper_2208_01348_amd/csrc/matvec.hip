@@ -34,9 +34,15 @@ constexpr int pow2floor(int v) {
 }
 constexpr int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-// rows per block for row kernels (about 2048 elements per block)
+// rows per block for row kernels: about 2048 elements per block in FP32 and
+// 1024 in FP64 (16 KB of LDS either way, so more blocks are resident to hide
+// the gather and store latencies of the FP64 x kernels)
+constexpr int row_elems(int csize) { return csize == 16 ? 1024 : 2048; }
 template <typename T, int L>
-constexpr int rows_nl() { return L >= 2048 ? 1 : 2048 / L; }
+constexpr int rows_nl() {
+    constexpr int R = row_elems(int(sizeof(cx<T>)));
+    return L >= R ? 1 : R / L;
+}
 // columns per block for strided-axis kernels (default; the autotuner may
 // pick another width for L >= kTuneMinL)
 template <typename T, int L>
@@ -707,12 +713,13 @@ static inline unsigned nblk(int64_t n, int64_t per) { return unsigned((n + per -
 
 int xfft_blocks_per_slot(const Geo& g, int csize) {
     if (yz_fused_ok(g, csize)) return yz_pack_blocks_per_slot(g, csize);  // same grid as k_xfft_t
-    return pack_blocks_per_slot(g);  // k_unpack_xfft has the grid of k_ixfft_pack
+    return pack_blocks_per_slot(g, csize);  // k_unpack_xfft has the grid of k_ixfft_pack
 }
 
-int pack_blocks_per_slot(const Geo& g) {
+int pack_blocks_per_slot(const Geo& g, int csize) {
     const int64_t nrows = int64_t(g.nz) * g.ny;
-    const int nl = g.mx >= 2048 ? 1 : 2048 / g.mx;  // rows_nl<T, L>() for either T
+    const int r = row_elems(csize);
+    const int nl = g.mx >= r ? 1 : r / g.mx;  // rows_nl<T, mx>()
     return int(3 * ((nrows + nl - 1) / nl));
 }
 
@@ -934,7 +941,7 @@ void launch_ixfft_pack(const cx<T>* G, const cx<T>* xin, const cx<T>* ainv, cx<T
                        const int* slot_sys, int n_act, int mode, SlotFilter f, RedScratch red,
                        hipStream_t s, const cx<T>* wv) {
     if (n_act == 0) return;
-    if (pack_fused(mode) && pack_blocks_per_slot(g) > red.max_blocks)
+    if (pack_fused(mode) && pack_blocks_per_slot(g, int(sizeof(cx<T>))) > red.max_blocks)
         throw Error(-3, "reduction scratch too small for the fused pack kernel");
     if (mode == PACK_AX_DOTW && !wv) throw Error(-1, "PACK_AX_DOTW needs the vector w");
     const int64_t nrows = int64_t(g.nz) * g.ny;
