@@ -102,7 +102,20 @@ __device__ __forceinline__ void dft(cx<T>* a) {
     else if constexpr (R == 8) dft8<INV>(a);
 }
 
-template <typename T, int L, int R, int NS, bool INV, int NLINES, int LS, int ES, int NTHR>
+// Position of element i of a line whose LDS layout has one spare slot after
+// every 16 elements (PAD), or none.  A radix-R Stockham stage stores each
+// lane's R outputs next to each other, so at one store the lanes of a wave are
+// R elements apart; with 16-byte elements and R = 8 that puts 16 lanes on two
+// groups of banks, and the spare slots spread them over all of them (the
+// reads, at consecutive positions, stay conflict-free).
+template <bool PAD>
+__device__ __forceinline__ constexpr int line_pos(int i) { return PAD ? i + (i >> 4) : i; }
+// Line pitch for the padded layout of a line of L elements.
+template <int L>
+constexpr int padded_len() { return L + (L + 15) / 16; }
+
+template <typename T, int L, int R, int NS, bool INV, int NLINES, int LS, int ES, int NTHR,
+          bool PAD = false>
 __device__ __forceinline__ void fft_stage(cx<T>* lds, const cx<T>* __restrict__ tw, int tid,
                                           int nl) {
     constexpr int LR = L / R;
@@ -118,7 +131,7 @@ __device__ __forceinline__ void fft_stage(cx<T>* lds, const cx<T>* __restrict__ 
             const int line = LINE_FAST ? b % NLINES : b / LR;
             const int j = LINE_FAST ? b / NLINES : b % LR;
 #pragma unroll
-            for (int m = 0; m < R; ++m) v[q][m] = lds[line * LS + (j + m * LR) * ES];
+            for (int m = 0; m < R; ++m) v[q][m] = lds[line * LS + line_pos<PAD>((j + m * LR) * ES)];
         }
     }
     __syncthreads();
@@ -140,20 +153,20 @@ __device__ __forceinline__ void fft_stage(cx<T>* lds, const cx<T>* __restrict__ 
             dft<R, INV>(v[q]);
             const int base = (j / NS) * NS * R + k;
 #pragma unroll
-            for (int m = 0; m < R; ++m) lds[line * LS + (base + m * NS) * ES] = v[q][m];
+            for (int m = 0; m < R; ++m) lds[line * LS + line_pos<PAD>((base + m * NS) * ES)] = v[q][m];
         }
     }
     __syncthreads();
 }
 
-template <typename T, int L, int NS, bool INV, int NLINES, int LS, int ES, int NTHR>
+template <typename T, int L, int NS, bool INV, int NLINES, int LS, int ES, int NTHR, bool PAD>
 __device__ __forceinline__ void fft_stages(cx<T>* lds, const cx<T>* __restrict__ tw, int tid,
                                            int nl) {
     if constexpr (NS < L) {
         constexpr int R = pick_radix(L / NS);
         static_assert(R > 1, "FFT length must be 2^a 3^b");
-        fft_stage<T, L, R, NS, INV, NLINES, LS, ES, NTHR>(lds, tw, tid, nl);
-        fft_stages<T, L, NS * R, INV, NLINES, LS, ES, NTHR>(lds, tw, tid, nl);
+        fft_stage<T, L, R, NS, INV, NLINES, LS, ES, NTHR, PAD>(lds, tw, tid, nl);
+        fft_stages<T, L, NS * R, INV, NLINES, LS, ES, NTHR, PAD>(lds, tw, tid, nl);
     }
 }
 
@@ -196,11 +209,13 @@ __device__ __forceinline__ void reg_dft(cx<T> (&v)[Q], const cx<T>* __restrict__
 // of NLINES lines held in LDS.  tw[t] = exp(-2 pi i t / L), t < L.
 // Must be called by all NTHR threads of the block; ends with a barrier.  Only
 // the first nl lines are transformed (nl <= NLINES; ES == 1 when nl < NLINES).
-template <typename T, int L, bool INV, int NLINES, int LS, int ES, int NTHR>
+// PAD: lines in the padded layout of line_pos (ES == 1, LS >= padded_len<L>()).
+template <typename T, int L, bool INV, int NLINES, int LS, int ES, int NTHR, bool PAD = false>
 __device__ __forceinline__ void fft_tile(cx<T>* lds, const cx<T>* __restrict__ tw, int tid,
                                          int nl = NLINES) {
     static_assert(fft_size_ok(L), "FFT length must be 2^a 3^b");
-    fft_stages<T, L, 1, INV, NLINES, LS, ES, NTHR>(lds, tw, tid, nl);
+    static_assert(!PAD || (ES == 1 && LS >= padded_len<L>()), "padded lines need ES == 1");
+    fft_stages<T, L, 1, INV, NLINES, LS, ES, NTHR, PAD>(lds, tw, tid, nl);
 }
 
 }  // namespace dda

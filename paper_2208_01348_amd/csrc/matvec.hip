@@ -91,7 +91,8 @@ __global__ __launch_bounds__(NTHR) void k_unpack_xfft(cx<T>* __restrict__ xin,
     constexpr bool FUSE_S = FUSE == FUSE_BICG_S;
     constexpr bool FUSE_BP = FUSE == FUSE_BICG_P;
     constexpr int NL = rows_nl<T, L>();
-    __shared__ cx<T> lds[NL * L];
+    constexpr int RP = padded_len<L>();  // row pitch (one spare slot per 16 elements)
+    __shared__ cx<T> lds[NL * RP];
     __shared__ cx<T> twl[L];
     const int tid = threadIdx.x;
     const int c = blockIdx.y;
@@ -213,8 +214,8 @@ __global__ __launch_bounds__(NTHR) void k_unpack_xfft(cx<T>* __restrict__ xin,
         // not prove rr < NL from the block size, and the branch it made held back
         // that element's index and data loads until the others had returned)
         if (NE * NTHR <= NL * HX || rr < NL) {
-            lds[rr * L + x] = vq;
-            if (x + HX < L) lds[rr * L + x + HX] = zero;
+            lds[rr * RP + line_pos<true>(x)] = vq;
+            if (x + HX < L) lds[rr * RP + line_pos<true>(x + HX)] = zero;
         }
     }
     if constexpr (FUSE_S) {
@@ -224,7 +225,7 @@ __global__ __launch_bounds__(NTHR) void k_unpack_xfft(cx<T>* __restrict__ xin,
         }
     }
     __syncthreads();
-    fft_tile<T, L, false, NL, L, 1, NTHR>(lds, twl, tid);
+    fft_tile<T, L, false, NL, RP, 1, NTHR, true>(lds, twl, tid);
     cx<T>* dst = G + (int64_t(pos) * 3 + c) * g.nz * g.my * int64_t(g.mx);
     if constexpr (sizeof(T) == 4) {
         // FP32: every LDS read before the first store (32.8 against 34.6 us on
@@ -232,7 +233,10 @@ __global__ __launch_bounds__(NTHR) void k_unpack_xfft(cx<T>* __restrict__ xin,
         constexpr int NST = (NL * L + NTHR - 1) / NTHR;
         cx<T> t[NST];
 #pragma unroll
-        for (int q = 0; q < NST; ++q) t[q] = lds[min(tid + q * NTHR, NL * L - 1)];
+        for (int q = 0; q < NST; ++q) {
+            const int e = min(tid + q * NTHR, NL * L - 1);
+            t[q] = lds[(e / L) * RP + line_pos<true>(e % L)];
+        }
 #pragma unroll
         for (int q = 0; q < NST; ++q) {
             const int e = tid + q * NTHR;
@@ -249,7 +253,7 @@ __global__ __launch_bounds__(NTHR) void k_unpack_xfft(cx<T>* __restrict__ xin,
             const int row = row0 + rr;
             if (row < nrows) {
                 const int z = row / g.ny, y = row - z * g.ny;
-                dst[(int64_t(z) * g.my + y) * g.mx + x] = lds[e];
+                dst[(int64_t(z) * g.my + y) * g.mx + x] = lds[rr * RP + line_pos<true>(x)];
             }
         }
     }
@@ -642,7 +646,8 @@ __global__ __launch_bounds__(NTHR) void k_ixfft_pack(const cx<T>* __restrict__ G
                                                      SlotFilter f, RedScratch red,
                                                      const cx<T>* __restrict__ wv) {
     constexpr int NL = rows_nl<T, L>();
-    __shared__ cx<T> lds[NL * L];
+    constexpr int RP = padded_len<L>();  // row pitch (one spare slot per 16 elements)
+    __shared__ cx<T> lds[NL * RP];
     __shared__ cx<T> twl[L];
     const int tid = threadIdx.x;
     const int c = blockIdx.y;
@@ -668,11 +673,13 @@ __global__ __launch_bounds__(NTHR) void k_ixfft_pack(const cx<T>* __restrict__ G
 #pragma unroll
         for (int q = 0; q < NLD; ++q) {
             const int e = tid + q * NTHR;
-            if (e < NL * L) lds[e] = (row0 + e / L < nrows) ? t[q] : cx<T>{T(0), T(0)};
+            if (e < NL * L)
+                lds[(e / L) * RP + line_pos<true>(e % L)] =
+                    (row0 + e / L < nrows) ? t[q] : cx<T>{T(0), T(0)};
         }
     }
     __syncthreads();
-    fft_tile<T, L, true, NL, L, 1, NTHR>(lds, twl, tid);
+    fft_tile<T, L, true, NL, RP, 1, NTHR, true>(lds, twl, tid);
     const int64_t voff = (slot * 3 + c) * g.n_occ;
     constexpr int HX = (L + 1) / 2;  // x < (L+1)/2 holds every occupied cell
     constexpr int NE = (NL * HX + NTHR - 1) / NTHR;
@@ -694,7 +701,7 @@ __global__ __launch_bounds__(NTHR) void k_ixfft_pack(const cx<T>* __restrict__ G
         if (idx[q] < 0) continue;
         const int e = tid + q * NTHR;
         const int rr = e / HX, x = e - (e / HX) * HX;
-        const cx<T> conv = lds[rr * L + x];
+        const cx<T> conv = lds[rr * RP + line_pos<true>(x)];
         if (MODE == PACK_GX) {
             yout[voff + idx[q]] = conv;
         } else {
