@@ -660,6 +660,15 @@ __global__ __launch_bounds__(NTHR) void k_ixfft_pack(const cx<T>* __restrict__ G
     const int nrows = g.nz * g.ny;
     const int row0 = blockIdx.x * NL;
     const cx<T>* gsrc = G + (int64_t(pos) * 3 + c) * g.nz * g.my * int64_t(g.mx);
+    // the index loads go out with the grid loads and return during the x-iFFT
+    // (the vector loads that depend on them wait until after it: issued here
+    // they would hold registers through it)
+    const int64_t voff = (slot * 3 + c) * g.n_occ;
+    constexpr int HX = (L + 1) / 2;  // x < (L+1)/2 holds every occupied cell
+    constexpr int NE = (NL * HX + NTHR - 1) / NTHR;
+    int idx[NE];
+    row_indices<NE, NTHR, HX>(map + int64_t(row0) * g.nx, min(NL, nrows - row0), g.nx, tid, idx);
+    cx<T> xv[NE], av[NE], wq[MODE == PACK_AX_DOTW ? NE : 1];
     {
         constexpr int NLD = (NL * L + NTHR - 1) / NTHR;
         cx<T> t[NLD];
@@ -680,12 +689,6 @@ __global__ __launch_bounds__(NTHR) void k_ixfft_pack(const cx<T>* __restrict__ G
     }
     __syncthreads();
     fft_tile<T, L, true, NL, RP, 1, NTHR, true>(lds, twl, tid);
-    const int64_t voff = (slot * 3 + c) * g.n_occ;
-    constexpr int HX = (L + 1) / 2;  // x < (L+1)/2 holds every occupied cell
-    constexpr int NE = (NL * HX + NTHR - 1) / NTHR;
-    int idx[NE];
-    row_indices<NE, NTHR, HX>(map + int64_t(row0) * g.nx, min(NL, nrows - row0), g.nx, tid, idx);
-    cx<T> xv[NE], av[NE], wq[MODE == PACK_AX_DOTW ? NE : 1];
     if (MODE != PACK_GX) {
 #pragma unroll
         for (int q = 0; q < NE; ++q) {
