@@ -159,14 +159,15 @@ __device__ __forceinline__ void fft_stage(cx<T>* lds, const cx<T>* __restrict__ 
     __syncthreads();
 }
 
-template <typename T, int L, int NS, bool INV, int NLINES, int LS, int ES, int NTHR, bool PAD>
+template <typename T, int L, int NS, bool INV, int NLINES, int LS, int ES, int NTHR, bool PAD,
+          bool R3F>
 __device__ __forceinline__ void fft_stages(cx<T>* lds, const cx<T>* __restrict__ tw, int tid,
                                            int nl) {
     if constexpr (NS < L) {
-        constexpr int R = pick_radix(L / NS);
+        constexpr int R = (R3F && (L / NS) % 3 == 0) ? 3 : pick_radix(L / NS);
         static_assert(R > 1, "FFT length must be 2^a 3^b");
         fft_stage<T, L, R, NS, INV, NLINES, LS, ES, NTHR, PAD>(lds, tw, tid, nl);
-        fft_stages<T, L, NS * R, INV, NLINES, LS, ES, NTHR, PAD>(lds, tw, tid, nl);
+        fft_stages<T, L, NS * R, INV, NLINES, LS, ES, NTHR, PAD, R3F>(lds, tw, tid, nl);
     }
 }
 
@@ -210,12 +211,16 @@ __device__ __forceinline__ void reg_dft(cx<T> (&v)[Q], const cx<T>* __restrict__
 // Must be called by all NTHR threads of the block; ends with a barrier.  Only
 // the first nl lines are transformed (nl <= NLINES; ES == 1 when nl < NLINES).
 // PAD: lines in the padded layout of line_pos (ES == 1, LS >= padded_len<L>()).
-template <typename T, int L, bool INV, int NLINES, int LS, int ES, int NTHR, bool PAD = false>
+// R3F: the radix-3 stage first (for L = 3 * 2^k: its stores are 3 elements
+// apart, and the radix-8 stages after it store 3 and 24 elements apart instead
+// of 1 and 8, which spreads the lanes of a row over more LDS banks).
+template <typename T, int L, bool INV, int NLINES, int LS, int ES, int NTHR, bool PAD = false,
+          bool R3F = false>
 __device__ __forceinline__ void fft_tile(cx<T>* lds, const cx<T>* __restrict__ tw, int tid,
                                          int nl = NLINES) {
     static_assert(fft_size_ok(L), "FFT length must be 2^a 3^b");
     static_assert(!PAD || (ES == 1 && LS >= padded_len<L>()), "padded lines need ES == 1");
-    fft_stages<T, L, 1, INV, NLINES, LS, ES, NTHR, PAD>(lds, tw, tid, nl);
+    fft_stages<T, L, 1, INV, NLINES, LS, ES, NTHR, PAD, R3F>(lds, tw, tid, nl);
 }
 
 }  // namespace dda

@@ -230,7 +230,7 @@ __global__ __launch_bounds__(NT) void k_xfft_t(cx<T>* __restrict__ xin,
         }
     }
     __syncthreads();
-    fft_tile<T, LX, false, NR, LP, 1, NT>(lds, twl, tid, nrow);
+    fft_tile<T, LX, false, NR, LP, 1, NT, false, true>(lds, twl, tid, nrow);
     const int64_t cplane = int64_t(3) * g.nz * g.ny;  // one kx column
     cx<T>* dst = Tb + int64_t(pos) * g.mx * cplane + (int64_t(c) * g.nz + z) * g.ny;
     const bool perm = (g.ny & 7) == 0;
@@ -306,7 +306,7 @@ __global__ __launch_bounds__(NT) void k_ixfft_t(const cx<T>* __restrict__ Tb,
         }
     }
     __syncthreads();
-    fft_tile<T, LX, true, NR, LP, 1, NT>(lds, twl, tid, nrow);
+    fft_tile<T, LX, true, NR, LP, 1, NT, false, true>(lds, twl, tid, nrow);
     const int64_t voff = (slot * 3 + c) * g.n_occ;
     int idx[NE];
     row_indices<NE, NT, HX>(map + (int64_t(z) * g.ny + y0) * g.nx, nrow, g.nx, tid, idx);
